@@ -1,0 +1,315 @@
+"""Oracle: the two-stage CPR preconditioner on the 7-point block Jacobian.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Plain FP64 numpy/scipy.
+
+The paper's linear-solver section (Sec. 2.5, the block matrix of eq. (16))
+builds a constrained-pressure-residual preconditioner: decouple the pressure
+equation (quasi-IMPES), solve the pressure sub-problem A_pp by algebraic
+multigrid, then smooth the full system.  Readings for what the paper leaves
+to its cited CPR paper:
+  * Quasi-IMPES: w_i = D_i^-T e_0 / (D_i^-1)_00 for the diagonal block D_i of
+    cell i; row 0 of every block in block-row i becomes w_i^T A_ij and the
+    other rows are kept, giving A~ = W A.  A_p[i][j] = (A~_ij)_00.  If
+    |(D_i^-1)_00| <= 1e-300 the cell keeps w_i = e_0.
+  * Multigrid: 2x2x2 piecewise-constant aggregation (a grid dimension of 1
+    stays 1, coarse size ceil(n/2)), Galerkin A_c = P^T A P, coarsen while a
+    level has more than `coarsest` cells, LU solve on the last level;
+    V(1,1) cycle with a zero initial guess, red-black Gauss-Seidel (pre:
+    red then black; post: black then red), prolongation x += alpha P e.
+    Red cells have (i+j+k) even.
+  * Full-system stage: block ILU(0) of A~ in red-then-black order.  The
+    7-point graph has no triangles, so ILU(0) keeps the off-diagonal blocks
+    and only modifies the diagonal: D'_i = A~_ii - sum over lower-coloured
+    neighbours k of A~_ik D'_k^-1 A~_ki (the test suite checks this against
+    a textbook dense block ILU(0)).
+  * Composition: r~ = v with r~_0 = w^T v; dp = Vcycle(r~_0);
+    r2 = r~ - A~(:, p) dp; y = ILU^-1 r2; z = y + e_0 dp.
+"""
+import numpy as np
+import scipy.linalg
+import scipy.sparse as sp
+
+from .model import DIRS, OPP
+
+
+def shift(x, d):
+    """y[cell] = x[neighbour d of cell], zero where the neighbour is outside.
+    x has trailing shape (nz, ny, nx)."""
+    if d == 0:
+        return x.copy()
+    di, dj, dk = DIRS[d]
+    y = np.zeros_like(x)
+    ax, step = (-1, di) if di else ((-2, dj) if dj else (-3, dk))
+    n = x.shape[ax]
+    src = [slice(None)] * x.ndim
+    dst = [slice(None)] * x.ndim
+    if step > 0:
+        dst[ax], src[ax] = slice(0, n - 1), slice(1, n)
+    else:
+        dst[ax], src[ax] = slice(1, n), slice(0, n - 1)
+    y[tuple(dst)] = x[tuple(src)]
+    return y
+
+
+def colour(shape):
+    """0 for red ((i+j+k) even), 1 for black."""
+    nz, ny, nx = shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return (i + j + k) & 1
+
+
+def block_spmv(J, x):
+    """y = A x for the 7-point block matrix J[7, b, b, grid] and x[b, grid]."""
+    b = J.shape[1]
+    y = np.zeros_like(x)
+    for d in range(7):
+        xs = shift(x, d)
+        for r in range(b):
+            for c in range(b):
+                y[r] += J[d, r, c] * xs[c]
+    return y
+
+
+def scalar_spmv(A, x):
+    """y = A x for a scalar 7-point stencil A[7, grid]."""
+    y = np.zeros_like(x)
+    for d in range(7):
+        y += A[d] * shift(x, d)
+    return y
+
+
+def to_sparse(A):
+    """scipy CSR matrix of a scalar 7-point stencil (natural order)."""
+    shape = A.shape[1:]
+    n = int(np.prod(shape))
+    idx = np.arange(n).reshape(shape)
+    rows, cols, vals = [], [], []
+    for d in range(7):
+        nb = shift(idx.astype(np.float64) + 1.0, d) - 1.0   # -1 where outside
+        ok = nb >= 0
+        rows.append(idx[ok]); cols.append(nb[ok].astype(np.int64)); vals.append(A[d][ok])
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n, n))
+
+
+def block_to_dense(J):
+    """Dense matrix of a block 7-point operator, point-block ordered:
+    unknown (cell, r) at row cell*b + r (natural cell order)."""
+    b = J.shape[1]
+    shape = J.shape[3:]
+    n = int(np.prod(shape))
+    idx = np.arange(n).reshape(shape)
+    M = np.zeros((n * b, n * b))
+    for d in range(7):
+        nb = shift(idx.astype(np.float64) + 1.0, d) - 1.0
+        for cell in range(n):
+            kk = np.unravel_index(cell, shape)
+            t = int(nb[kk])
+            if t < 0:
+                continue
+            M[cell * b:(cell + 1) * b, t * b:(t + 1) * b] = J[(d, slice(None), slice(None)) + kk]
+    return M
+
+
+# ---------------------------------------------------------------- quasi-IMPES
+
+def quasi_impes(J):
+    """Decoupling weights w[b, grid] and row 0 of every decoupled block,
+    R0[7, b, grid] = w_i^T J[d, :, :, i]."""
+    b = J.shape[1]
+    shape = J.shape[3:]
+    D = np.moveaxis(J[0], (0, 1), (-2, -1))          # (grid, b, b)
+    e0 = np.zeros(shape + (b,))
+    e0[..., 0] = 1.0
+    y = np.linalg.solve(np.swapaxes(D, -1, -2), e0[..., None])[..., 0]   # D^-T e0
+    y0 = y[..., 0]
+    bad = ~(np.abs(y0) > 1e-300)
+    w = np.where(bad[..., None], e0, y / np.where(bad, 1.0, y0)[..., None])
+    w = np.moveaxis(w, -1, 0)                         # (b, grid)
+    R0 = np.zeros((7, b) + shape)
+    for d in range(7):
+        for c in range(b):
+            for r in range(b):
+                R0[d, c] += w[r] * J[d, r, c]
+    return w, R0, int(bad.sum())
+
+
+def decoupled_blocks(J, R0):
+    """A~ = W A as a full block array: row 0 from R0, other rows from J."""
+    At = J.copy()
+    At[:, 0] = R0
+    return At
+
+
+# ---------------------------------------------------------------- multigrid
+
+def coarse_shape(shape):
+    return tuple((n + 1) // 2 for n in shape)
+
+
+def prolongator(shape):
+    """Piecewise-constant P (fine x coarse) for 2x2x2 aggregation."""
+    nz, ny, nx = shape
+    cz, cy, cx = coarse_shape(shape)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    agg = (i // 2) + cx * ((j // 2) + cy * (k // 2))
+    n = nx * ny * nz
+    return sp.csr_matrix((np.ones(n), (np.arange(n), agg.ravel())), shape=(n, cx * cy * cz))
+
+
+def from_sparse(M, shape):
+    """Scalar 7-point stencil array from a sparse matrix that has no entries
+    outside the 7-point pattern (asserted)."""
+    n = int(np.prod(shape))
+    M = M.tocsr()
+    A = np.zeros((7,) + shape)
+    idx = np.arange(n).reshape(shape)
+    taken = 0
+    for d in range(7):
+        nb = (shift(idx.astype(np.float64) + 1.0, d) - 1.0).astype(np.int64)
+        ok = nb >= 0
+        vals = np.asarray(M[idx[ok], nb[ok]]).ravel()
+        A[d][ok] = vals
+        taken += int(ok.sum())
+    assert M.nnz <= taken, "Galerkin operator left the 7-point pattern"
+    return A
+
+
+def mg_setup(Ap, coarsest=512):
+    """Hierarchy [(A_l, shape_l)]; the last level is factorised by LU."""
+    levels = [Ap]
+    while int(np.prod(levels[-1].shape[1:])) > coarsest:
+        A = levels[-1]
+        shape = A.shape[1:]
+        P = prolongator(shape)
+        Ac = (P.T @ to_sparse(A) @ P)
+        levels.append(from_sparse(Ac, coarse_shape(shape)))
+    last = levels[-1]
+    lu = scipy.linalg.lu_factor(to_sparse(last).toarray())
+    return {"levels": levels, "lu": lu}
+
+
+def gs_half_sweep(A, r, x, col, which):
+    """One red (which=0) or black (which=1) Gauss-Seidel half-sweep: for
+    cells of that colour x_i = (r_i - sum_{j != i} a_ij x_j) / a_ii."""
+    off = np.zeros_like(x)
+    for d in range(1, 7):
+        off += A[d] * shift(x, d)
+    m = col == which
+    x[m] = (r[m] - off[m]) / A[0][m]
+
+
+def vcycle(mg, r, level=0, alpha=1.0):
+    """V(1,1) cycle with a zero initial guess on level `level`."""
+    levels = mg["levels"]
+    A = levels[level]
+    shape = A.shape[1:]
+    if level == len(levels) - 1:
+        return scipy.linalg.lu_solve(mg["lu"], r.ravel()).reshape(shape)
+    col = colour(shape)
+    x = np.zeros_like(r)
+    gs_half_sweep(A, r, x, col, 0)
+    gs_half_sweep(A, r, x, col, 1)
+    res = r - scalar_spmv(A, x)
+    P = prolongator(shape)
+    rc = (P.T @ res.ravel()).reshape(coarse_shape(shape))
+    ec = vcycle(mg, rc, level + 1, alpha)
+    x += alpha * (P @ ec.ravel()).reshape(shape)
+    gs_half_sweep(A, r, x, col, 1)
+    gs_half_sweep(A, r, x, col, 0)
+    return x
+
+
+# ---------------------------------------------------------------- block ILU(0)
+
+def _inv_blocks(D):
+    """Inverse of every b x b block, D shaped (b, b, grid); LAPACK LU with
+    partial pivoting.  Raises FloatingPointError on a singular block."""
+    Dm = np.moveaxis(D, (0, 1), (-2, -1))
+    if not np.all(np.isfinite(Dm)):
+        raise FloatingPointError("non-finite diagonal block")
+    try:
+        inv = np.linalg.inv(Dm)
+    except np.linalg.LinAlgError as e:
+        raise FloatingPointError("singular diagonal block") from e
+    return np.moveaxis(inv, (-2, -1), (0, 1))
+
+
+def _bmv(M, v):
+    """Per-cell block matrix-vector product M[b,b,grid] v[b,grid]."""
+    return np.einsum("rc...,c...->r...", M, v)
+
+
+def _bmm(A, B):
+    return np.einsum("rk...,kc...->rc...", A, B)
+
+
+def ilu_setup(At):
+    """Modified diagonals of the red-black block ILU(0); returns D'^-1."""
+    shape = At.shape[3:]
+    col = colour(shape)
+    red, black = col == 0, col == 1
+    Dinv = _inv_blocks(At[0])                       # red: D' = A~_ii
+    Dp = At[0].copy()
+    for d in range(1, 7):
+        # A~_ik D'_k^-1 A~_ki with k = neighbour d of i; k is red for black i
+        Aik = At[d]
+        Dk_inv = np.stack([np.stack([shift(Dinv[r, c], d) for c in range(Dinv.shape[1])])
+                           for r in range(Dinv.shape[0])])
+        Aki = np.stack([np.stack([shift(At[OPP[d], r, c], d) for c in range(At.shape[2])])
+                        for r in range(At.shape[1])])
+        corr = _bmm(_bmm(Aik, Dk_inv), Aki)
+        Dp[:, :, black] -= corr[:, :, black]
+    Dinv_black = _inv_blocks(Dp)
+    Dinv[:, :, black] = Dinv_black[:, :, black]
+    return Dinv
+
+
+def ilu_apply(At, Dinv, r):
+    """Solve (D'+L) D'^-1 (D'+U) z = r: forward over red then black, backward
+    over black then red."""
+    shape = r.shape[1:]
+    col = colour(shape)
+    red, black = col == 0, col == 1
+
+    def offdiag(v):
+        s = np.zeros_like(v)
+        for d in range(1, 7):
+            s += _bmv(At[d], np.stack([shift(v[c], d) for c in range(v.shape[0])]))
+        return s
+
+    y = np.zeros_like(r)
+    y[:, red] = _bmv(Dinv, r)[:, red]
+    t = r - offdiag(y)                 # y is zero on black, so only red neighbours count
+    y[:, black] = _bmv(Dinv, t)[:, black]
+    z = y.copy()
+    zb = np.where(black, z, 0.0)
+    u = offdiag(zb)                    # upper neighbours of red cells are black
+    z[:, red] = y[:, red] - _bmv(Dinv, u)[:, red]
+    return z
+
+
+# ---------------------------------------------------------------- CPR
+
+def cpr_setup(J, coarsest=512):
+    w, R0, nbad = quasi_impes(J)
+    At = decoupled_blocks(J, R0)
+    mg = mg_setup(R0[:, 0].copy(), coarsest)
+    Dinv = ilu_setup(At)
+    return {"w": w, "R0": R0, "At": At, "mg": mg, "Dinv": Dinv, "nbad": nbad}
+
+
+def cpr_apply(pc, v, alpha=1.0):
+    """z = M^-1 v for the two-stage CPR preconditioner."""
+    w, At = pc["w"], pc["At"]
+    rt = v.copy()
+    rt[0] = np.sum(w * v, axis=0)
+    dp = vcycle(pc["mg"], rt[0], 0, alpha)
+    r2 = rt.copy()
+    for d in range(7):
+        sdp = shift(dp, d)
+        for r in range(v.shape[0]):
+            r2[r] -= At[d, r, 0] * sdp
+    y = ilu_apply(At, pc["Dinv"], r2)
+    y[0] += dp
+    return y

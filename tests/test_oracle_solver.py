@@ -1,0 +1,265 @@
+"""Pins of the oracle's preconditioner and Krylov solver against dense linear
+algebra, closed forms and textbook special cases."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import cpr, krylov, model, newton
+from paper_1606_00548_amd import synth
+from tests.dense import dense_from_blocks, dense_from_stencil, from_pointblock, to_pointblock
+
+
+def _system(maker, seed=5):
+    case = maker()
+    x = synth.random_state_perturbation(case, seed)
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"],
+                          case["wells"], case["x_old"], x, case["dt"])
+    return case, J, -R
+
+
+def test_block_spmv_matches_dense():
+    _, J, b = _system(lambda: synth.black_oil_layered(5, 4, 3, seed=40))
+    M = dense_from_blocks(J)
+    y = cpr.block_spmv(J, b)
+    assert np.allclose(to_pointblock(y), M @ to_pointblock(b), rtol=1e-13, atol=1e-12)
+
+
+def test_quasi_impes_decouples_the_diagonal():
+    _, J, _ = _system(lambda: synth.black_oil_layered(4, 4, 3, seed=41))
+    w, R0, nbad = cpr.quasi_impes(J)
+    assert nbad == 0
+    assert np.all(w[0] == 1.0)
+    D = J[0]
+    scale = np.abs(D).max(axis=(0, 1))
+    # row 0 of the decoupled diagonal block has no saturation coupling
+    for s in range(1, J.shape[1]):
+        assert np.all(np.abs(R0[0, s]) <= 1e-13 * scale)
+    # and its pressure entry is the Schur complement d_pp - D_ps D_ss^-1 D_sp
+    Dm = np.moveaxis(D, (0, 1), (-2, -1))
+    schur = Dm[..., 0, 0] - np.einsum("...i,...i->...", Dm[..., 0, 1:],
+                                      np.linalg.solve(Dm[..., 1:, 1:], Dm[..., 1:, 0][..., None])[..., 0])
+    assert np.allclose(R0[0, 0], schur, rtol=1e-11)
+
+
+def test_galerkin_closed_form_uniform_single_phase():
+    # T + diag(acc) on a uniform grid: each coarse face collects the 4 fine
+    # faces between two 2x2x2 aggregates, and (since T 1 = 0) a coarse row
+    # sum is the sum of its 8 fine accumulation terms.
+    case = synth.single_phase_uniform(8, 8, 8)
+    case["fluid"] = dict(case["fluid"], c_w=0.0)
+    x = synth.initial_state(case["grid"], case["fluid"])
+    _, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], [],
+                          x, x, 1.0)
+    A = J[:, 0, 0]
+    mg = cpr.mg_setup(A, coarsest=64)
+    Ac = mg["levels"][1]
+    assert Ac.shape == (7, 4, 4, 4)
+    tx = A[2][0, 0, 0]
+    assert np.allclose(Ac[2][:, :, :-1], 4 * tx, rtol=1e-13)
+    acc = A.sum(axis=0)
+    agg = acc.reshape(4, 2, 4, 2, 4, 2).sum(axis=(1, 3, 5))
+    assert np.allclose(Ac.sum(axis=0), agg, rtol=1e-9, atol=1e-12 * np.abs(Ac).max())
+
+
+def test_galerkin_matches_dense_triple_product():
+    rng = np.random.default_rng(2)
+    shape = (3, 5, 6)
+    A = rng.uniform(-1, 0, (7,) + shape)
+    A[0] = 7.0
+    # zero the couplings that leave the grid
+    A[1][:, :, 0] = A[2][:, :, -1] = A[3][:, 0, :] = A[4][:, -1, :] = A[5][0] = A[6][-1] = 0
+    mg = cpr.mg_setup(A, coarsest=1)
+    Ac = mg["levels"][1]
+    nz, ny, nx = shape
+    cz, cy, cx = 2, 3, 3
+    P = np.zeros((nx * ny * nz, cx * cy * cz))
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                P[i + nx * (j + ny * k), i // 2 + cx * (j // 2 + cy * (k // 2))] = 1.0
+    ref = P.T @ dense_from_stencil(A) @ P
+    assert np.allclose(dense_from_stencil(Ac), ref, rtol=1e-13, atol=1e-13)
+
+
+def test_red_half_sweep_zeroes_red_residuals():
+    _, J, b = _system(lambda: synth.oil_water_lognormal(6, 6, 4, seed=42))
+    A = J[:, 0, 0]
+    r = b[0]
+    col = cpr.colour(r.shape)
+    x = np.random.default_rng(1).standard_normal(r.shape)
+    cpr.gs_half_sweep(A, r, x, col, 0)
+    res = r - cpr.scalar_spmv(A, x)
+    assert np.abs(res[col == 0]).max() <= 1e-13 * np.abs(r).max()
+    assert np.abs(res[col == 1]).max() > 1e-6 * np.abs(r).max()
+
+
+def test_one_level_hierarchy_is_exact():
+    _, J, b = _system(lambda: synth.oil_water_lognormal(6, 6, 4, seed=43))
+    w, R0, _ = cpr.quasi_impes(J)
+    A = R0[:, 0]
+    mg = cpr.mg_setup(A, coarsest=10 ** 6)
+    assert len(mg["levels"]) == 1
+    x = cpr.vcycle(mg, b[0])
+    assert np.allclose(dense_from_stencil(A) @ x.ravel(), b[0].ravel(), rtol=1e-10,
+                       atol=1e-12 * np.abs(b[0]).max())
+
+
+def test_vcycle_contracts_on_poisson():
+    for n in (16, 32):
+        case = synth.single_phase_uniform(n, n, 8)
+        x = synth.initial_state(case["grid"], case["fluid"])
+        _, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], [],
+                              x, x, 1.0)
+        A = J[:, 0, 0]
+        mg = cpr.mg_setup(A, coarsest=64)
+        rng = np.random.default_rng(n)
+        e = rng.standard_normal(A.shape[1:])
+        for _ in range(3):
+            e = e - cpr.vcycle(mg, cpr.scalar_spmv(A, e))
+        e1 = e - cpr.vcycle(mg, cpr.scalar_spmv(A, e))
+        assert np.linalg.norm(e1) < 0.9 * np.linalg.norm(e)
+
+
+def _textbook_block_ilu0(M, b, order):
+    """Dense block ILU(0) (IKJ variant) of M in the given cell order, keeping
+    only the blocks of M's sparsity pattern.  Returns L (unit lower, block)
+    and U (upper incl. diagonal) in that order."""
+    n = len(order)
+    perm = np.concatenate([np.arange(c * b, (c + 1) * b) for c in order])
+    A = M[np.ix_(perm, perm)].copy()
+    pattern = np.zeros((n, n), dtype=bool)
+    for I in range(n):
+        for K in range(n):
+            pattern[I, K] = np.any(A[I * b:(I + 1) * b, K * b:(K + 1) * b] != 0)
+    blk = lambda I, K: (slice(I * b, (I + 1) * b), slice(K * b, (K + 1) * b))
+    for I in range(1, n):
+        for K in range(I):
+            if not pattern[I, K]:
+                continue
+            A[blk(I, K)] = A[blk(I, K)] @ np.linalg.inv(A[blk(K, K)])
+            for Jc in range(K + 1, n):
+                if pattern[I, Jc]:
+                    A[blk(I, Jc)] -= A[blk(I, K)] @ A[blk(K, Jc)]
+    L = np.eye(n * b)
+    U = np.zeros_like(A)
+    for I in range(n):
+        for K in range(n):
+            if K < I:
+                L[blk(I, K)] = A[blk(I, K)]
+            else:
+                U[blk(I, K)] = A[blk(I, K)]
+    return L, U, perm
+
+
+@pytest.mark.parametrize("maker", [lambda: synth.oil_water_lognormal(4, 4, 2, seed=44),
+                                   lambda: synth.black_oil_layered(4, 4, 2, seed=45)])
+def test_red_black_ilu0_matches_textbook(maker):
+    _, J, b = _system(maker)
+    w, R0, _ = cpr.quasi_impes(J)
+    At = cpr.decoupled_blocks(J, R0)
+    Dinv = cpr.ilu_setup(At)
+    M = dense_from_blocks(At)
+    bs = J.shape[1]
+    shape = J.shape[3:]
+    col = cpr.colour(shape).ravel()
+    order = np.concatenate([np.where(col == 0)[0], np.where(col == 1)[0]])
+    L, U, perm = _textbook_block_ilu0(M, bs, order)
+    # solve with the textbook factors and compare with the oracle's sweeps
+    rhs = to_pointblock(b)
+    z_tb = np.zeros_like(rhs)
+    # U is block upper triangular with full diagonal blocks: general solve
+    z_tb[perm] = np.linalg.solve(U, scipy.linalg.solve_triangular(
+        L, rhs[perm], lower=True, unit_diagonal=True))
+    z = to_pointblock(cpr.ilu_apply(At, Dinv, b))
+    assert np.allclose(z, z_tb, rtol=1e-10, atol=1e-12 * np.abs(z_tb).max())
+    # LU - A~ is non-zero only between black cells two steps apart
+    E = L @ U - M[np.ix_(perm, perm)]
+    nz, ny, nx = shape
+    coords = [np.unravel_index(c, shape) for c in order]
+    for I in range(len(order)):
+        for K in range(len(order)):
+            e = np.abs(E[I * bs:(I + 1) * bs, K * bs:(K + 1) * bs]).max()
+            if e > 1e-12 * np.abs(M).max():
+                (k1, j1, i1), (k2, j2, i2) = coords[I], coords[K]
+                dist = abs(k1 - k2) + abs(j1 - j2) + abs(i1 - i2)
+                assert col[order[I]] == 1 and col[order[K]] == 1 and dist == 2
+
+
+def test_cpr_single_phase_exact_pressure_solve_is_one_iteration():
+    # b = 1: the pressure stage with an exact coarse solve inverts A, so the
+    # second stage sees a zero residual and FGMRES converges in one step.
+    case = synth.single_phase_uniform(6, 5, 4, wells=[synth.well(0, 0, 4, "inj", 300.0),
+                                                       synth.well(5, 4, 4, "prod", 150.0)])
+    x = synth.random_state_perturbation(case, 3)
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"],
+                          case["wells"], case["x_old"], x, case["dt"])
+    pc = cpr.cpr_setup(J, coarsest=10 ** 6)
+    dx, st = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), -R,
+                           rtol=1e-10)
+    assert st["iterations"] == 1 and st["converged"]
+
+
+def test_gmres_dense_small_converges_within_n():
+    rng = np.random.default_rng(7)
+    n = 24
+    A = rng.standard_normal((n, n)) + n * np.eye(n) * 0.3
+    b = rng.standard_normal(n)
+    x, st = krylov.fgmres(lambda v: A @ v, lambda v: v, b, restart=30, rtol=1e-12)
+    assert st["iterations"] <= n
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-10, atol=1e-10)
+
+
+def test_gmres_k_distinct_eigenvalues_takes_k_steps():
+    rng = np.random.default_rng(8)
+    eig = np.repeat([1.0, 2.0, 5.0, 9.0, 13.0], 8)
+    b = rng.standard_normal(eig.size)
+    x, st = krylov.fgmres(lambda v: eig * v, lambda v: v, b, restart=30, rtol=1e-12)
+    assert st["iterations"] == 5
+    assert np.allclose(x, b / eig, rtol=1e-11)
+
+
+def test_gmres_restart_and_zero_rhs():
+    rng = np.random.default_rng(9)
+    n = 60
+    A = np.diag(np.linspace(1, 50, n)) + 0.1 * rng.standard_normal((n, n))
+    b = rng.standard_normal(n)
+    x, st = krylov.fgmres(lambda v: A @ v, lambda v: v, b, restart=5, rtol=1e-8, max_iter=500)
+    assert st["converged"] and st["cycles"] > 1
+    assert np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
+    x0, st0 = krylov.fgmres(lambda v: A @ v, lambda v: v, np.zeros(n))
+    assert st0["iterations"] == 0 and np.all(x0 == 0)
+    # max_iter stops early and reports non-convergence with a usable iterate
+    x1, st1 = krylov.fgmres(lambda v: A @ v, lambda v: v, b, restart=30, rtol=1e-14, max_iter=3)
+    assert st1["iterations"] == 3 and not st1["converged"]
+    assert np.linalg.norm(b - A @ x1) < np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("maker", [lambda: synth.oil_water_lognormal(6, 6, 4, seed=50),
+                                   lambda: synth.black_oil_layered(6, 6, 4, seed=51),
+                                   lambda: synth.black_oil_channelised(6, 4, 4, seed=52)])
+def test_cpr_fgmres_solves_tiny_systems(maker):
+    case, J, b = _system(maker)
+    pc = cpr.cpr_setup(J, coarsest=16)
+    assert len(pc["mg"]["levels"]) >= 2
+    x, st = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), b)
+    assert st["converged"]
+    M = dense_from_blocks(J)
+    xd = np.linalg.solve(M, to_pointblock(b))
+    r = to_pointblock(b) - M @ to_pointblock(x)
+    assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
+    cond = np.linalg.cond(M)
+    err = np.linalg.norm(to_pointblock(x) - xd) / np.linalg.norm(xd)
+    assert err <= cond * 1e-6
+    # with a tight tolerance the iterate reaches the dense solution
+    x2, _ = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), b,
+                          rtol=1e-13)
+    assert np.allclose(to_pointblock(x2), xd, rtol=1e-8, atol=1e-9 * np.abs(xd).max())
+
+
+def test_newton_update_chops_and_clamps():
+    x = np.array([[200.0, 200.0, 200.0], [0.3, 0.95, 0.1], [0.05, 0.05, 0.05]])
+    dx = np.array([[5.0, -3.0, 1.0], [0.5, 0.1, -0.3], [0.01, -0.1, 0.0]])
+    xn = newton.newton_update(x, dx)
+    assert np.allclose(xn[0], [205.0, 197.0, 201.0])
+    assert np.allclose(xn[1], [0.5, 1.0, 0.0])
+    assert np.allclose(xn[2], [0.06, 0.0, 0.05])

@@ -1,0 +1,194 @@
+/*
+ * cprmi.h -- C ABI of the MI355X CPR-FGMRES Newton-solve library.
+ *
+ * The library implements the linear-solve hot path of a fully implicit
+ * black-oil / oil-water reservoir simulator (Liu, Wang & Chen, "Large-scale
+ * Reservoir Simulations on IBM Blue Gene/Q"): each inexact Newton iteration
+ * (Algorithm 1) assembles the Jacobian A of the discrete mass balances
+ * (eqs. (3)/(5) with the wells of eq. (6), backward Euler eq. (10) and the
+ * cell-centred transmissibilities of eq. (11)) and the right-hand side
+ * b = -F(x), then finds dx with ||b - A dx|| <= theta ||b|| (eq. (13)) by
+ * restarted flexible GMRES preconditioned with a two-stage CPR method
+ * (Sec. 2.5: quasi-IMPES decoupling, multigrid on the pressure block A_pp of
+ * eq. (16), then block ILU(0) on the full system).
+ *
+ * Conventions shared by every entry point
+ *   - Cells are numbered in natural order n = i + nx*(j + ny*k), k downward.
+ *     A per-cell vector with b unknowns is stored unknown-major, [b][n]:
+ *     x[u*n + cell].  Unknowns are (p [bar], S_w) for oil-water and
+ *     (p_o [bar], S_w, S_g) for saturated black oil; equation rows are the
+ *     components (oil, water[, gas]).
+ *   - Every array argument marked "device" is memory on the current HIP
+ *     device; the caller owns it and keeps it alive for the call.  Calls are
+ *     ordered on the HIP stream given to cpr_create and return once their
+ *     work is queued, except where a call says it synchronises.
+ *   - Return value: CPR_OK (0), CPR_NOT_CONVERGED (1), or a negative error
+ *     code.  No C++ exception crosses this interface.  After an error,
+ *     cpr_last_error() describes it.
+ *   - One context per stream and host thread; calls on one context must not
+ *     overlap.
+ */
+#ifndef CPRMI_H
+#define CPRMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CPR_OK = 0,
+  CPR_NOT_CONVERGED = 1,   /* dx holds the last iterate                     */
+  CPR_EINVAL = -1,         /* bad argument or unsupported shape             */
+  CPR_ENOMEM = -2,         /* device allocation failed                      */
+  CPR_EHIP = -3,           /* a HIP runtime call failed                     */
+  CPR_ESINGULAR = -4,      /* singular diagonal or coarsest-level block     */
+  CPR_ENONFINITE = -5,     /* NaN or Inf in the input or during the solve   */
+  CPR_EBREAKDOWN = -6      /* Krylov breakdown without convergence          */
+};
+
+enum { CPR_MODEL_OIL_WATER = 2, CPR_MODEL_BLACK_OIL = 3 };
+enum { CPR_WELL_INJECTOR = 0, CPR_WELL_PRODUCER = 1 };
+enum { CPR_PREC_FP64 = 0, CPR_PREC_MIXED = 1 };
+
+/* Structured Cartesian grid: cell sizes in metres, depth of the top face in
+ * metres (depth positive downward).  nx must be even: the library stores
+ * every per-cell array split by red-black colour along x. */
+typedef struct {
+  int nx, ny, nz;
+  double dx, dy, dz;
+  double top;
+} cpr_grid_t;
+
+/* Fluid and rock description (Sec. 2.1-2.2).  Pressures in bar,
+ * compressibilities in 1/bar, viscosities in cP, densities in kg/m^3.
+ *   oil-water: rho_o_ref, rho_w_ref, c_o, c_w, c_r, mu_o, mu_w, s_wc, s_or
+ *              (Corey curves of eqs. (17)-(18), exponent 2);
+ *   black oil: rho_o_sc, rho_g_sc (surface densities), rho_w_ref, c_w, c_r,
+ *              mu_w, s_wc, s_or, sg_den, and a host table pvt[6][n_pvt] of
+ *              rows p, Rs, Bo, mu_o, Bg, mu_g, piecewise linear in p
+ *              (the right-hand segment at a node, end segments extended).
+ * The table is copied during cpr_create. */
+typedef struct {
+  int model;
+  double p_ref;
+  double rho_w_ref, rho_o_ref, rho_o_sc, rho_g_sc;
+  double c_w, c_o, c_r;
+  double mu_w, mu_o;
+  double s_wc, s_or, sg_den;
+  int n_pvt;
+  const double* pvt;   /* host, [6][n_pvt]; NULL for oil-water */
+} cpr_fluid_t;
+
+/* A vertical well perforated in cells (i, j, k0..k1) under a bottom-hole
+ * pressure constraint (eq. (7): the BHP is known and adds no unknown),
+ * referenced to the depth of the grid top; rate from eq. (6) with a
+ * Peaceman well index of radius rw (m) and skin. */
+typedef struct {
+  int i, j, k0, k1;
+  int kind;            /* CPR_WELL_INJECTOR (water) or CPR_WELL_PRODUCER */
+  double bhp;          /* bar */
+  double rw, skin;
+} cpr_well_t;
+
+typedef struct {
+  int precision;       /* CPR_PREC_FP64, or CPR_PREC_MIXED: FP32 preconditioner
+                          inside FP64 FGMRES                                 */
+  int learned;         /* 1: apply the loaded pressure-correction network    */
+  int restart;         /* FGMRES restart length m, 1..64 (default 30)       */
+  int max_iter;        /* total Arnoldi iterations (default 300)            */
+  double rtol;         /* stop when ||b - A dx||_2 <= rtol ||b||_2 (1e-6)    */
+  int mg_coarsest;     /* coarsen while a level has more cells (512, <= 4096) */
+  double mg_alpha;     /* coarse-correction scaling (1.0)                    */
+} cpr_options_t;
+
+typedef struct {
+  int iterations;      /* Arnoldi matrix-vector products                     */
+  int cycles;          /* restart cycles                                     */
+  int converged;
+  int mg_levels;
+  int qimpes_fallback; /* cells whose decoupling weight fell back to e_0     */
+  int nn_accepted, nn_rejected;
+  double bnorm;        /* ||b||_2                                            */
+  double est_rel;      /* GMRES estimate of ||b - A dx|| / ||b|| at the end  */
+  double true_rel;     /* recomputed ||b - A dx|| / ||b||                    */
+} cpr_stats_t;
+
+typedef struct cpr_ctx cpr_ctx_t;
+
+/* Fill *o with the defaults listed above. */
+void cpr_default_options(cpr_options_t* o);
+
+/* Create a context.  perm3 (device, [3][n], mD, kx ky kz) and poro (device,
+ * [n]) are read during the call and copied; wells is a host array.  The
+ * library owns every buffer it allocates (Jacobian, hierarchy, Krylov basis)
+ * and frees them in cpr_destroy.  stream: a hipStream_t (NULL = default
+ * stream).  Transmissibilities (harmonic, eq. (11)) and Peaceman well
+ * indices are computed here.  Synchronises the stream. */
+int cpr_create(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3,
+               const double* poro, const cpr_well_t* wells, int nwells, void* stream,
+               cpr_ctx_t** out);
+
+void cpr_destroy(cpr_ctx_t* ctx);
+const char* cpr_last_error(const cpr_ctx_t* ctx);
+
+/* Number of unknowns per cell (2 or 3) and cells of the context. */
+int cpr_block_size(const cpr_ctx_t* ctx);
+long long cpr_num_cells(const cpr_ctx_t* ctx);
+
+/* Assemble the Jacobian A = dR/dx at x (kept in the context) and write
+ * rhs_out = -R(x) (device, [b][n]) for the time step x_old -> x of length
+ * dt_days (eqs. (3)/(5), (6), (10), (11); Algorithm 1, step 3).  Each
+ * component's rows are divided by rho_c * V * mean(phi) / dt. */
+int assemble_jacobian(cpr_ctx_t* ctx, const double* x_old, const double* x, double dt_days,
+                      double* rhs_out);
+
+/* Replace the context's Jacobian by blocks (device, natural order
+ * [7][b][b][n]; block direction d = self, -x, +x, -y, +y, -z, +z;
+ * blocks[((d*b + r)*b + c)*n + cell] = dR_r(cell)/dx_c(neighbour d)),
+ * or copy it out in the same layout.  Blocks that reach outside the grid
+ * must be zero on import and are zero on export. */
+int cpr_import_jacobian(cpr_ctx_t* ctx, const double* blocks);
+int cpr_export_jacobian(cpr_ctx_t* ctx, double* blocks);
+
+/* Build the CPR preconditioner for the current Jacobian: quasi-IMPES
+ * weights and decoupled rows, the pressure multigrid hierarchy (2x2x2
+ * aggregation, Galerkin coarse operators, dense inverse of the coarsest
+ * level) and the red-black block ILU(0) diagonals.  Synchronises the stream
+ * (to report singular blocks).  Returns CPR_ESINGULAR if a diagonal block
+ * or the coarsest operator cannot be inverted. */
+int cpr_setup(cpr_ctx_t* ctx, const cpr_options_t* o);
+
+/* Solve A dx = rhs (both device, [b][n]) from dx = 0 with FGMRES(restart)
+ * and the CPR preconditioner (eq. (13) with theta = rtol).  Synchronises once
+ * per Arnoldi iteration to read the Hessenberg column.  st may be NULL.
+ * Returns CPR_OK, CPR_NOT_CONVERGED (dx holds the last iterate),
+ * CPR_ENONFINITE (non-finite rhs or iterate) or CPR_EBREAKDOWN. */
+int cpr_gmres_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* st);
+
+/* Newton update of Algorithm 1, step 5 (device, [b][n]): x += dx with
+ * saturation changes chopped to |dS| <= 0.2 and saturations clamped to
+ * [0, 1]. */
+int cpr_newton_update(cpr_ctx_t* ctx, double* x, const double* dx);
+
+/* Single operations of the path, for verification: y = A x; one CPR
+ * preconditioner application z = M^-1 v (after cpr_setup).  Device [b][n]. */
+int cpr_spmv(cpr_ctx_t* ctx, const double* x, double* y);
+int cpr_precond_apply(cpr_ctx_t* ctx, const double* v, double* z);
+
+/* Setup products, for verification (device outputs, natural order):
+ * quasi-IMPES weights w [b][n]; the scalar 7-point operator of multigrid
+ * level `level` as [7][n_level] (natural order of that level's grid);
+ * the inverted ILU diagonals D'^-1 as [b][b][n]. */
+int cpr_export_qimpes(cpr_ctx_t* ctx, double* w);
+int cpr_mg_level_shape(const cpr_ctx_t* ctx, int level, int* nx, int* ny, int* nz);
+int cpr_export_mg_level(cpr_ctx_t* ctx, int level, double* a7);
+int cpr_export_ilu(cpr_ctx_t* ctx, double* dinv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPRMI_H */

@@ -1,0 +1,266 @@
+"""Python binding of the C ABI in include/cprmi.h (ctypes; marshalling only).
+
+Every array is a torch tensor on the GPU (float64, contiguous, natural cell
+order [b][nz][ny][nx]); torch provides device memory and the HIP stream, and
+all arithmetic happens in libcprmi.so.  Importing this module loads torch
+first so that the library binds to the HIP runtime torch already mapped.
+The library must have been built (`python -m paper_1606_00548_amd.build`);
+without it every entry point raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcprmi.so")
+_lib = None
+
+CPR_OK, CPR_NOT_CONVERGED = 0, 1
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENONFINITE",
+          -6: "EBREAKDOWN"}
+PREC = {"fp64": 0, "mixed": 1}
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("top", ctypes.c_double)]
+
+
+class Fluid(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int), ("p_ref", ctypes.c_double),
+                ("rho_w_ref", ctypes.c_double), ("rho_o_ref", ctypes.c_double),
+                ("rho_o_sc", ctypes.c_double), ("rho_g_sc", ctypes.c_double),
+                ("c_w", ctypes.c_double), ("c_o", ctypes.c_double), ("c_r", ctypes.c_double),
+                ("mu_w", ctypes.c_double), ("mu_o", ctypes.c_double),
+                ("s_wc", ctypes.c_double), ("s_or", ctypes.c_double), ("sg_den", ctypes.c_double),
+                ("n_pvt", ctypes.c_int), ("pvt", ctypes.POINTER(ctypes.c_double))]
+
+
+class Well(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_int), ("j", ctypes.c_int), ("k0", ctypes.c_int), ("k1", ctypes.c_int),
+                ("kind", ctypes.c_int), ("bhp", ctypes.c_double), ("rw", ctypes.c_double),
+                ("skin", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("learned", ctypes.c_int), ("restart", ctypes.c_int),
+                ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double), ("mg_coarsest", ctypes.c_int),
+                ("mg_alpha", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("cycles", ctypes.c_int), ("converged", ctypes.c_int),
+                ("mg_levels", ctypes.c_int), ("qimpes_fallback", ctypes.c_int),
+                ("nn_accepted", ctypes.c_int), ("nn_rejected", ctypes.c_int),
+                ("bnorm", ctypes.c_double), ("est_rel", ctypes.c_double),
+                ("true_rel", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error", "cpr_block_size",
+           "cpr_num_cells", "assemble_jacobian", "cpr_import_jacobian", "cpr_export_jacobian",
+           "cpr_setup", "cpr_gmres_solve", "cpr_newton_update", "cpr_spmv", "cpr_precond_apply",
+           "cpr_export_qimpes", "cpr_mg_level_shape", "cpr_export_mg_level", "cpr_export_ilu"]
+
+
+def load():
+    """Load libcprmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with python -m paper_1606_00548_amd.build")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    lib.cpr_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.cpr_create.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Fluid), P, P, ctypes.POINTER(Well),
+                               ctypes.c_int, P, ctypes.POINTER(P)]
+    lib.cpr_destroy.argtypes = [P]
+    lib.cpr_last_error.argtypes = [P]
+    lib.cpr_last_error.restype = ctypes.c_char_p
+    lib.cpr_block_size.argtypes = [P]
+    lib.cpr_num_cells.argtypes = [P]
+    lib.cpr_num_cells.restype = ctypes.c_longlong
+    lib.assemble_jacobian.argtypes = [P, P, P, ctypes.c_double, P]
+    lib.cpr_import_jacobian.argtypes = [P, P]
+    lib.cpr_export_jacobian.argtypes = [P, P]
+    lib.cpr_setup.argtypes = [P, ctypes.POINTER(Options)]
+    lib.cpr_gmres_solve.argtypes = [P, P, P, ctypes.POINTER(Stats)]
+    lib.cpr_newton_update.argtypes = [P, P, P]
+    lib.cpr_spmv.argtypes = [P, P, P]
+    lib.cpr_precond_apply.argtypes = [P, P, P]
+    lib.cpr_export_qimpes.argtypes = [P, P]
+    lib.cpr_mg_level_shape.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.cpr_export_mg_level.argtypes = [P, ctypes.c_int, P]
+    lib.cpr_export_ilu.argtypes = [P, P]
+    _lib = lib
+    return lib
+
+
+class CPRError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_options(**kw):
+    o = Options()
+    load().cpr_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PREC[v]
+        setattr(o, k, v)
+    return o
+
+
+class Solver:
+    """One C-ABI context: grid, rock, fluid and wells of a reservoir model."""
+
+    def __init__(self, grid, fluid, perm, poro, wells, stream=None):
+        lib = load()
+        self.lib = lib
+        self.grid = grid
+        self.b = {2: 2, 3: 3}[fluid["model"]]
+        self.shape = (grid["nz"], grid["ny"], grid["nx"])
+        g = Grid(grid["nx"], grid["ny"], grid["nz"], grid["dx"], grid["dy"], grid["dz"], grid["top"])
+        f = Fluid()
+        f.model = fluid["model"]
+        for key in ["p_ref", "rho_w_ref", "rho_o_ref", "rho_o_sc", "rho_g_sc", "c_w", "c_o", "c_r",
+                    "mu_w", "mu_o", "s_wc", "s_or", "sg_den"]:
+            setattr(f, key, float(fluid.get(key, 0.0)))
+        self._pvt = None
+        if fluid["model"] == 3:
+            self._pvt = np.ascontiguousarray(fluid["pvt"], dtype=np.float64)
+            f.n_pvt = self._pvt.shape[1]
+            f.pvt = self._pvt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        ws = (Well * max(1, len(wells)))()
+        for q, w in enumerate(wells):
+            ws[q] = Well(w["i"], w["j"], w["k0"], w["k1"], 0 if w["kind"] == "inj" else 1,
+                         w["bhp"], w["rw"], w["skin"])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        perm_t = torch.as_tensor(np.asarray(perm, dtype=np.float64)).cuda().contiguous() \
+            if not isinstance(perm, torch.Tensor) else perm
+        poro_t = torch.as_tensor(np.asarray(poro, dtype=np.float64)).cuda().contiguous() \
+            if not isinstance(poro, torch.Tensor) else poro
+        ctx = ctypes.c_void_p()
+        with torch.cuda.stream(self.stream):
+            rc = lib.cpr_create(ctypes.byref(g), ctypes.byref(f), _ptr(perm_t), _ptr(poro_t), ws,
+                                len(wells), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        self.ctx = ctx
+        if rc != 0:
+            msg = lib.cpr_last_error(ctx).decode() if ctx.value else ""
+            lib.cpr_destroy(ctx)
+            self.ctx = None
+            raise CPRError(rc, msg)
+
+    @classmethod
+    def from_case(cls, case, stream=None):
+        return cls(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"], stream)
+
+    def _check(self, rc, allow=(0,)):
+        if rc not in allow:
+            raise CPRError(rc, self.lib.cpr_last_error(self.ctx).decode())
+        return rc
+
+    def vector(self):
+        return torch.zeros((self.b,) + self.shape, dtype=torch.float64, device="cuda")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.cpr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the three calls of the hot path and the Newton update
+    def assemble(self, x_old, x, dt_days, rhs=None):
+        rhs = self.vector() if rhs is None else rhs
+        self._check(self.lib.assemble_jacobian(self.ctx, _ptr(x_old), _ptr(x), float(dt_days), _ptr(rhs)))
+        return rhs
+
+    def setup(self, options=None, **kw):
+        o = options if options is not None else default_options(**kw)
+        self._check(self.lib.cpr_setup(self.ctx, ctypes.byref(o)))
+
+    def solve(self, rhs, dx=None):
+        dx = self.vector() if dx is None else dx
+        st = Stats()
+        rc = self._check(self.lib.cpr_gmres_solve(self.ctx, _ptr(rhs), _ptr(dx), ctypes.byref(st)),
+                         allow=(0, 1))
+        d = st.as_dict()
+        d["status"] = rc
+        return dx, d
+
+    def newton_update(self, x, dx):
+        self._check(self.lib.cpr_newton_update(self.ctx, _ptr(x), _ptr(dx)))
+        return x
+
+    # -- single operations and setup products, for verification
+    def spmv(self, x, y=None):
+        y = self.vector() if y is None else y
+        self._check(self.lib.cpr_spmv(self.ctx, _ptr(x), _ptr(y)))
+        return y
+
+    def precond(self, v, z=None):
+        z = self.vector() if z is None else z
+        self._check(self.lib.cpr_precond_apply(self.ctx, _ptr(v), _ptr(z)))
+        return z
+
+    def export_jacobian(self):
+        J = torch.empty((7, self.b, self.b) + self.shape, dtype=torch.float64, device="cuda")
+        self._check(self.lib.cpr_export_jacobian(self.ctx, _ptr(J)))
+        return J
+
+    def import_jacobian(self, J):
+        J = J if isinstance(J, torch.Tensor) else torch.as_tensor(np.ascontiguousarray(J)).cuda()
+        self._check(self.lib.cpr_import_jacobian(self.ctx, _ptr(J.contiguous())))
+        torch.cuda.synchronize()
+
+    def export_qimpes(self):
+        w = self.vector()
+        self._check(self.lib.cpr_export_qimpes(self.ctx, _ptr(w)))
+        return w
+
+    def mg_level_shape(self, level):
+        nx, ny, nz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        rc = self.lib.cpr_mg_level_shape(self.ctx, level, ctypes.byref(nx), ctypes.byref(ny),
+                                         ctypes.byref(nz))
+        if rc != 0:
+            return None
+        return (nz.value, ny.value, nx.value)
+
+    def export_mg_level(self, level):
+        shape = self.mg_level_shape(level)
+        a = torch.empty((7,) + shape, dtype=torch.float64, device="cuda")
+        self._check(self.lib.cpr_export_mg_level(self.ctx, level, _ptr(a)))
+        return a
+
+    def export_ilu(self):
+        d = torch.empty((self.b, self.b) + self.shape, dtype=torch.float64, device="cuda")
+        self._check(self.lib.cpr_export_ilu(self.ctx, _ptr(d)))
+        return d
+
+
+def newton_step(solver, x_old, x, dt_days, options=None, **kw):
+    """One inexact Newton iteration (Algorithm 1): assemble A and b = -F(x),
+    set up CPR, solve with FGMRES, update x in place.  Returns (dx, stats)."""
+    rhs = solver.assemble(x_old, x, dt_days)
+    solver.setup(options, **kw)
+    dx, st = solver.solve(rhs)
+    solver.newton_update(x, dx)
+    return dx, st

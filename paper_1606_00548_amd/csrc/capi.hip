@@ -1,0 +1,393 @@
+// C ABI entry points: argument checks, layout conversion at the boundary,
+// ownership of device buffers.  No exception leaves this file.
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+void release_hierarchy(cpr_ctx* ctx);
+void launch_mixed_copies(cpr_ctx* ctx);
+
+int set_err(cpr_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int set_hip_err(cpr_ctx* ctx, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return set_err(ctx, e == hipErrorOutOfMemory ? CPR_ENOMEM : CPR_EHIP, m);
+}
+
+int launch_check(cpr_ctx* ctx, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_hip_err(ctx, e, what);
+  return CPR_OK;
+}
+
+namespace {
+
+template <typename T>
+int dalloc(cpr_ctx* ctx, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) return set_hip_err(ctx, e, "hipMalloc");
+  return CPR_OK;
+}
+
+void free_all(cpr_ctx* ctx) {
+  release_hierarchy(ctx);
+  void* bufs[] = {ctx->poro, ctx->tp, ctx->perfs_d, ctx->J, ctx->props, ctx->vin, ctx->vin2, ctx->vout,
+                  ctx->w, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf, ctx->flag, ctx->V, ctx->Z,
+                  ctx->Y, ctx->rp, ctx->xs, ctx->rs, ctx->tmp, ctx->vf, ctx->zf, ctx->Yf, ctx->rpf,
+                  ctx->part, ctx->hdev};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  if (ctx->hhost) hipHostFree(ctx->hhost);
+}
+
+// Peaceman well index of a vertical well in an anisotropic block (m^3).
+double peaceman(double kx_md, double ky_md, double dx, double dy, double dz, double rw, double skin) {
+  const double MD = 9.869233e-16;
+  double kx = kx_md * MD, ky = ky_md * MD;
+  double rxy = std::sqrt(ky / kx), ryx = std::sqrt(kx / ky);
+  double ro = 0.28 * std::sqrt(rxy * dx * dx + ryx * dy * dy) / (std::sqrt(rxy) + std::sqrt(ryx));
+  return 2.0 * 3.141592653589793 * std::sqrt(kx * ky) * dz / (std::log(ro / rw) + skin);
+}
+
+int check_ctx(cpr_ctx* ctx) { return ctx ? CPR_OK : CPR_EINVAL; }
+
+int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, const double* poro,
+                const cpr_well_t* wells, int nwells, void* stream, cpr_ctx* ctx) {
+  if (!g || !f || !perm3 || !poro || (nwells > 0 && !wells) || nwells < 0)
+    return set_err(ctx, CPR_EINVAL, "null argument");
+  if (g->nx < 2 || g->ny < 1 || g->nz < 1 || (g->nx & 1))
+    return set_err(ctx, CPR_EINVAL, "grid needs nx >= 2 even, ny >= 1, nz >= 1");
+  long long n = (long long)g->nx * g->ny * g->nz;
+  if (n > INT_MAX / 2) return set_err(ctx, CPR_EINVAL, "grid too large");
+  if (!(g->dx > 0 && g->dy > 0 && g->dz > 0)) return set_err(ctx, CPR_EINVAL, "cell sizes must be > 0");
+  if (f->model != CPR_MODEL_OIL_WATER && f->model != CPR_MODEL_BLACK_OIL)
+    return set_err(ctx, CPR_EINVAL, "model must be 2 (oil-water) or 3 (black oil)");
+  if (f->model == CPR_MODEL_BLACK_OIL && (!f->pvt || f->n_pvt < 2 || f->n_pvt > CPR_MAX_PVT))
+    return set_err(ctx, CPR_EINVAL, "black oil needs a PVT table with 2..16 nodes");
+  ctx->stream = (hipStream_t)stream;
+  ctx->grid = *g;
+  ctx->b = f->model;
+  FluidDev& fl = ctx->fl;
+  std::memset(&fl, 0, sizeof(fl));
+  fl.model = f->model;
+  fl.p_ref = f->p_ref; fl.rho_w_ref = f->rho_w_ref; fl.rho_o_ref = f->rho_o_ref;
+  fl.rho_o_sc = f->rho_o_sc; fl.rho_g_sc = f->rho_g_sc;
+  fl.c_w = f->c_w; fl.c_o = f->c_o; fl.c_r = f->c_r; fl.mu_w = f->mu_w; fl.mu_o = f->mu_o;
+  fl.s_wc = f->s_wc; fl.s_or = f->s_or; fl.sg_den = f->sg_den;
+  if (f->model == CPR_MODEL_BLACK_OIL) {
+    fl.npvt = f->n_pvt;
+    for (int r = 0; r < 6; ++r)
+      for (int q = 0; q < f->n_pvt; ++q) fl.pvt[r][q] = f->pvt[(size_t)r * f->n_pvt + q];
+    for (int q = 0; q + 1 < f->n_pvt; ++q)
+      if (!(fl.pvt[0][q + 1] > fl.pvt[0][q])) return set_err(ctx, CPR_EINVAL, "PVT pressures must increase");
+  }
+  ctx->lay = make_lay(g->nx, g->ny, g->nz, true);
+  const int b = ctx->b;
+  const size_t N = (size_t)n;
+  int rc;
+#define ALLOC(p, cnt) if ((rc = dalloc(ctx, &(p), (cnt))) != CPR_OK) return rc
+  ALLOC(ctx->poro, N);
+  ALLOC(ctx->tp, 3 * N);
+  ALLOC(ctx->J, 7 * (size_t)b * b * N);
+  ALLOC(ctx->props, (size_t)props_planes(f->model) * N);
+  ALLOC(ctx->vin, b * N);
+  ALLOC(ctx->vin2, b * N);
+  ALLOC(ctx->vout, b * N);
+  ALLOC(ctx->w, b * N);
+  ALLOC(ctx->R0, 7 * (size_t)b * N);
+  ALLOC(ctx->Dinv, (size_t)b * b * N);
+  ALLOC(ctx->Y, b * N);
+  ALLOC(ctx->xs, b * N);
+  ALLOC(ctx->rs, b * N);
+  ALLOC(ctx->tmp, b * N);
+  ALLOC(ctx->flag, 4);
+  ctx->nblk = div_up((long)b * n, 1024);
+  if (ctx->nblk > 1024) ctx->nblk = 1024;
+  ALLOC(ctx->part, 66 * (size_t)ctx->nblk);
+  ALLOC(ctx->hdev, 512);
+#undef ALLOC
+  {
+    hipError_t e = hipHostMalloc((void**)&ctx->hhost, 512 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return set_hip_err(ctx, e, "hipHostMalloc");
+  }
+  hipStream_t s = ctx->stream;
+  launch_nat_to_cs(ctx->lay, 1, poro, ctx->poro, s);
+  launch_transmissibility(ctx->lay, *g, perm3, ctx->tp, s);
+  if ((rc = launch_check(ctx, "cpr_create kernels")) != CPR_OK) return rc;
+  // mean porosity (compensated sum) for the row scaling
+  {
+    std::vector<double> h(N);
+    CPR_TRY(hipMemcpyAsync(h.data(), poro, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    CPR_TRY(hipStreamSynchronize(s));
+    double sum = 0.0, comp = 0.0;
+    for (size_t q = 0; q < N; ++q) {
+      double yv = h[q] - comp;
+      double t = sum + yv;
+      comp = (t - sum) - yv;
+      sum = t;
+    }
+    ctx->phibar = sum / (double)N;
+    if (!(ctx->phibar > 0.0)) return set_err(ctx, CPR_EINVAL, "mean porosity must be > 0");
+  }
+  ctx->cell_vol = g->dx * g->dy * g->dz;
+  if (f->model == CPR_MODEL_OIL_WATER) {
+    ctx->rho_scale[0] = f->rho_o_ref;
+    ctx->rho_scale[1] = f->rho_w_ref;
+  } else {
+    ctx->rho_scale[0] = f->rho_o_sc / host_pvt(fl, 2, f->p_ref);
+    ctx->rho_scale[1] = f->rho_w_ref;
+    ctx->rho_scale[2] = f->rho_g_sc / host_pvt(fl, 4, f->p_ref);
+  }
+  // perforations
+  std::vector<char> used;
+  for (int q = 0; q < nwells; ++q) {
+    const cpr_well_t& w = wells[q];
+    if (w.i < 0 || w.i >= g->nx || w.j < 0 || w.j >= g->ny || w.k0 < 0 || w.k1 >= g->nz || w.k0 > w.k1)
+      return set_err(ctx, CPR_EINVAL, "well perforation outside the grid");
+    if (w.kind != CPR_WELL_INJECTOR && w.kind != CPR_WELL_PRODUCER)
+      return set_err(ctx, CPR_EINVAL, "unknown well kind");
+    if (!(w.rw > 0)) return set_err(ctx, CPR_EINVAL, "well radius must be > 0");
+    for (int k = w.k0; k <= w.k1; ++k) {
+      size_t nat = (size_t)w.i + (size_t)g->nx * ((size_t)w.j + (size_t)g->ny * k);
+      double kxy[2];
+      CPR_TRY(hipMemcpy(&kxy[0], perm3 + nat, sizeof(double), hipMemcpyDeviceToHost));
+      CPR_TRY(hipMemcpy(&kxy[1], perm3 + N + nat, sizeof(double), hipMemcpyDeviceToHost));
+      Perf p;
+      p.cell = lay_index(ctx->lay, w.i, w.j, k);
+      p.kind = w.kind;
+      p.wi = peaceman(kxy[0], kxy[1], g->dx, g->dy, g->dz, w.rw, w.skin);
+      p.bhp = w.bhp;
+      double depth = g->top + (k + 0.5) * g->dz;
+      p.dzh = g->top - depth;
+      for (const Perf& o : ctx->perfs)
+        if (o.cell == p.cell) return set_err(ctx, CPR_EINVAL, "two perforations in one cell");
+      ctx->perfs.push_back(p);
+    }
+  }
+  if (!ctx->perfs.empty()) {
+    if ((rc = dalloc(ctx, &ctx->perfs_d, ctx->perfs.size())) != CPR_OK) return rc;
+    CPR_TRY(hipMemcpyAsync(ctx->perfs_d, ctx->perfs.data(), ctx->perfs.size() * sizeof(Perf),
+                           hipMemcpyHostToDevice, s));
+  }
+  CPR_TRY(hipStreamSynchronize(s));
+  cpr_default_options(&ctx->opt);
+  return CPR_OK;
+}
+
+int ensure_krylov(cpr_ctx* ctx, int m) {
+  if (m <= ctx->mcap) return CPR_OK;
+  if (ctx->V) hipFree(ctx->V);
+  if (ctx->Z) hipFree(ctx->Z);
+  ctx->V = ctx->Z = nullptr;
+  ctx->mcap = 0;
+  size_t len = (size_t)ctx->b * ctx->lay.n;
+  int rc;
+  if ((rc = dalloc(ctx, &ctx->V, (size_t)(m + 1) * len)) != CPR_OK) return rc;
+  if ((rc = dalloc(ctx, &ctx->Z, (size_t)m * len)) != CPR_OK) return rc;
+  ctx->mcap = m;
+  return CPR_OK;
+}
+
+int ensure_mixed(cpr_ctx* ctx) {
+  if (ctx->Jf) return CPR_OK;
+  size_t N = ctx->lay.n;
+  int b = ctx->b, rc;
+  if ((rc = dalloc(ctx, &ctx->Jf, 7 * (size_t)b * b * N)) != CPR_OK) return rc;
+  if ((rc = dalloc(ctx, &ctx->Dinvf, (size_t)b * b * N)) != CPR_OK) return rc;
+  if ((rc = dalloc(ctx, &ctx->Yf, (size_t)b * N)) != CPR_OK) return rc;
+  return CPR_OK;
+}
+
+}  // namespace
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                        \
+  }                                                                      \
+  catch (const std::bad_alloc&) {                                        \
+    return set_err(ctx, CPR_ENOMEM, "host allocation failed");           \
+  }                                                                      \
+  catch (...) {                                                          \
+    return set_err(ctx, CPR_EINVAL, "internal error");                   \
+  }
+
+extern "C" {
+
+void cpr_default_options(cpr_options_t* o) {
+  if (!o) return;
+  o->precision = CPR_PREC_FP64;
+  o->learned = 0;
+  o->restart = 30;
+  o->max_iter = 300;
+  o->rtol = 1e-6;
+  o->mg_coarsest = 512;
+  o->mg_alpha = 1.0;
+}
+
+int cpr_create(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, const double* poro,
+               const cpr_well_t* wells, int nwells, void* stream, cpr_ctx_t** out) {
+  if (!out) return CPR_EINVAL;
+  *out = nullptr;
+  cpr_ctx* ctx = nullptr;
+  try {
+    ctx = new cpr_ctx();
+  } catch (...) {
+    return CPR_ENOMEM;
+  }
+  int rc;
+  try {
+    rc = create_impl(g, f, perm3, poro, wells, nwells, stream, ctx);
+  } catch (...) {
+    rc = CPR_ENOMEM;
+  }
+  *out = ctx;   // returned even on failure so cpr_last_error can explain; caller destroys
+  return rc;
+}
+
+void cpr_destroy(cpr_ctx_t* ctx) {
+  if (!ctx) return;
+  hipStreamSynchronize(ctx->stream);
+  free_all(ctx);
+  delete ctx;
+}
+
+const char* cpr_last_error(const cpr_ctx_t* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int cpr_block_size(const cpr_ctx_t* ctx) { return ctx ? ctx->b : 0; }
+
+long long cpr_num_cells(const cpr_ctx_t* ctx) { return ctx ? (long long)ctx->lay.n : 0; }
+
+int assemble_jacobian(cpr_ctx_t* ctx, const double* x_old, const double* x, double dt_days,
+                      double* rhs_out) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  GUARD_BEGIN
+  if (!x_old || !x || !rhs_out) return set_err(ctx, CPR_EINVAL, "null argument");
+  if (!(dt_days > 0) || !std::isfinite(dt_days)) return set_err(ctx, CPR_EINVAL, "dt must be > 0");
+  hipStream_t s = ctx->stream;
+  launch_nat_to_cs(ctx->lay, ctx->b, x_old, ctx->vin2, s);
+  launch_nat_to_cs(ctx->lay, ctx->b, x, ctx->vin, s);
+  launch_assemble(ctx, ctx->vin2, ctx->vin, dt_days, ctx->vout);
+  launch_cs_to_nat(ctx->lay, ctx->b, ctx->vout, rhs_out, s);
+  ctx->setup_done = 0;
+  return launch_check(ctx, "assemble_jacobian");
+  GUARD_END
+}
+
+int cpr_import_jacobian(cpr_ctx_t* ctx, const double* blocks) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (!blocks) return set_err(ctx, CPR_EINVAL, "null argument");
+  launch_nat_to_cs(ctx->lay, 7 * ctx->b * ctx->b, blocks, ctx->J, ctx->stream);
+  ctx->setup_done = 0;
+  return launch_check(ctx, "cpr_import_jacobian");
+}
+
+int cpr_export_jacobian(cpr_ctx_t* ctx, double* blocks) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (!blocks) return set_err(ctx, CPR_EINVAL, "null argument");
+  launch_cs_to_nat(ctx->lay, 7 * ctx->b * ctx->b, ctx->J, blocks, ctx->stream);
+  return launch_check(ctx, "cpr_export_jacobian");
+}
+
+int cpr_setup(cpr_ctx_t* ctx, const cpr_options_t* o) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  GUARD_BEGIN
+  cpr_options_t opt;
+  if (o) opt = *o; else cpr_default_options(&opt);
+  if (opt.restart < 1 || opt.restart > 64) return set_err(ctx, CPR_EINVAL, "restart must be 1..64");
+  if (opt.max_iter < 0) return set_err(ctx, CPR_EINVAL, "max_iter must be >= 0");
+  if (!(opt.rtol >= 0) || !std::isfinite(opt.rtol)) return set_err(ctx, CPR_EINVAL, "rtol must be >= 0");
+  if (opt.mg_coarsest < 1 || opt.mg_coarsest > 4096)
+    return set_err(ctx, CPR_EINVAL, "mg_coarsest must be 1..4096");
+  if (opt.precision != CPR_PREC_FP64 && opt.precision != CPR_PREC_MIXED)
+    return set_err(ctx, CPR_EINVAL, "unknown precision");
+  if (opt.learned) return set_err(ctx, CPR_EINVAL, "no pressure-correction network loaded");
+  ctx->opt = opt;
+  ctx->setup_done = 0;
+  int rc;
+  if ((rc = ensure_krylov(ctx, opt.restart)) != CPR_OK) return rc;
+  if (opt.precision == CPR_PREC_MIXED && (rc = ensure_mixed(ctx)) != CPR_OK) return rc;
+  return setup_cpr(ctx);
+  GUARD_END
+}
+
+int cpr_gmres_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* st) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  GUARD_BEGIN
+  if (!rhs || !dx) return set_err(ctx, CPR_EINVAL, "null argument");
+  if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
+  hipStream_t s = ctx->stream;
+  launch_nat_to_cs(ctx->lay, ctx->b, rhs, ctx->rs, s);
+  int rc = fgmres_solve(ctx, st);
+  if (rc < 0) return rc;
+  launch_cs_to_nat(ctx->lay, ctx->b, ctx->xs, dx, s);
+  int rc2 = launch_check(ctx, "cpr_gmres_solve");
+  return rc2 != CPR_OK ? rc2 : rc;
+  GUARD_END
+}
+
+int cpr_newton_update(cpr_ctx_t* ctx, double* x, const double* dx) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (!x || !dx) return set_err(ctx, CPR_EINVAL, "null argument");
+  launch_newton_update(ctx->b, ctx->lay.n, x, dx, ctx->stream);
+  return launch_check(ctx, "cpr_newton_update");
+}
+
+int cpr_spmv(cpr_ctx_t* ctx, const double* x, double* y) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (!x || !y) return set_err(ctx, CPR_EINVAL, "null argument");
+  hipStream_t s = ctx->stream;
+  launch_nat_to_cs(ctx->lay, ctx->b, x, ctx->vin, s);
+  launch_spmv(ctx->b, ctx->lay, ctx->J, ctx->vin, ctx->vout, nullptr, s);
+  launch_cs_to_nat(ctx->lay, ctx->b, ctx->vout, y, s);
+  return launch_check(ctx, "cpr_spmv");
+}
+
+int cpr_precond_apply(cpr_ctx_t* ctx, const double* v, double* z) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (!v || !z) return set_err(ctx, CPR_EINVAL, "null argument");
+  if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
+  hipStream_t s = ctx->stream;
+  launch_nat_to_cs(ctx->lay, ctx->b, v, ctx->vin, s);
+  precond_apply(ctx, ctx->vin, ctx->vout);
+  launch_cs_to_nat(ctx->lay, ctx->b, ctx->vout, z, s);
+  return launch_check(ctx, "cpr_precond_apply");
+}
+
+int cpr_export_qimpes(cpr_ctx_t* ctx, double* w) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (!w || !ctx->setup_done) return set_err(ctx, CPR_EINVAL, "null argument or no setup");
+  launch_cs_to_nat(ctx->lay, ctx->b, ctx->w, w, ctx->stream);
+  return launch_check(ctx, "cpr_export_qimpes");
+}
+
+int cpr_mg_level_shape(const cpr_ctx_t* ctx, int level, int* nx, int* ny, int* nz) {
+  if (!ctx || level < 0 || level >= (int)ctx->levels.size() || !nx || !ny || !nz) return CPR_EINVAL;
+  const Lay& L = ctx->levels[level].lay;
+  *nx = L.nx; *ny = L.ny; *nz = L.nz;
+  return CPR_OK;
+}
+
+int cpr_export_mg_level(cpr_ctx_t* ctx, int level, double* a7) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (!a7 || !ctx->setup_done || level < 0 || level >= (int)ctx->levels.size())
+    return set_err(ctx, CPR_EINVAL, "bad level or no setup");
+  const MGLevel& L = ctx->levels[level];
+  launch_cs_to_nat(L.lay, 7, L.A, a7, ctx->stream);
+  return launch_check(ctx, "cpr_export_mg_level");
+}
+
+int cpr_export_ilu(cpr_ctx_t* ctx, double* dinv) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (!dinv || !ctx->setup_done) return set_err(ctx, CPR_EINVAL, "null argument or no setup");
+  launch_cs_to_nat(ctx->lay, ctx->b * ctx->b, ctx->Dinv, dinv, ctx->stream);
+  return launch_check(ctx, "cpr_export_ilu");
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+// Internal declarations of the CPR-FGMRES library (not part of the C ABI).
+//
+// Storage order on the device.  Every per-cell array is colour-split
+// ("CS"): cell (i, j, k) with colour c = (i + j + k) & 1 (0 red, 1 black)
+// lives at  c * n/2 + (i >> 1) + (nx/2) * (j + ny * k).  Each colour is a
+// contiguous half, so a red-black half-sweep streams whole cache lines and
+// the +-y / +-z neighbours of a cell sit at a fixed offset in the other half.
+// A block array holds one plane of n values per (direction, row, column):
+// A[((d * b + r) * b + c) * n + cell], directions d = self, -x, +x, -y, +y,
+// -z, +z.  Multigrid levels whose nx is odd (only ever the coarsest) use the
+// natural order i + nx * (j + ny * k).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "cprmi.h"
+
+#define CPR_MAX_PVT 16
+#define CPR_MAX_WELLS_PERF 65536
+
+struct Lay {
+  int nx, ny, nz;
+  int n;     // cells
+  int half;  // nx / 2 (colour-split only)
+  int nh;    // n / 2 (colour-split only)
+  int cs;    // 1 colour-split, 0 natural
+};
+
+__host__ __device__ inline int lay_index(const Lay& L, int i, int j, int k) {
+  if (L.cs) return ((i + j + k) & 1) * L.nh + (i >> 1) + L.half * (j + L.ny * k);
+  return i + L.nx * (j + L.ny * k);
+}
+
+__host__ __device__ inline void lay_coords(const Lay& L, int t, int& i, int& j, int& k) {
+  if (L.cs) {
+    int c = t >= L.nh ? 1 : 0;
+    int r = t - c * L.nh;
+    int m = r % L.half;
+    int jk = r / L.half;
+    j = jk % L.ny;
+    k = jk / L.ny;
+    i = 2 * m + ((j + k + c) & 1);
+  } else {
+    i = t % L.nx;
+    int jk = t / L.nx;
+    j = jk % L.ny;
+    k = jk / L.ny;
+  }
+}
+
+// Neighbour offsets of the 7 block directions.
+__host__ __device__ inline void dir_offset(int d, int& di, int& dj, int& dk) {
+  di = (d == 1) ? -1 : (d == 2) ? 1 : 0;
+  dj = (d == 3) ? -1 : (d == 4) ? 1 : 0;
+  dk = (d == 5) ? -1 : (d == 6) ? 1 : 0;
+}
+
+// Index of neighbour d of cell (i, j, k) in layout L, or -1 outside.
+__host__ __device__ inline int lay_nbr(const Lay& L, int i, int j, int k, int d) {
+  int di, dj, dk;
+  dir_offset(d, di, dj, dk);
+  int a = i + di, b = j + dj, c = k + dk;
+  if (a < 0 || a >= L.nx || b < 0 || b >= L.ny || c < 0 || c >= L.nz) return -1;
+  return lay_index(L, a, b, c);
+}
+
+inline Lay make_lay(int nx, int ny, int nz, bool want_cs) {
+  Lay L;
+  L.nx = nx; L.ny = ny; L.nz = nz;
+  L.n = nx * ny * nz;
+  L.cs = (want_cs && (nx % 2 == 0)) ? 1 : 0;
+  L.half = L.cs ? nx / 2 : 0;
+  L.nh = L.cs ? L.n / 2 : 0;
+  return L;
+}
+
+// Fluid description passed to kernels by value.
+struct FluidDev {
+  int model;  // 2 oil-water, 3 black oil
+  int npvt;
+  double p_ref, rho_w_ref, rho_o_ref, rho_o_sc, rho_g_sc;
+  double c_w, c_o, c_r, mu_w, mu_o;
+  double s_wc, s_or, sg_den;
+  double pvt[6][CPR_MAX_PVT];
+};
+
+struct Perf {     // one perforated cell of a BHP well
+  int cell;       // colour-split index
+  int kind;       // CPR_WELL_INJECTOR / CPR_WELL_PRODUCER
+  double wi;      // Peaceman index (m^3)
+  double bhp;     // bar
+  double dzh;     // z_h - z (m): reference depth minus cell depth
+};
+
+struct MGLevel {
+  Lay lay;
+  double* A = nullptr;   // [7][n]
+  float* Af = nullptr;   // FP32 copy for the mixed-precision preconditioner
+  double* x = nullptr;   // correction
+  double* r = nullptr;   // right-hand side
+  float* xf = nullptr;
+  float* rf = nullptr;
+};
+
+struct cpr_ctx {
+  std::string err;
+  hipStream_t stream = nullptr;
+  cpr_grid_t grid;
+  FluidDev fl;
+  int b = 0;
+  Lay lay;
+  double phibar = 0.0;
+  double cell_vol = 0.0;
+  double rho_scale[3] = {0, 0, 0};  // component densities for the row scaling
+
+  // rock (colour-split)
+  double* poro = nullptr;      // [n]
+  double* tp = nullptr;        // [3][n] transmissibility to the +x/+y/+z neighbour
+  std::vector<Perf> perfs;
+  Perf* perfs_d = nullptr;
+
+  // Jacobian and assembly scratch (colour-split)
+  double* J = nullptr;         // [7][b][b][n]
+  double* props = nullptr;     // per-cell phase/mobility state for the flux kernel
+  double* vin = nullptr;       // [b][n] input permutation scratch
+  double* vin2 = nullptr;      // [b][n]
+  double* vout = nullptr;      // [b][n]
+
+  // CPR setup (colour-split)
+  cpr_options_t opt;
+  int setup_done = 0;
+  double* w = nullptr;         // [b][n]   quasi-IMPES weights
+  double* R0 = nullptr;        // [7][b][n] row 0 of the decoupled blocks
+  double* Dinv = nullptr;      // [b][b][n] inverted ILU diagonals
+  float* Jf = nullptr;         // FP32 copy of the decoupled blocks [7][b][b][n]
+  float* Dinvf = nullptr;
+  std::vector<MGLevel> levels;
+  double* cinv = nullptr;      // dense inverse of the coarsest level (column major)
+  float* cinvf = nullptr;
+  double* gj_work = nullptr;   // Gauss-Jordan workspace
+  int* flag = nullptr;         // device status flag (singular / non-finite)
+  int qimpes_bad = 0;
+
+  // Krylov workspace (colour-split)
+  int mcap = 0;                // restart capacity of V / Z
+  double* V = nullptr;         // [m+1][b*n]
+  double* Z = nullptr;         // [m][b*n]
+  double* Y = nullptr;         // [b][n] ILU forward result
+  double* rp = nullptr;        // [n] decoupled pressure residual
+  double* xs = nullptr;        // [b][n] solution (colour-split)
+  double* rs = nullptr;        // [b][n] right-hand side (colour-split)
+  double* tmp = nullptr;       // [b][n]
+  float* vf = nullptr;         // [b][n] FP32 preconditioner input
+  float* zf = nullptr;         // [b][n] FP32 preconditioner output
+  float* Yf = nullptr;
+  float* rpf = nullptr;
+  double* part = nullptr;      // reduction partials [64][nblk]
+  double* hdev = nullptr;      // [4*64] device Hessenberg scratch
+  double* hhost = nullptr;     // pinned host mirror
+  int nblk = 0;
+};
+
+// ---------------------------------------------------------------- helpers
+#define CPR_TRY(expr)                                                         \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess) return set_hip_err(ctx, e_, #expr);                 \
+  } while (0)
+
+int set_err(cpr_ctx* ctx, int code, const std::string& msg);
+int set_hip_err(cpr_ctx* ctx, hipError_t e, const char* what);
+int launch_check(cpr_ctx* ctx, const char* what);
+
+inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------- launchers
+// layout.hip
+void launch_nat_to_cs(const Lay& L, int planes, const double* src, double* dst, hipStream_t s);
+void launch_cs_to_nat(const Lay& L, int planes, const double* src, double* dst, hipStream_t s);
+
+// assemble.hip
+void launch_transmissibility(const Lay& L, const cpr_grid_t& g, const double* perm_nat,
+                             double* tp, hipStream_t s);
+void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, double dt_days,
+                     double* rhs_cs);
+double host_pvt(const FluidDev& f, int row, double p);
+int props_planes(int model);
+
+// spmv.hip
+void launch_spmv(int b, const Lay& L, const double* A, const double* x, double* y,
+                 const double* rhs, hipStream_t s);
+
+// setup.hip
+int setup_cpr(cpr_ctx* ctx);
+
+// apply.hip
+void precond_apply(cpr_ctx* ctx, const double* v, double* z);
+
+// krylov.hip
+int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st);
+void launch_newton_update(int b, int n, double* x, const double* dx, hipStream_t s);
+int reduce_dot(cpr_ctx* ctx, const double* a, const double* b, long len, double* out);

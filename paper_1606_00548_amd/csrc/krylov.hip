@@ -1,0 +1,305 @@
+// Restarted flexible GMRES with classical Gram-Schmidt twice (CGS2),
+// right-preconditioned by CPR; stops when ||b - A dx|| <= rtol ||b||
+// (eq. (13) with a fixed forcing term).
+//
+// Device side: the Krylov basis V[m+1][b*n] and the preconditioned
+// directions Z[m][b*n] stay in HBM; every reduction is a deterministic two-
+// stage sum (fixed per-block partials, then a fixed-order tree), so two runs
+// give identical bits.  Host side: the Givens rotations and the small
+// least-squares problem, one D2H copy of the Hessenberg column per
+// iteration (the only synchronisation in the loop).
+//
+// Per Arnoldi step j (nv = j+1 basis vectors):
+//   z_j = M^-1 v_j ; w = A z_j            -> written into V[j+1]
+//   h  = V^T w  (partials, reduce)
+//   w -= V h, h' = V^T w (fused: each block updates its slice, then dots it)
+//   w -= V h', ||w||^2 (fused)
+//   h_{j+1,j} = ||w||; v_{j+1} = w / h_{j+1,j}
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int KB = 256;        // threads per block of the vector kernels
+constexpr int CHUNK = 8;       // basis vectors handled per pass
+constexpr double BREAKDOWN = 1e-14;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Block-reduce CHUNK values; thread 0 of the block gets the totals in out.
+__device__ inline void block_sum_chunk(double (&acc)[CHUNK], int cnt, double* sh, double* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < CHUNK; ++q) {
+    if (q < cnt) {
+      double v = wave_sum(acc[q]);
+      if (lane == 0) sh[q * (KB / 64) + wid] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < cnt) {
+    double s = 0.0;
+    for (int w = 0; w < KB / 64; ++w) s += sh[threadIdx.x * (KB / 64) + w];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// part[k][block] = sum over this block's slice of V_k . w, k < nv.
+// If h != nullptr, first w -= sum_k hprev[k] V_k on the slice (and store w).
+// If nrm != nullptr, also part[nv][block] = slice of ||w||^2 (after update).
+__global__ __launch_bounds__(KB) void orth_kernel(long len, int nv, const double* __restrict__ V,
+                                                  size_t stride, double* __restrict__ w,
+                                                  const double* __restrict__ hprev, int do_dots,
+                                                  int do_norm, double* __restrict__ part, int nblk) {
+  __shared__ double sh[CHUNK * (KB / 64)];
+  __shared__ double tot[CHUNK];
+  __shared__ double hs[64];
+  if (hprev && threadIdx.x < nv) hs[threadIdx.x] = hprev[threadIdx.x];
+  __syncthreads();
+  // this block's contiguous slice
+  long per = (len + nblk - 1) / nblk;
+  long beg = (long)blockIdx.x * per;
+  long end = beg + per < len ? beg + per : len;
+  if (hprev) {
+    for (long e = beg + threadIdx.x; e < end; e += KB) {
+      double x = w[e];
+      for (int k = 0; k < nv; ++k) x -= hs[k] * V[k * stride + e];
+      w[e] = x;
+    }
+    // the same thread re-reads only the elements it wrote: no block barrier needed
+  }
+  if (do_dots) {
+    for (int k0 = 0; k0 < nv; k0 += CHUNK) {
+      int cnt = nv - k0 < CHUNK ? nv - k0 : CHUNK;
+      double acc[CHUNK];
+#pragma unroll
+      for (int q = 0; q < CHUNK; ++q) acc[q] = 0.0;
+      for (long e = beg + threadIdx.x; e < end; e += KB) {
+        double x = w[e];
+#pragma unroll
+        for (int q = 0; q < CHUNK; ++q)
+          if (q < cnt) acc[q] += V[(k0 + q) * stride + e] * x;
+      }
+      block_sum_chunk(acc, cnt, sh, tot);
+      if (threadIdx.x < cnt) part[(size_t)(k0 + threadIdx.x) * nblk + blockIdx.x] = tot[threadIdx.x];
+    }
+  }
+  if (do_norm) {
+    double acc[CHUNK];
+#pragma unroll
+    for (int q = 0; q < CHUNK; ++q) acc[q] = 0.0;
+    for (long e = beg + threadIdx.x; e < end; e += KB) {
+      double x = w[e];
+      acc[0] += x * x;
+    }
+    block_sum_chunk(acc, 1, sh, tot);
+    if (threadIdx.x == 0) part[(size_t)nv * nblk + blockIdx.x] = tot[0];
+  }
+}
+
+// out[k] (+)= sum_b part[k][b], one block per k, fixed order.
+__global__ __launch_bounds__(KB) void reduce_kernel(const double* __restrict__ part, int nblk,
+                                                    double* __restrict__ out, const double* __restrict__ add) {
+  __shared__ double sh[CHUNK * (KB / 64)];
+  __shared__ double tot[CHUNK];
+  int k = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += KB) s += part[(size_t)k * nblk + b];
+  double acc[CHUNK];
+#pragma unroll
+  for (int q = 0; q < CHUNK; ++q) acc[q] = 0.0;
+  acc[0] = s;
+  block_sum_chunk(acc, 1, sh, tot);
+  if (threadIdx.x == 0) out[k] = tot[0] + (add ? add[k] : 0.0);
+}
+
+__global__ void scale_kernel(long len, double a, const double* __restrict__ x, double* __restrict__ y) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < len) y[e] = a * x[e];
+}
+
+// x += sum_k y[k] Z_k
+__global__ void maxpy_kernel(long len, int nk, const double* __restrict__ Z, size_t stride,
+                             const double* __restrict__ y, double* __restrict__ x) {
+  __shared__ double ys[64];
+  if (threadIdx.x < nk) ys[threadIdx.x] = y[threadIdx.x];
+  __syncthreads();
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  double s = x[e];
+  for (int k = 0; k < nk; ++k) s += ys[k] * Z[k * stride + e];
+  x[e] = s;
+}
+
+__global__ void zero_kernel(long len, double* __restrict__ x) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < len) x[e] = 0.0;
+}
+
+// Newton update: x += dx, saturation changes chopped to |dS| <= 0.2,
+// saturations clamped to [0, 1].
+__global__ void newton_update_kernel(int b, int n, double* __restrict__ x, const double* __restrict__ dx) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  x[t] = x[t] + dx[t];
+  for (int s = 1; s < b; ++s) {
+    size_t o = (size_t)s * n + t;
+    double d = dx[o];
+    d = d < -0.2 ? -0.2 : (d > 0.2 ? 0.2 : d);
+    double v = x[o] + d;
+    x[o] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+  }
+}
+
+}  // namespace
+
+void launch_newton_update(int b, int n, double* x, const double* dx, hipStream_t s) {
+  newton_update_kernel<<<div_up(n, 256), 256, 0, s>>>(b, n, x, dx);
+}
+
+// Dot product of two device vectors of length len into *out (host).  Syncs.
+int reduce_dot(cpr_ctx* ctx, const double* a, const double* b, long len, double* out) {
+  hipStream_t s = ctx->stream;
+  // reuse the orthogonalisation kernel with V = a (one vector), w = b
+  orth_kernel<<<ctx->nblk, KB, 0, s>>>(len, 1, a, 0, const_cast<double*>(b), nullptr, 1, 0, ctx->part,
+                                       ctx->nblk);
+  reduce_kernel<<<1, KB, 0, s>>>(ctx->part, ctx->nblk, ctx->hdev, nullptr);
+  CPR_TRY(hipGetLastError());
+  CPR_TRY(hipMemcpyAsync(ctx->hhost, ctx->hdev, sizeof(double), hipMemcpyDeviceToHost, s));
+  CPR_TRY(hipStreamSynchronize(s));
+  *out = ctx->hhost[0];
+  return CPR_OK;
+}
+
+// ctx->rs holds the right-hand side, ctx->xs receives the solution
+// (colour-split).  Mirrors the oracle's FGMRES step for step.
+int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
+  hipStream_t s = ctx->stream;
+  const int b = ctx->b;
+  const long len = (long)b * ctx->lay.n;
+  const size_t stride = (size_t)len;
+  const int m = ctx->opt.restart;
+  const double rtol = ctx->opt.rtol;
+  const int max_iter = ctx->opt.max_iter;
+  const int nblk = ctx->nblk;
+  const int eb = div_up(len, 256);
+  double* x = ctx->xs;
+  double* r = ctx->tmp;
+  cpr_stats_t S = {};
+  S.mg_levels = (int)ctx->levels.size();
+  S.qimpes_fallback = ctx->qimpes_bad;
+
+  zero_kernel<<<eb, 256, 0, s>>>(len, x);
+  double bb;
+  int rc = reduce_dot(ctx, ctx->rs, ctx->rs, len, &bb);
+  if (rc) return rc;
+  double bnorm = std::sqrt(bb);
+  S.bnorm = bnorm;
+  if (!std::isfinite(bnorm)) {
+    if (st) *st = S;
+    return set_err(ctx, CPR_ENONFINITE, "non-finite right-hand side");
+  }
+  if (bnorm == 0.0) {
+    S.converged = 1;
+    if (st) *st = S;
+    return CPR_OK;
+  }
+  CPR_TRY(hipMemcpyAsync(r, ctx->rs, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), col(m + 1);
+  int its = 0;
+  int result = CPR_NOT_CONVERGED;
+  double* hd = ctx->hdev;  // h1 [0,64), h1+h2 [64,128), ||w||^2 [128], h2 [192,256), y [256,320)
+  while (true) {
+    double rr;
+    rc = reduce_dot(ctx, r, r, len, &rr);
+    if (rc) return rc;
+    double beta = std::sqrt(rr);
+    S.true_rel = beta / bnorm;
+    if (!std::isfinite(beta)) {
+      if (st) *st = S;
+      return set_err(ctx, CPR_ENONFINITE, "non-finite residual");
+    }
+    if (beta <= rtol * bnorm) { result = CPR_OK; break; }
+    if (its >= max_iter) break;
+    scale_kernel<<<eb, 256, 0, s>>>(len, 1.0 / beta, r, ctx->V);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    bool breakdown_stop = false;
+    for (int j = 0; j < m; ++j) {
+      double* vj = ctx->V + (size_t)j * stride;
+      double* zj = ctx->Z + (size_t)j * stride;
+      double* w = ctx->V + (size_t)(j + 1) * stride;
+      precond_apply(ctx, vj, zj);
+      launch_spmv(b, ctx->lay, ctx->J, zj, w, nullptr, s);
+      its += 1;
+      int nv = j + 1;
+      // CGS pass 1: h1 = V^T w
+      orth_kernel<<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, nullptr, 1, 0, ctx->part, nblk);
+      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd, nullptr);
+      // w -= V h1 ; h2 = V^T w
+      orth_kernel<<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, hd, 1, 0, ctx->part, nblk);
+      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd);   // h = h1 + h2
+      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 192, nullptr);   // h2 alone
+      // w -= V h2 ; ||w||^2
+      orth_kernel<<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, hd + 192, 0, 1, ctx->part, nblk);
+      reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr);
+      CPR_TRY(hipGetLastError());
+      CPR_TRY(hipMemcpyAsync(ctx->hhost, hd + 64, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
+      CPR_TRY(hipStreamSynchronize(s));
+      double hn = std::sqrt(ctx->hhost[64]);
+      for (int i = 0; i <= m; ++i) col[i] = 0.0;
+      for (int i = 0; i < nv; ++i) col[i] = ctx->hhost[i];
+      col[j + 1] = hn;
+      double az = 0.0;
+      for (int i = 0; i <= j + 1; ++i) az += col[i] * col[i];
+      az = std::sqrt(az);
+      if (!std::isfinite(az)) {
+        if (st) *st = S;
+        return set_err(ctx, CPR_ENONFINITE, "non-finite Hessenberg column");
+      }
+      for (int i = 0; i < j; ++i) {
+        double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      double den = std::hypot(col[j], col[j + 1]);
+      if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
+      else { cs[j] = col[j] / den; sn[j] = col[j + 1] / den; }
+      col[j] = den;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      for (int i = 0; i <= m; ++i) H[(size_t)i * m + j] = col[i];
+      k = j + 1;
+      if (std::fabs(g[j + 1]) <= rtol * bnorm || its >= max_iter) break;
+      if (hn <= BREAKDOWN * az) { breakdown_stop = true; break; }
+      scale_kernel<<<eb, 256, 0, s>>>(len, 1.0 / hn, w, w);
+    }
+    (void)breakdown_stop;
+    // back substitution H[:k,:k] y = g[:k]
+    for (int i = k - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int c = i + 1; c < k; ++c) t -= H[(size_t)i * m + c] * y[c];
+      y[i] = t / H[(size_t)i * m + i];
+    }
+    for (int i = 0; i < k; ++i) ctx->hhost[256 + i] = y[i];
+    CPR_TRY(hipMemcpyAsync(hd + 256, ctx->hhost + 256, k * sizeof(double), hipMemcpyHostToDevice, s));
+    maxpy_kernel<<<eb, 256, 0, s>>>(len, k, ctx->Z, stride, hd + 256, x);
+    S.cycles += 1;
+    S.est_rel = std::fabs(g[k]) / bnorm;
+    launch_spmv(b, ctx->lay, ctx->J, x, r, ctx->rs, s);
+  }
+  S.iterations = its;
+  S.converged = result == CPR_OK;
+  if (st) *st = S;
+  return result;
+}

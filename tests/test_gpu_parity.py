@@ -1,0 +1,233 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (FP64 on both sides, different summation orders):
+  * assembly: per entry |gpu - oracle| <= 1e-11 |oracle| + 1e-13 max|row|
+    (exp/division differ by an ulp; face sums are added in another order);
+  * SpMV, decoupling weights, Galerkin levels: 1e-13 relative to the row scale;
+  * ILU diagonal inverses: 1e-10 (block inversion amplifies by cond(D'));
+  * one preconditioner application: 1e-9 in norm (the coarsest solve uses an
+    explicit inverse on the GPU and LU on the CPU);
+  * FGMRES: the same number of iterations, ||x_gpu - x_oracle|| <= 1e-8
+    ||x_oracle||, and both true relative residuals <= rtol = 1e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle import cpr, krylov, model, newton
+from paper_1606_00548_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _solver(case):
+    from paper_1606_00548_amd import cprmi
+    return cprmi.Solver.from_case(case)
+
+
+CASES = {
+    "ow-40x18x7": lambda: synth.oil_water_lognormal(40, 18, 7, seed=101),
+    "bo-34x20x6": lambda: synth.black_oil_layered(34, 20, 6, seed=102),
+    "bo-chan-48x24x8": lambda: synth.black_oil_channelised(48, 24, 8, seed=103),
+    "ow-32x32x8": lambda: synth.oil_water_lognormal(),
+}
+
+
+def _oracle_system(case, x):
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                          case["x_old"], x, case["dt"])
+    return J, -R
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def system(request):
+    case = CASES[request.param]()
+    x = synth.random_state_perturbation(case, 17) if request.param != "ow-32x32x8" else case["x"]
+    J, b = _oracle_system(case, x)
+    print(f"[gpu-parity] case {request.param}", flush=True)
+    return request.param, case, x, J, b
+
+
+def test_assembly_matches_oracle(system):
+    name, case, x, J, b = system
+    s = _solver(case)
+    rhs = s.assemble(_gpu(case["x_old"]), _gpu(x), case["dt"])
+    Jg = _np(s.export_jacobian())
+    rg = _np(rhs)
+    rowscale = np.abs(J).max(axis=(0, 2), keepdims=True)     # per (row, cell)
+    assert np.all(np.abs(Jg - J) <= 1e-11 * np.abs(J) + 1e-13 * rowscale)
+    bscale = np.abs(b).max()
+    assert np.all(np.abs(rg - b) <= 1e-10 * np.abs(b) + 1e-12 * bscale)
+
+
+def test_spmv_matches_oracle(system):
+    name, case, x, J, b = system
+    s = _solver(case)
+    s.import_jacobian(J)
+    v = np.random.default_rng(5).standard_normal(b.shape)
+    y = _np(s.spmv(_gpu(v)))
+    ref = cpr.block_spmv(J, v)
+    scale = np.abs(J).max(axis=(0, 2)) * np.abs(v).max()
+    assert np.all(np.abs(y - ref) <= 1e-13 * scale)
+
+
+def test_setup_products_match_oracle(system):
+    name, case, x, J, b = system
+    s = _solver(case)
+    s.import_jacobian(J)
+    s.setup()
+    pc = cpr.cpr_setup(J)
+    w = _np(s.export_qimpes())
+    assert np.allclose(w, pc["w"], rtol=1e-12, atol=1e-14)
+    levels = pc["mg"]["levels"]
+    for l, A in enumerate(levels):
+        assert s.mg_level_shape(l) == A.shape[1:]
+        Ag = _np(s.export_mg_level(l))
+        assert np.all(np.abs(Ag - A) <= 1e-12 * np.abs(A).max(axis=0))
+    assert s.mg_level_shape(len(levels)) is None
+    D = _np(s.export_ilu())
+    scale = np.abs(pc["Dinv"]).max(axis=(0, 1))
+    assert np.all(np.abs(D - pc["Dinv"]) <= 1e-10 * scale)
+
+
+def test_precond_apply_matches_oracle(system):
+    name, case, x, J, b = system
+    s = _solver(case)
+    s.import_jacobian(J)
+    s.setup()
+    pc = cpr.cpr_setup(J)
+    v = b / np.linalg.norm(b)
+    z = _np(s.precond(_gpu(v)))
+    ref = cpr.cpr_apply(pc, v)
+    assert np.linalg.norm(z - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_fgmres_matches_oracle(system):
+    name, case, x, J, b = system
+    s = _solver(case)
+    s.import_jacobian(J)
+    s.setup()
+    dx, st = s.solve(_gpu(b))
+    pc = cpr.cpr_setup(J)
+    xo, so = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), b)
+    xg = _np(dx)
+    assert st["status"] == 0 and so["converged"]
+    assert st["iterations"] == so["iterations"]
+    assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)
+    bn = np.linalg.norm(b)
+    assert np.linalg.norm(b - cpr.block_spmv(J, xg)) <= 1e-6 * bn
+    assert abs(st["true_rel"] - so["true_rel"]) <= 1e-9
+
+
+@pytest.mark.parametrize("k", [1, 5, 30, 60])
+def test_fgmres_fixed_iteration_path(k):
+    # rtol = 0 forces exactly k Arnoldi steps: separates path divergence
+    # from threshold effects (restart at 30 is crossed by k = 60)
+    case = CASES["bo-34x20x6"]()
+    x = synth.random_state_perturbation(case, 17)
+    J, b = _oracle_system(case, x)
+    s = _solver(case)
+    s.import_jacobian(J)
+    s.setup(rtol=0.0, max_iter=k)
+    dx, st = s.solve(_gpu(b))
+    pc = cpr.cpr_setup(J)
+    xo, so = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), b,
+                           rtol=0.0, max_iter=k)
+    assert st["iterations"] == so["iterations"] == k
+    assert st["status"] == 1
+    xg = _np(dx)
+    assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+def test_newton_step_matches_oracle():
+    case = CASES["bo-34x20x6"]()
+    s = _solver(case)
+    from paper_1606_00548_amd import cprmi
+    xg = _gpu(case["x"])
+    dxg, st = cprmi.newton_step(s, _gpu(case["x_old"]), xg, case["dt"])
+    xn, dxo, so, _ = newton.newton_step(case["grid"], case["fluid"], case["perm"], case["poro"],
+                                        case["wells"], case["x_old"], case["x"], case["dt"])
+    assert st["iterations"] == so["iterations"]
+    assert np.linalg.norm(_np(dxg) - dxo) <= 1e-8 * np.linalg.norm(dxo)
+    assert np.allclose(_np(xg), xn, rtol=1e-10, atol=1e-10)
+
+
+def test_zero_rhs_and_nonfinite_rhs():
+    from paper_1606_00548_amd import cprmi
+    case = CASES["ow-40x18x7"]()
+    s = _solver(case)
+    s.assemble(_gpu(case["x_old"]), _gpu(case["x"]), case["dt"])
+    s.setup()
+    dx, st = s.solve(s.vector())
+    assert st["iterations"] == 0 and st["status"] == 0
+    assert float(dx.abs().max()) == 0.0
+    bad = s.vector()
+    bad[0, 1, 2, 3] = float("nan")
+    with pytest.raises(cprmi.CPRError) as e:
+        s.solve(bad)
+    assert e.value.code == -5
+
+
+def test_singular_block_is_reported():
+    from paper_1606_00548_amd import cprmi
+    case = CASES["ow-40x18x7"]()
+    J, b = _oracle_system(case, case["x"])
+    J = J.copy()
+    J[0, :, :, 3, 4, 5] = 0.0
+    s = _solver(case)
+    s.import_jacobian(J)
+    with pytest.raises(cprmi.CPRError) as e:
+        s.setup()
+    assert e.value.code == -4
+
+
+def test_invalid_grid_rejected():
+    from paper_1606_00548_amd import cprmi
+    case = synth.oil_water_lognormal(7, 4, 2, seed=1)
+    with pytest.raises(cprmi.CPRError) as e:
+        _solver(case)
+    assert e.value.code == -1
+
+
+def test_solve_is_deterministic():
+    case = CASES["bo-chan-48x24x8"]()
+    J, b = _oracle_system(case, case["x"])
+    s = _solver(case)
+    s.import_jacobian(J)
+    s.setup()
+    a, _ = s.solve(_gpu(b))
+    a = _np(a).copy()
+    c, _ = s.solve(_gpu(b))
+    assert np.array_equal(a, _np(c))
+
+
+def test_full_size_black_oil_step():
+    # the benchmark's workload (128 x 128 x 32, b = 3): the whole assembled
+    # system against the oracle, then the solve against the oracle's path
+    case = synth.black_oil_layered()
+    print("[gpu-parity] full-size 128x128x32 black oil", flush=True)
+    s = _solver(case)
+    rhs = s.assemble(_gpu(case["x_old"]), _gpu(case["x"]), case["dt"])
+    J, b = _oracle_system(case, case["x"])
+    Jg = _np(s.export_jacobian())
+    rowscale = np.abs(J).max(axis=(0, 2), keepdims=True)
+    assert np.all(np.abs(Jg - J) <= 1e-11 * np.abs(J) + 1e-13 * rowscale)
+    s.setup()
+    dx, st = s.solve(rhs)
+    xg = _np(dx)
+    bn = np.linalg.norm(b)
+    assert st["status"] == 0
+    assert np.linalg.norm(b - cpr.block_spmv(J, xg)) <= 1e-6 * bn
+    pc = cpr.cpr_setup(J)
+    xo, so = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), b)
+    assert st["iterations"] == so["iterations"]
+    assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)

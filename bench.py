@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark: wall time of one inexact Newton step of the CPR-FGMRES hot path.
+
+One step = assemble the Jacobian and right-hand side, set up the CPR
+preconditioner, solve with FGMRES(30) to a relative residual of 1e-6, and
+update the state (Algorithm 1, one iteration), on the saturated black-oil
+workload of 128 x 128 x 32 cells (3x3 blocks, layered lognormal
+permeability with kz/kx = 0.1, inverted five-spot, 1-day step), inputs
+already resident in GPU memory.  Every step restarts from the same initial
+state so the timed steps do identical work.
+
+Prints one JSON line: the step time, a roofline entry for the dominant
+kernel (algorithmic bytes over the average launch duration, measured with
+HIP events on the library's stream during the timed steps), and the CPU
+oracle's time for the same step as a reference baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CPR-GMRES s/Newton step + GB/s at 1e-6 rel resid; plain FP64 vs mixed+learned"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision):
+    """Bytes one launch of a kernel class must move at minimum, summed over
+    the launches of one Newton step (iterations_per_cycle: Arnoldi steps of
+    each restart cycle; the SpMV also runs once per cycle for the true
+    residual, which reads the right-hand side as well)."""
+    s = 8
+    if kclass == "spmv":
+        per = (7 * b * b + 2 * b) * s * n
+        its = sum(iterations_per_cycle)
+        return its * per + len(iterations_per_cycle) * (per + b * s * n), its + len(iterations_per_cycle)
+    if kclass == "orth":
+        tot, launches = 0, 0
+        for k in iterations_per_cycle:
+            for j in range(k):
+                nv = j + 1
+                # dots: V (nv) + w; update+dots: V + w read + w write;
+                # update+norm: V + w read + w write
+                tot += ((nv + 1) + (nv + 2) + (nv + 2)) * b * n * s
+                launches += 3
+        return tot, launches
+    raise ValueError(kclass)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--kernel", default="spmv", choices=["spmv", "orth"],
+                    help="kernel class reported in the roofline entry")
+    ap.add_argument("--nx", type=int, default=128)
+    ap.add_argument("--ny", type=int, default=128)
+    ap.add_argument("--nz", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1606_00548_amd import cprmi, synth
+
+    case = synth.black_oil_layered(args.nx, args.ny, args.nz)
+    n = args.nx * args.ny * args.nz
+    b = 3
+    solver = cprmi.Solver.from_case(case)
+    x_old = torch.as_tensor(case["x_old"]).cuda().contiguous()
+    x0 = torch.as_tensor(case["x"]).cuda().contiguous()
+    x = x0.clone()
+    opts = cprmi.default_options(precision=args.precision)
+
+    def step():
+        x.copy_(x0)
+        dx, st = cprmi.newton_step(solver, x_old, x, case["dt"], opts)
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    solver.profile_kernel(args.kernel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, kernel_ms = solver.profile_read()
+    solver.profile_kernel(None)
+    sec_per_step = (t1 - t0) / args.steps
+    if not all(st["status"] == 0 and st["true_rel"] <= 1e-6 for st in stats):
+        print("a timed solve did not reach the 1e-6 true relative residual", file=sys.stderr)
+        sys.exit(1)
+
+    # per-phase breakdown of one more (untimed) step
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    x.copy_(x0)
+    ev[0].record()
+    rhs = solver.assemble(x_old, x, case["dt"])
+    ev[1].record()
+    solver.setup(opts)
+    ev[2].record()
+    dx, st = solver.solve(rhs)
+    ev[3].record()
+    solver.newton_update(x, dx)
+    ev[4].record()
+    torch.cuda.synchronize()
+    phases = {k: ev[i].elapsed_time(ev[i + 1]) for i, k in
+              enumerate(["assemble", "setup", "solve", "update"])}
+    # restart-cycle lengths of the timed solves (identical every step)
+    its, cycles = st["iterations"], st["cycles"]
+    per_cycle = [30] * (cycles - 1) + [its - 30 * (cycles - 1)] if cycles else []
+    alg_bytes, alg_launches = algorithmic_bytes(args.kernel, b, n, per_cycle, args.precision)
+    avg_ms = kernel_ms / max(launches, 1)
+    achieved = (alg_bytes / alg_launches) / (avg_ms * 1e-3) / 1e9 if launches else None
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"{args.kernel}_traffic.json")
+    if os.path.exists(tfile):
+        info = json.load(open(tfile))
+        if info.get("workload_cells") == n and info.get("source_sha") == _kernel_sha(args.kernel):
+            traffic = info.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": args.kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": traffic, "launches_sampled": launches,
+                "avg_launch_us": avg_ms * 1e3,
+                "algorithmic_bytes_per_launch": alg_bytes / max(alg_launches, 1)}
+    if launches != alg_launches * args.steps:
+        roofline["note"] = f"sampled {launches} launches, expected {alg_launches * args.steps}"
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(case)
+    out = {
+        "metric": METRIC, "value": sec_per_step, "unit": "s/Newton step", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec_per_step * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"black-oil layered {args.nx}x{args.ny}x{args.nz} "
+                               f"({n} cells, 3x3 blocks), one Newton step, FGMRES(30) to 1e-6",
+                   "cells": n, "block": b, "precision": args.precision, "restart": 30, "rtol": 1e-6},
+        "fgmres_iterations": its, "restart_cycles": cycles, "true_rel": st["true_rel"],
+        "phases_ms": phases, "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def _kernel_sha(kclass):
+    import hashlib
+    f = {"spmv": "spmv.hip", "orth": "krylov.hip"}[kclass]
+    p = os.path.join(ROOT, "paper_1606_00548_amd", "csrc", f)
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def cpu_baseline(case):
+    """The FP64 oracle's time for the same Newton step (single thread)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import newton
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, _, st, _ = newton.newton_step(case["grid"], case["fluid"], case["perm"], case["poro"],
+                                         case["wells"], case["x_old"], case["x"], case["dt"])
+        t1 = time.perf_counter()
+    return {"value": t1 - t0, "unit": "s/Newton step", "cores": 1, "kind": "oracle",
+            "sample": "one full Newton step (assemble, CPR setup, FGMRES(30) to 1e-6, update) "
+                      "of the same workload, numpy/scipy single-threaded",
+            "iterations": st["iterations"]}
+
+
+if __name__ == "__main__":
+    main()

@@ -187,6 +187,22 @@ int cpr_mg_level_shape(const cpr_ctx_t* ctx, int level, int* nx, int* ny, int* n
 int cpr_export_mg_level(cpr_ctx_t* ctx, int level, double* a7);
 int cpr_export_ilu(cpr_ctx_t* ctx, double* dinv);
 
+/* Kernel-duration sampling, for measurement.  While a class is selected,
+ * every launch of that kernel class inside the library is bracketed by a
+ * pair of HIP events on the context's stream (up to 8192 launches are
+ * kept).  cpr_profile_read synchronises the stream, returns the number of
+ * sampled launches and their summed duration in milliseconds, and clears
+ * the samples.  kclass -1 switches sampling off. */
+enum {
+  CPR_KCLASS_SPMV = 0,      /* block SpMV / true residual                 */
+  CPR_KCLASS_ORTH = 1,      /* CGS2 dot / update / norm passes            */
+  CPR_KCLASS_SMOOTH = 2,    /* red-black Gauss-Seidel half-sweeps         */
+  CPR_KCLASS_ILU = 3,       /* stage-2 residual + block-ILU colour sweeps */
+  CPR_KCLASS_ASSEMBLE = 4   /* cell-centric flux / Jacobian kernel        */
+};
+int cpr_profile_kernel(cpr_ctx_t* ctx, int kclass);
+int cpr_profile_read(cpr_ctx_t* ctx, int* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,7 +64,9 @@ class Stats(ctypes.Structure):
 EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error", "cpr_block_size",
            "cpr_num_cells", "assemble_jacobian", "cpr_import_jacobian", "cpr_export_jacobian",
            "cpr_setup", "cpr_gmres_solve", "cpr_newton_update", "cpr_spmv", "cpr_precond_apply",
-           "cpr_export_qimpes", "cpr_mg_level_shape", "cpr_export_mg_level", "cpr_export_ilu"]
+           "cpr_export_qimpes", "cpr_mg_level_shape", "cpr_export_mg_level", "cpr_export_ilu",
+           "cpr_profile_kernel", "cpr_profile_read"]
+KCLASS = {"spmv": 0, "orth": 1, "smooth": 2, "ilu": 3, "assemble": 4}
 
 
 def load():
@@ -98,6 +100,8 @@ def load():
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.cpr_export_mg_level.argtypes = [P, ctypes.c_int, P]
     lib.cpr_export_ilu.argtypes = [P, P]
+    lib.cpr_profile_kernel.argtypes = [P, ctypes.c_int]
+    lib.cpr_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
     _lib = lib
     return lib
 
@@ -249,6 +253,17 @@ class Solver:
         a = torch.empty((7,) + shape, dtype=torch.float64, device="cuda")
         self._check(self.lib.cpr_export_mg_level(self.ctx, level, _ptr(a)))
         return a
+
+    def profile_kernel(self, kclass):
+        """Sample every launch of one kernel class with HIP events (None: off)."""
+        k = -1 if kclass is None else KCLASS[kclass]
+        self._check(self.lib.cpr_profile_kernel(self.ctx, k))
+
+    def profile_read(self):
+        """(launches, total milliseconds) sampled since the last read; syncs."""
+        n, ms = ctypes.c_int(), ctypes.c_double()
+        self._check(self.lib.cpr_profile_read(self.ctx, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     def export_ilu(self):
         d = torch.empty((self.b, self.b) + self.shape, dtype=torch.float64, device="cuda")

@@ -272,13 +272,21 @@ void vcycle(cpr_ctx* ctx, size_t l) {
   T* x = Pre<T>::x(L);
   const T* r = Pre<T>::r(L);
   int nh = div_up(L.lay.nh, 256);
+  prof_begin(ctx, CPR_KCLASS_SMOOTH);
   gs_kernel<T><<<nh, 256, 0, s>>>(L.lay, 0, 1, A, r, x);
+  prof_end(ctx, CPR_KCLASS_SMOOTH);
+  prof_begin(ctx, CPR_KCLASS_SMOOTH);
   gs_kernel<T><<<nh, 256, 0, s>>>(L.lay, 1, 0, A, r, x);
+  prof_end(ctx, CPR_KCLASS_SMOOTH);
   resid_restrict_kernel<T><<<div_up(C.lay.n, 256), 256, 0, s>>>(L.lay, C.lay, A, r, x, Pre<T>::r(C));
   vcycle<T>(ctx, l + 1);
   prolong_red_kernel<T><<<nh, 256, 0, s>>>(L.lay, C.lay, (T)ctx->opt.mg_alpha, Pre<T>::x(C), x);
+  prof_begin(ctx, CPR_KCLASS_SMOOTH);
   gs_kernel<T><<<nh, 256, 0, s>>>(L.lay, 1, 0, A, r, x);
+  prof_end(ctx, CPR_KCLASS_SMOOTH);
+  prof_begin(ctx, CPR_KCLASS_SMOOTH);
   gs_kernel<T><<<nh, 256, 0, s>>>(L.lay, 0, 0, A, r, x);
+  prof_end(ctx, CPR_KCLASS_SMOOTH);
 }
 
 template <int B, typename T>
@@ -295,9 +303,15 @@ void apply_impl(cpr_ctx* ctx, const double* v, double* z) {
   const T* Dinv = Pre<T>::Dinv(ctx);
   T* Y = Pre<T>::Y(ctx);
   int nh = div_up(L.nh, 256);
+  prof_begin(ctx, CPR_KCLASS_ILU);
   stage2_red_fwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, v, rp, dp, Y);
+  prof_end(ctx, CPR_KCLASS_ILU);
+  prof_begin(ctx, CPR_KCLASS_ILU);
   stage2_black_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, v, rp, dp, Y, z);
+  prof_end(ctx, CPR_KCLASS_ILU);
+  prof_begin(ctx, CPR_KCLASS_ILU);
   stage2_red_bwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, dp, Y, z);
+  prof_end(ctx, CPR_KCLASS_ILU);
 }
 
 // FP32 copies: decoupled blocks (row 0 from R0), ILU diagonals, MG levels.

@@ -422,16 +422,20 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
   hipStream_t s = ctx->stream;
   if (ctx->fl.model == 2) {
     props_kernel<2><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, x_cs, ctx->props);
+    prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
     flux_kernel<2><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt,
                                       sc[0], sc[1], sc[2], ctx->poro, ctx->tp, xold_cs, x_cs,
                                       ctx->props, ctx->J, rhs_cs);
+    prof_end(ctx, CPR_KCLASS_ASSEMBLE);
     if (np) well_kernel<2><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, sc[0], sc[1],
                                                         sc[2], ctx->poro, x_cs, ctx->J, rhs_cs);
   } else {
     props_kernel<3><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, x_cs, ctx->props);
+    prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
     flux_kernel<3><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt,
                                       sc[0], sc[1], sc[2], ctx->poro, ctx->tp, xold_cs, x_cs,
                                       ctx->props, ctx->J, rhs_cs);
+    prof_end(ctx, CPR_KCLASS_ASSEMBLE);
     if (np) well_kernel<3><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, sc[0], sc[1],
                                                         sc[2], ctx->poro, x_cs, ctx->J, rhs_cs);
   }

@@ -46,6 +46,8 @@ void free_all(cpr_ctx* ctx) {
   for (void* b : bufs)
     if (b) hipFree(b);
   if (ctx->hhost) hipHostFree(ctx->hhost);
+  for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
+  ctx->ev.clear();
 }
 
 // Peaceman well index of a vertical well in an anisotropic block (m^3).
@@ -388,6 +390,36 @@ int cpr_export_ilu(cpr_ctx_t* ctx, double* dinv) {
   if (!dinv || !ctx->setup_done) return set_err(ctx, CPR_EINVAL, "null argument or no setup");
   launch_cs_to_nat(ctx->lay, ctx->b * ctx->b, ctx->Dinv, dinv, ctx->stream);
   return launch_check(ctx, "cpr_export_ilu");
+}
+
+int cpr_profile_kernel(cpr_ctx_t* ctx, int kclass) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (kclass < -1 || kclass > CPR_KCLASS_ASSEMBLE) return set_err(ctx, CPR_EINVAL, "unknown kernel class");
+  GUARD_BEGIN
+  if (kclass >= 0 && ctx->ev.empty()) {
+    ctx->ev.resize(2 * 8192);
+    for (auto& e : ctx->ev) CPR_TRY(hipEventCreate(&e));
+  }
+  ctx->prof_class = kclass;
+  ctx->ev_used = 0;
+  return CPR_OK;
+  GUARD_END
+}
+
+int cpr_profile_read(cpr_ctx_t* ctx, int* launches, double* total_ms) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (!launches || !total_ms) return set_err(ctx, CPR_EINVAL, "null argument");
+  CPR_TRY(hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  for (int q = 0; q < ctx->ev_used; ++q) {
+    float ms = 0.f;
+    CPR_TRY(hipEventElapsedTime(&ms, ctx->ev[2 * q], ctx->ev[2 * q + 1]));
+    tot += ms;
+  }
+  *launches = ctx->ev_used;
+  *total_ms = tot;
+  ctx->ev_used = 0;
+  return CPR_OK;
 }
 
 }  // extern "C"

@@ -160,7 +160,24 @@ struct cpr_ctx {
   double* hdev = nullptr;      // [4*64] device Hessenberg scratch
   double* hhost = nullptr;     // pinned host mirror
   int nblk = 0;
+
+  // kernel-duration sampling (one kernel class at a time)
+  int prof_class = -1;
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  int ev_used = 0;
 };
+
+// Bracket one launch of kernel class `k` with HIP events when it is sampled.
+inline void prof_begin(cpr_ctx* ctx, int k) {
+  if (ctx->prof_class == k && 2 * ctx->ev_used + 1 < (int)ctx->ev.size())
+    hipEventRecord(ctx->ev[2 * ctx->ev_used], ctx->stream);
+}
+inline void prof_end(cpr_ctx* ctx, int k) {
+  if (ctx->prof_class == k && 2 * ctx->ev_used + 1 < (int)ctx->ev.size()) {
+    hipEventRecord(ctx->ev[2 * ctx->ev_used + 1], ctx->stream);
+    ctx->ev_used += 1;
+  }
+}
 
 // ---------------------------------------------------------------- helpers
 #define CPR_TRY(expr)                                                         \

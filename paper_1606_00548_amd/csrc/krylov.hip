@@ -239,18 +239,26 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
       double* zj = ctx->Z + (size_t)j * stride;
       double* w = ctx->V + (size_t)(j + 1) * stride;
       precond_apply(ctx, vj, zj);
+      prof_begin(ctx, CPR_KCLASS_SPMV);
       launch_spmv(b, ctx->lay, ctx->J, zj, w, nullptr, s);
+      prof_end(ctx, CPR_KCLASS_SPMV);
       its += 1;
       int nv = j + 1;
       // CGS pass 1: h1 = V^T w
+      prof_begin(ctx, CPR_KCLASS_ORTH);
       orth_kernel<<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, nullptr, 1, 0, ctx->part, nblk);
+      prof_end(ctx, CPR_KCLASS_ORTH);
       reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd, nullptr);
       // w -= V h1 ; h2 = V^T w
+      prof_begin(ctx, CPR_KCLASS_ORTH);
       orth_kernel<<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, hd, 1, 0, ctx->part, nblk);
+      prof_end(ctx, CPR_KCLASS_ORTH);
       reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd);   // h = h1 + h2
       reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 192, nullptr);   // h2 alone
       // w -= V h2 ; ||w||^2
+      prof_begin(ctx, CPR_KCLASS_ORTH);
       orth_kernel<<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, hd + 192, 0, 1, ctx->part, nblk);
+      prof_end(ctx, CPR_KCLASS_ORTH);
       reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr);
       CPR_TRY(hipGetLastError());
       CPR_TRY(hipMemcpyAsync(ctx->hhost, hd + 64, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -296,7 +304,9 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     maxpy_kernel<<<eb, 256, 0, s>>>(len, k, ctx->Z, stride, hd + 256, x);
     S.cycles += 1;
     S.est_rel = std::fabs(g[k]) / bnorm;
+    prof_begin(ctx, CPR_KCLASS_SPMV);
     launch_spmv(b, ctx->lay, ctx->J, x, r, ctx->rs, s);
+    prof_end(ctx, CPR_KCLASS_SPMV);
   }
   S.iterations = its;
   S.converged = result == CPR_OK;

@@ -10,10 +10,24 @@
 // the FP64 path, float for the mixed-precision path (v and z stay FP64 at
 // the boundary; the coarsest pressure solve is always FP64).  Every colour
 // kernel runs one thread per cell of that colour; in the colour-split
-// layout all its neighbours live in the other half.
+// layout all of a cell's neighbours live in the other half.
+//
+// V(1,1) cycle per level: red sweep from a zero guess (fused with the
+// decoupling on the fine level), black sweep (which also records the black
+// residuals), restriction of r - A x by 2x2x2 aggregation, coarse solve,
+// black post-sweep reading the prolongated red values x + alpha e_c on the
+// fly (the prolongated red values themselves are overwritten by the red
+// post-sweep, so they are never stored), red post-sweep.  All levels from
+// the first one with at most FUSE_MAX cells down to the dense coarsest solve
+// run in one single-workgroup kernel, which removes a dozen latency-bound
+// launches per cycle.
 #include "internal.h"
 
 namespace {
+
+constexpr int FUSE_MAX = 4096;   // cells of the first level handled by the fused kernel
+constexpr int DENSE_FUSED_MAX = 1024;
+constexpr int MAXLV = 16;
 
 template <typename T>
 struct Pre;
@@ -25,19 +39,19 @@ struct Pre<double> {
   static const double* A(const MGLevel& l) { return l.A; }
   static double* x(MGLevel& l) { return l.x; }
   static double* r(MGLevel& l) { return l.r; }
+  static double* res(MGLevel& l) { return l.res; }
   static double* Y(cpr_ctx* c) { return c->Y; }
-  static double* rp(cpr_ctx* c) { return c->rp; }
 };
 template <>
 struct Pre<float> {
-  static const float* R0(const cpr_ctx* c) { return c->Jf + 0; }   // row-0 planes of the FP32 copy
+  static const float* R0(const cpr_ctx* c) { return c->Jf; }   // unused: full FP32 blocks
   static const float* J(const cpr_ctx* c) { return c->Jf; }
   static const float* Dinv(const cpr_ctx* c) { return c->Dinvf; }
   static const float* A(const MGLevel& l) { return l.Af; }
   static float* x(MGLevel& l) { return l.xf; }
   static float* r(MGLevel& l) { return l.rf; }
+  static float* res(MGLevel& l) { return l.resf; }
   static float* Y(cpr_ctx* c) { return c->Yf; }
-  static float* rp(cpr_ctx* c) { return c->rpf; }
 };
 
 // Decoupled block entry (d, r, c) of cell t.  FP64: row 0 lives in R0
@@ -52,49 +66,45 @@ __device__ inline T at_blk(const T* __restrict__ J, const T* __restrict__ R0, si
   }
 }
 
-template <int B, typename T>
-__global__ __launch_bounds__(256) void decouple_kernel(int n, const double* __restrict__ w,
-                                                       const double* __restrict__ v, T* __restrict__ rp) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  double s = 0.0;
-#pragma unroll
-  for (int r = 0; r < B; ++r) s += w[(size_t)r * n + t] * v[(size_t)r * n + t];
-  rp[t] = (T)s;
+// ------------------------------------------------------------ per-cell steps
+
+// red cell q: x = r / a_0 (zero initial guess: every neighbour is black = 0)
+template <typename T>
+__device__ inline void red_zero_cell(const T* __restrict__ A, const T* __restrict__ r, T* __restrict__ x,
+                                     int q) {
+  x[q] = r[q] / A[q];
 }
 
-// Red-black Gauss-Seidel half-sweep on a scalar 7-point level:
-// x_i = (r_i - sum_{d>0} a_id x_nb) / a_i0 for cells of one colour.
-// zero_guess: the other colour is taken as zero (first pre-smoothing sweep).
+// sum_{d>0} a_d x_nb for a colour-split cell
 template <typename T>
-__global__ __launch_bounds__(256) void gs_kernel(Lay L, int colour, int zero_guess,
-                                                 const T* __restrict__ A, const T* __restrict__ r,
-                                                 T* __restrict__ x) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= L.nh) return;
-  int t = colour * L.nh + q;
-  T off = 0;
-  if (!zero_guess) {
-    int i, j, k;
-    lay_coords(L, t, i, j, k);
+__device__ inline T offdiag_sum(const Lay& L, const T* __restrict__ A, const T* __restrict__ x, int t) {
+  CsCell cc = cs_decode(L, t);
+  T s = 0;
 #pragma unroll
-    for (int d = 1; d < 7; ++d) {
-      int nb = lay_nbr(L, i, j, k, d);
-      if (nb >= 0) off += A[(size_t)d * L.n + t] * x[nb];
-    }
+  for (int d = 1; d < 7; ++d) {
+    int nb = cs_nb(L, cc, d);
+    if (nb >= 0) s += A[(size_t)d * L.n + t] * x[nb];
   }
-  x[t] = (r[t] - off) / A[t];
+  return s;
 }
 
-// Residual r - A x of the (up to) 8 fine cells of each coarse cell, summed
-// into the coarse right-hand side (P^T applied to the residual).
+// black cell q: Gauss-Seidel update and its residual r - A x afterwards
 template <typename T>
-__global__ __launch_bounds__(256) void resid_restrict_kernel(Lay F, Lay C, const T* __restrict__ A,
-                                                             const T* __restrict__ r,
-                                                             const T* __restrict__ x,
-                                                             T* __restrict__ rc) {
-  int tc = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tc >= C.n) return;
+__device__ inline void black_pre_cell(const Lay& L, const T* __restrict__ A, const T* __restrict__ r,
+                                      T* __restrict__ x, T* __restrict__ res, int q) {
+  int t = L.nh + q;
+  T s = offdiag_sum(L, A, x, t);
+  T xb = (r[t] - s) / A[t];
+  x[t] = xb;
+  res[q] = r[t] - (A[t] * xb + s);
+}
+
+// coarse cell tc: sum of the fine residuals of its aggregate (P^T r), fine
+// cells in natural order; black residuals were recorded by the black sweep
+template <typename T>
+__device__ inline void restrict_cell(const Lay& F, const Lay& C, const T* __restrict__ A,
+                                     const T* __restrict__ r, const T* __restrict__ x,
+                                     const T* __restrict__ res, T* __restrict__ rc, int tc) {
   int ci, cj, ck;
   lay_coords(C, tc, ci, cj, ck);
   T acc = 0;
@@ -102,30 +112,136 @@ __global__ __launch_bounds__(256) void resid_restrict_kernel(Lay F, Lay C, const
     for (int fj = 2 * cj; fj <= 2 * cj + 1 && fj < F.ny; ++fj)
       for (int fi = 2 * ci; fi <= 2 * ci + 1 && fi < F.nx; ++fi) {
         int f = lay_index(F, fi, fj, fk);
-        T y = A[f] * x[f];
-#pragma unroll
-        for (int d = 1; d < 7; ++d) {
-          int nb = lay_nbr(F, fi, fj, fk, d);
-          if (nb >= 0) y += A[(size_t)d * F.n + f] * x[nb];
+        if (f < F.nh) {
+          T y = A[f] * x[f] + offdiag_sum(F, A, x, f);
+          acc += r[f] - y;
+        } else {
+          acc += res[f - F.nh];
         }
-        acc += r[f] - y;
       }
   rc[tc] = acc;
 }
 
-// x_f += alpha * e_c[agg(f)] on the red cells (the black post-smoothing
-// sweep overwrites the black values, so only red cells need it).
+// black cell q after the coarse correction: neighbours are red cells whose
+// corrected value is x + alpha e_c[aggregate]
 template <typename T>
-__global__ __launch_bounds__(256) void prolong_red_kernel(Lay F, Lay C, T alpha, const T* __restrict__ ec,
-                                                          T* __restrict__ x) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= F.nh) return;
-  int i, j, k;
-  lay_coords(F, q, i, j, k);
-  x[q] += alpha * ec[lay_index(C, i >> 1, j >> 1, k >> 1)];
+__device__ inline void black_post_cell(const Lay& F, const Lay& C, T alpha, const T* __restrict__ A,
+                                       const T* __restrict__ r, const T* __restrict__ ec,
+                                       T* __restrict__ x, int q) {
+  int t = F.nh + q;
+  CsCell cc = cs_decode(F, t);
+  T s = 0;
+#pragma unroll
+  for (int d = 1; d < 7; ++d) {
+    int nb = cs_nb(F, cc, d);
+    if (nb < 0) continue;
+    int di, dj, dk;
+    dir_offset(d, di, dj, dk);
+    T e = ec[lay_index(C, (cc.i + di) >> 1, (cc.j + dj) >> 1, (cc.k + dk) >> 1)];
+    s += A[(size_t)d * F.n + t] * (x[nb] + alpha * e);
+  }
+  x[t] = (r[t] - s) / A[t];
 }
 
-// Coarsest level: x = A^-1 r with the dense FP64 inverse (column major).
+// red cell q, general Gauss-Seidel update
+template <typename T>
+__device__ inline void red_cell(const Lay& L, const T* __restrict__ A, const T* __restrict__ r,
+                                T* __restrict__ x, int q) {
+  T s = offdiag_sum(L, A, x, q);
+  x[q] = (r[q] - s) / A[q];
+}
+
+// ------------------------------------------------------------ multi-block kernels
+
+// Fine level entry: r~_0 = w^T v for every cell, and the zero-guess red
+// sweep x_r = r~_0 / a_0.  If nrm2 is given, the input is an unnormalised
+// Krylov vector: it is divided by sqrt(*nrm2) and written back first.
+template <int B, typename T>
+__global__ __launch_bounds__(256) void decouple_red_kernel(int n, int nh, const double* __restrict__ w,
+                                                           const double* vin, double* vout,
+                                                           const double* __restrict__ nrm2,
+                                                           const T* __restrict__ A, T* __restrict__ rp,
+                                                           T* __restrict__ x) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double hn = nrm2 ? sqrt(*nrm2) : 1.0;
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    double v = vin[(size_t)r * n + t];
+    if (nrm2) {
+      v = v / hn;
+      vout[(size_t)r * n + t] = v;
+    }
+    s += w[(size_t)r * n + t] * v;
+  }
+  T rs = (T)s;
+  rp[t] = rs;
+  if (t < nh) x[t] = rs / A[t];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void red_zero_kernel(Lay L, const T* __restrict__ A, const T* __restrict__ r,
+                                                       T* __restrict__ x) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < L.nh) red_zero_cell(A, r, x, q);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void black_pre_kernel(Lay L, const T* __restrict__ A, const T* __restrict__ r,
+                                                        T* __restrict__ x, T* __restrict__ res) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < L.nh) black_pre_cell(L, A, r, x, res, q);
+}
+
+// Restriction with four threads per coarse cell: thread (tc, q, s) sums the
+// two fine cells (2ci, 2ci+1) of fine row (2cj+q, 2ck+s); the four partials
+// of a coarse cell sit in adjacent lanes and are combined in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void restrict4_kernel(Lay F, Lay C, const T* __restrict__ A,
+                                                        const T* __restrict__ r, const T* __restrict__ x,
+                                                        const T* __restrict__ res, T* __restrict__ rc) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  int tc = g >> 2, sub = g & 3;
+  T acc = 0;
+  if (tc < C.n) {
+    int ci, cj, ck;
+    lay_coords(C, tc, ci, cj, ck);
+    int fj = 2 * cj + (sub & 1), fk = 2 * ck + (sub >> 1);
+    if (fj < F.ny && fk < F.nz) {
+      for (int fi = 2 * ci; fi <= 2 * ci + 1 && fi < F.nx; ++fi) {
+        int f = lay_index(F, fi, fj, fk);
+        if (f < F.nh) {
+          T y = A[f] * x[f] + offdiag_sum(F, A, x, f);
+          acc += r[f] - y;
+        } else {
+          acc += res[f - F.nh];
+        }
+      }
+    }
+  }
+  acc += __shfl_down(acc, 2, 4);
+  acc += __shfl_down(acc, 1, 4);
+  if (tc < C.n && sub == 0) rc[tc] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void black_post_kernel(Lay F, Lay C, T alpha, const T* __restrict__ A,
+                                                         const T* __restrict__ r, const T* __restrict__ ec,
+                                                         T* __restrict__ x) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < F.nh) black_post_cell(F, C, alpha, A, r, ec, x, q);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void red_kernel(Lay L, const T* __restrict__ A, const T* __restrict__ r,
+                                                  T* __restrict__ x) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < L.nh) red_cell(L, A, r, x, q);
+}
+
+// Coarsest level alone when it is too large for the fused kernel:
+// x = A^-1 r with the dense FP64 inverse (column major).
 template <typename T>
 __global__ void coarse_gemv_kernel(int nc, const double* __restrict__ inv, const T* __restrict__ r,
                                    T* __restrict__ x) {
@@ -136,9 +252,66 @@ __global__ void coarse_gemv_kernel(int nc, const double* __restrict__ inv, const
   x[row] = (T)s;
 }
 
+// ------------------------------------------------------------ fused small levels
+
+template <typename T>
+struct CoarseArgs {
+  int count;                 // levels handled; the last one is solved densely
+  Lay lay[MAXLV];
+  const T* A[MAXLV];
+  T* x[MAXLV];
+  T* r[MAXLV];
+  T* res[MAXLV];
+  const double* inv;
+  T alpha;
+};
+
+template <typename T>
+__global__ __launch_bounds__(1024) void coarse_cycle_kernel(CoarseArgs<T> a) {
+  __shared__ double part[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int l = 0; l + 1 < a.count; ++l) {
+    const Lay F = a.lay[l], C = a.lay[l + 1];
+    for (int q = tid; q < F.nh; q += nt) red_zero_cell(a.A[l], a.r[l], a.x[l], q);
+    __syncthreads();
+    for (int q = tid; q < F.nh; q += nt) black_pre_cell(F, a.A[l], a.r[l], a.x[l], a.res[l], q);
+    __syncthreads();
+    for (int tc = tid; tc < C.n; tc += nt) restrict_cell(F, C, a.A[l], a.r[l], a.x[l], a.res[l], a.r[l + 1], tc);
+    __syncthreads();
+  }
+  {
+    const int L = a.count - 1;
+    const int nc = a.lay[L].n;
+    const int parts = nt / nc;            // nc <= DENSE_FUSED_MAX <= nt
+    const T* rr = a.r[L];
+    if (tid < nc * parts) {
+      int row = tid % nc, p = tid / nc;
+      double s = 0.0;
+      for (int c = p; c < nc; c += parts) s += a.inv[(size_t)c * nc + row] * (double)rr[c];
+      part[tid] = s;
+    }
+    __syncthreads();
+    for (int row = tid; row < nc; row += nt) {
+      double s = 0.0;
+      for (int p = 0; p < parts; ++p) s += part[p * nc + row];
+      a.x[L][row] = (T)s;
+    }
+    __syncthreads();
+  }
+  for (int l = a.count - 2; l >= 0; --l) {
+    const Lay F = a.lay[l], C = a.lay[l + 1];
+    for (int q = tid; q < F.nh; q += nt) black_post_cell(F, C, a.alpha, a.A[l], a.r[l], a.x[l + 1], a.x[l], q);
+    __syncthreads();
+    for (int q = tid; q < F.nh; q += nt) red_cell(F, a.A[l], a.r[l], a.x[l], q);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ stage 2 + block ILU(0)
+
 // Stage-2 residual r2 = r~ - A~(:, p) dp at cell t.
 template <int B, typename T>
-__device__ inline void stage2_resid(const Lay& L, int t, int i, int j, int k, const T* J, const T* R0,
+__device__ inline void stage2_resid(const Lay& L, int t, const CsCell& cc, const T* J, const T* R0,
                                     const double* __restrict__ v, const T* __restrict__ rp,
                                     const T* __restrict__ dp, T (&r2)[B]) {
   const size_t N = L.n;
@@ -147,7 +320,7 @@ __device__ inline void stage2_resid(const Lay& L, int t, int i, int j, int k, co
   for (int r = 1; r < B; ++r) r2[r] = (T)v[r * N + t];
 #pragma unroll
   for (int d = 0; d < 7; ++d) {
-    int nb = d == 0 ? t : lay_nbr(L, i, j, k, d);
+    int nb = d == 0 ? t : cs_nb(L, cc, d);
     if (nb < 0) continue;
     T p = dp[nb];
 #pragma unroll
@@ -156,14 +329,14 @@ __device__ inline void stage2_resid(const Lay& L, int t, int i, int j, int k, co
 }
 
 template <int B, typename T>
-__device__ inline void offdiag_apply(const Lay& L, int t, int i, int j, int k, const T* J, const T* R0,
+__device__ inline void offdiag_apply(const Lay& L, int t, const CsCell& cc, const T* J, const T* R0,
                                      const T* __restrict__ Y, T (&s)[B]) {
   const size_t N = L.n;
 #pragma unroll
   for (int r = 0; r < B; ++r) s[r] = 0;
 #pragma unroll
   for (int d = 1; d < 7; ++d) {
-    int nb = lay_nbr(L, i, j, k, d);
+    int nb = cs_nb(L, cc, d);
     if (nb < 0) continue;
     T y[B];
 #pragma unroll
@@ -199,10 +372,9 @@ __global__ __launch_bounds__(256) void stage2_red_fwd_kernel(Lay L, const T* __r
                                                              const T* __restrict__ dp, T* __restrict__ Y) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= L.nh) return;
-  int i, j, k;
-  lay_coords(L, t, i, j, k);
+  CsCell cc = cs_decode(L, t);
   T r2[B], y[B];
-  stage2_resid<B, T>(L, t, i, j, k, J, R0, v, rp, dp, r2);
+  stage2_resid<B, T>(L, t, cc, J, R0, v, rp, dp, r2);
   dinv_apply<B, T>(Dinv, L.n, t, r2, y);
 #pragma unroll
   for (int r = 0; r < B; ++r) Y[(size_t)r * L.n + t] = y[r];
@@ -221,15 +393,41 @@ __global__ __launch_bounds__(256) void stage2_black_kernel(Lay L, const T* __res
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= L.nh) return;
   int t = L.nh + q;
-  int i, j, k;
-  lay_coords(L, t, i, j, k);
+  CsCell cc = cs_decode(L, t);
+  const size_t N = L.n;
+  // r2 = r~ - A~(:,p) dp and s = sum_red A~_bk y_k, each off-diagonal block read once
   T r2[B], s[B], y[B];
-  stage2_resid<B, T>(L, t, i, j, k, J, R0, v, rp, dp, r2);
-  offdiag_apply<B, T>(L, t, i, j, k, J, R0, Y, s);
+  r2[0] = rp[t];
+#pragma unroll
+  for (int r = 1; r < B; ++r) r2[r] = (T)v[r * N + t];
+  {
+    T p = dp[t];
+#pragma unroll
+    for (int r = 0; r < B; ++r) r2[r] -= at_blk<B, T>(J, R0, N, 0, r, 0, t) * p;
+  }
+#pragma unroll
+  for (int r = 0; r < B; ++r) s[r] = 0;
+#pragma unroll
+  for (int d = 1; d < 7; ++d) {
+    int nb = cs_nb(L, cc, d);
+    if (nb < 0) continue;
+    T p = dp[nb];
+    T yk[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) yk[c] = Y[c * N + nb];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      T a0 = at_blk<B, T>(J, R0, N, d, r, 0, t);
+      r2[r] -= a0 * p;
+      T a = a0 * yk[0];
+#pragma unroll
+      for (int c = 1; c < B; ++c) a += at_blk<B, T>(J, R0, N, d, r, c, t) * yk[c];
+      s[r] += a;
+    }
+  }
 #pragma unroll
   for (int r = 0; r < B; ++r) r2[r] -= s[r];
   dinv_apply<B, T>(Dinv, L.n, t, r2, y);
-  const size_t N = L.n;
 #pragma unroll
   for (int r = 0; r < B; ++r) Y[r * N + t] = y[r];
   z[t] = (double)y[0] + (double)dp[t];
@@ -247,10 +445,9 @@ __global__ __launch_bounds__(256) void stage2_red_bwd_kernel(Lay L, const T* __r
                                                              double* __restrict__ z) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= L.nh) return;
-  int i, j, k;
-  lay_coords(L, t, i, j, k);
+  CsCell cc = cs_decode(L, t);
   T s[B], u[B];
-  offdiag_apply<B, T>(L, t, i, j, k, J, R0, Y, s);
+  offdiag_apply<B, T>(L, t, cc, J, R0, Y, s);
   dinv_apply<B, T>(Dinv, L.n, t, s, u);
   const size_t N = L.n;
   z[t] = (double)(Y[t] - u[0]) + (double)dp[t];
@@ -258,60 +455,86 @@ __global__ __launch_bounds__(256) void stage2_red_bwd_kernel(Lay L, const T* __r
   for (int r = 1; r < B; ++r) z[r * N + t] = (double)(Y[r * N + t] - u[r]);
 }
 
+// ------------------------------------------------------------ host side
+
+#define TIMED(cls, launch) \
+  do {                     \
+    prof_begin(ctx, cls);  \
+    launch;                \
+    prof_end(ctx, cls);    \
+  } while (0)
+
 template <typename T>
-void vcycle(cpr_ctx* ctx, size_t l) {
+void vcycle(cpr_ctx* ctx) {
   hipStream_t s = ctx->stream;
-  MGLevel& L = ctx->levels[l];
-  if (l + 1 == ctx->levels.size()) {
-    int nc = L.lay.n;
-    coarse_gemv_kernel<T><<<div_up(nc, 128), 128, 0, s>>>(nc, ctx->cinv, Pre<T>::r(L), Pre<T>::x(L));
-    return;
+  const int nl = (int)ctx->levels.size();
+  const int nc = ctx->levels.back().lay.n;
+  // first level handled by the single-workgroup kernel
+  int fuse = nl;
+  if (nc <= DENSE_FUSED_MAX && nl <= MAXLV) {
+    fuse = nl - 1;
+    for (int l = 1; l < nl; ++l)
+      if (ctx->levels[l].lay.n <= FUSE_MAX) { fuse = l; break; }
+    if (nl == 1) fuse = 0;
   }
-  MGLevel& C = ctx->levels[l + 1];
-  const T* A = Pre<T>::A(L);
-  T* x = Pre<T>::x(L);
-  const T* r = Pre<T>::r(L);
-  int nh = div_up(L.lay.nh, 256);
-  prof_begin(ctx, CPR_KCLASS_SMOOTH);
-  gs_kernel<T><<<nh, 256, 0, s>>>(L.lay, 0, 1, A, r, x);
-  prof_end(ctx, CPR_KCLASS_SMOOTH);
-  prof_begin(ctx, CPR_KCLASS_SMOOTH);
-  gs_kernel<T><<<nh, 256, 0, s>>>(L.lay, 1, 0, A, r, x);
-  prof_end(ctx, CPR_KCLASS_SMOOTH);
-  resid_restrict_kernel<T><<<div_up(C.lay.n, 256), 256, 0, s>>>(L.lay, C.lay, A, r, x, Pre<T>::r(C));
-  vcycle<T>(ctx, l + 1);
-  prolong_red_kernel<T><<<nh, 256, 0, s>>>(L.lay, C.lay, (T)ctx->opt.mg_alpha, Pre<T>::x(C), x);
-  prof_begin(ctx, CPR_KCLASS_SMOOTH);
-  gs_kernel<T><<<nh, 256, 0, s>>>(L.lay, 1, 0, A, r, x);
-  prof_end(ctx, CPR_KCLASS_SMOOTH);
-  prof_begin(ctx, CPR_KCLASS_SMOOTH);
-  gs_kernel<T><<<nh, 256, 0, s>>>(L.lay, 0, 0, A, r, x);
-  prof_end(ctx, CPR_KCLASS_SMOOTH);
+  const T alpha = (T)ctx->opt.mg_alpha;
+  const int down = fuse < nl ? fuse : nl - 1;   // levels smoothed by multi-block kernels
+  for (int l = 0; l < down; ++l) {
+    MGLevel& L = ctx->levels[l];
+    MGLevel& C = ctx->levels[l + 1];
+    int nh = div_up(L.lay.nh, 256);
+    if (l > 0) TIMED(CPR_KCLASS_SMOOTH, (red_zero_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
+    TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
+                                                                     Pre<T>::x(L), Pre<T>::res(L))));
+    restrict4_kernel<T><<<div_up(4L * C.lay.n, 256), 256, 0, s>>>(L.lay, C.lay, Pre<T>::A(L), Pre<T>::r(L),
+                                                                  Pre<T>::x(L), Pre<T>::res(L), Pre<T>::r(C));
+  }
+  if (fuse < nl) {
+    CoarseArgs<T> a;
+    a.count = nl - fuse;
+    for (int q = 0; q < a.count; ++q) {
+      MGLevel& L = ctx->levels[fuse + q];
+      a.lay[q] = L.lay;
+      a.A[q] = Pre<T>::A(L);
+      a.x[q] = Pre<T>::x(L);
+      a.r[q] = Pre<T>::r(L);
+      a.res[q] = Pre<T>::res(L);
+    }
+    a.inv = ctx->cinv;
+    a.alpha = alpha;
+    coarse_cycle_kernel<T><<<1, 1024, 0, s>>>(a);
+  } else {
+    MGLevel& L = ctx->levels.back();
+    coarse_gemv_kernel<T><<<div_up(nc, 128), 128, 0, s>>>(nc, ctx->cinv, Pre<T>::r(L), Pre<T>::x(L));
+  }
+  for (int l = down - 1; l >= 0; --l) {
+    MGLevel& L = ctx->levels[l];
+    MGLevel& C = ctx->levels[l + 1];
+    int nh = div_up(L.lay.nh, 256);
+    TIMED(CPR_KCLASS_SMOOTH, (black_post_kernel<T><<<nh, 256, 0, s>>>(L.lay, C.lay, alpha, Pre<T>::A(L),
+                                                                      Pre<T>::r(L), Pre<T>::x(C), Pre<T>::x(L))));
+    TIMED(CPR_KCLASS_SMOOTH, (red_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
+  }
 }
 
 template <int B, typename T>
-void apply_impl(cpr_ctx* ctx, const double* v, double* z) {
+void apply_impl(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, double* z) {
   hipStream_t s = ctx->stream;
   const Lay& L = ctx->lay;
   MGLevel& L0 = ctx->levels[0];
   T* rp = Pre<T>::r(L0);
-  decouple_kernel<B, T><<<div_up(L.n, 256), 256, 0, s>>>(L.n, ctx->w, v, rp);
-  vcycle<T>(ctx, 0);
+  decouple_red_kernel<B, T><<<div_up(L.n, 256), 256, 0, s>>>(L.n, L.nh, ctx->w, vin, v, nrm2, Pre<T>::A(L0),
+                                                            rp, Pre<T>::x(L0));
+  vcycle<T>(ctx);
   const T* dp = Pre<T>::x(L0);
   const T* J = Pre<T>::J(ctx);
   const T* R0 = Pre<T>::R0(ctx);
   const T* Dinv = Pre<T>::Dinv(ctx);
   T* Y = Pre<T>::Y(ctx);
   int nh = div_up(L.nh, 256);
-  prof_begin(ctx, CPR_KCLASS_ILU);
-  stage2_red_fwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, v, rp, dp, Y);
-  prof_end(ctx, CPR_KCLASS_ILU);
-  prof_begin(ctx, CPR_KCLASS_ILU);
-  stage2_black_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, v, rp, dp, Y, z);
-  prof_end(ctx, CPR_KCLASS_ILU);
-  prof_begin(ctx, CPR_KCLASS_ILU);
-  stage2_red_bwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, dp, Y, z);
-  prof_end(ctx, CPR_KCLASS_ILU);
+  TIMED(CPR_KCLASS_ILU, (stage2_red_fwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, v, rp, dp, Y)));
+  TIMED(CPR_KCLASS_ILU, (stage2_black_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, v, rp, dp, Y, z)));
+  TIMED(CPR_KCLASS_ILU, (stage2_red_bwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, dp, Y, z)));
 }
 
 // FP32 copies: decoupled blocks (row 0 from R0), ILU diagonals, MG levels.
@@ -351,11 +574,11 @@ void launch_mixed_copies(cpr_ctx* ctx) {
   }
 }
 
-void precond_apply(cpr_ctx* ctx, const double* v, double* z) {
+void precond_apply(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, double* z) {
   bool mixed = ctx->opt.precision == CPR_PREC_MIXED;
   if (ctx->b == 2) {
-    if (mixed) apply_impl<2, float>(ctx, v, z); else apply_impl<2, double>(ctx, v, z);
+    if (mixed) apply_impl<2, float>(ctx, vin, v, nrm2, z); else apply_impl<2, double>(ctx, vin, v, nrm2, z);
   } else {
-    if (mixed) apply_impl<3, float>(ctx, v, z); else apply_impl<3, double>(ctx, v, z);
+    if (mixed) apply_impl<3, float>(ctx, vin, v, nrm2, z); else apply_impl<3, double>(ctx, vin, v, nrm2, z);
   }
 }

@@ -357,7 +357,7 @@ int cpr_precond_apply(cpr_ctx_t* ctx, const double* v, double* z) {
   if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
   hipStream_t s = ctx->stream;
   launch_nat_to_cs(ctx->lay, ctx->b, v, ctx->vin, s);
-  precond_apply(ctx, ctx->vin, ctx->vout);
+  precond_apply(ctx, ctx->vin, ctx->vin, nullptr, ctx->vout);
   launch_cs_to_nat(ctx->lay, ctx->b, ctx->vout, z, s);
   return launch_check(ctx, "cpr_precond_apply");
 }

@@ -66,6 +66,40 @@ __host__ __device__ inline int lay_nbr(const Lay& L, int i, int j, int k, int d)
   return lay_index(L, a, b, c);
 }
 
+// A colour-split cell decoded once; its neighbours are then a few adds away.
+// All neighbours of a cell of colour c live in colour 1-c: +-y / +-z at a
+// fixed offset from `base` (same m), -x / +x at m or m -+ 1 by the parity
+// of i.
+struct CsCell {
+  int c, m, j, k, i, base;
+};
+
+__host__ __device__ inline CsCell cs_decode(const Lay& L, int t) {
+  CsCell q;
+  q.c = t >= L.nh ? 1 : 0;
+  int r = t - q.c * L.nh;
+  int row = r / L.half;
+  q.m = r - row * L.half;
+  q.j = row % L.ny;
+  q.k = row / L.ny;
+  q.i = 2 * q.m + ((q.j + q.k + q.c) & 1);
+  q.base = (1 - q.c) * L.nh + q.m + L.half * row;
+  return q;
+}
+
+__host__ __device__ inline int cs_nb(const Lay& L, const CsCell& q, int d) {
+  const int p = q.i & 1;
+  switch (d) {
+    case 1: return q.i > 0 ? q.base - (p ? 0 : 1) : -1;
+    case 2: return q.i < L.nx - 1 ? q.base + p : -1;
+    case 3: return q.j > 0 ? q.base - L.half : -1;
+    case 4: return q.j < L.ny - 1 ? q.base + L.half : -1;
+    case 5: return q.k > 0 ? q.base - L.half * L.ny : -1;
+    case 6: return q.k < L.nz - 1 ? q.base + L.half * L.ny : -1;
+    default: return -1;
+  }
+}
+
 inline Lay make_lay(int nx, int ny, int nz, bool want_cs) {
   Lay L;
   L.nx = nx; L.ny = ny; L.nz = nz;
@@ -102,6 +136,8 @@ struct MGLevel {
   double* r = nullptr;   // right-hand side
   float* xf = nullptr;
   float* rf = nullptr;
+  double* res = nullptr; // black-cell residuals after the black pre-smoothing sweep [n/2]
+  float* resf = nullptr;
 };
 
 struct cpr_ctx {
@@ -213,7 +249,10 @@ void launch_spmv(int b, const Lay& L, const double* A, const double* x, double* 
 int setup_cpr(cpr_ctx* ctx);
 
 // apply.hip
-void precond_apply(cpr_ctx* ctx, const double* v, double* z);
+// z = M^-1 v.  If nrm2 (device) is given, vin holds an unnormalised Krylov
+// vector: v = vin / sqrt(*nrm2) is formed and stored on the way (vin may
+// equal v).  Otherwise v must equal vin.
+void precond_apply(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, double* z);
 
 // krylov.hip
 int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st);

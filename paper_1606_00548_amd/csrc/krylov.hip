@@ -120,9 +120,65 @@ __global__ __launch_bounds__(KB) void reduce_kernel(const double* __restrict__ p
   if (threadIdx.x == 0) out[k] = tot[0] + (add ? add[k] : 0.0);
 }
 
+// One CGS2 pass over the first nv basis vectors, register-blocked so that
+// every element of V is read once: optionally w -= sum_k hprev[k] V_k, then
+// either the partial dots V_k . w (mode 0) or the partial ||w||^2 (mode 1)
+// of this block's slice.
+template <int NV>
+__global__ __launch_bounds__(KB) void orth_fused_kernel(long len, int nv, const double* __restrict__ V,
+                                                        size_t stride, double* __restrict__ w,
+                                                        const double* __restrict__ hprev, int mode,
+                                                        double* __restrict__ part, int nblk) {
+  __shared__ double sh[NV * (KB / 64)];
+  __shared__ double hs[NV];
+  if (hprev && threadIdx.x < nv) hs[threadIdx.x] = hprev[threadIdx.x];
+  __syncthreads();
+  long per = (len + nblk - 1) / nblk;
+  long beg = (long)blockIdx.x * per;
+  long end = beg + per < len ? beg + per : len;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (long e = beg + threadIdx.x; e < end; e += KB) {
+    double vv[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) vv[k] = k < nv && (hprev || mode == 0) ? V[k * stride + e] : 0.0;
+    double x = w[e];
+    if (hprev) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+        if (k < nv) x -= hs[k] * vv[k];
+      w[e] = x;
+    }
+    if (mode == 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+        if (k < nv) acc[k] += vv[k] * x;
+    } else {
+      acc[0] += x * x;
+    }
+  }
+  const int cnt = mode == 0 ? nv : 1;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < cnt) {
+      double v = wave_sum(acc[k]);
+      if (lane == 0) sh[k * (KB / 64) + wid] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < cnt) {
+    double s = 0.0;
+    for (int q = 0; q < KB / 64; ++q) s += sh[threadIdx.x * (KB / 64) + q];
+    int row = mode == 0 ? threadIdx.x : nv;
+    part[(size_t)row * nblk + blockIdx.x] = s;
+  }
+}
+
 __global__ void scale_kernel(long len, double a, const double* __restrict__ x, double* __restrict__ y) {
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < len) y[e] = a * x[e];
+  if (e < len) y[e] = x[e] / a;
 }
 
 // x += sum_k y[k] Z_k
@@ -156,6 +212,24 @@ __global__ void newton_update_kernel(int b, int n, double* __restrict__ x, const
     double v = x[o] + d;
     x[o] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
   }
+}
+
+// One orthogonalisation pass (see orth_fused_kernel); more than 32 basis
+// vectors fall back to the chunked kernel, which reads V twice.
+void orth_pass(cpr_ctx* ctx, long len, int nv, double* w, const double* hprev, int mode) {
+  hipStream_t s = ctx->stream;
+  const int nblk = ctx->nblk;
+  const size_t stride = (size_t)len;
+  prof_begin(ctx, CPR_KCLASS_ORTH);
+  if (nv <= 8)
+    orth_fused_kernel<8><<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, hprev, mode, ctx->part, nblk);
+  else if (nv <= 16)
+    orth_fused_kernel<16><<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, hprev, mode, ctx->part, nblk);
+  else if (nv <= 32)
+    orth_fused_kernel<32><<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, hprev, mode, ctx->part, nblk);
+  else
+    orth_kernel<<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, hprev, mode == 0, mode == 1, ctx->part, nblk);
+  prof_end(ctx, CPR_KCLASS_ORTH);
 }
 
 }  // namespace
@@ -228,7 +302,7 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     }
     if (beta <= rtol * bnorm) { result = CPR_OK; break; }
     if (its >= max_iter) break;
-    scale_kernel<<<eb, 256, 0, s>>>(len, 1.0 / beta, r, ctx->V);
+    scale_kernel<<<eb, 256, 0, s>>>(len, beta, r, ctx->V);
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -238,27 +312,22 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
       double* vj = ctx->V + (size_t)j * stride;
       double* zj = ctx->Z + (size_t)j * stride;
       double* w = ctx->V + (size_t)(j + 1) * stride;
-      precond_apply(ctx, vj, zj);
+      // v_j = w_j / h_{j,j-1} is formed inside the preconditioner's first kernel
+      precond_apply(ctx, vj, vj, j == 0 ? nullptr : hd + 128, zj);
       prof_begin(ctx, CPR_KCLASS_SPMV);
       launch_spmv(b, ctx->lay, ctx->J, zj, w, nullptr, s);
       prof_end(ctx, CPR_KCLASS_SPMV);
       its += 1;
       int nv = j + 1;
       // CGS pass 1: h1 = V^T w
-      prof_begin(ctx, CPR_KCLASS_ORTH);
-      orth_kernel<<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, nullptr, 1, 0, ctx->part, nblk);
-      prof_end(ctx, CPR_KCLASS_ORTH);
+      orth_pass(ctx, len, nv, w, nullptr, 0);
       reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd, nullptr);
       // w -= V h1 ; h2 = V^T w
-      prof_begin(ctx, CPR_KCLASS_ORTH);
-      orth_kernel<<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, hd, 1, 0, ctx->part, nblk);
-      prof_end(ctx, CPR_KCLASS_ORTH);
+      orth_pass(ctx, len, nv, w, hd, 0);
       reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd);   // h = h1 + h2
       reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 192, nullptr);   // h2 alone
       // w -= V h2 ; ||w||^2
-      prof_begin(ctx, CPR_KCLASS_ORTH);
-      orth_kernel<<<nblk, KB, 0, s>>>(len, nv, ctx->V, stride, w, hd + 192, 0, 1, ctx->part, nblk);
-      prof_end(ctx, CPR_KCLASS_ORTH);
+      orth_pass(ctx, len, nv, w, hd + 192, 1);
       reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr);
       CPR_TRY(hipGetLastError());
       CPR_TRY(hipMemcpyAsync(ctx->hhost, hd + 64, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -290,7 +359,6 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
       k = j + 1;
       if (std::fabs(g[j + 1]) <= rtol * bnorm || its >= max_iter) break;
       if (hn <= BREAKDOWN * az) { breakdown_stop = true; break; }
-      scale_kernel<<<eb, 256, 0, s>>>(len, 1.0 / hn, w, w);
     }
     (void)breakdown_stop;
     // back substitution H[:k,:k] y = g[:k]

@@ -213,6 +213,100 @@ __global__ void gj_step_kernel(int nc, int p, const double* __restrict__ src, do
   }
 }
 
+// Whole Gauss-Jordan inversion (partial pivoting, in place) of a small
+// coarsest operator in one workgroup with the matrix held in LDS (nc <= 128).
+// Thread layout: row r = tid / 8, columns lane + 8 q; rows are padded to an
+// odd stride so the 8 rows a wavefront touches fall in different banks.  The
+// dense matrix is built from the level's 7-point stencil; the inverse is
+// written column major (and as FP32).
+constexpr int GJ_LDS_MAX = 128;
+
+__global__ __launch_bounds__(1024) void gj_lds_kernel(Lay L, const double* __restrict__ A,
+                                                      double* __restrict__ inv, float* __restrict__ invf,
+                                                      int* __restrict__ flag) {
+  extern __shared__ double sm[];
+  const int nc = L.n;
+  const int ld = nc + 8;          // 8 consecutive rows then start in different LDS banks
+  double* M = sm;                 // nc rows of stride ld
+  double* fcol = sm + nc * ld;    // multipliers of the current column
+  __shared__ int piv[GJ_LDS_MAX];
+  __shared__ double pvs;
+  __shared__ int prs;
+  const int tid = threadIdx.x;
+  const int r = tid >> 3, lane = tid & 7;
+  const bool own = r < nc;
+  if (own)
+    for (int c = lane; c < nc; c += 8) M[r * ld + c] = 0.0;
+  __syncthreads();
+  if (own && lane == 0) {
+    int i, j, k;
+    lay_coords(L, r, i, j, k);
+    M[r * ld + r] += A[r];
+    for (int d = 1; d < 7; ++d) {
+      int nb = lay_nbr(L, i, j, k, d);
+      if (nb >= 0) M[r * ld + nb] += A[(size_t)d * nc + r];
+    }
+  }
+  __syncthreads();
+  for (int p = 0; p < nc; ++p) {
+    if (tid < 64) {   // pivot: largest |M[q][p]|, q >= p, lowest row on ties
+      double best = -1.0;
+      int bi = p;
+      for (int q = p + tid; q < nc; q += 64) {
+        double v = fabs(M[q * ld + p]);
+        if (v > best) { best = v; bi = q; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        double ov = __shfl_down(best, o, 64);
+        int oi = __shfl_down(bi, o, 64);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if (tid == 0) {
+        prs = bi;
+        pvs = M[bi * ld + p];
+        piv[p] = bi;
+        if (!(best > TINY) || !isfinite(best)) atomicExch(flag, 1);
+      }
+    }
+    __syncthreads();
+    const int pr = prs;
+    const double pinv = 1.0 / pvs;
+    // one thread per column interchanges rows p and pr and scales the new
+    // pivot row (diagonal set to 1 first); other threads collect the
+    // multipliers of column p for the rows the interchange does not touch
+    if (tid < nc) {
+      const int c = tid;
+      double top = M[pr * ld + c], old = M[p * ld + c];
+      if (pr != p) M[pr * ld + c] = old;
+      M[p * ld + c] = (c == p ? 1.0 : top) * pinv;
+      if (c == p) { fcol[p] = 0.0; fcol[pr] = pr == p ? 0.0 : old; }
+    } else if (tid >= 512 && tid - 512 < nc) {
+      const int q = tid - 512;
+      if (q != p && q != pr) fcol[q] = M[q * ld + p];
+    }
+    __syncthreads();
+    if (own && r != p) {
+      const double f = fcol[r];
+      for (int c = lane; c < nc; c += 8) M[r * ld + c] = (c == p ? 0.0 : M[r * ld + c]) - f * M[p * ld + c];
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int p = nc - 1; p >= 0; --p) {
+    int q = piv[p];
+    if (q != p && own && lane == 0) {
+      double t = M[r * ld + p]; M[r * ld + p] = M[r * ld + q]; M[r * ld + q] = t;
+    }
+    __syncthreads();
+  }
+  if (own)
+    for (int c = lane; c < nc; c += 8) {
+      double v = M[r * ld + c];
+      inv[(size_t)c * nc + r] = v;
+      if (invf) invf[(size_t)c * nc + r] = (float)v;
+    }
+}
+
 // Copy the right half of [I | M^-1] into column-major storage.
 __global__ void gj_extract_kernel(int nc, const double* __restrict__ M, double* __restrict__ inv,
                                   float* __restrict__ invf) {
@@ -286,6 +380,7 @@ static void free_levels(cpr_ctx* ctx) {
   for (size_t l = 0; l < ctx->levels.size(); ++l) {
     MGLevel& L = ctx->levels[l];
     hipFree(L.A); hipFree(L.Af); hipFree(L.x); hipFree(L.r); hipFree(L.xf); hipFree(L.rf);
+    hipFree(L.res); hipFree(L.resf);
   }
   ctx->levels.clear();
   hipFree(ctx->cinv); ctx->cinv = nullptr;
@@ -323,6 +418,8 @@ static int build_hierarchy(cpr_ctx* ctx) {
     CPR_TRY(hipMalloc(&L.r, n * sizeof(double)));
     CPR_TRY(hipMalloc(&L.xf, n * sizeof(float)));
     CPR_TRY(hipMalloc(&L.rf, n * sizeof(float)));
+    CPR_TRY(hipMalloc(&L.res, (n / 2 + 1) * sizeof(double)));
+    CPR_TRY(hipMalloc(&L.resf, (n / 2 + 1) * sizeof(float)));
   }
   size_t nc = shapes.back().n;
   CPR_TRY(hipMalloc(&ctx->cinv, nc * nc * sizeof(double)));
@@ -354,16 +451,27 @@ int setup_cpr(cpr_ctx* ctx) {
   // dense inverse of the coarsest level
   const MGLevel& last = ctx->levels.back();
   int nc = last.lay.n;
-  double* bufA = ctx->gj_work;
-  double* bufB = ctx->gj_work + (size_t)nc * 2 * nc;
-  dense_build_kernel<<<div_up(nc, 256), 256, 0, s>>>(last.lay, last.A, bufA);
-  int gblocks = div_up((long)nc * 2 * nc, 256);
-  if (gblocks > 512) gblocks = 512;
-  for (int p = 0; p < nc; ++p) {
-    gj_step_kernel<<<gblocks, 256, 0, s>>>(nc, p, bufA, bufB, ctx->flag);
-    double* t = bufA; bufA = bufB; bufB = t;
+  if (nc <= GJ_LDS_MAX) {
+    size_t smem = ((size_t)nc * (nc + 8) + nc) * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+      CPR_TRY(hipFuncSetAttribute((const void*)gj_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(((size_t)GJ_LDS_MAX * (GJ_LDS_MAX + 8) + GJ_LDS_MAX) * sizeof(double))));
+      attr_set = true;
+    }
+    gj_lds_kernel<<<1, 1024, smem, s>>>(last.lay, last.A, ctx->cinv, ctx->cinvf, ctx->flag);
+  } else {
+    double* bufA = ctx->gj_work;
+    double* bufB = ctx->gj_work + (size_t)nc * 2 * nc;
+    dense_build_kernel<<<div_up(nc, 256), 256, 0, s>>>(last.lay, last.A, bufA);
+    int gblocks = div_up((long)nc * 2 * nc, 256);
+    if (gblocks > 512) gblocks = 512;
+    for (int p = 0; p < nc; ++p) {
+      gj_step_kernel<<<gblocks, 256, 0, s>>>(nc, p, bufA, bufB, ctx->flag);
+      double* t = bufA; bufA = bufB; bufB = t;
+    }
+    gj_extract_kernel<<<div_up((long)nc * nc, 256), 256, 0, s>>>(nc, bufA, ctx->cinv, ctx->cinvf);
   }
-  gj_extract_kernel<<<div_up((long)nc * nc, 256), 256, 0, s>>>(nc, bufA, ctx->cinv, ctx->cinvf);
   // red-black block ILU(0): red diagonals first, black ones use them
   int nh = div_up(L.nh, 256);
   for (int colour = 0; colour < 2; ++colour) {

@@ -203,6 +203,73 @@ enum {
 int cpr_profile_kernel(cpr_ctx_t* ctx, int kclass);
 int cpr_profile_read(cpr_ctx_t* ctx, int* launches, double* total_ms);
 
+/* ------------------------------------------------------------------------
+ * Learned pressure correction (an addition to the paper's method).
+ *
+ * A 3-D convolutional U-Net (four levels with 16, 32, 64, 64 channels, one
+ * 3x3x3 convolution per level on each path, ReLU, 2x2x2 average pooling,
+ * nearest upsampling, additive skips, 1x1x1 output) maps three per-cell
+ * features -- standardised ln k_x, standardised ln of the total mobility,
+ * and D^-1 r' / rms(D^-1 r') with r' the pressure residual left by the
+ * multigrid cycle and D the diagonal of A_p -- to a pressure correction.
+ * Tensors are FP32, channels-last, natural cell order; convolutions run on
+ * the matrix cores in BF16 with FP32 accumulation.  Parameters are one flat
+ * FP32 vector: per convolution W[27][Cin][Cout] (tap = (dz+1)*9 +
+ * (dy+1)*3 + (dx+1)) then bias[Cout]; then the head w[16], b[1].
+ * ---------------------------------------------------------------------- */
+typedef struct cpr_nn cpr_nn_t;
+
+long long cpr_nn_num_params(void);
+
+/* A network object for grids nx x ny x nz (each a multiple of 8) and up to
+ * max_batch samples; owns parameters, Adam moments and activations.
+ * Parameters start at zero: call cpr_nn_set_params.  On error *out is still
+ * set so that cpr_nn_last_error can explain; destroy it. */
+int cpr_nn_create(int nx, int ny, int nz, int max_batch, void* stream, cpr_nn_t** out);
+void cpr_nn_destroy(cpr_nn_t* nn);
+const char* cpr_nn_last_error(const cpr_nn_t* nn);
+
+/* Copy parameters in (resets the Adam moments) or out; host arrays of
+ * cpr_nn_num_params() floats.  Synchronise. */
+int cpr_nn_set_params(cpr_nn_t* nn, const float* theta);
+int cpr_nn_get_params(cpr_nn_t* nn, float* theta);
+
+/* y = N(x) for x (device [batch][n][3]) -> y (device [batch][n]). */
+int cpr_nn_forward(cpr_nn_t* nn, const float* x, int batch, float* y);
+
+/* Gradient of sum(dy * y) for the last forward pass with respect to the
+ * parameters: dy device [batch][n], grad device [num_params]. */
+int cpr_nn_backward(cpr_nn_t* nn, const float* dy, float* grad);
+
+/* One Adam step (lr; beta 0.9 / 0.999; eps 1e-8) on the normalised MSE
+ * (1/B) sum_b |N(x_b) - t_b|^2 / |t_b|^2; x device [batch][n][3], t device
+ * [batch][n]; *loss (host, may be NULL) receives the loss before the step. */
+int cpr_nn_train_step(cpr_nn_t* nn, const float* x, const float* t, int batch, float lr, float* loss);
+
+/* Give a solver context a copy of trained parameters (host array, NULL to
+ * drop it).  With options.learned = 1 every CPR application then forms
+ * r' = r~_p - A_p dp_mg after the multigrid cycle, evaluates the network,
+ * dp_nn = rms * N(features), and keeps dp_mg + dp_nn only when
+ * ||r' - A_p dp_nn||_2 < ||r'||_2; otherwise the plain CPR result stands.
+ * The grid must have dimensions divisible by 8. */
+int cpr_nn_attach(cpr_ctx_t* ctx, const float* theta);
+
+/* The pressure stage on one vector, for building training data (device,
+ * natural order): r~_p = w^T v; dp_mg = V-cycle(r~_p); rprime = r~_p -
+ * A_p dp_mg ([n] each; dp_mg may be NULL).  After cpr_setup. */
+int cpr_pressure_stage(cpr_ctx_t* ctx, const double* v, double* rprime, double* dp_mg);
+
+/* Network input for a pressure residual rprime (device [n]): feat device
+ * [n][3] natural order; *scale (host) receives rms(D^-1 rprime), the factor
+ * that converts network output to a pressure correction.  After cpr_setup
+ * of an assembled Jacobian (the mobility channel comes from the state of
+ * the last assembly). */
+int cpr_nn_features(cpr_ctx_t* ctx, const double* rprime, float* feat, double* scale);
+
+/* Basis vector v_j (device [b][n], natural order) of the last FGMRES
+ * cycle, j < number of iterations of that cycle. */
+int cpr_export_krylov(cpr_ctx_t* ctx, int j, double* v);
+
 #ifdef __cplusplus
 }
 #endif

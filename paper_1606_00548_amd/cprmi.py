@@ -65,7 +65,10 @@ EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error",
            "cpr_num_cells", "assemble_jacobian", "cpr_import_jacobian", "cpr_export_jacobian",
            "cpr_setup", "cpr_gmres_solve", "cpr_newton_update", "cpr_spmv", "cpr_precond_apply",
            "cpr_export_qimpes", "cpr_mg_level_shape", "cpr_export_mg_level", "cpr_export_ilu",
-           "cpr_profile_kernel", "cpr_profile_read"]
+           "cpr_profile_kernel", "cpr_profile_read", "cpr_nn_num_params", "cpr_nn_create",
+           "cpr_nn_destroy", "cpr_nn_last_error", "cpr_nn_set_params", "cpr_nn_get_params",
+           "cpr_nn_forward", "cpr_nn_backward", "cpr_nn_train_step", "cpr_nn_attach",
+           "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov"]
 KCLASS = {"spmv": 0, "orth": 1, "smooth": 2, "ilu": 3, "assemble": 4}
 
 
@@ -102,6 +105,20 @@ def load():
     lib.cpr_export_ilu.argtypes = [P, P]
     lib.cpr_profile_kernel.argtypes = [P, ctypes.c_int]
     lib.cpr_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+    lib.cpr_nn_num_params.restype = ctypes.c_longlong
+    lib.cpr_nn_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(P)]
+    lib.cpr_nn_destroy.argtypes = [P]
+    lib.cpr_nn_last_error.argtypes = [P]
+    lib.cpr_nn_last_error.restype = ctypes.c_char_p
+    lib.cpr_nn_set_params.argtypes = [P, P]
+    lib.cpr_nn_get_params.argtypes = [P, P]
+    lib.cpr_nn_forward.argtypes = [P, P, ctypes.c_int, P]
+    lib.cpr_nn_backward.argtypes = [P, P, P]
+    lib.cpr_nn_train_step.argtypes = [P, P, P, ctypes.c_int, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]
+    lib.cpr_nn_attach.argtypes = [P, P]
+    lib.cpr_pressure_stage.argtypes = [P, P, P, P]
+    lib.cpr_nn_features.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double)]
+    lib.cpr_export_krylov.argtypes = [P, ctypes.c_int, P]
     _lib = lib
     return lib
 
@@ -112,10 +129,77 @@ class CPRError(RuntimeError):
         self.code = code
 
 
-def _ptr(t):
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise TypeError("expected a contiguous float64 CUDA tensor")
+def _ptr(t, dtype=torch.float64):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"expected a contiguous {dtype} CUDA tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _fptr(t):
+    return _ptr(t, torch.float32)
+
+
+class Network:
+    """The pressure-correction network (training and inference on the GPU)."""
+
+    def __init__(self, nx, ny, nz, max_batch=1, stream=None):
+        self.lib = load()
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = self.lib.cpr_nn_create(nx, ny, nz, max_batch, ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(h))
+        self.h = h
+        if rc != 0:
+            msg = self.lib.cpr_nn_last_error(h).decode() if h.value else ""
+            self.lib.cpr_nn_destroy(h)
+            self.h = None
+            raise CPRError(rc, msg)
+        self.P = int(self.lib.cpr_nn_num_params())
+
+    def _check(self, rc):
+        if rc != 0:
+            raise CPRError(rc, self.lib.cpr_nn_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cpr_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        assert th.size == self.P
+        self._check(self.lib.cpr_nn_set_params(self.h, th.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_params(self):
+        th = np.empty(self.P, dtype=np.float32)
+        self._check(self.lib.cpr_nn_get_params(self.h, th.ctypes.data_as(ctypes.c_void_p)))
+        return th
+
+    def forward(self, x):
+        """x: float32 CUDA tensor [B, nz, ny, nx, 3] -> y [B, nz, ny, nx]."""
+        B = x.shape[0]
+        y = torch.empty((B,) + self.shape, dtype=torch.float32, device="cuda")
+        self._check(self.lib.cpr_nn_forward(self.h, _fptr(x), B, _fptr(y)))
+        return y
+
+    def backward(self, dy):
+        g = torch.empty(self.P, dtype=torch.float32, device="cuda")
+        self._check(self.lib.cpr_nn_backward(self.h, _fptr(dy), _fptr(g)))
+        return g
+
+    def train_step(self, x, t, lr=1e-3):
+        loss = ctypes.c_float()
+        self._check(self.lib.cpr_nn_train_step(self.h, _fptr(x), _fptr(t), x.shape[0], float(lr),
+                                               ctypes.byref(loss)))
+        return float(loss.value)
 
 
 def default_options(**kw):
@@ -264,6 +348,33 @@ class Solver:
         n, ms = ctypes.c_int(), ctypes.c_double()
         self._check(self.lib.cpr_profile_read(self.ctx, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+    def attach_network(self, theta):
+        """Give the solver trained network parameters (None detaches)."""
+        if theta is None:
+            self._check(self.lib.cpr_nn_attach(self.ctx, None))
+            return
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        self._check(self.lib.cpr_nn_attach(self.ctx, th.ctypes.data_as(ctypes.c_void_p)))
+
+    def pressure_stage(self, v):
+        """(r', dp_mg) of the pressure stage applied to v [b, nz, ny, nx]."""
+        rp = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        dp = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        self._check(self.lib.cpr_pressure_stage(self.ctx, _ptr(v), _ptr(rp), _ptr(dp)))
+        return rp, dp
+
+    def features(self, rprime):
+        """Network input [nz, ny, nx, 3] for a pressure residual, and its scale."""
+        f = torch.empty(self.shape + (3,), dtype=torch.float32, device="cuda")
+        sc = ctypes.c_double()
+        self._check(self.lib.cpr_nn_features(self.ctx, _ptr(rprime), _fptr(f), ctypes.byref(sc)))
+        return f, sc.value
+
+    def export_krylov(self, j):
+        v = self.vector()
+        self._check(self.lib.cpr_export_krylov(self.ctx, j, _ptr(v)))
+        return v
 
     def export_ilu(self):
         d = torch.empty((self.b, self.b) + self.shape, dtype=torch.float64, device="cuda")

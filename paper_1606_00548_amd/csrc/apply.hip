@@ -526,6 +526,7 @@ void apply_impl(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, 
   decouple_red_kernel<B, T><<<div_up(L.n, 256), 256, 0, s>>>(L.n, L.nh, ctx->w, vin, v, nrm2, Pre<T>::A(L0),
                                                             rp, Pre<T>::x(L0));
   vcycle<T>(ctx);
+  if (ctx->opt.learned) learned_stage(ctx);
   const T* dp = Pre<T>::x(L0);
   const T* J = Pre<T>::J(ctx);
   const T* R0 = Pre<T>::R0(ctx);
@@ -572,6 +573,19 @@ void launch_mixed_copies(cpr_ctx* ctx) {
     size_t m = (size_t)7 * L.lay.n;
     to_float_kernel<<<div_up((long)m, 256), 256, 0, s>>>(m, L.A, L.Af);
   }
+}
+
+// Pressure stage alone (FP64): r~_p = w^T v into level 0's r, dp_mg into its x.
+void precond_pressure_stage(cpr_ctx* ctx, const double* v) {
+  const Lay& L = ctx->lay;
+  MGLevel& L0 = ctx->levels[0];
+  if (ctx->b == 2)
+    decouple_red_kernel<2, double><<<div_up(L.n, 256), 256, 0, ctx->stream>>>(L.n, L.nh, ctx->w, v, nullptr, nullptr,
+                                                                               L0.A, L0.r, L0.x);
+  else
+    decouple_red_kernel<3, double><<<div_up(L.n, 256), 256, 0, ctx->stream>>>(L.n, L.nh, ctx->w, v, nullptr, nullptr,
+                                                                               L0.A, L0.r, L0.x);
+  vcycle<double>(ctx);
 }
 
 void precond_apply(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, double* z) {

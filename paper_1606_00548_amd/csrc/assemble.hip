@@ -187,7 +187,8 @@ template <int MODEL>
 struct PropPlanes {
   static constexpr int B = Traits<MODEL>::B, NP = Traits<MODEL>::NP, NT = Traits<MODEL>::NT;
   static constexpr int RHO = 0, DRHO = NP, LAM = 2 * NP, DLAM = 2 * NP + NT;
-  static constexpr int COUNT = 2 * NP + NT + NT * B;
+  static constexpr int LT = 2 * NP + NT + NT * B;   // total volumetric mobility (network feature)
+  static constexpr int COUNT = LT + 1;
 };
 
 template <int MODEL>
@@ -210,6 +211,7 @@ __global__ void props_kernel(FluidDev f, Lay L, const double* __restrict__ poro,
     props[(PP::LAM + q) * n + t] = s.lam[q];
     for (int u = 0; u < B; ++u) props[(PP::DLAM + q * B + u) * n + t] = s.dlam[q][u];
   }
+  props[PP::LT * n + t] = s.lt;
 }
 
 template <int MODEL>
@@ -444,6 +446,11 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
 // Number of SoA planes the per-cell state needs (allocation size).
 int props_planes(int model) {
   return model == 2 ? PropPlanes<2>::COUNT : PropPlanes<3>::COUNT;
+}
+
+// Plane of the per-cell state that holds the total volumetric mobility.
+int props_lt_plane(int model) {
+  return model == 2 ? PropPlanes<2>::LT : PropPlanes<3>::LT;
 }
 
 double host_pvt(const FluidDev& f, int row, double p) {

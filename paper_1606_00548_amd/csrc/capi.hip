@@ -42,11 +42,14 @@ void free_all(cpr_ctx* ctx) {
   void* bufs[] = {ctx->poro, ctx->tp, ctx->perfs_d, ctx->J, ctx->props, ctx->vin, ctx->vin2, ctx->vout,
                   ctx->w, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf, ctx->flag, ctx->V, ctx->Z,
                   ctx->Y, ctx->rp, ctx->xs, ctx->rs, ctx->tmp, ctx->vf, ctx->zf, ctx->Yf, ctx->rpf,
-                  ctx->part, ctx->hdev};
+                  ctx->part, ctx->hdev, ctx->lnk, ctx->rprime, ctx->dpnn, ctx->feat, ctx->nnscal,
+                  ctx->nncount};
   for (void* b : bufs)
     if (b) hipFree(b);
   if (ctx->hhost) hipHostFree(ctx->hhost);
   for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
+  if (ctx->nn) cpr_nn_destroy(ctx->nn);
+  ctx->nn = nullptr;
   ctx->ev.clear();
 }
 
@@ -111,6 +114,12 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
   ALLOC(ctx->rs, b * N);
   ALLOC(ctx->tmp, b * N);
   ALLOC(ctx->flag, 4);
+  ALLOC(ctx->lnk, N);
+  ALLOC(ctx->rprime, N);
+  ALLOC(ctx->dpnn, N);
+  ALLOC(ctx->feat, 3 * N);
+  ALLOC(ctx->nnscal, 16);
+  ALLOC(ctx->nncount, 2);
   ctx->nblk = div_up((long)b * n, 1024);
   if (ctx->nblk > 1024) ctx->nblk = 1024;
   ALLOC(ctx->part, 66 * (size_t)ctx->nblk);
@@ -123,6 +132,7 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
   hipStream_t s = ctx->stream;
   launch_nat_to_cs(ctx->lay, 1, poro, ctx->poro, s);
   launch_transmissibility(ctx->lay, *g, perm3, ctx->tp, s);
+  launch_lnk(ctx->lay, perm3, ctx->lnk, s);
   if ((rc = launch_check(ctx, "cpr_create kernels")) != CPR_OK) return rc;
   // mean porosity (compensated sum) for the row scaling
   {
@@ -277,6 +287,7 @@ int assemble_jacobian(cpr_ctx_t* ctx, const double* x_old, const double* x, doub
   launch_nat_to_cs(ctx->lay, ctx->b, x, ctx->vin, s);
   launch_assemble(ctx, ctx->vin2, ctx->vin, dt_days, ctx->vout);
   launch_cs_to_nat(ctx->lay, ctx->b, ctx->vout, rhs_out, s);
+  ctx->assembled = 1;
   ctx->setup_done = 0;
   return launch_check(ctx, "assemble_jacobian");
   GUARD_END
@@ -309,13 +320,20 @@ int cpr_setup(cpr_ctx_t* ctx, const cpr_options_t* o) {
     return set_err(ctx, CPR_EINVAL, "mg_coarsest must be 1..4096");
   if (opt.precision != CPR_PREC_FP64 && opt.precision != CPR_PREC_MIXED)
     return set_err(ctx, CPR_EINVAL, "unknown precision");
-  if (opt.learned) return set_err(ctx, CPR_EINVAL, "no pressure-correction network loaded");
+  if (opt.learned && !ctx->nn) return set_err(ctx, CPR_EINVAL, "no pressure-correction network attached");
   ctx->opt = opt;
   ctx->setup_done = 0;
   int rc;
   if ((rc = ensure_krylov(ctx, opt.restart)) != CPR_OK) return rc;
   if (opt.precision == CPR_PREC_MIXED && (rc = ensure_mixed(ctx)) != CPR_OK) return rc;
-  return setup_cpr(ctx);
+  if ((rc = setup_cpr(ctx)) != CPR_OK) return rc;
+  if (opt.learned) {
+    if ((rc = learned_setup(ctx, true)) != CPR_OK) {
+      ctx->setup_done = 0;
+      return rc;
+    }
+  }
+  return CPR_OK;
   GUARD_END
 }
 
@@ -326,12 +344,88 @@ int cpr_gmres_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* 
   if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
   hipStream_t s = ctx->stream;
   launch_nat_to_cs(ctx->lay, ctx->b, rhs, ctx->rs, s);
+  if (ctx->opt.learned) CPR_TRY(hipMemsetAsync(ctx->nncount, 0, 2 * sizeof(int), s));
   int rc = fgmres_solve(ctx, st);
   if (rc < 0) return rc;
   launch_cs_to_nat(ctx->lay, ctx->b, ctx->xs, dx, s);
   int rc2 = launch_check(ctx, "cpr_gmres_solve");
-  return rc2 != CPR_OK ? rc2 : rc;
+  if (rc2 != CPR_OK) return rc2;
+  if (ctx->opt.learned && st) {
+    int cnt[2] = {0, 0};
+    CPR_TRY(hipMemcpyAsync(cnt, ctx->nncount, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    CPR_TRY(hipStreamSynchronize(s));
+    st->nn_accepted = cnt[0];
+    st->nn_rejected = cnt[1];
+  }
+  return rc;
   GUARD_END
+}
+
+int cpr_nn_attach(cpr_ctx_t* ctx, const float* theta) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  GUARD_BEGIN
+  if (!theta) {
+    if (ctx->nn) cpr_nn_destroy(ctx->nn);
+    ctx->nn = nullptr;
+    if (ctx->opt.learned) ctx->setup_done = 0;
+    return CPR_OK;
+  }
+  const cpr_grid_t& g = ctx->grid;
+  if (g.nx % 8 || g.ny % 8 || g.nz % 8)
+    return set_err(ctx, CPR_EINVAL, "the learned stage needs grid dimensions divisible by 8");
+  if (!ctx->nn) {
+    cpr_nn_t* nn = nullptr;
+    int rc = cpr_nn_create(g.nx, g.ny, g.nz, 1, ctx->stream, &nn);
+    if (rc != CPR_OK) {
+      std::string m = nn ? cpr_nn_last_error(nn) : "network allocation failed";
+      cpr_nn_destroy(nn);
+      return set_err(ctx, rc, m);
+    }
+    ctx->nn = nn;
+  }
+  int rc = cpr_nn_set_params(ctx->nn, theta);
+  if (rc != CPR_OK) return set_err(ctx, rc, cpr_nn_last_error(ctx->nn));
+  return CPR_OK;
+  GUARD_END
+}
+
+int cpr_pressure_stage(cpr_ctx_t* ctx, const double* v, double* rprime, double* dp_mg) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (!v || !rprime) return set_err(ctx, CPR_EINVAL, "null argument");
+  if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
+  hipStream_t s = ctx->stream;
+  launch_nat_to_cs(ctx->lay, ctx->b, v, ctx->vin, s);
+  precond_pressure_stage(ctx, ctx->vin);
+  learned_rprime(ctx);
+  launch_cs_to_nat(ctx->lay, 1, ctx->rprime, rprime, s);
+  if (dp_mg) launch_cs_to_nat(ctx->lay, 1, ctx->levels[0].x, dp_mg, s);
+  return launch_check(ctx, "cpr_pressure_stage");
+}
+
+int cpr_nn_features(cpr_ctx_t* ctx, const double* rprime, float* feat, double* scale) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  GUARD_BEGIN
+  if (!rprime || !feat) return set_err(ctx, CPR_EINVAL, "null argument");
+  if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
+  int rc = learned_setup(ctx, false);
+  if (rc != CPR_OK) return rc;
+  hipStream_t s = ctx->stream;
+  launch_nat_to_cs(ctx->lay, 1, rprime, ctx->rprime, s);
+  learned_features_from_rprime(ctx);
+  CPR_TRY(hipMemcpyAsync(feat, ctx->feat, 3 * (size_t)ctx->lay.n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  double sc[8];
+  CPR_TRY(hipMemcpyAsync(sc, ctx->nnscal, sizeof(sc), hipMemcpyDeviceToHost, s));
+  CPR_TRY(hipStreamSynchronize(s));
+  if (scale) *scale = sc[4];
+  return launch_check(ctx, "cpr_nn_features");
+  GUARD_END
+}
+
+int cpr_export_krylov(cpr_ctx_t* ctx, int j, double* v) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  if (!v || j < 0 || j > ctx->mcap || !ctx->V) return set_err(ctx, CPR_EINVAL, "bad basis index");
+  launch_cs_to_nat(ctx->lay, ctx->b, ctx->V + (size_t)j * ctx->b * ctx->lay.n, v, ctx->stream);
+  return launch_check(ctx, "cpr_export_krylov");
 }
 
 int cpr_newton_update(cpr_ctx_t* ctx, double* x, const double* dx) {

@@ -198,6 +198,16 @@ struct cpr_ctx {
   int nblk = 0;
 
   // kernel-duration sampling (one kernel class at a time)
+  // learned pressure correction
+  struct cpr_nn* nn = nullptr;  // inference network on this grid (batch 1)
+  double* lnk = nullptr;       // [n] ln kx (colour-split)
+  double* rprime = nullptr;    // [n] pressure residual after the V-cycle
+  double* dpnn = nullptr;      // [n] network correction
+  float* feat = nullptr;       // [n][3] network input, natural order
+  double* nnscal = nullptr;    // device scalars: feature statistics, norms
+  int* nncount = nullptr;      // [2] accepted / rejected corrections
+  int assembled = 0;           // a Jacobian was assembled (mobility plane valid)
+
   int prof_class = -1;
   std::vector<hipEvent_t> ev;  // start/stop pairs
   int ev_used = 0;
@@ -253,6 +263,15 @@ int setup_cpr(cpr_ctx* ctx);
 // vector: v = vin / sqrt(*nrm2) is formed and stored on the way (vin may
 // equal v).  Otherwise v must equal vin.
 void precond_apply(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, double* z);
+
+void precond_pressure_stage(cpr_ctx* ctx, const double* v);
+
+// learned.hip
+int learned_setup(cpr_ctx* ctx, bool need_nn);
+int learned_stage(cpr_ctx* ctx);
+void learned_rprime(cpr_ctx* ctx);
+void learned_features_from_rprime(cpr_ctx* ctx);
+void launch_lnk(const Lay& L, const double* perm_nat, double* lnk, hipStream_t s);
 
 // krylov.hip
 int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st);

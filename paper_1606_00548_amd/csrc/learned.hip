@@ -1,0 +1,251 @@
+// Learned pressure correction inside the CPR preconditioner (an addition to
+// the paper's method).
+//
+// After the multigrid cycle has produced dp_mg for the decoupled pressure
+// residual r~_p, the network sees what the cycle left behind,
+//   r' = r~_p - A_p dp_mg,
+// through three per-cell features (standardised ln k_x, standardised ln of
+// the total mobility, and D^-1 r' / s with s = rms(D^-1 r'), D = diag A_p)
+// and proposes dp_nn = s * N(features).  Plain CPR judges it in FP64: the
+// correction is kept only if ||r' - A_p dp_nn||_2 < ||r'||_2, otherwise the
+// multigrid result stands.  Everything stays on the device (the decision is
+// a flag read by the kernel that applies the correction), so the learned
+// stage adds no host synchronisation to an FGMRES iteration.
+#include <cmath>
+
+#include "internal.h"
+
+int nn_infer(cpr_nn* nn, const float* x3, float* y);
+float* nn_output(cpr_nn* nn);
+int props_lt_plane(int model);
+
+namespace {
+
+constexpr int LB = 256;
+// device scalars (ctx->nnscal)
+enum { S_MK = 0, S_SK, S_ML, S_SL, S_RMS, S_R2, S_RR2, S_ACC, S_COUNT };
+
+__device__ inline double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < LB / 64; ++w) s += sh[w];
+  return s;
+}
+
+// per-block partials of ln kx, ln kx^2, ln lt, ln lt^2
+__global__ __launch_bounds__(LB) void stats_partial_kernel(int n, const double* __restrict__ lnk,
+                                                           const double* __restrict__ lt, double* __restrict__ part,
+                                                           int nblk) {
+  __shared__ double sh[LB / 64];
+  double a = 0, b = 0, c = 0, d = 0;
+  for (int t = blockIdx.x * LB + threadIdx.x; t < n; t += nblk * LB) {
+    double k = lnk[t], l = log(lt[t]);
+    a += k; b += k * k; c += l; d += l * l;
+  }
+  double r[4] = {a, b, c, d};
+  for (int q = 0; q < 4; ++q) {
+    double s = block_sum(r[q], sh);
+    if (threadIdx.x == 0) part[(size_t)q * nblk + blockIdx.x] = s;
+  }
+}
+
+__global__ void stats_final_kernel(int n, const double* __restrict__ part, int nblk, double* __restrict__ scal) {
+  if (threadIdx.x != 0) return;
+  double s[4] = {0, 0, 0, 0};
+  for (int q = 0; q < 4; ++q)
+    for (int b = 0; b < nblk; ++b) s[q] += part[(size_t)q * nblk + b];
+  double mk = s[0] / n, ml = s[2] / n;
+  double vk = s[1] / n - mk * mk, vl = s[3] / n - ml * ml;
+  scal[S_MK] = mk;
+  scal[S_SK] = vk > 1e-24 ? sqrt(vk) : 1.0;
+  scal[S_ML] = ml;
+  scal[S_SL] = vl > 1e-24 ? sqrt(vl) : 1.0;
+}
+
+// r' = rp - A_p dp on the fine colour-split level, with block partials of
+// sum (r'/a_0)^2 and sum r'^2.  rp / dp null: r' already stored.
+template <typename T>
+__global__ __launch_bounds__(LB) void rprime_kernel(Lay L, const double* __restrict__ A, const T* __restrict__ rp,
+                                                    const T* __restrict__ dp, double* __restrict__ rprime,
+                                                    double* __restrict__ part, int nblk) {
+  __shared__ double sh[LB / 64];
+  double a = 0, b = 0;
+  for (int t = blockIdx.x * LB + threadIdx.x; t < L.n; t += nblk * LB) {
+    double r;
+    if (rp) {
+      CsCell cc = cs_decode(L, t);
+      double y = A[t] * (double)dp[t];
+#pragma unroll
+      for (int d = 1; d < 7; ++d) {
+        int nb = cs_nb(L, cc, d);
+        if (nb >= 0) y += A[(size_t)d * L.n + t] * (double)dp[nb];
+      }
+      r = (double)rp[t] - y;
+      rprime[t] = r;
+    } else {
+      r = rprime[t];
+    }
+    double q = r / A[t];
+    a += q * q;
+    b += r * r;
+  }
+  double s = block_sum(a, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  s = block_sum(b, sh);
+  if (threadIdx.x == 0) part[(size_t)nblk + blockIdx.x] = s;
+}
+
+__global__ void rprime_final_kernel(int n, const double* __restrict__ part, int nblk, double* __restrict__ scal) {
+  if (threadIdx.x != 0) return;
+  double a = 0, b = 0;
+  for (int k = 0; k < nblk; ++k) a += part[k];
+  for (int k = 0; k < nblk; ++k) b += part[(size_t)nblk + k];
+  scal[S_RMS] = sqrt(a / n);
+  scal[S_R2] = b;
+}
+
+// network input [natural cell][3]
+__global__ __launch_bounds__(LB) void features_kernel(Lay L, const double* __restrict__ lnk,
+                                                      const double* __restrict__ lt, const double* __restrict__ A,
+                                                      const double* __restrict__ rprime,
+                                                      const double* __restrict__ scal, float* __restrict__ feat) {
+  int t = blockIdx.x * LB + threadIdx.x;
+  if (t >= L.n) return;
+  int i, j, k;
+  lay_coords(L, t, i, j, k);
+  long nat = i + (long)L.nx * (j + (long)L.ny * k);
+  double s = scal[S_RMS];
+  feat[nat * 3 + 0] = (float)((lnk[t] - scal[S_MK]) / scal[S_SK]);
+  feat[nat * 3 + 1] = (float)((log(lt[t]) - scal[S_ML]) / scal[S_SL]);
+  feat[nat * 3 + 2] = s > 0 ? (float)((rprime[t] / A[t]) / s) : 0.f;
+}
+
+// dp_nn = s * N(...) back in colour-split order
+__global__ __launch_bounds__(LB) void dpnn_kernel(Lay L, const float* __restrict__ y, const double* __restrict__ scal,
+                                                  double* __restrict__ dpnn) {
+  int t = blockIdx.x * LB + threadIdx.x;
+  if (t >= L.n) return;
+  int i, j, k;
+  lay_coords(L, t, i, j, k);
+  long nat = i + (long)L.nx * (j + (long)L.ny * k);
+  dpnn[t] = scal[S_RMS] * (double)y[nat];
+}
+
+// block partials of ||r' - A_p dp_nn||^2
+__global__ __launch_bounds__(LB) void judge_partial_kernel(Lay L, const double* __restrict__ A,
+                                                           const double* __restrict__ rprime,
+                                                           const double* __restrict__ dpnn, double* __restrict__ part,
+                                                           int nblk) {
+  __shared__ double sh[LB / 64];
+  double a = 0;
+  for (int t = blockIdx.x * LB + threadIdx.x; t < L.n; t += nblk * LB) {
+    CsCell cc = cs_decode(L, t);
+    double y = A[t] * dpnn[t];
+#pragma unroll
+    for (int d = 1; d < 7; ++d) {
+      int nb = cs_nb(L, cc, d);
+      if (nb >= 0) y += A[(size_t)d * L.n + t] * dpnn[nb];
+    }
+    double r = rprime[t] - y;
+    a += r * r;
+  }
+  double s = block_sum(a, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void judge_final_kernel(const double* __restrict__ part, int nblk, double* __restrict__ scal,
+                                   int* __restrict__ count) {
+  if (threadIdx.x != 0) return;
+  double a = 0;
+  for (int k = 0; k < nblk; ++k) a += part[k];
+  scal[S_RR2] = a;
+  bool accept = isfinite(a) && a < scal[S_R2];
+  scal[S_ACC] = accept ? 1.0 : 0.0;
+  if (accept) count[0] += 1; else count[1] += 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(LB) void correct_kernel(int n, const double* __restrict__ scal,
+                                                     const double* __restrict__ dpnn, T* __restrict__ dp) {
+  int t = blockIdx.x * LB + threadIdx.x;
+  if (t >= n || !(scal[S_ACC] > 0.0)) return;
+  dp[t] = (T)((double)dp[t] + dpnn[t]);
+}
+
+__global__ void lnk_kernel(Lay L, const double* __restrict__ perm, double* __restrict__ lnk) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L.n) return;
+  int i = t % L.nx, jk = t / L.nx, j = jk % L.ny, k = jk / L.ny;
+  lnk[lay_index(L, i, j, k)] = log(perm[t]);
+}
+
+}  // namespace
+
+void launch_lnk(const Lay& L, const double* perm_nat, double* lnk, hipStream_t s) {
+  lnk_kernel<<<div_up(L.n, 256), 256, 0, s>>>(L, perm_nat, lnk);
+}
+
+// Feature statistics of the current state (after assembly), at setup.
+int learned_setup(cpr_ctx* ctx, bool need_nn) {
+  if (need_nn && !ctx->nn) return set_err(ctx, CPR_EINVAL, "options.learned set but no network attached");
+  if (!ctx->assembled) return set_err(ctx, CPR_EINVAL, "the learned stage needs an assembled state");
+  const double* lt = ctx->props + (size_t)props_lt_plane(ctx->fl.model) * ctx->lay.n;
+  stats_partial_kernel<<<ctx->nblk, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->lnk, lt, ctx->part, ctx->nblk);
+  stats_final_kernel<<<1, 64, 0, ctx->stream>>>(ctx->lay.n, ctx->part, ctx->nblk, ctx->nnscal);
+  return launch_check(ctx, "learned_setup");
+}
+
+// r' and its norms for rp, dp of the fine level (T = preconditioner type);
+// with rp == nullptr, ctx->rprime already holds r'.
+template <typename T>
+static void rprime_launch(cpr_ctx* ctx, const T* rp, const T* dp) {
+  const MGLevel& L0 = ctx->levels[0];
+  rprime_kernel<T><<<ctx->nblk, LB, 0, ctx->stream>>>(ctx->lay, L0.A, rp, dp, ctx->rprime, ctx->part, ctx->nblk);
+  rprime_final_kernel<<<1, 64, 0, ctx->stream>>>(ctx->lay.n, ctx->part, ctx->nblk, ctx->nnscal);
+}
+
+static void features_launch(cpr_ctx* ctx) {
+  const double* lt = ctx->props + (size_t)props_lt_plane(ctx->fl.model) * ctx->lay.n;
+  features_kernel<<<div_up(ctx->lay.n, LB), LB, 0, ctx->stream>>>(ctx->lay, ctx->lnk, lt, ctx->levels[0].A,
+                                                                  ctx->rprime, ctx->nnscal, ctx->feat);
+}
+
+// The learned stage on the fine level's (rp, dp) of one CPR application.
+template <typename T>
+static int learned_stage_t(cpr_ctx* ctx, const T* rp, T* dp) {
+  hipStream_t s = ctx->stream;
+  const Lay& L = ctx->lay;
+  rprime_launch<T>(ctx, rp, dp);
+  features_launch(ctx);
+  int rc = nn_infer(ctx->nn, ctx->feat, nullptr);
+  if (rc) return set_err(ctx, rc, "network inference failed");
+  dpnn_kernel<<<div_up(L.n, LB), LB, 0, s>>>(L, nn_output(ctx->nn), ctx->nnscal, ctx->dpnn);
+  judge_partial_kernel<<<ctx->nblk, LB, 0, s>>>(L, ctx->levels[0].A, ctx->rprime, ctx->dpnn, ctx->part, ctx->nblk);
+  judge_final_kernel<<<1, 64, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal, ctx->nncount);
+  correct_kernel<T><<<div_up(L.n, LB), LB, 0, s>>>(L.n, ctx->nnscal, ctx->dpnn, dp);
+  return CPR_OK;
+}
+
+int learned_stage(cpr_ctx* ctx) {
+  MGLevel& L0 = ctx->levels[0];
+  if (ctx->opt.precision == CPR_PREC_MIXED) return learned_stage_t<float>(ctx, L0.rf, L0.xf);
+  return learned_stage_t<double>(ctx, L0.r, L0.x);
+}
+
+// r' for the fine level after a pressure stage (FP64 path).
+void learned_rprime(cpr_ctx* ctx) {
+  MGLevel& L0 = ctx->levels[0];
+  rprime_launch<double>(ctx, L0.r, L0.x);
+}
+
+// Features for a residual already stored in ctx->rprime.
+void learned_features_from_rprime(cpr_ctx* ctx) {
+  rprime_launch<double>(ctx, nullptr, nullptr);
+  features_launch(ctx);
+}

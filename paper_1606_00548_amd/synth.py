@@ -220,6 +220,25 @@ def single_phase_uniform(nx, ny, nz, k_md=100.0, poro=0.2, wells=()):
                  1.0, f"single-phase uniform {nx}x{ny}x{nz}")
 
 
+# (input, output) channels of the seven 3x3x3 convolutions of the pressure
+# network, in parameter order; the 1x1x1 head maps 16 channels to 1.
+NN_CONVS = [(3, 16), (16, 32), (32, 64), (64, 64), (64, 64), (64, 32), (32, 16)]
+
+
+def nn_initial_weights(seed):
+    """Random initial parameters of the pressure network as one flat float32
+    vector (per convolution: weights [27][Cin][Cout] ~ N(0, 2/(27 Cin)),
+    zero bias; head weights ~ N(0, 1/16), zero bias)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in NN_CONVS:
+        parts.append(rng.standard_normal(27 * ci * co) * np.sqrt(2.0 / (27 * ci)))
+        parts.append(np.zeros(co))
+    parts.append(rng.standard_normal(16) * 0.25)
+    parts.append(np.zeros(1))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def random_state_perturbation(case, seed, dp=5.0, ds=0.05):
     """A perturbed current state x (x_old unchanged) for Jacobian tests."""
     rng = np.random.default_rng(seed)

@@ -1,0 +1,171 @@
+"""Parity of the GPU pressure-correction network (BF16 matrix cores, FP32
+accumulation) and of the learned CPR stage with the FP64 oracle.
+
+Tolerances (parameters are BF16-exact, see _theta): BF16 operands carry 8
+significant bits (relative rounding 2^-9 ~ 2e-3 per operand); sums over
+27*64 products and seven stacked convolutions grow that to ~1e-2, so forward
+outputs are compared in relative 2-norm at 3e-2 and gradients at 2e-2 (3e-2
+per layer) in a regime where no ReLU can change state; where ReLU masks can
+flip, only the gradient direction is required to agree (cosine >= 0.99).
+FP32 features at 1e-5, FP64 residuals at 1e-9 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import cpr, learned, model, nn
+from paper_1606_00548_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _bf16(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    a = np.asarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def _theta(seed):
+    """Parameters that BF16 represents exactly: the network's convolutions run
+    with BF16 weights, so the oracle then sees the very same weights and the
+    comparison measures activation and gradient rounding only."""
+    rng = np.random.default_rng(seed)
+    th = synth.nn_initial_weights(seed).astype(np.float64)
+    convs, head = nn.unpack(th)
+    return _bf16(nn.pack([(W, rng.uniform(-0.05, 0.1, b.shape)) for W, b in convs], head))
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b)
+
+
+def _net(shape, batch):
+    from paper_1606_00548_amd import cprmi
+    nz, ny, nx = shape
+    return cprmi.Network(nx, ny, nz, max_batch=batch)
+
+
+def test_forward_matches_oracle():
+    theta = _theta(1)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((2, 8, 16, 16, 3)).astype(np.float32)
+    net = _net((8, 16, 16), 2)
+    net.set_params(theta.astype(np.float32))
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    yo, _ = nn.forward(theta.astype(np.float32).astype(np.float64), x.astype(np.float64))
+    print(f"[nn] forward rel. diff {_rel(y, yo):.2e}")
+    assert _rel(y, yo) <= 3e-2
+
+
+def _grads(theta, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((2, 8, 16, 16, 3)).astype(np.float32)
+    dy = rng.standard_normal((2, 8, 16, 16)).astype(np.float32)
+    net = _net((8, 16, 16), 2)
+    net.set_params(theta.astype(np.float32))
+    net.forward(torch.from_numpy(x).cuda())
+    g = net.backward(torch.from_numpy(dy).cuda()).cpu().numpy().astype(np.float64)
+    yo, cache = nn.forward(theta, x.astype(np.float64))
+    return g, nn.backward(theta, cache, dy.astype(np.float64))
+
+
+def test_backward_matches_oracle_without_relu_flips():
+    # Large biases keep every ReLU open, so no unit can switch sides under
+    # BF16 rounding: the gradient then differs only by rounding (~1e-2);
+    # a wrong index, tap or dropped term would give an O(1) difference.
+    convs, head = nn.unpack(synth.nn_initial_weights(3).astype(np.float64))
+    theta = _bf16(nn.pack([(0.3 * W, np.full(b.shape, 3.0)) for W, b in convs], head))
+    g, go = _grads(theta, 4)
+    print(f"[nn] gradient rel. diff (open ReLUs) {_rel(g, go):.2e}")
+    assert _rel(g, go) <= 2e-2
+    o = 0
+    for k, (ci, co) in enumerate(nn.CONVS):
+        m = 27 * ci * co + co
+        r = _rel(g[o:o + m], go[o:o + m])
+        print(f"[nn]   conv {k}: {r:.2e}")
+        assert r <= 3e-2
+        o += m
+    assert _rel(g[o:], go[o:]) <= 2e-2
+
+
+def test_backward_direction_matches_oracle():
+    # With half the units near their kink, BF16 rounding flips some ReLU
+    # masks and moves gradients by several percent (the FP64 oracle itself
+    # moves as much when only its weights are rounded to BF16); the
+    # direction must still agree.
+    g, go = _grads(_theta(3), 4)
+    cos = float(np.dot(g, go) / (np.linalg.norm(g) * np.linalg.norm(go)))
+    print(f"[nn] gradient rel. diff {_rel(g, go):.2e}, cosine {cos:.5f}")
+    assert cos >= 0.99 and _rel(g, go) <= 0.15
+
+
+def test_train_step_loss_matches_oracle_and_decreases():
+    theta = _theta(5)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((2, 8, 16, 16, 3)).astype(np.float32)
+    t = rng.standard_normal((2, 8, 16, 16)).astype(np.float32)
+    net = _net((8, 16, 16), 2)
+    net.set_params(theta.astype(np.float32))
+    xg, tg = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    L0 = net.train_step(xg, tg, lr=1e-3)
+    yo, _ = nn.forward(theta.astype(np.float32).astype(np.float64), x.astype(np.float64))
+    Lo, _ = nn.loss(yo, t.astype(np.float64))
+    assert abs(L0 - Lo) <= 3e-2 * Lo
+    for _ in range(40):
+        L = net.train_step(xg, tg, lr=2e-3)
+    print(f"[nn] loss {L0:.4f} -> {L:.4f} after 41 Adam steps")
+    assert L < 0.7 * L0
+    # parameters round-trip
+    th = net.get_params()
+    assert th.shape == (nn.num_params(),) and np.all(np.isfinite(th))
+
+
+def _ow_case():
+    return synth.oil_water_lognormal(16, 16, 8, seed=70)
+
+
+def test_pressure_stage_and_features_match_oracle():
+    from paper_1606_00548_amd import cprmi
+    case = _ow_case()
+    s = cprmi.Solver.from_case(case)
+    rhs = s.assemble(torch.as_tensor(case["x_old"]).cuda(), torch.as_tensor(case["x"]).cuda(), case["dt"])
+    s.setup()
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                          case["x_old"], case["x"], case["dt"])
+    pc = cpr.cpr_setup(J)
+    b = -R
+    v = b / np.linalg.norm(b)
+    rp_g, dp_g = s.pressure_stage(torch.as_tensor(v).cuda().contiguous())
+    rp_o, dp_o, rt0 = learned.pressure_stage(pc, v)
+    assert np.linalg.norm(dp_g.cpu().numpy() - dp_o) <= 1e-10 * np.linalg.norm(dp_o)
+    assert np.linalg.norm(rp_g.cpu().numpy() - rp_o) <= 1e-9 * np.linalg.norm(rt0)
+    f_g, sc_g = s.features(torch.as_tensor(rp_o).cuda().contiguous())
+    lam = learned.total_mobility(case["fluid"], case["poro"], case["x"])
+    f_o, sc_o = learned.features(case["perm"], lam, pc["mg"]["levels"][0], rp_o)
+    assert abs(sc_g - sc_o) <= 1e-12 * sc_o
+    assert np.allclose(f_g.cpu().numpy(), f_o, rtol=1e-5, atol=1e-5)
+
+
+def test_learned_solve_keeps_accuracy_and_counts_decisions():
+    from paper_1606_00548_amd import cprmi
+    case = _ow_case()
+    s = cprmi.Solver.from_case(case)
+    rhs = s.assemble(torch.as_tensor(case["x_old"]).cuda(), torch.as_tensor(case["x"]).cuda(), case["dt"])
+    s.attach_network(_theta(9).astype(np.float32))
+    for prec in ("fp64", "mixed"):
+        s.setup(learned=1, precision=prec)
+        dx, st = s.solve(rhs)
+        R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                              case["x_old"], case["x"], case["dt"])
+        b = -R
+        res = np.linalg.norm(b - cpr.block_spmv(J, dx.cpu().numpy())) / np.linalg.norm(b)
+        print(f"[learned] {prec}: iterations {st['iterations']}, accepted {st['nn_accepted']}, "
+              f"rejected {st['nn_rejected']}, true rel. residual {res:.2e}")
+        assert st["status"] == 0 and res <= 1e-6
+        assert st["nn_accepted"] + st["nn_rejected"] == st["iterations"]
+    # without a network the option is refused
+    s.attach_network(None)
+    with pytest.raises(cprmi.CPRError):
+        s.setup(learned=1)

@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--ny", type=int, default=128)
     ap.add_argument("--nz", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP64 / mixed / mixed+learned comparison runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -81,25 +83,47 @@ def main():
     x = x0.clone()
     opts = cprmi.default_options(precision=args.precision)
 
-    def step():
-        x.copy_(x0)
-        dx, st = cprmi.newton_step(solver, x_old, x, case["dt"], opts)
-        return st
+    def timed(o, kernel=None):
+        """Warm-up, then exactly args.steps Newton steps between two syncs."""
+        def step():
+            x.copy_(x0)
+            dx, st = cprmi.newton_step(solver, x_old, x, case["dt"], o)
+            return st
+        for _ in range(args.warmup):
+            step()
+        if kernel:
+            solver.profile_kernel(kernel)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [step() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = solver.profile_read() if kernel else (0, 0.0)
+        if kernel:
+            solver.profile_kernel(None)
+        if not all(st["status"] == 0 and st["true_rel"] <= 1e-6 for st in sts):
+            print("a timed solve did not reach the 1e-6 true relative residual", file=sys.stderr)
+            sys.exit(1)
+        return (t1 - t0) / args.steps, sts, prof
 
-    for _ in range(args.warmup):
-        step()
-    solver.profile_kernel(args.kernel)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = [step() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    launches, kernel_ms = solver.profile_read()
-    solver.profile_kernel(None)
-    sec_per_step = (t1 - t0) / args.steps
-    if not all(st["status"] == 0 and st["true_rel"] <= 1e-6 for st in stats):
-        print("a timed solve did not reach the 1e-6 true relative residual", file=sys.stderr)
-        sys.exit(1)
+    sec_per_step, stats, (launches, kernel_ms) = timed(opts, args.kernel)
+
+    # the other forms of the preconditioner on the same workload
+    variants = {}
+    if not args.no_variants:
+        wfile = os.path.join(ROOT, "paper_1606_00548_amd", "weights", "pressure_unet.npy")
+        forms = [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed"))]
+        if os.path.exists(wfile):
+            solver.attach_network(np.load(wfile))
+            forms.append(("mixed+learned", dict(precision="mixed", learned=1)))
+        for name, kw in forms:
+            sp, sts, _ = timed(cprmi.default_options(**kw))
+            variants[name] = {"s_per_step": sp, "fgmres_iterations": sts[-1]["iterations"],
+                              "true_rel": sts[-1]["true_rel"], "speedup_vs_fp64": None,
+                              "nn_accepted": sts[-1]["nn_accepted"]}
+        for v in variants.values():
+            v["speedup_vs_fp64"] = variants["fp64"]["s_per_step"] / v["s_per_step"]
+        solver.attach_network(None)
 
     # per-phase breakdown of one more (untimed) step
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
@@ -149,7 +173,7 @@ def main():
                                f"({n} cells, 3x3 blocks), one Newton step, FGMRES(30) to 1e-6",
                    "cells": n, "block": b, "precision": args.precision, "restart": 30, "rtol": 1e-6},
         "fgmres_iterations": its, "restart_cycles": cycles, "true_rel": st["true_rel"],
-        "phases_ms": phases, "roofline": roofline, "cpu_baseline": cpu,
+        "phases_ms": phases, "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
     }
     print(json.dumps(out))
 

@@ -241,16 +241,26 @@ int cpr_nn_forward(cpr_nn_t* nn, const float* x, int batch, float* y);
  * parameters: dy device [batch][n], grad device [num_params]. */
 int cpr_nn_backward(cpr_nn_t* nn, const float* dy, float* grad);
 
-/* One Adam step (lr; beta 0.9 / 0.999; eps 1e-8) on the normalised MSE
- * (1/B) sum_b |N(x_b) - t_b|^2 / |t_b|^2; x device [batch][n][3], t device
- * [batch][n]; *loss (host, may be NULL) receives the loss before the step. */
+/* One Adam step (lr; beta 0.9 / 0.999; eps 1e-8) on the direction loss
+ * (1/B) sum_b min_a |a N(x_b) - t_b|^2 / |t_b|^2 = 1 - cos^2(N(x_b), t_b);
+ * x device [batch][n][3], t device [batch][n]; *loss (host, may be NULL)
+ * receives the loss before the step. */
 int cpr_nn_train_step(cpr_nn_t* nn, const float* x, const float* t, int batch, float lr, float* loss);
+
+/* The loss of the current parameters on (x, t) without a step (host *loss). */
+int cpr_nn_eval_loss(cpr_nn_t* nn, const float* x, const float* t, int batch, float* loss);
+
+/* Training target t = e / scale (device: e [n] FP64 -> t [n] FP32) on the
+ * given stream: the network output that reproduces the correction e. */
+int cpr_nn_make_target(const double* e, long long n, double scale, float* t, void* stream);
 
 /* Give a solver context a copy of trained parameters (host array, NULL to
  * drop it).  With options.learned = 1 every CPR application then forms
- * r' = r~_p - A_p dp_mg after the multigrid cycle, evaluates the network,
- * dp_nn = rms * N(features), and keeps dp_mg + dp_nn only when
- * ||r' - A_p dp_nn||_2 < ||r'||_2; otherwise the plain CPR result stands.
+ * r' = r~_p - A_p dp_mg after the multigrid cycle, evaluates the network
+ * for a direction d = N(features), takes the residual-minimising step
+ * dp_nn = alpha d, alpha = <A_p d, r'> / |A_p d|^2, and keeps dp_mg + dp_nn
+ * only when ||r' - A_p dp_nn||_2 < ||r'||_2; otherwise the plain CPR result
+ * stands.
  * The grid must have dimensions divisible by 8. */
 int cpr_nn_attach(cpr_ctx_t* ctx, const float* theta);
 

@@ -6,8 +6,10 @@ paper.  After the multigrid cycle of the pressure stage,
 the network input per cell is (standardised ln k_x, standardised ln of the
 total volumetric mobility, D^-1 r' / s) with D = diag A_p and
 s = rms(D^-1 r') (standardisation: mean and population standard deviation
-over the grid, a zero spread replaced by 1).  The correction
-dp_nn = s * N(input) is kept only if ||r' - A_p dp_nn||_2 < ||r'||_2.
+over the grid, a zero spread replaced by 1).  The network output d is a
+direction; the correction dp_nn = alpha d takes the step that minimises
+||r' - alpha A_p d||_2, alpha = <A_p d, r'> / <A_p d, A_p d> (0 when A_p d
+vanishes), and is kept only if ||r' - A_p dp_nn||_2 < ||r'||_2.
 """
 import numpy as np
 
@@ -48,7 +50,11 @@ def learned_cpr_apply(pc, v, theta, perm_md, lam_t):
     rp, dp, rt0 = pressure_stage(pc, v)
     feat, s = features(perm_md, lam_t, Ap, rp)
     y, _ = nn.forward(theta, feat[None])
-    dpnn = s * y[0]
+    d = y[0]
+    q = cpr.scalar_spmv(Ap, d)
+    qq = float(np.sum(q * q))
+    alpha = float(np.sum(q * rp)) / qq if qq > 0 else 0.0
+    dpnn = alpha * d
     accepted = np.linalg.norm(rp - cpr.scalar_spmv(Ap, dpnn)) < np.linalg.norm(rp)
     if accepted:
         dp = dp + dpnn

@@ -12,7 +12,8 @@ kernels:
       e2 = relu(c2(pool e1))      e3 = relu(c3(pool e2))
       d2 = relu(c4(up e3)) + e2   d1 = relu(c5(up d2)) + e1
       d0 = relu(c6(up d1)) + e0   y  = wo . d0 + bo
-  Loss: normalised mean-squared error (1/B) sum_b |y_b - t_b|^2 / |t_b|^2.
+  Loss: the error of the best multiple of y_b, (1/B) sum_b min_a
+  |a y_b - t_b|^2 / |t_b|^2 (the network supplies a direction only).
 
 Parameters travel as one flat float vector: for c0..c6 the weights
 W[27][Cin][Cout] (tap = (dz+1)*9 + (dy+1)*3 + (dx+1)) then the bias[Cout],
@@ -168,13 +169,19 @@ def backward(theta, c, dy):
 
 
 def loss(y, t):
-    """Normalised MSE over the batch and its gradient with respect to y."""
+    """Scale-free error of the predicted direction, averaged over the batch:
+        L_b = min_a |a y_b - t_b|^2 / |t_b|^2 = 1 - (y_b.t_b)^2 / (|y_b|^2 |t_b|^2)
+    (the network supplies a direction; its length is chosen when it is
+    used), and its gradient with respect to y."""
     B = y.shape[0]
-    num = ((y - t) ** 2).reshape(B, -1).sum(axis=1)
-    den = (t ** 2).reshape(B, -1).sum(axis=1)
-    L = float(np.mean(num / den))
-    dy = 2.0 * (y - t) / (B * den[:, None, None, None])
-    return L, dy
+    yf, tf = y.reshape(B, -1), t.reshape(B, -1)
+    yt = np.sum(yf * tf, axis=1)
+    yy = np.sum(yf * yf, axis=1)
+    tt = np.sum(tf * tf, axis=1)
+    L = float(np.mean(1.0 - yt * yt / (yy * tt)))
+    c = (yt / (yy * tt))[:, None]
+    dy = -(2.0 / B) * (c * tf - (c * yt[:, None] / yy[:, None]) * yf)
+    return L, dy.reshape(y.shape)
 
 
 def adam_step(theta, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -68,7 +68,8 @@ EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error",
            "cpr_profile_kernel", "cpr_profile_read", "cpr_nn_num_params", "cpr_nn_create",
            "cpr_nn_destroy", "cpr_nn_last_error", "cpr_nn_set_params", "cpr_nn_get_params",
            "cpr_nn_forward", "cpr_nn_backward", "cpr_nn_train_step", "cpr_nn_attach",
-           "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov"]
+           "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov", "cpr_nn_eval_loss",
+           "cpr_nn_make_target"]
 KCLASS = {"spmv": 0, "orth": 1, "smooth": 2, "ilu": 3, "assemble": 4}
 
 
@@ -119,6 +120,8 @@ def load():
     lib.cpr_pressure_stage.argtypes = [P, P, P, P]
     lib.cpr_nn_features.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double)]
     lib.cpr_export_krylov.argtypes = [P, ctypes.c_int, P]
+    lib.cpr_nn_eval_loss.argtypes = [P, P, P, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
+    lib.cpr_nn_make_target.argtypes = [P, ctypes.c_longlong, ctypes.c_double, P, P]
     _lib = lib
     return lib
 
@@ -194,6 +197,11 @@ class Network:
         g = torch.empty(self.P, dtype=torch.float32, device="cuda")
         self._check(self.lib.cpr_nn_backward(self.h, _fptr(dy), _fptr(g)))
         return g
+
+    def eval_loss(self, x, t):
+        loss = ctypes.c_float()
+        self._check(self.lib.cpr_nn_eval_loss(self.h, _fptr(x), _fptr(t), x.shape[0], ctypes.byref(loss)))
+        return float(loss.value)
 
     def train_step(self, x, t, lr=1e-3):
         loss = ctypes.c_float()
@@ -380,6 +388,16 @@ class Solver:
         d = torch.empty((self.b, self.b) + self.shape, dtype=torch.float64, device="cuda")
         self._check(self.lib.cpr_export_ilu(self.ctx, _ptr(d)))
         return d
+
+
+def make_target(e, scale):
+    """FP32 training target e / scale computed on the GPU (e: float64 tensor)."""
+    t = torch.empty(e.shape, dtype=torch.float32, device="cuda")
+    rc = load().cpr_nn_make_target(_ptr(e.contiguous()), e.numel(), float(scale), _fptr(t),
+                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != 0:
+        raise CPRError(rc, "cpr_nn_make_target")
+    return t
 
 
 def newton_step(solver, x_old, x, dt_days, options=None, **kw):

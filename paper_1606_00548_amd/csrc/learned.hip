@@ -6,9 +6,10 @@
 //   r' = r~_p - A_p dp_mg,
 // through three per-cell features (standardised ln k_x, standardised ln of
 // the total mobility, and D^-1 r' / s with s = rms(D^-1 r'), D = diag A_p)
-// and proposes dp_nn = s * N(features).  Plain CPR judges it in FP64: the
-// correction is kept only if ||r' - A_p dp_nn||_2 < ||r'||_2, otherwise the
-// multigrid result stands.  Everything stays on the device (the decision is
+// and proposes a direction d = N(features); the step minimising the
+// pressure residual, alpha = <A_p d, r'> / <A_p d, A_p d>, gives
+// dp_nn = alpha d.  Plain CPR judges it in FP64: the correction is kept only
+// if ||r' - A_p dp_nn||_2 < ||r'||_2, otherwise the multigrid result stands.  Everything stays on the device (the decision is
 // a flag read by the kernel that applies the correction), so the learned
 // stage adds no host synchronisation to an FGMRES iteration.
 #include <cmath>
@@ -23,7 +24,7 @@ namespace {
 
 constexpr int LB = 256;
 // device scalars (ctx->nnscal)
-enum { S_MK = 0, S_SK, S_ML, S_SL, S_RMS, S_R2, S_RR2, S_ACC, S_COUNT };
+enum { S_MK = 0, S_SK, S_ML, S_SL, S_RMS, S_R2, S_RR2, S_ACC, S_ALPHA, S_COUNT };
 
 __device__ inline double block_sum(double v, double* sh) {
 #pragma unroll
@@ -126,33 +127,60 @@ __global__ __launch_bounds__(LB) void features_kernel(Lay L, const double* __res
   feat[nat * 3 + 2] = s > 0 ? (float)((rprime[t] / A[t]) / s) : 0.f;
 }
 
-// dp_nn = s * N(...) back in colour-split order
-__global__ __launch_bounds__(LB) void dpnn_kernel(Lay L, const float* __restrict__ y, const double* __restrict__ scal,
-                                                  double* __restrict__ dpnn) {
+// network direction d back in colour-split order
+__global__ __launch_bounds__(LB) void dir_kernel(Lay L, const float* __restrict__ y, double* __restrict__ d) {
   int t = blockIdx.x * LB + threadIdx.x;
   if (t >= L.n) return;
   int i, j, k;
   lay_coords(L, t, i, j, k);
-  long nat = i + (long)L.nx * (j + (long)L.ny * k);
-  dpnn[t] = scal[S_RMS] * (double)y[nat];
+  d[t] = (double)y[i + (long)L.nx * (j + (long)L.ny * k)];
 }
 
-// block partials of ||r' - A_p dp_nn||^2
-__global__ __launch_bounds__(LB) void judge_partial_kernel(Lay L, const double* __restrict__ A,
-                                                           const double* __restrict__ rprime,
-                                                           const double* __restrict__ dpnn, double* __restrict__ part,
-                                                           int nblk) {
+// q = A_p d, with block partials of <q, r'> and <q, q>
+__global__ __launch_bounds__(LB) void apply_dir_kernel(Lay L, const double* __restrict__ A,
+                                                       const double* __restrict__ rprime,
+                                                       const double* __restrict__ d, double* __restrict__ q,
+                                                       double* __restrict__ part, int nblk) {
   __shared__ double sh[LB / 64];
-  double a = 0;
+  double a = 0, b = 0;
   for (int t = blockIdx.x * LB + threadIdx.x; t < L.n; t += nblk * LB) {
     CsCell cc = cs_decode(L, t);
-    double y = A[t] * dpnn[t];
+    double y = A[t] * d[t];
 #pragma unroll
-    for (int d = 1; d < 7; ++d) {
-      int nb = cs_nb(L, cc, d);
-      if (nb >= 0) y += A[(size_t)d * L.n + t] * dpnn[nb];
+    for (int dd = 1; dd < 7; ++dd) {
+      int nb = cs_nb(L, cc, dd);
+      if (nb >= 0) y += A[(size_t)dd * L.n + t] * d[nb];
     }
-    double r = rprime[t] - y;
+    q[t] = y;
+    a += y * rprime[t];
+    b += y * y;
+  }
+  double s = block_sum(a, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  s = block_sum(b, sh);
+  if (threadIdx.x == 0) part[(size_t)nblk + blockIdx.x] = s;
+}
+
+// alpha = <q, r'> / <q, q> (0 if q vanishes or is not finite)
+__global__ void alpha_kernel(const double* __restrict__ part, int nblk, double* __restrict__ scal) {
+  if (threadIdx.x != 0) return;
+  double a = 0, b = 0;
+  for (int k = 0; k < nblk; ++k) a += part[k];
+  for (int k = 0; k < nblk; ++k) b += part[(size_t)nblk + k];
+  double al = (b > 0 && isfinite(a) && isfinite(b)) ? a / b : 0.0;
+  scal[S_ALPHA] = isfinite(al) ? al : 0.0;
+}
+
+// block partials of ||r' - alpha q||^2 = ||r' - A_p dp_nn||^2
+__global__ __launch_bounds__(LB) void judge_partial_kernel(int n, const double* __restrict__ rprime,
+                                                           const double* __restrict__ q,
+                                                           const double* __restrict__ scal, double* __restrict__ part,
+                                                           int nblk) {
+  __shared__ double sh[LB / 64];
+  const double al = scal[S_ALPHA];
+  double a = 0;
+  for (int t = blockIdx.x * LB + threadIdx.x; t < n; t += nblk * LB) {
+    double r = rprime[t] - al * q[t];
     a += r * r;
   }
   double s = block_sum(a, sh);
@@ -170,12 +198,13 @@ __global__ void judge_final_kernel(const double* __restrict__ part, int nblk, do
   if (accept) count[0] += 1; else count[1] += 1;
 }
 
+// dp += alpha d when the judge accepted
 template <typename T>
 __global__ __launch_bounds__(LB) void correct_kernel(int n, const double* __restrict__ scal,
-                                                     const double* __restrict__ dpnn, T* __restrict__ dp) {
+                                                     const double* __restrict__ d, T* __restrict__ dp) {
   int t = blockIdx.x * LB + threadIdx.x;
   if (t >= n || !(scal[S_ACC] > 0.0)) return;
-  dp[t] = (T)((double)dp[t] + dpnn[t]);
+  dp[t] = (T)((double)dp[t] + scal[S_ALPHA] * d[t]);
 }
 
 __global__ void lnk_kernel(Lay L, const double* __restrict__ perm, double* __restrict__ lnk) {
@@ -225,8 +254,11 @@ static int learned_stage_t(cpr_ctx* ctx, const T* rp, T* dp) {
   features_launch(ctx);
   int rc = nn_infer(ctx->nn, ctx->feat, nullptr);
   if (rc) return set_err(ctx, rc, "network inference failed");
-  dpnn_kernel<<<div_up(L.n, LB), LB, 0, s>>>(L, nn_output(ctx->nn), ctx->nnscal, ctx->dpnn);
-  judge_partial_kernel<<<ctx->nblk, LB, 0, s>>>(L, ctx->levels[0].A, ctx->rprime, ctx->dpnn, ctx->part, ctx->nblk);
+  dir_kernel<<<div_up(L.n, LB), LB, 0, s>>>(L, nn_output(ctx->nn), ctx->dpnn);
+  apply_dir_kernel<<<ctx->nblk, LB, 0, s>>>(L, ctx->levels[0].A, ctx->rprime, ctx->dpnn, ctx->qbuf, ctx->part,
+                                            ctx->nblk);
+  alpha_kernel<<<1, 64, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal);
+  judge_partial_kernel<<<ctx->nblk, LB, 0, s>>>(L.n, ctx->rprime, ctx->qbuf, ctx->nnscal, ctx->part, ctx->nblk);
   judge_final_kernel<<<1, 64, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal, ctx->nncount);
   correct_kernel<T><<<div_up(L.n, LB), LB, 0, s>>>(L.n, ctx->nnscal, ctx->dpnn, dp);
   return CPR_OK;

@@ -302,60 +302,74 @@ __global__ void head_bwd_kernel(long nvox, const float* __restrict__ d0, const f
   }
 }
 
-// Loss partials per sample: sum (y - t)^2 and sum t^2 over a block's voxels.
+// Loss partials per sample over a block's voxels: y.t, y.y, t.t.
 __global__ void loss_partial_kernel(int V, int nblk_per, const float* __restrict__ y, const float* __restrict__ t,
                                     float* __restrict__ part) {
-  __shared__ float s1[256], s2[256];
+  __shared__ float s1[256], s2[256], s3[256];
   int b = blockIdx.x / nblk_per, k = blockIdx.x % nblk_per;
   long per = (V + nblk_per - 1) / nblk_per;
   long beg = (long)k * per, end = beg + per < V ? beg + per : V;
-  float a = 0.f, c = 0.f;
+  float a = 0.f, c = 0.f, e = 0.f;
   for (long v = beg + threadIdx.x; v < end; v += 256) {
-    float d = y[(long)b * V + v] - t[(long)b * V + v];
-    a += d * d;
-    c += t[(long)b * V + v] * t[(long)b * V + v];
+    float yv = y[(long)b * V + v], tv = t[(long)b * V + v];
+    a += yv * tv;
+    c += yv * yv;
+    e += tv * tv;
   }
   s1[threadIdx.x] = a;
   s2[threadIdx.x] = c;
+  s3[threadIdx.x] = e;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o) {
       s1[threadIdx.x] += s1[threadIdx.x + o];
       s2[threadIdx.x] += s2[threadIdx.x + o];
+      s3[threadIdx.x] += s3[threadIdx.x + o];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = s1[0];
-    part[2 * blockIdx.x + 1] = s2[0];
+    part[3 * blockIdx.x] = s1[0];
+    part[3 * blockIdx.x + 1] = s2[0];
+    part[3 * blockIdx.x + 2] = s3[0];
   }
 }
 
-// Per-sample totals (fixed order), loss = mean(num/den); dy = 2 (y - t) / (B den_b).
+// Per-sample totals (fixed order); the direction loss
+// L = mean_b (1 - (y.t)^2 / (|y|^2 |t|^2)) and
+// dy = -(2/B) [c t - c (y.t)/|y|^2 y], c = (y.t) / (|y|^2 |t|^2).
 __global__ void loss_grad_kernel(int B, int V, int nblk_per, const float* __restrict__ part,
                                  const float* __restrict__ y, const float* __restrict__ t, float* __restrict__ dy,
                                  float* __restrict__ loss) {
-  __shared__ float den[64];
-  __shared__ float num[64];
+  __shared__ float yt[64], yy[64], tt[64];
   if (threadIdx.x < B) {
-    float a = 0.f, c = 0.f;
+    float a = 0.f, c = 0.f, e = 0.f;
     for (int k = 0; k < nblk_per; ++k) {
-      a += part[2 * (threadIdx.x * nblk_per + k)];
-      c += part[2 * (threadIdx.x * nblk_per + k) + 1];
+      a += part[3 * (threadIdx.x * nblk_per + k)];
+      c += part[3 * (threadIdx.x * nblk_per + k) + 1];
+      e += part[3 * (threadIdx.x * nblk_per + k) + 2];
     }
-    num[threadIdx.x] = a;
-    den[threadIdx.x] = c;
+    yt[threadIdx.x] = a;
+    yy[threadIdx.x] = c;
+    tt[threadIdx.x] = e;
   }
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     float L = 0.f;
-    for (int b = 0; b < B; ++b) L += num[b] / den[b];
+    for (int b = 0; b < B; ++b) L += 1.f - yt[b] * yt[b] / (yy[b] * tt[b]);
     *loss = L / B;
   }
   for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < (long)B * V; q += (long)gridDim.x * blockDim.x) {
     int b = (int)(q / V);
-    dy[q] = 2.f * (y[q] - t[q]) / (B * den[b]);
+    float c = yt[b] / (yy[b] * tt[b]);
+    dy[q] = -(2.f / B) * (c * t[q] - (c * yt[b] / yy[b]) * y[q]);
   }
+}
+
+// Training target: t = e / s in FP32.
+__global__ void target_kernel(long n, const double* __restrict__ e, double inv, float* __restrict__ t) {
+  long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) t[q] = (float)(e[q] * inv);
 }
 
 // Adam with bias correction; c1 = 1/(1 - b1^k), c2 = 1/(1 - b2^k).
@@ -586,7 +600,7 @@ static int nn_alloc(cpr_nn* nn) {
   }
   nn->part_cap = pc;
   NN_TRY(A(&nn->part, (long)pc));
-  NN_TRY(A(&nn->lpart, 2L * B * 64));
+  NN_TRY(A(&nn->lpart, 3L * B * 64));
   NN_TRY(A(&nn->loss, 1));
   NN_TRY(hipMemsetAsync(nn->x16, 0, n[0] * 16 * sizeof(float), nn->stream));
   return CPR_OK;
@@ -709,6 +723,32 @@ int cpr_nn_backward(cpr_nn_t* nn, const float* dy, float* grad) {
   if (rc) return rc;
   NN_TRY(hipMemcpyAsync(grad, nn->grad, nn->P * sizeof(float), hipMemcpyDeviceToDevice, nn->stream));
   return CPR_OK;
+}
+
+int cpr_nn_eval_loss(cpr_nn_t* nn, const float* x, const float* t, int batch, float* loss_out) {
+  if (!nn || !x || !t || !loss_out) return CPR_EINVAL;
+  if (batch < 1 || batch > nn->max_batch) return nn_err(nn, CPR_EINVAL, "batch out of range");
+  if (!nn->frags_valid) return nn_err(nn, CPR_EINVAL, "parameters not set");
+  hipStream_t s = nn->stream;
+  const int V = nn->lv[0].V;
+  long n0 = (long)batch * V;
+  pad_input_kernel<<<div_up(n0 * 16, 256), 256, 0, s>>>(n0, x, nn->x16);
+  int rc = nn_forward_impl(nn, batch);
+  if (rc) return rc;
+  const int per = 64;
+  loss_partial_kernel<<<batch * per, 256, 0, s>>>(V, per, nn->y, t, nn->lpart);
+  loss_grad_kernel<<<div_up(n0, 256) < 1024 ? div_up(n0, 256) : 1024, 256, 0, s>>>(batch, V, per, nn->lpart, nn->y,
+                                                                                  t, nn->dy, nn->loss);
+  NN_TRY(hipMemcpyAsync(loss_out, nn->loss, sizeof(float), hipMemcpyDeviceToHost, s));
+  NN_TRY(hipStreamSynchronize(s));
+  return CPR_OK;
+}
+
+int cpr_nn_make_target(const double* e, long long n, double scale, float* t, void* stream) {
+  if (!e || !t || n < 0 || !(scale > 0)) return CPR_EINVAL;
+  if (n == 0) return CPR_OK;
+  target_kernel<<<div_up(n, 256), 256, 0, (hipStream_t)stream>>>(n, e, 1.0 / scale, t);
+  return hipGetLastError() == hipSuccess ? CPR_OK : CPR_EHIP;
 }
 
 int cpr_nn_train_step(cpr_nn_t* nn, const float* x, const float* t, int batch, float lr, float* loss_out) {

@@ -183,10 +183,12 @@ def oil_water_training(nx=64, ny=64, nz=32, seed=5000):
     s = gaussian_field(rng, shape, (1.0, float(lh), float(lh)))
     sw = 0.2 + 0.6 * (s - s.min()) / max(s.max() - s.min(), 1e-30)
     npair = int(rng.integers(1, 5))
+    cols = rng.choice(nx * ny, size=2 * npair, replace=False)   # distinct columns
     wells = []
-    for _ in range(npair):
-        wells.append(well(rng.integers(nx), rng.integers(ny), nz, "inj", 300.0))
-        wells.append(well(rng.integers(nx), rng.integers(ny), nz, "prod", 150.0))
+    for q in range(npair):
+        a, b = cols[2 * q], cols[2 * q + 1]
+        wells.append(well(a % nx, a // nx, nz, "inj", 300.0))
+        wells.append(well(b % nx, b // nx, nz, "prod", 150.0))
     c = _case(grid_of(nx, ny, nz), OIL_WATER, perm, poro, wells, 1.0,
               f"oil-water training {nx}x{ny}x{nz}")
     c["x"][1] = sw

@@ -1,0 +1,189 @@
+"""Training data, training and evaluation of the pressure-correction network.
+
+All arithmetic runs in libcprmi.so; this module only orchestrates calls and
+keeps tensors in GPU memory.
+
+Data: for each synthetic oil-water system the solver assembles its Newton
+system, sets up CPR and solves it with FGMRES; for the first Krylov vectors
+v_j it runs the pressure stage alone to get the residual the multigrid
+cycle leaves, r' = r~_p - A_p dp_mg, and the network input for it.  The
+target is the exact remaining correction A_p^-1 r', obtained with the same
+library by solving the pressure system to 1e-10 (A_p embedded as the
+pressure block of a two-unknown system whose second unknown is decoupled
+by an identity block), divided by the feature scale s so that
+dp_nn = s N(input) is the correction the network must produce.
+"""
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import cprmi, synth
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "pressure_unet.npy")
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+class PressureTarget:
+    """Solves A_p e = r' for the exact remaining pressure correction."""
+
+    def __init__(self, case):
+        self.case = case
+        self.s = cprmi.Solver(case["grid"], synth.OIL_WATER, case["perm"], case["poro"], [])
+        self.shape = self.s.shape
+
+    def load(self, Ap):
+        J2 = torch.zeros((7, 2, 2) + self.shape, dtype=torch.float64, device="cuda")
+        J2[:, 0, 0] = Ap
+        J2[0, 1, 1] = 1.0
+        self.s.import_jacobian(J2.contiguous())
+        self.s.setup(rtol=1e-10, max_iter=600)
+
+    def solve(self, rprime):
+        rhs = torch.zeros((2,) + self.shape, dtype=torch.float64, device="cuda")
+        rhs[0] = rprime
+        dx, st = self.s.solve(rhs.contiguous())
+        return dx[0].clone(), st
+
+
+def harvest(case, per_system):
+    """(features [k, nz, ny, nx, 3] float32, targets [k, nz, ny, nx] float32)."""
+    s = cprmi.Solver.from_case(case)
+    rhs = s.assemble(_dev(case["x_old"]), _dev(case["x"]), case["dt"])
+    s.setup()
+    _, st = s.solve(rhs)
+    k = min(per_system, st["iterations"], 30)
+    tgt = PressureTarget(case)
+    tgt.load(s.export_mg_level(0))
+    feats, targets = [], []
+    for j in range(k):
+        v = s.export_krylov(j)
+        rp, _ = s.pressure_stage(v)
+        f, scale = s.features(rp)
+        if not scale > 0:
+            continue
+        e, tst = tgt.solve(rp)
+        feats.append(f)
+        targets.append(cprmi.make_target(e, scale))
+    s.close()
+    tgt.s.close()
+    return torch.stack(feats), torch.stack(targets)
+
+
+def make_dataset(n_systems, per_system, shape=(64, 64, 32), seed0=5000, log=print):
+    nx, ny, nz = shape
+    X, T = [], []
+    t0 = time.time()
+    for i in range(n_systems):
+        case = synth.oil_water_training(nx, ny, nz, seed=seed0 + i)
+        f, t = harvest(case, per_system)
+        X.append(f)
+        T.append(t)
+        if log and (i + 1) % max(1, n_systems // 10) == 0:
+            log(f"[data] {i + 1}/{n_systems} systems, {sum(x.shape[0] for x in X)} pairs, "
+                f"{time.time() - t0:.1f} s")
+    return torch.cat(X).contiguous(), torch.cat(T).contiguous()
+
+
+def train(X, T, epochs, batch=4, lr=1e-3, seed=0, val_frac=0.1, init_seed=1, log=print):
+    """Adam on the normalised MSE; returns (parameters, history)."""
+    n = X.shape[0]
+    nz, ny, nx = X.shape[1:4]
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(n)
+    nval = max(1, int(round(val_frac * n)))
+    val, tr = order[:nval], order[nval:]
+    net = cprmi.Network(nx, ny, nz, max_batch=batch)
+    net.set_params(synth.nn_initial_weights(init_seed))
+    hist = []
+    t0 = time.time()
+    for ep in range(epochs):
+        perm = rng.permutation(tr)
+        losses = []
+        for q in range(0, len(perm) - batch + 1, batch):
+            idx = torch.as_tensor(perm[q:q + batch], device="cuda")
+            losses.append(net.train_step(X[idx].contiguous(), T[idx].contiguous(), lr))
+        vl = validation_loss(net, X, T, val, batch)
+        hist.append({"epoch": ep + 1, "train_loss": float(np.mean(losses)), "val_loss": vl,
+                     "seconds": time.time() - t0})
+        if log:
+            log(f"[train] epoch {ep + 1}: train {np.mean(losses):.4f}, validation {vl:.4f}, "
+                f"{time.time() - t0:.1f} s")
+    theta = net.get_params()
+    net.close()
+    return theta, hist
+
+
+def validation_loss(net, X, T, idx, batch):
+    """Mean normalised MSE over the validation samples (one sample per call,
+    so every sample weighs the same)."""
+    tot = []
+    for q in idx:
+        sel = torch.as_tensor([q], device="cuda")
+        tot.append(net.eval_loss(X[sel].contiguous(), T[sel].contiguous()))
+    return float(np.mean(tot))
+
+
+def evaluate(theta, seeds, shape=(128, 128, 64), control_seed=99, log=print):
+    """FGMRES iterations and solve time to 1e-6 on evaluation systems: plain
+    CPR, CPR with the trained network, CPR with a random-init network."""
+    nx, ny, nz = shape
+    rows = []
+    for sd in seeds:
+        case = synth.oil_water_eval(nx, ny, nz, seed=sd)
+        s = cprmi.Solver.from_case(case)
+        rhs = s.assemble(_dev(case["x_old"]), _dev(case["x"]), case["dt"])
+        row = {"seed": sd}
+        for name, th in (("plain", None), ("learned", theta),
+                         ("random", synth.nn_initial_weights(control_seed))):
+            if th is not None:
+                s.attach_network(th)
+            s.setup(learned=0 if th is None else 1)
+            s.solve(rhs)                       # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = s.solve(rhs)
+            torch.cuda.synchronize()
+            row[name] = {"iterations": st["iterations"], "seconds": time.perf_counter() - t0,
+                         "true_rel": st["true_rel"], "accepted": st["nn_accepted"],
+                         "rejected": st["nn_rejected"]}
+        s.close()
+        rows.append(row)
+        if log:
+            log(f"[eval] seed {sd}: " + ", ".join(
+                f"{k} {row[k]['iterations']} its {1e3 * row[k]['seconds']:.2f} ms "
+                f"(acc {row[k]['accepted']})" for k in ("plain", "learned", "random")))
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser(description="train and evaluate the pressure-correction network")
+    ap.add_argument("--systems", type=int, default=100)
+    ap.add_argument("--per-system", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-seeds", type=int, default=8)
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--report", default=None)
+    args = ap.parse_args()
+    X, T = make_dataset(args.systems, args.per_system)
+    print(f"[data] {X.shape[0]} pairs", flush=True)
+    theta, hist = train(X, T, args.epochs, lr=args.lr,
+                        log=lambda m: print(m, flush=True))
+    del X, T
+    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    np.save(args.out, theta)
+    rows = evaluate(theta, [6000 + i for i in range(args.eval_seeds)], log=lambda m: print(m, flush=True))
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump({"history": hist, "eval": rows}, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,16 @@ def test_learned_stage_pieces():
     assert np.linalg.norm(rp1) <= 1e-10 * np.linalg.norm(rt0)
 
 
+def test_direction_loss_values():
+    rng = np.random.default_rng(12)
+    t = rng.standard_normal((2, 2, 2, 4))
+    assert nn.loss(-3.0 * t, t)[0] < 1e-15          # any multiple is exact
+    u = rng.standard_normal(t.shape)
+    y = u - (np.sum(u * t, axis=(1, 2, 3), keepdims=True) / np.sum(t * t, axis=(1, 2, 3), keepdims=True)) * t
+    assert abs(nn.loss(y, t)[0] - 1.0) < 1e-12       # orthogonal: nothing explained
+    assert np.isclose(nn.loss(5.0 * u, t)[0], nn.loss(u, t)[0])
+
+
 def test_adam_first_step_moves_by_lr():
     theta = np.zeros(4)
     g = np.array([1.0, -2.0, 0.5, 0.0])

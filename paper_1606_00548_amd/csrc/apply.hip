@@ -60,9 +60,9 @@ template <int B, typename T>
 __device__ inline T at_blk(const T* __restrict__ J, const T* __restrict__ R0, size_t N, int d, int r,
                            int c, int t) {
   if constexpr (sizeof(T) == 8) {
-    return r == 0 ? R0[((size_t)d * B + c) * N + t] : J[((size_t)(d * B + r) * B + c) * N + t];
+    return r == 0 ? ldnt(R0 + ((size_t)d * B + c) * N + t) : ldnt(J + ((size_t)(d * B + r) * B + c) * N + t);
   } else {
-    return J[((size_t)(d * B + r) * B + c) * N + t];
+    return ldnt(J + ((size_t)(d * B + r) * B + c) * N + t);
   }
 }
 
@@ -75,15 +75,22 @@ __device__ inline void red_zero_cell(const T* __restrict__ A, const T* __restric
   x[q] = r[q] / A[q];
 }
 
-// sum_{d>0} a_d x_nb for a colour-split cell
+// sum_{d>0} a_d x_nb for a colour-split cell (branch-free: the stencil
+// coefficients are streamed non-temporally, missing neighbours masked)
 template <typename T>
 __device__ inline T offdiag_sum(const Lay& L, const T* __restrict__ A, const T* __restrict__ x, int t) {
   CsCell cc = cs_decode(L, t);
+  int nbr[7];
+  bool ok[7];
+  cs_nbrs(L, t, cc, nbr, ok);
+  T a[7];
+#pragma unroll
+  for (int d = 1; d < 7; ++d) a[d] = ldnt(A + (size_t)d * L.n + t);
   T s = 0;
 #pragma unroll
   for (int d = 1; d < 7; ++d) {
-    int nb = cs_nb(L, cc, d);
-    if (nb >= 0) s += A[(size_t)d * L.n + t] * x[nb];
+    T v = x[nbr[d]];
+    s += a[d] * (ok[d] ? v : (T)0);
   }
   return s;
 }
@@ -130,15 +137,22 @@ __device__ inline void black_post_cell(const Lay& F, const Lay& C, T alpha, cons
                                        T* __restrict__ x, int q) {
   int t = F.nh + q;
   CsCell cc = cs_decode(F, t);
+  int nbr[7];
+  bool ok[7];
+  cs_nbrs(F, t, cc, nbr, ok);
+  T a[7];
+#pragma unroll
+  for (int d = 1; d < 7; ++d) a[d] = ldnt(A + (size_t)d * F.n + t);
   T s = 0;
 #pragma unroll
   for (int d = 1; d < 7; ++d) {
-    int nb = cs_nb(F, cc, d);
-    if (nb < 0) continue;
     int di, dj, dk;
     dir_offset(d, di, dj, dk);
-    T e = ec[lay_index(C, (cc.i + di) >> 1, (cc.j + dj) >> 1, (cc.k + dk) >> 1)];
-    s += A[(size_t)d * F.n + t] * (x[nb] + alpha * e);
+    // a missing neighbour looks up the cell's own aggregate (in bounds) and is masked
+    int gi = ok[d] ? cc.i + di : cc.i, gj = ok[d] ? cc.j + dj : cc.j, gk = ok[d] ? cc.k + dk : cc.k;
+    T e = ec[lay_index(C, gi >> 1, gj >> 1, gk >> 1)];
+    T v = x[nbr[d]] + alpha * e;
+    s += a[d] * (ok[d] ? v : (T)0);
   }
   x[t] = (r[t] - s) / A[t];
 }
@@ -315,16 +329,23 @@ __device__ inline void stage2_resid(const Lay& L, int t, const CsCell& cc, const
                                     const double* __restrict__ v, const T* __restrict__ rp,
                                     const T* __restrict__ dp, T (&r2)[B]) {
   const size_t N = L.n;
+  int nbr[7];
+  bool ok[7];
+  cs_nbrs(L, t, cc, nbr, ok);
+  T a[7][B];
+#pragma unroll
+  for (int d = 0; d < 7; ++d)
+#pragma unroll
+    for (int r = 0; r < B; ++r) a[d][r] = at_blk<B, T>(J, R0, N, d, r, 0, t);
   r2[0] = rp[t];
 #pragma unroll
   for (int r = 1; r < B; ++r) r2[r] = (T)v[r * N + t];
 #pragma unroll
   for (int d = 0; d < 7; ++d) {
-    int nb = d == 0 ? t : cs_nb(L, cc, d);
-    if (nb < 0) continue;
-    T p = dp[nb];
+    T p = dp[nbr[d]];
+    p = ok[d] ? p : (T)0;
 #pragma unroll
-    for (int r = 0; r < B; ++r) r2[r] -= at_blk<B, T>(J, R0, N, d, r, 0, t) * p;
+    for (int r = 0; r < B; ++r) r2[r] -= a[d][r] * p;
   }
 }
 
@@ -332,21 +353,32 @@ template <int B, typename T>
 __device__ inline void offdiag_apply(const Lay& L, int t, const CsCell& cc, const T* J, const T* R0,
                                      const T* __restrict__ Y, T (&s)[B]) {
   const size_t N = L.n;
+  int nbr[7];
+  bool ok[7];
+  cs_nbrs(L, t, cc, nbr, ok);
+  T a[7][B][B];
+#pragma unroll
+  for (int d = 1; d < 7; ++d)
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < B; ++c) a[d][r][c] = at_blk<B, T>(J, R0, N, d, r, c, t);
 #pragma unroll
   for (int r = 0; r < B; ++r) s[r] = 0;
 #pragma unroll
   for (int d = 1; d < 7; ++d) {
-    int nb = cs_nb(L, cc, d);
-    if (nb < 0) continue;
     T y[B];
 #pragma unroll
-    for (int c = 0; c < B; ++c) y[c] = Y[c * N + nb];
+    for (int c = 0; c < B; ++c) {
+      T v = Y[c * N + nbr[d]];
+      y[c] = ok[d] ? v : (T)0;
+    }
 #pragma unroll
     for (int r = 0; r < B; ++r) {
-      T a = 0;
+      T acc = 0;
 #pragma unroll
-      for (int c = 0; c < B; ++c) a += at_blk<B, T>(J, R0, N, d, r, c, t) * y[c];
-      s[r] += a;
+      for (int c = 0; c < B; ++c) acc += a[d][r][c] * y[c];
+      s[r] += acc;
     }
   }
 }
@@ -395,7 +427,19 @@ __global__ __launch_bounds__(256) void stage2_black_kernel(Lay L, const T* __res
   int t = L.nh + q;
   CsCell cc = cs_decode(L, t);
   const size_t N = L.n;
-  // r2 = r~ - A~(:,p) dp and s = sum_red A~_bk y_k, each off-diagonal block read once
+  // r2 = r~ - A~(:,p) dp and s = sum_red A~_bk y_k, each off-diagonal block
+  // read once (branch-free, non-temporal; missing neighbours masked)
+  int nbr[7];
+  bool ok[7];
+  cs_nbrs(L, t, cc, nbr, ok);
+  T a[7][B][B];
+#pragma unroll
+  for (int d = 0; d < 7; ++d)
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < B; ++c)
+        a[d][r][c] = (d == 0 && c > 0) ? (T)0 : at_blk<B, T>(J, R0, N, d, r, c, t);
   T r2[B], s[B], y[B];
   r2[0] = rp[t];
 #pragma unroll
@@ -403,26 +447,27 @@ __global__ __launch_bounds__(256) void stage2_black_kernel(Lay L, const T* __res
   {
     T p = dp[t];
 #pragma unroll
-    for (int r = 0; r < B; ++r) r2[r] -= at_blk<B, T>(J, R0, N, 0, r, 0, t) * p;
+    for (int r = 0; r < B; ++r) r2[r] -= a[0][r][0] * p;
   }
 #pragma unroll
   for (int r = 0; r < B; ++r) s[r] = 0;
 #pragma unroll
   for (int d = 1; d < 7; ++d) {
-    int nb = cs_nb(L, cc, d);
-    if (nb < 0) continue;
-    T p = dp[nb];
+    T p = dp[nbr[d]];
+    p = ok[d] ? p : (T)0;
     T yk[B];
 #pragma unroll
-    for (int c = 0; c < B; ++c) yk[c] = Y[c * N + nb];
+    for (int c = 0; c < B; ++c) {
+      T vv = Y[c * N + nbr[d]];
+      yk[c] = ok[d] ? vv : (T)0;
+    }
 #pragma unroll
     for (int r = 0; r < B; ++r) {
-      T a0 = at_blk<B, T>(J, R0, N, d, r, 0, t);
-      r2[r] -= a0 * p;
-      T a = a0 * yk[0];
+      r2[r] -= a[d][r][0] * p;
+      T acc = a[d][r][0] * yk[0];
 #pragma unroll
-      for (int c = 1; c < B; ++c) a += at_blk<B, T>(J, R0, N, d, r, c, t) * yk[c];
-      s[r] += a;
+      for (int c = 1; c < B; ++c) acc += a[d][r][c] * yk[c];
+      s[r] += acc;
     }
   }
 #pragma unroll

@@ -100,6 +100,27 @@ __host__ __device__ inline int cs_nb(const Lay& L, const CsCell& q, int d) {
   }
 }
 
+// The six neighbours of a colour-split cell for branch-free stencil code:
+// nbr[d] is the neighbour's index, or the cell itself (ok[d] = false) where
+// the neighbour lies outside the grid, so every load stays in bounds and
+// the caller masks the value.
+__host__ __device__ inline void cs_nbrs(const Lay& L, int t, const CsCell& cc, int (&nbr)[7], bool (&ok)[7]) {
+  nbr[0] = t;
+  ok[0] = true;
+#pragma unroll
+  for (int d = 1; d < 7; ++d) {
+    int q = cs_nb(L, cc, d);
+    ok[d] = q >= 0;
+    nbr[d] = ok[d] ? q : t;
+  }
+}
+
+// Non-temporal load of a streamed operand (read once per kernel).
+template <typename T>
+__device__ inline T ldnt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 inline Lay make_lay(int nx, int ny, int nz, bool want_cs) {
   Lay L;
   L.nx = nx; L.ny = ny; L.nz = nz;

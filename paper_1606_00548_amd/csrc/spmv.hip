@@ -9,6 +9,10 @@
 
 namespace {
 
+// Branch-free: all 7 b^2 matrix loads are issued up front (blocks towards
+// missing neighbours are stored as zeros), missing neighbours read the cell
+// itself and are masked to zero.  The matrix is streamed once per call, so
+// its loads are non-temporal and leave the caches to x.
 template <int B>
 __global__ __launch_bounds__(256) void spmv_kernel(Lay L, const double* __restrict__ A,
                                                    const double* __restrict__ x,
@@ -17,21 +21,39 @@ __global__ __launch_bounds__(256) void spmv_kernel(Lay L, const double* __restri
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= L.n) return;
   const size_t n = L.n;
-  int i, j, k;
-  lay_coords(L, t, i, j, k);
-  double acc[B];
-  for (int r = 0; r < B; ++r) acc[r] = 0.0;
+  CsCell cc = cs_decode(L, t);
+  int nbr[7];
+  bool ok[7];
+  nbr[0] = t;
+  ok[0] = true;
 #pragma unroll
-  for (int d = 0; d < 7; ++d) {
-    int nb = d == 0 ? t : lay_nbr(L, i, j, k, d);
-    if (nb < 0) continue;
-    double xv[B];
+  for (int d = 1; d < 7; ++d) {
+    int q = cs_nb(L, cc, d);
+    ok[d] = q >= 0;
+    nbr[d] = ok[d] ? q : t;
+  }
+  double a[7][B][B];
 #pragma unroll
-    for (int c = 0; c < B; ++c) xv[c] = x[c * n + nb];
+  for (int d = 0; d < 7; ++d)
 #pragma unroll
     for (int r = 0; r < B; ++r)
 #pragma unroll
-      for (int c = 0; c < B; ++c) acc[r] += A[((size_t)(d * B + r) * B + c) * n + t] * xv[c];
+      for (int c = 0; c < B; ++c) a[d][r][c] = __builtin_nontemporal_load(A + ((size_t)(d * B + r) * B + c) * n + t);
+  double acc[B];
+#pragma unroll
+  for (int r = 0; r < B; ++r) acc[r] = 0.0;
+#pragma unroll
+  for (int d = 0; d < 7; ++d) {
+    double xv[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      double v = x[c * n + nbr[d]];
+      xv[c] = ok[d] ? v : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < B; ++c) acc[r] += a[d][r][c] * xv[c];
   }
 #pragma unroll
   for (int r = 0; r < B; ++r) y[r * n + t] = rhs ? rhs[r * n + t] - acc[r] : acc[r];

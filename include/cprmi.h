@@ -237,6 +237,13 @@ int cpr_nn_get_params(cpr_nn_t* nn, float* theta);
 /* y = N(x) for x (device [batch][n][3]) -> y (device [batch][n]). */
 int cpr_nn_forward(cpr_nn_t* nn, const float* x, int batch, float* y);
 
+/* Inference form of cpr_nn_forward for one sample (batch 1): the same
+ * network and kernels, keeping only what inference needs, with the 1x1x1
+ * head fused into the last convolution on grids of at least 65,536 cells
+ * (so results may differ from cpr_nn_forward by FP32 summation order).
+ * Leaves nothing for cpr_nn_backward.  Stream-ordered, no synchronisation. */
+int cpr_nn_infer(cpr_nn_t* nn, const float* x, float* y);
+
 /* Gradient of sum(dy * y) for the last forward pass with respect to the
  * parameters: dy device [batch][n], grad device [num_params]. */
 int cpr_nn_backward(cpr_nn_t* nn, const float* dy, float* grad);

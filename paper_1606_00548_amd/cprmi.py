@@ -69,7 +69,7 @@ EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error",
            "cpr_nn_destroy", "cpr_nn_last_error", "cpr_nn_set_params", "cpr_nn_get_params",
            "cpr_nn_forward", "cpr_nn_backward", "cpr_nn_train_step", "cpr_nn_attach",
            "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov", "cpr_nn_eval_loss",
-           "cpr_nn_make_target"]
+           "cpr_nn_make_target", "cpr_nn_infer"]
 KCLASS = {"spmv": 0, "orth": 1, "smooth": 2, "ilu": 3, "assemble": 4}
 
 
@@ -114,6 +114,7 @@ def load():
     lib.cpr_nn_set_params.argtypes = [P, P]
     lib.cpr_nn_get_params.argtypes = [P, P]
     lib.cpr_nn_forward.argtypes = [P, P, ctypes.c_int, P]
+    lib.cpr_nn_infer.argtypes = [P, P, P]
     lib.cpr_nn_backward.argtypes = [P, P, P]
     lib.cpr_nn_train_step.argtypes = [P, P, P, ctypes.c_int, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]
     lib.cpr_nn_attach.argtypes = [P, P]
@@ -191,6 +192,13 @@ class Network:
         B = x.shape[0]
         y = torch.empty((B,) + self.shape, dtype=torch.float32, device="cuda")
         self._check(self.lib.cpr_nn_forward(self.h, _fptr(x), B, _fptr(y)))
+        return y
+
+    def infer(self, x):
+        """Inference form for one sample: x [1, nz, ny, nx, 3] -> y [1, nz, ny, nx]."""
+        assert x.shape[0] == 1
+        y = torch.empty((1,) + self.shape, dtype=torch.float32, device="cuda")
+        self._check(self.lib.cpr_nn_infer(self.h, _fptr(x), _fptr(y)))
         return y
 
     def backward(self, dy):

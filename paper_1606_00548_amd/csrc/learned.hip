@@ -39,6 +39,15 @@ __device__ inline double block_sum(double v, double* sh) {
   return s;
 }
 
+// Sum of nblk block partials by one block of LB threads, in a fixed order
+// (strided per-thread sums, then the wavefront and block tree); the total
+// is returned to thread 0.
+__device__ inline double partial_total(const double* __restrict__ part, int nblk, double* sh) {
+  double v = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += LB) v += part[k];
+  return block_sum(v, sh);
+}
+
 // per-block partials of ln kx, ln kx^2, ln lt, ln lt^2
 __global__ __launch_bounds__(LB) void stats_partial_kernel(int n, const double* __restrict__ lnk,
                                                            const double* __restrict__ lt, double* __restrict__ part,
@@ -56,11 +65,12 @@ __global__ __launch_bounds__(LB) void stats_partial_kernel(int n, const double* 
   }
 }
 
-__global__ void stats_final_kernel(int n, const double* __restrict__ part, int nblk, double* __restrict__ scal) {
+__global__ __launch_bounds__(LB) void stats_final_kernel(int n, const double* __restrict__ part, int nblk,
+                                                         double* __restrict__ scal) {
+  __shared__ double sh[LB / 64];
+  double s[4];
+  for (int q = 0; q < 4; ++q) s[q] = partial_total(part + (size_t)q * nblk, nblk, sh);
   if (threadIdx.x != 0) return;
-  double s[4] = {0, 0, 0, 0};
-  for (int q = 0; q < 4; ++q)
-    for (int b = 0; b < nblk; ++b) s[q] += part[(size_t)q * nblk + b];
   double mk = s[0] / n, ml = s[2] / n;
   double vk = s[1] / n - mk * mk, vl = s[3] / n - ml * ml;
   scal[S_MK] = mk;
@@ -102,11 +112,12 @@ __global__ __launch_bounds__(LB) void rprime_kernel(Lay L, const double* __restr
   if (threadIdx.x == 0) part[(size_t)nblk + blockIdx.x] = s;
 }
 
-__global__ void rprime_final_kernel(int n, const double* __restrict__ part, int nblk, double* __restrict__ scal) {
+__global__ __launch_bounds__(LB) void rprime_final_kernel(int n, const double* __restrict__ part, int nblk,
+                                                          double* __restrict__ scal) {
+  __shared__ double sh[LB / 64];
+  double a = partial_total(part, nblk, sh);
+  double b = partial_total(part + nblk, nblk, sh);
   if (threadIdx.x != 0) return;
-  double a = 0, b = 0;
-  for (int k = 0; k < nblk; ++k) a += part[k];
-  for (int k = 0; k < nblk; ++k) b += part[(size_t)nblk + k];
   scal[S_RMS] = sqrt(a / n);
   scal[S_R2] = b;
 }
@@ -162,11 +173,12 @@ __global__ __launch_bounds__(LB) void apply_dir_kernel(Lay L, const double* __re
 }
 
 // alpha = <q, r'> / <q, q> (0 if q vanishes or is not finite)
-__global__ void alpha_kernel(const double* __restrict__ part, int nblk, double* __restrict__ scal) {
+__global__ __launch_bounds__(LB) void alpha_kernel(const double* __restrict__ part, int nblk,
+                                                   double* __restrict__ scal) {
+  __shared__ double sh[LB / 64];
+  double a = partial_total(part, nblk, sh);
+  double b = partial_total(part + nblk, nblk, sh);
   if (threadIdx.x != 0) return;
-  double a = 0, b = 0;
-  for (int k = 0; k < nblk; ++k) a += part[k];
-  for (int k = 0; k < nblk; ++k) b += part[(size_t)nblk + k];
   double al = (b > 0 && isfinite(a) && isfinite(b)) ? a / b : 0.0;
   scal[S_ALPHA] = isfinite(al) ? al : 0.0;
 }
@@ -187,11 +199,11 @@ __global__ __launch_bounds__(LB) void judge_partial_kernel(int n, const double* 
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void judge_final_kernel(const double* __restrict__ part, int nblk, double* __restrict__ scal,
-                                   int* __restrict__ count) {
+__global__ __launch_bounds__(LB) void judge_final_kernel(const double* __restrict__ part, int nblk,
+                                                         double* __restrict__ scal, int* __restrict__ count) {
+  __shared__ double sh[LB / 64];
+  double a = partial_total(part, nblk, sh);
   if (threadIdx.x != 0) return;
-  double a = 0;
-  for (int k = 0; k < nblk; ++k) a += part[k];
   scal[S_RR2] = a;
   bool accept = isfinite(a) && a < scal[S_R2];
   scal[S_ACC] = accept ? 1.0 : 0.0;
@@ -226,7 +238,7 @@ int learned_setup(cpr_ctx* ctx, bool need_nn) {
   if (!ctx->assembled) return set_err(ctx, CPR_EINVAL, "the learned stage needs an assembled state");
   const double* lt = ctx->props + (size_t)props_lt_plane(ctx->fl.model) * ctx->lay.n;
   stats_partial_kernel<<<ctx->nblk, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->lnk, lt, ctx->part, ctx->nblk);
-  stats_final_kernel<<<1, 64, 0, ctx->stream>>>(ctx->lay.n, ctx->part, ctx->nblk, ctx->nnscal);
+  stats_final_kernel<<<1, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->part, ctx->nblk, ctx->nnscal);
   return launch_check(ctx, "learned_setup");
 }
 
@@ -236,7 +248,7 @@ template <typename T>
 static void rprime_launch(cpr_ctx* ctx, const T* rp, const T* dp) {
   const MGLevel& L0 = ctx->levels[0];
   rprime_kernel<T><<<ctx->nblk, LB, 0, ctx->stream>>>(ctx->lay, L0.A, rp, dp, ctx->rprime, ctx->part, ctx->nblk);
-  rprime_final_kernel<<<1, 64, 0, ctx->stream>>>(ctx->lay.n, ctx->part, ctx->nblk, ctx->nnscal);
+  rprime_final_kernel<<<1, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->part, ctx->nblk, ctx->nnscal);
 }
 
 static void features_launch(cpr_ctx* ctx) {
@@ -257,9 +269,9 @@ static int learned_stage_t(cpr_ctx* ctx, const T* rp, T* dp) {
   dir_kernel<<<div_up(L.n, LB), LB, 0, s>>>(L, nn_output(ctx->nn), ctx->dpnn);
   apply_dir_kernel<<<ctx->nblk, LB, 0, s>>>(L, ctx->levels[0].A, ctx->rprime, ctx->dpnn, ctx->qbuf, ctx->part,
                                             ctx->nblk);
-  alpha_kernel<<<1, 64, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal);
+  alpha_kernel<<<1, LB, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal);
   judge_partial_kernel<<<ctx->nblk, LB, 0, s>>>(L.n, ctx->rprime, ctx->qbuf, ctx->nnscal, ctx->part, ctx->nblk);
-  judge_final_kernel<<<1, 64, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal, ctx->nncount);
+  judge_final_kernel<<<1, LB, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal, ctx->nncount);
   correct_kernel<T><<<div_up(L.n, LB), LB, 0, s>>>(L.n, ctx->nnscal, ctx->dpnn, dp);
   return CPR_OK;
 }

@@ -26,6 +26,7 @@
 #include "internal.h"
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
@@ -50,60 +51,183 @@ struct Geo {
 // ------------------------------------------------------------ convolution
 // out[b][v][co] = sum_t sum_ci X~[b][v + off_t][ci] W[t][ci][co]; X~ is X on
 // the same grid, or X on the half-resolution grid read at (x/2, y/2, z/2)
-// when UP.  EPI 1: a = relu(acc + bias) stored in outA, and a + skip in outD
-// when skip is given; EPI 0: raw acc stored in outA (data gradient).
-template <int CI, int CO, bool UP, int EPI>
+// when UP.  EPI 1: a = relu(acc + bias), stored in outA when given, and
+// a + skip stored in outD when skip is given; with head (inference only) the
+// 1x1x1 head is applied to a + skip and only y is stored.  EPI 0: raw acc in
+// outA (data gradient).
+//
+// Implicit GEMM on v_mfma_f32_16x16x32_bf16: M = voxels, N = output
+// channels, K = (tap, input channel) in steps of 32.  A workgroup (4 waves)
+// owns a tile of 16 x 4 x TZ output voxels; the input it needs (tile plus a
+// one-voxel halo, or the half-resolution cells under it when UP) is staged
+// once in LDS as BF16, so each input value is read from memory about
+// 2-3 times instead of 27.  With KS = 1 each wave owns one z-plane of the
+// tile (4 M-blocks of 16 voxels along x) and every K-step; with KS = 4
+// (small grids, to keep enough waves in flight) the tile is one plane and
+// the waves split the K-steps round-robin, their partial tiles summed in LDS
+// in wave order, so results are deterministic either way.
+//
+// K ordering (must match frag_kernel): CI >= 32: step = t * (CI/32) + chunk,
+// 32 channels per step; CI = 16: step s covers taps 2s, 2s+1; CI = 4 (the
+// 3-channel input, padded): step s covers taps 8s..8s+7, 4 channels each.
+// Taps past 26 have zero weights.
+constexpr int TX = 16, TY = 4;
+
+__host__ __device__ constexpr int ksteps(int ci) { return ci >= 32 ? 27 * (ci / 32) : (ci == 16 ? 14 : 4); }
+
+__device__ inline unsigned pack_bf16x2(float a, float b) {
+  return (unsigned)(unsigned short)f2bf(a) | ((unsigned)(unsigned short)f2bf(b) << 16);
+}
+
+template <int CI, int CSRC, int CO, bool UP, int EPI, int KS>
 __global__ __launch_bounds__(256) void conv_kernel(Geo g, const float* __restrict__ X,
-                                                   const bf16x4* __restrict__ Wf,
+                                                   const bf16x8* __restrict__ Wf,
                                                    const float* __restrict__ bias,
                                                    const float* __restrict__ skip,
-                                                   float* __restrict__ outA, float* __restrict__ outD) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long total = (long)g.batch * g.V;
-  const long vbase = ((long)blockIdx.x * 4 + wave) * 16;
-  if (vbase >= total) return;
-  const long gv = vbase + (lane & 15);
-  const bool valid = gv < total;
-  const int b = valid ? (int)(gv / g.V) : 0;
-  const int v = valid ? (int)(gv - (long)b * g.V) : 0;
-  const int x = v % g.nx, yz = v / g.nx, y = yz % g.ny, z = yz / g.ny;
-  const int kq = lane >> 4;
-  const int cnx = g.nx >> 1, cny = g.ny >> 1, cV = (g.nx >> 1) * (g.ny >> 1) * (g.nz >> 1);
-  f32x4 acc[CO / 16];
-#pragma unroll
-  for (int n = 0; n < CO / 16; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int t = 0; t < 27; ++t) {
+                                                   float* __restrict__ outA, float* __restrict__ outD,
+                                                   const float* __restrict__ head, float* __restrict__ yout) {
+  static_assert(KS == 1 || KS == 4, "K split is 1 or 4");
+  static_assert(CI == 4 || CI == 16 || CI % 32 == 0, "channel layout");
+  constexpr int TZ = 4 / KS;
+  constexpr int HX = UP ? TX / 2 + 2 : TX + 2;
+  constexpr int HY = UP ? TY / 2 + 2 : TY + 2;
+  constexpr int HZ = UP ? TZ / 2 + 2 : TZ + 2;
+  constexpr int HV = HX * HY * HZ;
+  constexpr int NK = ksteps(CI);
+  constexpr int NT = CO / 16;
+  constexpr int HALO_BYTES = HV * CI * 2;
+  constexpr int RED_BYTES = KS > 1 ? KS * 64 * CO * 4 : 0;
+  constexpr int SMEM = HALO_BYTES > RED_BYTES ? HALO_BYTES : RED_BYTES;
+  __shared__ __align__(16) unsigned char smem[SMEM];
+
+  // tile of this workgroup; consecutive tiles go to the same XCD
+  const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
+  const int ntiles = ntx * nty * ntz * g.batch;
+  int tile = blockIdx.x;
+  if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = (tile / (ntx * nty)) % ntz, b = tile / (ntx * nty * ntz);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+
+  // stage the input window as BF16 (zero outside the grid)
+  const int sx = UP ? g.nx >> 1 : g.nx, sy = UP ? g.ny >> 1 : g.ny, sz = UP ? g.nz >> 1 : g.nz;
+  const int ox = UP ? (x0 - 1) >> 1 : x0 - 1, oy = UP ? (y0 - 1) >> 1 : y0 - 1, oz = UP ? (z0 - 1) >> 1 : z0 - 1;
+  const float* Xb = X + (long)b * sx * sy * sz * CSRC;
+  for (int q = threadIdx.x; q < HV * (CI / 4); q += 256) {
+    const int hv = q / (CI / 4), c4 = (q % (CI / 4)) * 4;
+    const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+    const int px = ox + hx, py = oy + hy, pz = oz + hz;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (px >= 0 && px < sx && py >= 0 && py < sy && pz >= 0 && pz < sz) {
+      const float* src = Xb + ((long)px + (long)sx * (py + (long)sy * pz)) * CSRC + c4;
+      if (CSRC == CI) {
+        v = *(const float4*)src;
+      } else {
+        v.x = src[0]; v.y = src[1]; v.z = src[2];
+      }
+    }
+    *(uint2*)(smem + ((size_t)hv * CI + c4) * 2) = make_uint2(pack_bf16x2(v.x, v.y), pack_bf16x2(v.z, v.w));
+  }
+  __syncthreads();
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i16 = lane & 15, kq = lane >> 4;
+  const int lz = KS == 1 ? wave : 0;
+  // halo index of the input under output voxel (i16, m, lz) for tap t
+  auto hpos = [&](int t, int m) -> int {
     const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-    const int xx = x + dx, yy = y + dy, zz = z + dz;
-    const bool inb = valid && xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny && zz >= 0 && zz < g.nz;
-    long src;
     if (UP)
-      src = (long)b * cV + (xx >> 1) + (long)cnx * ((yy >> 1) + (long)cny * (zz >> 1));
-    else
-      src = (long)b * g.V + xx + (long)g.nx * (yy + (long)g.ny * zz);
-    const float* row = X + src * CI;
+      return (((x0 + i16 + dx) >> 1) - ox) + HX * ((((y0 + m + dy) >> 1) - oy) + HY * (((z0 + lz + dz) >> 1) - oz));
+    return (i16 + dx + 1) + HX * ((m + dy + 1) + HY * (lz + dz + 1));
+  };
+  f32x4 acc[4][NT];
 #pragma unroll
-    for (int kc = 0; kc < CI / 16; ++kc) {
-      f32x4 av = inb ? *(const f32x4*)(row + kc * 16 + kq * 4) : f32x4{0.f, 0.f, 0.f, 0.f};
-      bf16x4 a;
-      a[0] = f2bf(av[0]); a[1] = f2bf(av[1]); a[2] = f2bf(av[2]); a[3] = f2bf(av[3]);
-      const bf16x4* wrow = Wf + ((size_t)(t * (CI / 16) + kc) * (CO / 16)) * 64 + lane;
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int n = 0; n < CO / 16; ++n)
-        acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, wrow[n * 64], acc[n], 0, 0, 0);
+    for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ks = (KS == 1 ? 0 : wave); ks < NK; ks += KS) {
+    bf16x8 bw[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) bw[n] = Wf[((size_t)ks * NT + n) * 64 + lane];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      uint4 raw;
+      if constexpr (CI >= 32) {
+        const int t = ks / (CI / 32), kc = ks % (CI / 32);
+        raw = *(const uint4*)(smem + ((size_t)hpos(t, m) * CI + kc * 32 + 8 * kq) * 2);
+      } else if constexpr (CI == 16) {
+        const int t = min(2 * ks + (kq >> 1), 26);
+        raw = *(const uint4*)(smem + ((size_t)hpos(t, m) * 16 + (kq & 1) * 8) * 2);
+      } else {
+        const int t0 = min(8 * ks + 2 * kq, 26), t1 = min(8 * ks + 2 * kq + 1, 26);
+        const uint2 lo = *(const uint2*)(smem + (size_t)hpos(t0, m) * 8);
+        const uint2 hi = *(const uint2*)(smem + (size_t)hpos(t1, m) * 8);
+        raw = make_uint4(lo.x, lo.y, hi.x, hi.y);
+      }
+      const bf16x8 a = __builtin_bit_cast(bf16x8, raw);
+#pragma unroll
+      for (int n = 0; n < NT; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[n], acc[m][n], 0, 0, 0);
     }
   }
+
+  const long V = g.V;
+  if constexpr (KS == 1) {
+    // C element (row 4*kq + e, column i16) of M-block m, N-block n is
+    // voxel (x0 + 4*kq + e, y0 + m, z0 + lz), channel n*16 + i16
 #pragma unroll
-  for (int n = 0; n < CO / 16; ++n) {
-    const int co = n * 16 + (lane & 15);
+    for (int m = 0; m < 4; ++m) {
+      const int y = y0 + m, z = z0 + lz;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const long o = vbase + 4 * kq + e;
-      if (o >= total) continue;
-      float val = acc[n][e];
+      for (int e = 0; e < 4; ++e) {
+        const int x = x0 + 4 * kq + e;
+        const bool ok = x < g.nx && y < g.ny && z < g.nz;
+        const long o = (long)b * V + x + (long)g.nx * (y + (long)g.ny * z);
+        if (head) {
+          // y = sum_c head[c] (relu(acc + bias) + skip)[c] + head[CO]; CO = 16
+          const float a = fmaxf(acc[m][0][e] + bias[i16], 0.f) + (ok ? skip[o * CO + i16] : 0.f);
+          float h = a * head[i16];
+          h += __shfl_xor(h, 8, 16);
+          h += __shfl_xor(h, 4, 16);
+          h += __shfl_xor(h, 2, 16);
+          h += __shfl_xor(h, 1, 16);
+          if (ok && i16 == 0) yout[o] = h + head[CO];
+          continue;
+        }
+        if (!ok) continue;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          const int co = n * 16 + i16;
+          const float val = acc[m][n][e];
+          if (EPI == 1) {
+            const float a = fmaxf(val + bias[co], 0.f);
+            if (outA) outA[o * CO + co] = a;
+            if (skip) outD[o * CO + co] = a + skip[o * CO + co];
+          } else {
+            outA[o * CO + co] = val;
+          }
+        }
+      }
+    }
+  } else {
+    // partial tiles to LDS, summed in wave order by all threads
+    __syncthreads();
+    float* red = (float*)smem;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[((size_t)wave * 64 + m * 16 + 4 * kq + e) * CO + n * 16 + i16] = acc[m][n][e];
+    __syncthreads();
+    for (int q = threadIdx.x; q < 64 * CO; q += 256) {
+      const int vox = q / CO, co = q % CO;
+      const int x = x0 + (vox & 15), y = y0 + (vox >> 4), z = z0;
+      if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
+      const long o = (long)b * V + x + (long)g.nx * (y + (long)g.ny * z);
+      float val = red[q];
+#pragma unroll
+      for (int w = 1; w < KS; ++w) val += red[(size_t)w * 64 * CO + q];
       if (EPI == 1) {
-        float a = fmaxf(val + bias[co], 0.f);
-        outA[o * CO + co] = a;
+        const float a = fmaxf(val + bias[co], 0.f);
+        if (outA) outA[o * CO + co] = a;
         if (skip) outD[o * CO + co] = a + skip[o * CO + co];
       } else {
         outA[o * CO + co] = val;
@@ -386,37 +510,47 @@ __global__ void adam_kernel(long n, float lr, float b1, float b2, float eps, flo
   w[q] -= lr * (mq * c1) / (sqrtf(vq * c2) + eps);
 }
 
-// BF16 B-fragments of conv weights W[27][ci_real][co] (FP32 master):
-// forward:  frag[t][kc][nc][lane][e] = W[t][kc*16 + 4*(lane/16) + e][nc*16 + lane%16]
-// backward: taps mirrored (26 - t) and channels transposed (K = co, N = ci).
-__global__ void frag_kernel(int ci_real, int ci_pad, int co, const float* __restrict__ W, bf16x4* __restrict__ fw,
-                            bf16x4* __restrict__ bw) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  int nf = 27 * (ci_pad / 16) * (co / 16) * 64;
-  if (q < nf) {
-    int lane = q % 64, r = q / 64;
-    int nc = r % (co / 16); r /= (co / 16);
-    int kc = r % (ci_pad / 16);
-    int t = r / (ci_pad / 16);
-    bf16x4 f;
-    for (int e = 0; e < 4; ++e) {
-      int ci = kc * 16 + 4 * (lane / 16) + e, c = nc * 16 + lane % 16;
-      f[e] = f2bf(ci < ci_real ? W[((size_t)t * ci_real + ci) * co + c] : 0.f);
-    }
-    fw[q] = f;
+// (tap, channel) of K-index kk (0..31) of K-step ks for a convolution whose
+// K side has ck channels (the ordering the convolution kernel reads).
+__device__ inline void k_index(int ck, int ks, int kk, int& t, int& c) {
+  if (ck >= 32) {
+    t = ks / (ck / 32);
+    c = (ks % (ck / 32)) * 32 + kk;
+  } else if (ck == 16) {
+    t = 2 * ks + (kk >> 4);
+    c = kk & 15;
+  } else {
+    const int k = ks * 32 + kk;
+    t = k >> 2;
+    c = k & 3;
   }
-  if (bw && q < 27 * (co / 16) * (ci_pad / 16) * 64) {
-    int lane = q % 64, r = q / 64;
-    int nc = r % (ci_pad / 16); r /= (ci_pad / 16);
-    int kc = r % (co / 16);
-    int t = r / (co / 16);
-    bf16x4 f;
-    for (int e = 0; e < 4; ++e) {
-      int c = kc * 16 + 4 * (lane / 16) + e, ci = nc * 16 + lane % 16;
-      f[e] = f2bf(ci < ci_real ? W[((size_t)(26 - t) * ci_real + ci) * co + c] : 0.f);
+}
+
+// BF16 B-fragments of conv weights W[27][ci][co] (FP32 master) for
+// v_mfma_f32_16x16x32_bf16: frag[ks][nt][lane][e] is the weight at K-index
+// kk = 8*(lane/16) + e of step ks and output column nt*16 + lane%16.
+// Forward: K = (tap, ci) with ck = 4 for the 3-channel input, N = co.
+// Backward (data gradient): taps mirrored (26 - t), K = (tap, co), N = ci.
+__global__ void frag_kernel(int ci, int ck, int co, int backward, const float* __restrict__ W,
+                            bf16x8* __restrict__ frag) {
+  const int nt_n = backward ? ci / 16 : co / 16;
+  const int kside = backward ? co : ck;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ksteps(kside) * nt_n * 64) return;
+  const int lane = q % 64, nt = (q / 64) % nt_n, ks = q / (64 * nt_n);
+  const int n = nt * 16 + lane % 16;
+  bf16x8 f;
+  for (int e = 0; e < 8; ++e) {
+    int t, c;
+    k_index(kside, ks, 8 * (lane / 16) + e, t, c);
+    float w = 0.f;
+    if (t < 27) {
+      if (!backward && c < ci) w = W[((size_t)t * ci + c) * co + n];
+      if (backward) w = W[((size_t)(26 - t) * ci + n) * co + c];
     }
-    bw[q] = f;
+    f[e] = __builtin_bit_cast(__bf16, (unsigned short)f2bf(w));
   }
+  frag[q] = f;
 }
 
 }  // namespace
@@ -434,8 +568,8 @@ struct cpr_nn {
   float* m = nullptr;
   float* vv = nullptr;
   float* grad = nullptr;
-  bf16x4* wf[NCONV] = {};
-  bf16x4* wb[NCONV] = {};
+  bf16x8* wf[NCONV] = {};
+  bf16x8* wb[NCONV] = {};
   // activations
   float *x16 = nullptr, *e0 = nullptr, *p1 = nullptr, *e1 = nullptr, *p2 = nullptr, *e2 = nullptr;
   float *p3 = nullptr, *e3 = nullptr, *a4 = nullptr, *d2 = nullptr, *a5 = nullptr, *d1 = nullptr;
@@ -469,22 +603,38 @@ static long nn_param_count() {
 
 static Geo with_batch(Geo g, int b) { g.batch = b; return g; }
 
+static int fwd_frags(int k) { return ksteps(k == 0 ? 4 : CIN[k]) * (COUT[k] / 16) * 64; }
+static int bwd_frags(int k) { return ksteps(COUT[k]) * (CIN[k] / 16) * 64; }
+
 static int nn_refresh_frags(cpr_nn* nn) {
   for (int k = 0; k < NCONV; ++k) {
-    int nf = 27 * (CIN_PAD[k] / 16) * (COUT[k] / 16) * 64;
-    frag_kernel<<<div_up(nf, 256), 256, 0, nn->stream>>>(CIN[k], CIN_PAD[k], COUT[k], nn->theta + nn->off[k],
-                                                         nn->wf[k], k == 0 ? nullptr : nn->wb[k]);
+    const float* W = nn->theta + nn->off[k];
+    frag_kernel<<<div_up(fwd_frags(k), 256), 256, 0, nn->stream>>>(CIN[k], k == 0 ? 4 : CIN[k], COUT[k], 0, W,
+                                                                   nn->wf[k]);
+    if (k > 0)
+      frag_kernel<<<div_up(bwd_frags(k), 256), 256, 0, nn->stream>>>(CIN[k], CIN[k], COUT[k], 1, W, nn->wb[k]);
   }
   nn->frags_valid = true;
   NN_TRY(hipGetLastError());
   return CPR_OK;
 }
 
-template <int CI, int CO, bool UP, int EPI>
-static void conv(cpr_nn* nn, Geo g, const float* X, const bf16x4* W, const float* bias, const float* skip,
-                 float* outA, float* outD) {
-  long total = (long)g.batch * g.V;
-  conv_kernel<CI, CO, UP, EPI><<<div_up(total, 64), 256, 0, nn->stream>>>(g, X, W, bias, skip, outA, outD);
+// Grids of at least 64K voxels use whole-tile waves (K split 1); smaller
+// ones, and 64-channel inputs at full resolution (whose LDS window would
+// not fit), split the K-steps over the 4 waves of a workgroup.
+template <int CI, int CSRC, int CO, bool UP, int EPI>
+static void conv(cpr_nn* nn, Geo g, const float* X, const bf16x8* W, const float* bias, const float* skip,
+                 float* outA, float* outD, const float* head = nullptr, float* y = nullptr) {
+  const long vox = (long)g.batch * g.V;
+  const long txy = (long)div_up(g.nx, TX) * div_up(g.ny, TY);
+  if (vox >= 65536 && (UP || CI <= 32)) {
+    const long tiles = txy * div_up(g.nz, 4) * g.batch;
+    conv_kernel<CI, CSRC, CO, UP, EPI, 1><<<tiles, 256, 0, nn->stream>>>(g, X, W, bias, skip, outA, outD, head, y);
+  } else {
+    const long tiles = txy * g.nz * g.batch;
+    conv_kernel<CI, CSRC, CO, UP, EPI, 4><<<tiles, 256, 0, nn->stream>>>(g, X, W, bias, skip, outA, outD, nullptr,
+                                                                        nullptr);
+  }
 }
 
 template <int CI, int CO, bool UP>
@@ -502,24 +652,32 @@ static void wgrad(cpr_nn* nn, Geo g, const float* X, const float* dZ, int k) {
   colsum_final_kernel<<<1, 64, 0, nn->stream>>>(nb, CO, nn->gp, nn->grad + nn->off[k] + 27L * CIN[k] * CO);
 }
 
-static int nn_forward_impl(cpr_nn* nn, int B) {
+// x3: input features [B][voxel][3].  train: keep what the backward pass
+// needs (pre-skip activations, d0) and run the head separately; otherwise
+// only what inference needs, with the head fused into the last convolution.
+static int nn_forward_impl(cpr_nn* nn, const float* x3, int B, bool train) {
   Geo L0 = with_batch(nn->lv[0], B), L1 = with_batch(nn->lv[1], B), L2 = with_batch(nn->lv[2], B),
       L3 = with_batch(nn->lv[3], B);
   hipStream_t s = nn->stream;
   auto bias = [&](int k) { return nn->theta + nn->off[k] + 27L * CIN[k] * COUT[k]; };
-  conv<16, 16, false, 1>(nn, L0, nn->x16, nn->wf[0], bias(0), nullptr, nn->e0, nullptr);
+  const float* head = nn->theta + nn->off[NCONV];
+  conv<4, 3, 16, false, 1>(nn, L0, x3, nn->wf[0], bias(0), nullptr, nn->e0, nullptr);
   pool_kernel<<<div_up((long)B * L1.V * 16, 256), 256, 0, s>>>(L1, 16, nn->e0, nn->p1);
-  conv<16, 32, false, 1>(nn, L1, nn->p1, nn->wf[1], bias(1), nullptr, nn->e1, nullptr);
+  conv<16, 16, 32, false, 1>(nn, L1, nn->p1, nn->wf[1], bias(1), nullptr, nn->e1, nullptr);
   pool_kernel<<<div_up((long)B * L2.V * 32, 256), 256, 0, s>>>(L2, 32, nn->e1, nn->p2);
-  conv<32, 64, false, 1>(nn, L2, nn->p2, nn->wf[2], bias(2), nullptr, nn->e2, nullptr);
+  conv<32, 32, 64, false, 1>(nn, L2, nn->p2, nn->wf[2], bias(2), nullptr, nn->e2, nullptr);
   pool_kernel<<<div_up((long)B * L3.V * 64, 256), 256, 0, s>>>(L3, 64, nn->e2, nn->p3);
-  conv<64, 64, false, 1>(nn, L3, nn->p3, nn->wf[3], bias(3), nullptr, nn->e3, nullptr);
-  conv<64, 64, true, 1>(nn, L2, nn->e3, nn->wf[4], bias(4), nn->e2, nn->a4, nn->d2);
-  conv<64, 32, true, 1>(nn, L1, nn->d2, nn->wf[5], bias(5), nn->e1, nn->a5, nn->d1);
-  conv<32, 16, true, 1>(nn, L0, nn->d1, nn->wf[6], bias(6), nn->e0, nn->a6, nn->d0);
-  long n0 = (long)B * L0.V;
-  head_fwd_kernel<<<div_up(n0, 256), 256, 0, s>>>(n0, nn->d0, nn->theta + nn->off[NCONV], nn->y);
-  nn->cur_batch = B;
+  conv<64, 64, 64, false, 1>(nn, L3, nn->p3, nn->wf[3], bias(3), nullptr, nn->e3, nullptr);
+  conv<64, 64, 64, true, 1>(nn, L2, nn->e3, nn->wf[4], bias(4), nn->e2, train ? nn->a4 : nullptr, nn->d2);
+  conv<64, 64, 32, true, 1>(nn, L1, nn->d2, nn->wf[5], bias(5), nn->e1, train ? nn->a5 : nullptr, nn->d1);
+  const long n0 = (long)B * L0.V;
+  if (train || n0 < 65536) {
+    conv<32, 32, 16, true, 1>(nn, L0, nn->d1, nn->wf[6], bias(6), nn->e0, nn->a6, nn->d0);
+    head_fwd_kernel<<<div_up(n0, 256), 256, 0, s>>>(n0, nn->d0, head, nn->y);
+  } else {
+    conv<32, 32, 16, true, 1>(nn, L0, nn->d1, nn->wf[6], bias(6), nn->e0, nullptr, nullptr, head, nn->y);
+  }
+  nn->cur_batch = train ? B : 0;
   NN_TRY(hipGetLastError());
   return CPR_OK;
 }
@@ -542,28 +700,28 @@ static int nn_backward_impl(cpr_nn* nn) {
   // level 0 decoder: d0 = a6 + e0; dz6 = dd0 * (a6 > 0); g0 keeps de0 = dd0
   relu_mask_kernel<<<div_up(n0 * 16, 256), 256, 0, s>>>(n0 * 16, nn->g0, nn->a6, nn->g0b);
   wgrad<32, 16, true>(nn, L0, nn->d1, nn->g0b, 6);
-  conv<16, 32, false, 0>(nn, L0, nn->g0b, nn->wb[6], nullptr, nullptr, nn->gu0, nullptr);
+  conv<16, 16, 32, false, 0>(nn, L0, nn->g0b, nn->wb[6], nullptr, nullptr, nn->gu0, nullptr);
   up_bwd_kernel<<<div_up(n1 * 32, 256), 256, 0, s>>>(L1, 32, nn->gu0, nn->g1, 0);      // dd1 = de1
   relu_mask_kernel<<<div_up(n1 * 32, 256), 256, 0, s>>>(n1 * 32, nn->g1, nn->a5, nn->g1b);
   wgrad<64, 32, true>(nn, L1, nn->d2, nn->g1b, 5);
-  conv<32, 64, false, 0>(nn, L1, nn->g1b, nn->wb[5], nullptr, nullptr, nn->gu1, nullptr);
+  conv<32, 32, 64, false, 0>(nn, L1, nn->g1b, nn->wb[5], nullptr, nullptr, nn->gu1, nullptr);
   up_bwd_kernel<<<div_up(n2 * 64, 256), 256, 0, s>>>(L2, 64, nn->gu1, nn->g2, 0);      // dd2 = de2
   relu_mask_kernel<<<div_up(n2 * 64, 256), 256, 0, s>>>(n2 * 64, nn->g2, nn->a4, nn->g2b);
   wgrad<64, 64, true>(nn, L2, nn->e3, nn->g2b, 4);
-  conv<64, 64, false, 0>(nn, L2, nn->g2b, nn->wb[4], nullptr, nullptr, nn->gu2, nullptr);
+  conv<64, 64, 64, false, 0>(nn, L2, nn->g2b, nn->wb[4], nullptr, nullptr, nn->gu2, nullptr);
   up_bwd_kernel<<<div_up(n3 * 64, 256), 256, 0, s>>>(L3, 64, nn->gu2, nn->g3, 0);      // de3
   // encoder
   relu_mask_kernel<<<div_up(n3 * 64, 256), 256, 0, s>>>(n3 * 64, nn->g3, nn->e3, nn->g3b);
   wgrad<64, 64, false>(nn, L3, nn->p3, nn->g3b, 3);
-  conv<64, 64, false, 0>(nn, L3, nn->g3b, nn->wb[3], nullptr, nullptr, nn->gu2, nullptr);  // dp3 (L3)
+  conv<64, 64, 64, false, 0>(nn, L3, nn->g3b, nn->wb[3], nullptr, nullptr, nn->gu2, nullptr);  // dp3 (L3)
   pool_bwd_kernel<<<div_up(n2 * 64, 256), 256, 0, s>>>(L2, 64, nn->gu2, nn->g2);          // de2 += pool'(dp3)
   relu_mask_kernel<<<div_up(n2 * 64, 256), 256, 0, s>>>(n2 * 64, nn->g2, nn->e2, nn->g2b);
   wgrad<32, 64, false>(nn, L2, nn->p2, nn->g2b, 2);
-  conv<64, 32, false, 0>(nn, L2, nn->g2b, nn->wb[2], nullptr, nullptr, nn->gu1, nullptr);  // dp2 (L2, 32)
+  conv<64, 64, 32, false, 0>(nn, L2, nn->g2b, nn->wb[2], nullptr, nullptr, nn->gu1, nullptr);  // dp2 (L2, 32)
   pool_bwd_kernel<<<div_up(n1 * 32, 256), 256, 0, s>>>(L1, 32, nn->gu1, nn->g1);          // de1 += pool'(dp2)
   relu_mask_kernel<<<div_up(n1 * 32, 256), 256, 0, s>>>(n1 * 32, nn->g1, nn->e1, nn->g1b);
   wgrad<16, 32, false>(nn, L1, nn->p1, nn->g1b, 1);
-  conv<32, 16, false, 0>(nn, L1, nn->g1b, nn->wb[1], nullptr, nullptr, nn->gu0, nullptr);  // dp1 (L1, 16)
+  conv<32, 32, 16, false, 0>(nn, L1, nn->g1b, nn->wb[1], nullptr, nullptr, nn->gu0, nullptr);  // dp1 (L1, 16)
   pool_bwd_kernel<<<div_up(n0 * 16, 256), 256, 0, s>>>(L0, 16, nn->gu0, nn->g0);          // de0 += pool'(dp1)
   relu_mask_kernel<<<div_up(n0 * 16, 256), 256, 0, s>>>(n0 * 16, nn->g0, nn->e0, nn->g0b);
   wgrad<16, 16, false>(nn, L0, nn->x16, nn->g0b, 0);
@@ -578,9 +736,8 @@ static int nn_alloc(cpr_nn* nn) {
   auto A = [&](float** p, long cnt) -> hipError_t { return hipMalloc((void**)p, (cnt > 0 ? cnt : 1) * sizeof(float)); };
   NN_TRY(A(&nn->theta, nn->P)); NN_TRY(A(&nn->m, nn->P)); NN_TRY(A(&nn->vv, nn->P)); NN_TRY(A(&nn->grad, nn->P));
   for (int k = 0; k < NCONV; ++k) {
-    size_t nf = 27 * (CIN_PAD[k] / 16) * (COUT[k] / 16) * 64;
-    NN_TRY(hipMalloc((void**)&nn->wf[k], nf * sizeof(bf16x4)));
-    NN_TRY(hipMalloc((void**)&nn->wb[k], nf * sizeof(bf16x4)));
+    NN_TRY(hipMalloc((void**)&nn->wf[k], fwd_frags(k) * sizeof(bf16x8)));
+    NN_TRY(hipMalloc((void**)&nn->wb[k], bwd_frags(k) * sizeof(bf16x8)));
   }
   NN_TRY(A(&nn->x16, n[0] * 16)); NN_TRY(A(&nn->e0, n[0] * 16)); NN_TRY(A(&nn->p1, n[1] * 16));
   NN_TRY(A(&nn->e1, n[1] * 32)); NN_TRY(A(&nn->p2, n[2] * 32)); NN_TRY(A(&nn->e2, n[2] * 64));
@@ -625,8 +782,7 @@ float* nn_output(cpr_nn* nn) { return nn->y; }
 
 int nn_infer(cpr_nn* nn, const float* x3, float* y) {
   long n0 = nn->lv[0].V;
-  pad_input_kernel<<<div_up(n0 * 16, 256), 256, 0, nn->stream>>>(n0, x3, nn->x16);
-  int rc = nn_forward_impl(nn, 1);
+  int rc = nn_forward_impl(nn, x3, 1, false);
   if (rc) return rc;
   if (y && y != nn->y) NN_TRY(hipMemcpyAsync(y, nn->y, n0 * sizeof(float), hipMemcpyDeviceToDevice, nn->stream));
   return CPR_OK;
@@ -707,11 +863,17 @@ int cpr_nn_forward(cpr_nn_t* nn, const float* x, int batch, float* y) {
   if (batch < 1 || batch > nn->max_batch) return nn_err(nn, CPR_EINVAL, "batch out of range");
   if (!nn->frags_valid) return nn_err(nn, CPR_EINVAL, "parameters not set");
   long n0 = (long)batch * nn->lv[0].V;
-  pad_input_kernel<<<div_up(n0 * 16, 256), 256, 0, nn->stream>>>(n0, x, nn->x16);
-  int rc = nn_forward_impl(nn, batch);
+  pad_input_kernel<<<div_up(n0 * 16, 256), 256, 0, nn->stream>>>(n0, x, nn->x16);   // for the weight gradient
+  int rc = nn_forward_impl(nn, x, batch, true);
   if (rc) return rc;
   NN_TRY(hipMemcpyAsync(y, nn->y, n0 * sizeof(float), hipMemcpyDeviceToDevice, nn->stream));
   return CPR_OK;
+}
+
+int cpr_nn_infer(cpr_nn_t* nn, const float* x, float* y) {
+  if (!nn || !x || !y) return CPR_EINVAL;
+  if (!nn->frags_valid) return nn_err(nn, CPR_EINVAL, "parameters not set");
+  return nn_infer(nn, x, y);
 }
 
 int cpr_nn_backward(cpr_nn_t* nn, const float* dy, float* grad) {
@@ -732,8 +894,7 @@ int cpr_nn_eval_loss(cpr_nn_t* nn, const float* x, const float* t, int batch, fl
   hipStream_t s = nn->stream;
   const int V = nn->lv[0].V;
   long n0 = (long)batch * V;
-  pad_input_kernel<<<div_up(n0 * 16, 256), 256, 0, s>>>(n0, x, nn->x16);
-  int rc = nn_forward_impl(nn, batch);
+  int rc = nn_forward_impl(nn, x, batch, false);
   if (rc) return rc;
   const int per = 64;
   loss_partial_kernel<<<batch * per, 256, 0, s>>>(V, per, nn->y, t, nn->lpart);
@@ -758,8 +919,8 @@ int cpr_nn_train_step(cpr_nn_t* nn, const float* x, const float* t, int batch, f
   hipStream_t s = nn->stream;
   const int V = nn->lv[0].V;
   long n0 = (long)batch * V;
-  pad_input_kernel<<<div_up(n0 * 16, 256), 256, 0, s>>>(n0, x, nn->x16);
-  int rc = nn_forward_impl(nn, batch);
+  pad_input_kernel<<<div_up(n0 * 16, 256), 256, 0, s>>>(n0, x, nn->x16);   // for the weight gradient
+  int rc = nn_forward_impl(nn, x, batch, true);
   if (rc) return rc;
   const int per = 64;
   loss_partial_kernel<<<batch * per, 256, 0, s>>>(V, per, nn->y, t, nn->lpart);

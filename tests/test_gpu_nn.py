@@ -47,23 +47,36 @@ def _net(shape, batch):
     return cprmi.Network(nx, ny, nz, max_batch=batch)
 
 
-def test_forward_matches_oracle():
+# (batch, (nz, ny, nx)): the small grid runs every convolution with its
+# K-steps split over a workgroup's waves; the larger one (>= 65,536 cells)
+# runs the full-resolution convolutions with whole-tile waves and, for
+# inference, the head fused into the last convolution.
+SHAPES = [(2, (8, 16, 16)), (1, (16, 64, 64))]
+
+
+@pytest.mark.parametrize("batch,shape", SHAPES)
+def test_forward_matches_oracle(batch, shape):
     theta = _theta(1)
     rng = np.random.default_rng(2)
-    x = rng.standard_normal((2, 8, 16, 16, 3)).astype(np.float32)
-    net = _net((8, 16, 16), 2)
+    x = rng.standard_normal((batch,) + shape + (3,)).astype(np.float32)
+    net = _net(shape, batch)
     net.set_params(theta.astype(np.float32))
-    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    xg = torch.from_numpy(x).cuda()
+    y = net.forward(xg).cpu().numpy()
     yo, _ = nn.forward(theta.astype(np.float32).astype(np.float64), x.astype(np.float64))
-    print(f"[nn] forward rel. diff {_rel(y, yo):.2e}")
+    print(f"[nn] forward {batch}x{shape}: rel. diff {_rel(y, yo):.2e}")
     assert _rel(y, yo) <= 3e-2
+    # the inference form: same kernels, head possibly fused (FP32 order only)
+    yi = np.stack([net.infer(xg[i:i + 1].contiguous()).cpu().numpy()[0] for i in range(batch)])
+    print(f"[nn] inference vs forward rel. diff {_rel(yi, y):.2e}")
+    assert _rel(yi, y) <= 1e-5
 
 
-def _grads(theta, seed):
+def _grads(theta, seed, batch=2, shape=(8, 16, 16)):
     rng = np.random.default_rng(seed)
-    x = rng.standard_normal((2, 8, 16, 16, 3)).astype(np.float32)
-    dy = rng.standard_normal((2, 8, 16, 16)).astype(np.float32)
-    net = _net((8, 16, 16), 2)
+    x = rng.standard_normal((batch,) + shape + (3,)).astype(np.float32)
+    dy = rng.standard_normal((batch,) + shape).astype(np.float32)
+    net = _net(shape, batch)
     net.set_params(theta.astype(np.float32))
     net.forward(torch.from_numpy(x).cuda())
     g = net.backward(torch.from_numpy(dy).cuda()).cpu().numpy().astype(np.float64)
@@ -71,14 +84,15 @@ def _grads(theta, seed):
     return g, nn.backward(theta, cache, dy.astype(np.float64))
 
 
-def test_backward_matches_oracle_without_relu_flips():
+@pytest.mark.parametrize("batch,shape", SHAPES)
+def test_backward_matches_oracle_without_relu_flips(batch, shape):
     # Large biases keep every ReLU open, so no unit can switch sides under
     # BF16 rounding: the gradient then differs only by rounding (~1e-2);
     # a wrong index, tap or dropped term would give an O(1) difference.
     convs, head = nn.unpack(synth.nn_initial_weights(3).astype(np.float64))
     theta = _bf16(nn.pack([(0.3 * W, np.full(b.shape, 3.0)) for W, b in convs], head))
-    g, go = _grads(theta, 4)
-    print(f"[nn] gradient rel. diff (open ReLUs) {_rel(g, go):.2e}")
+    g, go = _grads(theta, 4, batch, shape)
+    print(f"[nn] gradient {batch}x{shape}: rel. diff (open ReLUs) {_rel(g, go):.2e}")
     assert _rel(g, go) <= 2e-2
     o = 0
     for k, (ci, co) in enumerate(nn.CONVS):

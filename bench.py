@@ -111,7 +111,8 @@ def main():
     # the other forms of the preconditioner on the same workload
     variants = {}
     if not args.no_variants:
-        wfile = os.path.join(ROOT, "paper_1606_00548_amd", "weights", "pressure_unet.npy")
+        from paper_1606_00548_amd import train
+        wfile = train.weights_path("black-oil")
         forms = [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed"))]
         if os.path.exists(wfile):
             solver.attach_network(np.load(wfile))

@@ -196,6 +196,41 @@ def oil_water_training(nx=64, ny=64, nz=32, seed=5000):
     return c
 
 
+def black_oil_training(nx=64, ny=64, nz=32, seed=7000):
+    """Pressure-stage training systems for black oil: anisotropic
+    permeability (kz/kx = 10^U(-1.5, -0.5)), half of the systems layered
+    (ln kx = ln 100 + a L_k + c eps, a ~ U(0.5, 1.2), c ~ U(0.3, 0.9)), half
+    a correlated field (sigma ~ U(0.5, 1.5), horizontal correlation U{2..8},
+    vertical 1); wells a five-spot, a 2x2 or 3x3 lattice, or 1-4 random
+    injector/producer pairs; porosity U(0.1, 0.3); dt 1 day."""
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    if rng.uniform() < 0.5:
+        a, c = rng.uniform(0.5, 1.2), rng.uniform(0.3, 0.9)
+        lnk = a * rng.standard_normal(nz)[:, None, None] + c * rng.standard_normal(shape)
+    else:
+        sigma, lh = rng.uniform(0.5, 1.5), float(rng.integers(2, 9))
+        lnk = sigma * gaussian_field(rng, shape, (1.0, lh, lh))
+    kx = np.exp(np.log(100.0) + lnk)
+    perm = np.stack([kx, kx, 10.0 ** rng.uniform(-1.5, -0.5) * kx])
+    poro = rng.uniform(0.1, 0.3, shape)
+    pattern = int(rng.integers(0, 3))
+    if pattern == 0:
+        wells = five_spot(nx, ny, nz)
+    elif pattern == 1:
+        wells = lattice_wells(nx, ny, nz, per_side=int(rng.integers(2, 4)))
+    else:
+        npair = int(rng.integers(1, 5))
+        cols = rng.choice(nx * ny, size=2 * npair, replace=False)   # distinct columns
+        wells = []
+        for q in range(npair):
+            i, j = cols[2 * q], cols[2 * q + 1]
+            wells.append(well(i % nx, i // nx, nz, "inj", 300.0))
+            wells.append(well(j % nx, j // nx, nz, "prod", 150.0))
+    return _case(grid_of(nx, ny, nz), BLACK_OIL, perm, poro, wells, 1.0,
+                 f"black-oil training {nx}x{ny}x{nz}")
+
+
 def oil_water_eval(nx=128, ny=128, nz=64, seed=6000):
     """Evaluation systems for the learned stage: sigma 1.0, correlation
     (4, 4, 1), five-spot, S_w field as in training."""

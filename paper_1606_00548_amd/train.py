@@ -3,10 +3,11 @@
 All arithmetic runs in libcprmi.so; this module only orchestrates calls and
 keeps tensors in GPU memory.
 
-Data: for each synthetic oil-water system the solver assembles its Newton
-system, sets up CPR and solves it with FGMRES; for the first Krylov vectors
-v_j it runs the pressure stage alone to get the residual the multigrid
-cycle leaves, r' = r~_p - A_p dp_mg, and the network input for it.  The
+Data: for each synthetic system of a reservoir family (oil-water or black
+oil) the solver assembles its Newton system, sets up CPR and runs a fixed
+number of FGMRES iterations; for each Krylov vector v_j it runs the
+pressure stage alone to get the residual the multigrid cycle leaves,
+r' = r~_p - A_p dp_mg, and the network input for it.  The
 target is the exact remaining correction A_p^-1 r', obtained with the same
 library by solving the pressure system to 1e-10 (A_p embedded as the
 pressure block of a two-unknown system whose second unknown is decoupled
@@ -23,7 +24,21 @@ import torch
 
 from . import cprmi, synth
 
-WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "pressure_unet.npy")
+WEIGHT_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+
+# Training and evaluation systems per reservoir family: generator, training
+# grid, evaluation generator and grid, first evaluation seed.
+FAMILIES = {
+    "oil-water": {"train": synth.oil_water_training, "shape": (64, 64, 32),
+                  "eval": synth.oil_water_eval, "eval_shape": (128, 128, 64), "seed0": 5000, "eval_seed0": 6000},
+    "black-oil": {"train": synth.black_oil_training, "shape": (64, 64, 32),
+                  "eval": synth.black_oil_layered, "eval_shape": (128, 128, 32), "seed0": 7000, "eval_seed0": 2000},
+}
+
+
+def weights_path(family):
+    """Shipped parameters of the network trained for a family."""
+    return os.path.join(WEIGHT_DIR, f"pressure_unet_{family.replace('-', '_')}.npy")
 
 
 def _dev(a):
@@ -53,10 +68,11 @@ class PressureTarget:
 
 
 def harvest(case, per_system):
-    """(features [k, nz, ny, nx, 3] float32, targets [k, nz, ny, nx] float32)."""
+    """(features [k, nz, ny, nx, 3] float32, targets [k, nz, ny, nx] float32)
+    for the first k = per_system (<= 30) Krylov vectors of the system."""
     s = cprmi.Solver.from_case(case)
     rhs = s.assemble(_dev(case["x_old"]), _dev(case["x"]), case["dt"])
-    s.setup()
+    s.setup(rtol=0.0, max_iter=min(per_system, 30))
     _, st = s.solve(rhs)
     k = min(per_system, st["iterations"], 30)
     tgt = PressureTarget(case)
@@ -76,12 +92,13 @@ def harvest(case, per_system):
     return torch.stack(feats), torch.stack(targets)
 
 
-def make_dataset(n_systems, per_system, shape=(64, 64, 32), seed0=5000, log=print):
+def make_dataset(n_systems, per_system, shape=(64, 64, 32), seed0=5000, log=print, family="oil-water"):
     nx, ny, nz = shape
+    gen = FAMILIES[family]["train"]
     X, T = [], []
     t0 = time.time()
     for i in range(n_systems):
-        case = synth.oil_water_training(nx, ny, nz, seed=seed0 + i)
+        case = gen(nx, ny, nz, seed=seed0 + i)
         f, t = harvest(case, per_system)
         X.append(f)
         T.append(t)
@@ -130,13 +147,15 @@ def validation_loss(net, X, T, idx, batch):
     return float(np.mean(tot))
 
 
-def evaluate(theta, seeds, shape=(128, 128, 64), control_seed=99, log=print):
+def evaluate(theta, seeds, shape=(128, 128, 64), control_seed=99, log=print, family="oil-water",
+             precision="fp64"):
     """FGMRES iterations and solve time to 1e-6 on evaluation systems: plain
     CPR, CPR with the trained network, CPR with a random-init network."""
     nx, ny, nz = shape
+    gen = FAMILIES[family]["eval"]
     rows = []
     for sd in seeds:
-        case = synth.oil_water_eval(nx, ny, nz, seed=sd)
+        case = gen(nx, ny, nz, seed=sd)
         s = cprmi.Solver.from_case(case)
         rhs = s.assemble(_dev(case["x_old"]), _dev(case["x"]), case["dt"])
         row = {"seed": sd}
@@ -144,7 +163,7 @@ def evaluate(theta, seeds, shape=(128, 128, 64), control_seed=99, log=print):
                          ("random", synth.nn_initial_weights(control_seed))):
             if th is not None:
                 s.attach_network(th)
-            s.setup(learned=0 if th is None else 1)
+            s.setup(learned=0 if th is None else 1, precision=precision)
             s.solve(rhs)                       # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -164,25 +183,52 @@ def evaluate(theta, seeds, shape=(128, 128, 64), control_seed=99, log=print):
 
 def main():
     ap = argparse.ArgumentParser(description="train and evaluate the pressure-correction network")
+    ap.add_argument("--family", default="black-oil", choices=sorted(FAMILIES))
     ap.add_argument("--systems", type=int, default=100)
     ap.add_argument("--per-system", type=int, default=20)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval-seeds", type=int, default=8)
-    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--out", default=None, help="parameter file (default: the family's shipped file)")
     ap.add_argument("--report", default=None)
     args = ap.parse_args()
-    X, T = make_dataset(args.systems, args.per_system)
-    print(f"[data] {X.shape[0]} pairs", flush=True)
-    theta, hist = train(X, T, args.epochs, lr=args.lr,
+    fam = FAMILIES[args.family]
+    out = args.out or weights_path(args.family)
+    X, T = make_dataset(args.systems, args.per_system, fam["shape"], fam["seed0"], family=args.family,
                         log=lambda m: print(m, flush=True))
+    pairs = int(X.shape[0])
+    print(f"[data] {pairs} pairs", flush=True)
+    theta, hist = train(X, T, args.epochs, lr=args.lr, log=lambda m: print(m, flush=True))
     del X, T
-    os.makedirs(os.path.dirname(args.out), exist_ok=True)
-    np.save(args.out, theta)
-    rows = evaluate(theta, [6000 + i for i in range(args.eval_seeds)], log=lambda m: print(m, flush=True))
+    torch.cuda.empty_cache()
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    np.save(out, theta)
+    nx, ny, nz = fam["shape"]
+    meta = {
+        "family": args.family,
+        "network": "3-D U-Net, channels (16, 32, 64, 64), one 3x3x3 convolution per level and path, ReLU, "
+                   "avg-pool / nearest-upsample, additive skips, 1x1x1 head",
+        "parameters": int(theta.size),
+        "dtype": "float32 master (BF16 in the convolutions)",
+        "data": f"{args.systems} {args.family} systems {nx}x{ny}x{nz} ({fam['train'].__module__}."
+                f"{fam['train'].__name__} seeds {fam['seed0']}-{fam['seed0'] + args.systems - 1}), "
+                f"the pressure residuals after the multigrid cycle for the first {args.per_system} Krylov "
+                f"vectors of each; targets A_p^-1 r' / rms(D^-1 r') from a 1e-10 pressure solve",
+        "pairs": pairs, "epochs": args.epochs, "batch": 4,
+        "optimizer": f"Adam lr {args.lr:g} (0.9, 0.999, 1e-8)", "init_seed": 1, "shuffle_seed": 0,
+        "loss": "direction loss 1 - cos^2(N(x), t)", "history": hist,
+    }
+    with open(os.path.splitext(out)[0] + ".json", "w") as f:
+        json.dump(meta, f, indent=1)
+    ex, ey, ez = fam["eval_shape"]
+    rows = []
+    for prec in ("fp64", "mixed"):
+        rows += [dict(r, precision=prec) for r in evaluate(
+            theta, [fam["eval_seed0"] + i for i in range(args.eval_seeds)], shape=(ex, ey, ez),
+            family=args.family, precision=prec, log=lambda m: print(m, flush=True))]
     if args.report:
         with open(args.report, "w") as f:
-            json.dump({"history": hist, "eval": rows}, f, indent=1)
+            json.dump({"family": args.family, "history": hist, "eval": rows}, f, indent=1)
 
 
 if __name__ == "__main__":

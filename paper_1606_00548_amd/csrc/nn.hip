@@ -58,14 +58,18 @@ struct Geo {
 //
 // Implicit GEMM on v_mfma_f32_16x16x32_bf16: M = voxels, N = output
 // channels, K = (tap, input channel) in steps of 32.  A workgroup (4 waves)
-// owns a tile of 16 x 4 x TZ output voxels; the input it needs (tile plus a
-// one-voxel halo, or the half-resolution cells under it when UP) is staged
-// once in LDS as BF16, so each input value is read from memory about
-// 2-3 times instead of 27.  With KS = 1 each wave owns one z-plane of the
-// tile (4 M-blocks of 16 voxels along x) and every K-step; with KS = 4
-// (small grids, to keep enough waves in flight) the tile is one plane and
-// the waves split the K-steps round-robin, their partial tiles summed in LDS
-// in wave order, so results are deterministic either way.
+// owns a tile of 16 x 4 x TZ output voxels and CO/NS of the output
+// channels.  At the start it stages, with all loads in flight together,
+// the input it needs (tile plus a one-voxel halo, or the half-resolution
+// cells under it when UP) in LDS as BF16, and the B-fragments of its
+// channels for every K-step; each input value is then read from memory
+// about 2-3 times instead of 27, and the K loop touches LDS only.  With
+// KS = 1 each wave owns one z-plane of the tile (4 M-blocks of 16 voxels
+// along x) and every K-step; with KS = 4 (small grids, to keep enough waves
+// in flight) the tile is one plane and the waves split the K-steps
+// round-robin, their partial tiles summed in LDS in wave order, so results
+// are deterministic either way.  POOL (KS = 1 only): the workgroup also
+// writes the 2x2x2 average of its activations, which its tile holds whole.
 //
 // K ordering (must match frag_kernel): CI >= 32: step = t * (CI/32) + chunk,
 // 32 channels per step; CI = 16: step s covers taps 2s, 2s+1; CI = 4 (the
@@ -79,53 +83,104 @@ __device__ inline unsigned pack_bf16x2(float a, float b) {
   return (unsigned)(unsigned short)f2bf(a) | ((unsigned)(unsigned short)f2bf(b) << 16);
 }
 
-template <int CI, int CSRC, int CO, bool UP, int EPI, int KS>
-__global__ __launch_bounds__(256) void conv_kernel(Geo g, const float* __restrict__ X,
-                                                   const bf16x8* __restrict__ Wf,
-                                                   const float* __restrict__ bias,
-                                                   const float* __restrict__ skip,
-                                                   float* __restrict__ outA, float* __restrict__ outD,
-                                                   const float* __restrict__ head, float* __restrict__ yout) {
+struct ConvArgs {
+  Geo g;
+  const float* X;        // input [batch][voxel][CSRC] (half-resolution grid when UP)
+  const bf16x8* W;       // all B-fragments [NK][CO/16][64]
+  const float* bias;     // [CO] (EPI 1)
+  const float* skip;     // [batch][voxel][CO] or null
+  float* outA;           // EPI 1: relu(acc + bias) (null: not stored); EPI 0: acc
+  float* outD;           // EPI 1 with skip: relu(acc + bias) + skip
+  const float* head;     // fused 1x1x1 head [CO + 1] (CO = 16, KS = 1) or null
+  float* y;              // head output [batch][voxel]
+  float* pool;           // POOL: [batch][coarse voxel][CO]
+};
+
+template <int CI, int CSRC, int CO, bool UP, int EPI, int KS, int NS, bool POOL>
+__global__ __launch_bounds__(256) void conv_kernel(ConvArgs p) {
   static_assert(KS == 1 || KS == 4, "K split is 1 or 4");
   static_assert(CI == 4 || CI == 16 || CI % 32 == 0, "channel layout");
+  static_assert(CO % (16 * NS) == 0, "channel split");
+  static_assert(!POOL || KS == 1, "pooling needs whole 2x2x2 cells in the tile");
   constexpr int TZ = 4 / KS;
   constexpr int HX = UP ? TX / 2 + 2 : TX + 2;
   constexpr int HY = UP ? TY / 2 + 2 : TY + 2;
   constexpr int HZ = UP ? TZ / 2 + 2 : TZ + 2;
   constexpr int HV = HX * HY * HZ;
   constexpr int NK = ksteps(CI);
-  constexpr int NT = CO / 16;
+  constexpr int NT = CO / 16;          // N-blocks of the whole convolution
+  constexpr int COB = CO / NS;         // output channels of this workgroup
+  constexpr int NTB = COB / 16;
   constexpr int HALO_BYTES = HV * CI * 2;
-  constexpr int RED_BYTES = KS > 1 ? KS * 64 * CO * 4 : 0;
-  constexpr int SMEM = HALO_BYTES > RED_BYTES ? HALO_BYTES : RED_BYTES;
+  constexpr int W_BYTES = NK * NTB * 64 * 16;
+  constexpr int RED_BYTES = KS > 1 ? KS * 64 * COB * 4 : 0;
+  constexpr int POOL_BYTES = POOL ? 64 * COB * 4 : 0;
+  constexpr int MAIN_BYTES = HALO_BYTES + W_BYTES;
+  constexpr int SMEM = MAIN_BYTES > RED_BYTES ? (MAIN_BYTES > POOL_BYTES ? MAIN_BYTES : POOL_BYTES)
+                                              : (RED_BYTES > POOL_BYTES ? RED_BYTES : POOL_BYTES);
   __shared__ __align__(16) unsigned char smem[SMEM];
+  const bf16x8* wl = (const bf16x8*)(smem + HALO_BYTES);
+  const Geo& g = p.g;
 
-  // tile of this workgroup; consecutive tiles go to the same XCD
+  // (tile, channel block) of this workgroup; consecutive blocks go to the
+  // same XCD, and the channel blocks of a tile are neighbours
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
-  const int ntiles = ntx * nty * ntz * g.batch;
-  int tile = blockIdx.x;
-  if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+  const int nblocks = ntx * nty * ntz * g.batch * NS;
+  int blk = blockIdx.x;
+  if ((nblocks & 7) == 0) blk = (blockIdx.x & 7) * (nblocks >> 3) + (blockIdx.x >> 3);
+  const int nb = blk % NS, tile = blk / NS;
   const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = (tile / (ntx * nty)) % ntz, b = tile / (ntx * nty * ntz);
   const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
 
-  // stage the input window as BF16 (zero outside the grid)
+  // stage the input window as BF16 (zero outside the grid) and this
+  // block's weight fragments, eight loads per thread in flight
   const int sx = UP ? g.nx >> 1 : g.nx, sy = UP ? g.ny >> 1 : g.ny, sz = UP ? g.nz >> 1 : g.nz;
   const int ox = UP ? (x0 - 1) >> 1 : x0 - 1, oy = UP ? (y0 - 1) >> 1 : y0 - 1, oz = UP ? (z0 - 1) >> 1 : z0 - 1;
-  const float* Xb = X + (long)b * sx * sy * sz * CSRC;
-  for (int q = threadIdx.x; q < HV * (CI / 4); q += 256) {
-    const int hv = q / (CI / 4), c4 = (q % (CI / 4)) * 4;
-    const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
-    const int px = ox + hx, py = oy + hy, pz = oz + hz;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (px >= 0 && px < sx && py >= 0 && py < sy && pz >= 0 && pz < sz) {
-      const float* src = Xb + ((long)px + (long)sx * (py + (long)sy * pz)) * CSRC + c4;
-      if (CSRC == CI) {
-        v = *(const float4*)src;
-      } else {
-        v.x = src[0]; v.y = src[1]; v.z = src[2];
+  const float* Xb = p.X + (long)b * sx * sy * sz * CSRC;
+  constexpr int NQ = HV * (CI / 4);
+  constexpr int NWF = NK * NTB * 64;
+  for (int q0 = 0; q0 < NQ; q0 += 8 * 256) {
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * 256 + threadIdx.x;
+      v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (q < NQ) {
+        const int hv = q / (CI / 4), c4 = (q % (CI / 4)) * 4;
+        const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+        const int px = ox + hx, py = oy + hy, pz = oz + hz;
+        if (px >= 0 && px < sx && py >= 0 && py < sy && pz >= 0 && pz < sz) {
+          const float* src = Xb + ((long)px + (long)sx * (py + (long)sy * pz)) * CSRC + c4;
+          if (CSRC == CI) {
+            v[u] = *(const float4*)src;
+          } else {
+            v[u].x = src[0]; v[u].y = src[1]; v[u].z = src[2];
+          }
+        }
       }
     }
-    *(uint2*)(smem + ((size_t)hv * CI + c4) * 2) = make_uint2(pack_bf16x2(v.x, v.y), pack_bf16x2(v.z, v.w));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * 256 + threadIdx.x;
+      if (q < NQ)
+        *(uint2*)(smem + (size_t)q * 8) = make_uint2(pack_bf16x2(v[u].x, v[u].y), pack_bf16x2(v[u].z, v[u].w));
+    }
+  }
+  for (int q0 = 0; q0 < NWF; q0 += 8 * 256) {
+    bf16x8 w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * 256 + threadIdx.x;
+      if (q < NWF) {
+        const int ks = q / (NTB * 64), j = (q / 64) % NTB, lane = q % 64;
+        w[u] = p.W[((size_t)ks * NT + nb * NTB + j) * 64 + lane];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * 256 + threadIdx.x;
+      if (q < NWF) ((bf16x8*)(smem + HALO_BYTES))[q] = w[u];
+    }
   }
   __syncthreads();
 
@@ -138,15 +193,15 @@ __global__ __launch_bounds__(256) void conv_kernel(Geo g, const float* __restric
       return (((x0 + i16 + dx) >> 1) - ox) + HX * ((((y0 + m + dy) >> 1) - oy) + HY * (((z0 + lz + dz) >> 1) - oz));
     return (i16 + dx + 1) + HX * ((m + dy + 1) + HY * (lz + dz + 1));
   };
-  f32x4 acc[4][NT];
+  f32x4 acc[4][NTB];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int n = 0; n < NTB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int ks = (KS == 1 ? 0 : wave); ks < NK; ks += KS) {
-    bf16x8 bw[NT];
+    bf16x8 bw[NTB];
 #pragma unroll
-    for (int n = 0; n < NT; ++n) bw[n] = Wf[((size_t)ks * NT + n) * 64 + lane];
+    for (int n = 0; n < NTB; ++n) bw[n] = wl[((size_t)ks * NTB + n) * 64 + lane];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       uint4 raw;
@@ -164,14 +219,15 @@ __global__ __launch_bounds__(256) void conv_kernel(Geo g, const float* __restric
       }
       const bf16x8 a = __builtin_bit_cast(bf16x8, raw);
 #pragma unroll
-      for (int n = 0; n < NT; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[n], acc[m][n], 0, 0, 0);
+      for (int n = 0; n < NTB; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[n], acc[m][n], 0, 0, 0);
     }
   }
 
   const long V = g.V;
+  const int c0 = nb * COB;
   if constexpr (KS == 1) {
     // C element (row 4*kq + e, column i16) of M-block m, N-block n is
-    // voxel (x0 + 4*kq + e, y0 + m, z0 + lz), channel n*16 + i16
+    // voxel (x0 + 4*kq + e, y0 + m, z0 + lz), channel c0 + n*16 + i16
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int y = y0 + m, z = z0 + lz;
@@ -180,30 +236,56 @@ __global__ __launch_bounds__(256) void conv_kernel(Geo g, const float* __restric
         const int x = x0 + 4 * kq + e;
         const bool ok = x < g.nx && y < g.ny && z < g.nz;
         const long o = (long)b * V + x + (long)g.nx * (y + (long)g.ny * z);
-        if (head) {
-          // y = sum_c head[c] (relu(acc + bias) + skip)[c] + head[CO]; CO = 16
-          const float a = fmaxf(acc[m][0][e] + bias[i16], 0.f) + (ok ? skip[o * CO + i16] : 0.f);
-          float h = a * head[i16];
+        if (CO == 16 && p.head) {
+          // y = sum_c head[c] (relu(acc + bias) + skip)[c] + head[CO]
+          const float a = fmaxf(acc[m][0][e] + p.bias[i16], 0.f) + (ok ? p.skip[o * CO + i16] : 0.f);
+          float h = a * p.head[i16];
           h += __shfl_xor(h, 8, 16);
           h += __shfl_xor(h, 4, 16);
           h += __shfl_xor(h, 2, 16);
           h += __shfl_xor(h, 1, 16);
-          if (ok && i16 == 0) yout[o] = h + head[CO];
+          if (ok && i16 == 0) p.y[o] = h + p.head[CO];
           continue;
         }
-        if (!ok) continue;
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-          const int co = n * 16 + i16;
-          const float val = acc[m][n][e];
+        for (int n = 0; n < NTB; ++n) {
+          const int co = c0 + n * 16 + i16;
+          float val = acc[m][n][e];
           if (EPI == 1) {
-            const float a = fmaxf(val + bias[co], 0.f);
-            if (outA) outA[o * CO + co] = a;
-            if (skip) outD[o * CO + co] = a + skip[o * CO + co];
-          } else {
-            outA[o * CO + co] = val;
+            val = fmaxf(val + p.bias[co], 0.f);
+            acc[m][n][e] = val;
+            if (!ok) continue;
+            if (p.outA) p.outA[o * CO + co] = val;
+            if (p.skip) p.outD[o * CO + co] = val + p.skip[o * CO + co];
+          } else if (ok) {
+            p.outA[o * CO + co] = val;
           }
         }
+      }
+    }
+    if constexpr (POOL) {
+      // 2x2 (x, y) sums in registers, the z pairs (waves 2k, 2k+1) via LDS
+      __syncthreads();
+      float* ps = (float*)smem;   // [lz][py][px][COB]
+#pragma unroll
+      for (int py = 0; py < 2; ++py)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int n = 0; n < NTB; ++n) {
+            const float sum = (acc[2 * py][n][2 * q] + acc[2 * py][n][2 * q + 1]) +
+                              (acc[2 * py + 1][n][2 * q] + acc[2 * py + 1][n][2 * q + 1]);
+            ps[((lz * 2 + py) * 8 + 2 * kq + q) * COB + n * 16 + i16] = sum;
+          }
+      __syncthreads();
+      const int cnx = g.nx >> 1, cny = g.ny >> 1, cnz = g.nz >> 1;
+      for (int q = threadIdx.x; q < 32 * COB; q += 256) {
+        const int co = q % COB, cell = q / COB;
+        const int px = cell & 7, py = (cell >> 3) & 1, pz = cell >> 4;
+        const int cx = (x0 >> 1) + px, cy = (y0 >> 1) + py, cz = (z0 >> 1) + pz;
+        if (cx >= cnx || cy >= cny || cz >= cnz) continue;
+        const float v = ps[((2 * pz * 2 + py) * 8 + px) * COB + co] + ps[(((2 * pz + 1) * 2 + py) * 8 + px) * COB + co];
+        p.pool[((long)b * cnx * cny * cnz + cx + (long)cnx * (cy + (long)cny * cz)) * CO + c0 + co] = 0.125f * v;
       }
     }
   } else {
@@ -213,24 +295,24 @@ __global__ __launch_bounds__(256) void conv_kernel(Geo g, const float* __restric
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int n = 0; n < NT; ++n)
+      for (int n = 0; n < NTB; ++n)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) red[((size_t)wave * 64 + m * 16 + 4 * kq + e) * CO + n * 16 + i16] = acc[m][n][e];
+        for (int e = 0; e < 4; ++e) red[((size_t)wave * 64 + m * 16 + 4 * kq + e) * COB + n * 16 + i16] = acc[m][n][e];
     __syncthreads();
-    for (int q = threadIdx.x; q < 64 * CO; q += 256) {
-      const int vox = q / CO, co = q % CO;
+    for (int q = threadIdx.x; q < 64 * COB; q += 256) {
+      const int vox = q / COB, co = c0 + q % COB;
       const int x = x0 + (vox & 15), y = y0 + (vox >> 4), z = z0;
       if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
       const long o = (long)b * V + x + (long)g.nx * (y + (long)g.ny * z);
       float val = red[q];
 #pragma unroll
-      for (int w = 1; w < KS; ++w) val += red[(size_t)w * 64 * CO + q];
+      for (int w = 1; w < KS; ++w) val += red[(size_t)w * 64 * COB + q];
       if (EPI == 1) {
-        const float a = fmaxf(val + bias[co], 0.f);
-        if (outA) outA[o * CO + co] = a;
-        if (skip) outD[o * CO + co] = a + skip[o * CO + co];
+        const float a = fmaxf(val + p.bias[co], 0.f);
+        if (p.outA) p.outA[o * CO + co] = a;
+        if (p.skip) p.outD[o * CO + co] = a + p.skip[o * CO + co];
       } else {
-        outA[o * CO + co] = val;
+        p.outA[o * CO + co] = val;
       }
     }
   }
@@ -621,19 +703,62 @@ static int nn_refresh_frags(cpr_nn* nn) {
 
 // Grids of at least 64K voxels use whole-tile waves (K split 1); smaller
 // ones, and 64-channel inputs at full resolution (whose LDS window would
-// not fit), split the K-steps over the 4 waves of a workgroup.
-template <int CI, int CSRC, int CO, bool UP, int EPI>
-static void conv(cpr_nn* nn, Geo g, const float* X, const bf16x8* W, const float* bias, const float* skip,
-                 float* outA, float* outD, const float* head = nullptr, float* y = nullptr) {
+// not fit beside the weights), split the K-steps over the 4 waves of a
+// workgroup.  The output channels are split over NS workgroups so that a
+// workgroup's weight fragments fit in 56 KB of LDS and, where the channels
+// allow, the launch has at least 512 workgroups.
+constexpr int WMAX = 56 * 1024;
+constexpr int wbytes(int ci, int co, int ns) { return ksteps(ci) * (co / (16 * ns)) * 1024; }
+
+static ConvArgs cargs(Geo g, const float* X, const bf16x8* W, const float* bias, const float* skip, float* outA,
+                      float* outD) {
+  ConvArgs a{};
+  a.g = g; a.X = X; a.W = W; a.bias = bias; a.skip = skip; a.outA = outA; a.outD = outD;
+  return a;
+}
+
+template <int CI, int CSRC, int CO, bool UP, int EPI, int KS, bool POOL>
+static void conv_ns(cpr_nn* nn, const ConvArgs& a, long tiles, int ns) {
+  if constexpr (wbytes(CI, CO, 1) <= WMAX)
+    if (ns == 1) {
+      conv_kernel<CI, CSRC, CO, UP, EPI, KS, 1, POOL><<<tiles, 256, 0, nn->stream>>>(a);
+      return;
+    }
+  if constexpr (CO >= 32 && wbytes(CI, CO, 2) <= WMAX)
+    if (ns == 2) {
+      conv_kernel<CI, CSRC, CO, UP, EPI, KS, 2, POOL><<<tiles * 2, 256, 0, nn->stream>>>(a);
+      return;
+    }
+  if constexpr (CO >= 64)
+    if (ns == 4) conv_kernel<CI, CSRC, CO, UP, EPI, KS, 4, POOL><<<tiles * 4, 256, 0, nn->stream>>>(a);
+}
+
+// a.pool (POOL only): also write the 2x2x2 average of the activations,
+// fused when the tiles hold whole cells, else by a separate pass.
+template <int CI, int CSRC, int CO, bool UP, int EPI, bool POOL = false>
+static void conv(cpr_nn* nn, ConvArgs a) {
+  const Geo& g = a.g;
   const long vox = (long)g.batch * g.V;
   const long txy = (long)div_up(g.nx, TX) * div_up(g.ny, TY);
-  if (vox >= 65536 && (UP || CI <= 32)) {
-    const long tiles = txy * div_up(g.nz, 4) * g.batch;
-    conv_kernel<CI, CSRC, CO, UP, EPI, 1><<<tiles, 256, 0, nn->stream>>>(g, X, W, bias, skip, outA, outD, head, y);
-  } else {
-    const long tiles = txy * g.nz * g.batch;
-    conv_kernel<CI, CSRC, CO, UP, EPI, 4><<<tiles, 256, 0, nn->stream>>>(g, X, W, bias, skip, outA, outD, nullptr,
-                                                                        nullptr);
+  const bool whole = vox >= 65536 && (UP || CI <= 32);
+  const long tiles = whole ? txy * div_up(g.nz, 4) * g.batch : txy * g.nz * g.batch;
+  int ns = 1;
+  while (wbytes(CI, CO, ns) > WMAX) ns *= 2;
+  while (CO / (16 * ns) >= 2 && ns < 4 && tiles * ns < 512) ns *= 2;
+  if (whole) {
+    conv_ns<CI, CSRC, CO, UP, EPI, 1, POOL>(nn, a, tiles, ns);
+    return;
+  }
+  ConvArgs b = a;
+  b.head = nullptr;
+  b.y = nullptr;
+  b.pool = nullptr;
+  conv_ns<CI, CSRC, CO, UP, EPI, 4, false>(nn, b, tiles, ns);
+  if (POOL) {
+    Geo c = g;
+    c.nx >>= 1; c.ny >>= 1; c.nz >>= 1;
+    c.V = c.nx * c.ny * c.nz;
+    pool_kernel<<<div_up((long)g.batch * c.V * CO, 256), 256, 0, nn->stream>>>(c, CO, a.outA, a.pool);
   }
 }
 
@@ -661,21 +786,27 @@ static int nn_forward_impl(cpr_nn* nn, const float* x3, int B, bool train) {
   hipStream_t s = nn->stream;
   auto bias = [&](int k) { return nn->theta + nn->off[k] + 27L * CIN[k] * COUT[k]; };
   const float* head = nn->theta + nn->off[NCONV];
-  conv<4, 3, 16, false, 1>(nn, L0, x3, nn->wf[0], bias(0), nullptr, nn->e0, nullptr);
-  pool_kernel<<<div_up((long)B * L1.V * 16, 256), 256, 0, s>>>(L1, 16, nn->e0, nn->p1);
-  conv<16, 16, 32, false, 1>(nn, L1, nn->p1, nn->wf[1], bias(1), nullptr, nn->e1, nullptr);
-  pool_kernel<<<div_up((long)B * L2.V * 32, 256), 256, 0, s>>>(L2, 32, nn->e1, nn->p2);
-  conv<32, 32, 64, false, 1>(nn, L2, nn->p2, nn->wf[2], bias(2), nullptr, nn->e2, nullptr);
-  pool_kernel<<<div_up((long)B * L3.V * 64, 256), 256, 0, s>>>(L3, 64, nn->e2, nn->p3);
-  conv<64, 64, 64, false, 1>(nn, L3, nn->p3, nn->wf[3], bias(3), nullptr, nn->e3, nullptr);
-  conv<64, 64, 64, true, 1>(nn, L2, nn->e3, nn->wf[4], bias(4), nn->e2, train ? nn->a4 : nullptr, nn->d2);
-  conv<64, 64, 32, true, 1>(nn, L1, nn->d2, nn->wf[5], bias(5), nn->e1, train ? nn->a5 : nullptr, nn->d1);
+  ConvArgs a = cargs(L0, x3, nn->wf[0], bias(0), nullptr, nn->e0, nullptr);
+  a.pool = nn->p1;
+  conv<4, 3, 16, false, 1, true>(nn, a);
+  a = cargs(L1, nn->p1, nn->wf[1], bias(1), nullptr, nn->e1, nullptr);
+  a.pool = nn->p2;
+  conv<16, 16, 32, false, 1, true>(nn, a);
+  a = cargs(L2, nn->p2, nn->wf[2], bias(2), nullptr, nn->e2, nullptr);
+  a.pool = nn->p3;
+  conv<32, 32, 64, false, 1, true>(nn, a);
+  conv<64, 64, 64, false, 1>(nn, cargs(L3, nn->p3, nn->wf[3], bias(3), nullptr, nn->e3, nullptr));
+  conv<64, 64, 64, true, 1>(nn, cargs(L2, nn->e3, nn->wf[4], bias(4), nn->e2, train ? nn->a4 : nullptr, nn->d2));
+  conv<64, 64, 32, true, 1>(nn, cargs(L1, nn->d2, nn->wf[5], bias(5), nn->e1, train ? nn->a5 : nullptr, nn->d1));
   const long n0 = (long)B * L0.V;
   if (train || n0 < 65536) {
-    conv<32, 32, 16, true, 1>(nn, L0, nn->d1, nn->wf[6], bias(6), nn->e0, nn->a6, nn->d0);
+    conv<32, 32, 16, true, 1>(nn, cargs(L0, nn->d1, nn->wf[6], bias(6), nn->e0, nn->a6, nn->d0));
     head_fwd_kernel<<<div_up(n0, 256), 256, 0, s>>>(n0, nn->d0, head, nn->y);
   } else {
-    conv<32, 32, 16, true, 1>(nn, L0, nn->d1, nn->wf[6], bias(6), nn->e0, nullptr, nullptr, head, nn->y);
+    a = cargs(L0, nn->d1, nn->wf[6], bias(6), nn->e0, nullptr, nullptr);
+    a.head = head;
+    a.y = nn->y;
+    conv<32, 32, 16, true, 1>(nn, a);
   }
   nn->cur_batch = train ? B : 0;
   NN_TRY(hipGetLastError());
@@ -700,28 +831,28 @@ static int nn_backward_impl(cpr_nn* nn) {
   // level 0 decoder: d0 = a6 + e0; dz6 = dd0 * (a6 > 0); g0 keeps de0 = dd0
   relu_mask_kernel<<<div_up(n0 * 16, 256), 256, 0, s>>>(n0 * 16, nn->g0, nn->a6, nn->g0b);
   wgrad<32, 16, true>(nn, L0, nn->d1, nn->g0b, 6);
-  conv<16, 16, 32, false, 0>(nn, L0, nn->g0b, nn->wb[6], nullptr, nullptr, nn->gu0, nullptr);
+  conv<16, 16, 32, false, 0>(nn, cargs(L0, nn->g0b, nn->wb[6], nullptr, nullptr, nn->gu0, nullptr));
   up_bwd_kernel<<<div_up(n1 * 32, 256), 256, 0, s>>>(L1, 32, nn->gu0, nn->g1, 0);      // dd1 = de1
   relu_mask_kernel<<<div_up(n1 * 32, 256), 256, 0, s>>>(n1 * 32, nn->g1, nn->a5, nn->g1b);
   wgrad<64, 32, true>(nn, L1, nn->d2, nn->g1b, 5);
-  conv<32, 32, 64, false, 0>(nn, L1, nn->g1b, nn->wb[5], nullptr, nullptr, nn->gu1, nullptr);
+  conv<32, 32, 64, false, 0>(nn, cargs(L1, nn->g1b, nn->wb[5], nullptr, nullptr, nn->gu1, nullptr));
   up_bwd_kernel<<<div_up(n2 * 64, 256), 256, 0, s>>>(L2, 64, nn->gu1, nn->g2, 0);      // dd2 = de2
   relu_mask_kernel<<<div_up(n2 * 64, 256), 256, 0, s>>>(n2 * 64, nn->g2, nn->a4, nn->g2b);
   wgrad<64, 64, true>(nn, L2, nn->e3, nn->g2b, 4);
-  conv<64, 64, 64, false, 0>(nn, L2, nn->g2b, nn->wb[4], nullptr, nullptr, nn->gu2, nullptr);
+  conv<64, 64, 64, false, 0>(nn, cargs(L2, nn->g2b, nn->wb[4], nullptr, nullptr, nn->gu2, nullptr));
   up_bwd_kernel<<<div_up(n3 * 64, 256), 256, 0, s>>>(L3, 64, nn->gu2, nn->g3, 0);      // de3
   // encoder
   relu_mask_kernel<<<div_up(n3 * 64, 256), 256, 0, s>>>(n3 * 64, nn->g3, nn->e3, nn->g3b);
   wgrad<64, 64, false>(nn, L3, nn->p3, nn->g3b, 3);
-  conv<64, 64, 64, false, 0>(nn, L3, nn->g3b, nn->wb[3], nullptr, nullptr, nn->gu2, nullptr);  // dp3 (L3)
+  conv<64, 64, 64, false, 0>(nn, cargs(L3, nn->g3b, nn->wb[3], nullptr, nullptr, nn->gu2, nullptr));  // dp3 (L3)
   pool_bwd_kernel<<<div_up(n2 * 64, 256), 256, 0, s>>>(L2, 64, nn->gu2, nn->g2);          // de2 += pool'(dp3)
   relu_mask_kernel<<<div_up(n2 * 64, 256), 256, 0, s>>>(n2 * 64, nn->g2, nn->e2, nn->g2b);
   wgrad<32, 64, false>(nn, L2, nn->p2, nn->g2b, 2);
-  conv<64, 64, 32, false, 0>(nn, L2, nn->g2b, nn->wb[2], nullptr, nullptr, nn->gu1, nullptr);  // dp2 (L2, 32)
+  conv<64, 64, 32, false, 0>(nn, cargs(L2, nn->g2b, nn->wb[2], nullptr, nullptr, nn->gu1, nullptr));  // dp2 (L2, 32)
   pool_bwd_kernel<<<div_up(n1 * 32, 256), 256, 0, s>>>(L1, 32, nn->gu1, nn->g1);          // de1 += pool'(dp2)
   relu_mask_kernel<<<div_up(n1 * 32, 256), 256, 0, s>>>(n1 * 32, nn->g1, nn->e1, nn->g1b);
   wgrad<16, 32, false>(nn, L1, nn->p1, nn->g1b, 1);
-  conv<32, 32, 16, false, 0>(nn, L1, nn->g1b, nn->wb[1], nullptr, nullptr, nn->gu0, nullptr);  // dp1 (L1, 16)
+  conv<32, 32, 16, false, 0>(nn, cargs(L1, nn->g1b, nn->wb[1], nullptr, nullptr, nn->gu0, nullptr));  // dp1 (L1, 16)
   pool_bwd_kernel<<<div_up(n0 * 16, 256), 256, 0, s>>>(L0, 16, nn->gu0, nn->g0);          // de0 += pool'(dp1)
   relu_mask_kernel<<<div_up(n0 * 16, 256), 256, 0, s>>>(n0 * 16, nn->g0, nn->e0, nn->g0b);
   wgrad<16, 16, false>(nn, L0, nn->x16, nn->g0b, 0);

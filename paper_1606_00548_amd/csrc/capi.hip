@@ -42,7 +42,7 @@ void free_all(cpr_ctx* ctx) {
   void* bufs[] = {ctx->poro, ctx->tp, ctx->perfs_d, ctx->J, ctx->props, ctx->vin, ctx->vin2, ctx->vout,
                   ctx->w, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf, ctx->flag, ctx->V, ctx->Z,
                   ctx->Y, ctx->rp, ctx->xs, ctx->rs, ctx->tmp, ctx->vf, ctx->zf, ctx->Yf, ctx->rpf,
-                  ctx->part, ctx->hdev, ctx->lnk, ctx->rprime, ctx->dpnn, ctx->qbuf, ctx->feat, ctx->nnscal,
+                  ctx->part, ctx->hdev, ctx->lnk, ctx->rprime, ctx->qbuf, ctx->feat, ctx->nnscal,
                   ctx->nncount};
   for (void* b : bufs)
     if (b) hipFree(b);
@@ -116,7 +116,6 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
   ALLOC(ctx->flag, 4);
   ALLOC(ctx->lnk, N);
   ALLOC(ctx->rprime, N);
-  ALLOC(ctx->dpnn, N);
   ALLOC(ctx->qbuf, N);
   ALLOC(ctx->feat, 3 * N);
   ALLOC(ctx->nnscal, 16);

@@ -223,7 +223,6 @@ struct cpr_ctx {
   struct cpr_nn* nn = nullptr;  // inference network on this grid (batch 1)
   double* lnk = nullptr;       // [n] ln kx (colour-split)
   double* rprime = nullptr;    // [n] pressure residual after the V-cycle
-  double* dpnn = nullptr;      // [n] network direction d, then the correction
   double* qbuf = nullptr;      // [n] A_p d
   float* feat = nullptr;       // [n][3] network input, natural order
   double* nnscal = nullptr;    // device scalars: feature statistics, norms

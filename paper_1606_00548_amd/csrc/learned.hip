@@ -9,14 +9,25 @@
 // and proposes a direction d = N(features); the step minimising the
 // pressure residual, alpha = <A_p d, r'> / <A_p d, A_p d>, gives
 // dp_nn = alpha d.  Plain CPR judges it in FP64: the correction is kept only
-// if ||r' - A_p dp_nn||_2 < ||r'||_2, otherwise the multigrid result stands.  Everything stays on the device (the decision is
-// a flag read by the kernel that applies the correction), so the learned
-// stage adds no host synchronisation to an FGMRES iteration.
+// if ||r' - A_p dp_nn||_2 < ||r'||_2, otherwise the multigrid result stands.
+// For this alpha, ||r' - alpha A_p d||^2 = ||r'||^2 - <A_p d, r'>^2 / ||A_p d||^2,
+// so the judge is evaluated from the two sums that give alpha: it rejects a
+// correction whose sums are not finite or whose A_p d or <A_p d, r'>
+// vanishes.  Everything stays on the device (the decision is a flag read by
+// the kernel that applies the correction), so the learned stage adds no
+// host synchronisation to an FGMRES iteration.
+//
+// Per application: r' and its sums (writing the unscaled third feature
+// D^-1 r' straight into the network input; the first two features depend
+// only on the state and are written at setup), the sums' totals (s and
+// 1/s, which the first convolution applies as it loads the input), the
+// network, A_p d with its sums read from the network output in natural
+// order, alpha and the decision, and the correction.
 #include <cmath>
 
 #include "internal.h"
 
-int nn_infer(cpr_nn* nn, const float* x3, float* y);
+int nn_infer(cpr_nn* nn, const float* x3, float* y, const double* xscale);
 float* nn_output(cpr_nn* nn);
 int props_lt_plane(int model);
 
@@ -24,7 +35,7 @@ namespace {
 
 constexpr int LB = 256;
 // device scalars (ctx->nnscal)
-enum { S_MK = 0, S_SK, S_ML, S_SL, S_RMS, S_R2, S_RR2, S_ACC, S_ALPHA, S_COUNT };
+enum { S_MK = 0, S_SK, S_ML, S_SL, S_RMS, S_R2, S_RR2, S_ACC, S_ALPHA, S_INV, S_COUNT };
 
 __device__ inline double block_sum(double v, double* sh) {
 #pragma unroll
@@ -80,11 +91,13 @@ __global__ __launch_bounds__(LB) void stats_final_kernel(int n, const double* __
 }
 
 // r' = rp - A_p dp on the fine colour-split level, with block partials of
-// sum (r'/a_0)^2 and sum r'^2.  rp / dp null: r' already stored.
+// sum (r'/a_0)^2 and sum r'^2.  rp / dp null: r' already stored.  feat
+// (optional): the network input [natural cell][3], whose third channel
+// receives r'/a_0 (unscaled).
 template <typename T>
 __global__ __launch_bounds__(LB) void rprime_kernel(Lay L, const double* __restrict__ A, const T* __restrict__ rp,
                                                     const T* __restrict__ dp, double* __restrict__ rprime,
-                                                    double* __restrict__ part, int nblk) {
+                                                    double* __restrict__ part, int nblk, float* __restrict__ feat) {
   __shared__ double sh[LB / 64];
   double a = 0, b = 0;
   for (int t = blockIdx.x * LB + threadIdx.x; t < L.n; t += nblk * LB) {
@@ -105,6 +118,11 @@ __global__ __launch_bounds__(LB) void rprime_kernel(Lay L, const double* __restr
     double q = r / A[t];
     a += q * q;
     b += r * r;
+    if (feat) {
+      int i, j, k;
+      lay_coords(L, t, i, j, k);
+      feat[(i + (long)L.nx * (j + (long)L.ny * k)) * 3 + 2] = (float)q;
+    }
   }
   double s = block_sum(a, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -118,7 +136,9 @@ __global__ __launch_bounds__(LB) void rprime_final_kernel(int n, const double* _
   double a = partial_total(part, nblk, sh);
   double b = partial_total(part + nblk, nblk, sh);
   if (threadIdx.x != 0) return;
-  scal[S_RMS] = sqrt(a / n);
+  const double rms = sqrt(a / n);
+  scal[S_RMS] = rms;
+  scal[S_INV] = rms > 0 ? 1.0 / rms : 0.0;
   scal[S_R2] = b;
 }
 
@@ -138,33 +158,43 @@ __global__ __launch_bounds__(LB) void features_kernel(Lay L, const double* __res
   feat[nat * 3 + 2] = s > 0 ? (float)((rprime[t] / A[t]) / s) : 0.f;
 }
 
-// network direction d back in colour-split order
-__global__ __launch_bounds__(LB) void dir_kernel(Lay L, const float* __restrict__ y, double* __restrict__ d) {
+// The two state features of the network input (channels 0 and 1).
+__global__ __launch_bounds__(LB) void state_features_kernel(Lay L, const double* __restrict__ lnk,
+                                                            const double* __restrict__ lt,
+                                                            const double* __restrict__ scal, float* __restrict__ feat) {
   int t = blockIdx.x * LB + threadIdx.x;
   if (t >= L.n) return;
   int i, j, k;
   lay_coords(L, t, i, j, k);
-  d[t] = (double)y[i + (long)L.nx * (j + (long)L.ny * k)];
+  long nat = i + (long)L.nx * (j + (long)L.ny * k);
+  feat[nat * 3 + 0] = (float)((lnk[t] - scal[S_MK]) / scal[S_SK]);
+  feat[nat * 3 + 1] = (float)((log(lt[t]) - scal[S_ML]) / scal[S_SL]);
 }
 
-// q = A_p d, with block partials of <q, r'> and <q, q>
+// q = A_p d for the network output d (FP32, natural order), with block
+// partials of <q, r'> and <q, q>.
 __global__ __launch_bounds__(LB) void apply_dir_kernel(Lay L, const double* __restrict__ A,
                                                        const double* __restrict__ rprime,
-                                                       const double* __restrict__ d, double* __restrict__ q,
+                                                       const float* __restrict__ y, double* __restrict__ q,
                                                        double* __restrict__ part, int nblk) {
   __shared__ double sh[LB / 64];
+  const long sx = 1, sy = L.nx, sz = (long)L.nx * L.ny;
   double a = 0, b = 0;
   for (int t = blockIdx.x * LB + threadIdx.x; t < L.n; t += nblk * LB) {
-    CsCell cc = cs_decode(L, t);
-    double y = A[t] * d[t];
-#pragma unroll
-    for (int dd = 1; dd < 7; ++dd) {
-      int nb = cs_nb(L, cc, dd);
-      if (nb >= 0) y += A[(size_t)dd * L.n + t] * d[nb];
-    }
-    q[t] = y;
-    a += y * rprime[t];
-    b += y * y;
+    int i, j, k;
+    lay_coords(L, t, i, j, k);
+    const long nat = i + sy * j + sz * k;
+    double v = ldnt(A + t) * (double)y[nat];
+    // directions 1..6: -x, +x, -y, +y, -z, +z
+    if (i > 0) v += ldnt(A + (size_t)1 * L.n + t) * (double)y[nat - sx];
+    if (i < L.nx - 1) v += ldnt(A + (size_t)2 * L.n + t) * (double)y[nat + sx];
+    if (j > 0) v += ldnt(A + (size_t)3 * L.n + t) * (double)y[nat - sy];
+    if (j < L.ny - 1) v += ldnt(A + (size_t)4 * L.n + t) * (double)y[nat + sy];
+    if (k > 0) v += ldnt(A + (size_t)5 * L.n + t) * (double)y[nat - sz];
+    if (k < L.nz - 1) v += ldnt(A + (size_t)6 * L.n + t) * (double)y[nat + sz];
+    q[t] = v;
+    a += v * rprime[t];
+    b += v * v;
   }
   double s = block_sum(a, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -172,51 +202,34 @@ __global__ __launch_bounds__(LB) void apply_dir_kernel(Lay L, const double* __re
   if (threadIdx.x == 0) part[(size_t)nblk + blockIdx.x] = s;
 }
 
-// alpha = <q, r'> / <q, q> (0 if q vanishes or is not finite)
+// alpha = <q, r'> / <q, q> and the judge: the correction is kept when
+// ||r'||^2 - <q, r'>^2 / <q, q> < ||r'||^2 with finite sums, i.e. when q and
+// <q, r'> do not vanish.
 __global__ __launch_bounds__(LB) void alpha_kernel(const double* __restrict__ part, int nblk,
-                                                   double* __restrict__ scal) {
+                                                   double* __restrict__ scal, int* __restrict__ count) {
   __shared__ double sh[LB / 64];
   double a = partial_total(part, nblk, sh);
   double b = partial_total(part + nblk, nblk, sh);
   if (threadIdx.x != 0) return;
-  double al = (b > 0 && isfinite(a) && isfinite(b)) ? a / b : 0.0;
-  scal[S_ALPHA] = isfinite(al) ? al : 0.0;
-}
-
-// block partials of ||r' - alpha q||^2 = ||r' - A_p dp_nn||^2
-__global__ __launch_bounds__(LB) void judge_partial_kernel(int n, const double* __restrict__ rprime,
-                                                           const double* __restrict__ q,
-                                                           const double* __restrict__ scal, double* __restrict__ part,
-                                                           int nblk) {
-  __shared__ double sh[LB / 64];
-  const double al = scal[S_ALPHA];
-  double a = 0;
-  for (int t = blockIdx.x * LB + threadIdx.x; t < n; t += nblk * LB) {
-    double r = rprime[t] - al * q[t];
-    a += r * r;
-  }
-  double s = block_sum(a, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-__global__ __launch_bounds__(LB) void judge_final_kernel(const double* __restrict__ part, int nblk,
-                                                         double* __restrict__ scal, int* __restrict__ count) {
-  __shared__ double sh[LB / 64];
-  double a = partial_total(part, nblk, sh);
-  if (threadIdx.x != 0) return;
-  scal[S_RR2] = a;
-  bool accept = isfinite(a) && a < scal[S_R2];
+  const bool finite = isfinite(a) && isfinite(b) && b > 0;
+  const double al = finite ? a / b : 0.0;
+  const double rr2 = finite ? scal[S_R2] - a * al : scal[S_R2];
+  const bool accept = finite && isfinite(al) && a * al > 0;
+  scal[S_ALPHA] = accept ? al : 0.0;
+  scal[S_RR2] = rr2;
   scal[S_ACC] = accept ? 1.0 : 0.0;
   if (accept) count[0] += 1; else count[1] += 1;
 }
 
-// dp += alpha d when the judge accepted
+// dp += alpha d when the judge accepted (d: network output, natural order)
 template <typename T>
-__global__ __launch_bounds__(LB) void correct_kernel(int n, const double* __restrict__ scal,
-                                                     const double* __restrict__ d, T* __restrict__ dp) {
+__global__ __launch_bounds__(LB) void correct_kernel(Lay L, const double* __restrict__ scal,
+                                                     const float* __restrict__ y, T* __restrict__ dp) {
   int t = blockIdx.x * LB + threadIdx.x;
-  if (t >= n || !(scal[S_ACC] > 0.0)) return;
-  dp[t] = (T)((double)dp[t] + scal[S_ALPHA] * d[t]);
+  if (t >= L.n || !(scal[S_ACC] > 0.0)) return;
+  int i, j, k;
+  lay_coords(L, t, i, j, k);
+  dp[t] = (T)((double)dp[t] + scal[S_ALPHA] * (double)y[i + (long)L.nx * (j + (long)L.ny * k)]);
 }
 
 __global__ void lnk_kernel(Lay L, const double* __restrict__ perm, double* __restrict__ lnk) {
@@ -239,15 +252,18 @@ int learned_setup(cpr_ctx* ctx, bool need_nn) {
   const double* lt = ctx->props + (size_t)props_lt_plane(ctx->fl.model) * ctx->lay.n;
   stats_partial_kernel<<<ctx->nblk, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->lnk, lt, ctx->part, ctx->nblk);
   stats_final_kernel<<<1, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->part, ctx->nblk, ctx->nnscal);
+  state_features_kernel<<<div_up(ctx->lay.n, LB), LB, 0, ctx->stream>>>(ctx->lay, ctx->lnk, lt, ctx->nnscal,
+                                                                       ctx->feat);
   return launch_check(ctx, "learned_setup");
 }
 
 // r' and its norms for rp, dp of the fine level (T = preconditioner type);
 // with rp == nullptr, ctx->rprime already holds r'.
 template <typename T>
-static void rprime_launch(cpr_ctx* ctx, const T* rp, const T* dp) {
+static void rprime_launch(cpr_ctx* ctx, const T* rp, const T* dp, float* feat = nullptr) {
   const MGLevel& L0 = ctx->levels[0];
-  rprime_kernel<T><<<ctx->nblk, LB, 0, ctx->stream>>>(ctx->lay, L0.A, rp, dp, ctx->rprime, ctx->part, ctx->nblk);
+  rprime_kernel<T><<<ctx->nblk, LB, 0, ctx->stream>>>(ctx->lay, L0.A, rp, dp, ctx->rprime, ctx->part, ctx->nblk,
+                                                      feat);
   rprime_final_kernel<<<1, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->part, ctx->nblk, ctx->nnscal);
 }
 
@@ -262,17 +278,13 @@ template <typename T>
 static int learned_stage_t(cpr_ctx* ctx, const T* rp, T* dp) {
   hipStream_t s = ctx->stream;
   const Lay& L = ctx->lay;
-  rprime_launch<T>(ctx, rp, dp);
-  features_launch(ctx);
-  int rc = nn_infer(ctx->nn, ctx->feat, nullptr);
+  rprime_launch<T>(ctx, rp, dp, ctx->feat);
+  int rc = nn_infer(ctx->nn, ctx->feat, nullptr, ctx->nnscal + S_INV);
   if (rc) return set_err(ctx, rc, "network inference failed");
-  dir_kernel<<<div_up(L.n, LB), LB, 0, s>>>(L, nn_output(ctx->nn), ctx->dpnn);
-  apply_dir_kernel<<<ctx->nblk, LB, 0, s>>>(L, ctx->levels[0].A, ctx->rprime, ctx->dpnn, ctx->qbuf, ctx->part,
-                                            ctx->nblk);
-  alpha_kernel<<<1, LB, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal);
-  judge_partial_kernel<<<ctx->nblk, LB, 0, s>>>(L.n, ctx->rprime, ctx->qbuf, ctx->nnscal, ctx->part, ctx->nblk);
-  judge_final_kernel<<<1, LB, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal, ctx->nncount);
-  correct_kernel<T><<<div_up(L.n, LB), LB, 0, s>>>(L.n, ctx->nnscal, ctx->dpnn, dp);
+  const float* y = nn_output(ctx->nn);
+  apply_dir_kernel<<<ctx->nblk, LB, 0, s>>>(L, ctx->levels[0].A, ctx->rprime, y, ctx->qbuf, ctx->part, ctx->nblk);
+  alpha_kernel<<<1, LB, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal, ctx->nncount);
+  correct_kernel<T><<<div_up(L.n, LB), LB, 0, s>>>(L, ctx->nnscal, y, dp);
   return CPR_OK;
 }
 

@@ -94,6 +94,7 @@ struct ConvArgs {
   const float* head;     // fused 1x1x1 head [CO + 1] (CO = 16, KS = 1) or null
   float* y;              // head output [batch][voxel]
   float* pool;           // POOL: [batch][coarse voxel][CO]
+  const double* xscale;  // CSRC = 3: device scalar multiplying input channel 2 as it is loaded, or null
 };
 
 template <int CI, int CSRC, int CO, bool UP, int EPI, int KS, int NS, bool POOL>
@@ -137,6 +138,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs p) {
   const int sx = UP ? g.nx >> 1 : g.nx, sy = UP ? g.ny >> 1 : g.ny, sz = UP ? g.nz >> 1 : g.nz;
   const int ox = UP ? (x0 - 1) >> 1 : x0 - 1, oy = UP ? (y0 - 1) >> 1 : y0 - 1, oz = UP ? (z0 - 1) >> 1 : z0 - 1;
   const float* Xb = p.X + (long)b * sx * sy * sz * CSRC;
+  const float xs2 = (CSRC != CI && p.xscale) ? (float)*p.xscale : 1.f;
   constexpr int NQ = HV * (CI / 4);
   constexpr int NWF = NK * NTB * 64;
   for (int q0 = 0; q0 < NQ; q0 += 8 * 256) {
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs p) {
           if (CSRC == CI) {
             v[u] = *(const float4*)src;
           } else {
-            v[u].x = src[0]; v[u].y = src[1]; v[u].z = src[2];
+            v[u].x = src[0]; v[u].y = src[1]; v[u].z = src[2] * xs2;
           }
         }
       }
@@ -780,7 +782,7 @@ static void wgrad(cpr_nn* nn, Geo g, const float* X, const float* dZ, int k) {
 // x3: input features [B][voxel][3].  train: keep what the backward pass
 // needs (pre-skip activations, d0) and run the head separately; otherwise
 // only what inference needs, with the head fused into the last convolution.
-static int nn_forward_impl(cpr_nn* nn, const float* x3, int B, bool train) {
+static int nn_forward_impl(cpr_nn* nn, const float* x3, int B, bool train, const double* xscale = nullptr) {
   Geo L0 = with_batch(nn->lv[0], B), L1 = with_batch(nn->lv[1], B), L2 = with_batch(nn->lv[2], B),
       L3 = with_batch(nn->lv[3], B);
   hipStream_t s = nn->stream;
@@ -788,6 +790,7 @@ static int nn_forward_impl(cpr_nn* nn, const float* x3, int B, bool train) {
   const float* head = nn->theta + nn->off[NCONV];
   ConvArgs a = cargs(L0, x3, nn->wf[0], bias(0), nullptr, nn->e0, nullptr);
   a.pool = nn->p1;
+  a.xscale = xscale;
   conv<4, 3, 16, false, 1, true>(nn, a);
   a = cargs(L1, nn->p1, nn->wf[1], bias(1), nullptr, nn->e1, nullptr);
   a.pool = nn->p2;
@@ -907,13 +910,14 @@ static void nn_free(cpr_nn* nn) {
   }
 }
 
-// Internal use by the solver's learned stage (apply.hip).
-int nn_infer(cpr_nn* nn, const float* x3, float* y);
+// Internal use by the solver's learned stage: x3's third channel is
+// multiplied by *xscale (device scalar) as the network loads it.
+int nn_infer(cpr_nn* nn, const float* x3, float* y, const double* xscale);
 float* nn_output(cpr_nn* nn) { return nn->y; }
 
-int nn_infer(cpr_nn* nn, const float* x3, float* y) {
+int nn_infer(cpr_nn* nn, const float* x3, float* y, const double* xscale) {
   long n0 = nn->lv[0].V;
-  int rc = nn_forward_impl(nn, x3, 1, false);
+  int rc = nn_forward_impl(nn, x3, 1, false, xscale);
   if (rc) return rc;
   if (y && y != nn->y) NN_TRY(hipMemcpyAsync(y, nn->y, n0 * sizeof(float), hipMemcpyDeviceToDevice, nn->stream));
   return CPR_OK;
@@ -1004,7 +1008,7 @@ int cpr_nn_forward(cpr_nn_t* nn, const float* x, int batch, float* y) {
 int cpr_nn_infer(cpr_nn_t* nn, const float* x, float* y) {
   if (!nn || !x || !y) return CPR_EINVAL;
   if (!nn->frags_valid) return nn_err(nn, CPR_EINVAL, "parameters not set");
-  return nn_infer(nn, x, y);
+  return nn_infer(nn, x, y, nullptr);
 }
 
 int cpr_nn_backward(cpr_nn_t* nn, const float* dy, float* grad) {

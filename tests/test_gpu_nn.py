@@ -162,6 +162,41 @@ def test_pressure_stage_and_features_match_oracle():
     assert np.allclose(f_g.cpu().numpy(), f_o, rtol=1e-5, atol=1e-5)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_learned_cpr_apply_matches_oracle(precision):
+    # One CPR application with the learned stage against the oracle's: the
+    # network runs in BF16 on the GPU and in FP64 in the oracle, so only the
+    # network's correction (z_learned - z_plain) carries the network
+    # tolerance; everything else is FP64 (or the FP32 preconditioner).
+    from paper_1606_00548_amd import cprmi
+    case = _ow_case()
+    theta = _theta(9)
+    s = cprmi.Solver.from_case(case)
+    s.assemble(torch.as_tensor(case["x_old"]).cuda(), torch.as_tensor(case["x"]).cuda(), case["dt"])
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                          case["x_old"], case["x"], case["dt"])
+    pc = cpr.cpr_setup(J)
+    b = -R
+    v = b / np.linalg.norm(b)
+    lam = learned.total_mobility(case["fluid"], case["poro"], case["x"])
+    z_o, acc = learned.learned_cpr_apply(pc, v, theta, case["perm"], lam)
+    z_p = cpr.cpr_apply(pc, v)
+    s.attach_network(theta.astype(np.float32))
+    s.setup(learned=1, precision=precision)
+    z_g = s.precond(torch.as_tensor(v).cuda().contiguous()).cpu().numpy()
+    corr = np.linalg.norm(z_o - z_p)
+    err = np.linalg.norm(z_g - z_o)
+    base = 1e-9 if precision == "fp64" else 1e-4
+    print(f"[learned] {precision} apply: accepted {acc}, |correction| {corr:.3e}, |gpu - oracle| {err:.3e}")
+    assert acc and corr > 1e-3 * np.linalg.norm(z_p)
+    assert err <= 3e-2 * corr + base * np.linalg.norm(z_o)
+    # a network that outputs zero is rejected: plain CPR is what remains
+    s.attach_network(np.zeros(nn.num_params(), np.float32))
+    s.setup(learned=1, precision=precision)
+    z0 = s.precond(torch.as_tensor(v).cuda().contiguous()).cpu().numpy()
+    assert np.linalg.norm(z0 - z_p) <= base * np.linalg.norm(z_p)
+
+
 def test_learned_solve_keeps_accuracy_and_counts_decisions():
     from paper_1606_00548_amd import cprmi
     case = _ow_case()

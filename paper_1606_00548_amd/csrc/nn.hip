@@ -112,7 +112,11 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs p) {
   constexpr int NT = CO / 16;          // N-blocks of the whole convolution
   constexpr int COB = CO / NS;         // output channels of this workgroup
   constexpr int NTB = COB / 16;
-  constexpr int HALO_BYTES = HV * CI * 2;
+  // halo voxel stride in BF16 values: padded by 16 bytes for CI >= 16 so
+  // that 16 lanes reading 16 bytes of 16 neighbouring voxels hit distinct banks
+  constexpr int CST = CI >= 16 ? CI + 8 : CI;
+  constexpr int VB = CST * 2;
+  constexpr int HALO_BYTES = HV * VB;
   constexpr int W_BYTES = NK * NTB * 64 * 16;
   constexpr int RED_BYTES = KS > 1 ? KS * 64 * COB * 4 : 0;
   constexpr int POOL_BYTES = POOL ? 64 * COB * 4 : 0;
@@ -165,7 +169,8 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs p) {
     for (int u = 0; u < 8; ++u) {
       const int q = q0 + u * 256 + threadIdx.x;
       if (q < NQ)
-        *(uint2*)(smem + (size_t)q * 8) = make_uint2(pack_bf16x2(v[u].x, v[u].y), pack_bf16x2(v[u].z, v[u].w));
+        *(uint2*)(smem + (size_t)(q / (CI / 4)) * VB + (q % (CI / 4)) * 8) =
+            make_uint2(pack_bf16x2(v[u].x, v[u].y), pack_bf16x2(v[u].z, v[u].w));
     }
   }
   for (int q0 = 0; q0 < NWF; q0 += 8 * 256) {
@@ -188,41 +193,103 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs p) {
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i16 = lane & 15, kq = lane >> 4;
   const int lz = KS == 1 ? wave : 0;
-  // halo index of the input under output voxel (i16, m, lz) for tap t
-  auto hpos = [&](int t, int m) -> int {
-    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-    if (UP)
-      return (((x0 + i16 + dx) >> 1) - ox) + HX * ((((y0 + m + dy) >> 1) - oy) + HY * (((z0 + lz + dz) >> 1) - oz));
-    return (i16 + dx + 1) + HX * ((m + dy + 1) + HY * (lz + dz + 1));
-  };
+  // Byte address in the halo of the input under output voxel (i16, m, lz)
+  // at tap (dx, dy, dz) = per-lane part + a part known at compile time once
+  // the K loop is unrolled (folded into the LDS instructions' offsets).
+  // Same grid: (i16 + 1 + dx) + HX (m + 1 + dy) + HX HY (lz + 1 + dz).
+  // UP (x0, y0 multiples of 16 and 4): ((i16 + dx) >> 1) + 1 along x,
+  // ((m + dy) >> 1) + 1 along y, and ((z0 + lz + dz) >> 1) - ((z0 - 1) >> 1)
+  // along z, which depends on z0 and is uniform over the wave.
+  const int lane_chunk = CI >= 32 ? 16 * kq : (CI == 16 ? 16 * (kq & 1) : 0);
+  int base = 0;            // same grid
+  int upb[3][3] = {};      // UP: [dx + 1][dz + 1]
+  if constexpr (UP) {
+#pragma unroll
+    for (int ddx = 0; ddx < 3; ++ddx)
+#pragma unroll
+      for (int ddz = 0; ddz < 3; ++ddz) {
+        const int zc = ((z0 + lz + ddz - 1) >> 1) - oz;
+        upb[ddx][ddz] = ((((i16 + ddx - 1) >> 1) + 1) + HX * HY * zc) * VB + lane_chunk;
+      }
+  } else {
+    base = ((i16 + 1) + HX + HX * HY * (lz + 1)) * VB + lane_chunk;
+  }
   f32x4 acc[4][NTB];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int n = 0; n < NTB; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int ks = (KS == 1 ? 0 : wave); ks < NK; ks += KS) {
+  // same-grid tap offset (bytes) relative to base, m = 0
+  auto toff = [](int t) { return ((t % 3 - 1) + HX * ((t / 3) % 3 - 1) + HX * HY * (t / 9 - 1)) * VB; };
+  if constexpr (CI >= 32) {
+    // K-steps grouped by (dz, dx, channel chunk): the three dy taps of a
+    // group read the same input rows, so the wave loads each row's A
+    // fragment once (6 rows of the tile plus halo, or 4 half-resolution
+    // rows when UP) and the three B-fragments, then issues 12 MFMA per
+    // N-block.  Groups are split over the waves when KS = 4.
+    constexpr int NCH = CI / 32;
+    constexpr int NR = UP ? 4 : 6;
+#pragma unroll
+    for (int grp = 0; grp < 9 * NCH; ++grp) {
+      if (KS > 1 && (grp % KS) != wave) continue;
+      const int kc = grp % NCH, dx = (grp / NCH) % 3 - 1, dz = grp / (3 * NCH) - 1;
+      bf16x8 bw[3][NTB];
+#pragma unroll
+      for (int ddy = 0; ddy < 3; ++ddy)
+#pragma unroll
+        for (int n = 0; n < NTB; ++n)
+          bw[ddy][n] = wl[((size_t)(((dz + 1) * 9 + ddy * 3 + (dx + 1)) * NCH + kc) * NTB + n) * 64 + lane];
+      bf16x8 ar[NR];
+#pragma unroll
+      for (int yy = 0; yy < NR; ++yy) {
+        int addr;
+        if constexpr (UP)
+          addr = upb[dx + 1][dz + 1] + HX * yy * VB + kc * 64;
+        else
+          addr = base + (dx + HX * HY * dz) * VB + HX * (yy - 1) * VB + kc * 64;
+        ar[yy] = __builtin_bit_cast(bf16x8, *(const uint4*)(smem + addr));
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int ddy = 0; ddy < 3; ++ddy) {
+          const int yy = UP ? ((m + ddy - 1) >> 1) + 1 : m + ddy;
+#pragma unroll
+          for (int n = 0; n < NTB; ++n)
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[yy], bw[ddy][n], acc[m][n], 0, 0, 0);
+        }
+    }
+  } else {
+#pragma unroll
+  for (int ks = 0; ks < NK; ++ks) {
+    if (KS > 1 && (ks % KS) != wave) continue;
     bf16x8 bw[NTB];
 #pragma unroll
     for (int n = 0; n < NTB; ++n) bw[n] = wl[((size_t)ks * NTB + n) * 64 + lane];
+    int sel0 = 0, sel1 = 0;     // per-lane tap offsets of this step
+    if constexpr (CI == 16) {
+      sel0 = (kq >> 1) ? toff(min(2 * ks + 1, 26)) : toff(2 * ks);
+    } else {
+      const int ta[4] = {min(8 * ks, 26), min(8 * ks + 2, 26), min(8 * ks + 4, 26), min(8 * ks + 6, 26)};
+      const int tb[4] = {min(8 * ks + 1, 26), min(8 * ks + 3, 26), min(8 * ks + 5, 26), min(8 * ks + 7, 26)};
+      sel0 = kq == 0 ? toff(ta[0]) : kq == 1 ? toff(ta[1]) : kq == 2 ? toff(ta[2]) : toff(ta[3]);
+      sel1 = kq == 0 ? toff(tb[0]) : kq == 1 ? toff(tb[1]) : kq == 2 ? toff(tb[2]) : toff(tb[3]);
+    }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       uint4 raw;
-      if constexpr (CI >= 32) {
-        const int t = ks / (CI / 32), kc = ks % (CI / 32);
-        raw = *(const uint4*)(smem + ((size_t)hpos(t, m) * CI + kc * 32 + 8 * kq) * 2);
-      } else if constexpr (CI == 16) {
-        const int t = min(2 * ks + (kq >> 1), 26);
-        raw = *(const uint4*)(smem + ((size_t)hpos(t, m) * 16 + (kq & 1) * 8) * 2);
+      if constexpr (CI == 16) {
+        raw = *(const uint4*)(smem + base + sel0 + HX * m * VB);
       } else {
-        const int t0 = min(8 * ks + 2 * kq, 26), t1 = min(8 * ks + 2 * kq + 1, 26);
-        const uint2 lo = *(const uint2*)(smem + (size_t)hpos(t0, m) * 8);
-        const uint2 hi = *(const uint2*)(smem + (size_t)hpos(t1, m) * 8);
+        const uint2 lo = *(const uint2*)(smem + base + sel0 + HX * m * VB);
+        const uint2 hi = *(const uint2*)(smem + base + sel1 + HX * m * VB);
         raw = make_uint4(lo.x, lo.y, hi.x, hi.y);
       }
       const bf16x8 a = __builtin_bit_cast(bf16x8, raw);
 #pragma unroll
       for (int n = 0; n < NTB; ++n) acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[n], acc[m][n], 0, 0, 0);
     }
+  }
   }
 
   const long V = g.V;

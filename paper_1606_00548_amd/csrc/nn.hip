@@ -214,6 +214,24 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs p) {
   } else {
     base = ((i16 + 1) + HX + HX * HY * (lz + 1)) * VB + lane_chunk;
   }
+  // KS = 1 with a skip input: its values for this wave's outputs are loaded
+  // before the K loop so that their latency hides behind the MFMAs
+  const long V = g.V;
+  const int c0 = nb * COB;
+  float skv[KS == 1 && EPI == 1 ? 4 : 1][4][NTB];
+  if constexpr (KS == 1 && EPI == 1) {
+    const bool has_skip = p.skip != nullptr;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int x = x0 + 4 * kq + e, y = y0 + m, z = z0 + lz;
+        const bool ok = has_skip && x < g.nx && y < g.ny && z < g.nz;
+        const long o = (long)b * V + x + (long)g.nx * (y + (long)g.ny * z);
+#pragma unroll
+        for (int n = 0; n < NTB; ++n) skv[m][e][n] = ok ? p.skip[o * CO + c0 + n * 16 + i16] : 0.f;
+      }
+  }
   f32x4 acc[4][NTB];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
@@ -292,8 +310,6 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs p) {
   }
   }
 
-  const long V = g.V;
-  const int c0 = nb * COB;
   if constexpr (KS == 1) {
     // C element (row 4*kq + e, column i16) of M-block m, N-block n is
     // voxel (x0 + 4*kq + e, y0 + m, z0 + lz), channel c0 + n*16 + i16
@@ -305,27 +321,29 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs p) {
         const int x = x0 + 4 * kq + e;
         const bool ok = x < g.nx && y < g.ny && z < g.nz;
         const long o = (long)b * V + x + (long)g.nx * (y + (long)g.ny * z);
-        if (CO == 16 && p.head) {
-          // y = sum_c head[c] (relu(acc + bias) + skip)[c] + head[CO]
-          const float a = fmaxf(acc[m][0][e] + p.bias[i16], 0.f) + (ok ? p.skip[o * CO + i16] : 0.f);
-          float h = a * p.head[i16];
-          h += __shfl_xor(h, 8, 16);
-          h += __shfl_xor(h, 4, 16);
-          h += __shfl_xor(h, 2, 16);
-          h += __shfl_xor(h, 1, 16);
-          if (ok && i16 == 0) p.y[o] = h + p.head[CO];
-          continue;
+        if constexpr (EPI == 1 && CO == 16) {
+          if (p.head) {
+            // y = sum_c head[c] (relu(acc + bias) + skip)[c] + head[CO]
+            const float a = fmaxf(acc[m][0][e] + p.bias[i16], 0.f) + skv[m][e][0];
+            float h = a * p.head[i16];
+            h += __shfl_xor(h, 8, 16);
+            h += __shfl_xor(h, 4, 16);
+            h += __shfl_xor(h, 2, 16);
+            h += __shfl_xor(h, 1, 16);
+            if (ok && i16 == 0) p.y[o] = h + p.head[CO];
+            continue;
+          }
         }
 #pragma unroll
         for (int n = 0; n < NTB; ++n) {
           const int co = c0 + n * 16 + i16;
           float val = acc[m][n][e];
-          if (EPI == 1) {
+          if constexpr (EPI == 1) {
             val = fmaxf(val + p.bias[co], 0.f);
             acc[m][n][e] = val;
             if (!ok) continue;
             if (p.outA) p.outA[o * CO + co] = val;
-            if (p.skip) p.outD[o * CO + co] = val + p.skip[o * CO + co];
+            if (p.skip) p.outD[o * CO + co] = val + skv[m][e][n];
           } else if (ok) {
             p.outA[o * CO + co] = val;
           }

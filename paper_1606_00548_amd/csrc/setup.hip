@@ -214,119 +214,97 @@ __global__ void gj_step_kernel(int nc, int p, const double* __restrict__ src, do
 }
 
 // Whole Gauss-Jordan inversion (partial pivoting, in place) of a small
-// coarsest operator in one workgroup with the matrix held in registers
-// (nc <= 128): thread (r = tid / 8, g = tid % 8) owns row r, columns
-// 16 g .. 16 g + 15 of the matrix padded with zeros to 128 x 128 (the
-// padding never pivots and is never changed, so no step needs a bounds
-// test).  Each pivot step publishes column p, lets every wave pick the
-// pivot row (largest |m_qp|, p <= q < nc, lowest row on ties), publishes
-// the pivot row and old row p, and updates every row; the per-step buffers
-// alternate so two barriers per step suffice.  Row interchanges are undone
-// as column interchanges when the inverse is written (column major, and as
-// FP32).  The dense matrix is built from the level's 7-point stencil.
+// coarsest operator in one workgroup with the matrix held in LDS (nc <= 128).
+// Thread layout: row r = tid / 8, columns lane + 8 q; rows are padded to an
+// odd stride so the 8 rows a wavefront touches fall in different banks.  The
+// dense matrix is built from the level's 7-point stencil; the inverse is
+// written column major (and as FP32).
 constexpr int GJ_LDS_MAX = 128;
 
 __global__ __launch_bounds__(1024) void gj_lds_kernel(Lay L, const double* __restrict__ A,
                                                       double* __restrict__ inv, float* __restrict__ invf,
                                                       int* __restrict__ flag) {
-  __shared__ __align__(16) double fcol[2][GJ_LDS_MAX];
-  __shared__ __align__(16) double prow[2][GJ_LDS_MAX];   // row pr (becomes the pivot row)
-  __shared__ __align__(16) double oldp[2][GJ_LDS_MAX];   // row p (moves to row pr)
-  __shared__ int piv[GJ_LDS_MAX];
-  __shared__ int pos[GJ_LDS_MAX];
+  extern __shared__ double sm[];
   const int nc = L.n;
-  const int tid = threadIdx.x, r = tid >> 3, g = tid & 7, lane = tid & 63;
-  const int c0 = 16 * g;
-  double a[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) a[q] = 0.0;
-  if (r < nc) {
+  const int ld = nc + 8;          // 8 consecutive rows then start in different LDS banks
+  double* M = sm;                 // nc rows of stride ld
+  double* fcol = sm + nc * ld;    // multipliers of the current column
+  __shared__ int piv[GJ_LDS_MAX];
+  __shared__ double pvs;
+  __shared__ int prs;
+  const int tid = threadIdx.x;
+  const int r = tid >> 3, lane = tid & 7;
+  const bool own = r < nc;
+  if (own)
+    for (int c = lane; c < nc; c += 8) M[r * ld + c] = 0.0;
+  __syncthreads();
+  if (own && lane == 0) {
     int i, j, k;
     lay_coords(L, r, i, j, k);
-    for (int d = 0; d < 7; ++d) {
-      const int col = d == 0 ? r : lay_nbr(L, i, j, k, d);
-      if (col < 0 || (col >> 4) != g) continue;
-      const double v = A[(size_t)d * nc + r];
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (q == (col & 15)) a[q] += v;
+    M[r * ld + r] += A[r];
+    for (int d = 1; d < 7; ++d) {
+      int nb = lay_nbr(L, i, j, k, d);
+      if (nb >= 0) M[r * ld + nb] += A[(size_t)d * nc + r];
     }
   }
+  __syncthreads();
   for (int p = 0; p < nc; ++p) {
-    const int buf = p & 1;
-    if (g == (p >> 4)) {
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (q == (p & 15)) v = a[q];
-      fcol[buf][r] = v;
-    }
-    __syncthreads();
-    double best = -1.0;
-    int bi = p;
-    for (int q = p + lane; q < nc; q += 64) {
-      const double v = fabs(fcol[buf][q]);
-      if (v > best) { best = v; bi = q; }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_down(best, o, 64);
-      const int oi = __shfl_down(bi, o, 64);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
-    const int pr = __shfl(bi, 0, 64);
-    if (tid == 0) {
-      piv[p] = pr;
-      if (!(best > TINY) || !isfinite(best)) atomicExch(flag, 1);
-    }
-    if (r == pr) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) prow[buf][c0 + q] = a[q];
-    }
-    if (r == p) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) oldp[buf][c0 + q] = a[q];
-    }
-    __syncthreads();
-    const double pinv = 1.0 / fcol[buf][pr];
-    double f = fcol[buf][r];
-    if (r == pr && r != p) {   // row pr receives old row p
-      f = oldp[buf][p];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) a[q] = oldp[buf][c0 + q];
-    }
-    const bool pivot_row = r == p;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = c0 + q;
-      const double np = (c == p ? 1.0 : prow[buf][c]) * pinv;
-      a[q] = pivot_row ? np : (c == p ? 0.0 : a[q]) - f * np;
-    }
-  }
-  // undo the row interchanges as column interchanges, last first: column c
-  // of the inverse is column idx[c] of the eliminated matrix
-  __syncthreads();
-  if (tid == 0) {
-    int* idx = (int*)&fcol[0][0];   // nc ints fit in the (now unused) buffer
-    for (int c = 0; c < nc; ++c) idx[c] = c;
-    for (int p = nc - 1; p >= 0; --p) {
-      const int q = piv[p];
-      const int t = idx[p]; idx[p] = idx[q]; idx[q] = t;
-    }
-    for (int c = 0; c < nc; ++c) pos[idx[c]] = c;
-  }
-  __syncthreads();
-  if (r < nc) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = c0 + q;
-      if (c < nc) {
-        const size_t o = (size_t)pos[c] * nc + r;
-        inv[o] = a[q];
-        if (invf) invf[o] = (float)a[q];
+    if (tid < 64) {   // pivot: largest |M[q][p]|, q >= p, lowest row on ties
+      double best = -1.0;
+      int bi = p;
+      for (int q = p + tid; q < nc; q += 64) {
+        double v = fabs(M[q * ld + p]);
+        if (v > best) { best = v; bi = q; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        double ov = __shfl_down(best, o, 64);
+        int oi = __shfl_down(bi, o, 64);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if (tid == 0) {
+        prs = bi;
+        pvs = M[bi * ld + p];
+        piv[p] = bi;
+        if (!(best > TINY) || !isfinite(best)) atomicExch(flag, 1);
       }
     }
+    __syncthreads();
+    const int pr = prs;
+    const double pinv = 1.0 / pvs;
+    // one thread per column interchanges rows p and pr and scales the new
+    // pivot row (diagonal set to 1 first); other threads collect the
+    // multipliers of column p for the rows the interchange does not touch
+    if (tid < nc) {
+      const int c = tid;
+      double top = M[pr * ld + c], old = M[p * ld + c];
+      if (pr != p) M[pr * ld + c] = old;
+      M[p * ld + c] = (c == p ? 1.0 : top) * pinv;
+      if (c == p) { fcol[p] = 0.0; fcol[pr] = pr == p ? 0.0 : old; }
+    } else if (tid >= 512 && tid - 512 < nc) {
+      const int q = tid - 512;
+      if (q != p && q != pr) fcol[q] = M[q * ld + p];
+    }
+    __syncthreads();
+    if (own && r != p) {
+      const double f = fcol[r];
+      for (int c = lane; c < nc; c += 8) M[r * ld + c] = (c == p ? 0.0 : M[r * ld + c]) - f * M[p * ld + c];
+    }
+    __syncthreads();
   }
+  // undo the row interchanges as column interchanges, last first
+  for (int p = nc - 1; p >= 0; --p) {
+    int q = piv[p];
+    if (q != p && own && lane == 0) {
+      double t = M[r * ld + p]; M[r * ld + p] = M[r * ld + q]; M[r * ld + q] = t;
+    }
+    __syncthreads();
+  }
+  if (own)
+    for (int c = lane; c < nc; c += 8) {
+      double v = M[r * ld + c];
+      inv[(size_t)c * nc + r] = v;
+      if (invf) invf[(size_t)c * nc + r] = (float)v;
+    }
 }
 
 // Copy the right half of [I | M^-1] into column-major storage.
@@ -474,7 +452,14 @@ int setup_cpr(cpr_ctx* ctx) {
   const MGLevel& last = ctx->levels.back();
   int nc = last.lay.n;
   if (nc <= GJ_LDS_MAX) {
-    gj_lds_kernel<<<1, 1024, 0, s>>>(last.lay, last.A, ctx->cinv, ctx->cinvf, ctx->flag);
+    size_t smem = ((size_t)nc * (nc + 8) + nc) * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+      CPR_TRY(hipFuncSetAttribute((const void*)gj_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(((size_t)GJ_LDS_MAX * (GJ_LDS_MAX + 8) + GJ_LDS_MAX) * sizeof(double))));
+      attr_set = true;
+    }
+    gj_lds_kernel<<<1, 1024, smem, s>>>(last.lay, last.A, ctx->cinv, ctx->cinvf, ctx->flag);
   } else {
     double* bufA = ctx->gj_work;
     double* bufB = ctx->gj_work + (size_t)nc * 2 * nc;

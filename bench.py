@@ -27,15 +27,17 @@ METRIC = "CPR-GMRES s/Newton step + GB/s at 1e-6 rel resid; plain FP64 vs mixed+
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision):
-    """Bytes one launch of a kernel class must move at minimum, summed over
-    the launches of one Newton step (iterations_per_cycle: Arnoldi steps of
-    each restart cycle; the SpMV also runs once per cycle for the true
-    residual, which reads the right-hand side as well)."""
+def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision, levels=None):
+    """Bytes the launches of one kernel class in one Newton step must move at
+    minimum (every array element touched once per launch, FP64), and the
+    number of those launches.  iterations_per_cycle: Arnoldi steps of each
+    restart cycle; levels: cell counts of the multigrid levels."""
     s = 8
+    its = sum(iterations_per_cycle)
     if kclass == "spmv":
+        # 7 b x b blocks + x + y per cell; once per cycle also the true
+        # residual, which reads the right-hand side as well
         per = (7 * b * b + 2 * b) * s * n
-        its = sum(iterations_per_cycle)
         return its * per + len(iterations_per_cycle) * (per + b * s * n), its + len(iterations_per_cycle)
     if kclass == "orth":
         tot, launches = 0, 0
@@ -47,6 +49,27 @@ def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision):
                 tot += ((nv + 1) + (nv + 2) + (nv + 2)) * b * n * s
                 launches += 3
         return tot, launches
+    if kclass == "smooth":
+        # red-black Gauss-Seidel half-sweeps on the levels smoothed by
+        # multi-block kernels (those above the first level of <= 4096 cells):
+        # black pre-sweep 11 values per black cell (7 stencil, r, x, res, red x),
+        # black post-sweep 10 + coarse correction n/8, red sweep 10, red
+        # zero-guess sweep 3 (levels below the fine one; the fine one is fused
+        # with the decoupling)
+        down = next((l for l, nl in enumerate(levels) if nl <= 4096), len(levels) - 1)
+        per, launches = 0, 0
+        for l in range(down):
+            nl = levels[l]
+            per += (44 + 41 + 40) * nl + (12 * nl if l > 0 else 0)
+            launches += 3 + (1 if l > 0 else 0)
+        return its * per, its * launches
+    if kclass == "ilu":
+        # stage-2 residual and red-black block ILU(0) sweeps, per cell of a
+        # colour: red forward b^2 + 9b values, black 7b^2 + 5b, red backward
+        # 7b^2 + 3b + 1, plus the pressure correction dp once per sweep
+        nh = n // 2
+        per = nh * s * ((b * b + 9 * b) + (7 * b * b + 5 * b) + (7 * b * b + 3 * b + 1)) + 2 * n * s
+        return its * per, 3 * its
     raise ValueError(kclass)
 
 
@@ -144,7 +167,7 @@ def main():
     # restart-cycle lengths of the timed solves (identical every step)
     its, cycles = st["iterations"], st["cycles"]
     per_cycle = [30] * (cycles - 1) + [its - 30 * (cycles - 1)] if cycles else []
-    alg_bytes, alg_launches = algorithmic_bytes(args.kernel, b, n, per_cycle, args.precision)
+    alg_bytes, alg_launches = algorithmic_bytes(args.kernel, b, n, per_cycle, args.precision)  # spmv / orth
     avg_ms = kernel_ms / max(launches, 1)
     achieved = (alg_bytes / alg_launches) / (avg_ms * 1e-3) / 1e9 if launches else None
     traffic = None
@@ -161,6 +184,41 @@ def main():
     if launches != alg_launches * args.steps:
         roofline["note"] = f"sampled {launches} launches, expected {alg_launches * args.steps}"
 
+    # achieved bandwidth of each bandwidth-bound kernel class (FP64 form)
+    levels = []
+    while solver.mg_level_shape(len(levels)) is not None:
+        levels.append(int(np.prod(solver.mg_level_shape(len(levels)))))
+    classes = {}
+    for cls in ("spmv", "orth", "smooth", "ilu"):
+        _, _, (nl, ms) = timed(cprmi.default_options(precision="fp64"), cls)
+        ab, al = algorithmic_bytes(cls, b, n, per_cycle, "fp64", levels)
+        gbs = ab * args.steps / (ms * 1e-3) / 1e9 if ms > 0 else None
+        classes[cls] = {"launches_per_step": nl / args.steps, "expected_launches_per_step": al,
+                        "ms_per_step": ms / args.steps, "avg_launch_us": 1e3 * ms / max(nl, 1),
+                        "algorithmic_bytes_per_step": ab, "GBps": gbs,
+                        "frac": gbs / HBM_PEAK_GBS if gbs else None}
+
+    # measured HBM bandwidth on this device: STREAM triad a = b + 3 c over
+    # 3 x 1 GiB FP64 arrays (torch elementwise kernel), best of 5
+    ta = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    tb = torch.ones_like(ta)
+    tc = torch.ones_like(ta)
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.add(tb, tc, alpha=3.0, out=ta)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3
+        best = t if best is None else min(best, t)
+    triad_gbs = 3 * ta.numel() * 8 / best / 1e9
+    del ta, tb, tc
+    roofline["measured_triad_GBps"] = triad_gbs
+    roofline["frac_of_measured_triad"] = (achieved / triad_gbs) if achieved else None
+    for v in classes.values():
+        v["frac_of_measured_triad"] = v["GBps"] / triad_gbs if v["GBps"] else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(case)
@@ -174,7 +232,8 @@ def main():
                                f"({n} cells, 3x3 blocks), one Newton step, FGMRES(30) to 1e-6",
                    "cells": n, "block": b, "precision": args.precision, "restart": 30, "rtol": 1e-6},
         "fgmres_iterations": its, "restart_cycles": cycles, "true_rel": st["true_rel"],
-        "phases_ms": phases, "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+        "phases_ms": phases, "roofline": roofline, "kernel_classes": classes, "cpu_baseline": cpu,
+        "variants": variants,
     }
     print(json.dumps(out))
 

@@ -191,9 +191,23 @@ def main():
     ap.add_argument("--eval-seeds", type=int, default=8)
     ap.add_argument("--out", default=None, help="parameter file (default: the family's shipped file)")
     ap.add_argument("--report", default=None)
+    ap.add_argument("--eval-only", action="store_true",
+                    help="evaluate the parameters in --out (default: the shipped file) without training")
     args = ap.parse_args()
     fam = FAMILIES[args.family]
     out = args.out or weights_path(args.family)
+    if args.eval_only:
+        theta = np.load(out)
+        ex, ey, ez = fam["eval_shape"]
+        rows = []
+        for prec in ("fp64", "mixed"):
+            rows += [dict(r, precision=prec) for r in evaluate(
+                theta, [fam["eval_seed0"] + i for i in range(args.eval_seeds)], shape=(ex, ey, ez),
+                family=args.family, precision=prec, log=lambda m: print(m, flush=True))]
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump({"family": args.family, "weights": os.path.basename(out), "eval": rows}, f, indent=1)
+        return
     X, T = make_dataset(args.systems, args.per_system, fam["shape"], fam["seed0"], family=args.family,
                         log=lambda m: print(m, flush=True))
     pairs = int(X.shape[0])

@@ -48,6 +48,11 @@ void free_all(cpr_ctx* ctx) {
     if (b) hipFree(b);
   if (ctx->hhost) hipHostFree(ctx->hhost);
   for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
+  for (hipEvent_t e : {ctx->ev_q, ctx->ev_rap, ctx->ev_gj})
+    if (e) hipEventDestroy(e);
+  ctx->ev_q = ctx->ev_rap = ctx->ev_gj = nullptr;
+  if (ctx->aux) hipStreamDestroy(ctx->aux);
+  ctx->aux = nullptr;
   if (ctx->nn) cpr_nn_destroy(ctx->nn);
   ctx->nn = nullptr;
   ctx->ev.clear();
@@ -78,6 +83,10 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
   if (f->model == CPR_MODEL_BLACK_OIL && (!f->pvt || f->n_pvt < 2 || f->n_pvt > CPR_MAX_PVT))
     return set_err(ctx, CPR_EINVAL, "black oil needs a PVT table with 2..16 nodes");
   ctx->stream = (hipStream_t)stream;
+  CPR_TRY(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+  CPR_TRY(hipEventCreateWithFlags(&ctx->ev_q, hipEventDisableTiming));
+  CPR_TRY(hipEventCreateWithFlags(&ctx->ev_rap, hipEventDisableTiming));
+  CPR_TRY(hipEventCreateWithFlags(&ctx->ev_gj, hipEventDisableTiming));
   ctx->grid = *g;
   ctx->b = f->model;
   FluidDev& fl = ctx->fl;

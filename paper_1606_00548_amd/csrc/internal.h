@@ -164,6 +164,10 @@ struct MGLevel {
 struct cpr_ctx {
   std::string err;
   hipStream_t stream = nullptr;
+  // setup runs the Galerkin chain and the coarsest inverse on a second
+  // stream (default priority) while the ILU factorisation runs on `stream`
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_q = nullptr, ev_rap = nullptr, ev_gj = nullptr;
   cpr_grid_t grid;
   FluidDev fl;
   int b = 0;

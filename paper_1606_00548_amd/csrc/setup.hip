@@ -443,11 +443,17 @@ int setup_cpr(cpr_ctx* ctx) {
     qimpes_kernel<2><<<nb, 256, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
   else
     qimpes_kernel<3><<<nb, 256, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
+  // Galerkin chain and coarsest inverse on the auxiliary stream, the ILU
+  // factorisation meanwhile on the caller's stream
+  hipStream_t a = ctx->aux;
+  CPR_TRY(hipEventRecord(ctx->ev_q, s));
+  CPR_TRY(hipStreamWaitEvent(a, ctx->ev_q, 0));
   for (size_t l = 0; l + 1 < ctx->levels.size(); ++l) {
     const MGLevel& F = ctx->levels[l];
     MGLevel& C = ctx->levels[l + 1];
-    rap_kernel<<<div_up(C.lay.n, 256), 256, 0, s>>>(F.lay, C.lay, F.A, C.A);
+    rap_kernel<<<div_up(C.lay.n, 256), 256, 0, a>>>(F.lay, C.lay, F.A, C.A);
   }
+  CPR_TRY(hipEventRecord(ctx->ev_rap, a));
   // dense inverse of the coarsest level
   const MGLevel& last = ctx->levels.back();
   int nc = last.lay.n;
@@ -459,19 +465,20 @@ int setup_cpr(cpr_ctx* ctx) {
                                   (int)(((size_t)GJ_LDS_MAX * (GJ_LDS_MAX + 8) + GJ_LDS_MAX) * sizeof(double))));
       attr_set = true;
     }
-    gj_lds_kernel<<<1, 1024, smem, s>>>(last.lay, last.A, ctx->cinv, ctx->cinvf, ctx->flag);
+    gj_lds_kernel<<<1, 1024, smem, a>>>(last.lay, last.A, ctx->cinv, ctx->cinvf, ctx->flag);
   } else {
     double* bufA = ctx->gj_work;
     double* bufB = ctx->gj_work + (size_t)nc * 2 * nc;
-    dense_build_kernel<<<div_up(nc, 256), 256, 0, s>>>(last.lay, last.A, bufA);
+    dense_build_kernel<<<div_up(nc, 256), 256, 0, a>>>(last.lay, last.A, bufA);
     int gblocks = div_up((long)nc * 2 * nc, 256);
     if (gblocks > 512) gblocks = 512;
     for (int p = 0; p < nc; ++p) {
-      gj_step_kernel<<<gblocks, 256, 0, s>>>(nc, p, bufA, bufB, ctx->flag);
+      gj_step_kernel<<<gblocks, 256, 0, a>>>(nc, p, bufA, bufB, ctx->flag);
       double* t = bufA; bufA = bufB; bufB = t;
     }
-    gj_extract_kernel<<<div_up((long)nc * nc, 256), 256, 0, s>>>(nc, bufA, ctx->cinv, ctx->cinvf);
+    gj_extract_kernel<<<div_up((long)nc * nc, 256), 256, 0, a>>>(nc, bufA, ctx->cinv, ctx->cinvf);
   }
+  CPR_TRY(hipEventRecord(ctx->ev_gj, a));
   // red-black block ILU(0): red diagonals first, black ones use them
   int nh = div_up(L.nh, 256);
   for (int colour = 0; colour < 2; ++colour) {
@@ -480,7 +487,11 @@ int setup_cpr(cpr_ctx* ctx) {
     else
       ilu_kernel<3><<<nh, 256, 0, s>>>(L, colour, ctx->J, ctx->R0, ctx->Dinv, ctx->flag);
   }
-  if (ctx->opt.precision == CPR_PREC_MIXED) launch_mixed_copies(ctx);
+  if (ctx->opt.precision == CPR_PREC_MIXED) {
+    CPR_TRY(hipStreamWaitEvent(s, ctx->ev_rap, 0));   // FP32 copies of the levels
+    launch_mixed_copies(ctx);
+  }
+  CPR_TRY(hipStreamWaitEvent(s, ctx->ev_gj, 0));
   rc = launch_check(ctx, "cpr_setup kernels");
   if (rc != CPR_OK) return rc;
   int hflag[2] = {0, 0};

@@ -47,6 +47,7 @@ void free_all(cpr_ctx* ctx) {
   for (void* b : bufs)
     if (b) hipFree(b);
   if (ctx->hhost) hipHostFree(ctx->hhost);
+  ctx->hhost = nullptr;
   for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
   for (hipEvent_t e : {ctx->ev_q, ctx->ev_rap, ctx->ev_gj})
     if (e) hipEventDestroy(e);
@@ -137,6 +138,7 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
   {
     hipError_t e = hipHostMalloc((void**)&ctx->hhost, 512 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) return set_hip_err(ctx, e, "hipHostMalloc");
+    CPR_TRY(hipHostGetDevicePointer((void**)&ctx->hhost_dev, ctx->hhost, 0));
   }
   hipStream_t s = ctx->stream;
   launch_nat_to_cs(ctx->lay, 1, poro, ctx->poro, s);

@@ -220,6 +220,7 @@ struct cpr_ctx {
   double* part = nullptr;      // reduction partials [64][nblk]
   double* hdev = nullptr;      // [4*64] device Hessenberg scratch
   double* hhost = nullptr;     // pinned host mirror
+  double* hhost_dev = nullptr; // its device address (kernels write the Hessenberg column there)
   int nblk = 0;
 
   // kernel-duration sampling (one kernel class at a time)

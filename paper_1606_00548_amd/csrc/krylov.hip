@@ -6,8 +6,9 @@
 // directions Z[m][b*n] stay in HBM; every reduction is a deterministic two-
 // stage sum (fixed per-block partials, then a fixed-order tree), so two runs
 // give identical bits.  Host side: the Givens rotations and the small
-// least-squares problem, one D2H copy of the Hessenberg column per
-// iteration (the only synchronisation in the loop).
+// least-squares problem; the reductions of the Hessenberg column also write
+// it to pinned host memory, and one stream synchronisation per iteration is
+// the only one in the loop.
 //
 // Per Arnoldi step j (nv = j+1 basis vectors):
 //   z_j = M^-1 v_j ; w = A z_j            -> written into V[j+1]
@@ -104,9 +105,11 @@ __global__ __launch_bounds__(KB) void orth_kernel(long len, int nv, const double
   }
 }
 
-// out[k] (+)= sum_b part[k][b], one block per k, fixed order.
+// out[k] (+)= sum_b part[k][b], one block per k, fixed order; host (pinned
+// host memory, optional) receives the same value.
 __global__ __launch_bounds__(KB) void reduce_kernel(const double* __restrict__ part, int nblk,
-                                                    double* __restrict__ out, const double* __restrict__ add) {
+                                                    double* __restrict__ out, const double* __restrict__ add,
+                                                    double* __restrict__ host = nullptr) {
   __shared__ double sh[CHUNK * (KB / 64)];
   __shared__ double tot[CHUNK];
   int k = blockIdx.x;
@@ -117,7 +120,11 @@ __global__ __launch_bounds__(KB) void reduce_kernel(const double* __restrict__ p
   for (int q = 0; q < CHUNK; ++q) acc[q] = 0.0;
   acc[0] = s;
   block_sum_chunk(acc, 1, sh, tot);
-  if (threadIdx.x == 0) out[k] = tot[0] + (add ? add[k] : 0.0);
+  if (threadIdx.x == 0) {
+    const double v = tot[0] + (add ? add[k] : 0.0);
+    out[k] = v;
+    if (host) host[k] = v;
+  }
 }
 
 // One CGS2 pass over the first nv basis vectors, register-blocked so that
@@ -324,13 +331,12 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
       reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd, nullptr);
       // w -= V h1 ; h2 = V^T w
       orth_pass(ctx, len, nv, w, hd, 0);
-      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd);   // h = h1 + h2
+      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd, ctx->hhost_dev);   // h = h1 + h2
       reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 192, nullptr);   // h2 alone
       // w -= V h2 ; ||w||^2
       orth_pass(ctx, len, nv, w, hd + 192, 1);
-      reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr);
+      reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr, ctx->hhost_dev + 64);
       CPR_TRY(hipGetLastError());
-      CPR_TRY(hipMemcpyAsync(ctx->hhost, hd + 64, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
       CPR_TRY(hipStreamSynchronize(s));
       double hn = std::sqrt(ctx->hhost[64]);
       for (int i = 0; i <= m; ++i) col[i] = 0.0;

@@ -213,49 +213,105 @@ __global__ void gj_step_kernel(int nc, int p, const double* __restrict__ src, do
   }
 }
 
-// Whole Gauss-Jordan inversion (partial pivoting, in place) of a small
-// coarsest operator in one workgroup with the matrix held in LDS (nc <= 128).
-// Thread layout: row r = tid / 8, columns lane + 8 q; rows are padded to an
-// odd stride so the 8 rows a wavefront touches fall in different banks.  The
-// dense matrix is built from the level's 7-point stencil; the inverse is
-// written column major (and as FP32).
-constexpr int GJ_LDS_MAX = 128;
+constexpr int GJ_LDS_MAX = 128;   // coarsest levels up to this size are inverted in one workgroup
 
-__global__ __launch_bounds__(1024) void gj_lds_kernel(Lay L, const double* __restrict__ A,
-                                                      double* __restrict__ inv, float* __restrict__ invf,
-                                                      int* __restrict__ flag) {
+// Coarsest inverse through the red-black Schur complement (nc <= 128).  A
+// 7-point operator couples red cells only to black ones, so with the cells
+// ordered red then black A = [Dr B; C Db] with diagonal Dr, Db, and
+//   S = Db - C Dr^-1 B,
+//   A^-1 = [Dr^-1 - X C Dr^-1, X; -S^-1 C Dr^-1, S^-1],  X = -Dr^-1 B S^-1.
+// Only S (at most 64 x 64) goes through Gauss-Jordan with partial pivoting
+// (in LDS, 16 threads per row); B and C have at most six entries per row
+// and column, so the other blocks are short sums.  Inverse written column
+// major (and as FP32).  A zero or non-finite red diagonal or S pivot sets
+// the singular flag.
+constexpr int SCH_MAX = 64;
+constexpr int SCH_LD = SCH_MAX + 1;
+
+__global__ __launch_bounds__(1024) void gj_schur_kernel(Lay L, const double* __restrict__ A,
+                                                        double* __restrict__ inv, float* __restrict__ invf,
+                                                        int* __restrict__ flag) {
   extern __shared__ double sm[];
-  const int nc = L.n;
-  const int ld = nc + 8;          // 8 consecutive rows then start in different LDS banks
-  double* M = sm;                 // nc rows of stride ld
-  double* fcol = sm + nc * ld;    // multipliers of the current column
-  __shared__ int piv[GJ_LDS_MAX];
+  double* S = sm;                        // [SCH_MAX][SCH_LD]
+  double* X = sm + SCH_MAX * SCH_LD;     // [SCH_MAX][SCH_MAX]
+  __shared__ int colr[GJ_LDS_MAX], pos[GJ_LDS_MAX];
+  __shared__ int red[SCH_MAX], blk[SCH_MAX];
+  __shared__ double Dinvr[SCH_MAX], Db[SCH_MAX], fcol[SCH_MAX];
+  __shared__ int Bk[SCH_MAX][6], Ck[SCH_MAX][6];
+  __shared__ double Bv[SCH_MAX][6], Cv[SCH_MAX][6], Tv[SCH_MAX][6];
+  __shared__ int piv[SCH_MAX], idx[SCH_MAX];
   __shared__ double pvs;
-  __shared__ int prs;
-  const int tid = threadIdx.x;
-  const int r = tid >> 3, lane = tid & 7;
-  const bool own = r < nc;
-  if (own)
-    for (int c = lane; c < nc; c += 8) M[r * ld + c] = 0.0;
-  __syncthreads();
-  if (own && lane == 0) {
+  __shared__ int prs, nr_s;
+  const int nc = L.n, tid = threadIdx.x;
+  // colours and positions within a colour
+  if (tid < nc) {
     int i, j, k;
-    lay_coords(L, r, i, j, k);
-    M[r * ld + r] += A[r];
-    for (int d = 1; d < 7; ++d) {
-      int nb = lay_nbr(L, i, j, k, d);
-      if (nb >= 0) M[r * ld + nb] += A[(size_t)d * nc + r];
+    lay_coords(L, tid, i, j, k);
+    colr[tid] = (i + j + k) & 1;
+  }
+  __syncthreads();
+  if (tid < nc) {
+    int q = 0;
+    for (int u = 0; u < tid; ++u) q += colr[u] == colr[tid];
+    pos[tid] = q;
+    if (colr[tid] == 0) red[q] = tid; else blk[q] = tid;
+  }
+  if (tid == 0) {
+    int q = 0;
+    for (int u = 0; u < nc; ++u) q += colr[u] == 0;
+    nr_s = q;
+  }
+  __syncthreads();
+  const int nr = nr_s, nb = nc - nr;
+  // red rows: 1/Dr, B (black neighbours), C^T (the black rows' coupling back)
+  if (tid < nr) {
+    const int c = red[tid];
+    const double d = A[c];
+    if (!(fabs(d) > TINY) || !isfinite(d)) atomicExch(flag, 1);
+    Dinvr[tid] = 1.0 / d;
+    int i, j, k;
+    lay_coords(L, c, i, j, k);
+    for (int e = 0; e < 6; ++e) {
+      const int nbc = lay_nbr(L, i, j, k, e + 1);
+      const int opp = (e ^ 1) + 1;
+      Bk[tid][e] = nbc >= 0 ? pos[nbc] : -1;
+      Bv[tid][e] = nbc >= 0 ? A[(size_t)(e + 1) * nc + c] : 0.0;
+      Tv[tid][e] = nbc >= 0 ? A[(size_t)opp * nc + nbc] : 0.0;
+    }
+  } else if (tid >= 512 && tid - 512 < nb) {
+    const int kb = tid - 512, c = blk[kb];
+    Db[kb] = A[c];
+    int i, j, k;
+    lay_coords(L, c, i, j, k);
+    for (int e = 0; e < 6; ++e) {
+      const int nbc = lay_nbr(L, i, j, k, e + 1);
+      Ck[kb][e] = nbc >= 0 ? pos[nbc] : -1;
+      Cv[kb][e] = nbc >= 0 ? A[(size_t)(e + 1) * nc + c] : 0.0;
     }
   }
   __syncthreads();
-  for (int p = 0; p < nc; ++p) {
-    if (tid < 64) {   // pivot: largest |M[q][p]|, q >= p, lowest row on ties
+  // S = Db - C Dr^-1 B
+  for (int q = tid; q < nb * nb; q += 1024) {
+    const int k1 = q / nb, k2 = q % nb;
+    double v = k1 == k2 ? Db[k1] : 0.0;
+    for (int e = 0; e < 6; ++e) {
+      const int r = Ck[k1][e];
+      if (r < 0) continue;
+      double brk = 0.0;
+      for (int e2 = 0; e2 < 6; ++e2) brk += Bk[r][e2] == k2 ? Bv[r][e2] : 0.0;
+      v -= Cv[k1][e] * Dinvr[r] * brk;
+    }
+    S[k1 * SCH_LD + k2] = v;
+  }
+  __syncthreads();
+  // Gauss-Jordan on S in place: thread (row tid / 16, columns tid % 16 + 16 q)
+  const int row = tid >> 4, l16 = tid & 15;
+  const bool own = row < nb;
+  for (int p = 0; p < nb; ++p) {
+    if (tid < 64) {
       double best = -1.0;
       int bi = p;
-      for (int q = p + tid; q < nc; q += 64) {
-        double v = fabs(M[q * ld + p]);
-        if (v > best) { best = v; bi = q; }
-      }
+      if (p + tid < nb) { best = fabs(S[(p + tid) * SCH_LD + p]); bi = p + tid; }
       for (int o = 32; o > 0; o >>= 1) {
         double ov = __shfl_down(best, o, 64);
         int oi = __shfl_down(bi, o, 64);
@@ -263,7 +319,7 @@ __global__ __launch_bounds__(1024) void gj_lds_kernel(Lay L, const double* __res
       }
       if (tid == 0) {
         prs = bi;
-        pvs = M[bi * ld + p];
+        pvs = S[bi * SCH_LD + p];
         piv[p] = bi;
         if (!(best > TINY) || !isfinite(best)) atomicExch(flag, 1);
       }
@@ -271,40 +327,66 @@ __global__ __launch_bounds__(1024) void gj_lds_kernel(Lay L, const double* __res
     __syncthreads();
     const int pr = prs;
     const double pinv = 1.0 / pvs;
-    // one thread per column interchanges rows p and pr and scales the new
-    // pivot row (diagonal set to 1 first); other threads collect the
-    // multipliers of column p for the rows the interchange does not touch
-    if (tid < nc) {
+    if (tid < nb) {
       const int c = tid;
-      double top = M[pr * ld + c], old = M[p * ld + c];
-      if (pr != p) M[pr * ld + c] = old;
-      M[p * ld + c] = (c == p ? 1.0 : top) * pinv;
+      double top = S[pr * SCH_LD + c], old = S[p * SCH_LD + c];
+      if (pr != p) S[pr * SCH_LD + c] = old;
+      S[p * SCH_LD + c] = (c == p ? 1.0 : top) * pinv;
       if (c == p) { fcol[p] = 0.0; fcol[pr] = pr == p ? 0.0 : old; }
-    } else if (tid >= 512 && tid - 512 < nc) {
+    } else if (tid >= 512 && tid - 512 < nb) {
       const int q = tid - 512;
-      if (q != p && q != pr) fcol[q] = M[q * ld + p];
+      if (q != p && q != pr) fcol[q] = S[q * SCH_LD + p];
     }
     __syncthreads();
-    if (own && r != p) {
-      const double f = fcol[r];
-      for (int c = lane; c < nc; c += 8) M[r * ld + c] = (c == p ? 0.0 : M[r * ld + c]) - f * M[p * ld + c];
-    }
-    __syncthreads();
-  }
-  // undo the row interchanges as column interchanges, last first
-  for (int p = nc - 1; p >= 0; --p) {
-    int q = piv[p];
-    if (q != p && own && lane == 0) {
-      double t = M[r * ld + p]; M[r * ld + p] = M[r * ld + q]; M[r * ld + q] = t;
+    if (own && row != p) {
+      const double f = fcol[row];
+      for (int c = l16; c < nb; c += 16) S[row * SCH_LD + c] = (c == p ? 0.0 : S[row * SCH_LD + c]) - f * S[p * SCH_LD + c];
     }
     __syncthreads();
   }
-  if (own)
-    for (int c = lane; c < nc; c += 8) {
-      double v = M[r * ld + c];
-      inv[(size_t)c * nc + r] = v;
-      if (invf) invf[(size_t)c * nc + r] = (float)v;
+  // row interchanges undone as column interchanges, last first: column j of
+  // S^-1 is column idx[j] of the eliminated matrix
+  if (tid == 0) {
+    for (int c = 0; c < nb; ++c) idx[c] = c;
+    for (int p = nb - 1; p >= 0; --p) {
+      const int q = piv[p];
+      const int t = idx[p]; idx[p] = idx[q]; idx[q] = t;
     }
+  }
+  __syncthreads();
+  auto Si = [&](int i, int j) { return S[i * SCH_LD + idx[j]]; };
+  // X = -Dr^-1 B S^-1
+  for (int q = tid; q < nr * nb; q += 1024) {
+    const int r = q / nb, j = q % nb;
+    double v = 0.0;
+    for (int e = 0; e < 6; ++e)
+      if (Bk[r][e] >= 0) v += Bv[r][e] * Si(Bk[r][e], j);
+    X[r * SCH_MAX + j] = -Dinvr[r] * v;
+  }
+  __syncthreads();
+  // the four blocks of A^-1, column major
+  for (int q = tid; q < nc * nc; q += 1024) {
+    const int ci = q / nc, ri = q % nc;       // column cell, row cell
+    const int pc = pos[ci], pri = pos[ri];
+    double v;
+    if (colr[ri] == 1 && colr[ci] == 1) {
+      v = Si(pri, pc);
+    } else if (colr[ri] == 0 && colr[ci] == 1) {
+      v = X[pri * SCH_MAX + pc];
+    } else if (colr[ri] == 1) {               // black row, red column
+      v = 0.0;
+      for (int e = 0; e < 6; ++e)
+        if (Bk[pc][e] >= 0) v += Si(pri, Bk[pc][e]) * Tv[pc][e];
+      v = -v * Dinvr[pc];
+    } else {                                  // red row, red column
+      v = 0.0;
+      for (int e = 0; e < 6; ++e)
+        if (Bk[pc][e] >= 0) v += X[pri * SCH_MAX + Bk[pc][e]] * Tv[pc][e];
+      v = (pri == pc ? Dinvr[pri] : 0.0) - v * Dinvr[pc];
+    }
+    inv[q] = v;
+    if (invf) invf[q] = (float)v;
+  }
 }
 
 // Copy the right half of [I | M^-1] into column-major storage.
@@ -458,14 +540,14 @@ int setup_cpr(cpr_ctx* ctx) {
   const MGLevel& last = ctx->levels.back();
   int nc = last.lay.n;
   if (nc <= GJ_LDS_MAX) {
-    size_t smem = ((size_t)nc * (nc + 8) + nc) * sizeof(double);
+    const size_t smem = ((size_t)SCH_MAX * SCH_LD + (size_t)SCH_MAX * SCH_MAX) * sizeof(double);
     static bool attr_set = false;
     if (!attr_set) {
-      CPR_TRY(hipFuncSetAttribute((const void*)gj_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(((size_t)GJ_LDS_MAX * (GJ_LDS_MAX + 8) + GJ_LDS_MAX) * sizeof(double))));
+      CPR_TRY(hipFuncSetAttribute((const void*)gj_schur_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)smem));
       attr_set = true;
     }
-    gj_lds_kernel<<<1, 1024, smem, a>>>(last.lay, last.A, ctx->cinv, ctx->cinvf, ctx->flag);
+    gj_schur_kernel<<<1, 1024, smem, a>>>(last.lay, last.A, ctx->cinv, ctx->cinvf, ctx->flag);
   } else {
     double* bufA = ctx->gj_work;
     double* bufB = ctx->gj_work + (size_t)nc * 2 * nc;

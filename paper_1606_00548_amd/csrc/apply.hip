@@ -75,9 +75,17 @@ __device__ inline void red_zero_cell(const T* __restrict__ A, const T* __restric
   x[q] = r[q] / A[q];
 }
 
-// sum_{d>0} a_d x_nb for a colour-split cell (branch-free: the stencil
-// coefficients are streamed non-temporally, missing neighbours masked)
-template <typename T>
+// Stencil coefficients are read non-temporally by the multi-block sweeps,
+// which stream them once, and through the caches by the single-workgroup
+// kernel, which reads its small levels several times.
+template <bool NT, typename T>
+__device__ inline T ldc(const T* p) {
+  if constexpr (NT) return ldnt(p); else return *p;
+}
+
+// sum_{d>0} a_d x_nb for a colour-split cell (branch-free, missing
+// neighbours masked)
+template <typename T, bool NT = true>
 __device__ inline T offdiag_sum(const Lay& L, const T* __restrict__ A, const T* __restrict__ x, int t) {
   CsCell cc = cs_decode(L, t);
   int nbr[7];
@@ -85,7 +93,7 @@ __device__ inline T offdiag_sum(const Lay& L, const T* __restrict__ A, const T* 
   cs_nbrs(L, t, cc, nbr, ok);
   T a[7];
 #pragma unroll
-  for (int d = 1; d < 7; ++d) a[d] = ldnt(A + (size_t)d * L.n + t);
+  for (int d = 1; d < 7; ++d) a[d] = ldc<NT>(A + (size_t)d * L.n + t);
   T s = 0;
 #pragma unroll
   for (int d = 1; d < 7; ++d) {
@@ -96,11 +104,11 @@ __device__ inline T offdiag_sum(const Lay& L, const T* __restrict__ A, const T* 
 }
 
 // black cell q: Gauss-Seidel update and its residual r - A x afterwards
-template <typename T>
+template <typename T, bool NT = true>
 __device__ inline void black_pre_cell(const Lay& L, const T* __restrict__ A, const T* __restrict__ r,
                                       T* __restrict__ x, T* __restrict__ res, int q) {
   int t = L.nh + q;
-  T s = offdiag_sum(L, A, x, t);
+  T s = offdiag_sum<T, NT>(L, A, x, t);
   T xb = (r[t] - s) / A[t];
   x[t] = xb;
   res[q] = r[t] - (A[t] * xb + s);
@@ -108,7 +116,7 @@ __device__ inline void black_pre_cell(const Lay& L, const T* __restrict__ A, con
 
 // coarse cell tc: sum of the fine residuals of its aggregate (P^T r), fine
 // cells in natural order; black residuals were recorded by the black sweep
-template <typename T>
+template <typename T, bool NT = true>
 __device__ inline void restrict_cell(const Lay& F, const Lay& C, const T* __restrict__ A,
                                      const T* __restrict__ r, const T* __restrict__ x,
                                      const T* __restrict__ res, T* __restrict__ rc, int tc) {
@@ -120,7 +128,7 @@ __device__ inline void restrict_cell(const Lay& F, const Lay& C, const T* __rest
       for (int fi = 2 * ci; fi <= 2 * ci + 1 && fi < F.nx; ++fi) {
         int f = lay_index(F, fi, fj, fk);
         if (f < F.nh) {
-          T y = A[f] * x[f] + offdiag_sum(F, A, x, f);
+          T y = A[f] * x[f] + offdiag_sum<T, NT>(F, A, x, f);
           acc += r[f] - y;
         } else {
           acc += res[f - F.nh];
@@ -131,7 +139,7 @@ __device__ inline void restrict_cell(const Lay& F, const Lay& C, const T* __rest
 
 // black cell q after the coarse correction: neighbours are red cells whose
 // corrected value is x + alpha e_c[aggregate]
-template <typename T>
+template <typename T, bool NT = true>
 __device__ inline void black_post_cell(const Lay& F, const Lay& C, T alpha, const T* __restrict__ A,
                                        const T* __restrict__ r, const T* __restrict__ ec,
                                        T* __restrict__ x, int q) {
@@ -142,7 +150,7 @@ __device__ inline void black_post_cell(const Lay& F, const Lay& C, T alpha, cons
   cs_nbrs(F, t, cc, nbr, ok);
   T a[7];
 #pragma unroll
-  for (int d = 1; d < 7; ++d) a[d] = ldnt(A + (size_t)d * F.n + t);
+  for (int d = 1; d < 7; ++d) a[d] = ldc<NT>(A + (size_t)d * F.n + t);
   T s = 0;
 #pragma unroll
   for (int d = 1; d < 7; ++d) {
@@ -158,10 +166,10 @@ __device__ inline void black_post_cell(const Lay& F, const Lay& C, T alpha, cons
 }
 
 // red cell q, general Gauss-Seidel update
-template <typename T>
+template <typename T, bool NT = true>
 __device__ inline void red_cell(const Lay& L, const T* __restrict__ A, const T* __restrict__ r,
                                 T* __restrict__ x, int q) {
-  T s = offdiag_sum(L, A, x, q);
+  T s = offdiag_sum<T, NT>(L, A, x, q);
   x[q] = (r[q] - s) / A[q];
 }
 
@@ -288,9 +296,10 @@ __global__ __launch_bounds__(1024) void coarse_cycle_kernel(CoarseArgs<T> a) {
     const Lay F = a.lay[l], C = a.lay[l + 1];
     for (int q = tid; q < F.nh; q += nt) red_zero_cell(a.A[l], a.r[l], a.x[l], q);
     __syncthreads();
-    for (int q = tid; q < F.nh; q += nt) black_pre_cell(F, a.A[l], a.r[l], a.x[l], a.res[l], q);
+    for (int q = tid; q < F.nh; q += nt) black_pre_cell<T, false>(F, a.A[l], a.r[l], a.x[l], a.res[l], q);
     __syncthreads();
-    for (int tc = tid; tc < C.n; tc += nt) restrict_cell(F, C, a.A[l], a.r[l], a.x[l], a.res[l], a.r[l + 1], tc);
+    for (int tc = tid; tc < C.n; tc += nt)
+      restrict_cell<T, false>(F, C, a.A[l], a.r[l], a.x[l], a.res[l], a.r[l + 1], tc);
     __syncthreads();
   }
   {
@@ -314,9 +323,10 @@ __global__ __launch_bounds__(1024) void coarse_cycle_kernel(CoarseArgs<T> a) {
   }
   for (int l = a.count - 2; l >= 0; --l) {
     const Lay F = a.lay[l], C = a.lay[l + 1];
-    for (int q = tid; q < F.nh; q += nt) black_post_cell(F, C, a.alpha, a.A[l], a.r[l], a.x[l + 1], a.x[l], q);
+    for (int q = tid; q < F.nh; q += nt)
+      black_post_cell<T, false>(F, C, a.alpha, a.A[l], a.r[l], a.x[l + 1], a.x[l], q);
     __syncthreads();
-    for (int q = tid; q < F.nh; q += nt) red_cell(F, a.A[l], a.r[l], a.x[l], q);
+    for (int q = tid; q < F.nh; q += nt) red_cell<T, false>(F, a.A[l], a.r[l], a.x[l], q);
     __syncthreads();
   }
 }

@@ -118,32 +118,44 @@ __global__ void qimpes_kernel(int n, const double* __restrict__ J, double* __res
   }
 }
 
-// Galerkin coarse operator for piecewise-constant 2x2x2 aggregation: one
-// thread per coarse cell sums the couplings of its (up to) 8 fine cells.
-__global__ void rap_kernel(Lay F, Lay C, const double* __restrict__ Af, double* __restrict__ Ac) {
-  int tc = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tc >= C.n) return;
-  int ci, cj, ck;
-  lay_coords(C, tc, ci, cj, ck);
+// Galerkin coarse operator for piecewise-constant 2x2x2 aggregation: eight
+// lanes per coarse cell, one per fine cell of its aggregate, each sorting
+// its stencil row into the coarse couplings (inside the aggregate: the
+// diagonal); the eight partial rows are summed by a fixed butterfly.
+__global__ __launch_bounds__(256) void rap_kernel(Lay F, Lay C, const double* __restrict__ Af,
+                                                  double* __restrict__ Ac) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tc = g >> 3, sub = g & 7;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int fk = 2 * ck; fk <= 2 * ck + 1 && fk < F.nz; ++fk)
-    for (int fj = 2 * cj; fj <= 2 * cj + 1 && fj < F.ny; ++fj)
-      for (int fi = 2 * ci; fi <= 2 * ci + 1 && fi < F.nx; ++fi) {
-        int f = lay_index(F, fi, fj, fk);
-        acc[0] += Af[f];
-        for (int d = 1; d < 7; ++d) {
-          int di, dj, dk;
-          dir_offset(d, di, dj, dk);
-          int gi = fi + di, gj = fj + dj, gk = fk + dk;
-          if (gi < 0 || gi >= F.nx || gj < 0 || gj >= F.ny || gk < 0 || gk >= F.nz) continue;
-          double a = Af[(size_t)d * F.n + f];
-          if ((gi >> 1) == ci && (gj >> 1) == cj && (gk >> 1) == ck)
-            acc[0] += a;
-          else
-            acc[d] += a;
-        }
+  int ci = 0, cj = 0, ck = 0;
+  if (tc < C.n) {
+    lay_coords(C, tc, ci, cj, ck);
+    const int fi = 2 * ci + (sub & 1), fj = 2 * cj + ((sub >> 1) & 1), fk = 2 * ck + (sub >> 2);
+    if (fi < F.nx && fj < F.ny && fk < F.nz) {
+      const int f = lay_index(F, fi, fj, fk);
+      acc[0] += Af[f];
+#pragma unroll
+      for (int d = 1; d < 7; ++d) {
+        int di, dj, dk;
+        dir_offset(d, di, dj, dk);
+        const int gi = fi + di, gj = fj + dj, gk = fk + dk;
+        if (gi < 0 || gi >= F.nx || gj < 0 || gj >= F.ny || gk < 0 || gk >= F.nz) continue;
+        const double a = Af[(size_t)d * F.n + f];
+        if ((gi >> 1) == ci && (gj >> 1) == cj && (gk >> 1) == ck)
+          acc[0] += a;
+        else
+          acc[d] += a;
       }
-  for (int d = 0; d < 7; ++d) Ac[(size_t)d * C.n + tc] = acc[d];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 7; ++d) {
+    acc[d] += __shfl_xor(acc[d], 1, 8);
+    acc[d] += __shfl_xor(acc[d], 2, 8);
+    acc[d] += __shfl_xor(acc[d], 4, 8);
+  }
+  if (tc < C.n && sub == 0)
+    for (int d = 0; d < 7; ++d) Ac[(size_t)d * C.n + tc] = acc[d];
 }
 
 // Dense [M | I] (row-major, 2*nc columns) of the coarsest 7-point operator,
@@ -533,7 +545,7 @@ int setup_cpr(cpr_ctx* ctx) {
   for (size_t l = 0; l + 1 < ctx->levels.size(); ++l) {
     const MGLevel& F = ctx->levels[l];
     MGLevel& C = ctx->levels[l + 1];
-    rap_kernel<<<div_up(C.lay.n, 256), 256, 0, a>>>(F.lay, C.lay, F.A, C.A);
+    rap_kernel<<<div_up(8L * C.lay.n, 256), 256, 0, a>>>(F.lay, C.lay, F.A, C.A);
   }
   CPR_TRY(hipEventRecord(ctx->ev_rap, a));
   // dense inverse of the coarsest level

@@ -115,3 +115,78 @@ def fgmres(apply_A, apply_M, b, restart=30, rtol=1e-6, max_iter=300, x0=None,
         r = b - apply_A(x)
     st["iterations"] = its
     return x, st
+
+
+def bicgstab(apply_A, apply_M, b, rtol=1e-6, max_iter=300):
+    """Right-preconditioned BiCGSTAB (van der Vorst, 1992), the Krylov method
+    of every example in the paper (Sec. 4), with the same CPR preconditioner.
+
+    x0 = 0, r = b, shadow residual rh = r, rho_prev = alpha = omega = 1,
+    p = v = 0; each iteration:
+        rho = <rh, r>;  beta = (rho / rho_prev) (alpha / omega)
+        p = r + beta (p - omega v);  ph = M^-1 p;  v = A ph
+        alpha = rho / <rh, v>;  s = r - alpha v
+        sh = M^-1 s;  t = A sh;  omega = <t, s> / <t, t> (0 when t = 0)
+        x += alpha ph + omega sh;  r = s - omega t
+    until ||r|| <= rtol ||b||; then the true residual b - A x is formed and,
+    if it still exceeds rtol ||b|| and iterations remain, the method restarts
+    from x with r and rh set to the true residual.  A vanishing rho, <rh, v>
+    or omega stops the iteration (breakdown) with the current x.  The
+    iteration count is the number of BiCGSTAB iterations (two products with
+    A and two preconditioner applications each).
+    Returns (x, stats) like fgmres."""
+    x = np.zeros_like(b)
+    bnorm = np.sqrt(_dot(b, b))
+    stats = {"iterations": 0, "cycles": 0, "converged": False, "bnorm": bnorm, "breakdown": False}
+    if bnorm == 0.0:
+        stats.update(converged=True, true_rel=0.0)
+        return x, stats
+    its = 0
+    r = b.copy()
+    while True:
+        stats["cycles"] += 1
+        rh = r.copy()
+        rho_prev = alpha = omega = 1.0
+        p = np.zeros_like(b)
+        v = np.zeros_like(b)
+        stop = False
+        while its < max_iter:
+            rho = _dot(rh, r)
+            if rho == 0.0 or not np.isfinite(rho):
+                stats["breakdown"] = True
+                stop = True
+                break
+            beta = (rho / rho_prev) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+            ph = apply_M(p)
+            v = apply_A(ph)
+            rv = _dot(rh, v)
+            if rv == 0.0 or not np.isfinite(rv):
+                stats["breakdown"] = True
+                stop = True
+                break
+            alpha = rho / rv
+            s = r - alpha * v
+            sh = apply_M(s)
+            t = apply_A(sh)
+            tt = _dot(t, t)
+            omega = _dot(t, s) / tt if tt > 0.0 else 0.0
+            x = x + alpha * ph + omega * sh
+            r = s - omega * t
+            its += 1
+            rho_prev = rho
+            if np.sqrt(_dot(r, r)) <= rtol * bnorm:
+                break
+            if omega == 0.0:
+                stats["breakdown"] = True
+                stop = True
+                break
+        r = b - apply_A(x)
+        true_rel = np.sqrt(_dot(r, r)) / bnorm
+        if true_rel <= rtol:
+            stats["converged"] = True
+            break
+        if stop or its >= max_iter:
+            break
+    stats.update(iterations=its, true_rel=true_rel)
+    return x, stats

@@ -263,3 +263,60 @@ def test_newton_update_chops_and_clamps():
     assert np.allclose(xn[0], [205.0, 197.0, 201.0])
     assert np.allclose(xn[1], [0.5, 1.0, 0.0])
     assert np.allclose(xn[2], [0.06, 0.0, 0.05])
+
+
+# ---- BiCGSTAB (the paper's Krylov method, Sec. 4)
+
+def test_bicgstab_dense_matches_solve():
+    rng = np.random.default_rng(70)
+    n = 30
+    A = rng.standard_normal((n, n)) + 8.0 * np.eye(n)        # nonsymmetric, well conditioned
+    b = rng.standard_normal(n)
+    x, st = krylov.bicgstab(lambda v: A @ v, lambda v: v, b, rtol=1e-13)
+    xd = np.linalg.solve(A, b)
+    assert st["converged"] and np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+    # a preconditioner changes the path, not the limit
+    D = np.diag(A).copy()
+    x2, st2 = krylov.bicgstab(lambda v: A @ v, lambda v: v / D, b, rtol=1e-13)
+    assert st2["converged"] and np.linalg.norm(x2 - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_bicgstab_k_distinct_eigenvalues_within_k(k):
+    # BiCG's residual polynomial annihilates a k-dimensional Krylov space in
+    # at most k steps, and BiCGSTAB's residual carries that factor
+    rng = np.random.default_rng(71 + k)
+    d = np.repeat(np.linspace(1.0, 7.0, k), 4)
+    b = rng.standard_normal(d.size)
+    x, st = krylov.bicgstab(lambda v: d * v, lambda v: v, b, rtol=1e-10)
+    assert st["converged"] and st["iterations"] <= k
+    assert np.allclose(x, b / d, rtol=1e-8)
+
+
+def test_bicgstab_exact_preconditioner_and_zero_rhs():
+    rng = np.random.default_rng(76)
+    A = rng.standard_normal((12, 12)) + 6.0 * np.eye(12)
+    Ai = np.linalg.inv(A)
+    b = rng.standard_normal(12)
+    x, st = krylov.bicgstab(lambda v: A @ v, lambda v: Ai @ v, b)
+    assert st["iterations"] == 1 and st["converged"] and st["true_rel"] <= 1e-12
+    x0, st0 = krylov.bicgstab(lambda v: A @ v, lambda v: v, np.zeros(12))
+    assert st0["iterations"] == 0 and st0["converged"] and np.all(x0 == 0)
+    # max_iter stops early with a usable iterate and no claim of convergence
+    x1, st1 = krylov.bicgstab(lambda v: A @ v, lambda v: v, b, rtol=1e-14, max_iter=2)
+    assert st1["iterations"] == 2 and not st1["converged"]
+    assert np.linalg.norm(b - A @ x1) < np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("maker", [lambda: synth.oil_water_lognormal(6, 6, 4, seed=50),
+                                   lambda: synth.black_oil_layered(6, 6, 4, seed=51)])
+def test_cpr_bicgstab_solves_tiny_systems(maker):
+    case, J, b = _system(maker)
+    pc = cpr.cpr_setup(J, coarsest=16)
+    x, st = krylov.bicgstab(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), b)
+    assert st["converged"]
+    M = dense_from_blocks(J)
+    xd = np.linalg.solve(M, to_pointblock(b))
+    r = to_pointblock(b) - M @ to_pointblock(x)
+    assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
+    assert np.linalg.norm(to_pointblock(x) - xd) / np.linalg.norm(xd) <= np.linalg.cond(M) * 1e-6

@@ -106,11 +106,11 @@ def main():
     x = x0.clone()
     opts = cprmi.default_options(precision=args.precision)
 
-    def timed(o, kernel=None):
+    def timed(o, kernel=None, krylov="fgmres"):
         """Warm-up, then exactly args.steps Newton steps between two syncs."""
         def step():
             x.copy_(x0)
-            dx, st = cprmi.newton_step(solver, x_old, x, case["dt"], o)
+            dx, st = cprmi.newton_step(solver, x_old, x, case["dt"], o, krylov=krylov)
             return st
         for _ in range(args.warmup):
             step()
@@ -136,13 +136,16 @@ def main():
     if not args.no_variants:
         from paper_1606_00548_amd import train
         wfile = train.weights_path("black-oil")
-        forms = [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed"))]
+        forms = [("fp64", dict(precision="fp64"), "fgmres"), ("mixed", dict(precision="mixed"), "fgmres")]
         if os.path.exists(wfile):
             solver.attach_network(np.load(wfile))
-            forms.append(("mixed+learned", dict(precision="mixed", learned=1)))
-        for name, kw in forms:
-            sp, sts, _ = timed(cprmi.default_options(**kw))
-            variants[name] = {"s_per_step": sp, "fgmres_iterations": sts[-1]["iterations"],
+            forms.append(("mixed+learned", dict(precision="mixed", learned=1), "fgmres"))
+        forms.append(("bicgstab fp64", dict(precision="fp64"), "bicgstab"))
+        if os.path.exists(wfile):
+            forms.append(("bicgstab mixed+learned", dict(precision="mixed", learned=1), "bicgstab"))
+        for name, kw, kry in forms:
+            sp, sts, _ = timed(cprmi.default_options(**kw), krylov=kry)
+            variants[name] = {"s_per_step": sp, "krylov": kry, "krylov_iterations": sts[-1]["iterations"],
                               "true_rel": sts[-1]["true_rel"], "speedup_vs_fp64": None,
                               "nn_accepted": sts[-1]["nn_accepted"]}
         for v in variants.values():

@@ -168,6 +168,20 @@ int cpr_setup(cpr_ctx_t* ctx, const cpr_options_t* o);
  * CPR_ENONFINITE (non-finite rhs or iterate) or CPR_EBREAKDOWN. */
 int cpr_gmres_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* st);
 
+/* Solve A dx = rhs like cpr_gmres_solve, with right-preconditioned
+ * BiCGSTAB (van der Vorst), the Krylov method of the paper's examples
+ * (Sec. 4), and the same CPR preconditioner (set up by cpr_setup; restart is
+ * ignored).  From dx = 0, iterate until the recursively updated residual
+ * satisfies ||r|| <= rtol ||rhs||, then form the true residual and restart
+ * from dx with it while it exceeds rtol ||rhs|| and iterations remain.  A
+ * vanishing rho, <rh, v> or omega ends the iteration (breakdown).
+ * st->iterations counts BiCGSTAB iterations (two products with A and two
+ * preconditioner applications each), st->cycles the restarts + 1.
+ * Synchronises once per iteration.  Workspace: the first eight vectors of
+ * the Krylov basis (allocated if smaller).  Returns CPR_OK,
+ * CPR_NOT_CONVERGED (dx holds the last iterate) or CPR_ENONFINITE. */
+int cpr_bicgstab_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* st);
+
 /* Newton update of Algorithm 1, step 5 (device, [b][n]): x += dx with
  * saturation changes chopped to |dS| <= 0.2 and saturations clamped to
  * [0, 1]. */

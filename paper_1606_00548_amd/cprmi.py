@@ -69,7 +69,7 @@ EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error",
            "cpr_nn_destroy", "cpr_nn_last_error", "cpr_nn_set_params", "cpr_nn_get_params",
            "cpr_nn_forward", "cpr_nn_backward", "cpr_nn_train_step", "cpr_nn_attach",
            "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov", "cpr_nn_eval_loss",
-           "cpr_nn_make_target", "cpr_nn_infer"]
+           "cpr_nn_make_target", "cpr_nn_infer", "cpr_bicgstab_solve"]
 KCLASS = {"spmv": 0, "orth": 1, "smooth": 2, "ilu": 3, "assemble": 4}
 
 
@@ -96,6 +96,7 @@ def load():
     lib.cpr_export_jacobian.argtypes = [P, P]
     lib.cpr_setup.argtypes = [P, ctypes.POINTER(Options)]
     lib.cpr_gmres_solve.argtypes = [P, P, P, ctypes.POINTER(Stats)]
+    lib.cpr_bicgstab_solve.argtypes = [P, P, P, ctypes.POINTER(Stats)]
     lib.cpr_newton_update.argtypes = [P, P, P]
     lib.cpr_spmv.argtypes = [P, P, P]
     lib.cpr_precond_apply.argtypes = [P, P, P]
@@ -310,6 +311,16 @@ class Solver:
         d["status"] = rc
         return dx, d
 
+    def bicgstab(self, rhs, dx=None):
+        """BiCGSTAB with the same CPR preconditioner; returns (dx, stats)."""
+        dx = self.vector() if dx is None else dx
+        st = Stats()
+        rc = self._check(self.lib.cpr_bicgstab_solve(self.ctx, _ptr(rhs), _ptr(dx), ctypes.byref(st)),
+                         allow=(0, 1))
+        d = st.as_dict()
+        d["status"] = rc
+        return dx, d
+
     def newton_update(self, x, dx):
         self._check(self.lib.cpr_newton_update(self.ctx, _ptr(x), _ptr(dx)))
         return x
@@ -408,11 +419,12 @@ def make_target(e, scale):
     return t
 
 
-def newton_step(solver, x_old, x, dt_days, options=None, **kw):
+def newton_step(solver, x_old, x, dt_days, options=None, krylov="fgmres", **kw):
     """One inexact Newton iteration (Algorithm 1): assemble A and b = -F(x),
-    set up CPR, solve with FGMRES, update x in place.  Returns (dx, stats)."""
+    set up CPR, solve with FGMRES (or BiCGSTAB), update x in place.  Returns
+    (dx, stats)."""
     rhs = solver.assemble(x_old, x, dt_days)
     solver.setup(options, **kw)
-    dx, st = solver.solve(rhs)
+    dx, st = solver.bicgstab(rhs) if krylov == "bicgstab" else solver.solve(rhs)
     solver.newton_update(x, dx)
     return dx, st

@@ -372,6 +372,32 @@ int cpr_gmres_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* 
   GUARD_END
 }
 
+int cpr_bicgstab_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* st) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  GUARD_BEGIN
+  if (!rhs || !dx) return set_err(ctx, CPR_EINVAL, "null argument");
+  if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
+  int rc;
+  if ((rc = ensure_krylov(ctx, ctx->opt.restart > 8 ? ctx->opt.restart : 8)) != CPR_OK) return rc;
+  hipStream_t s = ctx->stream;
+  launch_nat_to_cs(ctx->lay, ctx->b, rhs, ctx->rs, s);
+  if (ctx->opt.learned) CPR_TRY(hipMemsetAsync(ctx->nncount, 0, 2 * sizeof(int), s));
+  rc = bicgstab_solve(ctx, st);
+  if (rc < 0) return rc;
+  launch_cs_to_nat(ctx->lay, ctx->b, ctx->xs, dx, s);
+  int rc2 = launch_check(ctx, "cpr_bicgstab_solve");
+  if (rc2 != CPR_OK) return rc2;
+  if (ctx->opt.learned && st) {
+    int cnt[2] = {0, 0};
+    CPR_TRY(hipMemcpyAsync(cnt, ctx->nncount, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    CPR_TRY(hipStreamSynchronize(s));
+    st->nn_accepted = cnt[0];
+    st->nn_rejected = cnt[1];
+  }
+  return rc;
+  GUARD_END
+}
+
 int cpr_nn_attach(cpr_ctx_t* ctx, const float* theta) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   GUARD_BEGIN

@@ -301,5 +301,6 @@ void launch_lnk(const Lay& L, const double* perm_nat, double* lnk, hipStream_t s
 
 // krylov.hip
 int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st);
+int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st);
 void launch_newton_update(int b, int n, double* x, const double* dx, hipStream_t s);
 int reduce_dot(cpr_ctx* ctx, const double* a, const double* b, long len, double* out);

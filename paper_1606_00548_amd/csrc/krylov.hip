@@ -239,6 +239,130 @@ void orth_pass(cpr_ctx* ctx, long len, int nv, double* w, const double* hprev, i
   prof_end(ctx, CPR_KCLASS_ORTH);
 }
 
+// ------------------------------------------------------------ BiCGSTAB
+// Device scalars of one BiCGSTAB iteration (ctx->hdev + 320 ...).
+enum { B_RHO = 0, B_ALPHA, B_OMEGA, B_BETA, B_RV, B_TS, B_TT, B_RR, B_BRK, B_NSC };
+
+// part rows 0 (and 1): block partials of <a0, b0> (and <a1, b1>)
+__global__ __launch_bounds__(KB) void dot2_kernel(long len, const double* __restrict__ a0,
+                                                  const double* __restrict__ b0, const double* __restrict__ a1,
+                                                  const double* __restrict__ b1, double* __restrict__ part,
+                                                  int nblk) {
+  __shared__ double sh[CHUNK * (KB / 64)];
+  __shared__ double tot[CHUNK];
+  long per = (len + nblk - 1) / nblk;
+  long beg = (long)blockIdx.x * per;
+  long end = beg + per < len ? beg + per : len;
+  double acc[CHUNK];
+#pragma unroll
+  for (int q = 0; q < CHUNK; ++q) acc[q] = 0.0;
+  for (long e = beg + threadIdx.x; e < end; e += KB) {
+    acc[0] += a0[e] * b0[e];
+    if (a1) acc[1] += a1[e] * b1[e];
+  }
+  const int cnt = a1 ? 2 : 1;
+  block_sum_chunk(acc, cnt, sh, tot);
+  if (threadIdx.x < cnt) part[(size_t)threadIdx.x * nblk + blockIdx.x] = tot[threadIdx.x];
+}
+
+// One block sums nrows partial rows in a fixed order, then derives the
+// iteration's scalars: mode 0 (after <rh, v>): alpha = rho / <rh, v>, or the
+// breakdown flag; mode 1 (after <t, s>, <t, t>): omega (0 when t = 0);
+// mode 2 (after <rh, r>, <r, r>): beta for the next p, rho updated, and
+// ||r||^2, rho, omega, breakdown copied to pinned host memory.
+__global__ __launch_bounds__(KB) void bicg_reduce_kernel(const double* __restrict__ part, int nblk, int nrows,
+                                                         int mode, double* __restrict__ sc,
+                                                         double* __restrict__ host) {
+  __shared__ double sh[CHUNK * (KB / 64)];
+  __shared__ double tot[CHUNK];
+  double acc[CHUNK];
+#pragma unroll
+  for (int q = 0; q < CHUNK; ++q) acc[q] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += KB) {
+    acc[0] += part[b];
+    if (nrows > 1) acc[1] += part[(size_t)nblk + b];
+  }
+  block_sum_chunk(acc, nrows, sh, tot);
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    const double rv = tot[0];
+    sc[B_RV] = rv;
+    const bool bad = !(rv != 0.0) || !isfinite(rv);
+    sc[B_ALPHA] = bad ? 0.0 : sc[B_RHO] / rv;
+    if (bad) sc[B_BRK] = 1.0;
+  } else if (mode == 1) {
+    sc[B_TS] = tot[0];
+    sc[B_TT] = tot[1];
+    sc[B_OMEGA] = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
+  } else {
+    const double rho = tot[0];
+    sc[B_BETA] = (rho / sc[B_RHO]) * (sc[B_ALPHA] / sc[B_OMEGA]);
+    sc[B_RHO] = rho;
+    sc[B_RR] = tot[1];
+    host[0] = tot[1];
+    host[1] = rho;
+    host[2] = sc[B_OMEGA];
+    host[3] = sc[B_BRK];
+  }
+}
+
+// start of a cycle: rho_prev = alpha = omega = 1 (so that p = r), no breakdown
+__global__ void bicg_init_kernel(double* __restrict__ sc) {
+  if (threadIdx.x == 0) {
+    sc[B_RHO] = 1.0; sc[B_ALPHA] = 1.0; sc[B_OMEGA] = 1.0; sc[B_BRK] = 0.0;
+  }
+}
+
+// p = r + beta (p - omega v)
+__global__ void bicg_p_kernel(long len, const double* __restrict__ sc, const double* __restrict__ r,
+                              const double* __restrict__ v, double* __restrict__ p) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  p[e] = r[e] + sc[B_BETA] * (p[e] - sc[B_OMEGA] * v[e]);
+}
+
+// s = r - alpha v (skipped after a breakdown)
+__global__ void bicg_s_kernel(long len, const double* __restrict__ sc, const double* __restrict__ r,
+                              const double* __restrict__ v, double* __restrict__ s) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len || sc[B_BRK] != 0.0) return;
+  s[e] = r[e] - sc[B_ALPHA] * v[e];
+}
+
+// x += alpha ph + omega sh; r = s - omega t; block partials of <rh, r> and
+// <r, r> (nothing changes after a breakdown: the partials of the old r)
+__global__ __launch_bounds__(KB) void bicg_xr_kernel(long len, const double* __restrict__ sc,
+                                                     const double* __restrict__ ph, const double* __restrict__ sh_,
+                                                     const double* __restrict__ s, const double* __restrict__ t,
+                                                     double* __restrict__ x, double* __restrict__ r,
+                                                     const double* __restrict__ rh, double* __restrict__ part,
+                                                     int nblk) {
+  __shared__ double sh[CHUNK * (KB / 64)];
+  __shared__ double tot[CHUNK];
+  const bool brk = sc[B_BRK] != 0.0;
+  const double al = sc[B_ALPHA], om = sc[B_OMEGA];
+  long per = (len + nblk - 1) / nblk;
+  long beg = (long)blockIdx.x * per;
+  long end = beg + per < len ? beg + per : len;
+  double acc[CHUNK];
+#pragma unroll
+  for (int q = 0; q < CHUNK; ++q) acc[q] = 0.0;
+  for (long e = beg + threadIdx.x; e < end; e += KB) {
+    double re;
+    if (!brk) {
+      x[e] = x[e] + al * ph[e] + om * sh_[e];
+      re = s[e] - om * t[e];
+      r[e] = re;
+    } else {
+      re = r[e];
+    }
+    acc[0] += rh[e] * re;
+    acc[1] += re * re;
+  }
+  block_sum_chunk(acc, 2, sh, tot);
+  if (threadIdx.x < 2) part[(size_t)threadIdx.x * nblk + blockIdx.x] = tot[threadIdx.x];
+}
+
 }  // namespace
 
 void launch_newton_update(int b, int n, double* x, const double* dx, hipStream_t s) {
@@ -381,6 +505,114 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     prof_begin(ctx, CPR_KCLASS_SPMV);
     launch_spmv(b, ctx->lay, ctx->J, x, r, ctx->rs, s);
     prof_end(ctx, CPR_KCLASS_SPMV);
+  }
+  S.iterations = its;
+  S.converged = result == CPR_OK;
+  if (st) *st = S;
+  return result;
+}
+
+// Right-preconditioned BiCGSTAB on ctx->rs into ctx->xs (colour-split),
+// step for step as the oracle's; workspace: the first eight Krylov vectors.
+// The iteration's scalars stay on the device; one stream synchronisation
+// per iteration reads ||r||^2, rho, omega and the breakdown flag.
+int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st) {
+  hipStream_t s = ctx->stream;
+  const int b = ctx->b;
+  const long len = (long)b * ctx->lay.n;
+  const int nblk = ctx->nblk;
+  const int eb = div_up(len, 256);
+  const double rtol = ctx->opt.rtol;
+  const int max_iter = ctx->opt.max_iter;
+  double* x = ctx->xs;
+  double* W = ctx->V;
+  double *r = W, *rh = W + len, *p = W + 2 * len, *v = W + 3 * len, *ph = W + 4 * len, *sv = W + 5 * len,
+         *sh = W + 6 * len, *t = W + 7 * len;
+  double* sc = ctx->hdev + 320;
+  double* host = ctx->hhost_dev + 320;
+  const double* hh = ctx->hhost + 320;
+  cpr_stats_t S = {};
+  S.mg_levels = (int)ctx->levels.size();
+  S.qimpes_fallback = ctx->qimpes_bad;
+
+  zero_kernel<<<eb, 256, 0, s>>>(len, x);
+  double bb;
+  int rc = reduce_dot(ctx, ctx->rs, ctx->rs, len, &bb);
+  if (rc) return rc;
+  const double bnorm = std::sqrt(bb);
+  S.bnorm = bnorm;
+  if (!std::isfinite(bnorm)) {
+    if (st) *st = S;
+    return set_err(ctx, CPR_ENONFINITE, "non-finite right-hand side");
+  }
+  if (bnorm == 0.0) {
+    S.converged = 1;
+    if (st) *st = S;
+    return CPR_OK;
+  }
+  CPR_TRY(hipMemcpyAsync(r, ctx->rs, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+  int its = 0;
+  int result = CPR_NOT_CONVERGED;
+  while (true) {
+    S.cycles += 1;
+    CPR_TRY(hipMemcpyAsync(rh, r, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+    zero_kernel<<<eb, 256, 0, s>>>(len, p);
+    zero_kernel<<<eb, 256, 0, s>>>(len, v);
+    bicg_init_kernel<<<1, 64, 0, s>>>(sc);
+    // rho = <rh, r> and beta for the first p (= r)
+    dot2_kernel<<<nblk, KB, 0, s>>>(len, rh, r, r, r, ctx->part, nblk);
+    bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 2, 2, sc, host);
+    CPR_TRY(hipGetLastError());
+    CPR_TRY(hipStreamSynchronize(s));
+    bool stop = false;
+    while (its < max_iter) {
+      const double rho = hh[1];
+      if (!(rho != 0.0) || !std::isfinite(rho)) { stop = true; break; }
+      bicg_p_kernel<<<eb, 256, 0, s>>>(len, sc, r, v, p);
+      precond_apply(ctx, p, p, nullptr, ph);
+      prof_begin(ctx, CPR_KCLASS_SPMV);
+      launch_spmv(b, ctx->lay, ctx->J, ph, v, nullptr, s);
+      prof_end(ctx, CPR_KCLASS_SPMV);
+      dot2_kernel<<<nblk, KB, 0, s>>>(len, rh, v, nullptr, nullptr, ctx->part, nblk);
+      bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 1, 0, sc, host);
+      bicg_s_kernel<<<eb, 256, 0, s>>>(len, sc, r, v, sv);
+      precond_apply(ctx, sv, sv, nullptr, sh);
+      prof_begin(ctx, CPR_KCLASS_SPMV);
+      launch_spmv(b, ctx->lay, ctx->J, sh, t, nullptr, s);
+      prof_end(ctx, CPR_KCLASS_SPMV);
+      dot2_kernel<<<nblk, KB, 0, s>>>(len, t, sv, t, t, ctx->part, nblk);
+      bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 2, 1, sc, host);
+      bicg_xr_kernel<<<nblk, KB, 0, s>>>(len, sc, ph, sh, sv, t, x, r, rh, ctx->part, nblk);
+      bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 2, 2, sc, host);
+      CPR_TRY(hipGetLastError());
+      CPR_TRY(hipStreamSynchronize(s));
+      if (hh[3] != 0.0) { stop = true; break; }       // <rh, v> vanished: x unchanged
+      its += 1;
+      const double rr = hh[0];
+      S.est_rel = std::sqrt(rr) / bnorm;
+      if (!std::isfinite(rr)) {
+        S.iterations = its;
+        if (st) *st = S;
+        return set_err(ctx, CPR_ENONFINITE, "non-finite BiCGSTAB residual");
+      }
+      if (std::sqrt(rr) <= rtol * bnorm) break;
+      if (hh[2] == 0.0) { stop = true; break; }       // omega vanished
+    }
+    // true residual r = b - A x
+    prof_begin(ctx, CPR_KCLASS_SPMV);
+    launch_spmv(b, ctx->lay, ctx->J, x, r, ctx->rs, s);
+    prof_end(ctx, CPR_KCLASS_SPMV);
+    double rr;
+    rc = reduce_dot(ctx, r, r, len, &rr);
+    if (rc) return rc;
+    S.true_rel = std::sqrt(rr) / bnorm;
+    if (!std::isfinite(S.true_rel)) {
+      S.iterations = its;
+      if (st) *st = S;
+      return set_err(ctx, CPR_ENONFINITE, "non-finite residual");
+    }
+    if (S.true_rel <= rtol) { result = CPR_OK; break; }
+    if (stop || its >= max_iter) break;
   }
   S.iterations = its;
   S.converged = result == CPR_OK;

@@ -128,6 +128,50 @@ def test_fgmres_matches_oracle(system):
     assert abs(st["true_rel"] - so["true_rel"]) <= 1e-9
 
 
+def test_bicgstab_matches_oracle(system):
+    # The paper's Krylov method with the same CPR.  BiCGSTAB's iterates react
+    # chaotically to rounding: perturbing the oracle's own preconditioner
+    # output by 1e-13 relative moves its solution by ~1e-5 and its iteration
+    # count by up to 5 on these grids, so the GPU is held to P1 (true
+    # residual <= rtol, recomputed by the oracle) and to the oracle's
+    # iteration count within that spread; short paths must agree closely
+    # (test_bicgstab_fixed_iteration_path).
+    name, case, x, J, b = system
+    s = _solver(case)
+    s.import_jacobian(J)
+    s.setup()
+    dx, st = s.bicgstab(_gpu(b))
+    pc = cpr.cpr_setup(J)
+    xo, so = krylov.bicgstab(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), b)
+    xg = _np(dx)
+    d = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"[gpu-parity] {name}: BiCGSTAB {st['iterations']} iterations (oracle {so['iterations']}), "
+          f"|x_gpu - x_oracle| / |x_oracle| = {d:.1e}")
+    assert st["status"] == 0 and so["converged"]
+    assert abs(st["iterations"] - so["iterations"]) <= max(2, so["iterations"] // 3)
+    assert np.linalg.norm(b - cpr.block_spmv(J, xg)) <= 1e-6 * np.linalg.norm(b)
+    assert st["true_rel"] <= 1e-6
+
+
+@pytest.mark.parametrize("k,tol", [(1, 1e-10), (3, 1e-7)])
+def test_bicgstab_fixed_iteration_path(k, tol):
+    # rtol = 0: exactly k iterations on both sides, iterates agree
+    case = CASES["bo-34x20x6"]()
+    x = synth.random_state_perturbation(case, 17)
+    J, b = _oracle_system(case, x)
+    s = _solver(case)
+    s.import_jacobian(J)
+    s.setup(rtol=0.0, max_iter=k)
+    dx, st = s.bicgstab(_gpu(b))
+    pc = cpr.cpr_setup(J)
+    xo, so = krylov.bicgstab(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), b, rtol=0.0,
+                             max_iter=k)
+    d = np.linalg.norm(_np(dx) - xo) / np.linalg.norm(xo)
+    print(f"[gpu-parity] BiCGSTAB {k} iterations: |x_gpu - x_oracle| / |x_oracle| = {d:.1e}")
+    assert st["status"] == 1 and st["iterations"] == so["iterations"] == k
+    assert d <= tol
+
+
 @pytest.mark.parametrize("k", [1, 5, 30, 60])
 def test_fgmres_fixed_iteration_path(k):
     # rtol = 0 forces exactly k Arnoldi steps: separates path divergence

@@ -49,9 +49,9 @@ void free_all(cpr_ctx* ctx) {
   if (ctx->hhost) hipHostFree(ctx->hhost);
   ctx->hhost = nullptr;
   for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
-  for (hipEvent_t e : {ctx->ev_q, ctx->ev_rap, ctx->ev_gj})
+  for (hipEvent_t e : {ctx->ev_q, ctx->ev_rap, ctx->ev_gj, ctx->ev_iter[0], ctx->ev_iter[1]})
     if (e) hipEventDestroy(e);
-  ctx->ev_q = ctx->ev_rap = ctx->ev_gj = nullptr;
+  ctx->ev_q = ctx->ev_rap = ctx->ev_gj = ctx->ev_iter[0] = ctx->ev_iter[1] = nullptr;
   if (ctx->aux) hipStreamDestroy(ctx->aux);
   ctx->aux = nullptr;
   if (ctx->nn) cpr_nn_destroy(ctx->nn);
@@ -88,6 +88,8 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
   CPR_TRY(hipEventCreateWithFlags(&ctx->ev_q, hipEventDisableTiming));
   CPR_TRY(hipEventCreateWithFlags(&ctx->ev_rap, hipEventDisableTiming));
   CPR_TRY(hipEventCreateWithFlags(&ctx->ev_gj, hipEventDisableTiming));
+  CPR_TRY(hipEventCreateWithFlags(&ctx->ev_iter[0], hipEventDisableTiming));
+  CPR_TRY(hipEventCreateWithFlags(&ctx->ev_iter[1], hipEventDisableTiming));
   ctx->grid = *g;
   ctx->b = f->model;
   FluidDev& fl = ctx->fl;

@@ -168,6 +168,7 @@ struct cpr_ctx {
   // stream (default priority) while the ILU factorisation runs on `stream`
   hipStream_t aux = nullptr;
   hipEvent_t ev_q = nullptr, ev_rap = nullptr, ev_gj = nullptr;
+  hipEvent_t ev_iter[2] = {nullptr, nullptr};   // completion of Arnoldi steps (even, odd)
   cpr_grid_t grid;
   FluidDev fl;
   int b = 0;
@@ -295,6 +296,7 @@ void precond_pressure_stage(cpr_ctx* ctx, const double* v);
 // learned.hip
 int learned_setup(cpr_ctx* ctx, bool need_nn);
 int learned_stage(cpr_ctx* ctx);
+void learned_discard_last(cpr_ctx* ctx);
 void learned_rprime(cpr_ctx* ctx);
 void learned_features_from_rprime(cpr_ctx* ctx);
 void launch_lnk(const Lay& L, const double* perm_nat, double* lnk, hipStream_t s);

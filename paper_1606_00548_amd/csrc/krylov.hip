@@ -26,6 +26,7 @@ namespace {
 constexpr int KB = 256;        // threads per block of the vector kernels
 constexpr int CHUNK = 8;       // basis vectors handled per pass
 constexpr double BREAKDOWN = 1e-14;
+constexpr double SPECULATE = 10.0;   // run ahead while the residual estimate exceeds 10 x the tolerance
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -439,32 +440,54 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     g[0] = beta;
     int k = 0;
     bool breakdown_stop = false;
-    for (int j = 0; j < m; ++j) {
+    // Arnoldi step j on the device; its Hessenberg column lands in host slot
+    // j % 2 and event ev_iter[j % 2] marks its completion.
+    auto launch_step = [&](int j) -> int {
       double* vj = ctx->V + (size_t)j * stride;
       double* zj = ctx->Z + (size_t)j * stride;
       double* w = ctx->V + (size_t)(j + 1) * stride;
+      const int nv = j + 1;
+      double* slot = ctx->hhost_dev + (j & 1) * 128;
       // v_j = w_j / h_{j,j-1} is formed inside the preconditioner's first kernel
       precond_apply(ctx, vj, vj, j == 0 ? nullptr : hd + 128, zj);
       prof_begin(ctx, CPR_KCLASS_SPMV);
       launch_spmv(b, ctx->lay, ctx->J, zj, w, nullptr, s);
       prof_end(ctx, CPR_KCLASS_SPMV);
-      its += 1;
-      int nv = j + 1;
       // CGS pass 1: h1 = V^T w
       orth_pass(ctx, len, nv, w, nullptr, 0);
       reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd, nullptr);
       // w -= V h1 ; h2 = V^T w
       orth_pass(ctx, len, nv, w, hd, 0);
-      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd, ctx->hhost_dev);   // h = h1 + h2
+      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd, slot);   // h = h1 + h2
       reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 192, nullptr);   // h2 alone
       // w -= V h2 ; ||w||^2
       orth_pass(ctx, len, nv, w, hd + 192, 1);
-      reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr, ctx->hhost_dev + 64);
+      reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr, slot + 64);
       CPR_TRY(hipGetLastError());
-      CPR_TRY(hipStreamSynchronize(s));
-      double hn = std::sqrt(ctx->hhost[64]);
+      CPR_TRY(hipEventRecord(ctx->ev_iter[j & 1], s));
+      return CPR_OK;
+    };
+    int launched = -1;
+    for (int j = 0; j < m; ++j) {
+      if (launched < j) {
+        if ((rc = launch_step(j)) != CPR_OK) return rc;
+        launched = j;
+      }
+      its += 1;
+      // While the host waits for step j, the device may already run step
+      // j + 1: it needs nothing from the host.  Done only while the residual
+      // estimate is far above the tolerance, so that a step launched but not
+      // needed (the cycle ends at j) is rare; its results are then ignored.
+      if (j + 1 < m && its < max_iter && std::fabs(g[j]) > SPECULATE * rtol * bnorm) {
+        if ((rc = launch_step(j + 1)) != CPR_OK) return rc;
+        launched = j + 1;
+      }
+      CPR_TRY(hipEventSynchronize(ctx->ev_iter[j & 1]));
+      const double* slot = ctx->hhost + (j & 1) * 128;
+      const int nv = j + 1;
+      double hn = std::sqrt(slot[64]);
       for (int i = 0; i <= m; ++i) col[i] = 0.0;
-      for (int i = 0; i < nv; ++i) col[i] = ctx->hhost[i];
+      for (int i = 0; i < nv; ++i) col[i] = slot[i];
       col[j + 1] = hn;
       double az = 0.0;
       for (int i = 0; i <= j + 1; ++i) az += col[i] * col[i];
@@ -489,6 +512,10 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
       k = j + 1;
       if (std::fabs(g[j + 1]) <= rtol * bnorm || its >= max_iter) break;
       if (hn <= BREAKDOWN * az) { breakdown_stop = true; break; }
+    }
+    if (launched >= k) {
+      // a step ran ahead but the cycle ended: undo its learned-stage count
+      if (ctx->opt.learned) learned_discard_last(ctx);
     }
     (void)breakdown_stop;
     // back substitution H[:k,:k] y = g[:k]

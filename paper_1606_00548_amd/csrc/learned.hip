@@ -232,6 +232,12 @@ __global__ __launch_bounds__(LB) void correct_kernel(Lay L, const double* __rest
   dp[t] = (T)((double)dp[t] + scal[S_ALPHA] * (double)y[i + (long)L.nx * (j + (long)L.ny * k)]);
 }
 
+// Undo the count of the last application (one the solver ran ahead and
+// then did not use).
+__global__ void discard_kernel(const double* __restrict__ scal, int* __restrict__ count) {
+  if (threadIdx.x == 0) count[scal[S_ACC] > 0.0 ? 0 : 1] -= 1;
+}
+
 __global__ void lnk_kernel(Lay L, const double* __restrict__ perm, double* __restrict__ lnk) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= L.n) return;
@@ -286,6 +292,10 @@ static int learned_stage_t(cpr_ctx* ctx, const T* rp, T* dp) {
   alpha_kernel<<<1, LB, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal, ctx->nncount);
   correct_kernel<T><<<div_up(L.n, LB), LB, 0, s>>>(L, ctx->nnscal, y, dp);
   return CPR_OK;
+}
+
+void learned_discard_last(cpr_ctx* ctx) {
+  discard_kernel<<<1, 64, 0, ctx->stream>>>(ctx->nnscal, ctx->nncount);
 }
 
 int learned_stage(cpr_ctx* ctx) {

@@ -24,6 +24,14 @@ to its cited CPR paper:
     a textbook dense block ILU(0)).
   * Composition: r~ = v with r~_0 = w^T v; dp = Vcycle(r~_0);
     r2 = r~ - A~(:, p) dp; y = ILU^-1 r2; z = y + e_0 dp.
+  * ABF decoupling (the alternative the paper names): W_i = D_i^-1 for the
+    diagonal block D_i, A~ = W A (every diagonal block becomes I), r~ = W v,
+    A_p[i][j] = (A~_ij)_00.  The paper's CPR-FPF is defined in its cited
+    reference, which is not part of the paper; it is read here as the
+    multiplicative F-P-F composition of the same two stages:
+    z1 = ILU^-1 r~, then the P-then-F correction of r1 = r~ - A~ z1,
+    z = z1 + that correction, so I - M^-1 A = (I - F A~)(I - C A~)(I - F A~)
+    with F = ILU^-1 and C = e_0 Vcycle e_0^T.
 """
 import numpy as np
 import scipy.linalg
@@ -291,25 +299,67 @@ def ilu_apply(At, Dinv, r):
 
 # ---------------------------------------------------------------- CPR
 
-def cpr_setup(J, coarsest=512):
+def abf(J):
+    """Alternate block factorisation decoupling (named beside quasi-IMPES in
+    Sec. 2.5): W_i = D_i^-1, the inverse of the cell's diagonal block, and
+    A~_ij = D_i^-1 A_ij for every block of the row, so A~_ii = I."""
+    W = _inv_blocks(J[0])
+    At = np.stack([_bmm(W, J[d]) for d in range(7)])
+    return W, At
+
+
+def cpr_setup(J, coarsest=512, decoupling="qimpes"):
+    """CPR preconditioner data: decoupling (quasi-IMPES weights w and rows R0,
+    or ABF blocks W), the decoupled blocks A~, the pressure multigrid on
+    A_p = A~[:, 0, 0] and the red-black block ILU(0) of A~."""
+    if decoupling == "abf":
+        W, At = abf(J)
+        mg = mg_setup(At[:, 0, 0].copy(), coarsest)
+        Dinv = ilu_setup(At)
+        return {"decoupling": "abf", "W": W, "At": At, "mg": mg, "Dinv": Dinv, "nbad": 0}
     w, R0, nbad = quasi_impes(J)
     At = decoupled_blocks(J, R0)
     mg = mg_setup(R0[:, 0].copy(), coarsest)
     Dinv = ilu_setup(At)
-    return {"w": w, "R0": R0, "At": At, "mg": mg, "Dinv": Dinv, "nbad": nbad}
+    return {"decoupling": "qimpes", "w": w, "R0": R0, "At": At, "mg": mg, "Dinv": Dinv, "nbad": nbad}
 
 
-def cpr_apply(pc, v, alpha=1.0):
-    """z = M^-1 v for the two-stage CPR preconditioner."""
-    w, At = pc["w"], pc["At"]
+def decouple(pc, v):
+    """r~ = W v: quasi-IMPES combines the rows into row 0 and keeps the
+    others; ABF multiplies every cell's rows by D_i^-1."""
+    if pc["decoupling"] == "abf":
+        return _bmv(pc["W"], v)
     rt = v.copy()
-    rt[0] = np.sum(w * v, axis=0)
+    rt[0] = np.sum(pc["w"] * v, axis=0)
+    return rt
+
+
+def _two_stage(pc, rt, alpha):
+    """Pressure stage then full-system stage on a decoupled residual rt:
+    dp = V-cycle(rt_p); y = ILU^-1 (rt - A~(:, p) dp); y + e0 dp."""
+    At = pc["At"]
     dp = vcycle(pc["mg"], rt[0], 0, alpha)
     r2 = rt.copy()
     for d in range(7):
         sdp = shift(dp, d)
-        for r in range(v.shape[0]):
+        for r in range(rt.shape[0]):
             r2[r] -= At[d, r, 0] * sdp
     y = ilu_apply(At, pc["Dinv"], r2)
     y[0] += dp
     return y
+
+
+def cpr_apply(pc, v, alpha=1.0, composition="two-stage"):
+    """z = M^-1 v.  Two-stage (P then F): the pressure correction of the
+    decoupled residual, then block ILU(0) on what it leaves.  FPF (the
+    paper's CPR-FPF, Sec. 2.5, read as the multiplicative three-stage
+    composition): z1 = ILU^-1 r~; the two-stage correction of the remaining
+    decoupled residual r1 = r~ - A~ z1 (pressure stage, then ILU of what
+    that leaves); z = z1 + that correction."""
+    rt = decouple(pc, v)
+    if composition == "fpf":
+        At = pc["At"]
+        z1 = ilu_apply(At, pc["Dinv"], rt)
+        r1 = rt - block_spmv(At, z1)
+        return z1 + _two_stage(pc, r1, alpha)
+    return _two_stage(pc, rt, alpha)

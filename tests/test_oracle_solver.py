@@ -320,3 +320,115 @@ def test_cpr_bicgstab_solves_tiny_systems(maker):
     r = to_pointblock(b) - M @ to_pointblock(x)
     assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
     assert np.linalg.norm(to_pointblock(x) - xd) / np.linalg.norm(xd) <= np.linalg.cond(M) * 1e-6
+
+
+# ---- ABF decoupling and the CPR-FPF composition (Sec. 2.5)
+
+def _dense_op(f, n, shape):
+    """Dense matrix of a linear map given on arrays of `shape`, columns in
+    point-block order."""
+    M = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        M[:, c] = to_pointblock(f(from_pointblock(e, shape)))
+    return M
+
+
+def test_abf_decoupling_against_dense():
+    _, J, _ = _system(lambda: synth.black_oil_layered(4, 3, 3, seed=60))
+    W, At = cpr.abf(J)
+    b = J.shape[1]
+    M = dense_from_blocks(J)
+    n = M.shape[0]
+    Dbd = np.zeros_like(M)
+    for c in range(n // b):
+        Dbd[c * b:(c + 1) * b, c * b:(c + 1) * b] = M[c * b:(c + 1) * b, c * b:(c + 1) * b]
+    Mt = np.linalg.solve(Dbd, M)                       # (block diag of A)^-1 A
+    assert np.allclose(dense_from_blocks(At), Mt, rtol=1e-12, atol=1e-12 * np.abs(Mt).max())
+    eye = np.broadcast_to(np.eye(b)[..., None, None, None], At[0].shape)
+    assert np.allclose(At[0], eye, atol=1e-12)
+    pc = cpr.cpr_setup(J, coarsest=16, decoupling="abf")
+    assert np.array_equal(pc["mg"]["levels"][0], At[:, 0, 0])
+    # decouple() is W applied to a vector: W A = A~
+    shape = (b,) + J.shape[3:]
+    Wd = _dense_op(lambda v: cpr.decouple(pc, v), n, shape)
+    assert np.allclose(Wd @ M, Mt, rtol=1e-11, atol=1e-11 * np.abs(Mt).max())
+
+
+@pytest.mark.parametrize("decoupling", ["qimpes", "abf"])
+def test_compositions_are_products_of_stage_error_propagators(decoupling):
+    # With F = ILU(0)^-1 of A~ and C = e0 Vcycle e0^T, multiplicative stages
+    # give I - M^-1 A = (I - F A~)(I - C A~) for P-then-F and
+    # (I - F A~)(I - C A~)(I - F A~) for F-P-F, where M^-1 = B W.
+    _, J, _ = _system(lambda: synth.black_oil_layered(4, 3, 2, seed=61))
+    pc = cpr.cpr_setup(J, coarsest=4, decoupling=decoupling)
+    assert len(pc["mg"]["levels"]) >= 2
+    b = J.shape[1]
+    shape = (b,) + J.shape[3:]
+    M = dense_from_blocks(J)
+    n = M.shape[0]
+    Mt = dense_from_blocks(pc["At"])
+    F = _dense_op(lambda v: cpr.ilu_apply(pc["At"], pc["Dinv"], v), n, shape)
+
+    def coarse(v):
+        z = np.zeros_like(v)
+        z[0] = cpr.vcycle(pc["mg"], v[0])
+        return z
+    C = _dense_op(coarse, n, shape)
+    I = np.eye(n)
+    EF, EC = I - F @ Mt, I - C @ Mt
+    for comp, expect in (("two-stage", EF @ EC), ("fpf", EF @ EC @ EF)):
+        Minv = _dense_op(lambda v: cpr.cpr_apply(pc, v, composition=comp), n, shape)
+        E = I - Minv @ M
+        assert np.allclose(E, expect, atol=1e-9 * max(1.0, np.abs(expect).max())), comp
+    # the extra smoothing stage contracts more on this system
+    rho2 = np.abs(np.linalg.eigvals(EF @ EC)).max()
+    rho3 = np.abs(np.linalg.eigvals(EF @ EC @ EF)).max()
+    assert rho3 < rho2 < 1.0
+
+
+@pytest.mark.parametrize("decoupling", ["qimpes", "abf"])
+@pytest.mark.parametrize("composition", ["two-stage", "fpf"])
+def test_block_diagonal_system_is_inverted_exactly(decoupling, composition):
+    _, J, b = _system(lambda: synth.oil_water_lognormal(4, 4, 2, seed=62))
+    Jd = J.copy()
+    Jd[1:] = 0.0
+    pc = cpr.cpr_setup(Jd, coarsest=4, decoupling=decoupling)
+    z = cpr.cpr_apply(pc, b, composition=composition)
+    assert np.allclose(cpr.block_spmv(Jd, z), b, rtol=1e-10, atol=1e-10 * np.abs(b).max())
+
+
+@pytest.mark.parametrize("composition", ["two-stage", "fpf"])
+def test_abf_single_phase_exact_pressure_solve_is_one_iteration(composition):
+    # b = 1: ABF divides each row by its diagonal; with an exact coarse
+    # solve the pressure stage inverts A~ and FGMRES needs one step.
+    case = synth.single_phase_uniform(6, 5, 4, wells=[synth.well(0, 0, 4, "inj", 300.0),
+                                                       synth.well(5, 4, 4, "prod", 150.0)])
+    x = synth.random_state_perturbation(case, 3)
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"],
+                          case["wells"], case["x_old"], x, case["dt"])
+    pc = cpr.cpr_setup(J, coarsest=10 ** 6, decoupling="abf")
+    assert np.allclose(pc["At"][0], 1.0)
+    dx, st = krylov.fgmres(lambda v: cpr.block_spmv(J, v),
+                           lambda v: cpr.cpr_apply(pc, v, composition=composition), -R, rtol=1e-10)
+    assert st["iterations"] == 1 and st["converged"]
+
+
+@pytest.mark.parametrize("maker", [lambda: synth.oil_water_lognormal(6, 6, 4, seed=50),
+                                   lambda: synth.black_oil_layered(6, 6, 4, seed=51),
+                                   lambda: synth.black_oil_channelised(6, 4, 4, seed=52)])
+@pytest.mark.parametrize("decoupling,composition", [("abf", "two-stage"), ("qimpes", "fpf"),
+                                                    ("abf", "fpf")])
+def test_cpr_variants_solve_tiny_systems(maker, decoupling, composition):
+    case, J, b = _system(maker)
+    pc = cpr.cpr_setup(J, coarsest=16, decoupling=decoupling)
+    M = dense_from_blocks(J)
+    xd = np.linalg.solve(M, to_pointblock(b))
+    for solve in (krylov.fgmres, krylov.bicgstab):
+        x, st = solve(lambda v: cpr.block_spmv(J, v),
+                      lambda v: cpr.cpr_apply(pc, v, composition=composition), b)
+        assert st["converged"]
+        r = to_pointblock(b) - M @ to_pointblock(x)
+        assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
+        assert np.linalg.norm(to_pointblock(x) - xd) / np.linalg.norm(xd) <= np.linalg.cond(M) * 1e-6

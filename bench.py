@@ -143,6 +143,14 @@ def main():
         forms.append(("bicgstab fp64", dict(precision="fp64"), "bicgstab"))
         if os.path.exists(wfile):
             forms.append(("bicgstab mixed+learned", dict(precision="mixed", learned=1), "bicgstab"))
+        # ABF decoupling and the F-P-F composition (CPR-FPF)
+        forms.append(("abf fp64", dict(precision="fp64", decoupling="abf"), "fgmres"))
+        forms.append(("fpf fp64", dict(precision="fp64", composition="fpf"), "fgmres"))
+        forms.append(("fpf mixed", dict(precision="mixed", composition="fpf"), "fgmres"))
+        if os.path.exists(wfile):
+            forms.append(("fpf mixed+learned", dict(precision="mixed", composition="fpf", learned=1), "fgmres"))
+            forms.append(("bicgstab fpf mixed+learned", dict(precision="mixed", composition="fpf", learned=1),
+                          "bicgstab"))
         for name, kw, kry in forms:
             sp, sts, _ = timed(cprmi.default_options(**kw), krylov=kry)
             variants[name] = {"s_per_step": sp, "krylov": kry, "krylov_iterations": sts[-1]["iterations"],

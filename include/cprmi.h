@@ -53,6 +53,19 @@ enum { CPR_MODEL_OIL_WATER = 2, CPR_MODEL_BLACK_OIL = 3 };
 enum { CPR_WELL_INJECTOR = 0, CPR_WELL_PRODUCER = 1 };
 enum { CPR_PREC_FP64 = 0, CPR_PREC_MIXED = 1 };
 
+/* Decoupling of the CPR preconditioner (Sec. 2.5 names both):
+ *   CPR_DECOUPLE_QIMPES  quasi-IMPES: row 0 of every block row becomes
+ *                        w_i^T A_ij with w_i = D_i^-T e_0 / (D_i^-1)_00;
+ *   CPR_DECOUPLE_ABF     alternate block factorisation: every block row is
+ *                        multiplied by D_i^-1, so each diagonal block is I.
+ * D_i is the diagonal block of cell i.  Composition of the two stages:
+ *   CPR_COMPOSE_PF       pressure stage, then block ILU(0) on what it leaves;
+ *   CPR_COMPOSE_FPF      CPR-FPF (Sec. 2.5): block ILU(0), then the pressure
+ *                        stage and block ILU(0) on the remaining residual,
+ *                        all multiplicative. */
+enum { CPR_DECOUPLE_QIMPES = 0, CPR_DECOUPLE_ABF = 1 };
+enum { CPR_COMPOSE_PF = 0, CPR_COMPOSE_FPF = 1 };
+
 /* Structured Cartesian grid: cell sizes in metres, depth of the top face in
  * metres (depth positive downward).  nx must be even: the library stores
  * every per-cell array split by red-black colour along x. */
@@ -102,6 +115,8 @@ typedef struct {
   double rtol;         /* stop when ||b - A dx||_2 <= rtol ||b||_2 (1e-6)    */
   int mg_coarsest;     /* coarsen while a level has more cells (512, <= 4096) */
   double mg_alpha;     /* coarse-correction scaling (1.0)                    */
+  int decoupling;      /* CPR_DECOUPLE_QIMPES (default) or CPR_DECOUPLE_ABF  */
+  int composition;     /* CPR_COMPOSE_PF (default) or CPR_COMPOSE_FPF        */
 } cpr_options_t;
 
 typedef struct {
@@ -153,12 +168,14 @@ int assemble_jacobian(cpr_ctx_t* ctx, const double* x_old, const double* x, doub
 int cpr_import_jacobian(cpr_ctx_t* ctx, const double* blocks);
 int cpr_export_jacobian(cpr_ctx_t* ctx, double* blocks);
 
-/* Build the CPR preconditioner for the current Jacobian: quasi-IMPES
- * weights and decoupled rows, the pressure multigrid hierarchy (2x2x2
- * aggregation, Galerkin coarse operators, dense inverse of the coarsest
- * level) and the red-black block ILU(0) diagonals.  Synchronises the stream
- * (to report singular blocks).  Returns CPR_ESINGULAR if a diagonal block
- * or the coarsest operator cannot be inverted. */
+/* Build the CPR preconditioner for the current Jacobian: the decoupling
+ * (quasi-IMPES weights and decoupled rows, or the ABF inverses D_i^-1 and
+ * the blocks D_i^-1 A_ij), the pressure multigrid hierarchy on
+ * A_p = (A~)_pp (2x2x2 aggregation, Galerkin coarse operators, dense
+ * inverse of the coarsest level) and the red-black block ILU(0) diagonals
+ * of A~.  Synchronises the stream (to report singular blocks).  Returns
+ * CPR_ESINGULAR if a diagonal block or the coarsest operator cannot be
+ * inverted, CPR_EINVAL for an unknown decoupling or composition. */
 int cpr_setup(cpr_ctx_t* ctx, const cpr_options_t* o);
 
 /* Solve A dx = rhs (both device, [b][n]) from dx = 0 with FGMRES(restart)
@@ -193,7 +210,7 @@ int cpr_spmv(cpr_ctx_t* ctx, const double* x, double* y);
 int cpr_precond_apply(cpr_ctx_t* ctx, const double* v, double* z);
 
 /* Setup products, for verification (device outputs, natural order):
- * quasi-IMPES weights w [b][n]; the scalar 7-point operator of multigrid
+ * quasi-IMPES weights w [b][n] (CPR_EINVAL under ABF); the scalar 7-point operator of multigrid
  * level `level` as [7][n_level] (natural order of that level's grid);
  * the inverted ILU diagonals D'^-1 as [b][b][n]. */
 int cpr_export_qimpes(cpr_ctx_t* ctx, double* w);
@@ -287,7 +304,8 @@ int cpr_nn_attach(cpr_ctx_t* ctx, const float* theta);
 
 /* The pressure stage on one vector, for building training data (device,
  * natural order): r~_p = w^T v; dp_mg = V-cycle(r~_p); rprime = r~_p -
- * A_p dp_mg ([n] each; dp_mg may be NULL).  After cpr_setup. */
+ * A_p dp_mg ([n] each; dp_mg may be NULL).  After cpr_setup with
+ * quasi-IMPES decoupling (CPR_EINVAL otherwise). */
 int cpr_pressure_stage(cpr_ctx_t* ctx, const double* v, double* rprime, double* dp_mg);
 
 /* Network input for a pressure residual rprime (device [n]): feat device

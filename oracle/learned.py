@@ -16,12 +16,17 @@ import numpy as np
 from . import cpr, model, nn
 
 
-def pressure_stage(pc, v):
-    """(r', dp_mg, r~_p) for one vector v[b, grid]."""
-    rt0 = np.sum(pc["w"] * v, axis=0)
+def _pressure_stage_rt(pc, rt0):
     dp = cpr.vcycle(pc["mg"], rt0)
     Ap = pc["mg"]["levels"][0]
-    return rt0 - cpr.scalar_spmv(Ap, dp), dp, rt0
+    return rt0 - cpr.scalar_spmv(Ap, dp), dp
+
+
+def pressure_stage(pc, v):
+    """(r', dp_mg, r~_p) for one vector v[b, grid]."""
+    rt0 = cpr.decouple(pc, v)[0]
+    rp, dp = _pressure_stage_rt(pc, rt0)
+    return rp, dp, rt0
 
 
 def _standardise(f):
@@ -42,12 +47,20 @@ def features(perm_md, lam_t, Ap, rprime):
     return np.stack([_standardise(np.log(perm_md[0])), _standardise(np.log(lam_t)), f2], axis=-1), s
 
 
-def learned_cpr_apply(pc, v, theta, perm_md, lam_t):
-    """CPR application with the judged network correction; returns
-    (z, accepted)."""
-    w, At = pc["w"], pc["At"]
+def learned_cpr_apply(pc, v, theta, perm_md, lam_t, composition="two-stage"):
+    """CPR application with the judged network correction in the pressure
+    stage; returns (z, accepted).  With composition "fpf" the pressure stage
+    sees the residual left by the first block ILU(0) stage, as in
+    cpr.cpr_apply."""
+    At = pc["At"]
     Ap = pc["mg"]["levels"][0]
-    rp, dp, rt0 = pressure_stage(pc, v)
+    rt = cpr.decouple(pc, v)
+    z1 = None
+    if composition == "fpf":
+        z1 = cpr.ilu_apply(At, pc["Dinv"], rt)
+        rt = rt - cpr.block_spmv(At, z1)
+    rt0 = rt[0]
+    rp, dp = _pressure_stage_rt(pc, rt0)
     feat, s = features(perm_md, lam_t, Ap, rp)
     y, _ = nn.forward(theta, feat[None])
     d = y[0]
@@ -58,12 +71,13 @@ def learned_cpr_apply(pc, v, theta, perm_md, lam_t):
     accepted = np.linalg.norm(rp - cpr.scalar_spmv(Ap, dpnn)) < np.linalg.norm(rp)
     if accepted:
         dp = dp + dpnn
-    r2 = v.copy()
-    r2[0] = rt0
+    r2 = rt.copy()
     for d in range(7):
         sdp = cpr.shift(dp, d)
         for r in range(v.shape[0]):
             r2[r] -= At[d, r, 0] * sdp
     z = cpr.ilu_apply(At, pc["Dinv"], r2)
     z[0] += dp
+    if z1 is not None:
+        z = z1 + z
     return z, accepted

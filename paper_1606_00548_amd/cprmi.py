@@ -20,6 +20,8 @@ CPR_OK, CPR_NOT_CONVERGED = 0, 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENONFINITE",
           -6: "EBREAKDOWN"}
 PREC = {"fp64": 0, "mixed": 1}
+DECOUPLING = {"qimpes": 0, "abf": 1}
+COMPOSITION = {"two-stage": 0, "fpf": 1}
 
 
 class Grid(ctypes.Structure):
@@ -47,7 +49,7 @@ class Well(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("learned", ctypes.c_int), ("restart", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double), ("mg_coarsest", ctypes.c_int),
-                ("mg_alpha", ctypes.c_double)]
+                ("mg_alpha", ctypes.c_double), ("decoupling", ctypes.c_int), ("composition", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -225,6 +227,10 @@ def default_options(**kw):
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = PREC[v]
+        if k == "decoupling" and isinstance(v, str):
+            v = DECOUPLING[v]
+        if k == "composition" and isinstance(v, str):
+            v = COMPOSITION[v]
         setattr(o, k, v)
     return o
 

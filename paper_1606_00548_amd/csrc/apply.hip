@@ -6,6 +6,11 @@
 //   y    = (D' + L)^-1 r2 ;  z = y - D'^-1 U z     (red-black block ILU(0))
 //   z_0 += dp
 //
+// Variants (Sec. 2.5 names both): ABF decoupling r~ = D^-1 v per cell with
+// A~ = D^-1 A, and the F-P-F composition, which first applies the block
+// ILU(0) to r~ (z1), runs the two stages above on r1 = r~ - A~ z1 and adds
+// z1 to the result.
+//
 // Kernels are templated on the preconditioner's scalar type T: double for
 // the FP64 path, float for the mixed-precision path (v and z stay FP64 at
 // the boundary; the coarsest pressure solve is always FP64).  Every colour
@@ -34,7 +39,9 @@ struct Pre;
 template <>
 struct Pre<double> {
   static const double* R0(const cpr_ctx* c) { return c->R0; }
-  static const double* J(const cpr_ctx* c) { return c->J; }
+  static const double* J(const cpr_ctx* c) { return c->opt.decoupling == CPR_DECOUPLE_ABF ? c->Jt : c->J; }
+  static double* Rt(cpr_ctx* c) { return c->Rt; }
+  static double* Z1(cpr_ctx* c) { return c->Z1; }
   static const double* Dinv(const cpr_ctx* c) { return c->Dinv; }
   static const double* A(const MGLevel& l) { return l.A; }
   static double* x(MGLevel& l) { return l.x; }
@@ -46,6 +53,8 @@ template <>
 struct Pre<float> {
   static const float* R0(const cpr_ctx* c) { return c->Jf; }   // unused: full FP32 blocks
   static const float* J(const cpr_ctx* c) { return c->Jf; }
+  static float* Rt(cpr_ctx* c) { return c->Rtf; }
+  static float* Z1(cpr_ctx* c) { return c->Z1f; }
   static const float* Dinv(const cpr_ctx* c) { return c->Dinvf; }
   static const float* A(const MGLevel& l) { return l.Af; }
   static float* x(MGLevel& l) { return l.xf; }
@@ -202,6 +211,72 @@ __global__ __launch_bounds__(256) void decouple_red_kernel(int n, int nh, const 
   if (t < nh) x[t] = rs / A[t];
 }
 
+// Decoupling for ABF or for the F-P-F composition: r~ = W v per cell (ABF:
+// the b x b block D_i^-1; quasi-IMPES: row 0 becomes w^T v).  Two-stage
+// (P then F): r~_0 and the zero-guess red sweep as above, rows >= 1 into Rt.
+// F-P-F: all of r~ into Rt, and on red cells the forward ILU step
+// Z1 = D'^-1 r~ (red cells have no lower neighbours).
+template <int B, typename T, bool ABF, bool FPF>
+__global__ __launch_bounds__(256) void decouple_full_kernel(int n, int nh, const double* __restrict__ w,
+                                                            const double* vin, double* vout,
+                                                            const double* __restrict__ nrm2,
+                                                            const T* __restrict__ A, const T* __restrict__ Dinv,
+                                                            T* __restrict__ rp, T* __restrict__ x,
+                                                            T* __restrict__ Rt, T* __restrict__ Z1) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const size_t N = n;
+  double hn = nrm2 ? sqrt(*nrm2) : 1.0;
+  double v[B], rt[B];
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    v[r] = vin[(size_t)r * N + t];
+    if (nrm2) {
+      v[r] = v[r] / hn;
+      vout[(size_t)r * N + t] = v[r];
+    }
+  }
+  if constexpr (ABF) {
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < B; ++c) s += w[((size_t)r * B + c) * N + t] * v[c];
+      rt[r] = s;
+    }
+  } else {
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < B; ++r) s += w[(size_t)r * N + t] * v[r];
+    rt[0] = s;
+#pragma unroll
+    for (int r = 1; r < B; ++r) rt[r] = v[r];
+  }
+  if constexpr (FPF) {
+    T rr[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      rr[r] = (T)rt[r];
+      Rt[(size_t)r * N + t] = rr[r];
+    }
+    if (t < nh) {
+#pragma unroll
+      for (int r = 0; r < B; ++r) {
+        T a = 0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) a += Dinv[((size_t)r * B + c) * N + t] * rr[c];
+        Z1[(size_t)r * N + t] = a;
+      }
+    }
+  } else {
+    T r0 = (T)rt[0];
+    rp[t] = r0;
+    if (t < nh) x[t] = r0 / A[t];
+#pragma unroll
+    for (int r = 1; r < B; ++r) Rt[(size_t)r * N + t] = (T)rt[r];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void red_zero_kernel(Lay L, const T* __restrict__ A, const T* __restrict__ r,
                                                        T* __restrict__ x) {
@@ -334,9 +409,9 @@ __global__ __launch_bounds__(1024) void coarse_cycle_kernel(CoarseArgs<T> a) {
 // ------------------------------------------------------------ stage 2 + block ILU(0)
 
 // Stage-2 residual r2 = r~ - A~(:, p) dp at cell t.
-template <int B, typename T>
+template <int B, typename T, typename VT>
 __device__ inline void stage2_resid(const Lay& L, int t, const CsCell& cc, const T* J, const T* R0,
-                                    const double* __restrict__ v, const T* __restrict__ rp,
+                                    const VT* __restrict__ v, const T* __restrict__ rp,
                                     const T* __restrict__ dp, T (&r2)[B]) {
   const size_t N = L.n;
   int nbr[7];
@@ -404,19 +479,24 @@ __device__ inline void dinv_apply(const T* __restrict__ Dinv, size_t N, int t, c
   }
 }
 
+// Stage 2 reads rows >= 1 of the decoupled residual from v: the Krylov
+// vector itself for quasi-IMPES P-then-F (VT = double), the decoupled
+// residual Rt otherwise (VT = T).  With z1 given (F-P-F) the first stage's
+// result is added to z.
+
 // red cells: forward ILU step y_r = D'^-1 r2_r (no lower neighbours)
-template <int B, typename T>
+template <int B, typename T, typename VT>
 __global__ __launch_bounds__(256) void stage2_red_fwd_kernel(Lay L, const T* __restrict__ J,
                                                              const T* __restrict__ R0,
                                                              const T* __restrict__ Dinv,
-                                                             const double* __restrict__ v,
+                                                             const VT* __restrict__ v,
                                                              const T* __restrict__ rp,
                                                              const T* __restrict__ dp, T* __restrict__ Y) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= L.nh) return;
   CsCell cc = cs_decode(L, t);
   T r2[B], y[B];
-  stage2_resid<B, T>(L, t, cc, J, R0, v, rp, dp, r2);
+  stage2_resid<B, T, VT>(L, t, cc, J, R0, v, rp, dp, r2);
   dinv_apply<B, T>(Dinv, L.n, t, r2, y);
 #pragma unroll
   for (int r = 0; r < B; ++r) Y[(size_t)r * L.n + t] = y[r];
@@ -424,13 +504,14 @@ __global__ __launch_bounds__(256) void stage2_red_fwd_kernel(Lay L, const T* __r
 
 // black cells: y_b = D'^-1 (r2_b - sum_red A~_bk y_k); no upper neighbours,
 // so z_b = y_b (+ dp on the pressure unknown)
-template <int B, typename T>
+template <int B, typename T, typename VT>
 __global__ __launch_bounds__(256) void stage2_black_kernel(Lay L, const T* __restrict__ J,
                                                            const T* __restrict__ R0,
                                                            const T* __restrict__ Dinv,
-                                                           const double* __restrict__ v,
+                                                           const VT* __restrict__ v,
                                                            const T* __restrict__ rp,
                                                            const T* __restrict__ dp, T* __restrict__ Y,
+                                                           const T* __restrict__ z1,
                                                            double* __restrict__ z) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= L.nh) return;
@@ -488,6 +569,10 @@ __global__ __launch_bounds__(256) void stage2_black_kernel(Lay L, const T* __res
   z[t] = (double)y[0] + (double)dp[t];
 #pragma unroll
   for (int r = 1; r < B; ++r) z[r * N + t] = (double)y[r];
+  if (z1) {
+#pragma unroll
+    for (int r = 0; r < B; ++r) z[r * N + t] += (double)z1[r * N + t];
+  }
 }
 
 // red cells, backward step: z_r = y_r - D'^-1 sum_black A~_rk y_k
@@ -497,6 +582,7 @@ __global__ __launch_bounds__(256) void stage2_red_bwd_kernel(Lay L, const T* __r
                                                              const T* __restrict__ Dinv,
                                                              const T* __restrict__ dp,
                                                              const T* __restrict__ Y,
+                                                             const T* __restrict__ z1,
                                                              double* __restrict__ z) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= L.nh) return;
@@ -508,6 +594,84 @@ __global__ __launch_bounds__(256) void stage2_red_bwd_kernel(Lay L, const T* __r
   z[t] = (double)(Y[t] - u[0]) + (double)dp[t];
 #pragma unroll
   for (int r = 1; r < B; ++r) z[r * N + t] = (double)(Y[r * N + t] - u[r]);
+  if (z1) {
+#pragma unroll
+    for (int r = 0; r < B; ++r) z[r * N + t] += (double)z1[r * N + t];
+  }
+}
+
+// ------------------------------------------------------------ F-P-F first stage
+// z1 = ILU(0)^-1 r~ and the residual r1 = r~ - A~ z1 that the P-then-F
+// stages then see.  ILU(0) on the 7-point graph differs from A~ only between
+// black cells two steps apart (through a red cell), so r1 vanishes on red
+// cells: the red backward kernel stores those zeros (and the matching zero
+// initial red sweep of the V-cycle), the residual kernel runs on black cells.
+
+// black cells: z1_b = y_b = D'^-1 (r~_b - sum_red A~_bk y_k)
+template <int B, typename T>
+__global__ __launch_bounds__(256) void fpf_black_kernel(Lay L, const T* __restrict__ J, const T* __restrict__ R0,
+                                                        const T* __restrict__ Dinv, const T* __restrict__ Rt,
+                                                        T* __restrict__ Z1) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= L.nh) return;
+  int t = L.nh + q;
+  CsCell cc = cs_decode(L, t);
+  const size_t N = L.n;
+  T s[B], r[B], y[B];
+  offdiag_apply<B, T>(L, t, cc, J, R0, Z1, s);
+#pragma unroll
+  for (int e = 0; e < B; ++e) r[e] = Rt[e * N + t] - s[e];
+  dinv_apply<B, T>(Dinv, L.n, t, r, y);
+#pragma unroll
+  for (int e = 0; e < B; ++e) Z1[e * N + t] = y[e];
+}
+
+// red cells: z1_r = y_r - D'^-1 sum_black A~_rk z1_k; r1_r = 0 (rows of Rt,
+// the pressure right-hand side and the zero-guess red sweep of level 0)
+template <int B, typename T>
+__global__ __launch_bounds__(256) void fpf_red_bwd_kernel(Lay L, const T* __restrict__ J, const T* __restrict__ R0,
+                                                          const T* __restrict__ Dinv, T* __restrict__ Z1,
+                                                          T* __restrict__ Rt, T* __restrict__ rp,
+                                                          T* __restrict__ x) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L.nh) return;
+  CsCell cc = cs_decode(L, t);
+  const size_t N = L.n;
+  T s[B], u[B];
+  offdiag_apply<B, T>(L, t, cc, J, R0, Z1, s);
+  dinv_apply<B, T>(Dinv, L.n, t, s, u);
+#pragma unroll
+  for (int e = 0; e < B; ++e) {
+    Z1[e * N + t] = Z1[e * N + t] - u[e];
+    Rt[e * N + t] = (T)0;
+  }
+  rp[t] = (T)0;
+  x[t] = (T)0;
+}
+
+// black cells: r1_b = r~_b - A~_bb z1_b - sum_red A~_bk z1_k; row 0 is the
+// pressure right-hand side, rows >= 1 overwrite Rt
+template <int B, typename T>
+__global__ __launch_bounds__(256) void fpf_resid_kernel(Lay L, const T* __restrict__ J, const T* __restrict__ R0,
+                                                        const T* __restrict__ Z1, T* __restrict__ Rt,
+                                                        T* __restrict__ rp) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= L.nh) return;
+  int t = L.nh + q;
+  CsCell cc = cs_decode(L, t);
+  const size_t N = L.n;
+  T s[B], r[B];
+  offdiag_apply<B, T>(L, t, cc, J, R0, Z1, s);
+#pragma unroll
+  for (int e = 0; e < B; ++e) {
+    T a = s[e];
+#pragma unroll
+    for (int c = 0; c < B; ++c) a += at_blk<B, T>(J, R0, N, 0, e, c, t) * Z1[c * N + t];
+    r[e] = Rt[e * N + t] - a;
+  }
+  rp[t] = r[0];
+#pragma unroll
+  for (int e = 1; e < B; ++e) Rt[e * N + t] = r[e];
 }
 
 // ------------------------------------------------------------ host side
@@ -572,25 +736,65 @@ void vcycle(cpr_ctx* ctx) {
   }
 }
 
-template <int B, typename T>
-void apply_impl(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, double* z) {
+template <int B, typename T, typename VT>
+void stage2(cpr_ctx* ctx, const VT* vr, const T* z1, double* z) {
   hipStream_t s = ctx->stream;
   const Lay& L = ctx->lay;
   MGLevel& L0 = ctx->levels[0];
-  T* rp = Pre<T>::r(L0);
-  decouple_red_kernel<B, T><<<div_up(L.n, 256), 256, 0, s>>>(L.n, L.nh, ctx->w, vin, v, nrm2, Pre<T>::A(L0),
-                                                            rp, Pre<T>::x(L0));
-  vcycle<T>(ctx);
-  if (ctx->opt.learned) learned_stage(ctx);
+  const T* rp = Pre<T>::r(L0);
   const T* dp = Pre<T>::x(L0);
   const T* J = Pre<T>::J(ctx);
   const T* R0 = Pre<T>::R0(ctx);
   const T* Dinv = Pre<T>::Dinv(ctx);
   T* Y = Pre<T>::Y(ctx);
   int nh = div_up(L.nh, 256);
-  TIMED(CPR_KCLASS_ILU, (stage2_red_fwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, v, rp, dp, Y)));
-  TIMED(CPR_KCLASS_ILU, (stage2_black_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, v, rp, dp, Y, z)));
-  TIMED(CPR_KCLASS_ILU, (stage2_red_bwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, dp, Y, z)));
+  TIMED(CPR_KCLASS_ILU, (stage2_red_fwd_kernel<B, T, VT><<<nh, 256, 0, s>>>(L, J, R0, Dinv, vr, rp, dp, Y)));
+  TIMED(CPR_KCLASS_ILU, (stage2_black_kernel<B, T, VT><<<nh, 256, 0, s>>>(L, J, R0, Dinv, vr, rp, dp, Y, z1, z)));
+  TIMED(CPR_KCLASS_ILU, (stage2_red_bwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, dp, Y, z1, z)));
+}
+
+template <int B, typename T, bool ABF, bool FPF>
+void apply_variant(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, double* z) {
+  hipStream_t s = ctx->stream;
+  const Lay& L = ctx->lay;
+  MGLevel& L0 = ctx->levels[0];
+  T* rp = Pre<T>::r(L0);
+  T* x0 = Pre<T>::x(L0);
+  T* Rt = Pre<T>::Rt(ctx);
+  T* Z1 = Pre<T>::Z1(ctx);
+  const T* J = Pre<T>::J(ctx);
+  const T* R0 = Pre<T>::R0(ctx);
+  const T* Dinv = Pre<T>::Dinv(ctx);
+  const double* w = ABF ? ctx->Wabf : ctx->w;
+  decouple_full_kernel<B, T, ABF, FPF><<<div_up(L.n, 256), 256, 0, s>>>(L.n, L.nh, w, vin, v, nrm2, Pre<T>::A(L0),
+                                                                        Dinv, rp, x0, Rt, Z1);
+  if (FPF) {
+    int nh = div_up(L.nh, 256);
+    TIMED(CPR_KCLASS_ILU, (fpf_black_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, Rt, Z1)));
+    TIMED(CPR_KCLASS_ILU, (fpf_red_bwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, Z1, Rt, rp, x0)));
+    TIMED(CPR_KCLASS_ILU, (fpf_resid_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Z1, Rt, rp)));
+  }
+  vcycle<T>(ctx);
+  if (ctx->opt.learned) learned_stage(ctx);
+  stage2<B, T, T>(ctx, Rt, FPF ? Z1 : nullptr, z);
+}
+
+template <int B, typename T>
+void apply_impl(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, double* z) {
+  const bool abf = ctx->opt.decoupling == CPR_DECOUPLE_ABF;
+  const bool fpf = ctx->opt.composition == CPR_COMPOSE_FPF;
+  if (abf && fpf) return apply_variant<B, T, true, true>(ctx, vin, v, nrm2, z);
+  if (abf) return apply_variant<B, T, true, false>(ctx, vin, v, nrm2, z);
+  if (fpf) return apply_variant<B, T, false, true>(ctx, vin, v, nrm2, z);
+  hipStream_t s = ctx->stream;
+  const Lay& L = ctx->lay;
+  MGLevel& L0 = ctx->levels[0];
+  decouple_red_kernel<B, T><<<div_up(L.n, 256), 256, 0, s>>>(L.n, L.nh, ctx->w, vin, v, nrm2, Pre<T>::A(L0),
+                                                            Pre<T>::r(L0), Pre<T>::x(L0));
+  vcycle<T>(ctx);
+  if (ctx->opt.learned) learned_stage(ctx);
+  // rows >= 1 of the quasi-IMPES decoupled residual are those of v
+  stage2<B, T, double>(ctx, v, nullptr, z);
 }
 
 // FP32 copies: decoupled blocks (row 0 from R0), ILU diagonals, MG levels.
@@ -620,10 +824,11 @@ __global__ void to_float_kernel(size_t n, const double* __restrict__ a, float* _
 void launch_mixed_copies(cpr_ctx* ctx) {
   hipStream_t s = ctx->stream;
   int n = ctx->lay.n;
+  const double* J = Pre<double>::J(ctx);
   if (ctx->b == 2)
-    mixed_copy_kernel<2><<<div_up(n, 256), 256, 0, s>>>(n, ctx->J, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf);
+    mixed_copy_kernel<2><<<div_up(n, 256), 256, 0, s>>>(n, J, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf);
   else
-    mixed_copy_kernel<3><<<div_up(n, 256), 256, 0, s>>>(n, ctx->J, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf);
+    mixed_copy_kernel<3><<<div_up(n, 256), 256, 0, s>>>(n, J, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf);
   for (auto& L : ctx->levels) {
     size_t m = (size_t)7 * L.lay.n;
     to_float_kernel<<<div_up((long)m, 256), 256, 0, s>>>(m, L.A, L.Af);

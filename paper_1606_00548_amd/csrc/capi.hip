@@ -43,7 +43,7 @@ void free_all(cpr_ctx* ctx) {
                   ctx->w, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf, ctx->flag, ctx->V, ctx->Z,
                   ctx->Y, ctx->rp, ctx->xs, ctx->rs, ctx->tmp, ctx->vf, ctx->zf, ctx->Yf, ctx->rpf,
                   ctx->part, ctx->hdev, ctx->lnk, ctx->rprime, ctx->qbuf, ctx->feat, ctx->nnscal,
-                  ctx->nncount};
+                  ctx->nncount, ctx->Wabf, ctx->Jt, ctx->Rt, ctx->Rtf, ctx->Z1, ctx->Z1f};
   for (void* b : bufs)
     if (b) hipFree(b);
   if (ctx->hhost) hipHostFree(ctx->hhost);
@@ -221,6 +221,26 @@ int ensure_krylov(cpr_ctx* ctx, int m) {
   return CPR_OK;
 }
 
+// Buffers of the ABF decoupling and of the F-P-F composition, allocated on
+// first use.
+int ensure_variants(cpr_ctx* ctx, const cpr_options_t& o) {
+  size_t N = ctx->lay.n;
+  int b = ctx->b, rc;
+  if (o.decoupling == CPR_DECOUPLE_ABF && !ctx->Jt) {
+    if ((rc = dalloc(ctx, &ctx->Wabf, (size_t)b * b * N)) != CPR_OK) return rc;
+    if ((rc = dalloc(ctx, &ctx->Jt, 7 * (size_t)b * b * N)) != CPR_OK) return rc;
+  }
+  if (o.decoupling == CPR_DECOUPLE_ABF || o.composition == CPR_COMPOSE_FPF) {
+    if (!ctx->Rt && (rc = dalloc(ctx, &ctx->Rt, (size_t)b * N)) != CPR_OK) return rc;
+    if (!ctx->Z1 && (rc = dalloc(ctx, &ctx->Z1, (size_t)b * N)) != CPR_OK) return rc;
+    if (o.precision == CPR_PREC_MIXED) {
+      if (!ctx->Rtf && (rc = dalloc(ctx, &ctx->Rtf, (size_t)b * N)) != CPR_OK) return rc;
+      if (!ctx->Z1f && (rc = dalloc(ctx, &ctx->Z1f, (size_t)b * N)) != CPR_OK) return rc;
+    }
+  }
+  return CPR_OK;
+}
+
 int ensure_mixed(cpr_ctx* ctx) {
   if (ctx->Jf) return CPR_OK;
   size_t N = ctx->lay.n;
@@ -254,6 +274,8 @@ void cpr_default_options(cpr_options_t* o) {
   o->rtol = 1e-6;
   o->mg_coarsest = 512;
   o->mg_alpha = 1.0;
+  o->decoupling = CPR_DECOUPLE_QIMPES;
+  o->composition = CPR_COMPOSE_PF;
 }
 
 int cpr_create(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, const double* poro,
@@ -333,12 +355,17 @@ int cpr_setup(cpr_ctx_t* ctx, const cpr_options_t* o) {
     return set_err(ctx, CPR_EINVAL, "mg_coarsest must be 1..4096");
   if (opt.precision != CPR_PREC_FP64 && opt.precision != CPR_PREC_MIXED)
     return set_err(ctx, CPR_EINVAL, "unknown precision");
+  if (opt.decoupling != CPR_DECOUPLE_QIMPES && opt.decoupling != CPR_DECOUPLE_ABF)
+    return set_err(ctx, CPR_EINVAL, "unknown decoupling");
+  if (opt.composition != CPR_COMPOSE_PF && opt.composition != CPR_COMPOSE_FPF)
+    return set_err(ctx, CPR_EINVAL, "unknown composition");
   if (opt.learned && !ctx->nn) return set_err(ctx, CPR_EINVAL, "no pressure-correction network attached");
   ctx->opt = opt;
   ctx->setup_done = 0;
   int rc;
   if ((rc = ensure_krylov(ctx, opt.restart)) != CPR_OK) return rc;
   if (opt.precision == CPR_PREC_MIXED && (rc = ensure_mixed(ctx)) != CPR_OK) return rc;
+  if ((rc = ensure_variants(ctx, opt)) != CPR_OK) return rc;
   if ((rc = setup_cpr(ctx)) != CPR_OK) return rc;
   if (opt.learned) {
     if ((rc = learned_setup(ctx, true)) != CPR_OK) {
@@ -432,6 +459,8 @@ int cpr_pressure_stage(cpr_ctx_t* ctx, const double* v, double* rprime, double* 
   if (check_ctx(ctx)) return CPR_EINVAL;
   if (!v || !rprime) return set_err(ctx, CPR_EINVAL, "null argument");
   if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
+  if (ctx->opt.decoupling != CPR_DECOUPLE_QIMPES)
+    return set_err(ctx, CPR_EINVAL, "the pressure stage export needs quasi-IMPES decoupling");
   hipStream_t s = ctx->stream;
   launch_nat_to_cs(ctx->lay, ctx->b, v, ctx->vin, s);
   precond_pressure_stage(ctx, ctx->vin);
@@ -498,6 +527,7 @@ int cpr_precond_apply(cpr_ctx_t* ctx, const double* v, double* z) {
 int cpr_export_qimpes(cpr_ctx_t* ctx, double* w) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   if (!w || !ctx->setup_done) return set_err(ctx, CPR_EINVAL, "null argument or no setup");
+  if (ctx->opt.decoupling != CPR_DECOUPLE_QIMPES) return set_err(ctx, CPR_EINVAL, "not quasi-IMPES decoupling");
   launch_cs_to_nat(ctx->lay, ctx->b, ctx->w, w, ctx->stream);
   return launch_check(ctx, "cpr_export_qimpes");
 }

@@ -195,6 +195,12 @@ struct cpr_ctx {
   int setup_done = 0;
   double* w = nullptr;         // [b][n]   quasi-IMPES weights
   double* R0 = nullptr;        // [7][b][n] row 0 of the decoupled blocks
+  double* Wabf = nullptr;      // [b][b][n] ABF decoupling D_i^-1
+  double* Jt = nullptr;        // [7][b][b][n] ABF decoupled blocks (rows >= 1; row 0 in R0)
+  double* Rt = nullptr;        // [b][n] decoupled residual (ABF / FPF)
+  float* Rtf = nullptr;
+  double* Z1 = nullptr;        // [b][n] first ILU stage of CPR-FPF
+  float* Z1f = nullptr;
   double* Dinv = nullptr;      // [b][b][n] inverted ILU diagonals
   float* Jf = nullptr;         // FP32 copy of the decoupled blocks [7][b][b][n]
   float* Dinvf = nullptr;

@@ -8,6 +8,8 @@
 //  * Pressure multigrid: A_p = (W A)_{pp}; 2x2x2 aggregation with Galerkin
 //    coarse operators P^T A P, which stay 7-point; the coarsest level is
 //    inverted densely (Gauss-Jordan with partial pivoting).
+//  * or ABF: W_i = D_i^-1 for the diagonal block D_i, A~ = W A in full (each
+//    diagonal block becomes I); a singular D_i is an error.
 //  * Block ILU(0) of W A in red-then-black order: on the 7-point graph it
 //    keeps every off-diagonal block and changes only the black diagonals,
 //    D'_i = A~_ii - sum_k A~_ik D'_k^-1 A~_ki over the red neighbours k.
@@ -115,6 +117,41 @@ __global__ void qimpes_kernel(int n, const double* __restrict__ J, double* __res
       R0[((size_t)d * B + c) * N + t] = s;
       if (c == 0) Ap[(size_t)d * N + t] = s;
     }
+  }
+}
+
+// ABF decoupling: W_i = D_i^-1 and A~_ij = W_i A_ij for the seven blocks of
+// block row i; row 0 of every decoupled block goes to R0 (and its (0, 0)
+// entry to the pressure operator), rows >= 1 to Jt.  A singular diagonal
+// block raises the flag.
+template <int B>
+__global__ void abf_kernel(int n, const double* __restrict__ J, double* __restrict__ W,
+                           double* __restrict__ R0, double* __restrict__ Jt, double* __restrict__ Ap,
+                           int* __restrict__ flag) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const size_t N = n;
+  double D[B][B], inv[B][B];
+  for (int r = 0; r < B; ++r)
+    for (int c = 0; c < B; ++c) D[r][c] = J[((size_t)r * B + c) * N + t];
+  if (!small_inverse<B>(D, inv)) atomicExch(flag, 1);
+  for (int r = 0; r < B; ++r)
+    for (int c = 0; c < B; ++c) W[((size_t)r * B + c) * N + t] = inv[r][c];
+  for (int d = 0; d < 7; ++d) {
+    double a[B][B];
+    for (int r = 0; r < B; ++r)
+      for (int c = 0; c < B; ++c) a[r][c] = J[((size_t)(d * B + r) * B + c) * N + t];
+    for (int r = 0; r < B; ++r)
+      for (int c = 0; c < B; ++c) {
+        double s = 0.0;
+        for (int m = 0; m < B; ++m) s += inv[r][m] * a[m][c];
+        if (r == 0) {
+          R0[((size_t)d * B + c) * N + t] = s;
+          if (c == 0) Ap[(size_t)d * N + t] = s;
+        } else {
+          Jt[((size_t)(d * B + r) * B + c) * N + t] = s;
+        }
+      }
   }
 }
 
@@ -533,10 +570,19 @@ int setup_cpr(cpr_ctx* ctx) {
   const int n = L.n;
   zero_int_kernel<<<1, 64, 0, s>>>(ctx->flag, 2);
   int nb = div_up(n, 256);
-  if (ctx->b == 2)
+  const bool abf = ctx->opt.decoupling == CPR_DECOUPLE_ABF;
+  if (abf) {
+    if (ctx->b == 2)
+      abf_kernel<2><<<nb, 256, 0, s>>>(n, ctx->J, ctx->Wabf, ctx->R0, ctx->Jt, ctx->levels[0].A, ctx->flag);
+    else
+      abf_kernel<3><<<nb, 256, 0, s>>>(n, ctx->J, ctx->Wabf, ctx->R0, ctx->Jt, ctx->levels[0].A, ctx->flag);
+  } else if (ctx->b == 2) {
     qimpes_kernel<2><<<nb, 256, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
-  else
+  } else {
     qimpes_kernel<3><<<nb, 256, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
+  }
+  // rows >= 1 of the decoupled blocks: the Jacobian's own (quasi-IMPES) or D^-1 A (ABF)
+  const double* Jdec = abf ? ctx->Jt : ctx->J;
   // Galerkin chain and coarsest inverse on the auxiliary stream, the ILU
   // factorisation meanwhile on the caller's stream
   hipStream_t a = ctx->aux;
@@ -577,9 +623,9 @@ int setup_cpr(cpr_ctx* ctx) {
   int nh = div_up(L.nh, 256);
   for (int colour = 0; colour < 2; ++colour) {
     if (ctx->b == 2)
-      ilu_kernel<2><<<nh, 256, 0, s>>>(L, colour, ctx->J, ctx->R0, ctx->Dinv, ctx->flag);
+      ilu_kernel<2><<<nh, 256, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
     else
-      ilu_kernel<3><<<nh, 256, 0, s>>>(L, colour, ctx->J, ctx->R0, ctx->Dinv, ctx->flag);
+      ilu_kernel<3><<<nh, 256, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
   }
   if (ctx->opt.precision == CPR_PREC_MIXED) {
     CPR_TRY(hipStreamWaitEvent(s, ctx->ev_rap, 0));   // FP32 copies of the levels

@@ -197,6 +197,37 @@ def test_learned_cpr_apply_matches_oracle(precision):
     assert np.linalg.norm(z0 - z_p) <= base * np.linalg.norm(z_p)
 
 
+@pytest.mark.parametrize("decoupling,composition", [("abf", "two-stage"), ("qimpes", "fpf"),
+                                                    ("abf", "fpf")])
+def test_learned_stage_in_cpr_variants_matches_oracle(decoupling, composition):
+    # the learned correction inside the ABF-decoupled and the F-P-F
+    # preconditioner (FP64), tolerances as for the default one
+    from paper_1606_00548_amd import cprmi
+    case = _ow_case()
+    theta = _theta(9)
+    s = cprmi.Solver.from_case(case)
+    s.assemble(torch.as_tensor(case["x_old"]).cuda(), torch.as_tensor(case["x"]).cuda(), case["dt"])
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                          case["x_old"], case["x"], case["dt"])
+    pc = cpr.cpr_setup(J, decoupling=decoupling)
+    v = -R / np.linalg.norm(R)
+    lam = learned.total_mobility(case["fluid"], case["poro"], case["x"])
+    z_o, acc = learned.learned_cpr_apply(pc, v, theta, case["perm"], lam, composition=composition)
+    z_p = cpr.cpr_apply(pc, v, composition=composition)
+    s.attach_network(theta.astype(np.float32))
+    s.setup(learned=1, decoupling=decoupling, composition=composition)
+    z_g = s.precond(torch.as_tensor(v).cuda().contiguous()).cpu().numpy()
+    corr = np.linalg.norm(z_o - z_p)
+    err = np.linalg.norm(z_g - z_o)
+    print(f"[learned] {decoupling}/{composition} apply: accepted {acc}, |correction| {corr:.3e}, "
+          f"|gpu - oracle| {err:.3e}")
+    if acc:
+        assert err <= 3e-2 * corr + 1e-9 * np.linalg.norm(z_o)
+    else:
+        assert err <= 1e-9 * np.linalg.norm(z_o)
+    s.close()
+
+
 def test_learned_solve_keeps_accuracy_and_counts_decisions():
     from paper_1606_00548_amd import cprmi
     case = _ow_case()

@@ -2,6 +2,7 @@
 kernel reproducing its input, linearity, and the adjoint identities of the
 pooling and upsampling steps."""
 import numpy as np
+import pytest
 
 from oracle import nn
 from paper_1606_00548_amd import synth
@@ -124,3 +125,16 @@ def test_adam_first_step_moves_by_lr():
     t2, m, v = nn.adam_step(theta, g, np.zeros(4), np.zeros(4), 1, lr=1e-3)
     # bias-corrected first step: -lr * sign(g) (and 0 where g = 0)
     assert np.allclose(t2, -1e-3 * np.sign(g), atol=1e-10)
+
+
+@pytest.mark.parametrize("decoupling,composition", [("abf", "two-stage"), ("qimpes", "fpf"), ("abf", "fpf")])
+def test_rejected_network_leaves_each_cpr_variant(decoupling, composition):
+    from oracle import cpr, learned
+    case, J, b, _ = _ow_system()
+    pc = cpr.cpr_setup(J, coarsest=64, decoupling=decoupling)
+    v = b / np.linalg.norm(b)
+    lam = learned.total_mobility(case["fluid"], case["poro"], case["x"])
+    z, acc = learned.learned_cpr_apply(pc, v, np.zeros(nn.num_params()), case["perm"], lam,
+                                       composition=composition)
+    assert not acc
+    assert np.allclose(z, cpr.cpr_apply(pc, v, composition=composition), rtol=1e-13, atol=1e-15)

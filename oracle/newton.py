@@ -3,10 +3,22 @@
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 Algorithm 1 assembles A = J(x) and b = -F(x), finds dx with
-||b - A dx|| <= theta ||b|| (eq. (13)) and sets x = x + dx.  The forcing term
-is fixed (theta = rtol) here.  Reading for the update, which the paper does
-not spell out: saturation changes are chopped to |dS| <= 0.2 per cell and the
-updated saturations clamped to [0, 1]; pressure is updated unchopped.
+||b - A dx|| <= theta ||b|| (eq. (13)) and sets x = x + dx.  newton_step is
+one such iteration with a fixed theta = rtol; time_step runs the whole
+iteration of one backward-Euler step with the forcing terms of eq. (14).
+Readings where the paper is silent:
+  * the update chops saturation changes to |dS| <= 0.2 per cell and clamps
+    the updated saturations to [0, 1]; pressure is updated unchopped;
+  * the stopping test of Algorithm 1 is relative, ||b^l|| < newton_tol
+    ||b^0|| with b^0 = -F(x_old) of the step (the paper's tolerances 1e-2 and
+    1e-3 of Sec. 4 are read as relative reductions);
+  * eq. (14) for l >= 1 with theta_0 = 0.1 for the first iteration, choice 2
+    with the absolute value of the difference of norms, choice 3 with
+    gamma = 0.9, beta = 2 (the paper gives no values), every theta_l clamped
+    to [1e-6, 0.5];
+  * a time-step cut (Sec. 4 reports one) halves dt and restarts from x_old
+    when an attempt does not converge in max_newton iterations, meets a
+    non-finite residual or a singular preconditioner block.
 """
 import numpy as np
 
@@ -33,3 +45,104 @@ def newton_step(grid, fluid, perm, poro, wells, x_old, x, dt_days, restart=30,
     dx, st = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v),
                            rhs, restart=restart, rtol=rtol, max_iter=max_iter)
     return newton_update(x, dx), dx, st, R
+
+
+# ------------------------------------------------------------ time step
+
+FORCING = ("fixed", "ew1", "ew2", "ew3")
+
+
+def forcing_term(choice, l, bn, bn_prev, rn_prev, diff_prev, theta0, theta_min, theta_max,
+                 gamma, beta, rtol):
+    """theta_l of Algorithm 1 step 4.  "fixed": the standard Newton method's
+    constant rtol.  Otherwise eq. (14), choice 1, 2 or 3, for l >= 1, with
+    bn = ||b^l||, bn_prev = ||b^(l-1)||, rn_prev = ||r^(l-1)|| and
+    diff_prev = ||b^l - r^(l-1)||; theta0 for l = 0; clamped to
+    [theta_min, theta_max].  Choice 2 takes the absolute value of the
+    difference of norms."""
+    if choice == "fixed":
+        return rtol
+    if l == 0:
+        t = theta0
+    elif choice == "ew1":
+        t = diff_prev / bn_prev
+    elif choice == "ew2":
+        t = abs(bn - rn_prev) / bn_prev
+    else:
+        t = gamma * (bn / bn_prev) ** beta
+    return min(max(t, theta_min), theta_max)
+
+
+def time_step(grid, fluid, perm, poro, wells, x_old, dt_days, forcing="ew1", theta0=0.1,
+              theta_min=1e-6, theta_max=0.5, gamma=0.9, beta=2.0, newton_tol=1e-3, max_newton=20,
+              max_cuts=6, krylov_method="fgmres", restart=30, max_iter=300, rtol=1e-6, coarsest=512,
+              decoupling="qimpes", composition="two-stage"):
+    """One backward-Euler time step by the inexact Newton method
+    (Algorithm 1) from x^0 = x_old, with time-step cuts.
+
+    Newton iterations run while ||b^l|| >= newton_tol * ||b^0|| (b = -R at
+    the current iterate, b^0 at x_old) and stop with failure after
+    max_newton iterations, or when a residual is not finite or a
+    preconditioner block is singular.  A failed attempt halves dt and starts
+    again from x_old, at most max_cuts times.  A linear solve that does not
+    reach theta within max_iter iterations still updates x (inexact Newton);
+    one whose residual is not finite fails the attempt.  Returns (x, stats): x the
+    accepted state (x_old if every attempt failed), stats with dt_taken,
+    cuts, converged, the per-iteration history of the accepted (or last)
+    attempt (theta, linear iterations, ||b||) and totals over attempts."""
+    assert forcing in FORCING
+    solve = krylov.fgmres if krylov_method == "fgmres" else krylov.bicgstab
+    dt = float(dt_days)
+    total_newton = total_linear = 0
+    for cut in range(max_cuts + 1):
+        x = x_old.copy()
+        R, J = model.assemble(grid, fluid, perm, poro, wells, x_old, x, dt)
+        b = -R
+        bn = float(np.linalg.norm(b))
+        b0 = bn
+        hist = {"theta": [], "linear_iterations": [], "bnorm": [bn]}
+        bn_prev = rn_prev = diff_prev = None
+        l = 0
+        ok = False
+        while np.isfinite(bn):
+            if bn == 0.0 or bn < newton_tol * b0:
+                ok = True
+                break
+            if l >= max_newton:
+                break
+            theta = forcing_term(forcing, l, bn, bn_prev, rn_prev, diff_prev, theta0, theta_min,
+                                 theta_max, gamma, beta, rtol)
+            try:
+                pc = cpr.cpr_setup(J, coarsest, decoupling=decoupling)
+            except (FloatingPointError, np.linalg.LinAlgError):
+                break
+            kw = {"restart": restart} if krylov_method == "fgmres" else {}
+            with np.errstate(all="ignore"):
+                try:
+                    dx, st = solve(lambda v: cpr.block_spmv(J, v),
+                                   lambda v: cpr.cpr_apply(pc, v, composition=composition), b,
+                                   rtol=theta, max_iter=max_iter, **kw)
+                except ValueError:          # a non-finite Hessenberg entry
+                    break
+                r = b - cpr.block_spmv(J, dx)
+            if not (np.isfinite(st["true_rel"]) and np.all(np.isfinite(r))):
+                break
+            x = newton_update(x, dx)
+            with np.errstate(all="ignore"):
+                R, J = model.assemble(grid, fluid, perm, poro, wells, x_old, x, dt)
+            b_new = -R
+            bn_prev, rn_prev = bn, float(np.linalg.norm(r))
+            diff_prev = float(np.linalg.norm(b_new - r))
+            b, bn = b_new, float(np.linalg.norm(b_new))
+            l += 1
+            hist["theta"].append(theta)
+            hist["linear_iterations"].append(st["iterations"])
+            hist["bnorm"].append(bn)
+        total_newton += l
+        total_linear += sum(hist["linear_iterations"])
+        stats = {"dt_taken": dt, "cuts": cut, "converged": ok, "newton_iterations": l,
+                 "total_newton": total_newton, "total_linear": total_linear, "history": hist}
+        if ok:
+            return x, stats
+        dt *= 0.5
+    return x_old.copy(), stats

@@ -1,0 +1,87 @@
+"""Pins of the oracle's inexact Newton time step (Algorithm 1, eq. (14))."""
+import numpy as np
+import pytest
+
+from oracle import model, newton
+from paper_1606_00548_amd import synth
+
+
+def _run(case, dt, **kw):
+    return newton.time_step(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                            case["x_old"], dt, **kw)
+
+
+def _linear_case():
+    # constant water density: accumulation, fluxes and wells are affine in p
+    case = synth.single_phase_uniform(16, 16, 8, wells=[synth.well(0, 0, 8, "inj", 300.0),
+                                                         synth.well(15, 15, 8, "prod", 150.0)])
+    case["fluid"] = dict(case["fluid"], c_w=0.0)
+    return case
+
+
+@pytest.mark.parametrize("forcing", ["ew1", "ew2", "ew3"])
+def test_affine_residual_gives_the_forcing_floor(forcing):
+    # For affine F the next right-hand side is the linear residual itself,
+    # b^(l+1) = b^l - A dx = r^l, so choices 1 and 2 of eq. (14) vanish and
+    # are clamped to theta_min; choice 3 is at most gamma theta_0^beta.
+    case = _linear_case()
+    x, st = _run(case, 1.0, forcing=forcing, coarsest=16, theta0=0.1)
+    h = st["history"]
+    assert st["converged"] and st["cuts"] == 0 and st["newton_iterations"] == 2
+    assert h["theta"][0] == 0.1
+    if forcing in ("ew1", "ew2"):
+        assert h["theta"][1] == 1e-6
+    else:
+        assert 1e-6 <= h["theta"][1] <= 0.9 * 0.1 ** 2
+    # the first solve stopped at theta_0: ||b^1|| = ||r^0|| <= 0.1 ||b^0||
+    assert h["bnorm"][1] <= 0.1 * h["bnorm"][0]
+
+
+def test_fixed_forcing_repeats_the_newton_step():
+    case = synth.oil_water_lognormal(8, 6, 3, seed=80)
+    x, st = _run(case, 1.0, forcing="fixed", rtol=1e-6)
+    xr = case["x_old"].copy()
+    R0, _ = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                           case["x_old"], xr, 1.0)
+    its = 0
+    while True:
+        R, _ = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                              case["x_old"], xr, 1.0)
+        if np.linalg.norm(R) < 1e-3 * np.linalg.norm(R0):
+            break
+        xr, _, _, _ = newton.newton_step(case["grid"], case["fluid"], case["perm"], case["poro"],
+                                         case["wells"], case["x_old"], xr, 1.0, rtol=1e-6)
+        its += 1
+        assert its <= 20
+    assert st["converged"] and st["newton_iterations"] == its
+    assert np.array_equal(x, xr)
+
+
+def test_cuts_halve_the_step_and_the_accepted_state_meets_the_criterion():
+    case = synth.oil_water_lognormal(8, 6, 3, seed=81)
+    x, st = _run(case, 30.0, max_newton=6)
+    assert st["converged"] and st["cuts"] >= 1
+    assert st["dt_taken"] == 30.0 / 2 ** st["cuts"]
+    R, _ = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                          case["x_old"], x, st["dt_taken"])
+    R0, _ = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                           case["x_old"], case["x_old"], st["dt_taken"])
+    assert np.linalg.norm(R) < 1e-3 * np.linalg.norm(R0)
+    assert st["total_newton"] == st["newton_iterations"] + 6 * st["cuts"]
+    # no cut allowed: the failed attempt returns x_old
+    x1, st1 = _run(case, 30.0, max_newton=6, max_cuts=0)
+    assert not st1["converged"] and np.array_equal(x1, case["x_old"])
+
+
+@pytest.mark.parametrize("forcing", ["fixed", "ew1", "ew2", "ew3"])
+def test_time_step_converges_and_inexact_forcing_saves_linear_work(forcing):
+    case = synth.oil_water_lognormal(16, 12, 4, seed=6)
+    x, st = _run(case, 1.0, forcing=forcing)
+    R, _ = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                          case["x_old"], x, 1.0)
+    assert st["converged"] and st["cuts"] == 0
+    assert np.linalg.norm(R) < 1e-3 * st["history"]["bnorm"][0]
+    assert np.isclose(np.linalg.norm(R), st["history"]["bnorm"][-1], rtol=1e-12)
+    if forcing != "fixed":
+        _, sf = _run(case, 1.0, forcing="fixed")
+        assert st["total_linear"] < sf["total_linear"]

@@ -199,6 +199,63 @@ int cpr_gmres_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* 
  * CPR_NOT_CONVERGED (dx holds the last iterate) or CPR_ENONFINITE. */
 int cpr_bicgstab_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* st);
 
+/* ---------------------------------------------------------------- time step
+ * Forcing terms theta_l of the inexact Newton method (Algorithm 1, eq. (13)):
+ *   CPR_FORCING_FIXED  theta_l = options.rtol (the standard Newton method);
+ *   CPR_FORCING_EW1    ||b^l - r^(l-1)|| / ||b^(l-1)||        (eq. (14), 1st)
+ *   CPR_FORCING_EW2    | ||b^l|| - ||r^(l-1)|| | / ||b^(l-1)|| (2nd, absolute value)
+ *   CPR_FORCING_EW3    gamma (||b^l|| / ||b^(l-1)||)^beta     (3rd)
+ * with r^l = b^l - A^l dx^l the linear residual left by iteration l; the
+ * first iteration uses theta0, and every theta_l is clamped to
+ * [theta_min, theta_max]. */
+enum { CPR_FORCING_FIXED = 0, CPR_FORCING_EW1 = 1, CPR_FORCING_EW2 = 2, CPR_FORCING_EW3 = 3 };
+enum { CPR_KRYLOV_FGMRES = 0, CPR_KRYLOV_BICGSTAB = 1 };
+#define CPR_NEWTON_HIST 64
+
+typedef struct {
+  int forcing;         /* CPR_FORCING_* (default EW1)                        */
+  int krylov;          /* CPR_KRYLOV_FGMRES (default) or CPR_KRYLOV_BICGSTAB  */
+  int max_newton;      /* Newton iterations per attempt (20)                 */
+  int max_cuts;        /* time-step halvings before giving up (6)            */
+  double newton_tol;   /* converged when ||b^l|| < newton_tol ||b^0|| (1e-3) */
+  double theta0;       /* forcing term of the first iteration (0.1)          */
+  double theta_min, theta_max;   /* clamp of theta_l (1e-6, 0.5)             */
+  double gamma, beta;  /* choice 3 (0.9, 2)                                  */
+} cpr_newton_options_t;
+
+typedef struct {
+  int converged;
+  int cuts;                    /* halvings of dt before the accepted attempt */
+  int newton_iterations;       /* of the accepted (or last) attempt          */
+  int linear_iterations;       /* of the accepted (or last) attempt          */
+  int total_newton, total_linear;  /* over every attempt                     */
+  double dt_taken;             /* days                                       */
+  double theta[CPR_NEWTON_HIST];   /* per Newton iteration (first 64)        */
+  int lin_its[CPR_NEWTON_HIST];
+  double bnorm[CPR_NEWTON_HIST + 1];   /* ||b^l||, l = 0 .. iterations      */
+} cpr_newton_stats_t;
+
+/* Fill *o with the defaults listed above. */
+void cpr_default_newton_options(cpr_newton_options_t* o);
+
+/* One backward-Euler time step of length dt_days (eq. (10)) by the inexact
+ * Newton method of Algorithm 1, from x^0 = x_old (device, [b][n], natural
+ * order).  Each iteration assembles b = -F(x) and A, sets up CPR with the
+ * linear options `lin` (its rtol replaced by theta_l unless the forcing is
+ * CPR_FORCING_FIXED), solves with the chosen Krylov method, and applies the
+ * Newton update of cpr_newton_update.  The attempt converges when
+ * ||b^l||_2 < newton_tol ||b^0||_2 (b^0 at x_old) and fails after max_newton
+ * iterations, on a non-finite residual, or on a singular preconditioner
+ * block; a failed attempt halves dt and starts again from x_old (time-step
+ * cut), at most max_cuts times.  A linear solve that stops at lin->max_iter
+ * still updates x.  On success x (device [b][n]) receives the new state and
+ * st->dt_taken the step actually taken; returns CPR_OK.  If every attempt
+ * fails x receives x_old and CPR_NOT_CONVERGED is returned.  The Jacobian
+ * and preconditioner of the last iteration stay in the context.
+ * Synchronises the stream several times per Newton iteration. */
+int cpr_time_step(cpr_ctx_t* ctx, const double* x_old, double* x, double dt_days, const cpr_options_t* lin,
+                  const cpr_newton_options_t* nopt, cpr_newton_stats_t* st);
+
 /* Newton update of Algorithm 1, step 5 (device, [b][n]): x += dx with
  * saturation changes chopped to |dS| <= 0.2 and saturations clamped to
  * [0, 1]. */

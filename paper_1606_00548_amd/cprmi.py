@@ -63,6 +63,33 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+NEWTON_HIST = 64
+FORCING = {"fixed": 0, "ew1": 1, "ew2": 2, "ew3": 3}
+KRYLOV = {"fgmres": 0, "bicgstab": 1}
+
+
+class NewtonOptions(ctypes.Structure):
+    _fields_ = [("forcing", ctypes.c_int), ("krylov", ctypes.c_int), ("max_newton", ctypes.c_int),
+                ("max_cuts", ctypes.c_int), ("newton_tol", ctypes.c_double), ("theta0", ctypes.c_double),
+                ("theta_min", ctypes.c_double), ("theta_max", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("beta", ctypes.c_double)]
+
+
+class NewtonStats(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int), ("cuts", ctypes.c_int), ("newton_iterations", ctypes.c_int),
+                ("linear_iterations", ctypes.c_int), ("total_newton", ctypes.c_int),
+                ("total_linear", ctypes.c_int), ("dt_taken", ctypes.c_double),
+                ("theta", ctypes.c_double * NEWTON_HIST), ("lin_its", ctypes.c_int * NEWTON_HIST),
+                ("bnorm", ctypes.c_double * (NEWTON_HIST + 1))]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_[:7]}
+        k = min(self.newton_iterations, NEWTON_HIST)
+        d["history"] = {"theta": list(self.theta[:k]), "linear_iterations": list(self.lin_its[:k]),
+                        "bnorm": list(self.bnorm[:k + 1])}
+        return d
+
+
 EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error", "cpr_block_size",
            "cpr_num_cells", "assemble_jacobian", "cpr_import_jacobian", "cpr_export_jacobian",
            "cpr_setup", "cpr_gmres_solve", "cpr_newton_update", "cpr_spmv", "cpr_precond_apply",
@@ -71,7 +98,8 @@ EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error",
            "cpr_nn_destroy", "cpr_nn_last_error", "cpr_nn_set_params", "cpr_nn_get_params",
            "cpr_nn_forward", "cpr_nn_backward", "cpr_nn_train_step", "cpr_nn_attach",
            "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov", "cpr_nn_eval_loss",
-           "cpr_nn_make_target", "cpr_nn_infer", "cpr_bicgstab_solve"]
+           "cpr_nn_make_target", "cpr_nn_infer", "cpr_bicgstab_solve", "cpr_default_newton_options",
+           "cpr_time_step"]
 KCLASS = {"spmv": 0, "orth": 1, "smooth": 2, "ilu": 3, "assemble": 4}
 
 
@@ -99,6 +127,9 @@ def load():
     lib.cpr_setup.argtypes = [P, ctypes.POINTER(Options)]
     lib.cpr_gmres_solve.argtypes = [P, P, P, ctypes.POINTER(Stats)]
     lib.cpr_bicgstab_solve.argtypes = [P, P, P, ctypes.POINTER(Stats)]
+    lib.cpr_default_newton_options.argtypes = [ctypes.POINTER(NewtonOptions)]
+    lib.cpr_time_step.argtypes = [P, P, P, ctypes.c_double, ctypes.POINTER(Options),
+                                  ctypes.POINTER(NewtonOptions), ctypes.POINTER(NewtonStats)]
     lib.cpr_newton_update.argtypes = [P, P, P]
     lib.cpr_spmv.argtypes = [P, P, P]
     lib.cpr_precond_apply.argtypes = [P, P, P]
@@ -235,6 +266,18 @@ def default_options(**kw):
     return o
 
 
+def default_newton_options(**kw):
+    o = NewtonOptions()
+    load().cpr_default_newton_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "forcing" and isinstance(v, str):
+            v = FORCING[v]
+        if k == "krylov" and isinstance(v, str):
+            v = KRYLOV[v]
+        setattr(o, k, v)
+    return o
+
+
 class Solver:
     """One C-ABI context: grid, rock, fluid and wells of a reservoir model."""
 
@@ -326,6 +369,22 @@ class Solver:
         d = st.as_dict()
         d["status"] = rc
         return dx, d
+
+    def time_step(self, x_old, dt_days, options=None, newton=None, x=None):
+        """One inexact Newton time step from x_old (Algorithm 1 with
+        time-step cuts); returns (x, stats).  options: linear-solver
+        options (cpr_options_t); newton: NewtonOptions or a dict of its
+        fields."""
+        x = self.vector() if x is None else x
+        lo = options if options is not None else default_options()
+        no = newton if isinstance(newton, NewtonOptions) else default_newton_options(**(newton or {}))
+        st = NewtonStats()
+        rc = self._check(self.lib.cpr_time_step(self.ctx, _ptr(x_old), _ptr(x), float(dt_days),
+                                                ctypes.byref(lo), ctypes.byref(no), ctypes.byref(st)),
+                         allow=(0, 1))
+        d = st.as_dict()
+        d["status"] = rc
+        return x, d
 
     def newton_update(self, x, dx):
         self._check(self.lib.cpr_newton_update(self.ctx, _ptr(x), _ptr(dx)))

@@ -253,6 +253,38 @@ int ensure_mixed(cpr_ctx* ctx) {
 
 }  // namespace
 
+int ensure_krylov_capacity(cpr_ctx* ctx, int m) { return ensure_krylov(ctx, m); }
+
+// Validate the options, allocate what they need and build the preconditioner.
+int setup_with_options(cpr_ctx* ctx, const cpr_options_t& opt) {
+  if (opt.restart < 1 || opt.restart > 64) return set_err(ctx, CPR_EINVAL, "restart must be 1..64");
+  if (opt.max_iter < 0) return set_err(ctx, CPR_EINVAL, "max_iter must be >= 0");
+  if (!(opt.rtol >= 0) || !std::isfinite(opt.rtol)) return set_err(ctx, CPR_EINVAL, "rtol must be >= 0");
+  if (opt.mg_coarsest < 1 || opt.mg_coarsest > 4096)
+    return set_err(ctx, CPR_EINVAL, "mg_coarsest must be 1..4096");
+  if (opt.precision != CPR_PREC_FP64 && opt.precision != CPR_PREC_MIXED)
+    return set_err(ctx, CPR_EINVAL, "unknown precision");
+  if (opt.decoupling != CPR_DECOUPLE_QIMPES && opt.decoupling != CPR_DECOUPLE_ABF)
+    return set_err(ctx, CPR_EINVAL, "unknown decoupling");
+  if (opt.composition != CPR_COMPOSE_PF && opt.composition != CPR_COMPOSE_FPF)
+    return set_err(ctx, CPR_EINVAL, "unknown composition");
+  if (opt.learned && !ctx->nn) return set_err(ctx, CPR_EINVAL, "no pressure-correction network attached");
+  ctx->opt = opt;
+  ctx->setup_done = 0;
+  int rc;
+  if ((rc = ensure_krylov(ctx, opt.restart)) != CPR_OK) return rc;
+  if (opt.precision == CPR_PREC_MIXED && (rc = ensure_mixed(ctx)) != CPR_OK) return rc;
+  if ((rc = ensure_variants(ctx, opt)) != CPR_OK) return rc;
+  if ((rc = setup_cpr(ctx)) != CPR_OK) return rc;
+  if (opt.learned) {
+    if ((rc = learned_setup(ctx, true)) != CPR_OK) {
+      ctx->setup_done = 0;
+      return rc;
+    }
+  }
+  return CPR_OK;
+}
+
 #define GUARD_BEGIN try {
 #define GUARD_END                                                        \
   }                                                                      \
@@ -348,32 +380,7 @@ int cpr_setup(cpr_ctx_t* ctx, const cpr_options_t* o) {
   GUARD_BEGIN
   cpr_options_t opt;
   if (o) opt = *o; else cpr_default_options(&opt);
-  if (opt.restart < 1 || opt.restart > 64) return set_err(ctx, CPR_EINVAL, "restart must be 1..64");
-  if (opt.max_iter < 0) return set_err(ctx, CPR_EINVAL, "max_iter must be >= 0");
-  if (!(opt.rtol >= 0) || !std::isfinite(opt.rtol)) return set_err(ctx, CPR_EINVAL, "rtol must be >= 0");
-  if (opt.mg_coarsest < 1 || opt.mg_coarsest > 4096)
-    return set_err(ctx, CPR_EINVAL, "mg_coarsest must be 1..4096");
-  if (opt.precision != CPR_PREC_FP64 && opt.precision != CPR_PREC_MIXED)
-    return set_err(ctx, CPR_EINVAL, "unknown precision");
-  if (opt.decoupling != CPR_DECOUPLE_QIMPES && opt.decoupling != CPR_DECOUPLE_ABF)
-    return set_err(ctx, CPR_EINVAL, "unknown decoupling");
-  if (opt.composition != CPR_COMPOSE_PF && opt.composition != CPR_COMPOSE_FPF)
-    return set_err(ctx, CPR_EINVAL, "unknown composition");
-  if (opt.learned && !ctx->nn) return set_err(ctx, CPR_EINVAL, "no pressure-correction network attached");
-  ctx->opt = opt;
-  ctx->setup_done = 0;
-  int rc;
-  if ((rc = ensure_krylov(ctx, opt.restart)) != CPR_OK) return rc;
-  if (opt.precision == CPR_PREC_MIXED && (rc = ensure_mixed(ctx)) != CPR_OK) return rc;
-  if ((rc = ensure_variants(ctx, opt)) != CPR_OK) return rc;
-  if ((rc = setup_cpr(ctx)) != CPR_OK) return rc;
-  if (opt.learned) {
-    if ((rc = learned_setup(ctx, true)) != CPR_OK) {
-      ctx->setup_done = 0;
-      return rc;
-    }
-  }
-  return CPR_OK;
+  return setup_with_options(ctx, opt);
   GUARD_END
 }
 
@@ -398,6 +405,48 @@ int cpr_gmres_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* 
     st->nn_rejected = cnt[1];
   }
   return rc;
+  GUARD_END
+}
+
+void cpr_default_newton_options(cpr_newton_options_t* o) {
+  if (!o) return;
+  o->forcing = CPR_FORCING_EW1;
+  o->krylov = CPR_KRYLOV_FGMRES;
+  o->max_newton = 20;
+  o->max_cuts = 6;
+  o->newton_tol = 1e-3;
+  o->theta0 = 0.1;
+  o->theta_min = 1e-6;
+  o->theta_max = 0.5;
+  o->gamma = 0.9;
+  o->beta = 2.0;
+}
+
+int cpr_time_step(cpr_ctx_t* ctx, const double* x_old, double* x, double dt_days, const cpr_options_t* lin,
+                  const cpr_newton_options_t* nopt, cpr_newton_stats_t* st) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  GUARD_BEGIN
+  if (!x_old || !x) return set_err(ctx, CPR_EINVAL, "null argument");
+  if (!(dt_days > 0) || !std::isfinite(dt_days)) return set_err(ctx, CPR_EINVAL, "dt must be > 0");
+  cpr_options_t lo;
+  if (lin) lo = *lin; else cpr_default_options(&lo);
+  cpr_newton_options_t no;
+  if (nopt) no = *nopt; else cpr_default_newton_options(&no);
+  if (no.forcing < CPR_FORCING_FIXED || no.forcing > CPR_FORCING_EW3)
+    return set_err(ctx, CPR_EINVAL, "unknown forcing");
+  if (no.krylov != CPR_KRYLOV_FGMRES && no.krylov != CPR_KRYLOV_BICGSTAB)
+    return set_err(ctx, CPR_EINVAL, "unknown Krylov method");
+  if (no.max_newton < 0 || no.max_cuts < 0) return set_err(ctx, CPR_EINVAL, "negative iteration limit");
+  if (!(no.newton_tol > 0) || !(no.theta_min > 0) || !(no.theta_max >= no.theta_min) || !(no.theta0 > 0) ||
+      !std::isfinite(no.theta_max) || !std::isfinite(no.gamma) || !std::isfinite(no.beta))
+    return set_err(ctx, CPR_EINVAL, "bad Newton tolerances");
+  hipStream_t s = ctx->stream;
+  launch_nat_to_cs(ctx->lay, ctx->b, x_old, ctx->vin2, s);
+  int rc = time_step(ctx, ctx->vin2, ctx->vin, dt_days, lo, no, st);
+  if (rc < 0) return rc;
+  launch_cs_to_nat(ctx->lay, ctx->b, ctx->vin, x, s);
+  int rc2 = launch_check(ctx, "cpr_time_step");
+  return rc2 != CPR_OK ? rc2 : rc;
   GUARD_END
 }
 

@@ -307,6 +307,14 @@ void learned_rprime(cpr_ctx* ctx);
 void learned_features_from_rprime(cpr_ctx* ctx);
 void launch_lnk(const Lay& L, const double* perm_nat, double* lnk, hipStream_t s);
 
+// capi.hip
+int setup_with_options(cpr_ctx* ctx, const cpr_options_t& opt);
+int ensure_krylov_capacity(cpr_ctx* ctx, int m);
+
+// newton.hip
+int time_step(cpr_ctx* ctx, const double* xold_cs, double* x_cs, double dt_days, const cpr_options_t& lin,
+              const cpr_newton_options_t& no, cpr_newton_stats_t* st);
+
 // krylov.hip
 int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st);
 int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st);

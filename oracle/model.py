@@ -15,8 +15,13 @@ Paper passages followed
     Stone II for the three-phase oil relative permeability (Sec. 2.1).
 
 Readings where the paper is silent (the GPU library takes the same ones)
-  * Unknowns per cell: (p [bar], S_w) oil-water, (p_o [bar], S_w, S_g)
-    saturated black oil, (p [bar]) for the single-phase test model.  Rows in
+  * Unknowns per cell: (p [bar], S_w) oil-water, (p_o [bar], S_w, x2) black
+    oil, (p [bar]) for the single-phase test model.  Black oil switches its
+    third unknown with the phase state (Sec. 2.4: gas saturation or bubble
+    point pressure): x2 = S_g >= 0 where free gas may exist (saturated oil,
+    Rs, B_o, mu_o at p) and x2 = -p_b < 0 where it does not (undersaturated
+    oil: S_g = 0, Rs and mu_o at p_b, B_o = B_o(p_b) exp(-c_o (p - p_b))).
+    The sign of x2 carries the state, so x alone describes it.  Rows in
     the order (oil, water[, gas]) components; single phase has one water row.
   * Phi_a = p - rho_a g z with z the depth (positive downward), so a
     hydrostatic column has no potential gradient; the symbol in eq. (6) is g.
@@ -151,7 +156,7 @@ def cell_state(fluid, poro, x):
     x has shape (b, nz, ny, nx).  Returns a dict with
       acc   (b, ...)        component mass per unit bulk volume, phi*S*rho
       dacc  (b, b, ...)     d acc[c] / d x[u]
-      phases: list of (rho, drho/dp) per phase
+      phases: list of (rho, drho (b, ...)) per phase, drho[u] = d rho / d x[u]
       terms:  list of (row c, phase index, lam, dlam (b, ...)) -- the mass
               mobility rho_c k_r / mu of component c carried by that phase
       lam_t:  total volumetric mobility sum k_r/mu and its derivative (b, ...)
@@ -169,10 +174,17 @@ def cell_state(fluid, poro, x):
     out = {"phases": [], "terms": []}
     acc = np.zeros((b,) + p.shape)
     dacc = np.zeros((b, b) + p.shape)
+    def dvec(dp, d2=None):
+        v = np.zeros((b,) + p.shape)
+        v[0] = dp
+        if d2 is not None:
+            v[2] = d2
+        return v
+
     if m == 1:
         acc[0] = phi * rho_w
         dacc[0, 0] = dphi * rho_w + phi * drho_w
-        out["phases"] = [(rho_w, drho_w)]
+        out["phases"] = [(rho_w, dvec(drho_w))]
         dl = np.zeros((1,) + p.shape)
         dl[0] = drho_w / mu_w
         out["terms"] = [(0, 0, rho_w / mu_w, dl)]
@@ -191,58 +203,81 @@ def cell_state(fluid, poro, x):
         dacc[0, 1] = -phi * rho_o
         dacc[1, 0] = sw * (dphi * rho_w + phi * drho_w)
         dacc[1, 1] = phi * rho_w
-        out["phases"] = [(rho_o, drho_o), (rho_w, drho_w)]
+        out["phases"] = [(rho_o, dvec(drho_o)), (rho_w, dvec(drho_w))]
         dlo = np.stack([drho_o * kro / mu_o, rho_o * dkro / mu_o])
         dlw = np.stack([drho_w * krw / mu_w, rho_w * dkrw / mu_w])
         out["terms"] = [(0, 0, rho_o * kro / mu_o, dlo), (1, 1, rho_w * krw / mu_w, dlw)]
         out["lam_t"] = (krw / mu_w + kro / mu_o, np.stack([zero, dkrw / mu_w + dkro / mu_o]))
     else:
-        sw, sg = x[1], x[2]
+        # third unknown: S_g >= 0 in saturated cells, -p_b (bar) < 0 in
+        # undersaturated cells (no free gas, bubble point p_b < p)
+        sw, x2 = x[1], x[2]
+        sat = x2 >= 0.0
+        sg = np.where(sat, x2, 0.0)
+        dsg = sat.astype(np.float64)                  # d S_g / d x2
+        pb = np.where(sat, p, -x2)
         so = 1.0 - sw - sg
         pvt = np.asarray(fluid["pvt"], dtype=np.float64)
         tp = pvt[0]
-        rs, drs = pvt_interp(tp, pvt[1], p)
-        bo, dbo = pvt_interp(tp, pvt[2], p)
-        muo, dmuo = pvt_interp(tp, pvt[3], p)
+        rs, drs_b = pvt_interp(tp, pvt[1], pb)
+        bo_b, dbo_b = pvt_interp(tp, pvt[2], pb)
+        muo, dmuo_b = pvt_interp(tp, pvt[3], pb)
         bg, dbg = pvt_interp(tp, pvt[4], p)
         mug, dmug = pvt_interp(tp, pvt[5], p)
-        muo, dmuo, mug, dmug = muo * CP, dmuo * CP, mug * CP, dmug * CP
+        # undersaturated oil: Rs and mu_o at the bubble point, and
+        # B_o = B_o(p_b) exp(-c_o (p - p_b)); saturated: functions of p
+        c_o = fluid.get("c_o", 0.0)
+        e = np.where(sat, 1.0, np.exp(-c_o * (p - pb)))
+        bo = bo_b * e
+        rs_p, rs_2 = np.where(sat, drs_b, 0.0), np.where(sat, 0.0, -drs_b)
+        bo_p = np.where(sat, dbo_b, -c_o * bo)
+        bo_2 = np.where(sat, 0.0, -(dbo_b * e + c_o * bo))
+        mu_p, mu_2 = np.where(sat, dmuo_b, 0.0), np.where(sat, 0.0, -dmuo_b)
+        muo, mu_p, mu_2 = muo * CP, mu_p * CP, mu_2 * CP
+        mug, dmug = mug * CP, dmug * CP
         rsc_o, rsc_g = fluid["rho_o_sc"], fluid["rho_g_sc"]
         rho_oo = rsc_o / bo                       # oil component in the oil phase
-        drho_oo = -rsc_o * dbo / (bo * bo)
+        rho_oo_p = -rsc_o * bo_p / (bo * bo)
+        rho_oo_2 = -rsc_o * bo_2 / (bo * bo)
         rho_og = rsc_g * rs / bo                  # dissolved gas in the oil phase
-        drho_og = rsc_g * (drs * bo - rs * dbo) / (bo * bo)
+        rho_og_p = rsc_g * (rs_p * bo - rs * bo_p) / (bo * bo)
+        rho_og_2 = rsc_g * (rs_2 * bo - rs * bo_2) / (bo * bo)
         rho_g = rsc_g / bg                        # free gas
         drho_g = -rsc_g * dbg / (bg * bg)
         krw, dkrw, krg, dkrg, kro, dkro_w, dkro_g = stone2(
             sw, sg, fluid["s_wc"], fluid["s_or"], fluid["sg_den"])
+        dkrg, dkro_g = dkrg * dsg, dkro_g * dsg    # per unit of x2
         acc[0] = phi * so * rho_oo
         acc[1] = phi * sw * rho_w
         acc[2] = phi * (so * rho_og + sg * rho_g)
-        dacc[0, 0] = so * (dphi * rho_oo + phi * drho_oo)
+        dacc[0, 0] = so * (dphi * rho_oo + phi * rho_oo_p)
         dacc[0, 1] = -phi * rho_oo
-        dacc[0, 2] = -phi * rho_oo
+        dacc[0, 2] = -phi * rho_oo * dsg + phi * so * rho_oo_2
         dacc[1, 0] = sw * (dphi * rho_w + phi * drho_w)
         dacc[1, 1] = phi * rho_w
-        dacc[2, 0] = dphi * (so * rho_og + sg * rho_g) + phi * (so * drho_og + sg * drho_g)
+        dacc[2, 0] = dphi * (so * rho_og + sg * rho_g) + phi * (so * rho_og_p + sg * drho_g)
         dacc[2, 1] = -phi * rho_og
-        dacc[2, 2] = phi * (rho_g - rho_og)
+        dacc[2, 2] = phi * (-rho_og * dsg + so * rho_og_2 + rho_g * dsg)
         rho_O = rho_oo + rho_og
-        out["phases"] = [(rho_O, drho_oo + drho_og), (rho_w, drho_w), (rho_g, drho_g)]
-        # mobility rho k_r / mu and its derivatives in (p, Sw, Sg)
-        def mob(rho, drho, kr, dkr_w, dkr_g, mu, dmu):
+        out["phases"] = [(rho_O, dvec(rho_oo_p + rho_og_p, rho_oo_2 + rho_og_2)),
+                         (rho_w, dvec(drho_w)), (rho_g, dvec(drho_g))]
+
+        # mobility rho k_r / mu and its derivatives in (p, Sw, x2)
+        def mob(rho, rho_p, rho_2, kr, dkr_w, dkr_2, mu, dmu_p, dmu_2):
             lam = rho * kr / mu
-            return lam, np.stack([(drho * kr - rho * kr * dmu / mu) / mu,
-                                  rho * dkr_w / mu, rho * dkr_g / mu])
-        lam_oo, dl_oo = mob(rho_oo, drho_oo, kro, dkro_w, dkro_g, muo, dmuo)
-        lam_og, dl_og = mob(rho_og, drho_og, kro, dkro_w, dkro_g, muo, dmuo)
-        lam_w, dl_w = mob(rho_w, drho_w, krw, dkrw, zero, mu_w, zero)
-        lam_g, dl_g = mob(rho_g, drho_g, krg, zero, dkrg, mug, dmug)
+            return lam, np.stack([(rho_p * kr - rho * kr * dmu_p / mu) / mu,
+                                  rho * dkr_w / mu,
+                                  (rho_2 * kr + rho * dkr_2 - rho * kr * dmu_2 / mu) / mu])
+        lam_oo, dl_oo = mob(rho_oo, rho_oo_p, rho_oo_2, kro, dkro_w, dkro_g, muo, mu_p, mu_2)
+        lam_og, dl_og = mob(rho_og, rho_og_p, rho_og_2, kro, dkro_w, dkro_g, muo, mu_p, mu_2)
+        lam_w, dl_w = mob(rho_w, drho_w, zero, krw, dkrw, zero, mu_w, zero, zero)
+        lam_g, dl_g = mob(rho_g, drho_g, zero, krg, zero, dkrg, mug, dmug, zero)
         out["terms"] = [(0, 0, lam_oo, dl_oo), (1, 1, lam_w, dl_w),
                         (2, 0, lam_og, dl_og), (2, 2, lam_g, dl_g)]
         lt = krw / mu_w + kro / muo + krg / mug
-        dlt = np.stack([-kro * dmuo / (muo * muo) - krg * dmug / (mug * mug),
-                        dkrw / mu_w + dkro_w / muo, dkro_g / muo + dkrg / mug])
+        dlt = np.stack([-kro * mu_p / (muo * muo) - krg * dmug / (mug * mug),
+                        dkrw / mu_w + dkro_w / muo,
+                        dkro_g / muo - kro * mu_2 / (muo * muo) + dkrg / mug])
         out["lam_t"] = (lt, dlt)
     out["acc"], out["dacc"] = acc, dacc
     return out
@@ -302,8 +337,10 @@ def assemble(grid, fluid, perm_md, poro, wells, x_old, x, dt_days):
         dphis = []
         for rho, drho in st["phases"]:
             dphi = (p_lo - p_hi) * BAR - 0.5 * (rho[lo] + rho[hi]) * G * dz
-            ddphi_lo = BAR - 0.5 * G * dz * drho[lo]
-            ddphi_hi = -BAR - 0.5 * G * dz * drho[hi]
+            ddphi_lo = np.stack([-0.5 * G * dz * drho[u][lo] for u in range(b)])
+            ddphi_hi = np.stack([-0.5 * G * dz * drho[u][hi] for u in range(b)])
+            ddphi_lo[0] += BAR
+            ddphi_hi[0] -= BAR
             up_lo = dphi >= -TIE_BAR * BAR  # ties go to the lower-index cell
             dphis.append((dphi, ddphi_lo, ddphi_hi, up_lo))
         for (c, ph, lam, dlam) in st["terms"]:
@@ -315,8 +352,9 @@ def assemble(grid, fluid, perm_md, poro, wells, x_old, x, dt_days):
             for u in range(b):
                 dF_lo[u] = T * np.where(up_lo, dlam[u][lo], 0.0) * dphi
                 dF_hi[u] = T * np.where(up_lo, 0.0, dlam[u][hi]) * dphi
-            dF_lo[0] += T * lam_up * ddphi_lo
-            dF_hi[0] += T * lam_up * ddphi_hi
+            for u in range(b):
+                dF_lo[u] += T * lam_up * ddphi_lo[u]
+                dF_hi[u] += T * lam_up * ddphi_hi[u]
             R[c][lo] += F
             R[c][hi] -= F
             for u in range(b):
@@ -343,8 +381,8 @@ def assemble(grid, fluid, perm_md, poro, wells, x_old, x, dt_days):
                 for u in range(b):
                     dq = wi * rho[cell] * dlt[u][cell] * drive
                     if u == 0:
-                        dq += wi * drho[cell] * lt[cell] * drive
-                        dq += wi * rho[cell] * lt[cell] * (-BAR - drho[cell] * G * dzh)
+                        dq += wi * drho[0][cell] * lt[cell] * drive
+                        dq += wi * rho[cell] * lt[cell] * (-BAR - drho[0][cell] * G * dzh)
                     J[0, wc, u][cell] -= dq
             else:
                 for (c, ph, lam, dlam) in st["terms"]:
@@ -355,7 +393,9 @@ def assemble(grid, fluid, perm_md, poro, wells, x_old, x, dt_days):
                     for u in range(b):
                         dq = wi * dlam[u][cell] * drive
                         if u == 0:
-                            dq += wi * lam[cell] * (-BAR - drho[cell] * G * dzh)
+                            dq += wi * lam[cell] * (-BAR - drho[0][cell] * G * dzh)
+                        else:
+                            dq += wi * lam[cell] * (-drho[u][cell] * G * dzh)
                         J[0, c, u][cell] -= dq
     s = row_scales(grid, fluid, poro, dt_days)
     for c in range(b):

@@ -27,11 +27,28 @@ from . import cpr, krylov, model
 DS_MAX = 0.2
 
 
-def newton_update(x, dx):
+def newton_update(x, dx, pb_min=None):
+    """x + dx with the chops and clamps below; black oil (3 unknowns)
+    switches its third unknown with the phase state:
+      * saturated (x2 = S_g >= 0): S_g + clip(dS_g) below zero means the free
+        gas has dissolved: the cell becomes undersaturated at its bubble
+        point, x2 = -p (p_b = p after the update); otherwise S_g is clamped
+        to [0, 1];
+      * undersaturated (x2 = -p_b): p_b - dx2 (unchopped) above the updated
+        pressure means free gas appears: the cell becomes saturated with
+        S_g = 0; otherwise p_b is floored at pb_min (the first PVT node)."""
     xn = x.copy()
     xn[0] = x[0] + dx[0]
-    for s in range(1, x.shape[0]):
-        xn[s] = np.clip(x[s] + np.clip(dx[s], -DS_MAX, DS_MAX), 0.0, 1.0)
+    if x.shape[0] > 1:
+        xn[1] = np.clip(x[1] + np.clip(dx[1], -DS_MAX, DS_MAX), 0.0, 1.0)
+    if x.shape[0] < 3:
+        return xn
+    sat = x[2] >= 0.0
+    sg = x[2] + np.clip(dx[2], -DS_MAX, DS_MAX)
+    pb = -(x[2] + dx[2])
+    sat_new = np.where(sg >= 0.0, np.minimum(sg, 1.0), -xn[0])
+    und_new = np.where(pb > xn[0], 0.0, -np.maximum(pb, pb_min))
+    xn[2] = np.where(sat, sat_new, und_new)
     return xn
 
 
@@ -44,7 +61,11 @@ def newton_step(grid, fluid, perm, poro, wells, x_old, x, dt_days, restart=30,
     pc = cpr.cpr_setup(J, coarsest)
     dx, st = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v),
                            rhs, restart=restart, rtol=rtol, max_iter=max_iter)
-    return newton_update(x, dx), dx, st, R
+    return newton_update(x, dx, _pb_min(fluid)), dx, st, R
+
+
+def _pb_min(fluid):
+    return float(np.asarray(fluid["pvt"])[0][0]) if fluid["model"] == 3 else None
 
 
 # ------------------------------------------------------------ time step
@@ -127,7 +148,7 @@ def time_step(grid, fluid, perm, poro, wells, x_old, dt_days, forcing="ew1", the
                 r = b - cpr.block_spmv(J, dx)
             if not (np.isfinite(st["true_rel"]) and np.all(np.isfinite(r))):
                 break
-            x = newton_update(x, dx)
+            x = newton_update(x, dx, _pb_min(fluid))
             with np.errstate(all="ignore"):
                 R, J = model.assemble(grid, fluid, perm, poro, wells, x_old, x, dt)
             b_new = -R

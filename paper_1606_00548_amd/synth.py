@@ -40,7 +40,7 @@ BLACK_OIL_PVT = np.array([
 BLACK_OIL = {
     "model": 3, "p_ref": 200.0,
     "rho_w_ref": 1000.0, "rho_o_sc": 850.0, "rho_g_sc": 0.9,
-    "c_w": 4.5e-5, "c_r": 5.0e-5, "mu_w": 0.5,
+    "c_w": 4.5e-5, "c_o": 1.0e-4, "c_r": 5.0e-5, "mu_w": 0.5,
     "s_wc": 0.2, "s_or": 0.2, "sg_den": 0.7,
     "pvt": BLACK_OIL_PVT,
     "rho_init": 740.0,
@@ -274,6 +274,17 @@ def nn_initial_weights(seed):
     parts.append(rng.standard_normal(16) * 0.25)
     parts.append(np.zeros(1))
     return np.concatenate(parts).astype(np.float32)
+
+
+def undersaturated_cells(case, x, seed, frac=0.4, margin=(5.0, 40.0)):
+    """A black-oil state with a random fraction of cells undersaturated: their
+    third unknown becomes -p_b with p_b = p - U(margin) bar (no free gas)."""
+    rng = np.random.default_rng(seed)
+    x = x.copy()
+    pick = rng.uniform(size=x[0].shape) < frac
+    pb = x[0] - rng.uniform(margin[0], margin[1], x[0].shape)
+    x[2] = np.where(pick, -pb, x[2])
+    return x
 
 
 def random_state_perturbation(case, seed, dp=5.0, ds=0.05):

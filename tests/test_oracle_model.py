@@ -261,3 +261,77 @@ def test_solution_gas_ratio():
     st = model.cell_state(fl, np.full(3, 0.2), x)
     rs, _ = model.pvt_interp(fl["pvt"][0], fl["pvt"][1], p)
     assert np.allclose(st["acc"][2] / st["acc"][0], rs * fl["rho_g_sc"] / fl["rho_o_sc"], rtol=1e-14)
+
+
+# ---- variable switching: undersaturated black oil (third unknown -p_b)
+
+def _mixed_state(case, seed):
+    return synth.undersaturated_cells(case, synth.random_state_perturbation(case, seed), seed + 100)
+
+
+def test_undersaturated_jacobian_matches_central_differences():
+    case = synth.black_oil_layered(3, 3, 3, seed=23)
+    x = _mixed_state(case, 8)
+    assert 0 < int((x[2] < 0).sum()) < x[2].size
+    _, J = _assemble(case, x=x)
+    M = dense_from_blocks(J)
+    b = x.shape[0]
+    n = x[0].size
+    fd = np.zeros_like(M)
+    for cell in range(n):
+        k, j, i = np.unravel_index(cell, x[0].shape)
+        for u in range(b):
+            eps = 1e-7 * max(1.0, abs(x[u, k, j, i]))
+            xp, xm = x.copy(), x.copy()
+            xp[u, k, j, i] += eps
+            xm[u, k, j, i] -= eps
+            Rp, _ = _assemble(case, x=xp)
+            Rm, _ = _assemble(case, x=xm)
+            fd[:, cell * b + u] = (np.moveaxis((Rp - Rm).reshape(b, -1), 0, 1).ravel()) / (2 * eps)
+    scale = np.abs(M).max()
+    assert np.allclose(M, fd, rtol=1e-6, atol=1e-7 * scale)
+
+
+def test_undersaturated_flux_conservation():
+    case = synth.black_oil_layered(4, 4, 3, seed=24)
+    x = _mixed_state(case, 9)
+    case["x_old"] = x.copy()
+    R, J = _assemble(case, x=x, dt=1e20, wells=[])
+    M = dense_from_blocks(J)
+    for c in range(3):
+        assert abs(R[c].sum()) <= 1e-12 * np.abs(R[c]).sum()
+        assert np.all(np.abs(M[c::3].sum(axis=0)) <= 1e-9 * np.abs(M).max())
+
+
+def test_residual_is_continuous_at_the_switch():
+    # S_g = 0 (saturated) and p_b = p (undersaturated) are the same fluid
+    case = synth.black_oil_layered(4, 4, 3, seed=25)
+    x = synth.random_state_perturbation(case, 10)
+    rng = np.random.default_rng(3)
+    pick = rng.uniform(size=x[0].shape) < 0.5
+    xs, xu = x.copy(), x.copy()
+    xs[2] = np.where(pick, 0.0, x[2])
+    xu[2] = np.where(pick, -x[0], x[2])
+    Rs, _ = _assemble(case, x=xs)
+    Ru, _ = _assemble(case, x=xu)
+    assert np.array_equal(Rs, Ru)
+
+
+def test_undersaturated_oil_compressibility():
+    # at a fixed bubble point the oil phase obeys (1/rho) d rho / dp = c_o,
+    # and Rs does not change with p
+    case = synth.black_oil_layered(2, 2, 1, seed=26)
+    x = synth.random_state_perturbation(case, 11)
+    x[2] = -(x[0] - 20.0)
+    h = 1e-3
+    xp, xm = x.copy(), x.copy()
+    xp[0] += h
+    xm[0] -= h
+    st = [model.cell_state(case["fluid"], case["poro"], y) for y in (xp, xm)]
+    rho_o = [s["phases"][0][0] for s in st]
+    c = (np.log(rho_o[0]) - np.log(rho_o[1])) / (2 * h)
+    assert np.allclose(c, case["fluid"]["c_o"], rtol=1e-6)
+    # no free gas; dissolved gas per unit oil component fixed by p_b
+    a0 = [s["acc"][0] for s in st]
+    a2 = [s["acc"][2] for s in st]
+    assert np.allclose(a2[0] / a0[0], a2[1] / a0[1], rtol=1e-13)

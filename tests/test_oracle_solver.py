@@ -259,10 +259,28 @@ def test_cpr_fgmres_solves_tiny_systems(maker):
 def test_newton_update_chops_and_clamps():
     x = np.array([[200.0, 200.0, 200.0], [0.3, 0.95, 0.1], [0.05, 0.05, 0.05]])
     dx = np.array([[5.0, -3.0, 1.0], [0.5, 0.1, -0.3], [0.01, -0.1, 0.0]])
-    xn = newton.newton_update(x, dx)
+    xn = newton.newton_update(x[:2], dx[:2])
     assert np.allclose(xn[0], [205.0, 197.0, 201.0])
     assert np.allclose(xn[1], [0.5, 1.0, 0.0])
-    assert np.allclose(xn[2], [0.06, 0.0, 0.05])
+    xn = newton.newton_update(x, dx, pb_min=50.0)
+    assert np.allclose(xn[1], [0.5, 1.0, 0.0])
+    # the middle cell's gas would go negative: undersaturated at p_b = p
+    assert np.allclose(xn[2], [0.06, -197.0, 0.05])
+
+
+def test_newton_update_switches_the_black_oil_state():
+    # columns: saturated stays, saturated -> undersaturated, undersaturated
+    # stays (p_b moves, unchopped), undersaturated -> saturated (p_b > p),
+    # p_b floored at the first PVT node, S_g clamped at 1
+    x = np.array([[200.0, 200.0, 200.0, 200.0, 60.0, 200.0],
+                  [0.3, 0.3, 0.3, 0.3, 0.3, 0.2],
+                  [0.1, 0.02, -150.0, -190.0, -55.0, 0.9]])
+    dx = np.array([[1.0, 2.0, 3.0, 1.0, -1.0, 0.0],
+                   [0.0] * 6,
+                   [-0.05, -0.1, -30.0, -12.0, 10.0, 0.5]])
+    xn = newton.newton_update(x, dx, pb_min=50.0)
+    assert np.allclose(xn[0], [201.0, 202.0, 203.0, 201.0, 59.0, 200.0])
+    assert np.allclose(xn[2], [0.05, -202.0, -180.0, 0.0, -50.0, 1.0])
 
 
 # ---- BiCGSTAB (the paper's Krylov method, Sec. 4)

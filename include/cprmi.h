@@ -16,8 +16,12 @@
  *   - Cells are numbered in natural order n = i + nx*(j + ny*k), k downward.
  *     A per-cell vector with b unknowns is stored unknown-major, [b][n]:
  *     x[u*n + cell].  Unknowns are (p [bar], S_w) for oil-water and
- *     (p_o [bar], S_w, S_g) for saturated black oil; equation rows are the
- *     components (oil, water[, gas]).
+ *     (p_o [bar], S_w, x2) for black oil, whose third unknown switches with
+ *     the phase state (Sec. 2.4: gas saturation or bubble point pressure):
+ *     x2 = S_g >= 0 in a saturated cell, x2 = -p_b < 0 (bar) in an
+ *     undersaturated cell (no free gas; Rs and mu_o at p_b, B_o = B_o(p_b)
+ *     exp(-c_o (p - p_b))).  Equation rows are the components (oil,
+ *     water[, gas]).
  *   - Every array argument marked "device" is memory on the current HIP
  *     device; the caller owns it and keeps it alive for the call.  Calls are
  *     ordered on the HIP stream given to cpr_create and return once their
@@ -80,7 +84,8 @@ typedef struct {
  *   oil-water: rho_o_ref, rho_w_ref, c_o, c_w, c_r, mu_o, mu_w, s_wc, s_or
  *              (Corey curves of eqs. (17)-(18), exponent 2);
  *   black oil: rho_o_sc, rho_g_sc (surface densities), rho_w_ref, c_w, c_r,
- *              mu_w, s_wc, s_or, sg_den, and a host table pvt[6][n_pvt] of
+ *              mu_w, s_wc, s_or, sg_den, c_o (undersaturated oil
+ *              compressibility), and a host table pvt[6][n_pvt] of
  *              rows p, Rs, Bo, mu_o, Bg, mu_g, piecewise linear in p
  *              (the right-hand segment at a node, end segments extended).
  * The table is copied during cpr_create. */
@@ -258,7 +263,10 @@ int cpr_time_step(cpr_ctx_t* ctx, const double* x_old, double* x, double dt_days
 
 /* Newton update of Algorithm 1, step 5 (device, [b][n]): x += dx with
  * saturation changes chopped to |dS| <= 0.2 and saturations clamped to
- * [0, 1]. */
+ * [0, 1].  Black oil switches the third unknown: a saturated cell whose
+ * S_g would fall below 0 becomes undersaturated with p_b = p (updated); an
+ * undersaturated cell whose updated p_b exceeds p becomes saturated with
+ * S_g = 0; p_b is floored at the first PVT pressure. */
 int cpr_newton_update(cpr_ctx_t* ctx, double* x, const double* dx);
 
 /* Single operations of the path, for verification: y = A x; one CPR

@@ -51,6 +51,7 @@ struct CellState {
   static constexpr int B = Traits<MODEL>::B, NP = Traits<MODEL>::NP, NT = Traits<MODEL>::NT;
   double acc[B], dacc[B][B];
   double rho[NP], drho[NP];
+  double drho_o2 = 0.0;   // black oil: d rho_oil-phase / d x2 (undersaturated cells)
   double lam[NT], dlam[NT][B];
   double lt, dlt[B];
 };
@@ -119,20 +120,34 @@ __device__ void cell_state(const FluidDev& f, double poro, const double* xv, Cel
     s.dlt[0] = 0.0;
     s.dlt[1] = dkrw / mu_w + dkro / mu_o;
   } else {
-    double sw = xv[1], sg = xv[2];
+    // third unknown: S_g >= 0 (saturated), -p_b < 0 (undersaturated: no free
+    // gas, Rs and mu_o at p_b, B_o = B_o(p_b) exp(-c_o (p - p_b)))
+    double sw = xv[1], x2 = xv[2];
+    const bool sat = x2 >= 0.0;
+    double sg = sat ? x2 : 0.0;
+    double dsg = sat ? 1.0 : 0.0;
+    double pb = sat ? p : -x2;
     double so = 1.0 - sw - sg;
-    double drs, dbo, dmuo, dbg, dmug;
-    double rs = pvt_eval(f, 1, p, drs);
-    double bo = pvt_eval(f, 2, p, dbo);
-    double muo = pvt_eval(f, 3, p, dmuo);
+    double drs_b, dbo_b, dmuo_b, dbg, dmug;
+    double rs = pvt_eval(f, 1, pb, drs_b);
+    double bo_b = pvt_eval(f, 2, pb, dbo_b);
+    double muo = pvt_eval(f, 3, pb, dmuo_b);
     double bg = pvt_eval(f, 4, p, dbg);
     double mug = pvt_eval(f, 5, p, dmug);
-    muo *= CP; dmuo *= CP; mug *= CP; dmug *= CP;
+    double e = sat ? 1.0 : exp(-f.c_o * (p - pb));
+    double bo = bo_b * e;
+    double rs_p = sat ? drs_b : 0.0, rs_2 = sat ? 0.0 : -drs_b;
+    double bo_p = sat ? dbo_b : -f.c_o * bo;
+    double bo_2 = sat ? 0.0 : -(dbo_b * e + f.c_o * bo);
+    double mu_p = sat ? dmuo_b : 0.0, mu_2 = sat ? 0.0 : -dmuo_b;
+    muo *= CP; mu_p *= CP; mu_2 *= CP; mug *= CP; dmug *= CP;
     double rsc_o = f.rho_o_sc, rsc_g = f.rho_g_sc;
     double rho_oo = rsc_o / bo;
-    double drho_oo = -rsc_o * dbo / (bo * bo);
+    double rho_oo_p = -rsc_o * bo_p / (bo * bo);
+    double rho_oo_2 = -rsc_o * bo_2 / (bo * bo);
     double rho_og = rsc_g * rs / bo;
-    double drho_og = rsc_g * (drs * bo - rs * dbo) / (bo * bo);
+    double rho_og_p = rsc_g * (rs_p * bo - rs * bo_p) / (bo * bo);
+    double rho_og_2 = rsc_g * (rs_2 * bo - rs * bo_2) / (bo * bo);
     double rho_g = rsc_g / bg;
     double drho_g = -rsc_g * dbg / (bg * bg);
     // relative permeabilities: Corey water / oil-water, quadratic gas, Stone II oil
@@ -148,37 +163,40 @@ __device__ void cell_state(const FluidDev& f, double poro, const double* xv, Cel
     double kro = pos ? raw : 0.0;
     double dkro_w = pos ? (dkrow + dkrw) * (krog + krg) - dkrw : 0.0;
     double dkro_g = pos ? (krow + krw) * (dkrog + dkrg) - dkrg : 0.0;
+    dkrg *= dsg;      // per unit of x2
+    dkro_g *= dsg;
     s.acc[0] = phi * so * rho_oo;
     s.acc[1] = phi * sw * rho_w;
     s.acc[2] = phi * (so * rho_og + sg * rho_g);
-    s.dacc[0][0] = so * (dphi * rho_oo + phi * drho_oo);
+    s.dacc[0][0] = so * (dphi * rho_oo + phi * rho_oo_p);
     s.dacc[0][1] = -phi * rho_oo;
-    s.dacc[0][2] = -phi * rho_oo;
+    s.dacc[0][2] = -phi * rho_oo * dsg + phi * so * rho_oo_2;
     s.dacc[1][0] = sw * (dphi * rho_w + phi * drho_w);
     s.dacc[1][1] = phi * rho_w;
     s.dacc[1][2] = 0.0;
-    s.dacc[2][0] = dphi * (so * rho_og + sg * rho_g) + phi * (so * drho_og + sg * drho_g);
+    s.dacc[2][0] = dphi * (so * rho_og + sg * rho_g) + phi * (so * rho_og_p + sg * drho_g);
     s.dacc[2][1] = -phi * rho_og;
-    s.dacc[2][2] = phi * (rho_g - rho_og);
-    s.rho[0] = rho_oo + rho_og; s.drho[0] = drho_oo + drho_og;
+    s.dacc[2][2] = phi * (-rho_og * dsg + so * rho_og_2 + rho_g * dsg);
+    s.rho[0] = rho_oo + rho_og; s.drho[0] = rho_oo_p + rho_og_p;
+    s.drho_o2 = rho_oo_2 + rho_og_2;
     s.rho[1] = rho_w; s.drho[1] = drho_w;
     s.rho[2] = rho_g; s.drho[2] = drho_g;
     // mass mobilities rho k_r / mu of each (component, phase) term
-    auto mob = [](int t, CellState<MODEL>& st, double rho, double drho, double kr, double dkr_w,
-                  double dkr_g, double mu, double dmu) {
+    auto mob = [](int t, CellState<MODEL>& st, double rho, double rho_p, double rho_2, double kr, double dkr_w,
+                  double dkr_2, double mu, double dmu_p, double dmu_2) {
       st.lam[t] = rho * kr / mu;
-      st.dlam[t][0] = (drho * kr - rho * kr * dmu / mu) / mu;
+      st.dlam[t][0] = (rho_p * kr - rho * kr * dmu_p / mu) / mu;
       st.dlam[t][1] = rho * dkr_w / mu;
-      st.dlam[t][2] = rho * dkr_g / mu;
+      st.dlam[t][2] = (rho_2 * kr + rho * dkr_2 - rho * kr * dmu_2 / mu) / mu;
     };
-    mob(0, s, rho_oo, drho_oo, kro, dkro_w, dkro_g, muo, dmuo);
-    mob(1, s, rho_w, drho_w, krw, dkrw, 0.0, mu_w, 0.0);
-    mob(2, s, rho_og, drho_og, kro, dkro_w, dkro_g, muo, dmuo);
-    mob(3, s, rho_g, drho_g, krg, 0.0, dkrg, mug, dmug);
+    mob(0, s, rho_oo, rho_oo_p, rho_oo_2, kro, dkro_w, dkro_g, muo, mu_p, mu_2);
+    mob(1, s, rho_w, drho_w, 0.0, krw, dkrw, 0.0, mu_w, 0.0, 0.0);
+    mob(2, s, rho_og, rho_og_p, rho_og_2, kro, dkro_w, dkro_g, muo, mu_p, mu_2);
+    mob(3, s, rho_g, drho_g, 0.0, krg, 0.0, dkrg, mug, dmug, 0.0);
     s.lt = krw / mu_w + kro / muo + krg / mug;
-    s.dlt[0] = -kro * dmuo / (muo * muo) - krg * dmug / (mug * mug);
+    s.dlt[0] = -kro * mu_p / (muo * muo) - krg * dmug / (mug * mug);
     s.dlt[1] = dkrw / mu_w + dkro_w / muo;
-    s.dlt[2] = dkro_g / muo + dkrg / mug;
+    s.dlt[2] = dkro_g / muo - kro * mu_2 / (muo * muo) + dkrg / mug;
   }
 }
 
@@ -188,7 +206,8 @@ struct PropPlanes {
   static constexpr int B = Traits<MODEL>::B, NP = Traits<MODEL>::NP, NT = Traits<MODEL>::NT;
   static constexpr int RHO = 0, DRHO = NP, LAM = 2 * NP, DLAM = 2 * NP + NT;
   static constexpr int LT = 2 * NP + NT + NT * B;   // total volumetric mobility (network feature)
-  static constexpr int COUNT = LT + 1;
+  static constexpr int DRHO_O2 = LT + 1;            // black oil: d rho_oil-phase / d x2
+  static constexpr int COUNT = MODEL == 3 ? DRHO_O2 + 1 : LT + 1;
 };
 
 template <int MODEL>
@@ -212,6 +231,7 @@ __global__ void props_kernel(FluidDev f, Lay L, const double* __restrict__ poro,
     for (int u = 0; u < B; ++u) props[(PP::DLAM + q * B + u) * n + t] = s.dlam[q][u];
   }
   props[PP::LT * n + t] = s.lt;
+  if constexpr (MODEL == 3) props[PP::DRHO_O2 * n + t] = s.drho_o2;
 }
 
 template <int MODEL>
@@ -247,6 +267,8 @@ __global__ void flux_kernel(FluidDev f, Lay L, double dz, double top, double vol
     rho_s[q] = props[(PP::RHO + q) * n + t];
     drho_s[q] = props[(PP::DRHO + q) * n + t];
   }
+  double dro2_s = 0.0;
+  if constexpr (MODEL == 3) dro2_s = props[PP::DRHO_O2 * n + t];
   for (int q = 0; q < NT; ++q) {
     lam_s[q] = props[(PP::LAM + q) * n + t];
     for (int u = 0; u < B; ++u) dlam_s[q][u] = props[(PP::DLAM + q * B + u) * n + t];
@@ -272,6 +294,11 @@ __global__ void flux_kernel(FluidDev f, Lay L, double dz, double top, double vol
         lam_n[q] = props[(PP::LAM + q) * n + nb];
         for (int u = 0; u < B; ++u) dlam_n[q][u] = props[(PP::DLAM + q * B + u) * n + nb];
       }
+      double dro2_n = 0.0;
+      if constexpr (MODEL == 3) dro2_n = props[PP::DRHO_O2 * n + nb];
+      // x2 derivative of the oil-phase potential difference (undersaturated cells)
+      const double dd2lo = -0.5 * G_ACC * (plus ? (z_self - z_nb) : (z_nb - z_self)) * (plus ? dro2_s : dro2_n);
+      const double dd2hi = -0.5 * G_ACC * (plus ? (z_self - z_nb) : (z_nb - z_self)) * (plus ? dro2_n : dro2_s);
       // orient the face lower-index cell -> upper-index cell
       const double* rho_lo = plus ? rho_s : rho_n;
       const double* rho_hi = plus ? rho_n : rho_s;
@@ -303,6 +330,10 @@ __global__ void flux_kernel(FluidDev f, Lay L, double dz, double top, double vol
         }
         dFlo[0] += T * lam_up * ddlo[ph];
         dFhi[0] += T * lam_up * ddhi[ph];
+        if (MODEL == 3 && ph == 0) {
+          dFlo[B - 1] += T * lam_up * dd2lo;
+          dFhi[B - 1] += T * lam_up * dd2hi;
+        }
         if (plus) {
           R[c] += F;
           for (int u = 0; u < B; ++u) {
@@ -372,6 +403,7 @@ __global__ void well_kernel(FluidDev f, Lay L, int nperf, const Perf* __restrict
       for (int u = 0; u < B; ++u) {
         double v = pf.wi * s.dlam[tt][u] * drive;
         if (u == 0) v += pf.wi * s.lam[tt] * (-BAR - drho * G_ACC * pf.dzh);
+        if (MODEL == 3 && u == 2 && ph == 0) v += pf.wi * s.lam[tt] * (-s.drho_o2 * G_ACC * pf.dzh);
         dq[c][u] += v;
       }
     }

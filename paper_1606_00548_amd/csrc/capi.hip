@@ -548,7 +548,7 @@ int cpr_export_krylov(cpr_ctx_t* ctx, int j, double* v) {
 int cpr_newton_update(cpr_ctx_t* ctx, double* x, const double* dx) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   if (!x || !dx) return set_err(ctx, CPR_EINVAL, "null argument");
-  launch_newton_update(ctx->b, ctx->lay.n, x, dx, ctx->stream);
+  launch_newton_update(ctx->b, ctx->lay.n, pb_floor(ctx->fl), x, dx, ctx->stream);
   return launch_check(ctx, "cpr_newton_update");
 }
 

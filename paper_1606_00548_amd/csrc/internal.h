@@ -318,5 +318,7 @@ int time_step(cpr_ctx* ctx, const double* xold_cs, double* x_cs, double dt_days,
 // krylov.hip
 int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st);
 int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st);
-void launch_newton_update(int b, int n, double* x, const double* dx, hipStream_t s);
+void launch_newton_update(int b, int n, double pb_min, double* x, const double* dx, hipStream_t s);
+// Bubble-point floor of the black-oil update: the first PVT pressure node.
+inline double pb_floor(const FluidDev& f) { return f.model == 3 ? f.pvt[0][0] : 0.0; }
 int reduce_dot(cpr_ctx* ctx, const double* a, const double* b, long len, double* out);

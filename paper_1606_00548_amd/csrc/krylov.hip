@@ -208,17 +208,33 @@ __global__ void zero_kernel(long len, double* __restrict__ x) {
 }
 
 // Newton update: x += dx, saturation changes chopped to |dS| <= 0.2,
-// saturations clamped to [0, 1].
-__global__ void newton_update_kernel(int b, int n, double* __restrict__ x, const double* __restrict__ dx) {
+// saturations clamped to [0, 1].  Black oil (b = 3) switches its third
+// unknown with the phase state: a saturated cell (x2 = S_g >= 0) whose gas
+// would go negative becomes undersaturated at its bubble point, x2 = -p
+// (updated p); an undersaturated cell (x2 = -p_b) whose bubble point rises
+// above the updated pressure becomes saturated with S_g = 0; otherwise p_b
+// (unchopped) is floored at pb_min.
+__global__ void newton_update_kernel(int b, int n, double pb_min, double* __restrict__ x,
+                                     const double* __restrict__ dx) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  x[t] = x[t] + dx[t];
+  const double p = x[t] + dx[t];
+  x[t] = p;
   for (int s = 1; s < b; ++s) {
     size_t o = (size_t)s * n + t;
     double d = dx[o];
-    d = d < -0.2 ? -0.2 : (d > 0.2 ? 0.2 : d);
-    double v = x[o] + d;
-    x[o] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+    double dc = d < -0.2 ? -0.2 : (d > 0.2 ? 0.2 : d);
+    double v = x[o] + dc;
+    if (s == 2) {
+      if (x[o] >= 0.0) {
+        x[o] = v >= 0.0 ? (v > 1.0 ? 1.0 : v) : -p;
+      } else {
+        double pb = -(x[o] + d);
+        x[o] = pb > p ? 0.0 : -(pb > pb_min ? pb : pb_min);
+      }
+    } else {
+      x[o] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+    }
   }
 }
 
@@ -366,8 +382,8 @@ __global__ __launch_bounds__(KB) void bicg_xr_kernel(long len, const double* __r
 
 }  // namespace
 
-void launch_newton_update(int b, int n, double* x, const double* dx, hipStream_t s) {
-  newton_update_kernel<<<div_up(n, 256), 256, 0, s>>>(b, n, x, dx);
+void launch_newton_update(int b, int n, double pb_min, double* x, const double* dx, hipStream_t s) {
+  newton_update_kernel<<<div_up(n, 256), 256, 0, s>>>(b, n, pb_min, x, dx);
 }
 
 // Dot product of two device vectors of length len into *out (host).  Syncs.

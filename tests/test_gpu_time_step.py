@@ -65,10 +65,12 @@ def test_time_step_cuts_match_oracle():
     assert st["cuts"] >= 1
 
 
-def test_black_oil_time_step_with_cuts_matches_oracle():
+def test_black_oil_time_step_matches_oracle():
+    # cells near the injector become undersaturated; with variable switching
+    # the step needs no cut (cuts with switching: the switching tests)
     case = synth.black_oil_layered(16, 12, 4, seed=5)
     st = _compare(case, 0.1, {}, "black oil 16x12x4, dt 0.1")
-    assert st["converged"] and st["cuts"] >= 1
+    assert st["converged"] and st["cuts"] == 0
 
 
 def test_failed_step_returns_x_old():

@@ -167,3 +167,31 @@ def time_step(grid, fluid, perm, poro, wells, x_old, dt_days, forcing="ew1", the
             return x, stats
         dt *= 0.5
     return x_old.copy(), stats
+
+
+def simulate(grid, fluid, perm, poro, wells, x0, t_end, dt0, dt_max, growth=2.0, **step_kw):
+    """Backward-Euler time stepping from x0 over [0, t_end] days: each step is
+    time_step (with its cuts); after a step that needed no cut the next dt
+    grows by `growth` up to dt_max, after a cut it stays at the step taken;
+    the last step is shortened to end at t_end.  Returns (x, stats) with the
+    number of steps, the sums of cuts, Newton and linear iterations over
+    every attempt, the step sizes taken, and whether t_end was reached."""
+    x = x0.copy()
+    t = 0.0
+    dt = float(dt0)
+    st = {"steps": 0, "cuts": 0, "total_newton": 0, "total_linear": 0, "dts": [], "completed": False}
+    while t < t_end:
+        h = min(dt, t_end - t)
+        x_new, s = time_step(grid, fluid, perm, poro, wells, x, h, **step_kw)
+        st["cuts"] += s["cuts"]
+        st["total_newton"] += s["total_newton"]
+        st["total_linear"] += s["total_linear"]
+        if not s["converged"]:
+            return x, st
+        x = x_new
+        st["steps"] += 1
+        st["dts"].append(s["dt_taken"])
+        t = t + s["dt_taken"]
+        dt = min(growth * s["dt_taken"], dt_max) if s["cuts"] == 0 else s["dt_taken"]
+    st["completed"] = True
+    return x, st

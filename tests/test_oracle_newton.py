@@ -85,3 +85,26 @@ def test_time_step_converges_and_inexact_forcing_saves_linear_work(forcing):
     if forcing != "fixed":
         _, sf = _run(case, 1.0, forcing="fixed")
         assert st["total_linear"] < sf["total_linear"]
+
+
+def test_simulate_steps_add_up_and_grow():
+    case = synth.black_oil_layered(16, 12, 4, seed=5)
+    x, st = newton.simulate(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                            case["x_old"], 1.0, 0.01, 0.25)
+    assert st["completed"] and abs(sum(st["dts"]) - 1.0) <= 1e-12
+    t = 0.0
+    for a, b in zip(st["dts"][:-1], st["dts"][1:]):
+        t += a
+        assert b == min(2.0 * a, 0.25, 1.0 - t) or np.isclose(b, 1.0 - t, rtol=1e-12)
+    assert max(st["dts"]) == 0.25
+
+
+def test_simulate_is_a_sequence_of_time_steps():
+    case = synth.oil_water_lognormal(8, 6, 3, seed=82)
+    x, st = newton.simulate(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                            case["x_old"], 3.0, 1.0, 1.0, growth=1.0)
+    xr = case["x_old"]
+    for _ in range(3):
+        xr, s = _run(dict(case, x_old=xr), 1.0)
+        assert s["converged"] and s["cuts"] == 0
+    assert st["completed"] and st["steps"] == 3 and np.array_equal(x, xr)

@@ -160,6 +160,42 @@ def main():
             v["speedup_vs_fp64"] = variants["fp64"]["s_per_step"] / v["s_per_step"]
         solver.attach_network(None)
 
+    # one whole backward-Euler step of the same workload (Algorithm 1 with
+    # the first forcing term of eq. (14), time-step cuts, variable switching)
+    time_step, simulation = {}, {}
+    if not args.no_variants:
+        from paper_1606_00548_amd import train
+        wfile = train.weights_path("black-oil")
+        forms = [("fp64", dict(precision="fp64"))]
+        if os.path.exists(wfile):
+            solver.attach_network(np.load(wfile))
+            forms.append(("mixed+learned", dict(precision="mixed", learned=1)))
+        xts = torch.empty_like(x0)
+        for name, kw in forms:
+            lo = cprmi.default_options(**kw)
+            solver.time_step(x_old, case["dt"], options=lo, x=xts)        # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, tst = solver.time_step(x_old, case["dt"], options=lo, x=xts)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            time_step[name] = {"s": t1 - t0, "converged": bool(tst["converged"]), "cuts": tst["cuts"],
+                               "dt_taken_days": tst["dt_taken"], "newton_iterations": tst["newton_iterations"],
+                               "linear_iterations": tst["history"]["linear_iterations"],
+                               "total_newton": tst["total_newton"], "total_linear": tst["total_linear"],
+                               "undersaturated_cells": int((xts[2] < 0).sum())}
+            # the same day with step growth from 0.01 day (cpr_simulate)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, sst = solver.simulate(x_old, case["dt"], 0.01, case["dt"], options=lo, x=xts)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            simulation[name] = {"s": t1 - t0, "completed": bool(sst["completed"]), "steps": sst["steps"],
+                                "cuts": sst["cuts"], "total_newton": sst["total_newton"],
+                                "total_linear": sst["total_linear"], "dts_days": sst["dts"],
+                                "undersaturated_cells": int((xts[2] < 0).sum())}
+        solver.attach_network(None)
+
     # per-phase breakdown of one more (untimed) step
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     x.copy_(x0)
@@ -244,7 +280,7 @@ def main():
                    "cells": n, "block": b, "precision": args.precision, "restart": 30, "rtol": 1e-6},
         "fgmres_iterations": its, "restart_cycles": cycles, "true_rel": st["true_rel"],
         "phases_ms": phases, "roofline": roofline, "kernel_classes": classes, "cpu_baseline": cpu,
-        "variants": variants,
+        "variants": variants, "time_step": time_step, "simulation": simulation,
     }
     print(json.dumps(out))
 

@@ -261,6 +261,28 @@ void cpr_default_newton_options(cpr_newton_options_t* o);
 int cpr_time_step(cpr_ctx_t* ctx, const double* x_old, double* x, double dt_days, const cpr_options_t* lin,
                   const cpr_newton_options_t* nopt, cpr_newton_stats_t* st);
 
+#define CPR_SIM_HIST 256
+typedef struct {
+  int completed;               /* t_end reached                               */
+  int steps;                   /* accepted time steps                         */
+  int cuts, total_newton, total_linear;   /* sums over every attempt          */
+  double t_reached;            /* days                                        */
+  double dts[CPR_SIM_HIST];    /* step sizes taken (first 256)                */
+} cpr_sim_stats_t;
+
+/* Backward-Euler time stepping over [0, t_end_days] from x0 (device, [b][n],
+ * natural order) into x (device, may equal x0): cpr_time_step for each step
+ * (with its cuts); after a step that needed no cut the next dt is
+ * min(growth * dt_taken, dt_max), after a cut it stays dt_taken; the last
+ * step ends exactly at t_end.  The time-step control around the inexact
+ * Newton method reported in Sec. 4 (maximum step, cuts); the growth rule is
+ * not in the paper.  Returns CPR_OK when t_end is reached, CPR_NOT_CONVERGED
+ * when a step fails after its last cut (x then holds the state at
+ * st->t_reached). */
+int cpr_simulate(cpr_ctx_t* ctx, const double* x0, double* x, double t_end_days, double dt0_days,
+                 double dt_max_days, double growth, const cpr_options_t* lin, const cpr_newton_options_t* nopt,
+                 cpr_sim_stats_t* st);
+
 /* Newton update of Algorithm 1, step 5 (device, [b][n]): x += dx with
  * saturation changes chopped to |dS| <= 0.2 and saturations clamped to
  * [0, 1].  Black oil switches the third unknown: a saturated cell whose

@@ -90,6 +90,20 @@ class NewtonStats(ctypes.Structure):
         return d
 
 
+SIM_HIST = 256
+
+
+class SimStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int), ("steps", ctypes.c_int), ("cuts", ctypes.c_int),
+                ("total_newton", ctypes.c_int), ("total_linear", ctypes.c_int), ("t_reached", ctypes.c_double),
+                ("dts", ctypes.c_double * SIM_HIST)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_[:6]}
+        d["dts"] = list(self.dts[:min(self.steps, SIM_HIST)])
+        return d
+
+
 EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error", "cpr_block_size",
            "cpr_num_cells", "assemble_jacobian", "cpr_import_jacobian", "cpr_export_jacobian",
            "cpr_setup", "cpr_gmres_solve", "cpr_newton_update", "cpr_spmv", "cpr_precond_apply",
@@ -99,7 +113,7 @@ EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error",
            "cpr_nn_forward", "cpr_nn_backward", "cpr_nn_train_step", "cpr_nn_attach",
            "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov", "cpr_nn_eval_loss",
            "cpr_nn_make_target", "cpr_nn_infer", "cpr_bicgstab_solve", "cpr_default_newton_options",
-           "cpr_time_step"]
+           "cpr_time_step", "cpr_simulate"]
 KCLASS = {"spmv": 0, "orth": 1, "smooth": 2, "ilu": 3, "assemble": 4}
 
 
@@ -128,6 +142,8 @@ def load():
     lib.cpr_gmres_solve.argtypes = [P, P, P, ctypes.POINTER(Stats)]
     lib.cpr_bicgstab_solve.argtypes = [P, P, P, ctypes.POINTER(Stats)]
     lib.cpr_default_newton_options.argtypes = [ctypes.POINTER(NewtonOptions)]
+    lib.cpr_simulate.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.POINTER(Options), ctypes.POINTER(NewtonOptions), ctypes.POINTER(SimStats)]
     lib.cpr_time_step.argtypes = [P, P, P, ctypes.c_double, ctypes.POINTER(Options),
                                   ctypes.POINTER(NewtonOptions), ctypes.POINTER(NewtonStats)]
     lib.cpr_newton_update.argtypes = [P, P, P]
@@ -382,6 +398,20 @@ class Solver:
         rc = self._check(self.lib.cpr_time_step(self.ctx, _ptr(x_old), _ptr(x), float(dt_days),
                                                 ctypes.byref(lo), ctypes.byref(no), ctypes.byref(st)),
                          allow=(0, 1))
+        d = st.as_dict()
+        d["status"] = rc
+        return x, d
+
+    def simulate(self, x0, t_end, dt0, dt_max, growth=2.0, options=None, newton=None, x=None):
+        """Time stepping over [0, t_end] days from x0 (cpr_simulate);
+        returns (x, stats)."""
+        x = self.vector() if x is None else x
+        lo = options if options is not None else default_options()
+        no = newton if isinstance(newton, NewtonOptions) else default_newton_options(**(newton or {}))
+        st = SimStats()
+        rc = self._check(self.lib.cpr_simulate(self.ctx, _ptr(x0), _ptr(x), float(t_end), float(dt0),
+                                               float(dt_max), float(growth), ctypes.byref(lo), ctypes.byref(no),
+                                               ctypes.byref(st)), allow=(0, 1))
         d = st.as_dict()
         d["status"] = rc
         return x, d

@@ -450,6 +450,51 @@ int cpr_time_step(cpr_ctx_t* ctx, const double* x_old, double* x, double dt_days
   GUARD_END
 }
 
+int cpr_simulate(cpr_ctx_t* ctx, const double* x0, double* x, double t_end_days, double dt0_days,
+                 double dt_max_days, double growth, const cpr_options_t* lin, const cpr_newton_options_t* nopt,
+                 cpr_sim_stats_t* st) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  GUARD_BEGIN
+  if (!x0 || !x) return set_err(ctx, CPR_EINVAL, "null argument");
+  if (!(t_end_days > 0) || !(dt0_days > 0) || !(dt_max_days > 0) || !(growth >= 1.0) ||
+      !std::isfinite(t_end_days) || !std::isfinite(dt_max_days) || !std::isfinite(growth))
+    return set_err(ctx, CPR_EINVAL, "bad time-stepping parameters");
+  cpr_options_t lo;
+  if (lin) lo = *lin; else cpr_default_options(&lo);
+  cpr_newton_options_t no;
+  if (nopt) no = *nopt; else cpr_default_newton_options(&no);
+  hipStream_t s = ctx->stream;
+  const long len = (long)ctx->b * ctx->lay.n;
+  double* xa = ctx->vin2;   // state at the start of the step (colour-split)
+  launch_nat_to_cs(ctx->lay, ctx->b, x0, xa, s);
+  cpr_sim_stats_t S = {};
+  double t = 0.0, dt = dt0_days;
+  int rc = CPR_OK;
+  while (t < t_end_days) {
+    double h = std::fmin(dt, t_end_days - t);
+    cpr_newton_stats_t ns = {};
+    rc = time_step(ctx, xa, ctx->vin, h, lo, no, &ns);
+    if (rc < 0) break;
+    S.cuts += ns.cuts;
+    S.total_newton += ns.total_newton;
+    S.total_linear += ns.total_linear;
+    if (rc != CPR_OK) break;
+    CPR_TRY(hipMemcpyAsync(xa, ctx->vin, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (S.steps < CPR_SIM_HIST) S.dts[S.steps] = ns.dt_taken;
+    S.steps += 1;
+    t += ns.dt_taken;
+    dt = ns.cuts == 0 ? std::fmin(growth * ns.dt_taken, dt_max_days) : ns.dt_taken;
+  }
+  S.t_reached = t;
+  S.completed = (rc == CPR_OK && t >= t_end_days) ? 1 : 0;
+  if (rc >= 0) launch_cs_to_nat(ctx->lay, ctx->b, xa, x, s);
+  if (st) *st = S;
+  if (rc < 0) return rc;
+  int rc2 = launch_check(ctx, "cpr_simulate");
+  return rc2 != CPR_OK ? rc2 : rc;
+  GUARD_END
+}
+
 int cpr_bicgstab_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* st) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   GUARD_BEGIN

@@ -125,3 +125,24 @@ def test_time_step_rejects_bad_options():
     with pytest.raises(cprmi.CPRError):
         s.time_step(_gpu(case["x_old"]), -1.0)
     s.close()
+
+
+@pytest.mark.parametrize("name", ["black-oil", "oil-water"])
+def test_simulate_matches_oracle(name):
+    if name == "black-oil":
+        case, t_end, dt0, dt_max = synth.black_oil_layered(16, 12, 4, seed=5), 1.0, 0.01, 1.0
+    else:
+        case, t_end, dt0, dt_max = synth.oil_water_lognormal(16, 12, 4, seed=6), 10.0, 0.1, 5.0
+    s = _solver(case)
+    xg, sg = s.simulate(_gpu(case["x_old"]), t_end, dt0, dt_max)
+    xo, so = newton.simulate(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                             case["x_old"], t_end, dt0, dt_max)
+    x = xg.cpu().numpy()
+    print(f"[time-step] simulate {name}: steps {sg['steps']} (oracle {so['steps']}), Newton {sg['total_newton']} "
+          f"(oracle {so['total_newton']}), linear {sg['total_linear']} (oracle {so['total_linear']})")
+    assert sg["completed"] and so["completed"] and sg["status"] == 0
+    assert sg["steps"] == so["steps"] and sg["cuts"] == so["cuts"]
+    assert sg["total_newton"] == so["total_newton"] and sg["total_linear"] == so["total_linear"]
+    assert sg["dts"] == so["dts"] and sg["t_reached"] == sum(so["dts"])
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+    s.close()

@@ -1,16 +1,14 @@
 """The larger workloads at their full sizes, checked where the oracle reaches.
 
 * Black oil, channelised, 256 x 256 x 64 (4.19 M cells, 3 x 3 blocks):
-  exactly ten Newton iterations of one 0.1-day time step with the FP64 and
-  with the mixed-precision preconditioner; every linear solve must reach
-  the 1e-6 true relative residual and the Newton residual must fall by
-  10x; the distance between the FP32-preconditioned and FP64 iterates is
-  printed per step.  The first Newton system of a 10-day step is solved
-  too.  (Without time-step control or variable switching, the Newton
-  iteration of longer steps on this grid does not settle in ten iterations
-  (0.25 and 0.5 day), and after the first iteration of a 10-day step its
-  systems stall FGMRES(30) at 300 iterations -- as they do for the oracle
-  at 64 x 64 x 16 and 128 x 128 x 32.)
+  the first Newton system of a 10-day step, solved to the 1e-6 true
+  relative residual with the FP64 and the mixed-precision preconditioner;
+  then the 10 days by time stepping from 0.01 day (step growth, cuts,
+  variable switching, inexact Newton with the first forcing term) with
+  both preconditioners: both must complete, and since each stops at the
+  Newton tolerance (1e-3 relative) rather than at one iterate, their final
+  pressures must agree to 1e-3, water saturations to 0.05 and phase states
+  in 99.9 % of the cells.
 * Black oil, lattice of 25 wells, 512 x 512 x 128 (33.5 M cells, 17 GB FP64
   Jacobian): one Newton step with plain FP64 CPR and with mixed precision +
   the learned pressure stage; both must reach 1e-6.
@@ -90,9 +88,9 @@ def _true_rel(s, rhs, dx):
     return float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(rhs))
 
 
-def test_channelised_256x256x64_ten_newton_steps_mixed_vs_fp64():
+def test_channelised_256x256x64_ten_days_mixed_vs_fp64():
     from paper_1606_00548_amd import cprmi
-    print("[full-size] black oil channelised 256x256x64, 10 Newton iterations", flush=True)
+    print("[full-size] black oil channelised 256x256x64, 10 days", flush=True)
     case = synth.black_oil_channelised()
     s = cprmi.Solver.from_case(case)
     x_old = _gpu(case["x_old"])
@@ -112,29 +110,25 @@ def test_channelised_256x256x64_ten_newton_steps_mixed_vs_fp64():
         print(f"[full-size]   {prec}, dt {case['dt']:g} days, first Newton system: {st['iterations']} "
               f"FGMRES iterations, true rel. {rel:.2e}", flush=True)
         assert st["status"] == 0 and rel <= 1e-6
-    dt = 0.1
-    xs = {}
-    fnorm = {}
+    # ten days of time stepping from dt0 = 0.01 day (step growth, cuts,
+    # variable switching) with the FP64 and the mixed-precision preconditioner
+    res = {}
     for prec in ("fp64", "mixed"):
-        x = _gpu(case["x"])
-        xs[prec], fnorm[prec] = [], []
-        for it in range(10):
-            rhs = s.assemble(x_old, x, dt)
-            fnorm[prec].append(float(torch.linalg.vector_norm(rhs)))
-            s.setup(precision=prec)
-            dx, st = s.solve(rhs)
-            rel = _true_rel(s, rhs, dx)
-            print(f"[full-size]   {prec}, dt {dt:g} day, Newton {it + 1}: |F| {fnorm[prec][-1]:.3e}, "
-                  f"{st['iterations']} FGMRES iterations, true rel. {rel:.2e}", flush=True)
-            assert st["status"] == 0 and rel <= 1e-6, (prec, it, st)
-            s.newton_update(x, dx)
-            xs[prec].append(x.clone())
-        assert fnorm[prec][-1] < 0.1 * fnorm[prec][0]
-    for it in range(10):
-        d = float(torch.linalg.vector_norm(xs["mixed"][it] - xs["fp64"][it]) /
-                  torch.linalg.vector_norm(xs["fp64"][it]))
-        print(f"[full-size]   Newton {it + 1}: |x_mixed - x_fp64| / |x_fp64| = {d:.2e}")
-        assert d <= 1e-3
+        xf, st = s.simulate(x_old, case["dt"], 0.01, case["dt"], options=cprmi.default_options(precision=prec))
+        torch.cuda.synchronize()
+        print(f"[full-size]   {prec}: {case['dt']:g} days in {st['steps']} steps, {st['cuts']} cuts, "
+              f"{st['total_newton']} Newton and {st['total_linear']} FGMRES iterations, "
+              f"{int((xf[2] < 0).sum())} undersaturated cells", flush=True)
+        assert st["completed"] and st["status"] == 0
+        res[prec] = xf.clone()
+    xf, xm = res["fp64"], res["mixed"]
+    dp = float(torch.linalg.vector_norm(xm[0] - xf[0]) / torch.linalg.vector_norm(xf[0]))
+    dsw = float((xm[1] - xf[1]).abs().max())
+    same = float(((xm[2] < 0) == (xf[2] < 0)).double().mean())
+    print(f"[full-size]   mixed vs fp64 after {case['dt']:g} days: |dp|/|p| {dp:.2e}, max |dSw| {dsw:.2e}, "
+          f"cells in the same phase state {same:.6f}")
+    # both stop at the Newton tolerance (1e-3 relative), not at the same iterate
+    assert dp <= 1e-3 and dsw <= 5e-2 and same >= 0.999
     s.close()
 
 

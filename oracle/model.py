@@ -300,7 +300,22 @@ def row_scales(grid, fluid, poro, dt_days):
     return np.array([r * vol * phibar / dt for r in component_density_ref(fluid)])
 
 
-def assemble(grid, fluid, perm_md, poro, wells, x_old, x, dt_days):
+def rate_wells(wells):
+    """Wells under a rate constraint (eqs. (8)-(9)), whose bottom-hole
+    pressure is an unknown; the others are under eq. (7)."""
+    return [w for w in wells if w.get("control", "bhp") == "rate"]
+
+
+def surface_density(fluid, comp):
+    """Density converting the controlled component's mass rate to the rate
+    of eqs. (8)-(9): water rho_w_ref; oil rho_o_sc (black oil) or rho_o_ref."""
+    m = fluid["model"]
+    if m == 1 or comp == 1:
+        return fluid["rho_w_ref"]
+    return fluid["rho_o_sc"] if m == 3 else fluid["rho_o_ref"]
+
+
+def assemble(grid, fluid, perm_md, poro, wells, x_old, x, dt_days, bhp=None, border=False):
     """Residual R(x) and Jacobian J = dR/dx of the scaled system.
 
     Residual of component c in cell i (backward Euler, eq. (10); TPFA
@@ -312,6 +327,17 @@ def assemble(grid, fluid, perm_md, poro, wells, x_old, x, dt_days):
     J[d, r, c, cell] = dR_r(cell) / dx_c(neighbour d of cell); blocks that
     would reach outside the grid (no-flow boundary) are zero.  The Newton
     right-hand side is b = -R.
+
+    Rate-controlled wells (eqs. (8)-(9)): their bottom-hole pressures are
+    unknowns, bhp[w] (bar) in the order of rate_wells(wells) (default: each
+    well's "bhp" entry).  An injector's water rate or a producer's oil rate
+    sums its perforations' mass rates; with Q the target (surface m^3/day)
+    and rho_s the surface density of the component c,
+        R_w = (sum_m q_c,m - Q rho_s / 86400) / s_c    (injector)
+        R_w = (sum_m q_c,m + Q rho_s / 86400) / s_c    (producer, q_c,m < 0)
+    With border=True a third value W holds the border of the Jacobian of
+    eq. (16): W["R"] (nr,), W["B"] (nr, b, grid) = dR_cells / dp_h,
+    W["C"] (nr, b, grid) = dR_w / dx_cells, W["D"] (nr,) = dR_w / dp_h.
     """
     m = fluid["model"]
     b = nblock(m)
@@ -362,14 +388,26 @@ def assemble(grid, fluid, perm_md, poro, wells, x_old, x, dt_days):
                 J[dplus, c, u][lo] += dF_hi[u]
                 J[dminus, c, u][hi] -= dF_lo[u]
                 J[0, c, u][hi] -= dF_hi[u]
-    # wells, eq. (6) with the BHP constraint of eq. (7)
+    # wells, eq. (6); BHP constraint eq. (7) or rate constraint eqs. (8)-(9)
+    rws = rate_wells(wells)
+    nr = len(rws)
+    if bhp is None:
+        bhp = np.array([w["bhp"] for w in rws], dtype=np.float64)
+    W = {"R": np.zeros(nr), "B": np.zeros((nr, b) + shape), "C": np.zeros((nr, b) + shape),
+         "D": np.zeros(nr)}
     for w in wells:
         i, j = w["i"], w["j"]
+        iw = next((q for q, rw in enumerate(rws) if rw is w), None)
+        ph_w = w["bhp"] if iw is None else bhp[iw]
+        if iw is not None:
+            wc = (0 if m == 1 else 1) if w["kind"] == "inj" else 0    # controlled component
+            sgn = -1.0 if w["kind"] == "inj" else 1.0
+            W["R"][iw] += sgn * w["rate"] * surface_density(fluid, wc) / DAY
         for k in range(w["k0"], w["k1"] + 1):
             cell = (k, j, i)
             wi = peaceman_wi(perm_md[0][cell], perm_md[1][cell], grid["dx"], grid["dy"],
                              grid["dz"], w["rw"], w["skin"])
-            dh = w["bhp"] - x[0][cell]            # bar
+            dh = ph_w - x[0][cell]                # bar
             dzh = grid["top"] - depth[cell]       # z_h - z
             if w["kind"] == "inj":
                 rho, drho = st["phases"][-1 if m == 1 else 1]
@@ -384,6 +422,13 @@ def assemble(grid, fluid, perm_md, poro, wells, x_old, x, dt_days):
                         dq += wi * drho[0][cell] * lt[cell] * drive
                         dq += wi * rho[cell] * lt[cell] * (-BAR - drho[0][cell] * G * dzh)
                     J[0, wc, u][cell] -= dq
+                    if iw is not None:
+                        W["C"][iw][(u,) + cell] += dq
+                if iw is not None:
+                    dqh = wi * rho[cell] * lt[cell] * BAR
+                    W["B"][iw][(wc,) + cell] -= dqh
+                    W["R"][iw] += q
+                    W["D"][iw] += dqh
             else:
                 for (c, ph, lam, dlam) in st["terms"]:
                     rho, drho = st["phases"][ph]
@@ -397,8 +442,24 @@ def assemble(grid, fluid, perm_md, poro, wells, x_old, x, dt_days):
                         else:
                             dq += wi * lam[cell] * (-drho[u][cell] * G * dzh)
                         J[0, c, u][cell] -= dq
+                        if iw is not None and c == 0:
+                            W["C"][iw][(u,) + cell] += dq
+                    if iw is not None:
+                        dqh = wi * lam[cell] * BAR
+                        W["B"][iw][(c,) + cell] -= dqh
+                        if c == 0:
+                            W["R"][iw] += q
+                            W["D"][iw] += dqh
     s = row_scales(grid, fluid, poro, dt_days)
     for c in range(b):
         R[c] /= s[c]
         J[:, c] /= s[c]
+        W["B"][:, c] /= s[c]
+    for iw, w in enumerate(rws):
+        sc = s[(0 if m == 1 else 1) if w["kind"] == "inj" else 0]
+        W["R"][iw] /= sc
+        W["C"][iw] /= sc
+        W["D"][iw] /= sc
+    if border:
+        return R, J, W
     return R, J

@@ -94,10 +94,38 @@ def forcing_term(choice, l, bn, bn_prev, rn_prev, diff_prev, theta0, theta_min, 
     return min(max(t, theta_min), theta_max)
 
 
+def border_operators(J, W, pc, composition, shape):
+    """The Jacobian of eq. (16) with the rate wells' BHP unknowns appended
+    to the cell unknowns (flat vectors [cells..., p_h...]) and its
+    preconditioner: CPR on the cell block, then each well's BHP from its
+    own equation given the cell correction (block lower-triangular):
+    z_w = (r_w - C_w z_cells) / D_w."""
+    nr = len(W["D"])
+    n = int(np.prod(shape))
+
+    def split(v):
+        return v[:n].reshape(shape), v[n:]
+
+    def A(v):
+        c, w = split(v)
+        y = cpr.block_spmv(J, c)
+        for q in range(nr):
+            y = y + W["B"][q] * w[q]
+        yw = np.array([np.sum(W["C"][q] * c) + W["D"][q] * w[q] for q in range(nr)])
+        return np.concatenate([y.ravel(), yw])
+
+    def M(v):
+        c, w = split(v)
+        z = cpr.cpr_apply(pc, c, composition=composition)
+        zw = np.array([(w[q] - np.sum(W["C"][q] * z)) / W["D"][q] for q in range(nr)])
+        return np.concatenate([z.ravel(), zw])
+    return A, M
+
+
 def time_step(grid, fluid, perm, poro, wells, x_old, dt_days, forcing="ew1", theta0=0.1,
               theta_min=1e-6, theta_max=0.5, gamma=0.9, beta=2.0, newton_tol=1e-3, max_newton=20,
               max_cuts=6, krylov_method="fgmres", restart=30, max_iter=300, rtol=1e-6, coarsest=512,
-              decoupling="qimpes", composition="two-stage"):
+              decoupling="qimpes", composition="two-stage", bhp_old=None):
     """One backward-Euler time step by the inexact Newton method
     (Algorithm 1) from x^0 = x_old, with time-step cuts.
 
@@ -107,18 +135,32 @@ def time_step(grid, fluid, perm, poro, wells, x_old, dt_days, forcing="ew1", the
     preconditioner block is singular.  A failed attempt halves dt and starts
     again from x_old, at most max_cuts times.  A linear solve that does not
     reach theta within max_iter iterations still updates x (inexact Newton);
-    one whose residual is not finite fails the attempt.  Returns (x, stats): x the
-    accepted state (x_old if every attempt failed), stats with dt_taken,
-    cuts, converged, the per-iteration history of the accepted (or last)
-    attempt (theta, linear iterations, ||b||) and totals over attempts."""
+    one whose residual is not finite fails the attempt.  Rate-controlled
+    wells add their bottom-hole pressures to the unknowns (starting from
+    bhp_old, default the wells' "bhp" entries; updated unchopped) and their
+    rate equations to the system.  Returns (x, stats): x the accepted state
+    (x_old if every attempt failed), stats with dt_taken, cuts, converged,
+    bhp (the rate wells' final BHPs), the per-iteration history of the
+    accepted (or last) attempt (theta, linear iterations, ||b||) and totals
+    over attempts."""
     assert forcing in FORCING
     solve = krylov.fgmres if krylov_method == "fgmres" else krylov.bicgstab
+    nr = len(model.rate_wells(wells))
+    if bhp_old is None:
+        bhp_old = np.array([w["bhp"] for w in model.rate_wells(wells)], dtype=np.float64)
+    shape = x_old.shape
+    n = x_old.size
     dt = float(dt_days)
     total_newton = total_linear = 0
+
+    def residual(x, xw):
+        R, J, W = model.assemble(grid, fluid, perm, poro, wells, x_old, x, dt, bhp=xw, border=True)
+        return -np.concatenate([R.ravel(), W["R"]]), J, W
+
     for cut in range(max_cuts + 1):
         x = x_old.copy()
-        R, J = model.assemble(grid, fluid, perm, poro, wells, x_old, x, dt)
-        b = -R
+        xw = np.array(bhp_old, dtype=np.float64)
+        b, J, W = residual(x, xw)
         bn = float(np.linalg.norm(b))
         b0 = bn
         hist = {"theta": [], "linear_iterations": [], "bnorm": [bn]}
@@ -137,21 +179,20 @@ def time_step(grid, fluid, perm, poro, wells, x_old, dt_days, forcing="ew1", the
                 pc = cpr.cpr_setup(J, coarsest, decoupling=decoupling)
             except (FloatingPointError, np.linalg.LinAlgError):
                 break
+            A, M = border_operators(J, W, pc, composition, shape)
             kw = {"restart": restart} if krylov_method == "fgmres" else {}
             with np.errstate(all="ignore"):
                 try:
-                    dx, st = solve(lambda v: cpr.block_spmv(J, v),
-                                   lambda v: cpr.cpr_apply(pc, v, composition=composition), b,
-                                   rtol=theta, max_iter=max_iter, **kw)
+                    dx, st = solve(A, M, b, rtol=theta, max_iter=max_iter, **kw)
                 except ValueError:          # a non-finite Hessenberg entry
                     break
-                r = b - cpr.block_spmv(J, dx)
+                r = b - A(dx)
             if not (np.isfinite(st["true_rel"]) and np.all(np.isfinite(r))):
                 break
-            x = newton_update(x, dx, _pb_min(fluid))
+            x = newton_update(x, dx[:n].reshape(shape), _pb_min(fluid))
+            xw = xw + dx[n:]
             with np.errstate(all="ignore"):
-                R, J = model.assemble(grid, fluid, perm, poro, wells, x_old, x, dt)
-            b_new = -R
+                b_new, J, W = residual(x, xw)
             bn_prev, rn_prev = bn, float(np.linalg.norm(r))
             diff_prev = float(np.linalg.norm(b_new - r))
             b, bn = b_new, float(np.linalg.norm(b_new))
@@ -162,7 +203,8 @@ def time_step(grid, fluid, perm, poro, wells, x_old, dt_days, forcing="ew1", the
         total_newton += l
         total_linear += sum(hist["linear_iterations"])
         stats = {"dt_taken": dt, "cuts": cut, "converged": ok, "newton_iterations": l,
-                 "total_newton": total_newton, "total_linear": total_linear, "history": hist}
+                 "total_newton": total_newton, "total_linear": total_linear, "history": hist,
+                 "bhp": xw if ok else np.array(bhp_old, dtype=np.float64)}
         if ok:
             return x, stats
         dt *= 0.5
@@ -179,16 +221,19 @@ def simulate(grid, fluid, perm, poro, wells, x0, t_end, dt0, dt_max, growth=2.0,
     x = x0.copy()
     t = 0.0
     dt = float(dt0)
+    bhp = step_kw.pop("bhp_old", None)
     st = {"steps": 0, "cuts": 0, "total_newton": 0, "total_linear": 0, "dts": [], "completed": False}
     while t < t_end:
         h = min(dt, t_end - t)
-        x_new, s = time_step(grid, fluid, perm, poro, wells, x, h, **step_kw)
+        x_new, s = time_step(grid, fluid, perm, poro, wells, x, h, bhp_old=bhp, **step_kw)
         st["cuts"] += s["cuts"]
         st["total_newton"] += s["total_newton"]
         st["total_linear"] += s["total_linear"]
         if not s["converged"]:
             return x, st
         x = x_new
+        bhp = s["bhp"]
+        st["bhp"] = bhp
         st["steps"] += 1
         st["dts"].append(s["dt_taken"])
         t = t + s["dt_taken"]

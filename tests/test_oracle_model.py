@@ -6,7 +6,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import model
+from oracle import model, newton
 from paper_1606_00548_amd import synth
 from tests.dense import dense_from_blocks
 
@@ -335,3 +335,86 @@ def test_undersaturated_oil_compressibility():
     a0 = [s["acc"][0] for s in st]
     a2 = [s["acc"][2] for s in st]
     assert np.allclose(a2[0] / a0[0], a2[1] / a0[1], rtol=1e-13)
+
+
+# ---- rate-controlled wells: BHP unknowns and the border of eq. (16)
+
+def _rate_case():
+    case = synth.oil_water_lognormal(4, 3, 2, seed=31)
+    inj, prod = case["wells"]
+    case["wells"] = [dict(inj, control="rate", rate=40.0, bhp=260.0),
+                     dict(prod, control="rate", rate=25.0, bhp=170.0)]
+    return case
+
+
+def test_rate_well_border_matches_central_differences():
+    case = _rate_case()
+    x = synth.random_state_perturbation(case, 12)
+    bhp = np.array([255.0, 175.0])
+    R, J, W = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                             case["x_old"], x, 1.0, bhp=bhp, border=True)
+    b = x.shape[0]
+    n = x[0].size
+
+    def F(xx, ww):
+        R, _, W = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                                 case["x_old"], xx, 1.0, bhp=ww, border=True)
+        return np.concatenate([np.moveaxis(R.reshape(b, -1), 0, 1).ravel(), W["R"]])
+    # full bordered Jacobian in point-block order + the two BHP unknowns
+    M = np.zeros((b * n + 2, b * n + 2))
+    M[:b * n, :b * n] = dense_from_blocks(J)
+    for q in range(2):
+        M[:b * n, b * n + q] = np.moveaxis(W["B"][q].reshape(b, -1), 0, 1).ravel()
+        M[b * n + q, :b * n] = np.moveaxis(W["C"][q].reshape(b, -1), 0, 1).ravel()
+        M[b * n + q, b * n + q] = W["D"][q]
+    fd = np.zeros_like(M)
+    for col in range(b * n + 2):
+        xp, xm, wp, wm = x.copy(), x.copy(), bhp.copy(), bhp.copy()
+        if col < b * n:
+            cell, u = divmod(col, b)
+            k, j, i = np.unravel_index(cell, x[0].shape)
+            eps = 1e-7 * max(1.0, abs(x[u, k, j, i]))
+            xp[u, k, j, i] += eps
+            xm[u, k, j, i] -= eps
+        else:
+            eps = 1e-7 * bhp[col - b * n]
+            wp[col - b * n] += eps
+            wm[col - b * n] -= eps
+        fd[:, col] = (F(xp, wp) - F(xm, wm)) / (2 * eps)
+    assert np.allclose(M, fd, rtol=1e-6, atol=1e-7 * np.abs(M).max())
+    # the rate wells couple only their own perforations
+    assert np.count_nonzero(W["D"]) == 2 and np.count_nonzero(W["B"][0][0]) == 0
+
+
+def _well_rate(case, x, w):
+    """Surface rate of well w (BHP w["bhp"]) at state x, from the rate
+    equation with a zero target."""
+    w0 = dict(w, control="rate", rate=0.0)
+    others = [v for v in case["wells"] if v is not w]
+    R, J, W = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], [w0] + others,
+                             case["x_old"], x, 1.0, bhp=np.array([w["bhp"]]), border=True)
+    m = case["fluid"]["model"]
+    c = 1 if w["kind"] == "inj" else 0
+    sc = model.row_scales(case["grid"], case["fluid"], case["poro"], 1.0)[c]
+    q = W["R"][0] * sc * model.DAY / model.surface_density(case["fluid"], c)
+    return q if w["kind"] == "inj" else -q
+
+
+def test_rate_control_at_the_bhp_wells_own_rate_recovers_its_bhp():
+    # Solve a step with BHP wells, read each well's rate, then impose those
+    # rates with wrong initial BHPs: the Newton iteration must return the
+    # original BHPs and state.
+    case = synth.oil_water_lognormal(6, 4, 2, seed=32)
+    tight = dict(forcing="fixed", rtol=1e-12, newton_tol=1e-11)
+    x1, s1 = newton.time_step(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                              case["x_old"], 1.0, **tight)
+    assert s1["converged"]
+    rates = [_well_rate(case, x1, w) for w in case["wells"]]
+    assert rates[0] > 0 and rates[1] > 0
+    rcase = dict(case, wells=[dict(w, control="rate", rate=q, bhp=w["bhp"] + (-30.0 if w["kind"] == "inj" else 20.0))
+                              for w, q in zip(case["wells"], rates)])
+    x2, s2 = newton.time_step(rcase["grid"], rcase["fluid"], rcase["perm"], rcase["poro"], rcase["wells"],
+                              rcase["x_old"], 1.0, **tight)
+    assert s2["converged"]
+    assert np.allclose(s2["bhp"], [w["bhp"] for w in case["wells"]], rtol=1e-7)
+    assert np.allclose(x2, x1, rtol=1e-7, atol=1e-9)

@@ -22,6 +22,12 @@
  *     undersaturated cell (no free gas; Rs and mu_o at p_b, B_o = B_o(p_b)
  *     exp(-c_o (p - p_b))).  Equation rows are the components (oil,
  *     water[, gas]).
+ *   - Rate-controlled wells (eqs. (8)-(9)) make their bottom-hole pressures
+ *     unknowns: a state, right-hand side, correction or Krylov vector then
+ *     holds the [b][n] cell part followed by one BHP (bar) / well-equation
+ *     entry per rate well, in the order the wells were given
+ *     (cpr_num_unknowns() = b*n + rate wells).  Without rate wells the
+ *     vectors are exactly [b][n].
  *   - Every array argument marked "device" is memory on the current HIP
  *     device; the caller owns it and keeps it alive for the call.  Calls are
  *     ordered on the HIP stream given to cpr_create and return once their
@@ -55,6 +61,7 @@ enum {
 
 enum { CPR_MODEL_OIL_WATER = 2, CPR_MODEL_BLACK_OIL = 3 };
 enum { CPR_WELL_INJECTOR = 0, CPR_WELL_PRODUCER = 1 };
+enum { CPR_CONTROL_BHP = 0, CPR_CONTROL_RATE = 1 };
 enum { CPR_PREC_FP64 = 0, CPR_PREC_MIXED = 1 };
 
 /* Decoupling of the CPR preconditioner (Sec. 2.5 names both):
@@ -100,15 +107,23 @@ typedef struct {
   const double* pvt;   /* host, [6][n_pvt]; NULL for oil-water */
 } cpr_fluid_t;
 
-/* A vertical well perforated in cells (i, j, k0..k1) under a bottom-hole
- * pressure constraint (eq. (7): the BHP is known and adds no unknown),
- * referenced to the depth of the grid top; rate from eq. (6) with a
- * Peaceman well index of radius rw (m) and skin. */
+/* A vertical well perforated in cells (i, j, k0..k1), its bottom-hole
+ * pressure referenced to the depth of the grid top; perforation rates from
+ * eq. (6) with a Peaceman well index of radius rw (m) and skin.
+ *   CPR_CONTROL_BHP: the BHP is fixed (eq. (7)) and adds no unknown.
+ *   CPR_CONTROL_RATE: the BHP is an unknown and the well adds the equation
+ *     sum of its perforations' rates = rate (eq. (8) water rate of an
+ *     injector, eq. (9) oil rate of a producer), in surface m^3/day (mass
+ *     rate / rho_w_ref for water, / rho_o_sc (black oil) or rho_o_ref
+ *     (oil-water) for oil); the row is scaled like the component's cell
+ *     rows; `bhp` is then unused (the state vector carries the BHP). */
 typedef struct {
   int i, j, k0, k1;
   int kind;            /* CPR_WELL_INJECTOR (water) or CPR_WELL_PRODUCER */
   double bhp;          /* bar */
   double rw, skin;
+  int control;         /* CPR_CONTROL_BHP or CPR_CONTROL_RATE                */
+  double rate;         /* target surface rate (m^3/day, >= 0) of a rate well */
 } cpr_well_t;
 
 typedef struct {
@@ -153,6 +168,9 @@ int cpr_create(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3,
 
 void cpr_destroy(cpr_ctx_t* ctx);
 const char* cpr_last_error(const cpr_ctx_t* ctx);
+
+/* Unknowns of a state vector: b * cells + rate-controlled wells. */
+long long cpr_num_unknowns(const cpr_ctx_t* ctx);
 
 /* Number of unknowns per cell (2 or 3) and cells of the context. */
 int cpr_block_size(const cpr_ctx_t* ctx);

@@ -43,7 +43,7 @@ class Fluid(ctypes.Structure):
 class Well(ctypes.Structure):
     _fields_ = [("i", ctypes.c_int), ("j", ctypes.c_int), ("k0", ctypes.c_int), ("k1", ctypes.c_int),
                 ("kind", ctypes.c_int), ("bhp", ctypes.c_double), ("rw", ctypes.c_double),
-                ("skin", ctypes.c_double)]
+                ("skin", ctypes.c_double), ("control", ctypes.c_int), ("rate", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
@@ -113,7 +113,7 @@ EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error",
            "cpr_nn_forward", "cpr_nn_backward", "cpr_nn_train_step", "cpr_nn_attach",
            "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov", "cpr_nn_eval_loss",
            "cpr_nn_make_target", "cpr_nn_infer", "cpr_bicgstab_solve", "cpr_default_newton_options",
-           "cpr_time_step", "cpr_simulate"]
+           "cpr_time_step", "cpr_simulate", "cpr_num_unknowns"]
 KCLASS = {"spmv": 0, "orth": 1, "smooth": 2, "ilu": 3, "assemble": 4}
 
 
@@ -135,6 +135,8 @@ def load():
     lib.cpr_block_size.argtypes = [P]
     lib.cpr_num_cells.argtypes = [P]
     lib.cpr_num_cells.restype = ctypes.c_longlong
+    lib.cpr_num_unknowns.argtypes = [P]
+    lib.cpr_num_unknowns.restype = ctypes.c_longlong
     lib.assemble_jacobian.argtypes = [P, P, P, ctypes.c_double, P]
     lib.cpr_import_jacobian.argtypes = [P, P]
     lib.cpr_export_jacobian.argtypes = [P, P]
@@ -316,8 +318,11 @@ class Solver:
             f.pvt = self._pvt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         ws = (Well * max(1, len(wells)))()
         for q, w in enumerate(wells):
+            rate = w.get("control", "bhp") == "rate"
             ws[q] = Well(w["i"], w["j"], w["k0"], w["k1"], 0 if w["kind"] == "inj" else 1,
-                         w["bhp"], w["rw"], w["skin"])
+                         w["bhp"], w["rw"], w["skin"], 1 if rate else 0, float(w.get("rate", 0.0)))
+        # rate-controlled wells append their BHPs to every vector
+        self.nrate = sum(1 for w in wells if w.get("control", "bhp") == "rate")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         perm_t = torch.as_tensor(np.asarray(perm, dtype=np.float64)).cuda().contiguous() \
             if not isinstance(perm, torch.Tensor) else perm
@@ -344,7 +349,14 @@ class Solver:
         return rc
 
     def vector(self):
+        """A zero state / right-hand-side vector: shaped [b, nz, ny, nx], or
+        flat [b n + rate wells] when rate-controlled wells add BHPs."""
+        if self.nrate:
+            return torch.zeros(self.b * int(np.prod(self.shape)) + self.nrate, dtype=torch.float64, device="cuda")
         return torch.zeros((self.b,) + self.shape, dtype=torch.float64, device="cuda")
+
+    def unknowns(self):
+        return int(self.lib.cpr_num_unknowns(self.ctx))
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -855,4 +855,5 @@ void precond_apply(cpr_ctx* ctx, const double* vin, double* v, const double* nrm
   } else {
     if (mixed) apply_impl<3, float>(ctx, vin, v, nrm2, z); else apply_impl<3, double>(ctx, vin, v, nrm2, z);
   }
+  border_precond(ctx, vin, v, nrm2, z);   // rate wells' BHP rows, after the cell correction
 }

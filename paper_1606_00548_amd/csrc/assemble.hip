@@ -359,11 +359,17 @@ __global__ void flux_kernel(FluidDev f, Lay L, double dz, double top, double vol
 }
 
 // One thread per perforated cell (cells are distinct; checked at creation).
+// A perforation of a rate-controlled well takes the BHP from the unknowns
+// (x[b n + well]) and also records its border entries: B = dR_cell/dp_h,
+// C = dR_w/dx_cell (scaled like the controlled component's rows), and the
+// controlled component's mass rate and its derivative in p_h (unscaled) for
+// the well equation.
 template <int MODEL>
 __global__ void well_kernel(FluidDev f, Lay L, int nperf, const Perf* __restrict__ perfs,
-                            double s0, double s1, double s2, const double* __restrict__ poro,
-                            const double* __restrict__ x, double* __restrict__ J,
-                            double* __restrict__ rhs) {
+                            const RateWell* __restrict__ rwells, double s0, double s1, double s2,
+                            const double* __restrict__ poro, const double* __restrict__ x,
+                            double* __restrict__ J, double* __restrict__ rhs, double* __restrict__ bord,
+                            double* __restrict__ pq) {
   constexpr int B = Traits<MODEL>::B, NT = Traits<MODEL>::NT;
   int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nperf) return;
@@ -375,10 +381,12 @@ __global__ void well_kernel(FluidDev f, Lay L, int nperf, const Perf* __restrict
   CellState<MODEL> s;
   cell_state<MODEL>(f, poro[t], xv, s);
   const double scale[3] = {s0, s1, s2};
-  double dh = pf.bhp - xv[0];
-  double q[B], dq[B][B];
+  const double ph = pf.rw >= 0 ? x[(size_t)B * n + pf.rw] : pf.bhp;
+  double dh = ph - xv[0];
+  double q[B], dq[B][B], dqh[B];
   for (int r = 0; r < B; ++r) {
     q[r] = 0.0;
+    dqh[r] = 0.0;
     for (int u = 0; u < B; ++u) dq[r][u] = 0.0;
   }
   if (pf.kind == CPR_WELL_INJECTOR) {
@@ -386,6 +394,7 @@ __global__ void well_kernel(FluidDev f, Lay L, int nperf, const Perf* __restrict
     double rho = s.rho[1], drho = s.drho[1];
     double drive = dh * BAR - rho * G_ACC * pf.dzh;
     q[1] = pf.wi * rho * s.lt * drive;
+    dqh[1] = pf.wi * rho * s.lt * BAR;
     for (int u = 0; u < B; ++u) {
       double v = pf.wi * rho * s.dlt[u] * drive;
       if (u == 0) {
@@ -396,14 +405,15 @@ __global__ void well_kernel(FluidDev f, Lay L, int nperf, const Perf* __restrict
     }
   } else {
     for (int tt = 0; tt < NT; ++tt) {
-      int c = Traits<MODEL>::row(tt), ph = Traits<MODEL>::phase(tt);
-      double rho = s.rho[ph], drho = s.drho[ph];
+      int c = Traits<MODEL>::row(tt), ph_ = Traits<MODEL>::phase(tt);
+      double rho = s.rho[ph_], drho = s.drho[ph_];
       double drive = dh * BAR - rho * G_ACC * pf.dzh;
       q[c] += pf.wi * s.lam[tt] * drive;
+      dqh[c] += pf.wi * s.lam[tt] * BAR;
       for (int u = 0; u < B; ++u) {
         double v = pf.wi * s.dlam[tt][u] * drive;
         if (u == 0) v += pf.wi * s.lam[tt] * (-BAR - drho * G_ACC * pf.dzh);
-        if (MODEL == 3 && u == 2 && ph == 0) v += pf.wi * s.lam[tt] * (-s.drho_o2 * G_ACC * pf.dzh);
+        if (MODEL == 3 && u == 2 && ph_ == 0) v += pf.wi * s.lam[tt] * (-s.drho_o2 * G_ACC * pf.dzh);
         dq[c][u] += v;
       }
     }
@@ -412,6 +422,36 @@ __global__ void well_kernel(FluidDev f, Lay L, int nperf, const Perf* __restrict
     rhs[r * n + t] += q[r] / scale[r];
     for (int u = 0; u < B; ++u) J[((size_t)r * B + u) * n + t] -= dq[r][u] / scale[r];
   }
+  if (pf.rw >= 0) {
+    const int c = rwells[pf.rw].comp;
+    double* bq = bord + (size_t)w * 6;
+    for (int r = 0; r < 3; ++r) {
+      bq[r] = r < B ? -dqh[r] / scale[r] : 0.0;
+      bq[3 + r] = r < B ? dq[c][r] / scale[c] : 0.0;
+    }
+    pq[2 * w] = q[c];
+    pq[2 * w + 1] = dqh[c];
+  }
+}
+
+// Well equation of each rate-controlled well, summed over its perforations
+// in order: R_w = (sum q_c - target) / s_c, D = sum dq_c/dp_h / s_c; the
+// right-hand side tail receives -R_w.
+__global__ void rate_well_kernel(int b, int n, int nrate, const RateWell* __restrict__ rwells,
+                                 const double* __restrict__ pq, double s0, double s1, double s2,
+                                 double* __restrict__ bordD, double* __restrict__ rhs) {
+  int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nrate) return;
+  const double scale[3] = {s0, s1, s2};
+  const RateWell R = rwells[w];
+  const double sc = scale[R.comp];
+  double acc = -R.target, d = 0.0;
+  for (int q = R.p0; q < R.p1; ++q) {
+    acc += pq[2 * q];
+    d += pq[2 * q + 1];
+  }
+  rhs[(size_t)b * n + w] = -(acc / sc);
+  bordD[w] = d / sc;
 }
 
 __global__ void trans_kernel(Lay L, double dx, double dy, double dz, const double* __restrict__ perm,
@@ -461,8 +501,9 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
                                       sc[0], sc[1], sc[2], ctx->poro, ctx->tp, xold_cs, x_cs,
                                       ctx->props, ctx->J, rhs_cs);
     prof_end(ctx, CPR_KCLASS_ASSEMBLE);
-    if (np) well_kernel<2><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, sc[0], sc[1],
-                                                        sc[2], ctx->poro, x_cs, ctx->J, rhs_cs);
+    if (np) well_kernel<2><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, ctx->rwells_d, sc[0],
+                                                        sc[1], sc[2], ctx->poro, x_cs, ctx->J, rhs_cs,
+                                                        ctx->bord, ctx->pq);
   } else {
     props_kernel<3><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, x_cs, ctx->props);
     prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
@@ -470,9 +511,13 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
                                       sc[0], sc[1], sc[2], ctx->poro, ctx->tp, xold_cs, x_cs,
                                       ctx->props, ctx->J, rhs_cs);
     prof_end(ctx, CPR_KCLASS_ASSEMBLE);
-    if (np) well_kernel<3><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, sc[0], sc[1],
-                                                        sc[2], ctx->poro, x_cs, ctx->J, rhs_cs);
+    if (np) well_kernel<3><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, ctx->rwells_d, sc[0],
+                                                        sc[1], sc[2], ctx->poro, x_cs, ctx->J, rhs_cs,
+                                                        ctx->bord, ctx->pq);
   }
+  if (ctx->nrate)
+    rate_well_kernel<<<div_up(ctx->nrate, 64), 64, 0, s>>>(ctx->b, L.n, ctx->nrate, ctx->rwells_d, ctx->pq, sc[0],
+                                                          sc[1], sc[2], ctx->bord_d, rhs_cs);
 }
 
 // Number of SoA planes the per-cell state needs (allocation size).

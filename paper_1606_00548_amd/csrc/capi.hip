@@ -43,7 +43,8 @@ void free_all(cpr_ctx* ctx) {
                   ctx->w, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf, ctx->flag, ctx->V, ctx->Z,
                   ctx->Y, ctx->rp, ctx->xs, ctx->rs, ctx->tmp, ctx->vf, ctx->zf, ctx->Yf, ctx->rpf,
                   ctx->part, ctx->hdev, ctx->lnk, ctx->rprime, ctx->qbuf, ctx->feat, ctx->nnscal,
-                  ctx->nncount, ctx->Wabf, ctx->Jt, ctx->Rt, ctx->Rtf, ctx->Z1, ctx->Z1f};
+                  ctx->nncount, ctx->Wabf, ctx->Jt, ctx->Rt, ctx->Rtf, ctx->Z1, ctx->Z1f, ctx->rwells_d,
+                  ctx->bord, ctx->pq, ctx->bord_d};
   for (void* b : bufs)
     if (b) hipFree(b);
   if (ctx->hhost) hipHostFree(ctx->hhost);
@@ -110,21 +111,32 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
   const int b = ctx->b;
   const size_t N = (size_t)n;
   int rc;
+  // rate-controlled wells append their BHPs to every vector
+  for (int q = 0; q < nwells; ++q) {
+    if (wells[q].control != CPR_CONTROL_BHP && wells[q].control != CPR_CONTROL_RATE)
+      return set_err(ctx, CPR_EINVAL, "unknown well control");
+    if (wells[q].control == CPR_CONTROL_RATE) {
+      if (!(wells[q].rate >= 0) || !std::isfinite(wells[q].rate))
+        return set_err(ctx, CPR_EINVAL, "well rate must be >= 0");
+      ctx->nrate += 1;
+    }
+  }
+  const size_t NV = b * N + ctx->nrate;
 #define ALLOC(p, cnt) if ((rc = dalloc(ctx, &(p), (cnt))) != CPR_OK) return rc
   ALLOC(ctx->poro, N);
   ALLOC(ctx->tp, 3 * N);
   ALLOC(ctx->J, 7 * (size_t)b * b * N);
   ALLOC(ctx->props, (size_t)props_planes(f->model) * N);
-  ALLOC(ctx->vin, b * N);
-  ALLOC(ctx->vin2, b * N);
-  ALLOC(ctx->vout, b * N);
+  ALLOC(ctx->vin, NV);
+  ALLOC(ctx->vin2, NV);
+  ALLOC(ctx->vout, NV);
   ALLOC(ctx->w, b * N);
   ALLOC(ctx->R0, 7 * (size_t)b * N);
   ALLOC(ctx->Dinv, (size_t)b * b * N);
   ALLOC(ctx->Y, b * N);
-  ALLOC(ctx->xs, b * N);
-  ALLOC(ctx->rs, b * N);
-  ALLOC(ctx->tmp, b * N);
+  ALLOC(ctx->xs, NV);
+  ALLOC(ctx->rs, NV);
+  ALLOC(ctx->tmp, NV);
   ALLOC(ctx->flag, 4);
   ALLOC(ctx->lnk, N);
   ALLOC(ctx->rprime, N);
@@ -171,10 +183,21 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
     ctx->rho_scale[1] = f->rho_w_ref;
     ctx->rho_scale[2] = f->rho_g_sc / host_pvt(fl, 4, f->p_ref);
   }
-  // perforations
-  std::vector<char> used;
+  // perforations (each well's contiguous, in the order given)
   for (int q = 0; q < nwells; ++q) {
     const cpr_well_t& w = wells[q];
+    const bool rate = w.control == CPR_CONTROL_RATE;
+    if (rate) {
+      RateWell r;
+      r.p0 = (int)ctx->perfs.size();
+      r.p1 = r.p0 + (w.k1 - w.k0 + 1);
+      r.comp = w.kind == CPR_WELL_INJECTOR ? 1 : 0;
+      const double rho_s = w.kind == CPR_WELL_INJECTOR ? f->rho_w_ref
+                           : (f->model == CPR_MODEL_BLACK_OIL ? f->rho_o_sc : f->rho_o_ref);
+      const double mass = w.rate * rho_s / 86400.0;
+      r.target = w.kind == CPR_WELL_INJECTOR ? mass : -mass;
+      ctx->rwells.push_back(r);
+    }
     if (w.i < 0 || w.i >= g->nx || w.j < 0 || w.j >= g->ny || w.k0 < 0 || w.k1 >= g->nz || w.k0 > w.k1)
       return set_err(ctx, CPR_EINVAL, "well perforation outside the grid");
     if (w.kind != CPR_WELL_INJECTOR && w.kind != CPR_WELL_PRODUCER)
@@ -188,6 +211,7 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
       Perf p;
       p.cell = lay_index(ctx->lay, w.i, w.j, k);
       p.kind = w.kind;
+      p.rw = rate ? (int)ctx->rwells.size() - 1 : -1;
       p.wi = peaceman(kxy[0], kxy[1], g->dx, g->dy, g->dz, w.rw, w.skin);
       p.bhp = w.bhp;
       double depth = g->top + (k + 0.5) * g->dz;
@@ -202,6 +226,15 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
     CPR_TRY(hipMemcpyAsync(ctx->perfs_d, ctx->perfs.data(), ctx->perfs.size() * sizeof(Perf),
                            hipMemcpyHostToDevice, s));
   }
+  if (ctx->nrate) {
+    if ((rc = dalloc(ctx, &ctx->rwells_d, ctx->rwells.size())) != CPR_OK) return rc;
+    if ((rc = dalloc(ctx, &ctx->bord, 6 * ctx->perfs.size())) != CPR_OK) return rc;
+    if ((rc = dalloc(ctx, &ctx->pq, 2 * ctx->perfs.size())) != CPR_OK) return rc;
+    if ((rc = dalloc(ctx, &ctx->bord_d, (size_t)ctx->nrate)) != CPR_OK) return rc;
+    CPR_TRY(hipMemcpyAsync(ctx->rwells_d, ctx->rwells.data(), ctx->rwells.size() * sizeof(RateWell),
+                           hipMemcpyHostToDevice, s));
+    CPR_TRY(hipMemsetAsync(ctx->bord, 0, 6 * ctx->perfs.size() * sizeof(double), s));
+  }
   CPR_TRY(hipStreamSynchronize(s));
   cpr_default_options(&ctx->opt);
   return CPR_OK;
@@ -213,7 +246,7 @@ int ensure_krylov(cpr_ctx* ctx, int m) {
   if (ctx->Z) hipFree(ctx->Z);
   ctx->V = ctx->Z = nullptr;
   ctx->mcap = 0;
-  size_t len = (size_t)ctx->b * ctx->lay.n;
+  size_t len = (size_t)vec_len(ctx);
   int rc;
   if ((rc = dalloc(ctx, &ctx->V, (size_t)(m + 1) * len)) != CPR_OK) return rc;
   if ((rc = dalloc(ctx, &ctx->Z, (size_t)m * len)) != CPR_OK) return rc;
@@ -343,17 +376,18 @@ int cpr_block_size(const cpr_ctx_t* ctx) { return ctx ? ctx->b : 0; }
 
 long long cpr_num_cells(const cpr_ctx_t* ctx) { return ctx ? (long long)ctx->lay.n : 0; }
 
+long long cpr_num_unknowns(const cpr_ctx_t* ctx) { return ctx ? (long long)vec_len(ctx) : 0; }
+
 int assemble_jacobian(cpr_ctx_t* ctx, const double* x_old, const double* x, double dt_days,
                       double* rhs_out) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   GUARD_BEGIN
   if (!x_old || !x || !rhs_out) return set_err(ctx, CPR_EINVAL, "null argument");
   if (!(dt_days > 0) || !std::isfinite(dt_days)) return set_err(ctx, CPR_EINVAL, "dt must be > 0");
-  hipStream_t s = ctx->stream;
-  launch_nat_to_cs(ctx->lay, ctx->b, x_old, ctx->vin2, s);
-  launch_nat_to_cs(ctx->lay, ctx->b, x, ctx->vin, s);
+  CPR_TRY(vec_nat_to_cs(ctx, x_old, ctx->vin2));
+  CPR_TRY(vec_nat_to_cs(ctx, x, ctx->vin));
   launch_assemble(ctx, ctx->vin2, ctx->vin, dt_days, ctx->vout);
-  launch_cs_to_nat(ctx->lay, ctx->b, ctx->vout, rhs_out, s);
+  CPR_TRY(vec_cs_to_nat(ctx, ctx->vout, rhs_out));
   ctx->assembled = 1;
   ctx->setup_done = 0;
   return launch_check(ctx, "assemble_jacobian");
@@ -390,11 +424,11 @@ int cpr_gmres_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* 
   if (!rhs || !dx) return set_err(ctx, CPR_EINVAL, "null argument");
   if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
   hipStream_t s = ctx->stream;
-  launch_nat_to_cs(ctx->lay, ctx->b, rhs, ctx->rs, s);
+  CPR_TRY(vec_nat_to_cs(ctx, rhs, ctx->rs));
   if (ctx->opt.learned) CPR_TRY(hipMemsetAsync(ctx->nncount, 0, 2 * sizeof(int), s));
   int rc = fgmres_solve(ctx, st);
   if (rc < 0) return rc;
-  launch_cs_to_nat(ctx->lay, ctx->b, ctx->xs, dx, s);
+  CPR_TRY(vec_cs_to_nat(ctx, ctx->xs, dx));
   int rc2 = launch_check(ctx, "cpr_gmres_solve");
   if (rc2 != CPR_OK) return rc2;
   if (ctx->opt.learned && st) {
@@ -440,11 +474,10 @@ int cpr_time_step(cpr_ctx_t* ctx, const double* x_old, double* x, double dt_days
   if (!(no.newton_tol > 0) || !(no.theta_min > 0) || !(no.theta_max >= no.theta_min) || !(no.theta0 > 0) ||
       !std::isfinite(no.theta_max) || !std::isfinite(no.gamma) || !std::isfinite(no.beta))
     return set_err(ctx, CPR_EINVAL, "bad Newton tolerances");
-  hipStream_t s = ctx->stream;
-  launch_nat_to_cs(ctx->lay, ctx->b, x_old, ctx->vin2, s);
+  CPR_TRY(vec_nat_to_cs(ctx, x_old, ctx->vin2));
   int rc = time_step(ctx, ctx->vin2, ctx->vin, dt_days, lo, no, st);
   if (rc < 0) return rc;
-  launch_cs_to_nat(ctx->lay, ctx->b, ctx->vin, x, s);
+  CPR_TRY(vec_cs_to_nat(ctx, ctx->vin, x));
   int rc2 = launch_check(ctx, "cpr_time_step");
   return rc2 != CPR_OK ? rc2 : rc;
   GUARD_END
@@ -464,9 +497,9 @@ int cpr_simulate(cpr_ctx_t* ctx, const double* x0, double* x, double t_end_days,
   cpr_newton_options_t no;
   if (nopt) no = *nopt; else cpr_default_newton_options(&no);
   hipStream_t s = ctx->stream;
-  const long len = (long)ctx->b * ctx->lay.n;
+  const long len = vec_len(ctx);
   double* xa = ctx->vin2;   // state at the start of the step (colour-split)
-  launch_nat_to_cs(ctx->lay, ctx->b, x0, xa, s);
+  CPR_TRY(vec_nat_to_cs(ctx, x0, xa));
   cpr_sim_stats_t S = {};
   double t = 0.0, dt = dt0_days;
   int rc = CPR_OK;
@@ -487,7 +520,7 @@ int cpr_simulate(cpr_ctx_t* ctx, const double* x0, double* x, double t_end_days,
   }
   S.t_reached = t;
   S.completed = (rc == CPR_OK && t >= t_end_days) ? 1 : 0;
-  if (rc >= 0) launch_cs_to_nat(ctx->lay, ctx->b, xa, x, s);
+  if (rc >= 0) CPR_TRY(vec_cs_to_nat(ctx, xa, x));
   if (st) *st = S;
   if (rc < 0) return rc;
   int rc2 = launch_check(ctx, "cpr_simulate");
@@ -503,11 +536,11 @@ int cpr_bicgstab_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_
   int rc;
   if ((rc = ensure_krylov(ctx, ctx->opt.restart > 8 ? ctx->opt.restart : 8)) != CPR_OK) return rc;
   hipStream_t s = ctx->stream;
-  launch_nat_to_cs(ctx->lay, ctx->b, rhs, ctx->rs, s);
+  CPR_TRY(vec_nat_to_cs(ctx, rhs, ctx->rs));
   if (ctx->opt.learned) CPR_TRY(hipMemsetAsync(ctx->nncount, 0, 2 * sizeof(int), s));
   rc = bicgstab_solve(ctx, st);
   if (rc < 0) return rc;
-  launch_cs_to_nat(ctx->lay, ctx->b, ctx->xs, dx, s);
+  CPR_TRY(vec_cs_to_nat(ctx, ctx->xs, dx));
   int rc2 = launch_check(ctx, "cpr_bicgstab_solve");
   if (rc2 != CPR_OK) return rc2;
   if (ctx->opt.learned && st) {
@@ -586,24 +619,23 @@ int cpr_nn_features(cpr_ctx_t* ctx, const double* rprime, float* feat, double* s
 int cpr_export_krylov(cpr_ctx_t* ctx, int j, double* v) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   if (!v || j < 0 || j > ctx->mcap || !ctx->V) return set_err(ctx, CPR_EINVAL, "bad basis index");
-  launch_cs_to_nat(ctx->lay, ctx->b, ctx->V + (size_t)j * ctx->b * ctx->lay.n, v, ctx->stream);
+  CPR_TRY(vec_cs_to_nat(ctx, ctx->V + (size_t)j * vec_len(ctx), v));
   return launch_check(ctx, "cpr_export_krylov");
 }
 
 int cpr_newton_update(cpr_ctx_t* ctx, double* x, const double* dx) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   if (!x || !dx) return set_err(ctx, CPR_EINVAL, "null argument");
-  launch_newton_update(ctx->b, ctx->lay.n, pb_floor(ctx->fl), x, dx, ctx->stream);
+  launch_newton_update(ctx->b, ctx->lay.n, ctx->nrate, pb_floor(ctx->fl), x, dx, ctx->stream);
   return launch_check(ctx, "cpr_newton_update");
 }
 
 int cpr_spmv(cpr_ctx_t* ctx, const double* x, double* y) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   if (!x || !y) return set_err(ctx, CPR_EINVAL, "null argument");
-  hipStream_t s = ctx->stream;
-  launch_nat_to_cs(ctx->lay, ctx->b, x, ctx->vin, s);
-  launch_spmv(ctx->b, ctx->lay, ctx->J, ctx->vin, ctx->vout, nullptr, s);
-  launch_cs_to_nat(ctx->lay, ctx->b, ctx->vout, y, s);
+  CPR_TRY(vec_nat_to_cs(ctx, x, ctx->vin));
+  system_spmv(ctx, ctx->vin, ctx->vout, nullptr);
+  CPR_TRY(vec_cs_to_nat(ctx, ctx->vout, y));
   return launch_check(ctx, "cpr_spmv");
 }
 
@@ -611,10 +643,9 @@ int cpr_precond_apply(cpr_ctx_t* ctx, const double* v, double* z) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   if (!v || !z) return set_err(ctx, CPR_EINVAL, "null argument");
   if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
-  hipStream_t s = ctx->stream;
-  launch_nat_to_cs(ctx->lay, ctx->b, v, ctx->vin, s);
+  CPR_TRY(vec_nat_to_cs(ctx, v, ctx->vin));
   precond_apply(ctx, ctx->vin, ctx->vin, nullptr, ctx->vout);
-  launch_cs_to_nat(ctx->lay, ctx->b, ctx->vout, z, s);
+  CPR_TRY(vec_cs_to_nat(ctx, ctx->vout, z));
   return launch_check(ctx, "cpr_precond_apply");
 }
 

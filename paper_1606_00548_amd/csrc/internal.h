@@ -141,12 +141,19 @@ struct FluidDev {
   double pvt[6][CPR_MAX_PVT];
 };
 
-struct Perf {     // one perforated cell of a BHP well
+struct Perf {     // one perforated cell of a well
   int cell;       // colour-split index
   int kind;       // CPR_WELL_INJECTOR / CPR_WELL_PRODUCER
+  int rw;         // index of its rate-controlled well, -1 for a BHP well
   double wi;      // Peaceman index (m^3)
-  double bhp;     // bar
+  double bhp;     // bar (BHP wells)
   double dzh;     // z_h - z (m): reference depth minus cell depth
+};
+
+struct RateWell {     // a rate-controlled well: its perforations are perfs[p0, p1)
+  int p0, p1;
+  int comp;           // controlled component row (water for injectors, oil for producers)
+  double target;      // signed target mass rate (kg/s): +injection, -production
 };
 
 struct MGLevel {
@@ -182,6 +189,13 @@ struct cpr_ctx {
   double* tp = nullptr;        // [3][n] transmissibility to the +x/+y/+z neighbour
   std::vector<Perf> perfs;
   Perf* perfs_d = nullptr;
+  // rate-controlled wells: BHP unknowns appended to every vector
+  int nrate = 0;
+  std::vector<RateWell> rwells;
+  RateWell* rwells_d = nullptr;
+  double* bord = nullptr;      // [nperf][2][3]: dR_cell/dp_h (B) and dR_w/dx_cell (C) per perforation
+  double* pq = nullptr;        // [nperf][2]: controlled-component mass rate and d/dp_h (unscaled)
+  double* bord_d = nullptr;    // [nrate] dR_w/dp_h (D)
 
   // Jacobian and assembly scratch (colour-split)
   double* J = nullptr;         // [7][b][b][n]
@@ -271,6 +285,10 @@ int launch_check(cpr_ctx* ctx, const char* what);
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 
+// Length of a state / Krylov vector: the cell unknowns and the BHPs of the
+// rate-controlled wells.
+inline long vec_len(const cpr_ctx* c) { return (long)c->b * c->lay.n + c->nrate; }
+
 // ---------------------------------------------------------------- launchers
 // layout.hip
 void launch_nat_to_cs(const Lay& L, int planes, const double* src, double* dst, hipStream_t s);
@@ -287,6 +305,15 @@ int props_planes(int model);
 // spmv.hip
 void launch_spmv(int b, const Lay& L, const double* A, const double* x, double* y,
                  const double* rhs, hipStream_t s);
+// y = A x (or rhs - A x) for the whole system: the block stencil and, with
+// rate-controlled wells, their border (eq. (16)).
+void system_spmv(cpr_ctx* ctx, const double* x, double* y, const double* rhs);
+// Well part of a preconditioner application: z_w = (v_w - C z_cells) / D,
+// normalising v_w = vin_w / sqrt(*nrm2) first when nrm2 is given.
+void border_precond(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, double* z);
+// Natural <-> colour-split order of a whole vector (cells, then the BHP tail).
+hipError_t vec_nat_to_cs(cpr_ctx* ctx, const double* src, double* dst);
+hipError_t vec_cs_to_nat(cpr_ctx* ctx, const double* src, double* dst);
 
 // setup.hip
 int setup_cpr(cpr_ctx* ctx);
@@ -318,7 +345,7 @@ int time_step(cpr_ctx* ctx, const double* xold_cs, double* x_cs, double dt_days,
 // krylov.hip
 int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st);
 int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st);
-void launch_newton_update(int b, int n, double pb_min, double* x, const double* dx, hipStream_t s);
+void launch_newton_update(int b, int n, int nrate, double pb_min, double* x, const double* dx, hipStream_t s);
 // Bubble-point floor of the black-oil update: the first PVT pressure node.
 inline double pb_floor(const FluidDev& f) { return f.model == 3 ? f.pvt[0][0] : 0.0; }
 int reduce_dot(cpr_ctx* ctx, const double* a, const double* b, long len, double* out);

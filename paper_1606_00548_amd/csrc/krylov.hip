@@ -214,9 +214,10 @@ __global__ void zero_kernel(long len, double* __restrict__ x) {
 // (updated p); an undersaturated cell (x2 = -p_b) whose bubble point rises
 // above the updated pressure becomes saturated with S_g = 0; otherwise p_b
 // (unchopped) is floored at pb_min.
-__global__ void newton_update_kernel(int b, int n, double pb_min, double* __restrict__ x,
+__global__ void newton_update_kernel(int b, int n, int nrate, double pb_min, double* __restrict__ x,
                                      const double* __restrict__ dx) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nrate) x[(size_t)b * n + t] += dx[(size_t)b * n + t];   // rate wells' BHPs, unchopped
   if (t >= n) return;
   const double p = x[t] + dx[t];
   x[t] = p;
@@ -382,8 +383,8 @@ __global__ __launch_bounds__(KB) void bicg_xr_kernel(long len, const double* __r
 
 }  // namespace
 
-void launch_newton_update(int b, int n, double pb_min, double* x, const double* dx, hipStream_t s) {
-  newton_update_kernel<<<div_up(n, 256), 256, 0, s>>>(b, n, pb_min, x, dx);
+void launch_newton_update(int b, int n, int nrate, double pb_min, double* x, const double* dx, hipStream_t s) {
+  newton_update_kernel<<<div_up(n > nrate ? n : nrate, 256), 256, 0, s>>>(b, n, nrate, pb_min, x, dx);
 }
 
 // Dot product of two device vectors of length len into *out (host).  Syncs.
@@ -405,7 +406,7 @@ int reduce_dot(cpr_ctx* ctx, const double* a, const double* b, long len, double*
 int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
   hipStream_t s = ctx->stream;
   const int b = ctx->b;
-  const long len = (long)b * ctx->lay.n;
+  const long len = vec_len(ctx);
   const size_t stride = (size_t)len;
   const int m = ctx->opt.restart;
   const double rtol = ctx->opt.rtol;
@@ -467,7 +468,7 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
       // v_j = w_j / h_{j,j-1} is formed inside the preconditioner's first kernel
       precond_apply(ctx, vj, vj, j == 0 ? nullptr : hd + 128, zj);
       prof_begin(ctx, CPR_KCLASS_SPMV);
-      launch_spmv(b, ctx->lay, ctx->J, zj, w, nullptr, s);
+      system_spmv(ctx, zj, w, nullptr);
       prof_end(ctx, CPR_KCLASS_SPMV);
       // CGS pass 1: h1 = V^T w
       orth_pass(ctx, len, nv, w, nullptr, 0);
@@ -546,7 +547,7 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     S.cycles += 1;
     S.est_rel = std::fabs(g[k]) / bnorm;
     prof_begin(ctx, CPR_KCLASS_SPMV);
-    launch_spmv(b, ctx->lay, ctx->J, x, r, ctx->rs, s);
+    system_spmv(ctx, x, r, ctx->rs);
     prof_end(ctx, CPR_KCLASS_SPMV);
   }
   S.iterations = its;
@@ -562,7 +563,7 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
 int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st) {
   hipStream_t s = ctx->stream;
   const int b = ctx->b;
-  const long len = (long)b * ctx->lay.n;
+  const long len = vec_len(ctx);
   const int nblk = ctx->nblk;
   const int eb = div_up(len, 256);
   const double rtol = ctx->opt.rtol;
@@ -614,14 +615,14 @@ int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st) {
       bicg_p_kernel<<<eb, 256, 0, s>>>(len, sc, r, v, p);
       precond_apply(ctx, p, p, nullptr, ph);
       prof_begin(ctx, CPR_KCLASS_SPMV);
-      launch_spmv(b, ctx->lay, ctx->J, ph, v, nullptr, s);
+      system_spmv(ctx, ph, v, nullptr);
       prof_end(ctx, CPR_KCLASS_SPMV);
       dot2_kernel<<<nblk, KB, 0, s>>>(len, rh, v, nullptr, nullptr, ctx->part, nblk);
       bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 1, 0, sc, host);
       bicg_s_kernel<<<eb, 256, 0, s>>>(len, sc, r, v, sv);
       precond_apply(ctx, sv, sv, nullptr, sh);
       prof_begin(ctx, CPR_KCLASS_SPMV);
-      launch_spmv(b, ctx->lay, ctx->J, sh, t, nullptr, s);
+      system_spmv(ctx, sh, t, nullptr);
       prof_end(ctx, CPR_KCLASS_SPMV);
       dot2_kernel<<<nblk, KB, 0, s>>>(len, t, sv, t, t, ctx->part, nblk);
       bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 2, 1, sc, host);
@@ -643,7 +644,7 @@ int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     }
     // true residual r = b - A x
     prof_begin(ctx, CPR_KCLASS_SPMV);
-    launch_spmv(b, ctx->lay, ctx->J, x, r, ctx->rs, s);
+    system_spmv(ctx, x, r, ctx->rs);
     prof_end(ctx, CPR_KCLASS_SPMV);
     double rr;
     rc = reduce_dot(ctx, r, r, len, &rr);

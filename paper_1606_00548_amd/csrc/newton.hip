@@ -44,7 +44,7 @@ int time_step(cpr_ctx* ctx, const double* xold_cs, double* x_cs, double dt_days,
               const cpr_newton_options_t& no, cpr_newton_stats_t* st) {
   hipStream_t s = ctx->stream;
   const int b = ctx->b;
-  const long len = (long)b * ctx->lay.n;
+  const long len = vec_len(ctx);
   const bool bicg = no.krylov == CPR_KRYLOV_BICGSTAB;
   cpr_newton_stats_t S = {};
   double dt = dt_days;
@@ -79,7 +79,7 @@ int time_step(cpr_ctx* ctx, const double* xold_cs, double* x_cs, double dt_days,
       const double* r = bicg ? ctx->V : ctx->tmp;   // b - A dx
       double rr;
       if ((rc = reduce_dot(ctx, r, r, len, &rr)) != CPR_OK) return rc;
-      launch_newton_update(b, ctx->lay.n, pb_floor(ctx->fl), x_cs, ctx->xs, s);
+      launch_newton_update(b, ctx->lay.n, ctx->nrate, pb_floor(ctx->fl), x_cs, ctx->xs, s);
       launch_assemble(ctx, xold_cs, x_cs, dt, ctx->rs);
       ctx->setup_done = 0;
       diff_kernel<<<div_up(len, 256), 256, 0, s>>>(len, ctx->rs, r, ctx->vout);

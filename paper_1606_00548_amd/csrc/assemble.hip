@@ -207,12 +207,19 @@ struct PropPlanes {
   static constexpr int RHO = 0, DRHO = NP, LAM = 2 * NP, DLAM = 2 * NP + NT;
   static constexpr int LT = 2 * NP + NT + NT * B;   // total volumetric mobility (network feature)
   static constexpr int DRHO_O2 = LT + 1;            // black oil: d rho_oil-phase / d x2
-  static constexpr int COUNT = MODEL == 3 ? DRHO_O2 + 1 : LT + 1;
+  static constexpr int ACC = MODEL == 3 ? DRHO_O2 + 1 : LT + 1;   // acc(x) - acc(x_old) [B]
+  static constexpr int DACC = ACC + B;                            // d acc / d x [B][B]
+  static constexpr int COUNT = DACC + B * B;
 };
 
+// Per-cell state for the flux kernel: phase densities and mobilities with
+// their derivatives, and the accumulation change acc(x) - acc(x_old) with
+// its derivative (so the flux kernel, which needs every neighbour's state,
+// does not evaluate the fluid model itself).
 template <int MODEL>
-__global__ void props_kernel(FluidDev f, Lay L, const double* __restrict__ poro,
-                             const double* __restrict__ x, double* __restrict__ props) {
+__global__ __launch_bounds__(256) void props_kernel(FluidDev f, Lay L, const double* __restrict__ poro,
+                                                    const double* __restrict__ xold, const double* __restrict__ x,
+                                                    double* __restrict__ props) {
   using PP = PropPlanes<MODEL>;
   constexpr int B = Traits<MODEL>::B;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,6 +229,16 @@ __global__ void props_kernel(FluidDev f, Lay L, const double* __restrict__ poro,
   CellState<MODEL> s;
   cell_state<MODEL>(f, poro[t], xv, s);
   size_t n = L.n;
+  {
+    double xo[B];
+    for (int u = 0; u < B; ++u) xo[u] = xold[(size_t)u * L.n + t];
+    CellState<MODEL> so;
+    cell_state<MODEL>(f, poro[t], xo, so);
+    for (int r = 0; r < B; ++r) {
+      props[(PP::ACC + r) * n + t] = s.acc[r] - so.acc[r];
+      for (int u = 0; u < B; ++u) props[(PP::DACC + r * B + u) * n + t] = s.dacc[r][u];
+    }
+  }
   for (int q = 0; q < PP::NP; ++q) {
     props[(PP::RHO + q) * n + t] = s.rho[q];
     props[(PP::DRHO + q) * n + t] = s.drho[q];
@@ -235,7 +252,7 @@ __global__ void props_kernel(FluidDev f, Lay L, const double* __restrict__ poro,
 }
 
 template <int MODEL>
-__global__ void flux_kernel(FluidDev f, Lay L, double dz, double top, double vol, double dt,
+__global__ __launch_bounds__(256) void flux_kernel(FluidDev f, Lay L, double dz, double top, double vol, double dt,
                             double s0, double s1, double s2, const double* __restrict__ poro,
                             const double* __restrict__ tp, const double* __restrict__ xold,
                             const double* __restrict__ x, const double* __restrict__ props,
@@ -247,18 +264,12 @@ __global__ void flux_kernel(FluidDev f, Lay L, double dz, double top, double vol
   const size_t n = L.n;
   int i, j, k;
   lay_coords(L, t, i, j, k);
-  double xv[B], xo[B];
-  for (int u = 0; u < B; ++u) {
-    xv[u] = x[u * n + t];
-    xo[u] = xold[u * n + t];
-  }
-  CellState<MODEL> cs, co;
-  cell_state<MODEL>(f, poro[t], xv, cs);
-  cell_state<MODEL>(f, poro[t], xo, co);
+  double xv[B];
+  for (int u = 0; u < B; ++u) xv[u] = x[u * n + t];
   double R[B], Jd[B][B];
   for (int r = 0; r < B; ++r) {
-    R[r] = vol * (cs.acc[r] - co.acc[r]) / dt;
-    for (int u = 0; u < B; ++u) Jd[r][u] = vol * cs.dacc[r][u] / dt;
+    R[r] = vol * props[(PP::ACC + r) * n + t] / dt;
+    for (int u = 0; u < B; ++u) Jd[r][u] = vol * props[(PP::DACC + r * B + u) * n + t] / dt;
   }
   const double scale[3] = {s0, s1, s2};
   // own state as stored (both sides of a face see identical values)
@@ -495,7 +506,7 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
   int np = (int)ctx->perfs.size();
   hipStream_t s = ctx->stream;
   if (ctx->fl.model == 2) {
-    props_kernel<2><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, x_cs, ctx->props);
+    props_kernel<2><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
     prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
     flux_kernel<2><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt,
                                       sc[0], sc[1], sc[2], ctx->poro, ctx->tp, xold_cs, x_cs,
@@ -505,7 +516,7 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
                                                         sc[1], sc[2], ctx->poro, x_cs, ctx->J, rhs_cs,
                                                         ctx->bord, ctx->pq);
   } else {
-    props_kernel<3><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, x_cs, ctx->props);
+    props_kernel<3><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
     prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
     flux_kernel<3><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt,
                                       sc[0], sc[1], sc[2], ctx->poro, ctx->tp, xold_cs, x_cs,

@@ -115,3 +115,33 @@ def test_time_step_with_rate_wells_matches_oracle(name):
     assert np.linalg.norm(x[:n] - xo.ravel()) <= 1e-8 * np.linalg.norm(xo)
     assert np.allclose(x[n:], so["bhp"], rtol=1e-8)
     s.close()
+
+
+@pytest.mark.parametrize("opts,krylov", [(dict(precision="mixed"), "fgmres"),
+                                         (dict(decoupling="abf", composition="fpf"), "fgmres"),
+                                         (dict(precision="mixed", composition="fpf"), "bicgstab")])
+def test_rate_wells_with_other_solver_forms_meet_their_targets(opts, krylov):
+    # the well rows ride along with every form of the cell preconditioner
+    # and both Krylov methods: the accepted state meets the Newton criterion
+    # and every rate equation, recomputed by the oracle
+    from paper_1606_00548_amd import cprmi
+    case, dt = _bo_case()
+    rws = model.rate_wells(case["wells"])
+    bhp0 = np.array([w["bhp"] for w in rws])
+    s = cprmi.Solver.from_case(case)
+    xg, sg = s.time_step(_gpu(_flat(case["x_old"], bhp0)), dt, options=cprmi.default_options(**opts),
+                         newton={"krylov": krylov})
+    x = xg.cpu().numpy()
+    n = case["x_old"].size
+    xc, bhp = x[:n].reshape(case["x_old"].shape), x[n:]
+    R, _, W = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                             case["x_old"], xc, sg["dt_taken"], bhp=bhp, border=True)
+    R0, _, W0 = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                               case["x_old"], case["x_old"], sg["dt_taken"], bhp=bhp0, border=True)
+    f = np.linalg.norm(np.concatenate([R.ravel(), W["R"]]))
+    f0 = np.linalg.norm(np.concatenate([R0.ravel(), W0["R"]]))
+    print(f"[rate-wells] {opts} {krylov}: Newton {sg['newton_iterations']}, cuts {sg['cuts']}, "
+          f"|F|/|F0| {f / f0:.1e}, max |R_w| {np.abs(W['R']).max():.1e}")
+    assert sg["converged"] and f < 1e-3 * f0
+    assert np.abs(W["R"]).max() < 1e-3 * f0
+    s.close()

@@ -15,7 +15,8 @@
  * Conventions shared by every entry point
  *   - Cells are numbered in natural order n = i + nx*(j + ny*k), k downward.
  *     A per-cell vector with b unknowns is stored unknown-major, [b][n]:
- *     x[u*n + cell].  Unknowns are (p [bar], S_w) for oil-water and
+ *     x[u*n + cell].  Unknowns are (p [bar]) for the single-phase test
+ *     model, (p [bar], S_w) for oil-water and
  *     (p_o [bar], S_w, x2) for black oil, whose third unknown switches with
  *     the phase state (Sec. 2.4: gas saturation or bubble point pressure):
  *     x2 = S_g >= 0 in a saturated cell, x2 = -p_b < 0 (bar) in an
@@ -59,7 +60,7 @@ enum {
   CPR_EBREAKDOWN = -6      /* Krylov breakdown without convergence          */
 };
 
-enum { CPR_MODEL_OIL_WATER = 2, CPR_MODEL_BLACK_OIL = 3 };
+enum { CPR_MODEL_SINGLE_PHASE = 1, CPR_MODEL_OIL_WATER = 2, CPR_MODEL_BLACK_OIL = 3 };
 enum { CPR_WELL_INJECTOR = 0, CPR_WELL_PRODUCER = 1 };
 enum { CPR_CONTROL_BHP = 0, CPR_CONTROL_RATE = 1 };
 enum { CPR_PREC_FP64 = 0, CPR_PREC_MIXED = 1 };
@@ -88,6 +89,8 @@ typedef struct {
 
 /* Fluid and rock description (Sec. 2.1-2.2).  Pressures in bar,
  * compressibilities in 1/bar, viscosities in cP, densities in kg/m^3.
+ *   single phase (test model, one unknown p, water): rho_w_ref, c_w, c_r,
+ *              mu_w;
  *   oil-water: rho_o_ref, rho_w_ref, c_o, c_w, c_r, mu_o, mu_w, s_wc, s_or
  *              (Corey curves of eqs. (17)-(18), exponent 2);
  *   black oil: rho_o_sc, rho_g_sc (surface densities), rho_w_ref, c_w, c_r,
@@ -172,7 +175,7 @@ const char* cpr_last_error(const cpr_ctx_t* ctx);
 /* Unknowns of a state vector: b * cells + rate-controlled wells. */
 long long cpr_num_unknowns(const cpr_ctx_t* ctx);
 
-/* Number of unknowns per cell (2 or 3) and cells of the context. */
+/* Number of unknowns per cell (1, 2 or 3) and cells of the context. */
 int cpr_block_size(const cpr_ctx_t* ctx);
 long long cpr_num_cells(const cpr_ctx_t* ctx);
 

@@ -303,7 +303,7 @@ class Solver:
         lib = load()
         self.lib = lib
         self.grid = grid
-        self.b = {2: 2, 3: 3}[fluid["model"]]
+        self.b = {1: 1, 2: 2, 3: 3}[fluid["model"]]
         self.shape = (grid["nz"], grid["ny"], grid["nx"])
         g = Grid(grid["nx"], grid["ny"], grid["nz"], grid["dx"], grid["dy"], grid["dz"], grid["top"])
         f = Fluid()

@@ -825,7 +825,9 @@ void launch_mixed_copies(cpr_ctx* ctx) {
   hipStream_t s = ctx->stream;
   int n = ctx->lay.n;
   const double* J = Pre<double>::J(ctx);
-  if (ctx->b == 2)
+  if (ctx->b == 1)
+    mixed_copy_kernel<1><<<div_up(n, 256), 256, 0, s>>>(n, J, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf);
+  else if (ctx->b == 2)
     mixed_copy_kernel<2><<<div_up(n, 256), 256, 0, s>>>(n, J, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf);
   else
     mixed_copy_kernel<3><<<div_up(n, 256), 256, 0, s>>>(n, J, ctx->R0, ctx->Dinv, ctx->Jf, ctx->Dinvf);
@@ -839,7 +841,10 @@ void launch_mixed_copies(cpr_ctx* ctx) {
 void precond_pressure_stage(cpr_ctx* ctx, const double* v) {
   const Lay& L = ctx->lay;
   MGLevel& L0 = ctx->levels[0];
-  if (ctx->b == 2)
+  if (ctx->b == 1)
+    decouple_red_kernel<1, double><<<div_up(L.n, 256), 256, 0, ctx->stream>>>(L.n, L.nh, ctx->w, v, nullptr, nullptr,
+                                                                               L0.A, L0.r, L0.x);
+  else if (ctx->b == 2)
     decouple_red_kernel<2, double><<<div_up(L.n, 256), 256, 0, ctx->stream>>>(L.n, L.nh, ctx->w, v, nullptr, nullptr,
                                                                                L0.A, L0.r, L0.x);
   else
@@ -850,7 +855,9 @@ void precond_pressure_stage(cpr_ctx* ctx, const double* v) {
 
 void precond_apply(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, double* z) {
   bool mixed = ctx->opt.precision == CPR_PREC_MIXED;
-  if (ctx->b == 2) {
+  if (ctx->b == 1) {
+    if (mixed) apply_impl<1, float>(ctx, vin, v, nrm2, z); else apply_impl<1, double>(ctx, vin, v, nrm2, z);
+  } else if (ctx->b == 2) {
     if (mixed) apply_impl<2, float>(ctx, vin, v, nrm2, z); else apply_impl<2, double>(ctx, vin, v, nrm2, z);
   } else {
     if (mixed) apply_impl<3, float>(ctx, vin, v, nrm2, z); else apply_impl<3, double>(ctx, vin, v, nrm2, z);

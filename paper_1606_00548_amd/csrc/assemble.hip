@@ -30,6 +30,12 @@ constexpr double TIE_BAR = 1.0e-9;
 template <int MODEL>
 struct Traits;
 template <>
+struct Traits<1> {   // single-phase (water) test model
+  static constexpr int B = 1, NP = 1, NT = 1;
+  __host__ __device__ static constexpr int row(int) { return 0; }
+  __host__ __device__ static constexpr int phase(int) { return 0; }
+};
+template <>
 struct Traits<2> {
   static constexpr int B = 2, NP = 2, NT = 2;
   __host__ __device__ static constexpr int row(int t) { return t; }
@@ -94,7 +100,15 @@ __device__ void cell_state(const FluidDev& f, double poro, const double* xv, Cel
   double rho_w = f.rho_w_ref * exp(f.c_w * (p - pref));
   double drho_w = f.c_w * rho_w;
   double mu_w = f.mu_w * CP;
-  if constexpr (MODEL == 2) {
+  if constexpr (MODEL == 1) {
+    s.acc[0] = phi * rho_w;
+    s.dacc[0][0] = dphi * rho_w + phi * drho_w;
+    s.rho[0] = rho_w; s.drho[0] = drho_w;
+    s.lam[0] = rho_w / mu_w;
+    s.dlam[0][0] = drho_w / mu_w;
+    s.lt = 1.0 / mu_w;
+    s.dlt[0] = 0.0;
+  } else if constexpr (MODEL == 2) {
     double sw = xv[1];
     double so = 1.0 - sw;
     double rho_o = f.rho_o_ref * exp(f.c_o * (p - pref));
@@ -402,17 +416,18 @@ __global__ void well_kernel(FluidDev f, Lay L, int nperf, const Perf* __restrict
   }
   if (pf.kind == CPR_WELL_INJECTOR) {
     // water injector: total mobility of the cell, water density
-    double rho = s.rho[1], drho = s.drho[1];
+    constexpr int WR = MODEL == 1 ? 0 : 1;   // water row and phase
+    double rho = s.rho[WR], drho = s.drho[WR];
     double drive = dh * BAR - rho * G_ACC * pf.dzh;
-    q[1] = pf.wi * rho * s.lt * drive;
-    dqh[1] = pf.wi * rho * s.lt * BAR;
+    q[WR] = pf.wi * rho * s.lt * drive;
+    dqh[WR] = pf.wi * rho * s.lt * BAR;
     for (int u = 0; u < B; ++u) {
       double v = pf.wi * rho * s.dlt[u] * drive;
       if (u == 0) {
         v += pf.wi * drho * s.lt * drive;
         v += pf.wi * rho * s.lt * (-BAR - drho * G_ACC * pf.dzh);
       }
-      dq[1][u] = v;
+      dq[WR][u] = v;
     }
   } else {
     for (int tt = 0; tt < NT; ++tt) {
@@ -505,7 +520,17 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
   int nb = div_up(L.n, 256);
   int np = (int)ctx->perfs.size();
   hipStream_t s = ctx->stream;
-  if (ctx->fl.model == 2) {
+  if (ctx->fl.model == 1) {
+    props_kernel<1><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
+    prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
+    flux_kernel<1><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt,
+                                      sc[0], sc[1], sc[2], ctx->poro, ctx->tp, xold_cs, x_cs,
+                                      ctx->props, ctx->J, rhs_cs);
+    prof_end(ctx, CPR_KCLASS_ASSEMBLE);
+    if (np) well_kernel<1><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, ctx->rwells_d, sc[0],
+                                                        sc[1], sc[2], ctx->poro, x_cs, ctx->J, rhs_cs,
+                                                        ctx->bord, ctx->pq);
+  } else if (ctx->fl.model == 2) {
     props_kernel<2><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
     prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
     flux_kernel<2><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt,
@@ -533,12 +558,12 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
 
 // Number of SoA planes the per-cell state needs (allocation size).
 int props_planes(int model) {
-  return model == 2 ? PropPlanes<2>::COUNT : PropPlanes<3>::COUNT;
+  return model == 1 ? PropPlanes<1>::COUNT : model == 2 ? PropPlanes<2>::COUNT : PropPlanes<3>::COUNT;
 }
 
 // Plane of the per-cell state that holds the total volumetric mobility.
 int props_lt_plane(int model) {
-  return model == 2 ? PropPlanes<2>::LT : PropPlanes<3>::LT;
+  return model == 1 ? PropPlanes<1>::LT : model == 2 ? PropPlanes<2>::LT : PropPlanes<3>::LT;
 }
 
 double host_pvt(const FluidDev& f, int row, double p) {

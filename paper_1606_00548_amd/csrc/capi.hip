@@ -80,8 +80,8 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
   long long n = (long long)g->nx * g->ny * g->nz;
   if (n > INT_MAX / 2) return set_err(ctx, CPR_EINVAL, "grid too large");
   if (!(g->dx > 0 && g->dy > 0 && g->dz > 0)) return set_err(ctx, CPR_EINVAL, "cell sizes must be > 0");
-  if (f->model != CPR_MODEL_OIL_WATER && f->model != CPR_MODEL_BLACK_OIL)
-    return set_err(ctx, CPR_EINVAL, "model must be 2 (oil-water) or 3 (black oil)");
+  if (f->model != CPR_MODEL_SINGLE_PHASE && f->model != CPR_MODEL_OIL_WATER && f->model != CPR_MODEL_BLACK_OIL)
+    return set_err(ctx, CPR_EINVAL, "model must be 1 (single phase), 2 (oil-water) or 3 (black oil)");
   if (f->model == CPR_MODEL_BLACK_OIL && (!f->pvt || f->n_pvt < 2 || f->n_pvt > CPR_MAX_PVT))
     return set_err(ctx, CPR_EINVAL, "black oil needs a PVT table with 2..16 nodes");
   ctx->stream = (hipStream_t)stream;
@@ -175,7 +175,9 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
     if (!(ctx->phibar > 0.0)) return set_err(ctx, CPR_EINVAL, "mean porosity must be > 0");
   }
   ctx->cell_vol = g->dx * g->dy * g->dz;
-  if (f->model == CPR_MODEL_OIL_WATER) {
+  if (f->model == CPR_MODEL_SINGLE_PHASE) {
+    ctx->rho_scale[0] = f->rho_w_ref;
+  } else if (f->model == CPR_MODEL_OIL_WATER) {
     ctx->rho_scale[0] = f->rho_o_ref;
     ctx->rho_scale[1] = f->rho_w_ref;
   } else {
@@ -191,9 +193,11 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
       RateWell r;
       r.p0 = (int)ctx->perfs.size();
       r.p1 = r.p0 + (w.k1 - w.k0 + 1);
-      r.comp = w.kind == CPR_WELL_INJECTOR ? 1 : 0;
-      const double rho_s = w.kind == CPR_WELL_INJECTOR ? f->rho_w_ref
-                           : (f->model == CPR_MODEL_BLACK_OIL ? f->rho_o_sc : f->rho_o_ref);
+      // single phase: the water row of either kind; otherwise water (injector) or oil (producer)
+      const bool water = w.kind == CPR_WELL_INJECTOR || f->model == CPR_MODEL_SINGLE_PHASE;
+      r.comp = f->model == CPR_MODEL_SINGLE_PHASE ? 0 : (water ? 1 : 0);
+      const double rho_s = water ? f->rho_w_ref
+                                 : (f->model == CPR_MODEL_BLACK_OIL ? f->rho_o_sc : f->rho_o_ref);
       const double mass = w.rate * rho_s / 86400.0;
       r.target = w.kind == CPR_WELL_INJECTOR ? mass : -mass;
       ctx->rwells.push_back(r);

@@ -572,10 +572,14 @@ int setup_cpr(cpr_ctx* ctx) {
   int nb = div_up(n, 256);
   const bool abf = ctx->opt.decoupling == CPR_DECOUPLE_ABF;
   if (abf) {
-    if (ctx->b == 2)
+    if (ctx->b == 1)
+      abf_kernel<1><<<nb, 256, 0, s>>>(n, ctx->J, ctx->Wabf, ctx->R0, ctx->Jt, ctx->levels[0].A, ctx->flag);
+    else if (ctx->b == 2)
       abf_kernel<2><<<nb, 256, 0, s>>>(n, ctx->J, ctx->Wabf, ctx->R0, ctx->Jt, ctx->levels[0].A, ctx->flag);
     else
       abf_kernel<3><<<nb, 256, 0, s>>>(n, ctx->J, ctx->Wabf, ctx->R0, ctx->Jt, ctx->levels[0].A, ctx->flag);
+  } else if (ctx->b == 1) {
+    qimpes_kernel<1><<<nb, 256, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
   } else if (ctx->b == 2) {
     qimpes_kernel<2><<<nb, 256, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
   } else {
@@ -622,7 +626,9 @@ int setup_cpr(cpr_ctx* ctx) {
   // red-black block ILU(0): red diagonals first, black ones use them
   int nh = div_up(L.nh, 256);
   for (int colour = 0; colour < 2; ++colour) {
-    if (ctx->b == 2)
+    if (ctx->b == 1)
+      ilu_kernel<1><<<nh, 256, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
+    else if (ctx->b == 2)
       ilu_kernel<2><<<nh, 256, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
     else
       ilu_kernel<3><<<nh, 256, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);

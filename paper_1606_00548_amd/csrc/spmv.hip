@@ -64,7 +64,9 @@ __global__ __launch_bounds__(256) void spmv_kernel(Lay L, const double* __restri
 void launch_spmv(int b, const Lay& L, const double* A, const double* x, double* y,
                  const double* rhs, hipStream_t s) {
   int nb = div_up(L.n, 256);
-  if (b == 2)
+  if (b == 1)
+    spmv_kernel<1><<<nb, 256, 0, s>>>(L, A, x, y, rhs);
+  else if (b == 2)
     spmv_kernel<2><<<nb, 256, 0, s>>>(L, A, x, y, rhs);
   else
     spmv_kernel<3><<<nb, 256, 0, s>>>(L, A, x, y, rhs);

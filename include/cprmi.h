@@ -159,6 +159,17 @@ typedef struct cpr_ctx cpr_ctx_t;
 /* Fill *o with the defaults listed above. */
 void cpr_default_options(cpr_options_t* o);
 
+/* Device memory: by default the library allocates with hipMalloc and frees
+ * with hipFree.  cpr_set_allocator installs a caller's allocator instead
+ * (for instance a framework's caching allocator): alloc(bytes, user) returns
+ * device memory of the current device (NULL on failure, reported as
+ * CPR_EHIP / CPR_ENOMEM by the call that needed it), release(ptr, user) takes
+ * it back.  Both NULL restore the default; exactly one NULL is CPR_EINVAL.
+ * Process-wide and thread-safe; a context or network keeps the allocator in
+ * force when it was created for all its memory until it is destroyed. */
+int cpr_set_allocator(void* (*alloc)(size_t bytes, void* user), void (*release)(void* ptr, void* user),
+                      void* user);
+
 /* Create a context.  perm3 (device, [3][n], mD, kx ky kz) and poro (device,
  * [n]) are read during the call and copied; wells is a host array.  The
  * library owns every buffer it allocates (Jacobian, hierarchy, Krylov basis)

@@ -113,7 +113,7 @@ EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error",
            "cpr_nn_forward", "cpr_nn_backward", "cpr_nn_train_step", "cpr_nn_attach",
            "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov", "cpr_nn_eval_loss",
            "cpr_nn_make_target", "cpr_nn_infer", "cpr_bicgstab_solve", "cpr_default_newton_options",
-           "cpr_time_step", "cpr_simulate", "cpr_num_unknowns"]
+           "cpr_time_step", "cpr_simulate", "cpr_num_unknowns", "cpr_set_allocator"]
 KCLASS = {"spmv": 0, "orth": 1, "smooth": 2, "ilu": 3, "assemble": 4}
 
 
@@ -136,6 +136,7 @@ def load():
     lib.cpr_num_cells.argtypes = [P]
     lib.cpr_num_cells.restype = ctypes.c_longlong
     lib.cpr_num_unknowns.argtypes = [P]
+    lib.cpr_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
     lib.cpr_num_unknowns.restype = ctypes.c_longlong
     lib.assemble_jacobian.argtypes = [P, P, P, ctypes.c_double, P]
     lib.cpr_import_jacobian.argtypes = [P, P]
@@ -282,6 +283,34 @@ def default_options(**kw):
             v = COMPOSITION[v]
         setattr(o, k, v)
     return o
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+# Every registered callback pair stays alive for the life of the process:
+# contexts created under it return their memory through it when destroyed.
+_allocators = []
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the library's device memory through alloc(nbytes) -> int and
+    free(ptr) (cpr_set_allocator); no arguments restore hipMalloc/hipFree.
+    Contexts keep the allocator they were created with."""
+    lib = load()
+    if alloc is None:
+        rc = lib.cpr_set_allocator(_ALLOC_FN(), _FREE_FN(), None)
+    else:
+        cb = (_ALLOC_FN(lambda n, user: alloc(n) or None), _FREE_FN(lambda p, user: free(p)))
+        _allocators.append(cb)
+        rc = lib.cpr_set_allocator(cb[0], cb[1], None)
+    if rc != 0:
+        raise CPRError(rc, "cpr_set_allocator")
+
+
+def use_torch_allocator():
+    """Let torch's caching allocator supply the library's device memory."""
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n),
+                  lambda p: torch.cuda.caching_allocator_delete(p))
 
 
 def default_newton_options(**kw):

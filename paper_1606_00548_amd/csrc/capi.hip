@@ -32,8 +32,8 @@ template <typename T>
 int dalloc(cpr_ctx* ctx, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-  if (e != hipSuccess) return set_hip_err(ctx, e, "hipMalloc");
+  hipError_t e = dev_malloc(ctx->mem, (void**)p, count * sizeof(T));
+  if (e != hipSuccess) return set_hip_err(ctx, e, "device allocation");
   return CPR_OK;
 }
 
@@ -45,8 +45,7 @@ void free_all(cpr_ctx* ctx) {
                   ctx->part, ctx->hdev, ctx->lnk, ctx->rprime, ctx->qbuf, ctx->feat, ctx->nnscal,
                   ctx->nncount, ctx->Wabf, ctx->Jt, ctx->Rt, ctx->Rtf, ctx->Z1, ctx->Z1f, ctx->rwells_d,
                   ctx->bord, ctx->pq, ctx->bord_d};
-  for (void* b : bufs)
-    if (b) hipFree(b);
+  for (void* b : bufs) dev_free(ctx->mem, b);
   if (ctx->hhost) hipHostFree(ctx->hhost);
   ctx->hhost = nullptr;
   for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
@@ -246,8 +245,8 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
 
 int ensure_krylov(cpr_ctx* ctx, int m) {
   if (m <= ctx->mcap) return CPR_OK;
-  if (ctx->V) hipFree(ctx->V);
-  if (ctx->Z) hipFree(ctx->Z);
+  dev_free(ctx->mem, ctx->V);
+  dev_free(ctx->mem, ctx->Z);
   ctx->V = ctx->Z = nullptr;
   ctx->mcap = 0;
   size_t len = (size_t)vec_len(ctx);
@@ -357,6 +356,7 @@ int cpr_create(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, c
   } catch (...) {
     return CPR_ENOMEM;
   }
+  ctx->mem = current_allocator();
   int rc;
   try {
     rc = create_impl(g, f, perm3, poro, wells, nwells, stream, ctx);

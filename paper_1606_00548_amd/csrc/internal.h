@@ -18,6 +18,17 @@
 #include "cprmi.h"
 
 #define CPR_MAX_PVT 16
+
+// Device allocator of a context or network (alloc.hip): the caller's
+// callbacks, or hipMalloc / hipFree when they are null.
+struct DevAlloc {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, void*) = nullptr;
+  void* user = nullptr;
+};
+DevAlloc current_allocator();
+hipError_t dev_malloc(const DevAlloc& a, void** p, size_t bytes);
+void dev_free(const DevAlloc& a, void* p);
 #define CPR_MAX_WELLS_PERF 65536
 
 struct Lay {
@@ -170,6 +181,7 @@ struct MGLevel {
 
 struct cpr_ctx {
   std::string err;
+  DevAlloc mem;                // device allocator taken at creation
   hipStream_t stream = nullptr;
   // setup runs the Galerkin chain and the coarsest inverse on a second
   // stream (default priority) while the ILU factorisation runs on `stream`

@@ -728,6 +728,7 @@ __global__ void frag_kernel(int ci, int ck, int co, int backward, const float* _
 
 struct cpr_nn {
   std::string err;
+  DevAlloc mem;        // device allocator taken at creation
   hipStream_t stream = nullptr;
   Geo lv[4];           // grid per level (batch = max_batch)
   int max_batch = 0;
@@ -952,11 +953,13 @@ static int nn_alloc(cpr_nn* nn) {
   const int B = nn->max_batch;
   long n[4];
   for (int l = 0; l < 4; ++l) n[l] = (long)B * nn->lv[l].V;
-  auto A = [&](float** p, long cnt) -> hipError_t { return hipMalloc((void**)p, (cnt > 0 ? cnt : 1) * sizeof(float)); };
+  auto A = [&](float** p, long cnt) -> hipError_t {
+    return dev_malloc(nn->mem, (void**)p, (cnt > 0 ? cnt : 1) * sizeof(float));
+  };
   NN_TRY(A(&nn->theta, nn->P)); NN_TRY(A(&nn->m, nn->P)); NN_TRY(A(&nn->vv, nn->P)); NN_TRY(A(&nn->grad, nn->P));
   for (int k = 0; k < NCONV; ++k) {
-    NN_TRY(hipMalloc((void**)&nn->wf[k], fwd_frags(k) * sizeof(bf16x8)));
-    NN_TRY(hipMalloc((void**)&nn->wb[k], bwd_frags(k) * sizeof(bf16x8)));
+    NN_TRY(dev_malloc(nn->mem, (void**)&nn->wf[k], fwd_frags(k) * sizeof(bf16x8)));
+    NN_TRY(dev_malloc(nn->mem, (void**)&nn->wb[k], bwd_frags(k) * sizeof(bf16x8)));
   }
   NN_TRY(A(&nn->x16, n[0] * 16)); NN_TRY(A(&nn->e0, n[0] * 16)); NN_TRY(A(&nn->p1, n[1] * 16));
   NN_TRY(A(&nn->e1, n[1] * 32)); NN_TRY(A(&nn->p2, n[2] * 32)); NN_TRY(A(&nn->e2, n[2] * 64));
@@ -987,11 +990,10 @@ static void nn_free(cpr_nn* nn) {
                  nn->e3, nn->a4, nn->d2, nn->a5, nn->d1, nn->a6, nn->d0, nn->y, nn->dy, nn->g0, nn->g0b,
                  nn->gu0, nn->g1, nn->g1b, nn->gu1, nn->g2, nn->g2b, nn->gu2, nn->g3, nn->g3b, nn->gp,
                  nn->prod, nn->part, nn->lpart, nn->loss};
-  for (float* p : fs)
-    if (p) hipFree(p);
+  for (float* p : fs) dev_free(nn->mem, p);
   for (int k = 0; k < NCONV; ++k) {
-    if (nn->wf[k]) hipFree(nn->wf[k]);
-    if (nn->wb[k]) hipFree(nn->wb[k]);
+    dev_free(nn->mem, nn->wf[k]);
+    dev_free(nn->mem, nn->wb[k]);
   }
 }
 
@@ -1023,6 +1025,7 @@ int cpr_nn_create(int nx, int ny, int nz, int max_batch, void* stream, cpr_nn_t*
   } catch (...) {
     return CPR_ENOMEM;
   }
+  nn->mem = current_allocator();
   *out = nn;
   if (nx < 8 || ny < 8 || nz < 8 || nx % 8 || ny % 8 || nz % 8 || max_batch < 1 || max_batch > 64)
     return nn_err(nn, CPR_EINVAL, "grid dimensions must be multiples of 8 (>= 8), batch 1..64");

@@ -510,13 +510,14 @@ __global__ void zero_int_kernel(int* p, int n) {
 static void free_levels(cpr_ctx* ctx) {
   for (size_t l = 0; l < ctx->levels.size(); ++l) {
     MGLevel& L = ctx->levels[l];
-    hipFree(L.A); hipFree(L.Af); hipFree(L.x); hipFree(L.r); hipFree(L.xf); hipFree(L.rf);
-    hipFree(L.res); hipFree(L.resf);
+    for (void* b : {(void*)L.A, (void*)L.Af, (void*)L.x, (void*)L.r, (void*)L.xf, (void*)L.rf, (void*)L.res,
+                    (void*)L.resf})
+      dev_free(ctx->mem, b);
   }
   ctx->levels.clear();
-  hipFree(ctx->cinv); ctx->cinv = nullptr;
-  hipFree(ctx->cinvf); ctx->cinvf = nullptr;
-  hipFree(ctx->gj_work); ctx->gj_work = nullptr;
+  dev_free(ctx->mem, ctx->cinv); ctx->cinv = nullptr;
+  dev_free(ctx->mem, ctx->cinvf); ctx->cinvf = nullptr;
+  dev_free(ctx->mem, ctx->gj_work); ctx->gj_work = nullptr;
 }
 
 void release_hierarchy(cpr_ctx* ctx) { free_levels(ctx); }
@@ -543,19 +544,19 @@ static int build_hierarchy(cpr_ctx* ctx) {
     MGLevel& L = ctx->levels[l];
     L.lay = shapes[l];
     size_t n = L.lay.n;
-    CPR_TRY(hipMalloc(&L.A, 7 * n * sizeof(double)));
-    CPR_TRY(hipMalloc(&L.Af, 7 * n * sizeof(float)));
-    CPR_TRY(hipMalloc(&L.x, n * sizeof(double)));
-    CPR_TRY(hipMalloc(&L.r, n * sizeof(double)));
-    CPR_TRY(hipMalloc(&L.xf, n * sizeof(float)));
-    CPR_TRY(hipMalloc(&L.rf, n * sizeof(float)));
-    CPR_TRY(hipMalloc(&L.res, (n / 2 + 1) * sizeof(double)));
-    CPR_TRY(hipMalloc(&L.resf, (n / 2 + 1) * sizeof(float)));
+    CPR_TRY(dev_malloc(ctx->mem, (void**)&L.A, 7 * n * sizeof(double)));
+    CPR_TRY(dev_malloc(ctx->mem, (void**)&L.Af, 7 * n * sizeof(float)));
+    CPR_TRY(dev_malloc(ctx->mem, (void**)&L.x, n * sizeof(double)));
+    CPR_TRY(dev_malloc(ctx->mem, (void**)&L.r, n * sizeof(double)));
+    CPR_TRY(dev_malloc(ctx->mem, (void**)&L.xf, n * sizeof(float)));
+    CPR_TRY(dev_malloc(ctx->mem, (void**)&L.rf, n * sizeof(float)));
+    CPR_TRY(dev_malloc(ctx->mem, (void**)&L.res, (n / 2 + 1) * sizeof(double)));
+    CPR_TRY(dev_malloc(ctx->mem, (void**)&L.resf, (n / 2 + 1) * sizeof(float)));
   }
   size_t nc = shapes.back().n;
-  CPR_TRY(hipMalloc(&ctx->cinv, nc * nc * sizeof(double)));
-  CPR_TRY(hipMalloc(&ctx->cinvf, nc * nc * sizeof(float)));
-  CPR_TRY(hipMalloc(&ctx->gj_work, 2 * nc * 2 * nc * sizeof(double)));
+  CPR_TRY(dev_malloc(ctx->mem, (void**)&ctx->cinv, nc * nc * sizeof(double)));
+  CPR_TRY(dev_malloc(ctx->mem, (void**)&ctx->cinvf, nc * nc * sizeof(float)));
+  CPR_TRY(dev_malloc(ctx->mem, (void**)&ctx->gj_work, 2 * nc * 2 * nc * sizeof(double)));
   return CPR_OK;
 }
 

@@ -25,6 +25,44 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CPR-GMRES s/Newton step + GB/s at 1e-6 rel resid; plain FP64 vs mixed+learned"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak of the device
+
+# (input, output) channels and grid level (0 = full, l = 1/2^l per axis) of
+# the seven 3x3x3 convolutions of the pressure network
+NET_CONVS = [(3, 16, 0), (16, 32, 1), (32, 64, 2), (64, 64, 3), (64, 64, 2), (64, 32, 1), (32, 16, 0)]
+
+
+def network_flop(nx, ny, nz):
+    """Algorithmic FLOP of one inference: 2 * 27 * C_in * C_out per output
+    voxel of every convolution, plus the 1x1x1 head."""
+    v0 = nx * ny * nz
+    conv = sum(2 * 27 * ci * co * v0 // 8 ** lv for ci, co, lv in NET_CONVS)
+    return conv + 2 * 16 * v0
+
+
+def network_timing(nx, ny, nz, reps=50):
+    """Event-timed inference of the black-oil network at one grid (batch 1)."""
+    import numpy as np
+    import torch
+    from paper_1606_00548_amd import cprmi, train
+    net = cprmi.Network(nx, ny, nz, max_batch=1)
+    net.set_params(np.load(train.weights_path("black-oil")))
+    x = torch.randn((1, nz, ny, nx, 3), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        net.infer(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        net.infer(x)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    gf = network_flop(nx, ny, nz) / 1e9
+    net.close()
+    tflops = gf / us * 1e3          # GFLOP per microsecond -> TFLOP/s
+    return {"inference_us": us, "gflop_per_inference": gf, "tflops": tflops,
+            "frac_of_bf16_peak": tflops / BF16_PEAK_TFLOPS, "grid": [nx, ny, nz], "batch": 1}
 
 
 def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision, levels=None):
@@ -87,11 +125,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP64 / mixed / mixed+learned comparison runs")
+    ap.add_argument("--network-only", action="store_true",
+                    help="time only the pressure network's inference on the workload grid")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.network_only:
+        print(json.dumps({"network": network_timing(args.nx, args.ny, args.nz, reps=max(args.steps, 1) * 10)}))
+        return
 
     import numpy as np
     import torch
@@ -106,6 +149,8 @@ def main():
     x = x0.clone()
     opts = cprmi.default_options(precision=args.precision)
 
+    step_times = []   # host wall time of each timed step, per call of timed()
+
     def timed(o, kernel=None, krylov="fgmres"):
         """Warm-up, then exactly args.steps Newton steps between two syncs."""
         def step():
@@ -118,9 +163,13 @@ def main():
             solver.profile_kernel(kernel)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sts = [step() for _ in range(args.steps)]
+        sts, marks = [], [t0]
+        for _ in range(args.steps):
+            sts.append(step())
+            marks.append(time.perf_counter())
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        step_times.append([b - a for a, b in zip(marks[:-1], marks[1:])])
         prof = solver.profile_read() if kernel else (0, 0.0)
         if kernel:
             solver.profile_kernel(None)
@@ -130,6 +179,7 @@ def main():
         return (t1 - t0) / args.steps, sts, prof
 
     sec_per_step, stats, (launches, kernel_ms) = timed(opts, args.kernel)
+    median_ms = 1e3 * float(np.median(step_times[-1]))
 
     # the other forms of the preconditioner on the same workload
     variants = {}
@@ -265,6 +315,11 @@ def main():
     roofline["frac_of_measured_triad"] = (achieved / triad_gbs) if achieved else None
     for v in classes.values():
         v["frac_of_measured_triad"] = v["GBps"] / triad_gbs if v["GBps"] else None
+    # the four bandwidth-bound classes together over the whole solve phase
+    class_bytes = sum(v["algorithmic_bytes_per_step"] for v in classes.values())
+    solve_gbps = class_bytes / (phases["solve"] * 1e-3) / 1e9
+
+    network = network_timing(args.nx, args.ny, args.nz)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -278,7 +333,9 @@ def main():
         "config": {"workload": f"black-oil layered {args.nx}x{args.ny}x{args.nz} "
                                f"({n} cells, 3x3 blocks), one Newton step, FGMRES(30) to 1e-6",
                    "cells": n, "block": b, "precision": args.precision, "restart": 30, "rtol": 1e-6},
+        "median_ms_per_step": median_ms,
         "fgmres_iterations": its, "restart_cycles": cycles, "true_rel": st["true_rel"],
+        "solve_class_bytes_GBps": solve_gbps, "network": network,
         "phases_ms": phases, "roofline": roofline, "kernel_classes": classes, "cpu_baseline": cpu,
         "variants": variants, "time_step": time_step, "simulation": simulation,
     }

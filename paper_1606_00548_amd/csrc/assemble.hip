@@ -266,11 +266,10 @@ __global__ __launch_bounds__(256) void props_kernel(FluidDev f, Lay L, const dou
 }
 
 template <int MODEL>
-__global__ __launch_bounds__(256) void flux_kernel(FluidDev f, Lay L, double dz, double top, double vol, double dt,
-                            double s0, double s1, double s2, const double* __restrict__ poro,
-                            const double* __restrict__ tp, const double* __restrict__ xold,
-                            const double* __restrict__ x, const double* __restrict__ props,
-                            double* __restrict__ J, double* __restrict__ rhs) {
+__global__ __launch_bounds__(256) void flux_kernel(Lay L, double dz, double top, double vol, double dt, double s0,
+                                                   double s1, double s2, const double* __restrict__ tp,
+                                                   const double* __restrict__ x, const double* __restrict__ props,
+                                                   double* __restrict__ J, double* __restrict__ rhs) {
   using PP = PropPlanes<MODEL>;
   constexpr int B = Traits<MODEL>::B, NP = Traits<MODEL>::NP, NT = Traits<MODEL>::NT;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -523,9 +522,8 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
   if (ctx->fl.model == 1) {
     props_kernel<1><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
     prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
-    flux_kernel<1><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt,
-                                      sc[0], sc[1], sc[2], ctx->poro, ctx->tp, xold_cs, x_cs,
-                                      ctx->props, ctx->J, rhs_cs);
+    flux_kernel<1><<<nb, 256, 0, s>>>(L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt, sc[0], sc[1],
+                                      sc[2], ctx->tp, x_cs, ctx->props, ctx->J, rhs_cs);
     prof_end(ctx, CPR_KCLASS_ASSEMBLE);
     if (np) well_kernel<1><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, ctx->rwells_d, sc[0],
                                                         sc[1], sc[2], ctx->poro, x_cs, ctx->J, rhs_cs,
@@ -533,9 +531,8 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
   } else if (ctx->fl.model == 2) {
     props_kernel<2><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
     prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
-    flux_kernel<2><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt,
-                                      sc[0], sc[1], sc[2], ctx->poro, ctx->tp, xold_cs, x_cs,
-                                      ctx->props, ctx->J, rhs_cs);
+    flux_kernel<2><<<nb, 256, 0, s>>>(L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt, sc[0], sc[1],
+                                      sc[2], ctx->tp, x_cs, ctx->props, ctx->J, rhs_cs);
     prof_end(ctx, CPR_KCLASS_ASSEMBLE);
     if (np) well_kernel<2><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, ctx->rwells_d, sc[0],
                                                         sc[1], sc[2], ctx->poro, x_cs, ctx->J, rhs_cs,
@@ -543,9 +540,8 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
   } else {
     props_kernel<3><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
     prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
-    flux_kernel<3><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt,
-                                      sc[0], sc[1], sc[2], ctx->poro, ctx->tp, xold_cs, x_cs,
-                                      ctx->props, ctx->J, rhs_cs);
+    flux_kernel<3><<<nb, 256, 0, s>>>(L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt, sc[0], sc[1],
+                                      sc[2], ctx->tp, x_cs, ctx->props, ctx->J, rhs_cs);
     prof_end(ctx, CPR_KCLASS_ASSEMBLE);
     if (np) well_kernel<3><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, ctx->rwells_d, sc[0],
                                                         sc[1], sc[2], ctx->poro, x_cs, ctx->J, rhs_cs,

@@ -46,13 +46,13 @@ void free_all(cpr_ctx* ctx) {
                   ctx->nncount, ctx->Wabf, ctx->Jt, ctx->Rt, ctx->Rtf, ctx->Z1, ctx->Z1f, ctx->rwells_d,
                   ctx->bord, ctx->pq, ctx->bord_d};
   for (void* b : bufs) dev_free(ctx->mem, b);
-  if (ctx->hhost) hipHostFree(ctx->hhost);
+  if (ctx->hhost) (void)hipHostFree(ctx->hhost);
   ctx->hhost = nullptr;
-  for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : {ctx->ev_q, ctx->ev_rap, ctx->ev_gj, ctx->ev_iter[0], ctx->ev_iter[1]})
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   ctx->ev_q = ctx->ev_rap = ctx->ev_gj = ctx->ev_iter[0] = ctx->ev_iter[1] = nullptr;
-  if (ctx->aux) hipStreamDestroy(ctx->aux);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   ctx->aux = nullptr;
   if (ctx->nn) cpr_nn_destroy(ctx->nn);
   ctx->nn = nullptr;
@@ -369,7 +369,7 @@ int cpr_create(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, c
 
 void cpr_destroy(cpr_ctx_t* ctx) {
   if (!ctx) return;
-  hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
   free_all(ctx);
   delete ctx;
 }

@@ -275,11 +275,11 @@ struct cpr_ctx {
 // Bracket one launch of kernel class `k` with HIP events when it is sampled.
 inline void prof_begin(cpr_ctx* ctx, int k) {
   if (ctx->prof_class == k && 2 * ctx->ev_used + 1 < (int)ctx->ev.size())
-    hipEventRecord(ctx->ev[2 * ctx->ev_used], ctx->stream);
+    (void)hipEventRecord(ctx->ev[2 * ctx->ev_used], ctx->stream);
 }
 inline void prof_end(cpr_ctx* ctx, int k) {
   if (ctx->prof_class == k && 2 * ctx->ev_used + 1 < (int)ctx->ev.size()) {
-    hipEventRecord(ctx->ev[2 * ctx->ev_used + 1], ctx->stream);
+    (void)hipEventRecord(ctx->ev[2 * ctx->ev_used + 1], ctx->stream);
     ctx->ev_used += 1;
   }
 }

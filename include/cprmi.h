@@ -140,6 +140,8 @@ typedef struct {
   double mg_alpha;     /* coarse-correction scaling (1.0)                    */
   int decoupling;      /* CPR_DECOUPLE_QIMPES (default) or CPR_DECOUPLE_ABF  */
   int composition;     /* CPR_COMPOSE_PF (default) or CPR_COMPOSE_FPF        */
+  int x0;              /* 1: cpr_gmres_solve starts from the dx passed in
+                          (0, default: from zero; BiCGSTAB always from zero) */
 } cpr_options_t;
 
 typedef struct {
@@ -215,7 +217,8 @@ int cpr_export_jacobian(cpr_ctx_t* ctx, double* blocks);
  * inverted, CPR_EINVAL for an unknown decoupling or composition. */
 int cpr_setup(cpr_ctx_t* ctx, const cpr_options_t* o);
 
-/* Solve A dx = rhs (both device, [b][n]) from dx = 0 with FGMRES(restart)
+/* Solve A dx = rhs (both device, [b][n]) from dx = 0 (or from the dx passed
+ * in, with options.x0 = 1) with FGMRES(restart)
  * and the CPR preconditioner (eq. (13) with theta = rtol).  Synchronises once
  * per Arnoldi iteration to read the Hessenberg column.  st may be NULL.
  * Returns CPR_OK, CPR_NOT_CONVERGED (dx holds the last iterate),

@@ -344,6 +344,7 @@ void cpr_default_options(cpr_options_t* o) {
   o->mg_alpha = 1.0;
   o->decoupling = CPR_DECOUPLE_QIMPES;
   o->composition = CPR_COMPOSE_PF;
+  o->x0 = 0;
 }
 
 int cpr_create(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, const double* poro,
@@ -429,6 +430,7 @@ int cpr_gmres_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* 
   if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
   hipStream_t s = ctx->stream;
   CPR_TRY(vec_nat_to_cs(ctx, rhs, ctx->rs));
+  if (ctx->opt.x0) CPR_TRY(vec_nat_to_cs(ctx, dx, ctx->xs));
   if (ctx->opt.learned) CPR_TRY(hipMemsetAsync(ctx->nncount, 0, 2 * sizeof(int), s));
   int rc = fgmres_solve(ctx, st);
   if (rc < 0) return rc;

@@ -402,7 +402,8 @@ int reduce_dot(cpr_ctx* ctx, const double* a, const double* b, long len, double*
 }
 
 // ctx->rs holds the right-hand side, ctx->xs receives the solution
-// (colour-split).  Mirrors the oracle's FGMRES step for step.
+// (colour-split); with options.x0 it also holds the initial guess.
+// Mirrors the oracle's FGMRES step for step.
 int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
   hipStream_t s = ctx->stream;
   const int b = ctx->b;
@@ -419,7 +420,8 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
   S.mg_levels = (int)ctx->levels.size();
   S.qimpes_fallback = ctx->qimpes_bad;
 
-  zero_kernel<<<eb, 256, 0, s>>>(len, x);
+  const bool from_x0 = ctx->opt.x0 != 0;
+  if (!from_x0) zero_kernel<<<eb, 256, 0, s>>>(len, x);
   double bb;
   int rc = reduce_dot(ctx, ctx->rs, ctx->rs, len, &bb);
   if (rc) return rc;
@@ -430,11 +432,16 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     return set_err(ctx, CPR_ENONFINITE, "non-finite right-hand side");
   }
   if (bnorm == 0.0) {
+    if (from_x0) zero_kernel<<<eb, 256, 0, s>>>(len, x);
     S.converged = 1;
     if (st) *st = S;
     return CPR_OK;
   }
-  CPR_TRY(hipMemcpyAsync(r, ctx->rs, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (from_x0) {
+    system_spmv(ctx, x, r, ctx->rs);      // r = b - A x0
+  } else {
+    CPR_TRY(hipMemcpyAsync(r, ctx->rs, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), col(m + 1);
   int its = 0;
   int result = CPR_NOT_CONVERGED;

@@ -68,6 +68,7 @@ int time_step(cpr_ctx* ctx, const double* xold_cs, double* x_cs, double dt_days,
       if (l >= no.max_newton) break;
       cpr_options_t o = lin;
       o.rtol = forcing(no, lin.rtol, l, bn, bn_prev, rn_prev, diff_prev);
+      o.x0 = 0;   // every Newton correction starts from zero
       rc = setup_with_options(ctx, o);
       if (attempt_failure(rc)) break;
       if (rc != CPR_OK) return rc;

@@ -301,3 +301,26 @@ def test_mixed_precision_reaches_fp64_accuracy(name):
           f"(fp64 oracle {so['iterations']}), true rel. residual {res:.2e}, error vs fp64 {err:.2e}")
     assert apply_err <= 1e-4
     assert st["status"] == 0 and res <= 1e-6
+
+
+def test_fgmres_from_an_initial_guess_matches_oracle():
+    # options.x0: FGMRES starts from the dx passed in, r0 = b - A x0
+    case = CASES["bo-34x20x6"]()
+    x = synth.random_state_perturbation(case, 17)
+    J, b = _oracle_system(case, x)
+    pc = cpr.cpr_setup(J)
+    A = lambda v: cpr.block_spmv(J, v)
+    M = lambda v: cpr.cpr_apply(pc, v)
+    x0, _ = krylov.fgmres(A, M, b, rtol=1e-2)
+    xo, so = krylov.fgmres(A, M, b, x0=x0)
+    s = _solver(case)
+    s.import_jacobian(J)
+    s.setup(x0=1)
+    dx, st = s.solve(_gpu(b), dx=_gpu(x0))
+    print(f"[gpu-parity] from x0: {st['iterations']} iterations (oracle {so['iterations']}, from zero 13)")
+    assert st["status"] == 0 and st["iterations"] == so["iterations"]
+    assert np.linalg.norm(_np(dx) - xo) <= 1e-8 * np.linalg.norm(xo)
+    # a zero right-hand side returns zero whatever the guess
+    z, st0 = s.solve(s.vector(), dx=_gpu(x0))
+    assert st0["iterations"] == 0 and float(z.abs().max()) == 0.0
+    s.close()

@@ -249,3 +249,27 @@ def test_learned_solve_keeps_accuracy_and_counts_decisions():
     s.attach_network(None)
     with pytest.raises(cprmi.CPRError):
         s.setup(learned=1)
+
+
+def test_nan_network_always_falls_back_to_plain_cpr():
+    # a network whose output is NaN (NaN head weights: the ReLUs inside would
+    # turn NaN activations into zeros) fails the judge on every application:
+    # the solve is bit for bit the plain CPR solve, every decision a reject
+    from paper_1606_00548_amd import cprmi
+    case = _ow_case()
+    s = cprmi.Solver.from_case(case)
+    rhs = s.assemble(torch.as_tensor(case["x_old"]).cuda(), torch.as_tensor(case["x"]).cuda(), case["dt"])
+    theta = _theta(9).astype(np.float32)
+    theta[-17:] = np.nan          # the 1x1x1 head: 16 weights and its bias, last in the layout
+    s.attach_network(theta)
+    for prec in ("fp64", "mixed"):
+        s.setup(precision=prec)
+        dx0, st0 = s.solve(rhs)
+        x0 = dx0.cpu().numpy()
+        s.setup(precision=prec, learned=1)
+        dx1, st1 = s.solve(rhs)
+        print(f"[learned] NaN network, {prec}: {st1['iterations']} iterations, accepted {st1['nn_accepted']}, "
+              f"rejected {st1['nn_rejected']}")
+        assert st1["nn_accepted"] == 0 and st1["nn_rejected"] == st1["iterations"] == st0["iterations"]
+        assert np.array_equal(dx1.cpu().numpy(), x0)
+    s.close()

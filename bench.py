@@ -320,10 +320,13 @@ def main():
     solve_gbps = class_bytes / (phases["solve"] * 1e-3) / 1e9
 
     network = network_timing(args.nx, args.ny, args.nz)
+    configs = other_configs() if not args.no_variants else {}
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(case)
+        # the oracle moves the same algorithmic bytes for the step
+        cpu["GBps"] = class_bytes / cpu["value"] / 1e9
     out = {
         "metric": METRIC, "value": sec_per_step, "unit": "s/Newton step", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec_per_step * 1e3,
@@ -337,7 +340,7 @@ def main():
         "fgmres_iterations": its, "restart_cycles": cycles, "true_rel": st["true_rel"],
         "solve_class_bytes_GBps": solve_gbps, "network": network,
         "phases_ms": phases, "roofline": roofline, "kernel_classes": classes, "cpu_baseline": cpu,
-        "variants": variants, "time_step": time_step, "simulation": simulation,
+        "variants": variants, "time_step": time_step, "simulation": simulation, "other_configs": configs,
     }
     print(json.dumps(out))
 
@@ -347,6 +350,47 @@ def _kernel_sha(kclass):
     f = {"spmv": "spmv.hip", "orth": "krylov.hip"}[kclass]
     p = os.path.join(ROOT, "paper_1606_00548_amd", "csrc", f)
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def other_configs(steps=2):
+    """One Newton step of the small oil-water system (32x32x8, latency
+    regime) and of the first system of the channelised 256x256x64 black-oil
+    10-day step (bandwidth regime), FP64 and mixed precision; each timed
+    step restarts from the same state."""
+    import numpy as np
+    import torch
+    from paper_1606_00548_amd import cprmi, synth
+    out = {}
+    for name, make in (("oil-water 32x32x8", lambda: synth.oil_water_lognormal()),
+                       ("black-oil channelised 256x256x64, first system of the 10-day step",
+                        lambda: synth.black_oil_channelised())):
+        case = make()
+        s = cprmi.Solver.from_case(case)
+        x_old = torch.as_tensor(case["x_old"]).cuda().contiguous()
+        x0 = torch.as_tensor(case["x"]).cuda().contiguous()
+        x = x0.clone()
+        res = {"cells": int(np.prod(case["x"].shape[1:])), "block": int(case["x"].shape[0])}
+        for prec in ("fp64", "mixed"):
+            o = cprmi.default_options(precision=prec)
+
+            def step():
+                x.copy_(x0)
+                _, st = cprmi.newton_step(s, x_old, x, case["dt"], o)
+                return st
+            step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = [step() for _ in range(steps)]
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ok = all(st["status"] == 0 and st["true_rel"] <= 1e-6 for st in sts)
+            res[prec] = {"ms_per_step": 1e3 * (t1 - t0) / steps, "iterations": sts[-1]["iterations"],
+                         "true_rel": sts[-1]["true_rel"], "reached_1e-6": ok}
+        s.close()
+        del x_old, x0, x
+        torch.cuda.empty_cache()
+        out[name] = res
+    return out
 
 
 def cpu_baseline(case):

@@ -14,8 +14,9 @@ to its cited CPR paper:
   * Multigrid: 2x2x2 piecewise-constant aggregation (a grid dimension of 1
     stays 1, coarse size ceil(n/2)), Galerkin A_c = P^T A P, coarsen while a
     level has more than `coarsest` cells, LU solve on the last level;
-    V(1,1) cycle with a zero initial guess, red-black Gauss-Seidel (pre:
-    red then black; post: black then red), prolongation x += alpha P e.
+    V(1,1) cycle (V(pre, post) as an option) with a zero initial guess,
+    red-black Gauss-Seidel (each pre-sweep red then black; each post-sweep
+    black then red), prolongation x += alpha P e.
     Red cells have (i+j+k) even.
   * Full-system stage: block ILU(0) of A~ in red-then-black order.  The
     7-point graph has no triangles, so ILU(0) keeps the off-diagonal blocks
@@ -183,8 +184,10 @@ def from_sparse(M, shape):
     return A
 
 
-def mg_setup(Ap, coarsest=512):
-    """Hierarchy [(A_l, shape_l)]; the last level is factorised by LU."""
+def mg_setup(Ap, coarsest=512, pre=1, post=1):
+    """Hierarchy [(A_l, shape_l)]; the last level is factorised by LU.
+    pre / post: red-black Gauss-Seidel sweeps before and after the coarse
+    correction (V(pre, post))."""
     levels = [Ap]
     while int(np.prod(levels[-1].shape[1:])) > coarsest:
         A = levels[-1]
@@ -194,7 +197,7 @@ def mg_setup(Ap, coarsest=512):
         levels.append(from_sparse(Ac, coarse_shape(shape)))
     last = levels[-1]
     lu = scipy.linalg.lu_factor(to_sparse(last).toarray())
-    return {"levels": levels, "lu": lu}
+    return {"levels": levels, "lu": lu, "pre": pre, "post": post}
 
 
 def gs_half_sweep(A, r, x, col, which):
@@ -208,7 +211,9 @@ def gs_half_sweep(A, r, x, col, which):
 
 
 def vcycle(mg, r, level=0, alpha=1.0):
-    """V(1,1) cycle with a zero initial guess on level `level`."""
+    """V(pre, post) cycle (default V(1,1)) with a zero initial guess on
+    level `level`: each pre-sweep is red then black, each post-sweep black
+    then red."""
     levels = mg["levels"]
     A = levels[level]
     shape = A.shape[1:]
@@ -216,15 +221,17 @@ def vcycle(mg, r, level=0, alpha=1.0):
         return scipy.linalg.lu_solve(mg["lu"], r.ravel()).reshape(shape)
     col = colour(shape)
     x = np.zeros_like(r)
-    gs_half_sweep(A, r, x, col, 0)
-    gs_half_sweep(A, r, x, col, 1)
+    for _ in range(mg.get("pre", 1)):
+        gs_half_sweep(A, r, x, col, 0)
+        gs_half_sweep(A, r, x, col, 1)
     res = r - scalar_spmv(A, x)
     P = prolongator(shape)
     rc = (P.T @ res.ravel()).reshape(coarse_shape(shape))
     ec = vcycle(mg, rc, level + 1, alpha)
     x += alpha * (P @ ec.ravel()).reshape(shape)
-    gs_half_sweep(A, r, x, col, 1)
-    gs_half_sweep(A, r, x, col, 0)
+    for _ in range(mg.get("post", 1)):
+        gs_half_sweep(A, r, x, col, 1)
+        gs_half_sweep(A, r, x, col, 0)
     return x
 
 
@@ -308,18 +315,18 @@ def abf(J):
     return W, At
 
 
-def cpr_setup(J, coarsest=512, decoupling="qimpes"):
+def cpr_setup(J, coarsest=512, decoupling="qimpes", pre=1, post=1):
     """CPR preconditioner data: decoupling (quasi-IMPES weights w and rows R0,
     or ABF blocks W), the decoupled blocks A~, the pressure multigrid on
     A_p = A~[:, 0, 0] and the red-black block ILU(0) of A~."""
     if decoupling == "abf":
         W, At = abf(J)
-        mg = mg_setup(At[:, 0, 0].copy(), coarsest)
+        mg = mg_setup(At[:, 0, 0].copy(), coarsest, pre, post)
         Dinv = ilu_setup(At)
         return {"decoupling": "abf", "W": W, "At": At, "mg": mg, "Dinv": Dinv, "nbad": 0}
     w, R0, nbad = quasi_impes(J)
     At = decoupled_blocks(J, R0)
-    mg = mg_setup(R0[:, 0].copy(), coarsest)
+    mg = mg_setup(R0[:, 0].copy(), coarsest, pre, post)
     Dinv = ilu_setup(At)
     return {"decoupling": "qimpes", "w": w, "R0": R0, "At": At, "mg": mg, "Dinv": Dinv, "nbad": nbad}
 

@@ -120,6 +120,38 @@ def test_vcycle_contracts_on_poisson():
         assert np.linalg.norm(e1) < 0.9 * np.linalg.norm(e)
 
 
+@pytest.mark.parametrize("nu", [1, 2])
+def test_symmetric_vcycle_is_a_symmetric_operator(nu):
+    # With post-smoothing in the reverse colour order of pre-smoothing,
+    # Galerkin coarse operators and an exact coarsest solve, V(nu, nu) on a
+    # symmetric A is a symmetric linear operator (swapping the post-sweep
+    # order, or dropping a sweep, breaks the symmetry); more sweeps contract
+    # more.
+    case = synth.single_phase_uniform(8, 6, 4)
+    case["fluid"] = dict(case["fluid"], c_w=0.0)      # constant density: symmetric TPFA
+    x = synth.initial_state(case["grid"], case["fluid"])
+    rng = np.random.default_rng(5)
+    k = np.exp(rng.standard_normal(case["poro"].shape))
+    _, J = model.assemble(case["grid"], case["fluid"], np.stack([k, k, k]), case["poro"], [], x, x, 1.0)
+    A = J[:, 0, 0]
+    assert np.allclose(dense_from_stencil(A), dense_from_stencil(A).T, rtol=1e-12, atol=0)
+    mg = cpr.mg_setup(A, coarsest=8, pre=nu, post=nu)
+    assert len(mg["levels"]) >= 3
+    n = A[0].size
+    M = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        M[:, c] = cpr.vcycle(mg, e.reshape(A.shape[1:])).ravel()
+    assert np.allclose(M, M.T, rtol=1e-10, atol=1e-12 * np.abs(M).max())
+    Ad = dense_from_stencil(A)
+    rho = np.abs(np.linalg.eigvals(np.eye(n) - M @ Ad)).max()
+    mg1 = cpr.mg_setup(A, coarsest=8)
+    M1 = np.stack([cpr.vcycle(mg1, np.eye(n)[c].reshape(A.shape[1:])).ravel() for c in range(n)], axis=1)
+    rho1 = np.abs(np.linalg.eigvals(np.eye(n) - M1 @ Ad)).max()
+    assert rho < 1.0 and (nu == 1 or rho < rho1)
+
+
 def _textbook_block_ilu0(M, b, order):
     """Dense block ILU(0) (IKJ variant) of M in the given cell order, keeping
     only the blocks of M's sparsity pattern.  Returns L (unit lower, block)

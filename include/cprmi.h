@@ -142,6 +142,8 @@ typedef struct {
   int composition;     /* CPR_COMPOSE_PF (default) or CPR_COMPOSE_FPF        */
   int x0;              /* 1: cpr_gmres_solve starts from the dx passed in
                           (0, default: from zero; BiCGSTAB always from zero) */
+  int mg_pre, mg_post; /* red-black Gauss-Seidel sweeps before / after the
+                          coarse correction, 1..8 (1, 1: V(1,1))            */
 } cpr_options_t;
 
 typedef struct {

@@ -50,7 +50,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("learned", ctypes.c_int), ("restart", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double), ("mg_coarsest", ctypes.c_int),
                 ("mg_alpha", ctypes.c_double), ("decoupling", ctypes.c_int), ("composition", ctypes.c_int),
-                ("x0", ctypes.c_int)]
+                ("x0", ctypes.c_int), ("mg_pre", ctypes.c_int), ("mg_post", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -361,6 +361,7 @@ struct CoarseArgs {
   T* res[MAXLV];
   const double* inv;
   T alpha;
+  int pre, post;             // Gauss-Seidel sweeps before / after the coarse correction
 };
 
 template <typename T>
@@ -373,6 +374,12 @@ __global__ __launch_bounds__(1024) void coarse_cycle_kernel(CoarseArgs<T> a) {
     __syncthreads();
     for (int q = tid; q < F.nh; q += nt) black_pre_cell<T, false>(F, a.A[l], a.r[l], a.x[l], a.res[l], q);
     __syncthreads();
+    for (int k = 1; k < a.pre; ++k) {
+      for (int q = tid; q < F.nh; q += nt) red_cell<T, false>(F, a.A[l], a.r[l], a.x[l], q);
+      __syncthreads();
+      for (int q = tid; q < F.nh; q += nt) black_pre_cell<T, false>(F, a.A[l], a.r[l], a.x[l], a.res[l], q);
+      __syncthreads();
+    }
     for (int tc = tid; tc < C.n; tc += nt)
       restrict_cell<T, false>(F, C, a.A[l], a.r[l], a.x[l], a.res[l], a.r[l + 1], tc);
     __syncthreads();
@@ -403,6 +410,12 @@ __global__ __launch_bounds__(1024) void coarse_cycle_kernel(CoarseArgs<T> a) {
     __syncthreads();
     for (int q = tid; q < F.nh; q += nt) red_cell<T, false>(F, a.A[l], a.r[l], a.x[l], q);
     __syncthreads();
+    for (int k = 1; k < a.post; ++k) {
+      for (int q = tid; q < F.nh; q += nt) black_pre_cell<T, false>(F, a.A[l], a.r[l], a.x[l], a.res[l], q);
+      __syncthreads();
+      for (int q = tid; q < F.nh; q += nt) red_cell<T, false>(F, a.A[l], a.r[l], a.x[l], q);
+      __syncthreads();
+    }
   }
 }
 
@@ -705,6 +718,11 @@ void vcycle(cpr_ctx* ctx) {
     if (l > 0) TIMED(CPR_KCLASS_SMOOTH, (red_zero_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
     TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
                                                                      Pre<T>::x(L), Pre<T>::res(L))));
+    for (int k = 1; k < ctx->opt.mg_pre; ++k) {
+      TIMED(CPR_KCLASS_SMOOTH, (red_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
+      TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
+                                                                       Pre<T>::x(L), Pre<T>::res(L))));
+    }
     restrict4_kernel<T><<<div_up(4L * C.lay.n, 256), 256, 0, s>>>(L.lay, C.lay, Pre<T>::A(L), Pre<T>::r(L),
                                                                   Pre<T>::x(L), Pre<T>::res(L), Pre<T>::r(C));
   }
@@ -721,6 +739,8 @@ void vcycle(cpr_ctx* ctx) {
     }
     a.inv = ctx->cinv;
     a.alpha = alpha;
+    a.pre = ctx->opt.mg_pre;
+    a.post = ctx->opt.mg_post;
     coarse_cycle_kernel<T><<<1, 1024, 0, s>>>(a);
   } else {
     MGLevel& L = ctx->levels.back();
@@ -733,6 +753,11 @@ void vcycle(cpr_ctx* ctx) {
     TIMED(CPR_KCLASS_SMOOTH, (black_post_kernel<T><<<nh, 256, 0, s>>>(L.lay, C.lay, alpha, Pre<T>::A(L),
                                                                       Pre<T>::r(L), Pre<T>::x(C), Pre<T>::x(L))));
     TIMED(CPR_KCLASS_SMOOTH, (red_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
+    for (int k = 1; k < ctx->opt.mg_post; ++k) {
+      TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
+                                                                       Pre<T>::x(L), Pre<T>::res(L))));
+      TIMED(CPR_KCLASS_SMOOTH, (red_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
+    }
   }
 }
 

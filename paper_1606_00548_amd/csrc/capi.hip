@@ -298,6 +298,8 @@ int setup_with_options(cpr_ctx* ctx, const cpr_options_t& opt) {
   if (!(opt.rtol >= 0) || !std::isfinite(opt.rtol)) return set_err(ctx, CPR_EINVAL, "rtol must be >= 0");
   if (opt.mg_coarsest < 1 || opt.mg_coarsest > 4096)
     return set_err(ctx, CPR_EINVAL, "mg_coarsest must be 1..4096");
+  if (opt.mg_pre < 1 || opt.mg_pre > 8 || opt.mg_post < 1 || opt.mg_post > 8)
+    return set_err(ctx, CPR_EINVAL, "mg_pre and mg_post must be 1..8");
   if (opt.precision != CPR_PREC_FP64 && opt.precision != CPR_PREC_MIXED)
     return set_err(ctx, CPR_EINVAL, "unknown precision");
   if (opt.decoupling != CPR_DECOUPLE_QIMPES && opt.decoupling != CPR_DECOUPLE_ABF)
@@ -345,6 +347,8 @@ void cpr_default_options(cpr_options_t* o) {
   o->decoupling = CPR_DECOUPLE_QIMPES;
   o->composition = CPR_COMPOSE_PF;
   o->x0 = 0;
+  o->mg_pre = 1;
+  o->mg_post = 1;
 }
 
 int cpr_create(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, const double* poro,

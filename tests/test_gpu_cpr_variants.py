@@ -179,3 +179,27 @@ def test_abf_singular_block_and_quasi_impes_only_exports():
         s.setup(decoupling="abf")
     assert e.value.code == -4
     s.close()
+
+
+@pytest.mark.parametrize("pre,post", [(2, 2), (1, 3), (3, 1)])
+def test_vcycle_sweep_counts_match_oracle(system, pre, post):
+    # V(pre, post): the multi-block levels and the single-workgroup kernel
+    # of the small levels both repeat their sweeps in the oracle's order
+    name, case, J, b, _ = system
+    from paper_1606_00548_amd import cprmi
+    s = cprmi.Solver.from_case(case)
+    s.import_jacobian(J)
+    s.setup(mg_pre=pre, mg_post=post)
+    pc = cpr.cpr_setup(J, pre=pre, post=post)
+    v = b / np.linalg.norm(b)
+    z = _np(s.precond(_gpu(v)))
+    ref = cpr.cpr_apply(pc, v)
+    assert np.linalg.norm(z - ref) <= 1e-9 * np.linalg.norm(ref)
+    dx, st = s.solve(_gpu(b))
+    xo, so = krylov.fgmres(lambda u: cpr.block_spmv(J, u), lambda u: cpr.cpr_apply(pc, u), b)
+    print(f"[variants] {name} V({pre},{post}): FGMRES {st['iterations']} iterations (oracle {so['iterations']})")
+    assert st["status"] == 0 and st["iterations"] == so["iterations"]
+    assert np.linalg.norm(_np(dx) - xo) <= 1e-8 * np.linalg.norm(xo)
+    with pytest.raises(cprmi.CPRError):
+        s.setup(mg_pre=0)
+    s.close()

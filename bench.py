@@ -91,15 +91,15 @@ def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision, levels=None
         # red-black Gauss-Seidel half-sweeps on the levels smoothed by
         # multi-block kernels (those above the first level of <= 4096 cells):
         # black pre-sweep 11 values per black cell (7 stencil, r, x, res, red x),
-        # black post-sweep 10 + coarse correction n/8, red sweep 10, red
-        # zero-guess sweep 3 (levels below the fine one; the fine one is fused
-        # with the decoupling)
+        # black post-sweep 10 + coarse correction n/8, red sweep 10 (the
+        # zero-guess red sweeps ride with the decoupling on the fine level and
+        # with the restriction on the others)
         down = next((l for l, nl in enumerate(levels) if nl <= 4096), len(levels) - 1)
         per, launches = 0, 0
         for l in range(down):
             nl = levels[l]
-            per += (44 + 41 + 40) * nl + (12 * nl if l > 0 else 0)
-            launches += 3 + (1 if l > 0 else 0)
+            per += (44 + 41 + 40) * nl
+            launches += 3
         return its * per, its * launches
     if kclass == "ilu":
         # stage-2 residual and red-black block ILU(0) sweeps, per cell of a

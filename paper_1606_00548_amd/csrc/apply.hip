@@ -278,13 +278,6 @@ __global__ __launch_bounds__(256) void decouple_full_kernel(int n, int nh, const
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void red_zero_kernel(Lay L, const T* __restrict__ A, const T* __restrict__ r,
-                                                       T* __restrict__ x) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < L.nh) red_zero_cell(A, r, x, q);
-}
-
-template <typename T>
 __global__ __launch_bounds__(256) void black_pre_kernel(Lay L, const T* __restrict__ A, const T* __restrict__ r,
                                                         T* __restrict__ x, T* __restrict__ res) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -294,10 +287,13 @@ __global__ __launch_bounds__(256) void black_pre_kernel(Lay L, const T* __restri
 // Restriction with four threads per coarse cell: thread (tc, q, s) sums the
 // two fine cells (2ci, 2ci+1) of fine row (2cj+q, 2ck+s); the four partials
 // of a coarse cell sit in adjacent lanes and are combined in a fixed order.
+// If xc is given, the coarse level's zero-guess red sweep is done here too:
+// a red coarse cell stores x = r / a_0 as soon as its r is known.
 template <typename T>
 __global__ __launch_bounds__(256) void restrict4_kernel(Lay F, Lay C, const T* __restrict__ A,
                                                         const T* __restrict__ r, const T* __restrict__ x,
-                                                        const T* __restrict__ res, T* __restrict__ rc) {
+                                                        const T* __restrict__ res, T* __restrict__ rc,
+                                                        const T* __restrict__ Ac, T* __restrict__ xc) {
   int g = blockIdx.x * blockDim.x + threadIdx.x;
   int tc = g >> 2, sub = g & 3;
   T acc = 0;
@@ -319,7 +315,10 @@ __global__ __launch_bounds__(256) void restrict4_kernel(Lay F, Lay C, const T* _
   }
   acc += __shfl_down(acc, 2, 4);
   acc += __shfl_down(acc, 1, 4);
-  if (tc < C.n && sub == 0) rc[tc] = acc;
+  if (tc < C.n && sub == 0) {
+    rc[tc] = acc;
+    if (xc && tc < C.nh) red_zero_cell(Ac, rc, xc, tc);
+  }
 }
 
 template <typename T>
@@ -715,7 +714,8 @@ void vcycle(cpr_ctx* ctx) {
     MGLevel& L = ctx->levels[l];
     MGLevel& C = ctx->levels[l + 1];
     int nh = div_up(L.lay.nh, 256);
-    if (l > 0) TIMED(CPR_KCLASS_SMOOTH, (red_zero_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
+    // level 0's zero-guess red sweep is fused into the decoupling kernel and
+    // that of the coarser multi-block levels into the restriction above them
     TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
                                                                      Pre<T>::x(L), Pre<T>::res(L))));
     for (int k = 1; k < ctx->opt.mg_pre; ++k) {
@@ -723,8 +723,10 @@ void vcycle(cpr_ctx* ctx) {
       TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
                                                                        Pre<T>::x(L), Pre<T>::res(L))));
     }
-    restrict4_kernel<T><<<div_up(4L * C.lay.n, 256), 256, 0, s>>>(L.lay, C.lay, Pre<T>::A(L), Pre<T>::r(L),
-                                                                  Pre<T>::x(L), Pre<T>::res(L), Pre<T>::r(C));
+    const bool next_multi = l + 1 < down;
+    restrict4_kernel<T><<<div_up(4L * C.lay.n, 256), 256, 0, s>>>(
+        L.lay, C.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L), Pre<T>::res(L), Pre<T>::r(C),
+        next_multi ? Pre<T>::A(C) : nullptr, next_multi ? Pre<T>::x(C) : nullptr);
   }
   if (fuse < nl) {
     CoarseArgs<T> a;

@@ -9,6 +9,11 @@
 
 namespace {
 
+// 3x3 systems up to this many cells take the one-wave kernel below: on
+// MI355X it streams the 128x128x32 black-oil matrix about 15 % faster,
+// while the kernel above is faster on the 4.2 M-cell grids.
+constexpr int SPMV_SMALL_N = 1 << 20;
+
 // Branch-free: all 7 b^2 matrix loads are issued up front (blocks towards
 // missing neighbours are stored as zeros), missing neighbours read the cell
 // itself and are masked to zero.  The matrix is streamed once per call, so
@@ -59,6 +64,53 @@ __global__ __launch_bounds__(256) void spmv_kernel(Lay L, const double* __restri
   for (int r = 0; r < B; ++r) y[r * n + t] = rhs ? rhs[r * n + t] - acc[r] : acc[r];
 }
 
+// The same product for systems up to SPMV_SMALL_N cells, one wave per
+// workgroup.  Written as a device function, the loads come out interleaved
+// with the FMAs: half the registers of the kernel above, eight waves per
+// SIMD and a finer tail.  Sums are formed in the same order as above.
+template <int B>
+__device__ inline void spmv_cell(const Lay& L, int t, const double* __restrict__ A, const double* __restrict__ x,
+                                 double* __restrict__ y, const double* __restrict__ rhs) {
+  const size_t n = L.n;
+  CsCell cc = cs_decode(L, t);
+  int nbr[7];
+  bool ok[7];
+  cs_nbrs(L, t, cc, nbr, ok);
+  double acc[B];
+#pragma unroll
+  for (int r = 0; r < B; ++r) acc[r] = 0.0;
+  double a[7][B][B];
+#pragma unroll
+  for (int d = 0; d < 7; ++d)
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < B; ++c) a[d][r][c] = __builtin_nontemporal_load(A + ((size_t)(d * B + r) * B + c) * n + t);
+#pragma unroll
+  for (int d = 0; d < 7; ++d) {
+    double xv[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      double v = x[c * n + nbr[d]];
+      xv[c] = ok[d] ? v : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < B; ++c) acc[r] += a[d][r][c] * xv[c];
+  }
+#pragma unroll
+  for (int r = 0; r < B; ++r) y[r * n + t] = rhs ? rhs[r * n + t] - acc[r] : acc[r];
+}
+
+template <int B>
+__global__ __launch_bounds__(64) void spmv_small_kernel(Lay L, const double* __restrict__ A,
+                                                        const double* __restrict__ x, double* __restrict__ y,
+                                                        const double* __restrict__ rhs) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < L.n) spmv_cell<B>(L, t, A, x, y, rhs);
+}
+
 }  // namespace
 
 void launch_spmv(int b, const Lay& L, const double* A, const double* x, double* y,
@@ -68,6 +120,8 @@ void launch_spmv(int b, const Lay& L, const double* A, const double* x, double* 
     spmv_kernel<1><<<nb, 256, 0, s>>>(L, A, x, y, rhs);
   else if (b == 2)
     spmv_kernel<2><<<nb, 256, 0, s>>>(L, A, x, y, rhs);
+  else if (L.n <= SPMV_SMALL_N)
+    spmv_small_kernel<3><<<div_up(L.n, 64), 64, 0, s>>>(L, A, x, y, rhs);
   else
     spmv_kernel<3><<<nb, 256, 0, s>>>(L, A, x, y, rhs);
 }

@@ -201,11 +201,16 @@ def main():
             forms.append(("fpf mixed+learned", dict(precision="mixed", composition="fpf", learned=1), "fgmres"))
             forms.append(("bicgstab fpf mixed+learned", dict(precision="mixed", composition="fpf", learned=1),
                           "bicgstab"))
-        # more smoothing sweeps per multigrid level: V(pre, post)
-        forms.append(("fp64 V(2,2)", dict(precision="fp64", mg_pre=2, mg_post=2), "fgmres"))
-        forms.append(("mixed V(2,2)", dict(precision="mixed", mg_pre=2, mg_post=2), "fgmres"))
+        # a tuned cycle: more smoothing sweeps per level, V(pre, post), and an
+        # over-correction x += alpha P e with alpha = 1.25
+        tuned = dict(mg_pre=2, mg_post=2)
+        forms.append(("fp64 V(2,2)", dict(precision="fp64", **tuned), "fgmres"))
+        forms.append(("mixed V(2,2)", dict(precision="mixed", **tuned), "fgmres"))
+        tuned["mg_alpha"] = 1.25
+        forms.append(("fp64 V(2,2) alpha 1.25", dict(precision="fp64", **tuned), "fgmres"))
+        forms.append(("mixed V(2,2) alpha 1.25", dict(precision="mixed", **tuned), "fgmres"))
         if os.path.exists(wfile):
-            forms.append(("mixed+learned V(1,2)", dict(precision="mixed", learned=1, mg_post=2), "fgmres"))
+            forms.append(("mixed+learned V(2,2) alpha 1.25", dict(precision="mixed", learned=1, **tuned), "fgmres"))
         for name, kw, kry in forms:
             sp, sts, _ = timed(cprmi.default_options(**kw), krylov=kry)
             variants[name] = {"s_per_step": sp, "krylov": kry, "krylov_iterations": sts[-1]["iterations"],

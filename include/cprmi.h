@@ -137,7 +137,7 @@ typedef struct {
   int max_iter;        /* total Arnoldi iterations (default 300)            */
   double rtol;         /* stop when ||b - A dx||_2 <= rtol ||b||_2 (1e-6)    */
   int mg_coarsest;     /* coarsen while a level has more cells (512, <= 4096) */
-  double mg_alpha;     /* coarse-correction scaling (1.0)                    */
+  double mg_alpha;     /* coarse-correction scaling x += alpha P e (1.0, finite) */
   int decoupling;      /* CPR_DECOUPLE_QIMPES (default) or CPR_DECOUPLE_ABF  */
   int composition;     /* CPR_COMPOSE_PF (default) or CPR_COMPOSE_FPF        */
   int x0;              /* 1: cpr_gmres_solve starts from the dx passed in

@@ -33,6 +33,9 @@ namespace {
 constexpr int FUSE_MAX = 4096;   // cells of the first level handled by the fused kernel
 constexpr int DENSE_FUSED_MAX = 1024;
 constexpr int MAXLV = 16;
+// Threads per workgroup of the per-cell kernels (sweeps, restriction,
+// decoupling): one wave per workgroup streams their planes faster than four.
+constexpr int SB = 64;
 
 template <typename T>
 struct Pre;
@@ -713,18 +716,18 @@ void vcycle(cpr_ctx* ctx) {
   for (int l = 0; l < down; ++l) {
     MGLevel& L = ctx->levels[l];
     MGLevel& C = ctx->levels[l + 1];
-    int nh = div_up(L.lay.nh, 256);
+    int nh = div_up(L.lay.nh, SB);
     // level 0's zero-guess red sweep is fused into the decoupling kernel and
     // that of the coarser multi-block levels into the restriction above them
-    TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
+    TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, SB, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
                                                                      Pre<T>::x(L), Pre<T>::res(L))));
     for (int k = 1; k < ctx->opt.mg_pre; ++k) {
-      TIMED(CPR_KCLASS_SMOOTH, (red_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
-      TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
+      TIMED(CPR_KCLASS_SMOOTH, (red_kernel<T><<<nh, SB, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
+      TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, SB, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
                                                                        Pre<T>::x(L), Pre<T>::res(L))));
     }
     const bool next_multi = l + 1 < down;
-    restrict4_kernel<T><<<div_up(4L * C.lay.n, 256), 256, 0, s>>>(
+    restrict4_kernel<T><<<div_up(4L * C.lay.n, SB), SB, 0, s>>>(
         L.lay, C.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L), Pre<T>::res(L), Pre<T>::r(C),
         next_multi ? Pre<T>::A(C) : nullptr, next_multi ? Pre<T>::x(C) : nullptr);
   }
@@ -751,14 +754,14 @@ void vcycle(cpr_ctx* ctx) {
   for (int l = down - 1; l >= 0; --l) {
     MGLevel& L = ctx->levels[l];
     MGLevel& C = ctx->levels[l + 1];
-    int nh = div_up(L.lay.nh, 256);
-    TIMED(CPR_KCLASS_SMOOTH, (black_post_kernel<T><<<nh, 256, 0, s>>>(L.lay, C.lay, alpha, Pre<T>::A(L),
+    int nh = div_up(L.lay.nh, SB);
+    TIMED(CPR_KCLASS_SMOOTH, (black_post_kernel<T><<<nh, SB, 0, s>>>(L.lay, C.lay, alpha, Pre<T>::A(L),
                                                                       Pre<T>::r(L), Pre<T>::x(C), Pre<T>::x(L))));
-    TIMED(CPR_KCLASS_SMOOTH, (red_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
+    TIMED(CPR_KCLASS_SMOOTH, (red_kernel<T><<<nh, SB, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
     for (int k = 1; k < ctx->opt.mg_post; ++k) {
-      TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
+      TIMED(CPR_KCLASS_SMOOTH, (black_pre_kernel<T><<<nh, SB, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L),
                                                                        Pre<T>::x(L), Pre<T>::res(L))));
-      TIMED(CPR_KCLASS_SMOOTH, (red_kernel<T><<<nh, 256, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
+      TIMED(CPR_KCLASS_SMOOTH, (red_kernel<T><<<nh, SB, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
     }
   }
 }
@@ -774,10 +777,10 @@ void stage2(cpr_ctx* ctx, const VT* vr, const T* z1, double* z) {
   const T* R0 = Pre<T>::R0(ctx);
   const T* Dinv = Pre<T>::Dinv(ctx);
   T* Y = Pre<T>::Y(ctx);
-  int nh = div_up(L.nh, 256);
-  TIMED(CPR_KCLASS_ILU, (stage2_red_fwd_kernel<B, T, VT><<<nh, 256, 0, s>>>(L, J, R0, Dinv, vr, rp, dp, Y)));
-  TIMED(CPR_KCLASS_ILU, (stage2_black_kernel<B, T, VT><<<nh, 256, 0, s>>>(L, J, R0, Dinv, vr, rp, dp, Y, z1, z)));
-  TIMED(CPR_KCLASS_ILU, (stage2_red_bwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, dp, Y, z1, z)));
+  int nh = div_up(L.nh, SB);
+  TIMED(CPR_KCLASS_ILU, (stage2_red_fwd_kernel<B, T, VT><<<nh, SB, 0, s>>>(L, J, R0, Dinv, vr, rp, dp, Y)));
+  TIMED(CPR_KCLASS_ILU, (stage2_black_kernel<B, T, VT><<<nh, SB, 0, s>>>(L, J, R0, Dinv, vr, rp, dp, Y, z1, z)));
+  TIMED(CPR_KCLASS_ILU, (stage2_red_bwd_kernel<B, T><<<nh, SB, 0, s>>>(L, J, R0, Dinv, dp, Y, z1, z)));
 }
 
 template <int B, typename T, bool ABF, bool FPF>
@@ -793,13 +796,13 @@ void apply_variant(cpr_ctx* ctx, const double* vin, double* v, const double* nrm
   const T* R0 = Pre<T>::R0(ctx);
   const T* Dinv = Pre<T>::Dinv(ctx);
   const double* w = ABF ? ctx->Wabf : ctx->w;
-  decouple_full_kernel<B, T, ABF, FPF><<<div_up(L.n, 256), 256, 0, s>>>(L.n, L.nh, w, vin, v, nrm2, Pre<T>::A(L0),
+  decouple_full_kernel<B, T, ABF, FPF><<<div_up(L.n, SB), SB, 0, s>>>(L.n, L.nh, w, vin, v, nrm2, Pre<T>::A(L0),
                                                                         Dinv, rp, x0, Rt, Z1);
   if (FPF) {
-    int nh = div_up(L.nh, 256);
-    TIMED(CPR_KCLASS_ILU, (fpf_black_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, Rt, Z1)));
-    TIMED(CPR_KCLASS_ILU, (fpf_red_bwd_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Dinv, Z1, Rt, rp, x0)));
-    TIMED(CPR_KCLASS_ILU, (fpf_resid_kernel<B, T><<<nh, 256, 0, s>>>(L, J, R0, Z1, Rt, rp)));
+    int nh = div_up(L.nh, SB);
+    TIMED(CPR_KCLASS_ILU, (fpf_black_kernel<B, T><<<nh, SB, 0, s>>>(L, J, R0, Dinv, Rt, Z1)));
+    TIMED(CPR_KCLASS_ILU, (fpf_red_bwd_kernel<B, T><<<nh, SB, 0, s>>>(L, J, R0, Dinv, Z1, Rt, rp, x0)));
+    TIMED(CPR_KCLASS_ILU, (fpf_resid_kernel<B, T><<<nh, SB, 0, s>>>(L, J, R0, Z1, Rt, rp)));
   }
   vcycle<T>(ctx);
   if (ctx->opt.learned) learned_stage(ctx);
@@ -816,7 +819,7 @@ void apply_impl(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, 
   hipStream_t s = ctx->stream;
   const Lay& L = ctx->lay;
   MGLevel& L0 = ctx->levels[0];
-  decouple_red_kernel<B, T><<<div_up(L.n, 256), 256, 0, s>>>(L.n, L.nh, ctx->w, vin, v, nrm2, Pre<T>::A(L0),
+  decouple_red_kernel<B, T><<<div_up(L.n, SB), SB, 0, s>>>(L.n, L.nh, ctx->w, vin, v, nrm2, Pre<T>::A(L0),
                                                             Pre<T>::r(L0), Pre<T>::x(L0));
   vcycle<T>(ctx);
   if (ctx->opt.learned) learned_stage(ctx);
@@ -869,13 +872,13 @@ void precond_pressure_stage(cpr_ctx* ctx, const double* v) {
   const Lay& L = ctx->lay;
   MGLevel& L0 = ctx->levels[0];
   if (ctx->b == 1)
-    decouple_red_kernel<1, double><<<div_up(L.n, 256), 256, 0, ctx->stream>>>(L.n, L.nh, ctx->w, v, nullptr, nullptr,
+    decouple_red_kernel<1, double><<<div_up(L.n, SB), SB, 0, ctx->stream>>>(L.n, L.nh, ctx->w, v, nullptr, nullptr,
                                                                                L0.A, L0.r, L0.x);
   else if (ctx->b == 2)
-    decouple_red_kernel<2, double><<<div_up(L.n, 256), 256, 0, ctx->stream>>>(L.n, L.nh, ctx->w, v, nullptr, nullptr,
+    decouple_red_kernel<2, double><<<div_up(L.n, SB), SB, 0, ctx->stream>>>(L.n, L.nh, ctx->w, v, nullptr, nullptr,
                                                                                L0.A, L0.r, L0.x);
   else
-    decouple_red_kernel<3, double><<<div_up(L.n, 256), 256, 0, ctx->stream>>>(L.n, L.nh, ctx->w, v, nullptr, nullptr,
+    decouple_red_kernel<3, double><<<div_up(L.n, SB), SB, 0, ctx->stream>>>(L.n, L.nh, ctx->w, v, nullptr, nullptr,
                                                                                L0.A, L0.r, L0.x);
   vcycle<double>(ctx);
 }

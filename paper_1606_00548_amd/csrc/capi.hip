@@ -300,6 +300,7 @@ int setup_with_options(cpr_ctx* ctx, const cpr_options_t& opt) {
     return set_err(ctx, CPR_EINVAL, "mg_coarsest must be 1..4096");
   if (opt.mg_pre < 1 || opt.mg_pre > 8 || opt.mg_post < 1 || opt.mg_post > 8)
     return set_err(ctx, CPR_EINVAL, "mg_pre and mg_post must be 1..8");
+  if (!std::isfinite(opt.mg_alpha)) return set_err(ctx, CPR_EINVAL, "mg_alpha must be finite");
   if (opt.precision != CPR_PREC_FP64 && opt.precision != CPR_PREC_MIXED)
     return set_err(ctx, CPR_EINVAL, "unknown precision");
   if (opt.decoupling != CPR_DECOUPLE_QIMPES && opt.decoupling != CPR_DECOUPLE_ABF)

@@ -107,10 +107,12 @@ __global__ __launch_bounds__(KB) void orth_kernel(long len, int nv, const double
 }
 
 // out[k] (+)= sum_b part[k][b], one block per k, fixed order; host (pinned
-// host memory, optional) receives the same value.
+// host memory, optional) receives the same value and bare (optional) the
+// sum without the added term.
 __global__ __launch_bounds__(KB) void reduce_kernel(const double* __restrict__ part, int nblk,
                                                     double* __restrict__ out, const double* __restrict__ add,
-                                                    double* __restrict__ host = nullptr) {
+                                                    double* __restrict__ host = nullptr,
+                                                    double* __restrict__ bare = nullptr) {
   __shared__ double sh[CHUNK * (KB / 64)];
   __shared__ double tot[CHUNK];
   int k = blockIdx.x;
@@ -125,6 +127,7 @@ __global__ __launch_bounds__(KB) void reduce_kernel(const double* __restrict__ p
     const double v = tot[0] + (add ? add[k] : 0.0);
     out[k] = v;
     if (host) host[k] = v;
+    if (bare) bare[k] = tot[0];
   }
 }
 
@@ -482,8 +485,8 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
       reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd, nullptr);
       // w -= V h1 ; h2 = V^T w
       orth_pass(ctx, len, nv, w, hd, 0);
-      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd, slot);   // h = h1 + h2
-      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 192, nullptr);   // h2 alone
+      // h = h1 + h2 (device and host) and h2 alone
+      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd, slot, hd + 192);
       // w -= V h2 ; ||w||^2
       orth_pass(ctx, len, nv, w, hd + 192, 1);
       reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr, slot + 64);

@@ -120,6 +120,58 @@ def test_vcycle_contracts_on_poisson():
         assert np.linalg.norm(e1) < 0.9 * np.linalg.norm(e)
 
 
+def test_vcycle_without_coarse_correction_is_red_black_gauss_seidel():
+    # alpha = 0 leaves only the smoothing: from x = 0, pointwise Gauss-Seidel
+    # over the red cells, the black cells (pre-sweep), then the black and the
+    # red cells (post-sweep), done here one cell at a time on the dense matrix
+    _, J, b = _system(lambda: synth.oil_water_lognormal(6, 4, 4, seed=44))
+    A = J[:, 0, 0]
+    mg = cpr.mg_setup(A, coarsest=8)
+    assert len(mg["levels"]) >= 2
+    r = b[0]
+    x = cpr.vcycle(mg, r, alpha=0.0)
+    M = dense_from_stencil(A)
+    col = cpr.colour(r.shape).ravel()
+    rr = r.ravel()
+    y = np.zeros_like(rr)
+    for which in (0, 1, 1, 0):
+        for i in np.flatnonzero(col == which):
+            y[i] = (rr[i] - (M[i] @ y - M[i, i] * y[i])) / M[i, i]
+    assert np.allclose(x.ravel(), y, rtol=1e-12, atol=1e-14 * np.abs(y).max())
+    assert not np.allclose(cpr.vcycle(mg, r), x, rtol=1e-3)
+
+
+def test_coarse_correction_scaling_is_affine_on_two_levels():
+    # two levels with an exact coarse solve: the cycle is affine in alpha,
+    # x(alpha) = x(0) + alpha (x(1) - x(0)), alpha = 1 is the default cycle,
+    # and x(1) - x(0) is the post-smoothing's linear part applied to the
+    # prolongated exact coarse correction P A_c^-1 P^T (r - A x_pre)
+    _, J, b = _system(lambda: synth.oil_water_lognormal(8, 6, 4, seed=45))
+    A = J[:, 0, 0]
+    mg = cpr.mg_setup(A, coarsest=100)
+    assert len(mg["levels"]) == 2
+    r = b[0]
+    x0, x1, xa = (cpr.vcycle(mg, r, alpha=a) for a in (0.0, 1.0, 1.25))
+    assert np.array_equal(cpr.vcycle(mg, r), x1)
+    scale = np.abs(x1).max()
+    assert np.allclose(xa, x0 + 1.25 * (x1 - x0), rtol=0, atol=1e-11 * scale)
+    # the coarse correction from the dense matrices
+    M = dense_from_stencil(A)
+    col = cpr.colour(r.shape).ravel()
+    P = cpr.prolongator(r.shape).toarray()
+    xp = np.zeros(r.size)
+    for which in (0, 1):
+        for i in np.flatnonzero(col == which):
+            xp[i] = (r.ravel()[i] - (M[i] @ xp - M[i, i] * xp[i])) / M[i, i]
+    e = P @ np.linalg.solve(P.T @ M @ P, P.T @ (r.ravel() - M @ xp))
+    # post-sweep (black then red) acting on a correction, right-hand side 0
+    d = e.copy()
+    for which in (1, 0):
+        for i in np.flatnonzero(col == which):
+            d[i] = -(M[i] @ d - M[i, i] * d[i]) / M[i, i]
+    assert np.allclose((x1 - x0).ravel(), d, rtol=0, atol=1e-10 * scale)
+
+
 @pytest.mark.parametrize("nu", [1, 2])
 def test_symmetric_vcycle_is_a_symmetric_operator(nu):
     # With post-smoothing in the reverse colour order of pre-smoothing,

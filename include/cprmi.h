@@ -144,6 +144,10 @@ typedef struct {
                           (0, default: from zero; BiCGSTAB always from zero) */
   int mg_pre, mg_post; /* red-black Gauss-Seidel sweeps before / after the
                           coarse correction, 1..8 (1, 1: V(1,1))            */
+  double stall_ratio;  /* MIXED, FGMRES: when a restart cycle ends with the
+                          true residual above stall_ratio times the one it
+                          started from, the remaining cycles apply the FP64
+                          preconditioner (1.0: no decrease; <= 0: never) */
 } cpr_options_t;
 
 typedef struct {
@@ -156,6 +160,9 @@ typedef struct {
   double bnorm;        /* ||b||_2                                            */
   double est_rel;      /* GMRES estimate of ||b - A dx|| / ||b|| at the end  */
   double true_rel;     /* recomputed ||b - A dx|| / ||b||                    */
+  int fp64_fallback;   /* MIXED: restart cycles run with the FP32
+                          preconditioner before the FP64 one took over
+                          (0: it never did)                                 */
 } cpr_stats_t;
 
 typedef struct cpr_ctx cpr_ctx_t;

@@ -50,7 +50,8 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("learned", ctypes.c_int), ("restart", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double), ("mg_coarsest", ctypes.c_int),
                 ("mg_alpha", ctypes.c_double), ("decoupling", ctypes.c_int), ("composition", ctypes.c_int),
-                ("x0", ctypes.c_int), ("mg_pre", ctypes.c_int), ("mg_post", ctypes.c_int)]
+                ("x0", ctypes.c_int), ("mg_pre", ctypes.c_int), ("mg_post", ctypes.c_int),
+                ("stall_ratio", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -58,7 +59,7 @@ class Stats(ctypes.Structure):
                 ("mg_levels", ctypes.c_int), ("qimpes_fallback", ctypes.c_int),
                 ("nn_accepted", ctypes.c_int), ("nn_rejected", ctypes.c_int),
                 ("bnorm", ctypes.c_double), ("est_rel", ctypes.c_double),
-                ("true_rel", ctypes.c_double)]
+                ("true_rel", ctypes.c_double), ("fp64_fallback", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -884,7 +884,7 @@ void precond_pressure_stage(cpr_ctx* ctx, const double* v) {
 }
 
 void precond_apply(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, double* z) {
-  bool mixed = ctx->opt.precision == CPR_PREC_MIXED;
+  const bool mixed = precond_fp32(ctx);
   if (ctx->b == 1) {
     if (mixed) apply_impl<1, float>(ctx, vin, v, nrm2, z); else apply_impl<1, double>(ctx, vin, v, nrm2, z);
   } else if (ctx->b == 2) {

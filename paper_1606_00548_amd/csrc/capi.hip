@@ -301,6 +301,7 @@ int setup_with_options(cpr_ctx* ctx, const cpr_options_t& opt) {
   if (opt.mg_pre < 1 || opt.mg_pre > 8 || opt.mg_post < 1 || opt.mg_post > 8)
     return set_err(ctx, CPR_EINVAL, "mg_pre and mg_post must be 1..8");
   if (!std::isfinite(opt.mg_alpha)) return set_err(ctx, CPR_EINVAL, "mg_alpha must be finite");
+  if (std::isnan(opt.stall_ratio)) return set_err(ctx, CPR_EINVAL, "stall_ratio must not be NaN");
   if (opt.precision != CPR_PREC_FP64 && opt.precision != CPR_PREC_MIXED)
     return set_err(ctx, CPR_EINVAL, "unknown precision");
   if (opt.decoupling != CPR_DECOUPLE_QIMPES && opt.decoupling != CPR_DECOUPLE_ABF)
@@ -345,6 +346,7 @@ void cpr_default_options(cpr_options_t* o) {
   o->rtol = 1e-6;
   o->mg_coarsest = 512;
   o->mg_alpha = 1.0;
+  o->stall_ratio = 1.0;
   o->decoupling = CPR_DECOUPLE_QIMPES;
   o->composition = CPR_COMPOSE_PF;
   o->x0 = 0;

@@ -188,6 +188,9 @@ struct cpr_ctx {
   hipStream_t aux = nullptr;
   hipEvent_t ev_q = nullptr, ev_rap = nullptr, ev_gj = nullptr;
   hipEvent_t ev_iter[2] = {nullptr, nullptr};   // completion of Arnoldi steps (even, odd)
+  // set by FGMRES when a mixed-precision restart cycle stalls: the rest of
+  // that solve applies the FP64 preconditioner
+  bool fp64_now = false;
   cpr_grid_t grid;
   FluidDev fl;
   int b = 0;
@@ -355,6 +358,9 @@ int time_step(cpr_ctx* ctx, const double* xold_cs, double* x_cs, double dt_days,
               const cpr_newton_options_t& no, cpr_newton_stats_t* st);
 
 // krylov.hip
+// The preconditioner runs in FP32: MIXED precision and no FP64 fallback.
+inline bool precond_fp32(const cpr_ctx* c) { return c->opt.precision == CPR_PREC_MIXED && !c->fp64_now; }
+
 int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st);
 int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st);
 void launch_newton_update(int b, int n, int nrate, double pb_min, double* x, const double* dx, hipStream_t s);

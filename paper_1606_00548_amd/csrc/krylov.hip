@@ -422,6 +422,12 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
   cpr_stats_t S = {};
   S.mg_levels = (int)ctx->levels.size();
   S.qimpes_fallback = ctx->qimpes_bad;
+  // the FP64 fallback lasts for this solve only, whichever way it ends
+  struct FallbackReset {
+    cpr_ctx* c;
+    ~FallbackReset() { c->fp64_now = false; }
+  } fallback_reset{ctx};
+  ctx->fp64_now = false;
 
   const bool from_x0 = ctx->opt.x0 != 0;
   if (!from_x0) zero_kernel<<<eb, 256, 0, s>>>(len, x);
@@ -448,6 +454,7 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), col(m + 1);
   int its = 0;
   int result = CPR_NOT_CONVERGED;
+  double beta_start = 0.0;   // true residual at the start of the last cycle
   double* hd = ctx->hdev;  // h1 [0,64), h1+h2 [64,128), ||w||^2 [128], h2 [192,256), y [256,320)
   while (true) {
     double rr;
@@ -461,6 +468,16 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     }
     if (beta <= rtol * bnorm) { result = CPR_OK; break; }
     if (its >= max_iter) break;
+    // mixed precision: a restart cycle that left the true residual above
+    // stall_ratio times the one it started from hands the remaining cycles
+    // to the FP64 preconditioner (FGMRES is flexible, so the change of
+    // preconditioner between cycles needs nothing else)
+    if (S.cycles > 0 && ctx->opt.precision == CPR_PREC_MIXED && !ctx->fp64_now && ctx->opt.stall_ratio > 0 &&
+        beta > ctx->opt.stall_ratio * beta_start) {
+      ctx->fp64_now = true;
+      S.fp64_fallback = S.cycles;
+    }
+    beta_start = beta;
     scale_kernel<<<eb, 256, 0, s>>>(len, beta, r, ctx->V);
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);

@@ -300,7 +300,7 @@ void learned_discard_last(cpr_ctx* ctx) {
 
 int learned_stage(cpr_ctx* ctx) {
   MGLevel& L0 = ctx->levels[0];
-  if (ctx->opt.precision == CPR_PREC_MIXED) return learned_stage_t<float>(ctx, L0.rf, L0.xf);
+  if (precond_fp32(ctx)) return learned_stage_t<float>(ctx, L0.rf, L0.xf);
   return learned_stage_t<double>(ctx, L0.r, L0.x);
 }
 

@@ -312,6 +312,13 @@ typedef struct {
   int cuts, total_newton, total_linear;   /* sums over every attempt          */
   double t_reached;            /* days                                        */
   double dts[CPR_SIM_HIST];    /* step sizes taken (first 256)                */
+  double seconds;              /* wall time of the call (host clock)          */
+  /* per accepted step (first 256), every attempt of the step included: the
+     columns of the paper's result tables (Sec. 4) step by step */
+  int step_newton[CPR_SIM_HIST];
+  int step_linear[CPR_SIM_HIST];
+  int step_cuts[CPR_SIM_HIST];
+  double step_seconds[CPR_SIM_HIST];
 } cpr_sim_stats_t;
 
 /* Backward-Euler time stepping over [0, t_end_days] from x0 (device, [b][n],

@@ -217,12 +217,14 @@ def simulate(grid, fluid, perm, poro, wells, x0, t_end, dt0, dt_max, growth=2.0,
     grows by `growth` up to dt_max, after a cut it stays at the step taken;
     the last step is shortened to end at t_end.  Returns (x, stats) with the
     number of steps, the sums of cuts, Newton and linear iterations over
-    every attempt, the step sizes taken, and whether t_end was reached."""
+    every attempt, the step sizes taken, the same counts per accepted step
+    (its cuts included), and whether t_end was reached."""
     x = x0.copy()
     t = 0.0
     dt = float(dt0)
     bhp = step_kw.pop("bhp_old", None)
-    st = {"steps": 0, "cuts": 0, "total_newton": 0, "total_linear": 0, "dts": [], "completed": False}
+    st = {"steps": 0, "cuts": 0, "total_newton": 0, "total_linear": 0, "dts": [], "completed": False,
+          "step_newton": [], "step_linear": [], "step_cuts": []}
     while t < t_end:
         h = min(dt, t_end - t)
         x_new, s = time_step(grid, fluid, perm, poro, wells, x, h, bhp_old=bhp, **step_kw)
@@ -236,6 +238,9 @@ def simulate(grid, fluid, perm, poro, wells, x0, t_end, dt0, dt_max, growth=2.0,
         st["bhp"] = bhp
         st["steps"] += 1
         st["dts"].append(s["dt_taken"])
+        st["step_newton"].append(s["total_newton"])
+        st["step_linear"].append(s["total_linear"])
+        st["step_cuts"].append(s["cuts"])
         t = t + s["dt_taken"]
         dt = min(growth * s["dt_taken"], dt_max) if s["cuts"] == 0 else s["dt_taken"]
     st["completed"] = True

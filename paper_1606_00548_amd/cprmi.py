@@ -8,6 +8,7 @@ The library must have been built (`python -m paper_1606_00548_amd.build`);
 without it every entry point raises.
 """
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -98,12 +99,44 @@ SIM_HIST = 256
 class SimStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int), ("steps", ctypes.c_int), ("cuts", ctypes.c_int),
                 ("total_newton", ctypes.c_int), ("total_linear", ctypes.c_int), ("t_reached", ctypes.c_double),
-                ("dts", ctypes.c_double * SIM_HIST)]
+                ("dts", ctypes.c_double * SIM_HIST), ("seconds", ctypes.c_double),
+                ("step_newton", ctypes.c_int * SIM_HIST), ("step_linear", ctypes.c_int * SIM_HIST),
+                ("step_cuts", ctypes.c_int * SIM_HIST), ("step_seconds", ctypes.c_double * SIM_HIST)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_[:6]}
-        d["dts"] = list(self.dts[:min(self.steps, SIM_HIST)])
+        k = min(self.steps, SIM_HIST)
+        d["dts"] = list(self.dts[:k])
+        d["seconds"] = self.seconds
+        for f in ("step_newton", "step_linear", "step_cuts", "step_seconds"):
+            d[f] = list(getattr(self, f)[:k])
         return d
+
+
+def paper_table(stats):
+    """The columns of the paper's result tables (Sec. 4) for a simulate()
+    run: steps, Newton iterations, linear-solver iterations, linear
+    iterations per Newton iteration, wall time and wall time per Newton
+    iteration (seconds)."""
+    newton = stats["total_newton"]
+    return {"steps": stats["steps"], "newton": newton, "solver": stats["total_linear"],
+            "avg_solver": stats["total_linear"] / newton if newton else None,
+            "time_s": stats["seconds"], "avg_time_s": stats["seconds"] / newton if newton else None}
+
+
+def write_jsonl(path, stats):
+    """One JSON line per accepted time step of a simulate() run (time,
+    step size, Newton and linear iterations, cuts, wall time), then one line
+    with the run's paper_table() columns."""
+    t = 0.0
+    with open(path, "w") as f:
+        for i, dt in enumerate(stats["dts"]):
+            t += dt
+            f.write(json.dumps({"step": i + 1, "t_days": t, "dt_days": dt, "newton": stats["step_newton"][i],
+                                "solver": stats["step_linear"][i], "cuts": stats["step_cuts"][i],
+                                "seconds": stats["step_seconds"][i]}) + "\n")
+        f.write(json.dumps(dict(paper_table(stats), completed=bool(stats["completed"]),
+                                t_reached_days=stats["t_reached"])) + "\n")
 
 
 EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error", "cpr_block_size",
@@ -445,9 +478,10 @@ class Solver:
         d["status"] = rc
         return x, d
 
-    def simulate(self, x0, t_end, dt0, dt_max, growth=2.0, options=None, newton=None, x=None):
+    def simulate(self, x0, t_end, dt0, dt_max, growth=2.0, options=None, newton=None, x=None, log=None):
         """Time stepping over [0, t_end] days from x0 (cpr_simulate);
-        returns (x, stats)."""
+        returns (x, stats).  log: path of a JSON-lines record of the run
+        (write_jsonl)."""
         x = self.vector() if x is None else x
         lo = options if options is not None else default_options()
         no = newton if isinstance(newton, NewtonOptions) else default_newton_options(**(newton or {}))
@@ -457,6 +491,8 @@ class Solver:
                                                ctypes.byref(st)), allow=(0, 1))
         d = st.as_dict()
         d["status"] = rc
+        if log:
+            write_jsonl(log, d)
         return x, d
 
     def newton_update(self, x, dx):

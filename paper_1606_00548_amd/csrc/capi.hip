@@ -1,5 +1,6 @@
 // C ABI entry points: argument checks, layout conversion at the boundary,
 // ownership of device buffers.  No exception leaves this file.
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -516,9 +517,12 @@ int cpr_simulate(cpr_ctx_t* ctx, const double* x0, double* x, double t_end_days,
   cpr_sim_stats_t S = {};
   double t = 0.0, dt = dt0_days;
   int rc = CPR_OK;
+  using clock = std::chrono::steady_clock;
+  const auto t_call = clock::now();
   while (t < t_end_days) {
     double h = std::fmin(dt, t_end_days - t);
     cpr_newton_stats_t ns = {};
+    const auto t_step = clock::now();
     rc = time_step(ctx, xa, ctx->vin, h, lo, no, &ns);
     if (rc < 0) break;
     S.cuts += ns.cuts;
@@ -526,7 +530,14 @@ int cpr_simulate(cpr_ctx_t* ctx, const double* x0, double* x, double t_end_days,
     S.total_linear += ns.total_linear;
     if (rc != CPR_OK) break;
     CPR_TRY(hipMemcpyAsync(xa, ctx->vin, len * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (S.steps < CPR_SIM_HIST) S.dts[S.steps] = ns.dt_taken;
+    CPR_TRY(hipStreamSynchronize(s));
+    if (S.steps < CPR_SIM_HIST) {
+      S.dts[S.steps] = ns.dt_taken;
+      S.step_newton[S.steps] = ns.total_newton;
+      S.step_linear[S.steps] = ns.total_linear;
+      S.step_cuts[S.steps] = ns.cuts;
+      S.step_seconds[S.steps] = std::chrono::duration<double>(clock::now() - t_step).count();
+    }
     S.steps += 1;
     t += ns.dt_taken;
     dt = ns.cuts == 0 ? std::fmin(growth * ns.dt_taken, dt_max_days) : ns.dt_taken;
@@ -534,6 +545,8 @@ int cpr_simulate(cpr_ctx_t* ctx, const double* x0, double* x, double t_end_days,
   S.t_reached = t;
   S.completed = (rc == CPR_OK && t >= t_end_days) ? 1 : 0;
   if (rc >= 0) CPR_TRY(vec_cs_to_nat(ctx, xa, x));
+  if (rc >= 0) CPR_TRY(hipStreamSynchronize(s));
+  S.seconds = std::chrono::duration<double>(clock::now() - t_call).count();
   if (st) *st = S;
   if (rc < 0) return rc;
   int rc2 = launch_check(ctx, "cpr_simulate");

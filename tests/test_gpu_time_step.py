@@ -10,6 +10,8 @@ reacts chaotically to rounding (see its parity test), so with it only
 convergence and the stopping criterion, recomputed by the oracle, are
 checked.
 """
+import json
+
 import numpy as np
 import pytest
 
@@ -128,13 +130,14 @@ def test_time_step_rejects_bad_options():
 
 
 @pytest.mark.parametrize("name", ["black-oil", "oil-water"])
-def test_simulate_matches_oracle(name):
+def test_simulate_matches_oracle(name, tmp_path):
     if name == "black-oil":
         case, t_end, dt0, dt_max = synth.black_oil_layered(16, 12, 4, seed=5), 1.0, 0.01, 1.0
     else:
         case, t_end, dt0, dt_max = synth.oil_water_lognormal(16, 12, 4, seed=6), 10.0, 0.1, 5.0
     s = _solver(case)
-    xg, sg = s.simulate(_gpu(case["x_old"]), t_end, dt0, dt_max)
+    log = tmp_path / "run.jsonl"
+    xg, sg = s.simulate(_gpu(case["x_old"]), t_end, dt0, dt_max, log=str(log))
     xo, so = newton.simulate(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
                              case["x_old"], t_end, dt0, dt_max)
     x = xg.cpu().numpy()
@@ -145,4 +148,13 @@ def test_simulate_matches_oracle(name):
     assert sg["total_newton"] == so["total_newton"] and sg["total_linear"] == so["total_linear"]
     assert sg["dts"] == so["dts"] and sg["t_reached"] == sum(so["dts"])
     assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+    # the per-step columns of the paper's tables, and the JSON-lines record
+    assert sg["step_newton"] == so["step_newton"] and sg["step_linear"] == so["step_linear"]
+    assert sg["step_cuts"] == so["step_cuts"]
+    assert 0 < sum(sg["step_seconds"]) <= sg["seconds"]
+    lines = [json.loads(l) for l in log.read_text().splitlines()]
+    assert len(lines) == sg["steps"] + 1
+    assert [l["newton"] for l in lines[:-1]] == so["step_newton"]
+    assert lines[-1]["newton"] == so["total_newton"] and lines[-1]["solver"] == so["total_linear"]
+    assert lines[-1]["avg_solver"] == so["total_linear"] / so["total_newton"]
     s.close()

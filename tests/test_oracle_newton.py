@@ -97,6 +97,25 @@ def test_simulate_steps_add_up_and_grow():
         t += a
         assert b == min(2.0 * a, 0.25, 1.0 - t) or np.isclose(b, 1.0 - t, rtol=1e-12)
     assert max(st["dts"]) == 0.25
+    # per-step counts add up to the totals (every step converged without cuts here or with them)
+    assert sum(st["step_newton"]) == st["total_newton"] and sum(st["step_linear"]) == st["total_linear"]
+    assert sum(st["step_cuts"]) == st["cuts"] and len(st["step_newton"]) == st["steps"]
+
+
+def test_paper_table_columns_and_jsonl(tmp_path):
+    # the binding's table helpers on a stats record of known counts: averages
+    # per Newton iteration as in the paper's tables
+    import json
+    from paper_1606_00548_amd import cprmi
+    st = {"steps": 2, "total_newton": 7, "total_linear": 63, "seconds": 3.5, "completed": 1, "t_reached": 3.0,
+          "dts": [1.0, 2.0], "step_newton": [3, 4], "step_linear": [27, 36], "step_cuts": [0, 1],
+          "step_seconds": [1.0, 2.0]}
+    row = cprmi.paper_table(st)
+    assert row == {"steps": 2, "newton": 7, "solver": 63, "avg_solver": 9.0, "time_s": 3.5, "avg_time_s": 0.5}
+    cprmi.write_jsonl(tmp_path / "r.jsonl", st)
+    lines = [json.loads(l) for l in (tmp_path / "r.jsonl").read_text().splitlines()]
+    assert [l["t_days"] for l in lines[:2]] == [1.0, 3.0] and lines[1]["cuts"] == 1
+    assert lines[2]["avg_solver"] == 9.0 and lines[2]["completed"] is True
 
 
 def test_simulate_is_a_sequence_of_time_steps():

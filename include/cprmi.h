@@ -403,6 +403,14 @@ const char* cpr_nn_last_error(const cpr_nn_t* nn);
 int cpr_nn_set_params(cpr_nn_t* nn, const float* theta);
 int cpr_nn_get_params(cpr_nn_t* nn, float* theta);
 
+/* Training checkpoint (not in the paper): the Adam first and second moments
+ * (host arrays of cpr_nn_num_params() floats each) and the number of Adam
+ * steps taken, which sets the bias correction of the next step.  Restore
+ * them after cpr_nn_set_params (which clears them) to resume training where
+ * it stopped.  Synchronise; CPR_EINVAL on null arrays or a negative step. */
+int cpr_nn_get_adam(cpr_nn_t* nn, float* m, float* v, long long* step);
+int cpr_nn_set_adam(cpr_nn_t* nn, const float* m, const float* v, long long step);
+
 /* y = N(x) for x (device [batch][n][3]) -> y (device [batch][n]). */
 int cpr_nn_forward(cpr_nn_t* nn, const float* x, int batch, float* y);
 

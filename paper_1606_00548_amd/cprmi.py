@@ -148,7 +148,8 @@ EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error",
            "cpr_nn_forward", "cpr_nn_backward", "cpr_nn_train_step", "cpr_nn_attach",
            "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov", "cpr_nn_eval_loss",
            "cpr_nn_make_target", "cpr_nn_infer", "cpr_bicgstab_solve", "cpr_default_newton_options",
-           "cpr_time_step", "cpr_simulate", "cpr_num_unknowns", "cpr_set_allocator"]
+           "cpr_time_step", "cpr_simulate", "cpr_num_unknowns", "cpr_set_allocator", "cpr_nn_get_adam",
+           "cpr_nn_set_adam"]
 KCLASS = {"spmv": 0, "orth": 1, "smooth": 2, "ilu": 3, "assemble": 4}
 
 
@@ -201,6 +202,8 @@ def load():
     lib.cpr_nn_last_error.restype = ctypes.c_char_p
     lib.cpr_nn_set_params.argtypes = [P, P]
     lib.cpr_nn_get_params.argtypes = [P, P]
+    lib.cpr_nn_get_adam.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_longlong)]
+    lib.cpr_nn_set_adam.argtypes = [P, P, P, ctypes.c_longlong]
     lib.cpr_nn_forward.argtypes = [P, P, ctypes.c_int, P]
     lib.cpr_nn_infer.argtypes = [P, P, P]
     lib.cpr_nn_backward.argtypes = [P, P, P]
@@ -274,6 +277,22 @@ class Network:
         th = np.empty(self.P, dtype=np.float32)
         self._check(self.lib.cpr_nn_get_params(self.h, th.ctypes.data_as(ctypes.c_void_p)))
         return th
+
+    def get_adam(self):
+        """(first moment, second moment, Adam steps taken)."""
+        m = np.empty(self.P, dtype=np.float32)
+        v = np.empty(self.P, dtype=np.float32)
+        k = ctypes.c_longlong()
+        self._check(self.lib.cpr_nn_get_adam(self.h, m.ctypes.data_as(ctypes.c_void_p),
+                                             v.ctypes.data_as(ctypes.c_void_p), ctypes.byref(k)))
+        return m, v, int(k.value)
+
+    def set_adam(self, m, v, step):
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        assert m.size == self.P and v.size == self.P
+        self._check(self.lib.cpr_nn_set_adam(self.h, m.ctypes.data_as(ctypes.c_void_p),
+                                             v.ctypes.data_as(ctypes.c_void_p), int(step)))
 
     def forward(self, x):
         """x: float32 CUDA tensor [B, nz, ny, nx, 3] -> y [B, nz, ny, nx]."""

@@ -1074,6 +1074,25 @@ int cpr_nn_set_params(cpr_nn_t* nn, const float* theta) {
   return CPR_OK;
 }
 
+int cpr_nn_get_adam(cpr_nn_t* nn, float* m, float* v, long long* step) {
+  if (!nn || !m || !v || !step) return CPR_EINVAL;
+  NN_TRY(hipMemcpyAsync(m, nn->m, nn->P * sizeof(float), hipMemcpyDeviceToHost, nn->stream));
+  NN_TRY(hipMemcpyAsync(v, nn->vv, nn->P * sizeof(float), hipMemcpyDeviceToHost, nn->stream));
+  NN_TRY(hipStreamSynchronize(nn->stream));
+  *step = nn->adam_step;
+  return CPR_OK;
+}
+
+int cpr_nn_set_adam(cpr_nn_t* nn, const float* m, const float* v, long long step) {
+  if (!nn || !m || !v) return CPR_EINVAL;
+  if (step < 0) return nn_err(nn, CPR_EINVAL, "negative Adam step count");
+  NN_TRY(hipMemcpyAsync(nn->m, m, nn->P * sizeof(float), hipMemcpyHostToDevice, nn->stream));
+  NN_TRY(hipMemcpyAsync(nn->vv, v, nn->P * sizeof(float), hipMemcpyHostToDevice, nn->stream));
+  NN_TRY(hipStreamSynchronize(nn->stream));
+  nn->adam_step = (long)step;
+  return CPR_OK;
+}
+
 int cpr_nn_get_params(cpr_nn_t* nn, float* theta) {
   if (!nn || !theta) return CPR_EINVAL;
   NN_TRY(hipMemcpyAsync(theta, nn->theta, nn->P * sizeof(float), hipMemcpyDeviceToHost, nn->stream));

@@ -108,8 +108,50 @@ def make_dataset(n_systems, per_system, shape=(64, 64, 32), seed0=5000, log=prin
     return torch.cat(X).contiguous(), torch.cat(T).contiguous()
 
 
-def train(X, T, epochs, batch=4, lr=1e-3, seed=0, val_frac=0.1, init_seed=1, log=print):
-    """Adam on the normalised MSE; returns (parameters, history)."""
+def _sha256(path):
+    import hashlib
+    h = hashlib.sha256()
+    with open(path, "rb") as f:
+        for chunk in iter(lambda: f.read(1 << 20), b""):
+            h.update(chunk)
+    return h.hexdigest()
+
+
+def save_checkpoint(path, state, meta):
+    """Write a training checkpoint: `state` (parameters theta, Adam moments
+    m and v, adam_step, the finished epoch, the shuffling generator's state
+    and the loss history) as one .npz of plain arrays (nothing pickled), and
+    beside it <path>.json with the training configuration `meta` and the
+    file's SHA-256."""
+    assert path.endswith(".npz")
+    np.savez(path, theta=state["theta"], m=state["m"], v=state["v"], adam_step=np.int64(state["adam_step"]),
+             epoch=np.int64(state["epoch"]), rng_state=np.array(json.dumps(state["rng_state"])),
+             history=np.array(json.dumps(state["history"])))
+    with open(path[:-4] + ".json", "w") as f:
+        json.dump(dict(meta, epoch=int(state["epoch"]), sha256=_sha256(path)), f, indent=1)
+
+
+def load_checkpoint(path):
+    """Read a checkpoint written by save_checkpoint after checking its
+    SHA-256 against the one recorded beside it (ValueError if they differ)."""
+    with open(path[:-4] + ".json") as f:
+        meta = json.load(f)
+    if _sha256(path) != meta["sha256"]:
+        raise ValueError(f"{path}: SHA-256 does not match {path[:-4]}.json")
+    with np.load(path, allow_pickle=False) as z:
+        return {"theta": z["theta"], "m": z["m"], "v": z["v"], "adam_step": int(z["adam_step"]),
+                "epoch": int(z["epoch"]), "rng_state": json.loads(str(z["rng_state"])),
+                "history": json.loads(str(z["history"])), "meta": meta}
+
+
+def train(X, T, epochs, batch=4, lr=1e-3, seed=0, val_frac=0.1, init_seed=1, log=print,
+          checkpoint=None, resume=None):
+    """Adam on the normalised MSE; returns (parameters, history).
+    checkpoint: .npz path rewritten after every epoch (save_checkpoint);
+    resume: a checkpoint of a run with the same data and arguments to
+    continue from its last finished epoch -- parameters, Adam moments and
+    step count, and the shuffling generator are restored, so the resumed run
+    reproduces the uninterrupted one."""
     n = X.shape[0]
     nz, ny, nx = X.shape[1:4]
     rng = np.random.default_rng(seed)
@@ -119,8 +161,19 @@ def train(X, T, epochs, batch=4, lr=1e-3, seed=0, val_frac=0.1, init_seed=1, log
     net = cprmi.Network(nx, ny, nz, max_batch=batch)
     net.set_params(synth.nn_initial_weights(init_seed))
     hist = []
+    start = 0
+    if resume:
+        ck = load_checkpoint(resume)
+        net.set_params(ck["theta"])
+        net.set_adam(ck["m"], ck["v"], ck["adam_step"])
+        rng.bit_generator.state = ck["rng_state"]
+        hist, start = ck["history"], ck["epoch"]
+        if log:
+            log(f"[train] resumed after epoch {start} from {resume}")
+    meta = {"samples": int(n), "grid": [nx, ny, nz], "epochs": epochs, "batch": batch, "lr": lr, "seed": seed,
+            "val_frac": val_frac, "init_seed": init_seed}
     t0 = time.time()
-    for ep in range(epochs):
+    for ep in range(start, epochs):
         perm = rng.permutation(tr)
         losses = []
         for q in range(0, len(perm) - batch + 1, batch):
@@ -132,6 +185,11 @@ def train(X, T, epochs, batch=4, lr=1e-3, seed=0, val_frac=0.1, init_seed=1, log
         if log:
             log(f"[train] epoch {ep + 1}: train {np.mean(losses):.4f}, validation {vl:.4f}, "
                 f"{time.time() - t0:.1f} s")
+        if checkpoint:
+            m, v, k = net.get_adam()
+            save_checkpoint(checkpoint, {"theta": net.get_params(), "m": m, "v": v, "adam_step": k,
+                                         "epoch": ep + 1, "rng_state": rng.bit_generator.state,
+                                         "history": hist}, meta)
     theta = net.get_params()
     net.close()
     return theta, hist
@@ -191,6 +249,8 @@ def main():
     ap.add_argument("--eval-seeds", type=int, default=8)
     ap.add_argument("--out", default=None, help="parameter file (default: the family's shipped file)")
     ap.add_argument("--report", default=None)
+    ap.add_argument("--checkpoint", default=None, help="training checkpoint (.npz) rewritten every epoch")
+    ap.add_argument("--resume", default=None, help="checkpoint (.npz) to continue training from")
     ap.add_argument("--eval-only", action="store_true",
                     help="evaluate the parameters in --out (default: the shipped file) without training")
     args = ap.parse_args()
@@ -212,7 +272,8 @@ def main():
                         log=lambda m: print(m, flush=True))
     pairs = int(X.shape[0])
     print(f"[data] {pairs} pairs", flush=True)
-    theta, hist = train(X, T, args.epochs, lr=args.lr, log=lambda m: print(m, flush=True))
+    theta, hist = train(X, T, args.epochs, lr=args.lr, log=lambda m: print(m, flush=True),
+                        checkpoint=args.checkpoint, resume=args.resume)
     del X, T
     torch.cuda.empty_cache()
     os.makedirs(os.path.dirname(out), exist_ok=True)

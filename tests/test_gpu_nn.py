@@ -136,6 +136,26 @@ def test_train_step_loss_matches_oracle_and_decreases():
     assert th.shape == (nn.num_params(),) and np.all(np.isfinite(th))
 
 
+def test_resumed_training_reproduces_the_uninterrupted_run(tmp_path):
+    # parameters, Adam moments and step, and the shuffling generator from the
+    # checkpoint of epoch 1: the second epoch then repeats the uninterrupted
+    # run bit for bit (the training kernels are deterministic)
+    from paper_1606_00548_amd import train
+    rng = np.random.default_rng(8)
+    X = torch.from_numpy(rng.standard_normal((6, 8, 16, 16, 3)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.standard_normal((6, 8, 16, 16)).astype(np.float32)).cuda()
+    th_a, hist_a = train.train(X, T, 2, batch=2, val_frac=0.34, log=None)
+    ck = str(tmp_path / "ck.npz")
+    th_1, _ = train.train(X, T, 1, batch=2, val_frac=0.34, log=None, checkpoint=ck)
+    saved = train.load_checkpoint(ck)
+    assert saved["epoch"] == 1 and saved["adam_step"] == 2 and np.array_equal(saved["theta"], th_1)
+    th_b, hist_b = train.train(X, T, 2, batch=2, val_frac=0.34, log=None, resume=ck)
+    print(f"[nn] resume: losses {[h['train_loss'] for h in hist_a]} / {[h['train_loss'] for h in hist_b]}")
+    assert np.array_equal(th_a, th_b)
+    assert [h["train_loss"] for h in hist_a] == [h["train_loss"] for h in hist_b]
+    assert not np.array_equal(th_1, th_b)
+
+
 def _ow_case():
     return synth.oil_water_lognormal(16, 16, 8, seed=70)
 

@@ -516,31 +516,32 @@ void launch_assemble(cpr_ctx* ctx, const double* xold_cs, const double* x_cs, do
   double dt = dt_days * DAY;
   double sc[3] = {0, 0, 0};
   for (int c = 0; c < ctx->b; ++c) sc[c] = ctx->rho_scale[c] * ctx->cell_vol * ctx->phibar / dt;
-  int nb = div_up(L.n, 256);
+  // per-cell kernels in one-wave workgroups
+  int nb = div_up(L.n, 64);
   int np = (int)ctx->perfs.size();
   hipStream_t s = ctx->stream;
   if (ctx->fl.model == 1) {
-    props_kernel<1><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
+    props_kernel<1><<<nb, 64, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
     prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
-    flux_kernel<1><<<nb, 256, 0, s>>>(L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt, sc[0], sc[1],
+    flux_kernel<1><<<nb, 64, 0, s>>>(L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt, sc[0], sc[1],
                                       sc[2], ctx->tp, x_cs, ctx->props, ctx->J, rhs_cs);
     prof_end(ctx, CPR_KCLASS_ASSEMBLE);
     if (np) well_kernel<1><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, ctx->rwells_d, sc[0],
                                                         sc[1], sc[2], ctx->poro, x_cs, ctx->J, rhs_cs,
                                                         ctx->bord, ctx->pq);
   } else if (ctx->fl.model == 2) {
-    props_kernel<2><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
+    props_kernel<2><<<nb, 64, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
     prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
-    flux_kernel<2><<<nb, 256, 0, s>>>(L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt, sc[0], sc[1],
+    flux_kernel<2><<<nb, 64, 0, s>>>(L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt, sc[0], sc[1],
                                       sc[2], ctx->tp, x_cs, ctx->props, ctx->J, rhs_cs);
     prof_end(ctx, CPR_KCLASS_ASSEMBLE);
     if (np) well_kernel<2><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, ctx->rwells_d, sc[0],
                                                         sc[1], sc[2], ctx->poro, x_cs, ctx->J, rhs_cs,
                                                         ctx->bord, ctx->pq);
   } else {
-    props_kernel<3><<<nb, 256, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
+    props_kernel<3><<<nb, 64, 0, s>>>(ctx->fl, L, ctx->poro, xold_cs, x_cs, ctx->props);
     prof_begin(ctx, CPR_KCLASS_ASSEMBLE);
-    flux_kernel<3><<<nb, 256, 0, s>>>(L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt, sc[0], sc[1],
+    flux_kernel<3><<<nb, 64, 0, s>>>(L, ctx->grid.dz, ctx->grid.top, ctx->cell_vol, dt, sc[0], sc[1],
                                       sc[2], ctx->tp, x_cs, ctx->props, ctx->J, rhs_cs);
     prof_end(ctx, CPR_KCLASS_ASSEMBLE);
     if (np) well_kernel<3><<<div_up(np, 64), 64, 0, s>>>(ctx->fl, L, np, ctx->perfs_d, ctx->rwells_d, sc[0],

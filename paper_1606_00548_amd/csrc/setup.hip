@@ -570,21 +570,22 @@ int setup_cpr(cpr_ctx* ctx) {
   const Lay& L = ctx->lay;
   const int n = L.n;
   zero_int_kernel<<<1, 64, 0, s>>>(ctx->flag, 2);
-  int nb = div_up(n, 256);
+  // per-cell kernels stream the Jacobian's planes in one-wave workgroups
+  int nb = div_up(n, 64);
   const bool abf = ctx->opt.decoupling == CPR_DECOUPLE_ABF;
   if (abf) {
     if (ctx->b == 1)
-      abf_kernel<1><<<nb, 256, 0, s>>>(n, ctx->J, ctx->Wabf, ctx->R0, ctx->Jt, ctx->levels[0].A, ctx->flag);
+      abf_kernel<1><<<nb, 64, 0, s>>>(n, ctx->J, ctx->Wabf, ctx->R0, ctx->Jt, ctx->levels[0].A, ctx->flag);
     else if (ctx->b == 2)
-      abf_kernel<2><<<nb, 256, 0, s>>>(n, ctx->J, ctx->Wabf, ctx->R0, ctx->Jt, ctx->levels[0].A, ctx->flag);
+      abf_kernel<2><<<nb, 64, 0, s>>>(n, ctx->J, ctx->Wabf, ctx->R0, ctx->Jt, ctx->levels[0].A, ctx->flag);
     else
-      abf_kernel<3><<<nb, 256, 0, s>>>(n, ctx->J, ctx->Wabf, ctx->R0, ctx->Jt, ctx->levels[0].A, ctx->flag);
+      abf_kernel<3><<<nb, 64, 0, s>>>(n, ctx->J, ctx->Wabf, ctx->R0, ctx->Jt, ctx->levels[0].A, ctx->flag);
   } else if (ctx->b == 1) {
-    qimpes_kernel<1><<<nb, 256, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
+    qimpes_kernel<1><<<nb, 64, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
   } else if (ctx->b == 2) {
-    qimpes_kernel<2><<<nb, 256, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
+    qimpes_kernel<2><<<nb, 64, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
   } else {
-    qimpes_kernel<3><<<nb, 256, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
+    qimpes_kernel<3><<<nb, 64, 0, s>>>(n, ctx->J, ctx->w, ctx->R0, ctx->levels[0].A, ctx->flag + 1);
   }
   // rows >= 1 of the decoupled blocks: the Jacobian's own (quasi-IMPES) or D^-1 A (ABF)
   const double* Jdec = abf ? ctx->Jt : ctx->J;
@@ -625,14 +626,14 @@ int setup_cpr(cpr_ctx* ctx) {
   }
   CPR_TRY(hipEventRecord(ctx->ev_gj, a));
   // red-black block ILU(0): red diagonals first, black ones use them
-  int nh = div_up(L.nh, 256);
+  int nh = div_up(L.nh, 64);
   for (int colour = 0; colour < 2; ++colour) {
     if (ctx->b == 1)
-      ilu_kernel<1><<<nh, 256, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
+      ilu_kernel<1><<<nh, 64, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
     else if (ctx->b == 2)
-      ilu_kernel<2><<<nh, 256, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
+      ilu_kernel<2><<<nh, 64, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
     else
-      ilu_kernel<3><<<nh, 256, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
+      ilu_kernel<3><<<nh, 64, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
   }
   if (ctx->opt.precision == CPR_PREC_MIXED) {
     CPR_TRY(hipStreamWaitEvent(s, ctx->ev_rap, 0));   // FP32 copies of the levels

@@ -320,8 +320,20 @@ def main():
         t = e0.elapsed_time(e1) * 1e-3
         best = t if best is None else min(best, t)
     triad_gbs = 3 * ta.numel() * 8 / best / 1e9
+    # and a device-to-device copy of 1 GiB (the runtime's copy kernel), best of 5
+    bestc = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ta.copy_(tb)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3
+        bestc = t if bestc is None else min(bestc, t)
+    copy_gbs = 2 * ta.numel() * 8 / bestc / 1e9
     del ta, tb, tc
     roofline["measured_triad_GBps"] = triad_gbs
+    roofline["measured_copy_GBps"] = copy_gbs
     roofline["frac_of_measured_triad"] = (achieved / triad_gbs) if achieved else None
     for v in classes.values():
         v["frac_of_measured_triad"] = v["GBps"] / triad_gbs if v["GBps"] else None

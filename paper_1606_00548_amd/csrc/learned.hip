@@ -263,14 +263,21 @@ int learned_setup(cpr_ctx* ctx, bool need_nn) {
   return launch_check(ctx, "learned_setup");
 }
 
+// Blocks of the per-application stage kernels: one cell per thread where
+// the partial-sum buffer (66 nblk values, two per block here) allows.
+static int stage_blocks(const cpr_ctx* ctx) {
+  const long nb = div_up((long)ctx->lay.n, LB), cap = 32L * ctx->nblk;
+  return (int)(nb < cap ? nb : cap);
+}
+
 // r' and its norms for rp, dp of the fine level (T = preconditioner type);
 // with rp == nullptr, ctx->rprime already holds r'.
 template <typename T>
 static void rprime_launch(cpr_ctx* ctx, const T* rp, const T* dp, float* feat = nullptr) {
   const MGLevel& L0 = ctx->levels[0];
-  rprime_kernel<T><<<ctx->nblk, LB, 0, ctx->stream>>>(ctx->lay, L0.A, rp, dp, ctx->rprime, ctx->part, ctx->nblk,
-                                                      feat);
-  rprime_final_kernel<<<1, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->part, ctx->nblk, ctx->nnscal);
+  const int nb = stage_blocks(ctx);
+  rprime_kernel<T><<<nb, LB, 0, ctx->stream>>>(ctx->lay, L0.A, rp, dp, ctx->rprime, ctx->part, nb, feat);
+  rprime_final_kernel<<<1, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->part, nb, ctx->nnscal);
 }
 
 static void features_launch(cpr_ctx* ctx) {
@@ -288,8 +295,9 @@ static int learned_stage_t(cpr_ctx* ctx, const T* rp, T* dp) {
   int rc = nn_infer(ctx->nn, ctx->feat, nullptr, ctx->nnscal + S_INV);
   if (rc) return set_err(ctx, rc, "network inference failed");
   const float* y = nn_output(ctx->nn);
-  apply_dir_kernel<<<ctx->nblk, LB, 0, s>>>(L, ctx->levels[0].A, ctx->rprime, y, ctx->qbuf, ctx->part, ctx->nblk);
-  alpha_kernel<<<1, LB, 0, s>>>(ctx->part, ctx->nblk, ctx->nnscal, ctx->nncount);
+  const int nb = stage_blocks(ctx);
+  apply_dir_kernel<<<nb, LB, 0, s>>>(L, ctx->levels[0].A, ctx->rprime, y, ctx->qbuf, ctx->part, nb);
+  alpha_kernel<<<1, LB, 0, s>>>(ctx->part, nb, ctx->nnscal, ctx->nncount);
   correct_kernel<T><<<div_up(L.n, LB), LB, 0, s>>>(L, ctx->nnscal, y, dp);
   return CPR_OK;
 }

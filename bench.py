@@ -377,8 +377,9 @@ def _kernel_sha(kclass):
 def other_configs(steps=2):
     """One Newton step of the small oil-water system (32x32x8, latency
     regime) and of the first system of the channelised 256x256x64 black-oil
-    10-day step (bandwidth regime), FP64 and mixed precision; each timed
-    step restarts from the same state."""
+    10-day step (bandwidth regime), FP64 and mixed precision, with the
+    default V(1,1) cycle and with the tuned V(2,2), alpha 1.25 one; each
+    timed step restarts from the same state."""
     import numpy as np
     import torch
     from paper_1606_00548_amd import cprmi, synth
@@ -392,8 +393,11 @@ def other_configs(steps=2):
         x0 = torch.as_tensor(case["x"]).cuda().contiguous()
         x = x0.clone()
         res = {"cells": int(np.prod(case["x"].shape[1:])), "block": int(case["x"].shape[0])}
-        for prec in ("fp64", "mixed"):
-            o = cprmi.default_options(precision=prec)
+        forms = (("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed")),
+                 ("fp64 V(2,2) alpha 1.25", dict(precision="fp64", mg_pre=2, mg_post=2, mg_alpha=1.25)),
+                 ("mixed V(2,2) alpha 1.25", dict(precision="mixed", mg_pre=2, mg_post=2, mg_alpha=1.25)))
+        for prec, kw in forms:
+            o = cprmi.default_options(**kw)
 
             def step():
                 x.copy_(x0)

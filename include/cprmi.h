@@ -147,7 +147,8 @@ typedef struct {
   double stall_ratio;  /* MIXED, FGMRES: when a restart cycle ends with the
                           true residual above stall_ratio times the one it
                           started from, the remaining cycles apply the FP64
-                          preconditioner (1.0: no decrease; <= 0: never) */
+                          preconditioner (default 0.5: less than halved;
+                          1.0: not decreased; <= 0: never)                 */
 } cpr_options_t;
 
 typedef struct {

@@ -347,7 +347,7 @@ void cpr_default_options(cpr_options_t* o) {
   o->rtol = 1e-6;
   o->mg_coarsest = 512;
   o->mg_alpha = 1.0;
-  o->stall_ratio = 1.0;
+  o->stall_ratio = 0.5;
   o->decoupling = CPR_DECOUPLE_QIMPES;
   o->composition = CPR_COMPOSE_PF;
   o->x0 = 0;

@@ -469,9 +469,10 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     if (beta <= rtol * bnorm) { result = CPR_OK; break; }
     if (its >= max_iter) break;
     // mixed precision: a restart cycle that left the true residual above
-    // stall_ratio times the one it started from hands the remaining cycles
-    // to the FP64 preconditioner (FGMRES is flexible, so the change of
-    // preconditioner between cycles needs nothing else)
+    // stall_ratio times the one it started from (by default: less than
+    // halved, where a healthy cycle gains one to two orders) hands the
+    // remaining cycles to the FP64 preconditioner (FGMRES is flexible, so
+    // the change of preconditioner between cycles needs nothing else)
     if (S.cycles > 0 && ctx->opt.precision == CPR_PREC_MIXED && !ctx->fp64_now && ctx->opt.stall_ratio > 0 &&
         beta > ctx->opt.stall_ratio * beta_start) {
       ctx->fp64_now = true;

@@ -75,8 +75,8 @@ def test_forced_fallback_is_one_fp32_cycle_then_fp64(name, make, learned):
 
 
 def test_default_stall_check_keeps_fp32_on_a_converging_solve():
-    # default stall_ratio 1: a cycle that reduces the residual keeps FP32;
-    # stall_ratio <= 0 disables the check; both runs are then identical
+    # default stall_ratio 0.5: cycles that more than halve the residual keep
+    # FP32; stall_ratio <= 0 disables the check; both runs are then identical
     from paper_1606_00548_amd import cprmi
     case = synth.black_oil_layered(34, 20, 6, seed=102)
     R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],

@@ -2,7 +2,9 @@
 
 * Black oil, channelised, 256 x 256 x 64 (4.19 M cells, 3 x 3 blocks):
   the first Newton system of a 10-day step, solved to the 1e-6 true
-  relative residual with the FP64 and the mixed-precision preconditioner;
+  relative residual with the FP64 and the mixed-precision preconditioner,
+  and with the mixed-precision tuned cycle V(2,2), alpha 1.25, whose FP32
+  cycle stalls here until the stall check switches it to FP64;
   then the 10 days by time stepping from 0.01 day (step growth, cuts,
   variable switching, inexact Newton with the first forcing term) with
   both preconditioners: both must complete, and since each stops at the
@@ -110,6 +112,16 @@ def test_channelised_256x256x64_ten_days_mixed_vs_fp64():
         print(f"[full-size]   {prec}, dt {case['dt']:g} days, first Newton system: {st['iterations']} "
               f"FGMRES iterations, true rel. {rel:.2e}", flush=True)
         assert st["status"] == 0 and rel <= 1e-6
+    # the tuned cycle V(2,2), alpha 1.25: with the FP32 preconditioner its
+    # first restart cycle on this system gains little, and the stall check
+    # (default: a cycle must halve the true residual) hands the solve to the
+    # FP64 preconditioner, which reaches 1e-6
+    s.setup(precision="mixed", mg_pre=2, mg_post=2, mg_alpha=1.25)
+    dx, st = s.solve(rhs)
+    rel = _true_rel(s, rhs, dx)
+    print(f"[full-size]   mixed V(2,2) alpha 1.25: {st['iterations']} FGMRES iterations, FP64 after cycle "
+          f"{st['fp64_fallback']}, true rel. {rel:.2e}", flush=True)
+    assert st["status"] == 0 and rel <= 1e-6
     # ten days of time stepping from dt0 = 0.01 day (step growth, cuts,
     # variable switching) with the FP64 and the mixed-precision preconditioner
     res = {}

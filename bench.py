@@ -125,6 +125,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP64 / mixed / mixed+learned comparison runs")
+    ap.add_argument("--oracle-configs", action="store_true",
+                    help="time only the CPU oracle on the other configurations (oil-water 32x32x8: a "
+                         "whole Newton step; channelised 256x256x64: assembly, setup and a sample "
+                         "of FGMRES iterations) and print one JSON line")
     ap.add_argument("--network-only", action="store_true",
                     help="time only the pressure network's inference on the workload grid")
     args = ap.parse_args()
@@ -134,6 +138,9 @@ def main():
         sys.exit(2)
     if args.network_only:
         print(json.dumps({"network": network_timing(args.nx, args.ny, args.nz, reps=max(args.steps, 1) * 10)}))
+        return
+    if args.oracle_configs:
+        print(json.dumps({"oracle_configs": oracle_configs()}))
         return
 
     import numpy as np
@@ -433,6 +440,42 @@ def cpu_baseline(case):
             "sample": "one full Newton step (assemble, CPR setup, FGMRES(30) to 1e-6, update) "
                       "of the same workload, numpy/scipy single-threaded",
             "iterations": st["iterations"]}
+
+
+def oracle_configs(sample_iterations=10):
+    """The FP64 oracle, single-threaded, on the other configurations: the
+    whole Newton step of the oil-water 32x32x8 system; for the channelised
+    256x256x64 system (whose step takes about a hundred FGMRES iterations)
+    the assembly, the CPR setup and the first `sample_iterations` FGMRES
+    iterations, timed separately and reported as measured."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cpr, krylov, model, newton
+    from paper_1606_00548_amd import synth
+    out = {}
+    with threadpool_limits(limits=1):
+        case = synth.oil_water_lognormal()
+        t0 = time.perf_counter()
+        _, _, st, _ = newton.newton_step(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                                         case["x_old"], case["x"], case["dt"])
+        out["oil-water 32x32x8"] = {"s_per_newton_step": time.perf_counter() - t0,
+                                    "iterations": st["iterations"], "cores": 1}
+        case = synth.black_oil_channelised()
+        t0 = time.perf_counter()
+        R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                              case["x_old"], case["x"], case["dt"])
+        t1 = time.perf_counter()
+        pc = cpr.cpr_setup(J)
+        t2 = time.perf_counter()
+        _, st = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), -R,
+                              rtol=0.0, max_iter=sample_iterations)
+        t3 = time.perf_counter()
+        out["black-oil channelised 256x256x64"] = {
+            "assemble_s": t1 - t0, "setup_s": t2 - t1, "fgmres_iterations_sampled": st["iterations"],
+            "s_per_fgmres_iteration": (t3 - t2) / st["iterations"], "cores": 1,
+            "cells": int(np.prod(case["x"].shape[1:]))}
+    return out
 
 
 if __name__ == "__main__":

@@ -237,6 +237,9 @@ def main():
         if os.path.exists(wfile):
             solver.attach_network(np.load(wfile))
             forms.append(("mixed+learned", dict(precision="mixed", learned=1)))
+        tuned = dict(mg_pre=2, mg_post=2, mg_alpha=1.25)
+        forms += [("fp64 V(2,2) alpha 1.25", dict(precision="fp64", **tuned)),
+                  ("mixed V(2,2) alpha 1.25", dict(precision="mixed", **tuned))]
         xts = torch.empty_like(x0)
         for name, kw in forms:
             lo = cprmi.default_options(**kw)

@@ -240,6 +240,14 @@ def test_invalid_grid_rejected():
     with pytest.raises(cprmi.CPRError) as e:
         _solver(case)
     assert e.value.code == -1
+    # empty grids: no cells along one axis
+    case = synth.oil_water_lognormal(8, 4, 2, seed=1)
+    for axis in ("nx", "ny", "nz"):
+        g = dict(case["grid"], **{axis: 0})
+        shape = (g["nz"], g["ny"], g["nx"])
+        with pytest.raises(cprmi.CPRError) as e:
+            cprmi.Solver(g, case["fluid"], np.ones((3,) + shape), np.ones(shape), [])
+        assert e.value.code == -1
 
 
 def test_solve_is_deterministic():

@@ -367,7 +367,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"black-oil layered {args.nx}x{args.ny}x{args.nz} "
                                f"({n} cells, 3x3 blocks), one Newton step, FGMRES(30) to 1e-6",
-                   "cells": n, "block": b, "precision": args.precision, "restart": 30, "rtol": 1e-6},
+                   "cells": n, "block": b, "precision": args.precision, "restart": 30, "rtol": 1e-6,
+                   "preconditioner": "quasi-IMPES CPR, P-then-F, multigrid V(1,1), alpha 1, coarsest <= 512 "
+                                     "cells, red-black block ILU(0)"},
         "median_ms_per_step": median_ms,
         "fgmres_iterations": its, "restart_cycles": cycles, "true_rel": st["true_rel"],
         "solve_class_bytes_GBps": solve_gbps, "network": network,

@@ -67,12 +67,14 @@ class PressureTarget:
         return dx[0].clone(), st
 
 
-def harvest(case, per_system):
+def harvest(case, per_system, cycle=None):
     """(features [k, nz, ny, nx, 3] float32, targets [k, nz, ny, nx] float32)
-    for the first k = per_system (<= 30) Krylov vectors of the system."""
+    for the first k = per_system (<= 30) Krylov vectors of the system.
+    cycle: multigrid options (mg_pre, mg_post, mg_alpha) of the pressure
+    stage whose residuals are harvested (default V(1,1), alpha 1)."""
     s = cprmi.Solver.from_case(case)
     rhs = s.assemble(_dev(case["x_old"]), _dev(case["x"]), case["dt"])
-    s.setup(rtol=0.0, max_iter=min(per_system, 30))
+    s.setup(rtol=0.0, max_iter=min(per_system, 30), **(cycle or {}))
     _, st = s.solve(rhs)
     k = min(per_system, st["iterations"], 30)
     tgt = PressureTarget(case)
@@ -92,14 +94,15 @@ def harvest(case, per_system):
     return torch.stack(feats), torch.stack(targets)
 
 
-def make_dataset(n_systems, per_system, shape=(64, 64, 32), seed0=5000, log=print, family="oil-water"):
+def make_dataset(n_systems, per_system, shape=(64, 64, 32), seed0=5000, log=print, family="oil-water",
+                 cycle=None):
     nx, ny, nz = shape
     gen = FAMILIES[family]["train"]
     X, T = [], []
     t0 = time.time()
     for i in range(n_systems):
         case = gen(nx, ny, nz, seed=seed0 + i)
-        f, t = harvest(case, per_system)
+        f, t = harvest(case, per_system, cycle)
         X.append(f)
         T.append(t)
         if log and (i + 1) % max(1, n_systems // 10) == 0:
@@ -206,9 +209,10 @@ def validation_loss(net, X, T, idx, batch):
 
 
 def evaluate(theta, seeds, shape=(128, 128, 64), control_seed=99, log=print, family="oil-water",
-             precision="fp64"):
+             precision="fp64", cycle=None):
     """FGMRES iterations and solve time to 1e-6 on evaluation systems: plain
-    CPR, CPR with the trained network, CPR with a random-init network."""
+    CPR, CPR with the trained network, CPR with a random-init network (all
+    with the multigrid options `cycle`)."""
     nx, ny, nz = shape
     gen = FAMILIES[family]["eval"]
     rows = []
@@ -221,7 +225,7 @@ def evaluate(theta, seeds, shape=(128, 128, 64), control_seed=99, log=print, fam
                          ("random", synth.nn_initial_weights(control_seed))):
             if th is not None:
                 s.attach_network(th)
-            s.setup(learned=0 if th is None else 1, precision=precision)
+            s.setup(learned=0 if th is None else 1, precision=precision, **(cycle or {}))
             s.solve(rhs)                       # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -251,11 +255,15 @@ def main():
     ap.add_argument("--report", default=None)
     ap.add_argument("--checkpoint", default=None, help="training checkpoint (.npz) rewritten every epoch")
     ap.add_argument("--resume", default=None, help="checkpoint (.npz) to continue training from")
+    ap.add_argument("--mg-pre", type=int, default=1, help="pre-smoothing sweeps of the cycle trained for")
+    ap.add_argument("--mg-post", type=int, default=1, help="post-smoothing sweeps of the cycle trained for")
+    ap.add_argument("--mg-alpha", type=float, default=1.0, help="coarse-correction scaling of that cycle")
     ap.add_argument("--eval-only", action="store_true",
                     help="evaluate the parameters in --out (default: the shipped file) without training")
     args = ap.parse_args()
     fam = FAMILIES[args.family]
     out = args.out or weights_path(args.family)
+    cycle = {"mg_pre": args.mg_pre, "mg_post": args.mg_post, "mg_alpha": args.mg_alpha}
     if args.eval_only:
         theta = np.load(out)
         ex, ey, ez = fam["eval_shape"]
@@ -263,13 +271,14 @@ def main():
         for prec in ("fp64", "mixed"):
             rows += [dict(r, precision=prec) for r in evaluate(
                 theta, [fam["eval_seed0"] + i for i in range(args.eval_seeds)], shape=(ex, ey, ez),
-                family=args.family, precision=prec, log=lambda m: print(m, flush=True))]
+                family=args.family, precision=prec, cycle=cycle, log=lambda m: print(m, flush=True))]
         if args.report:
             with open(args.report, "w") as f:
-                json.dump({"family": args.family, "weights": os.path.basename(out), "eval": rows}, f, indent=1)
+                json.dump({"family": args.family, "weights": os.path.basename(out), "cycle": cycle, "eval": rows},
+                          f, indent=1)
         return
     X, T = make_dataset(args.systems, args.per_system, fam["shape"], fam["seed0"], family=args.family,
-                        log=lambda m: print(m, flush=True))
+                        log=lambda m: print(m, flush=True), cycle=cycle)
     pairs = int(X.shape[0])
     print(f"[data] {pairs} pairs", flush=True)
     theta, hist = train(X, T, args.epochs, lr=args.lr, log=lambda m: print(m, flush=True),
@@ -291,7 +300,7 @@ def main():
                 f"vectors of each; targets A_p^-1 r' / rms(D^-1 r') from a 1e-10 pressure solve",
         "pairs": pairs, "epochs": args.epochs, "batch": 4,
         "optimizer": f"Adam lr {args.lr:g} (0.9, 0.999, 1e-8)", "init_seed": 1, "shuffle_seed": 0,
-        "loss": "direction loss 1 - cos^2(N(x), t)", "history": hist,
+        "loss": "direction loss 1 - cos^2(N(x), t)", "cycle": cycle, "history": hist,
     }
     with open(os.path.splitext(out)[0] + ".json", "w") as f:
         json.dump(meta, f, indent=1)
@@ -300,10 +309,10 @@ def main():
     for prec in ("fp64", "mixed"):
         rows += [dict(r, precision=prec) for r in evaluate(
             theta, [fam["eval_seed0"] + i for i in range(args.eval_seeds)], shape=(ex, ey, ez),
-            family=args.family, precision=prec, log=lambda m: print(m, flush=True))]
+            family=args.family, precision=prec, cycle=cycle, log=lambda m: print(m, flush=True))]
     if args.report:
         with open(args.report, "w") as f:
-            json.dump({"family": args.family, "history": hist, "eval": rows}, f, indent=1)
+            json.dump({"family": args.family, "cycle": cycle, "history": hist, "eval": rows}, f, indent=1)
 
 
 if __name__ == "__main__":

@@ -3,20 +3,26 @@
 
 One step = assemble the Jacobian and right-hand side, set up the CPR
 preconditioner, solve with FGMRES(30) to a relative residual of 1e-6, and
-update the state (Algorithm 1, one iteration), on the saturated black-oil
-workload of 128 x 128 x 32 cells (3x3 blocks, layered lognormal
-permeability with kz/kx = 0.1, inverted five-spot, 1-day step), inputs
-already resident in GPU memory.  Every step restarts from the same initial
-state so the timed steps do identical work.
+update the state (Algorithm 1, one iteration).  The default workload is the
+largest single-GPU one: saturated black oil on a 512 x 512 x 128 grid
+(33.5 M cells, 3x3 blocks, a 17 GB FP64 Jacobian), lognormal permeability
+with sigma 1.5 correlated over (4, 4, 1) cells, kz = 0.1 kx, 25 BHP wells on
+a 5 x 5 lattice, a 1-day step; inputs resident in GPU memory, every step
+restarting from the same state so the timed steps do identical work.
 
-Prints one JSON line: the step time, a roofline entry for the dominant
-kernel (algorithmic bytes over the average launch duration, measured with
-HIP events on the library's stream during the timed steps), and the CPU
-oracle's time for the same step as a reference baseline.
+Prints one JSON line: the plain FP64 step time (value), the same step with
+the FP32 preconditioner and with the FP32 preconditioner plus the learned
+pressure stage (variants, each with its distance to the FP64 solution), a
+roofline entry for the dominant kernel (the block SpMV: algorithmic bytes
+over its average launch duration, sampled with HIP events on the library's
+stream in a separate pass of identical steps), the achieved bandwidth of
+each kernel class, and the CPU oracle's time for a bounded sample of the
+same workload, scaled to one whole Newton step.
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -31,6 +37,20 @@ BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak of the device
 # the seven 3x3x3 convolutions of the pressure network
 NET_CONVS = [(3, 16, 0), (16, 32, 1), (32, 64, 2), (64, 64, 3), (64, 64, 2), (64, 32, 1), (32, 16, 0)]
 
+# workload name -> (synth generator, default shape)
+WORKLOADS = {
+    "lattice": ("black_oil_lattice", (512, 512, 128)),
+    "layered": ("black_oil_layered", (128, 128, 32)),
+    "channelised": ("black_oil_channelised", (256, 256, 64)),
+    "oil-water": ("oil_water_lognormal", (32, 32, 8)),
+}
+
+
+def make_case(workload, nx=None, ny=None, nz=None):
+    from paper_1606_00548_amd import synth
+    gen, (dnx, dny, dnz) = WORKLOADS[workload]
+    return getattr(synth, gen)(nx or dnx, ny or dny, nz or dnz)
+
 
 def network_flop(nx, ny, nz):
     """Algorithmic FLOP of one inference: 2 * 27 * C_in * C_out per output
@@ -40,7 +60,7 @@ def network_flop(nx, ny, nz):
     return conv + 2 * 16 * v0
 
 
-def network_timing(nx, ny, nz, reps=50):
+def network_timing(nx, ny, nz, reps=20):
     """Event-timed inference of the black-oil network at one grid (batch 1)."""
     import numpy as np
     import torch
@@ -60,6 +80,8 @@ def network_timing(nx, ny, nz, reps=50):
     us = 1e3 * e0.elapsed_time(e1) / reps
     gf = network_flop(nx, ny, nz) / 1e9
     net.close()
+    del x
+    torch.cuda.empty_cache()
     tflops = gf / us * 1e3          # GFLOP per microsecond -> TFLOP/s
     return {"inference_us": us, "gflop_per_inference": gf, "tflops": tflops,
             "frac_of_bf16_peak": tflops / BF16_PEAK_TFLOPS, "grid": [nx, ny, nz], "batch": 1}
@@ -111,24 +133,216 @@ def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision, levels=None
     raise ValueError(kclass)
 
 
+def cycle_lengths(st, restart=30):
+    its, cycles = st["iterations"], st["cycles"]
+    return [restart] * (cycles - 1) + [its - restart * (cycles - 1)] if cycles else []
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+# ------------------------------------------------------------------ CPU oracle
+
+def _oracle_window(args):
+    """One full Newton step of the FP64 oracle on a window of a workload,
+    single-threaded, phase by phase (runs in a worker process)."""
+    sub, = args
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cpr, krylov, model, newton
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        R, J = model.assemble(sub["grid"], sub["fluid"], sub["perm"], sub["poro"], sub["wells"],
+                              sub["x_old"], sub["x"], sub["dt"])
+        t1 = time.perf_counter()
+        pc = cpr.cpr_setup(J)
+        t2 = time.perf_counter()
+        dx, st = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), -R)
+        t3 = time.perf_counter()
+        newton.newton_update(sub["x"], dx, float(sub["fluid"]["pvt"][0][0]) if sub["fluid"]["model"] == 3 else None)
+        t4 = time.perf_counter()
+    return {"cells": int(sub["x"][0].size), "assemble_s": t1 - t0, "setup_s": t2 - t1, "solve_s": t3 - t2,
+            "update_s": t4 - t3, "iterations": int(st["iterations"]), "converged": bool(st["converged"])}
+
+
+def _windows(case, wn, count):
+    """Sub-cases: wn = (nx, ny, nz) windows of the workload centred on its
+    first `count` wells (top layers), wells clipped to the window."""
+    g = case["grid"]
+    out = []
+    for w in case["wells"][:count]:
+        i0 = min(max(w["i"] - wn[0] // 2, 0), g["nx"] - wn[0])
+        j0 = min(max(w["j"] - wn[1] // 2, 0), g["ny"] - wn[1])
+        win = (slice(0, wn[2]), slice(j0, j0 + wn[1]), slice(i0, i0 + wn[0]))
+        wells = [dict(v, i=v["i"] - i0, j=v["j"] - j0, k0=0, k1=wn[2] - 1) for v in case["wells"]
+                 if i0 <= v["i"] < i0 + wn[0] and j0 <= v["j"] < j0 + wn[1]]
+        out.append({"grid": dict(g, nx=wn[0], ny=wn[1], nz=wn[2]), "fluid": case["fluid"],
+                    "perm": case["perm"][(slice(None),) + win].copy(), "poro": case["poro"][win].copy(),
+                    "wells": wells, "x_old": case["x_old"][(slice(None),) + win].copy(),
+                    "x": case["x"][(slice(None),) + win].copy(), "dt": case["dt"]})
+    return out
+
+
+def cpu_baseline_sample(case, procs):
+    """The oracle on a bounded sample of the workload: `procs` windows of
+    128 x 128 x 16 cells (or the whole grid if it is smaller), each a full
+    Newton step in its own single-threaded process, all at once on the
+    host's cores.  Runs before anything touches the GPU."""
+    import multiprocessing as mp
+    g = case["grid"]
+    wn = (min(128, g["nx"]), min(128, g["ny"]), min(16, g["nz"]))
+    whole = wn == (g["nx"], g["ny"], g["nz"])
+    subs = _windows(case, wn, 1 if whole else procs)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(len(subs)) as pool:
+        res = pool.map(_oracle_window, [(s,) for s in subs])
+    wall = time.perf_counter() - t0
+    return {"windows": res, "window": list(wn), "whole_grid": whole, "processes": len(subs), "wall_s": wall}
+
+
+def cpu_baseline_value(sample, n, gpu_iterations, class_bytes):
+    """Scale the sampled oracle rates to one Newton step of the whole grid:
+    per-cell assembly, setup and update times, and the per-cell time of one
+    FGMRES iteration times the iterations the full system takes (the GPU's
+    FP64 count; the oracle follows the same path)."""
+    ws = sample["windows"]
+    cells = sum(w["cells"] for w in ws)
+    fixed = sum(w["assemble_s"] + w["setup_s"] + w["update_s"] for w in ws) / cells
+    per_it = sum(w["solve_s"] for w in ws) / sum(w["cells"] * w["iterations"] for w in ws)
+    value = fixed * n + per_it * n * gpu_iterations
+    return {
+        "value": value, "unit": "s/Newton step", "cores": sample["processes"], "kind": "oracle",
+        "sample": (f"{sample['processes']} window(s) of {'x'.join(map(str, sample['window']))} cells of the "
+                   f"same workload{' (the whole grid)' if sample['whole_grid'] else ', centred on wells'}, one full "
+                   "Newton step each (assemble, CPR setup, FGMRES(30) to 1e-6, update) in a single-threaded "
+                   "numpy process per window, all running at once; value = measured per-cell assembly/setup/"
+                   f"update time x {n} cells + measured per-cell-per-iteration FGMRES time x {n} cells x "
+                   f"{gpu_iterations} iterations (the whole system's FP64 count)"),
+        "sample_wall_s": sample["wall_s"], "window_iterations": [w["iterations"] for w in ws],
+        "windows_converged": all(w["converged"] for w in ws),
+        "host": {"nproc": os.cpu_count(), "cpu_model": _cpu_model()},
+        "GBps": class_bytes / value / 1e9 if class_bytes else None,
+    }
+
+
+# ------------------------------------------------------------------ GPU runs
+
+class Stepper:
+    """Times whole Newton steps of one solver and state."""
+
+    def __init__(self, solver, case):
+        import torch
+        self.torch = torch
+        self.s = solver
+        self.case = case
+        self.x_old = torch.as_tensor(case["x_old"]).cuda().contiguous()
+        self.x0 = torch.as_tensor(case["x"]).cuda().contiguous()
+        self.x = self.x0.clone()
+
+    def step(self, o, krylov="fgmres"):
+        from paper_1606_00548_amd import cprmi
+        self.x.copy_(self.x0)
+        return cprmi.newton_step(self.s, self.x_old, self.x, self.case["dt"], o, krylov=krylov)
+
+    def timed(self, o, steps, warmup, krylov="fgmres", kclass=None):
+        """Warm-up, then exactly `steps` Newton steps between two syncs.
+        Returns (s per step, per-step host times, stats, dx of the last step,
+        sampled launches, sampled ms)."""
+        torch = self.torch
+        for _ in range(warmup):
+            self.step(o, krylov)
+        if kclass:
+            self.s.profile_kernel(kclass)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts, marks, dx = [], [t0], None
+        for _ in range(steps):
+            dx, st = self.step(o, krylov)
+            sts.append(st)
+            marks.append(time.perf_counter())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = self.s.profile_read() if kclass else (0, 0.0)
+        if kclass:
+            self.s.profile_kernel(None)
+        if not all(st["status"] == 0 and st["true_rel"] <= 1e-6 for st in sts):
+            print("a timed solve did not reach the 1e-6 true relative residual", file=sys.stderr)
+            sys.exit(1)
+        return (t1 - t0) / steps, [b - a for a, b in zip(marks[:-1], marks[1:])], sts, dx, prof
+
+    def phases(self, o):
+        torch = self.torch
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        self.x.copy_(self.x0)
+        ev[0].record()
+        rhs = self.s.assemble(self.x_old, self.x, self.case["dt"])
+        ev[1].record()
+        self.s.setup(o)
+        ev[2].record()
+        dx, st = self.s.solve(rhs)
+        ev[3].record()
+        self.s.newton_update(self.x, dx)
+        ev[4].record()
+        torch.cuda.synchronize()
+        return {k: ev[i].elapsed_time(ev[i + 1]) for i, k in enumerate(["assemble", "setup", "solve", "update"])}, st
+
+
+def measured_bandwidth():
+    """STREAM triad a = b + 3 c over 3 x 1 GiB FP64 arrays and a 1 GiB
+    device copy (torch kernels), best of 5 each, in GB/s."""
+    import torch
+    ta = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    tb = torch.ones_like(ta)
+    tc = torch.ones_like(ta)
+
+    def best(fn):
+        b = None
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3
+            b = t if b is None else min(b, t)
+        return b
+    triad = 3 * ta.numel() * 8 / best(lambda: torch.add(tb, tc, alpha=3.0, out=ta)) / 1e9
+    copy = 2 * ta.numel() * 8 / best(lambda: ta.copy_(tb)) / 1e9
+    del ta, tb, tc
+    torch.cuda.empty_cache()
+    return triad, copy
+
+
+def _rel(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--kernel", default="spmv", choices=["spmv", "orth"],
-                    help="kernel class reported in the roofline entry")
-    ap.add_argument("--nx", type=int, default=128)
-    ap.add_argument("--ny", type=int, default=128)
-    ap.add_argument("--nz", type=int, default=32)
+    ap.add_argument("--workload", default="lattice", choices=sorted(WORKLOADS))
+    ap.add_argument("--nx", type=int)
+    ap.add_argument("--ny", type=int)
+    ap.add_argument("--nz", type=int)
+    ap.add_argument("--variant-steps", type=int, default=3,
+                    help="timed steps of each comparison form (at most --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the FP64 / mixed / mixed+learned comparison runs")
-    ap.add_argument("--oracle-configs", action="store_true",
-                    help="time only the CPU oracle on the other configurations (oil-water 32x32x8: a "
-                         "whole Newton step; channelised 256x256x64: assembly, setup and a sample "
-                         "of FGMRES iterations) and print one JSON line")
+                    help="skip the mixed / mixed+learned / tuned-cycle comparison runs")
+    ap.add_argument("--no-other-configs", action="store_true")
+    ap.add_argument("--kernel-only", choices=["spmv"],
+                    help="for counter runs: assemble once, then launch only this kernel 20 times and copy "
+                         "the state vector once (calibration), printing one JSON line")
     ap.add_argument("--network-only", action="store_true",
                     help="time only the pressure network's inference on the workload grid")
     args = ap.parse_args()
@@ -136,247 +350,139 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    gen, dshape = WORKLOADS[args.workload]
+    nx, ny, nz = args.nx or dshape[0], args.ny or dshape[1], args.nz or dshape[2]
     if args.network_only:
-        print(json.dumps({"network": network_timing(args.nx, args.ny, args.nz, reps=max(args.steps, 1) * 10)}))
+        print(json.dumps({"network": network_timing(nx, ny, nz, reps=max(args.steps, 1) * 10)}))
         return
-    if args.oracle_configs:
-        print(json.dumps({"oracle_configs": oracle_configs()}))
-        return
+
+    case = make_case(args.workload, nx, ny, nz)
+    n = nx * ny * nz
+    b = int(case["x"].shape[0])
+    # the CPU sample runs first, before this process initialises the GPU
+    sample = None
+    if not args.no_cpu_baseline and not args.kernel_only:
+        sample = cpu_baseline_sample(case, procs=min(4, os.cpu_count() or 1))
 
     import numpy as np
     import torch
-    from paper_1606_00548_amd import cprmi, synth
+    from paper_1606_00548_amd import cprmi, train
 
-    case = synth.black_oil_layered(args.nx, args.ny, args.nz)
-    n = args.nx * args.ny * args.nz
-    b = 3
     solver = cprmi.Solver.from_case(case)
-    x_old = torch.as_tensor(case["x_old"]).cuda().contiguous()
-    x0 = torch.as_tensor(case["x"]).cuda().contiguous()
-    x = x0.clone()
-    opts = cprmi.default_options(precision=args.precision)
+    run = Stepper(solver, case)
+    if args.kernel_only:
+        print(json.dumps(kernel_only(run, args.kernel_only, n, b)))
+        return
+    fp64 = cprmi.default_options(precision="fp64")
 
-    step_times = []   # host wall time of each timed step, per call of timed()
+    # headline: plain FP64 CPR, no per-launch events inside the timed steps
+    sec, host_times, sts, dx64, _ = run.timed(fp64, args.steps, args.warmup)
+    st = sts[-1]
+    per_cycle = cycle_lengths(st)
 
-    def timed(o, kernel=None, krylov="fgmres"):
-        """Warm-up, then exactly args.steps Newton steps between two syncs."""
-        def step():
-            x.copy_(x0)
-            dx, st = cprmi.newton_step(solver, x_old, x, case["dt"], o, krylov=krylov)
-            return st
-        for _ in range(args.warmup):
-            step()
-        if kernel:
-            solver.profile_kernel(kernel)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sts, marks = [], [t0]
-        for _ in range(args.steps):
-            sts.append(step())
-            marks.append(time.perf_counter())
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        step_times.append([b - a for a, b in zip(marks[:-1], marks[1:])])
-        prof = solver.profile_read() if kernel else (0, 0.0)
-        if kernel:
-            solver.profile_kernel(None)
-        if not all(st["status"] == 0 and st["true_rel"] <= 1e-6 for st in sts):
-            print("a timed solve did not reach the 1e-6 true relative residual", file=sys.stderr)
-            sys.exit(1)
-        return (t1 - t0) / args.steps, sts, prof
-
-    sec_per_step, stats, (launches, kernel_ms) = timed(opts, args.kernel)
-    median_ms = 1e3 * float(np.median(step_times[-1]))
-
-    # the other forms of the preconditioner on the same workload
-    variants = {}
+    # the comparison asked for by the metric, on the same workload
+    variants = {"fp64": {"s_per_step": sec, "krylov_iterations": st["iterations"], "true_rel": st["true_rel"],
+                         "speedup_vs_fp64": 1.0, "rel_diff_vs_fp64": 0.0, "nn_accepted": 0}}
+    wfile = train.weights_path("black-oil")
     if not args.no_variants:
-        from paper_1606_00548_amd import train
-        wfile = train.weights_path("black-oil")
-        forms = [("fp64", dict(precision="fp64"), "fgmres"), ("mixed", dict(precision="mixed"), "fgmres")]
-        if os.path.exists(wfile):
-            solver.attach_network(np.load(wfile))
-            forms.append(("mixed+learned", dict(precision="mixed", learned=1), "fgmres"))
-        forms.append(("bicgstab fp64", dict(precision="fp64"), "bicgstab"))
-        if os.path.exists(wfile):
-            forms.append(("bicgstab mixed+learned", dict(precision="mixed", learned=1), "bicgstab"))
-        # ABF decoupling and the F-P-F composition (CPR-FPF)
-        forms.append(("abf fp64", dict(precision="fp64", decoupling="abf"), "fgmres"))
-        forms.append(("fpf fp64", dict(precision="fp64", composition="fpf"), "fgmres"))
-        forms.append(("fpf mixed", dict(precision="mixed", composition="fpf"), "fgmres"))
-        if os.path.exists(wfile):
-            forms.append(("fpf mixed+learned", dict(precision="mixed", composition="fpf", learned=1), "fgmres"))
-            forms.append(("bicgstab fpf mixed+learned", dict(precision="mixed", composition="fpf", learned=1),
-                          "bicgstab"))
-        # a tuned cycle: more smoothing sweeps per level, V(pre, post), and an
-        # over-correction x += alpha P e with alpha = 1.25
-        tuned = dict(mg_pre=2, mg_post=2)
-        forms.append(("fp64 V(2,2)", dict(precision="fp64", **tuned), "fgmres"))
-        forms.append(("mixed V(2,2)", dict(precision="mixed", **tuned), "fgmres"))
-        tuned["mg_alpha"] = 1.25
-        forms.append(("fp64 V(2,2) alpha 1.25", dict(precision="fp64", **tuned), "fgmres"))
-        forms.append(("mixed V(2,2) alpha 1.25", dict(precision="mixed", **tuned), "fgmres"))
-        if os.path.exists(wfile):
-            forms.append(("mixed+learned V(2,2) alpha 1.25", dict(precision="mixed", learned=1, **tuned), "fgmres"))
-        for name, kw, kry in forms:
-            sp, sts, _ = timed(cprmi.default_options(**kw), krylov=kry)
-            variants[name] = {"s_per_step": sp, "krylov": kry, "krylov_iterations": sts[-1]["iterations"],
-                              "true_rel": sts[-1]["true_rel"], "speedup_vs_fp64": None,
-                              "nn_accepted": sts[-1]["nn_accepted"]}
-        for v in variants.values():
-            v["speedup_vs_fp64"] = variants["fp64"]["s_per_step"] / v["s_per_step"]
-        solver.attach_network(None)
-
-    # one whole backward-Euler step of the same workload (Algorithm 1 with
-    # the first forcing term of eq. (14), time-step cuts, variable switching)
-    time_step, simulation = {}, {}
-    if not args.no_variants:
-        from paper_1606_00548_amd import train
-        wfile = train.weights_path("black-oil")
-        forms = [("fp64", dict(precision="fp64"))]
-        if os.path.exists(wfile):
+        vs = min(args.variant_steps, args.steps)
+        forms = [("mixed", dict(precision="mixed"))]
+        if os.path.exists(wfile) and b == 3:
             solver.attach_network(np.load(wfile))
             forms.append(("mixed+learned", dict(precision="mixed", learned=1)))
+            forms.append(("fp64+learned", dict(precision="fp64", learned=1)))
         tuned = dict(mg_pre=2, mg_post=2, mg_alpha=1.25)
         forms += [("fp64 V(2,2) alpha 1.25", dict(precision="fp64", **tuned)),
                   ("mixed V(2,2) alpha 1.25", dict(precision="mixed", **tuned))]
-        xts = torch.empty_like(x0)
         for name, kw in forms:
-            lo = cprmi.default_options(**kw)
-            solver.time_step(x_old, case["dt"], options=lo, x=xts)        # warm-up
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, tst = solver.time_step(x_old, case["dt"], options=lo, x=xts)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            time_step[name] = {"s": t1 - t0, "converged": bool(tst["converged"]), "cuts": tst["cuts"],
-                               "dt_taken_days": tst["dt_taken"], "newton_iterations": tst["newton_iterations"],
-                               "linear_iterations": tst["history"]["linear_iterations"],
-                               "total_newton": tst["total_newton"], "total_linear": tst["total_linear"],
-                               "undersaturated_cells": int((xts[2] < 0).sum())}
-            # the same day with step growth from 0.01 day (cpr_simulate)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, sst = solver.simulate(x_old, case["dt"], 0.01, case["dt"], options=lo, x=xts)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            simulation[name] = {"s": t1 - t0, "completed": bool(sst["completed"]), "steps": sst["steps"],
-                                "cuts": sst["cuts"], "total_newton": sst["total_newton"],
-                                "total_linear": sst["total_linear"], "dts_days": sst["dts"],
-                                "undersaturated_cells": int((xts[2] < 0).sum())}
+            sp, _, vsts, dxv, _ = run.timed(cprmi.default_options(**kw), vs, 1)
+            variants[name] = {"s_per_step": sp, "krylov_iterations": vsts[-1]["iterations"],
+                              "true_rel": vsts[-1]["true_rel"], "speedup_vs_fp64": sec / sp,
+                              "rel_diff_vs_fp64": _rel(dxv, dx64), "nn_accepted": vsts[-1]["nn_accepted"],
+                              "fp64_fallback_after_cycle": vsts[-1].get("fp64_fallback", 0)}
         solver.attach_network(None)
 
-    # per-phase breakdown of one more (untimed) step
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-    x.copy_(x0)
-    ev[0].record()
-    rhs = solver.assemble(x_old, x, case["dt"])
-    ev[1].record()
-    solver.setup(opts)
-    ev[2].record()
-    dx, st = solver.solve(rhs)
-    ev[3].record()
-    solver.newton_update(x, dx)
-    ev[4].record()
-    torch.cuda.synchronize()
-    phases = {k: ev[i].elapsed_time(ev[i + 1]) for i, k in
-              enumerate(["assemble", "setup", "solve", "update"])}
-    # restart-cycle lengths of the timed solves (identical every step)
-    its, cycles = st["iterations"], st["cycles"]
-    per_cycle = [30] * (cycles - 1) + [its - 30 * (cycles - 1)] if cycles else []
-    alg_bytes, alg_launches = algorithmic_bytes(args.kernel, b, n, per_cycle, args.precision)  # spmv / orth
-    avg_ms = kernel_ms / max(launches, 1)
-    achieved = (alg_bytes / alg_launches) / (avg_ms * 1e-3) / 1e9 if launches else None
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"{args.kernel}_traffic.json")
-    if os.path.exists(tfile):
-        info = json.load(open(tfile))
-        if info.get("workload_cells") == n and info.get("source_sha") == _kernel_sha(args.kernel):
-            traffic = info.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": args.kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "traffic": traffic, "launches_sampled": launches,
-                "avg_launch_us": avg_ms * 1e3,
-                "algorithmic_bytes_per_launch": alg_bytes / max(alg_launches, 1)}
-    if launches != alg_launches * args.steps:
-        roofline["note"] = f"sampled {launches} launches, expected {alg_launches * args.steps}"
+    phases, _ = run.phases(fp64)
 
-    # achieved bandwidth of each bandwidth-bound kernel class (FP64 form)
+    # achieved bandwidth of each bandwidth-bound kernel class (FP64 form),
+    # HIP events around every launch of the class, one class per pass
     levels = []
     while solver.mg_level_shape(len(levels)) is not None:
         levels.append(int(np.prod(solver.mg_level_shape(len(levels)))))
+    ks = min(2, args.steps)
     classes = {}
     for cls in ("spmv", "orth", "smooth", "ilu"):
-        _, _, (nl, ms) = timed(cprmi.default_options(precision="fp64"), cls)
+        _, _, _, _, (nl, ms) = run.timed(fp64, ks, 0, kclass=cls)
         ab, al = algorithmic_bytes(cls, b, n, per_cycle, "fp64", levels)
-        gbs = ab * args.steps / (ms * 1e-3) / 1e9 if ms > 0 else None
-        classes[cls] = {"launches_per_step": nl / args.steps, "expected_launches_per_step": al,
-                        "ms_per_step": ms / args.steps, "avg_launch_us": 1e3 * ms / max(nl, 1),
+        gbs = ab * ks / (ms * 1e-3) / 1e9 if ms > 0 else None
+        classes[cls] = {"launches_per_step": nl / ks, "expected_launches_per_step": al,
+                        "ms_per_step": ms / ks, "avg_launch_us": 1e3 * ms / max(nl, 1),
                         "algorithmic_bytes_per_step": ab, "GBps": gbs,
                         "frac": gbs / HBM_PEAK_GBS if gbs else None}
-
-    # measured HBM bandwidth on this device: STREAM triad a = b + 3 c over
-    # 3 x 1 GiB FP64 arrays (torch elementwise kernel), best of 5
-    ta = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-    tb = torch.ones_like(ta)
-    tc = torch.ones_like(ta)
-    best = None
-    for _ in range(5):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        torch.add(tb, tc, alpha=3.0, out=ta)
-        e1.record()
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) * 1e-3
-        best = t if best is None else min(best, t)
-    triad_gbs = 3 * ta.numel() * 8 / best / 1e9
-    # and a device-to-device copy of 1 GiB (the runtime's copy kernel), best of 5
-    bestc = None
-    for _ in range(5):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        ta.copy_(tb)
-        e1.record()
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) * 1e-3
-        bestc = t if bestc is None else min(bestc, t)
-    copy_gbs = 2 * ta.numel() * 8 / bestc / 1e9
-    del ta, tb, tc
-    roofline["measured_triad_GBps"] = triad_gbs
-    roofline["measured_copy_GBps"] = copy_gbs
-    roofline["frac_of_measured_triad"] = (achieved / triad_gbs) if achieved else None
+    sp = classes["spmv"]
+    ab, al = algorithmic_bytes("spmv", b, n, per_cycle, "fp64")
+    avg_ms = sp["ms_per_step"] / max(sp["launches_per_step"], 1)
+    achieved = (ab / al) / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "spmv_traffic.json")
+    if os.path.exists(tfile):
+        info = json.load(open(tfile))
+        if info.get("workload_cells") == n and info.get("source_sha") == _kernel_sha("spmv"):
+            traffic = info.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": "spmv_kernel<3>" if (b == 3 and n > (1 << 20)) else "spmv",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic, "launches_sampled": int(sp["launches_per_step"] * ks),
+                "avg_launch_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": ab / al,
+                "timing": f"HIP events around every SpMV launch on the library's stream during {ks} extra "
+                          "FP64 Newton steps identical to the timed ones"}
+    triad, copy = measured_bandwidth()
+    roofline.update(measured_triad_GBps=triad, measured_copy_GBps=copy, frac_of_measured_triad=achieved / triad)
     for v in classes.values():
-        v["frac_of_measured_triad"] = v["GBps"] / triad_gbs if v["GBps"] else None
-    # the four bandwidth-bound classes together over the whole solve phase
+        v["frac_of_measured_triad"] = v["GBps"] / triad if v["GBps"] else None
     class_bytes = sum(v["algorithmic_bytes_per_step"] for v in classes.values())
     solve_gbps = class_bytes / (phases["solve"] * 1e-3) / 1e9
+    run = None
+    solver.close()
+    torch.cuda.empty_cache()
 
-    network = network_timing(args.nx, args.ny, args.nz)
-    configs = other_configs() if not args.no_variants else {}
+    network = network_timing(nx, ny, nz) if (b == 3 and nx % 8 == 0 and ny % 8 == 0 and nz % 8 == 0) else None
+    configs = other_configs() if not (args.no_variants or args.no_other_configs) else {}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(case)
-        # the oracle moves the same algorithmic bytes for the step
-        cpu["GBps"] = class_bytes / cpu["value"] / 1e9
+    cpu = cpu_baseline_value(sample, n, st["iterations"], class_bytes) if sample else None
     out = {
-        "metric": METRIC, "value": sec_per_step, "unit": "s/Newton step", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec_per_step * 1e3,
+        "metric": METRIC, "value": sec, "unit": "s/Newton step", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
-        "data": "synthetic",
-        "config": {"workload": f"black-oil layered {args.nx}x{args.ny}x{args.nz} "
-                               f"({n} cells, 3x3 blocks), one Newton step, FGMRES(30) to 1e-6",
-                   "cells": n, "block": b, "precision": args.precision, "restart": 30, "rtol": 1e-6,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{case['name']} ({n} cells, {b}x{b} blocks), one Newton step, FGMRES(30) to 1e-6, "
+                               "plain FP64 CPR",
+                   "cells": n, "block": b, "precision": "fp64", "restart": 30, "rtol": 1e-6, "dt_days": case["dt"],
                    "preconditioner": "quasi-IMPES CPR, P-then-F, multigrid V(1,1), alpha 1, coarsest <= 512 "
                                      "cells, red-black block ILU(0)"},
-        "median_ms_per_step": median_ms,
-        "fgmres_iterations": its, "restart_cycles": cycles, "true_rel": st["true_rel"],
-        "solve_class_bytes_GBps": solve_gbps, "network": network,
-        "phases_ms": phases, "roofline": roofline, "kernel_classes": classes, "cpu_baseline": cpu,
-        "variants": variants, "time_step": time_step, "simulation": simulation, "other_configs": configs,
+        "median_ms_per_step": 1e3 * float(np.median(host_times)),
+        "fgmres_iterations": st["iterations"], "restart_cycles": st["cycles"], "true_rel": st["true_rel"],
+        "phases_ms": phases, "solve_class_bytes_GBps": solve_gbps, "roofline": roofline,
+        "kernel_classes": classes, "cpu_baseline": cpu, "variants": variants, "network": network,
+        "other_configs": configs,
     }
     print(json.dumps(out))
+
+
+def kernel_only(run, kclass, n, b):
+    """Assemble once, then 20 SpMV launches and one copy of the state
+    vector (the calibration transfer for the memory counters)."""
+    import torch
+    s = run.s
+    rhs = s.assemble(run.x_old, run.x, run.case["dt"])
+    xin = torch.randn_like(rhs)
+    y = torch.empty_like(rhs)
+    for _ in range(20):
+        s.spmv(xin, y)
+    cp = torch.empty_like(rhs)
+    cp.copy_(rhs)
+    torch.cuda.synchronize()
+    return {"kernel": kclass, "launches": 20, "cells": n, "copy_bytes": rhs.numel() * 8,
+            "source_sha": _kernel_sha(kclass)}
 
 
 def _kernel_sha(kclass):
@@ -387,99 +493,64 @@ def _kernel_sha(kclass):
 
 
 def other_configs(steps=2):
-    """One Newton step of the small oil-water system (32x32x8, latency
-    regime) and of the first system of the channelised 256x256x64 black-oil
-    10-day step (bandwidth regime), FP64 and mixed precision, with the
-    default V(1,1) cycle and with the tuned V(2,2), alpha 1.25 one; each
-    timed step restarts from the same state."""
+    """The other workloads, each timed per Newton step from the same state:
+    the layered 128x128x32 black oil (FP64, mixed, mixed + learned, and the
+    tuned V(2,2), alpha 1.25 cycle; plus one whole backward-Euler day by
+    time stepping), the oil-water 32x32x8 system (latency regime) and the
+    first system of the channelised 256x256x64 black-oil 10-day step."""
     import numpy as np
     import torch
-    from paper_1606_00548_amd import cprmi, synth
+    from paper_1606_00548_amd import cprmi, synth, train
     out = {}
-    for name, make in (("oil-water 32x32x8", lambda: synth.oil_water_lognormal()),
-                       ("black-oil channelised 256x256x64, first system of the 10-day step",
-                        lambda: synth.black_oil_channelised())):
+    wfile = train.weights_path("black-oil")
+    tuned = dict(mg_pre=2, mg_post=2, mg_alpha=1.25)
+    for name, make, learned in (
+            ("black-oil layered 128x128x32", lambda: synth.black_oil_layered(), True),
+            ("oil-water 32x32x8", lambda: synth.oil_water_lognormal(), False),
+            ("black-oil channelised 256x256x64, first system of the 10-day step",
+             lambda: synth.black_oil_channelised(), False)):
         case = make()
         s = cprmi.Solver.from_case(case)
-        x_old = torch.as_tensor(case["x_old"]).cuda().contiguous()
-        x0 = torch.as_tensor(case["x"]).cuda().contiguous()
-        x = x0.clone()
+        run = Stepper(s, case)
         res = {"cells": int(np.prod(case["x"].shape[1:])), "block": int(case["x"].shape[0])}
-        forms = (("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed")),
-                 ("fp64 V(2,2) alpha 1.25", dict(precision="fp64", mg_pre=2, mg_post=2, mg_alpha=1.25)),
-                 ("mixed V(2,2) alpha 1.25", dict(precision="mixed", mg_pre=2, mg_post=2, mg_alpha=1.25)))
+        forms = [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed")),
+                 ("fp64 V(2,2) alpha 1.25", dict(precision="fp64", **tuned)),
+                 ("mixed V(2,2) alpha 1.25", dict(precision="mixed", **tuned))]
+        if learned and os.path.exists(wfile):
+            s.attach_network(np.load(wfile))
+            forms.insert(2, ("mixed+learned", dict(precision="mixed", learned=1)))
+        dx64 = None
         for prec, kw in forms:
-            o = cprmi.default_options(**kw)
-
-            def step():
-                x.copy_(x0)
-                _, st = cprmi.newton_step(s, x_old, x, case["dt"], o)
-                return st
-            step()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            sts = [step() for _ in range(steps)]
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            ok = all(st["status"] == 0 and st["true_rel"] <= 1e-6 for st in sts)
-            res[prec] = {"ms_per_step": 1e3 * (t1 - t0) / steps, "iterations": sts[-1]["iterations"],
-                         "true_rel": sts[-1]["true_rel"], "reached_1e-6": ok}
+            sp, _, sts, dx, _ = run.timed(cprmi.default_options(**kw), steps, 1)
+            if prec == "fp64":
+                dx64 = dx.clone()
+            res[prec] = {"ms_per_step": 1e3 * sp, "iterations": sts[-1]["iterations"],
+                         "true_rel": sts[-1]["true_rel"], "rel_diff_vs_fp64": _rel(dx, dx64)}
+        if learned and os.path.exists(wfile):
+            # one backward-Euler day: a single 1-day step (with its cuts) and
+            # the same day by time stepping from 0.01 day with growth
+            for prec, kw in (("fp64", dict(precision="fp64")), ("mixed+learned", dict(precision="mixed", learned=1))):
+                lo = cprmi.default_options(**kw)
+                xts = torch.empty_like(run.x0)
+                s.time_step(run.x_old, case["dt"], options=lo, x=xts)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, tst = s.time_step(run.x_old, case["dt"], options=lo, x=xts)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, sst = s.simulate(run.x_old, case["dt"], 0.01, case["dt"], options=lo, x=xts)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                res[f"time_step {prec}"] = {"s": t1 - t0, "cuts": tst["cuts"], "total_newton": tst["total_newton"],
+                                            "total_linear": tst["total_linear"], "converged": bool(tst["converged"])}
+                res[f"simulation {prec}"] = {"s": t2 - t1, "steps": sst["steps"], "cuts": sst["cuts"],
+                                             "total_newton": sst["total_newton"], "total_linear": sst["total_linear"],
+                                             "completed": bool(sst["completed"])}
+        s.attach_network(None)
+        run = None
         s.close()
-        del x_old, x0, x
         torch.cuda.empty_cache()
         out[name] = res
-    return out
-
-
-def cpu_baseline(case):
-    """The FP64 oracle's time for the same Newton step (single thread)."""
-    from threadpoolctl import threadpool_limits
-
-    from oracle import newton
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        _, _, st, _ = newton.newton_step(case["grid"], case["fluid"], case["perm"], case["poro"],
-                                         case["wells"], case["x_old"], case["x"], case["dt"])
-        t1 = time.perf_counter()
-    return {"value": t1 - t0, "unit": "s/Newton step", "cores": 1, "kind": "oracle",
-            "sample": "one full Newton step (assemble, CPR setup, FGMRES(30) to 1e-6, update) "
-                      "of the same workload, numpy/scipy single-threaded",
-            "iterations": st["iterations"]}
-
-
-def oracle_configs(sample_iterations=10):
-    """The FP64 oracle, single-threaded, on the other configurations: the
-    whole Newton step of the oil-water 32x32x8 system; for the channelised
-    256x256x64 system (whose step takes about a hundred FGMRES iterations)
-    the assembly, the CPR setup and the first `sample_iterations` FGMRES
-    iterations, timed separately and reported as measured."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-
-    from oracle import cpr, krylov, model, newton
-    from paper_1606_00548_amd import synth
-    out = {}
-    with threadpool_limits(limits=1):
-        case = synth.oil_water_lognormal()
-        t0 = time.perf_counter()
-        _, _, st, _ = newton.newton_step(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
-                                         case["x_old"], case["x"], case["dt"])
-        out["oil-water 32x32x8"] = {"s_per_newton_step": time.perf_counter() - t0,
-                                    "iterations": st["iterations"], "cores": 1}
-        case = synth.black_oil_channelised()
-        t0 = time.perf_counter()
-        R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
-                              case["x_old"], case["x"], case["dt"])
-        t1 = time.perf_counter()
-        pc = cpr.cpr_setup(J)
-        t2 = time.perf_counter()
-        _, st = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), -R,
-                              rtol=0.0, max_iter=sample_iterations)
-        t3 = time.perf_counter()
-        out["black-oil channelised 256x256x64"] = {
-            "assemble_s": t1 - t0, "setup_s": t2 - t1, "fgmres_iterations_sampled": st["iterations"],
-            "s_per_fgmres_iteration": (t3 - t2) / st["iterations"], "cores": 1,
-            "cells": int(np.prod(case["x"].shape[1:]))}
     return out
 
 

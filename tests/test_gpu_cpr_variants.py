@@ -4,7 +4,7 @@ Sec. 2.5 of the paper names ABF beside quasi-IMPES and applies CPR-FPF;
 both are options of cpr_setup.  Tolerances as for the default
 preconditioner (FP64 on both sides, different summation orders):
   * multigrid levels 1e-12 of the row scale, ILU diagonal inverses 1e-10;
-  * one FP64 application 1e-9 in norm, FP32 application 1e-4;
+  * one FP64 application 1e-9 in norm, FP32 application 1e-5;
   * FGMRES: the same number of iterations, ||x_gpu - x_oracle|| <= 1e-8
     ||x_oracle||, true relative residual <= 1e-6 (FP64 and mixed);
   * BiCGSTAB: converged with the iteration count within the spread that
@@ -116,7 +116,7 @@ def test_variant_mixed_precision(system, decoupling, composition):
     res = np.linalg.norm(b - cpr.block_spmv(J, _np(dx))) / np.linalg.norm(b)
     print(f"[variants] {name} {decoupling}/{composition} mixed: apply rel. diff {apply_err:.2e}, "
           f"{st['iterations']} iterations, true rel. residual {res:.2e}")
-    assert apply_err <= 1e-4
+    assert apply_err <= 1e-5
     assert st["status"] == 0 and res <= 1e-6
     s.close()
 
@@ -230,7 +230,7 @@ def test_coarse_correction_scaling_matches_oracle(system, alpha, pre, post):
 @pytest.mark.parametrize("decoupling,composition", VARIANTS)
 def test_tuned_cycle_in_every_variant(system, decoupling, composition):
     # V(2,2) with alpha 1.25 inside ABF / F-P-F: FP64 to the oracle's
-    # tolerance, FP32 within 1e-4 of it and still reaching 1e-6
+    # tolerance, FP32 within 1e-5 of it and still reaching 1e-6
     name, case, J, b, _ = system
     from paper_1606_00548_amd import cprmi
     tuned = dict(mg_pre=2, mg_post=2, mg_alpha=1.25)
@@ -252,6 +252,6 @@ def test_tuned_cycle_in_every_variant(system, decoupling, composition):
     print(f"[variants] {name} {decoupling}/{composition} tuned: FGMRES {st['iterations']} (oracle "
           f"{so['iterations']}); mixed apply diff {np.linalg.norm(zf - ref) / np.linalg.norm(ref):.1e}, "
           f"{stf['iterations']} iterations, true rel. {res:.1e}")
-    assert np.linalg.norm(zf - ref) <= 1e-4 * np.linalg.norm(ref)
+    assert np.linalg.norm(zf - ref) <= 1e-5 * np.linalg.norm(ref)
     assert stf["status"] == 0 and res <= 1e-6
     s.close()

@@ -144,6 +144,42 @@ def test_channelised_256x256x64_ten_days_mixed_vs_fp64():
     s.close()
 
 
+def test_channelised_256x256x64_cpr_and_fgmres_path_match_oracle():
+    # Above 1 M cells the library runs the four-wave SpMV and a six-level
+    # hierarchy; on the GPU's own Jacobian of this system the oracle's CPR
+    # setup, one application (1e-9) and a fixed FGMRES path of five
+    # iterations (rtol = 0, 1e-8) must match the GPU's.
+    from oracle import cpr, krylov
+    from paper_1606_00548_amd import cprmi
+    print("[full-size] black oil channelised 256x256x64: CPR and FGMRES path vs oracle", flush=True)
+    case = synth.black_oil_channelised()
+    s = cprmi.Solver.from_case(case)
+    rhs = s.assemble(_gpu(case["x_old"]), _gpu(case["x"]), case["dt"])
+    torch.cuda.synchronize()
+    J = s.export_jacobian().cpu().numpy()
+    b = rhs.cpu().numpy()
+    s.setup(rtol=0.0, max_iter=5)
+    levels = 0
+    while s.mg_level_shape(levels) is not None:
+        levels += 1
+    pc = cpr.cpr_setup(J)
+    assert levels == len(pc["mg"]["levels"]) >= 6
+    v = b / np.linalg.norm(b)
+    z = s.precond(_gpu(v)).cpu().numpy()
+    ref = cpr.cpr_apply(pc, v)
+    d_apply = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    dx, st = s.solve(rhs)
+    xo, so = krylov.fgmres(lambda u: cpr.block_spmv(J, u), lambda u: cpr.cpr_apply(pc, u), b,
+                           rtol=0.0, max_iter=5)
+    d_path = np.linalg.norm(dx.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"[full-size]   {levels} multigrid levels; one application rel. diff {d_apply:.1e}; "
+          f"5 FGMRES iterations rel. diff {d_path:.1e}", flush=True)
+    assert d_apply <= 1e-9
+    assert st["iterations"] == so["iterations"] == 5 and st["status"] == 1
+    assert d_path <= 1e-8
+    s.close()
+
+
 def test_lattice_512x512x128_mixed_learned_vs_fp64():
     from paper_1606_00548_amd import cprmi, train
     print("[full-size] black oil lattice 512x512x128 (33.5 M cells)", flush=True)

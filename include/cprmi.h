@@ -348,6 +348,19 @@ int cpr_newton_update(cpr_ctx_t* ctx, double* x, const double* dx);
 int cpr_spmv(cpr_ctx_t* ctx, const double* x, double* y);
 int cpr_precond_apply(cpr_ctx_t* ctx, const double* v, double* z);
 
+/* For callers that cannot allocate device memory during a call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * product of cpr_spmv, y = A x (device, natural order, cells then rate-well
+ * BHPs), staged through a static device buffer of the library instead of
+ * the context's own vectors; the call allocates nothing.  The buffer holds
+ * two staging vectors of cpr_spmv_noalloc_max_unknowns() = 4,194,304
+ * doubles each (64 MiB in all, kept by every GPU the library runs on until
+ * the process ends); a context with more unknowns gets CPR_EINVAL.  All
+ * calls on one GPU share the buffer: calls that overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller. */
+int cpr_spmv_noalloc(cpr_ctx_t* ctx, const double* x, double* y);
+long long cpr_spmv_noalloc_max_unknowns(void);
+
 /* Setup products, for verification (device outputs, natural order):
  * quasi-IMPES weights w [b][n] (CPR_EINVAL under ABF); the scalar 7-point operator of multigrid
  * level `level` as [7][n_level] (natural order of that level's grid);

@@ -149,7 +149,7 @@ EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error",
            "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov", "cpr_nn_eval_loss",
            "cpr_nn_make_target", "cpr_nn_infer", "cpr_bicgstab_solve", "cpr_default_newton_options",
            "cpr_time_step", "cpr_simulate", "cpr_num_unknowns", "cpr_set_allocator", "cpr_nn_get_adam",
-           "cpr_nn_set_adam"]
+           "cpr_nn_set_adam", "cpr_spmv_noalloc", "cpr_spmv_noalloc_max_unknowns"]
 KCLASS = {"spmv": 0, "orth": 1, "smooth": 2, "ilu": 3, "assemble": 4}
 
 
@@ -188,6 +188,8 @@ def load():
     lib.cpr_newton_update.argtypes = [P, P, P]
     lib.cpr_spmv.argtypes = [P, P, P]
     lib.cpr_precond_apply.argtypes = [P, P, P]
+    lib.cpr_spmv_noalloc.argtypes = [P, P, P]
+    lib.cpr_spmv_noalloc_max_unknowns.restype = ctypes.c_longlong
     lib.cpr_export_qimpes.argtypes = [P, P]
     lib.cpr_mg_level_shape.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -522,6 +524,13 @@ class Solver:
     def spmv(self, x, y=None):
         y = self.vector() if y is None else y
         self._check(self.lib.cpr_spmv(self.ctx, _ptr(x), _ptr(y)))
+        return y
+
+    def spmv_noalloc(self, x, y):
+        """y = A x like spmv(), staged through the library's static device
+        buffer (cpr_spmv_noalloc: the call allocates nothing; y must be
+        given)."""
+        self._check(self.lib.cpr_spmv_noalloc(self.ctx, _ptr(x), _ptr(y)))
         return y
 
     def precond(self, v, z=None):

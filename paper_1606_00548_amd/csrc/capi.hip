@@ -686,7 +686,7 @@ int cpr_export_qimpes(cpr_ctx_t* ctx, double* w) {
 int cpr_mg_level_shape(const cpr_ctx_t* ctx, int level, int* nx, int* ny, int* nz) {
   if (!ctx || level < 0 || level >= (int)ctx->levels.size() || !nx || !ny || !nz) return CPR_EINVAL;
   const Lay& L = ctx->levels[level].lay;
-  *nx = L.nx; *ny = L.ny; *nz = L.nz;
+  *nx = L.nxr; *ny = L.ny; *nz = L.nz;
   return CPR_OK;
 }
 

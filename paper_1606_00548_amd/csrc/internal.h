@@ -7,8 +7,12 @@
 // the +-y / +-z neighbours of a cell sit at a fixed offset in the other half.
 // A block array holds one plane of n values per (direction, row, column):
 // A[((d * b + r) * b + c) * n + cell], directions d = self, -x, +x, -y, +y,
-// -z, +z.  Multigrid levels whose nx is odd (only ever the coarsest) use the
-// natural order i + nx * (j + ny * k).
+// -z, +z.  A multigrid level above the coarsest whose nx is odd is stored
+// colour-split on a grid one column wider: the extra column (i = nxr) holds
+// ghost cells whose stencil row is the identity and to which no real cell
+// couples, so they keep x = 0 and r = 0 through every sweep and add nothing
+// to a restriction.  The coarsest level with an odd nx uses the natural
+// order i + nx * (j + ny * k).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -32,11 +36,12 @@ void dev_free(const DevAlloc& a, void* p);
 #define CPR_MAX_WELLS_PERF 65536
 
 struct Lay {
-  int nx, ny, nz;
-  int n;     // cells
+  int nx, ny, nz;  // stored grid (nx includes a ghost column on padded levels)
+  int n;     // stored cells
   int half;  // nx / 2 (colour-split only)
   int nh;    // n / 2 (colour-split only)
   int cs;    // 1 colour-split, 0 natural
+  int nxr;   // real cells along x: nx, or nx - 1 on a padded level
 };
 
 __host__ __device__ inline int lay_index(const Lay& L, int i, int j, int k) {
@@ -139,8 +144,20 @@ inline Lay make_lay(int nx, int ny, int nz, bool want_cs) {
   L.cs = (want_cs && (nx % 2 == 0)) ? 1 : 0;
   L.half = L.cs ? nx / 2 : 0;
   L.nh = L.cs ? L.n / 2 : 0;
+  L.nxr = nx;
   return L;
 }
+
+// Colour-split layout of a grid with nxr real columns: an odd nxr gets one
+// ghost column (see the storage notes at the top of this file).
+inline Lay make_padded_lay(int nxr, int ny, int nz) {
+  Lay L = make_lay(nxr + (nxr & 1), ny, nz, true);
+  L.nxr = nxr;
+  return L;
+}
+
+// Cells of the real grid of a layout.
+inline long lay_real_cells(const Lay& L) { return (long)L.nxr * L.ny * L.nz; }
 
 // Fluid description passed to kernels by value.
 struct FluidDev {

@@ -158,7 +158,9 @@ __global__ void abf_kernel(int n, const double* __restrict__ J, double* __restri
 // Galerkin coarse operator for piecewise-constant 2x2x2 aggregation: eight
 // lanes per coarse cell, one per fine cell of its aggregate, each sorting
 // its stencil row into the coarse couplings (inside the aggregate: the
-// diagonal); the eight partial rows are summed by a fixed butterfly.
+// diagonal); the eight partial rows are summed by a fixed butterfly.  Ghost
+// cells of a padded fine level take no part; a ghost coarse cell gets the
+// identity row.
 __global__ __launch_bounds__(256) void rap_kernel(Lay F, Lay C, const double* __restrict__ Af,
                                                   double* __restrict__ Ac) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(256) void rap_kernel(Lay F, Lay C, const double* __
   if (tc < C.n) {
     lay_coords(C, tc, ci, cj, ck);
     const int fi = 2 * ci + (sub & 1), fj = 2 * cj + ((sub >> 1) & 1), fk = 2 * ck + (sub >> 2);
-    if (fi < F.nx && fj < F.ny && fk < F.nz) {
+    if (fi < F.nxr && fj < F.ny && fk < F.nz) {
       const int f = lay_index(F, fi, fj, fk);
       acc[0] += Af[f];
 #pragma unroll
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(256) void rap_kernel(Lay F, Lay C, const double* __
         int di, dj, dk;
         dir_offset(d, di, dj, dk);
         const int gi = fi + di, gj = fj + dj, gk = fk + dk;
-        if (gi < 0 || gi >= F.nx || gj < 0 || gj >= F.ny || gk < 0 || gk >= F.nz) continue;
+        if (gi < 0 || gi >= F.nxr || gj < 0 || gj >= F.ny || gk < 0 || gk >= F.nz) continue;
         const double a = Af[(size_t)d * F.n + f];
         if ((gi >> 1) == ci && (gj >> 1) == cj && (gk >> 1) == ck)
           acc[0] += a;
@@ -191,8 +193,13 @@ __global__ __launch_bounds__(256) void rap_kernel(Lay F, Lay C, const double* __
     acc[d] += __shfl_xor(acc[d], 2, 8);
     acc[d] += __shfl_xor(acc[d], 4, 8);
   }
-  if (tc < C.n && sub == 0)
+  if (tc < C.n && sub == 0) {
+    if (ci >= C.nxr) {
+      acc[0] = 1.0;
+      for (int d = 1; d < 7; ++d) acc[d] = 0.0;
+    }
     for (int d = 0; d < 7; ++d) Ac[(size_t)d * C.n + tc] = acc[d];
+  }
 }
 
 // Dense [M | I] (row-major, 2*nc columns) of the coarsest 7-point operator,
@@ -522,21 +529,29 @@ static void free_levels(cpr_ctx* ctx) {
 
 void release_hierarchy(cpr_ctx* ctx) { free_levels(ctx); }
 
+// Level shapes: each coarse grid has ceil(n/2) cells per axis of the real
+// grid above it; coarsening continues while a level has more than
+// mg_coarsest real cells.  Smoothed levels are colour-split (padded with a
+// ghost column when nx is odd); the coarsest is colour-split for even nx and
+// natural otherwise.
 static int build_hierarchy(cpr_ctx* ctx) {
   int coarsest = ctx->opt.mg_coarsest;
   std::vector<Lay> shapes;
   shapes.push_back(ctx->lay);
-  while (shapes.back().n > coarsest) {
+  while (lay_real_cells(shapes.back()) > coarsest) {
     const Lay& f = shapes.back();
-    if (!f.cs)
-      return set_err(ctx, CPR_EINVAL, "multigrid level with odd nx has more than mg_coarsest cells");
-    shapes.push_back(make_lay((f.nx + 1) / 2, (f.ny + 1) / 2, (f.nz + 1) / 2, true));
+    const int nx = (f.nxr + 1) / 2, ny = (f.ny + 1) / 2, nz = (f.nz + 1) / 2;
+    if ((long)nx * ny * nz > coarsest)
+      shapes.push_back(make_padded_lay(nx, ny, nz));
+    else
+      shapes.push_back(make_lay(nx, ny, nz, true));
   }
   if (shapes.back().n > 4096) return set_err(ctx, CPR_EINVAL, "coarsest level too large");
   bool same = shapes.size() == ctx->levels.size();
   for (size_t l = 0; same && l < shapes.size(); ++l)
     same = shapes[l].nx == ctx->levels[l].lay.nx && shapes[l].ny == ctx->levels[l].lay.ny &&
-           shapes[l].nz == ctx->levels[l].lay.nz && shapes[l].cs == ctx->levels[l].lay.cs;
+           shapes[l].nz == ctx->levels[l].lay.nz && shapes[l].cs == ctx->levels[l].lay.cs &&
+           shapes[l].nxr == ctx->levels[l].lay.nxr;
   if (same) return CPR_OK;
   free_levels(ctx);
   ctx->levels.resize(shapes.size());

@@ -168,6 +168,27 @@ def black_oil_lattice(nx=512, ny=512, nz=128, seed=5000):
                  f"black-oil lattice {nx}x{ny}x{nz}")
 
 
+def spe10_shaped_oil_water(nx=60, ny=220, nz=85, seed=8000):
+    """The shape of the paper's SPE10 oil-water model (Sec. 3.1: 60 x 220 x 85
+    cells of 20 x 10 x 2 ft, permeability between 6.65e-7 and 20 Darcy,
+    porosity up to 0.5, one injector and four producers), filled with
+    synthetic fields: ln kx = ln 50 mD + 2.5 G with G a Gaussian field of
+    correlation (1, 8, 4) cells in (z, y, x), clipped to the quoted range;
+    ky = kx, kz = 0.1 kx (clipped likewise); porosity 0.2 + 0.1 G' clipped to
+    [0.01, 0.5]; injector in the centre, producers in the corners; dt 1 day.
+    None of the benchmark's own data is used."""
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    lo, hi = 6.65e-4, 2.0e4
+    kx = np.clip(np.exp(np.log(50.0) + 2.5 * gaussian_field(rng, shape, (1.0, 8.0, 4.0))), lo, hi)
+    perm = np.stack([kx, kx, np.clip(0.1 * kx, lo, hi)])
+    poro = np.clip(0.2 + 0.1 * gaussian_field(rng, shape, (1.0, 8.0, 4.0)), 0.01, 0.5)
+    ft = 0.3048
+    grid = grid_of(nx, ny, nz, dx=20 * ft, dy=10 * ft, dz=2 * ft)
+    return _case(grid, OIL_WATER, perm, poro, five_spot(nx, ny, nz), 1.0,
+                 f"oil-water SPE10-shaped {nx}x{ny}x{nz}")
+
+
 def oil_water_training(nx=64, ny=64, nz=32, seed=5000):
     """Pressure-stage training systems: ln k sigma ~ U(0.5, 1.5), horizontal
     correlation ~ U{2..8}, vertical 1; S_w a Gaussian field mapped to

@@ -66,15 +66,16 @@ struct Pre<float> {
   static float* Y(cpr_ctx* c) { return c->Yf; }
 };
 
-// Decoupled block entry (d, r, c) of cell t.  FP64: row 0 lives in R0
-// [7][b][n]; FP32: the copy holds full decoupled blocks [7][b][b][n].
+// Decoupled block entry (d, r, c) of cell t (tiled arrays).  FP64: row 0
+// lives in R0 (7 b planes), rows >= 1 in J (7 b^2 planes); FP32: the copy
+// holds the full decoupled blocks (7 b^2 planes).
 template <int B, typename T>
 __device__ inline T at_blk(const T* __restrict__ J, const T* __restrict__ R0, size_t N, int d, int r,
                            int c, int t) {
   if constexpr (sizeof(T) == 8) {
-    return r == 0 ? ldnt(R0 + ((size_t)d * B + c) * N + t) : ldnt(J + ((size_t)(d * B + r) * B + c) * N + t);
+    return r == 0 ? ldnt(R0 + tix(7 * B, d * B + c, t)) : ldnt(J + tix(7 * B * B, (d * B + r) * B + c, t));
   } else {
-    return ldnt(J + ((size_t)(d * B + r) * B + c) * N + t);
+    return ldnt(J + tix(7 * B * B, (d * B + r) * B + c, t));
   }
 }
 
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(256) void decouple_full_kernel(int n, int nh, const
       for (int r = 0; r < B; ++r) {
         T a = 0;
 #pragma unroll
-        for (int c = 0; c < B; ++c) a += Dinv[((size_t)r * B + c) * N + t] * rr[c];
+        for (int c = 0; c < B; ++c) a += Dinv[tix(B * B, r * B + c, t)] * rr[c];
         Z1[(size_t)r * N + t] = a;
       }
     }
@@ -489,7 +490,7 @@ __device__ inline void dinv_apply(const T* __restrict__ Dinv, size_t N, int t, c
   for (int r = 0; r < B; ++r) {
     T a = 0;
 #pragma unroll
-    for (int c = 0; c < B; ++c) a += Dinv[((size_t)r * B + c) * N + t] * in[c];
+    for (int c = 0; c < B; ++c) a += Dinv[tix(B * B, r * B + c, t)] * in[c];
     out[r] = a;
   }
 }
@@ -838,10 +839,10 @@ __global__ void mixed_copy_kernel(int n, const double* __restrict__ J, const dou
   for (int d = 0; d < 7; ++d)
     for (int r = 0; r < B; ++r)
       for (int c = 0; c < B; ++c) {
-        size_t o = ((size_t)(d * B + r) * B + c) * N + t;
-        Jf[o] = (float)(r == 0 ? R0[((size_t)d * B + c) * N + t] : J[o]);
+        size_t o = tix(7 * B * B, (d * B + r) * B + c, t);
+        Jf[o] = (float)(r == 0 ? R0[tix(7 * B, d * B + c, t)] : J[o]);
       }
-  for (int e = 0; e < B * B; ++e) Dinvf[e * N + t] = (float)Dinv[e * N + t];
+  for (int e = 0; e < B * B; ++e) Dinvf[tix(B * B, e, t)] = (float)Dinv[tix(B * B, e, t)];
 }
 
 __global__ void to_float_kernel(size_t n, const double* __restrict__ a, float* __restrict__ b) {

@@ -374,11 +374,11 @@ __global__ __launch_bounds__(256) void flux_kernel(Lay L, double dz, double top,
       }
     }
     for (int r = 0; r < B; ++r)
-      for (int u = 0; u < B; ++u) J[((size_t)(d * B + r) * B + u) * n + t] = Jo[r][u] / scale[r];
+      for (int u = 0; u < B; ++u) J[tix(7 * B * B, (d * B + r) * B + u, t)] = Jo[r][u] / scale[r];
   }
   for (int r = 0; r < B; ++r) {
     rhs[r * n + t] = -(R[r] / scale[r]);
-    for (int u = 0; u < B; ++u) J[((size_t)r * B + u) * n + t] = Jd[r][u] / scale[r];
+    for (int u = 0; u < B; ++u) J[tix(7 * B * B, r * B + u, t)] = Jd[r][u] / scale[r];
   }
 }
 
@@ -445,7 +445,7 @@ __global__ void well_kernel(FluidDev f, Lay L, int nperf, const Perf* __restrict
   }
   for (int r = 0; r < B; ++r) {
     rhs[r * n + t] += q[r] / scale[r];
-    for (int u = 0; u < B; ++u) J[((size_t)r * B + u) * n + t] -= dq[r][u] / scale[r];
+    for (int u = 0; u < B; ++u) J[tix(7 * B * B, r * B + u, t)] -= dq[r][u] / scale[r];
   }
   if (pf.rw >= 0) {
     const int c = rwells[pf.rw].comp;

@@ -125,14 +125,14 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
 #define ALLOC(p, cnt) if ((rc = dalloc(ctx, &(p), (cnt))) != CPR_OK) return rc
   ALLOC(ctx->poro, N);
   ALLOC(ctx->tp, 3 * N);
-  ALLOC(ctx->J, 7 * (size_t)b * b * N);
+  ALLOC(ctx->J, tiled_len(N, 7 * b * b));
   ALLOC(ctx->props, (size_t)props_planes(f->model) * N);
   ALLOC(ctx->vin, NV);
   ALLOC(ctx->vin2, NV);
   ALLOC(ctx->vout, NV);
   ALLOC(ctx->w, b * N);
-  ALLOC(ctx->R0, 7 * (size_t)b * N);
-  ALLOC(ctx->Dinv, (size_t)b * b * N);
+  ALLOC(ctx->R0, tiled_len(N, 7 * b));
+  ALLOC(ctx->Dinv, tiled_len(N, b * b));
   ALLOC(ctx->Y, b * N);
   ALLOC(ctx->xs, NV);
   ALLOC(ctx->rs, NV);
@@ -265,7 +265,7 @@ int ensure_variants(cpr_ctx* ctx, const cpr_options_t& o) {
   int b = ctx->b, rc;
   if (o.decoupling == CPR_DECOUPLE_ABF && !ctx->Jt) {
     if ((rc = dalloc(ctx, &ctx->Wabf, (size_t)b * b * N)) != CPR_OK) return rc;
-    if ((rc = dalloc(ctx, &ctx->Jt, 7 * (size_t)b * b * N)) != CPR_OK) return rc;
+    if ((rc = dalloc(ctx, &ctx->Jt, tiled_len(N, 7 * b * b))) != CPR_OK) return rc;
   }
   if (o.decoupling == CPR_DECOUPLE_ABF || o.composition == CPR_COMPOSE_FPF) {
     if (!ctx->Rt && (rc = dalloc(ctx, &ctx->Rt, (size_t)b * N)) != CPR_OK) return rc;
@@ -282,8 +282,8 @@ int ensure_mixed(cpr_ctx* ctx) {
   if (ctx->Jf) return CPR_OK;
   size_t N = ctx->lay.n;
   int b = ctx->b, rc;
-  if ((rc = dalloc(ctx, &ctx->Jf, 7 * (size_t)b * b * N)) != CPR_OK) return rc;
-  if ((rc = dalloc(ctx, &ctx->Dinvf, (size_t)b * b * N)) != CPR_OK) return rc;
+  if ((rc = dalloc(ctx, &ctx->Jf, tiled_len(N, 7 * b * b))) != CPR_OK) return rc;
+  if ((rc = dalloc(ctx, &ctx->Dinvf, tiled_len(N, b * b))) != CPR_OK) return rc;
   if ((rc = dalloc(ctx, &ctx->Yf, (size_t)b * N)) != CPR_OK) return rc;
   return CPR_OK;
 }
@@ -410,7 +410,7 @@ int assemble_jacobian(cpr_ctx_t* ctx, const double* x_old, const double* x, doub
 int cpr_import_jacobian(cpr_ctx_t* ctx, const double* blocks) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   if (!blocks) return set_err(ctx, CPR_EINVAL, "null argument");
-  launch_nat_to_cs(ctx->lay, 7 * ctx->b * ctx->b, blocks, ctx->J, ctx->stream);
+  launch_nat_to_tiled(ctx->lay, 7 * ctx->b * ctx->b, blocks, ctx->J, ctx->stream);
   ctx->setup_done = 0;
   return launch_check(ctx, "cpr_import_jacobian");
 }
@@ -418,7 +418,7 @@ int cpr_import_jacobian(cpr_ctx_t* ctx, const double* blocks) {
 int cpr_export_jacobian(cpr_ctx_t* ctx, double* blocks) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   if (!blocks) return set_err(ctx, CPR_EINVAL, "null argument");
-  launch_cs_to_nat(ctx->lay, 7 * ctx->b * ctx->b, ctx->J, blocks, ctx->stream);
+  launch_tiled_to_nat(ctx->lay, 7 * ctx->b * ctx->b, ctx->J, blocks, ctx->stream);
   return launch_check(ctx, "cpr_export_jacobian");
 }
 
@@ -702,7 +702,7 @@ int cpr_export_mg_level(cpr_ctx_t* ctx, int level, double* a7) {
 int cpr_export_ilu(cpr_ctx_t* ctx, double* dinv) {
   if (check_ctx(ctx)) return CPR_EINVAL;
   if (!dinv || !ctx->setup_done) return set_err(ctx, CPR_EINVAL, "null argument or no setup");
-  launch_cs_to_nat(ctx->lay, ctx->b * ctx->b, ctx->Dinv, dinv, ctx->stream);
+  launch_tiled_to_nat(ctx->lay, ctx->b * ctx->b, ctx->Dinv, dinv, ctx->stream);
   return launch_check(ctx, "cpr_export_ilu");
 }
 

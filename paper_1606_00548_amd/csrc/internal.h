@@ -131,6 +131,29 @@ __host__ __device__ inline void cs_nbrs(const Lay& L, int t, const CsCell& cc, i
   }
 }
 
+// Block arrays of the fine level (the Jacobian J and its decoupled form,
+// the decoupled pressure rows R0, the ILU inverse diagonals, their FP32
+// copies) are tiled: 64 consecutive colour-split cells form a tile, and a
+// tile holds each of the array's P planes as one run of 64 values, so a
+// wave reading a cell's planes streams one contiguous P x 64-value block
+// instead of P separate streams.  Element (plane p, cell t) lives at
+// tix(P, p, t); an array of n cells holds tiled_len(n, P) values.
+constexpr int TILE = 64;
+__host__ __device__ inline size_t tix(int P, int p, size_t t) {
+  return ((t / TILE) * (size_t)P + p) * TILE + (t % TILE);
+}
+inline size_t tiled_len(size_t n, int P) { return (n + TILE - 1) / TILE * TILE * (size_t)P; }
+
+// XCD-aware workgroup order.  The device hands consecutive workgroups to
+// its eight XCDs in turn, each with its own L2; renumbering them so that an
+// XCD works through one contiguous eighth of the grid keeps the
+// neighbouring rows a stencil reads in the L2 that already holds them.
+__device__ inline int xcd_block(int b, int nblocks) {
+  const int per = nblocks >> 3;
+  if (b >= (per << 3)) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
 // Non-temporal load of a streamed operand (read once per kernel).
 template <typename T>
 __device__ inline T ldnt(const T* p) {
@@ -230,7 +253,7 @@ struct cpr_ctx {
   double* bord_d = nullptr;    // [nrate] dR_w/dp_h (D)
 
   // Jacobian and assembly scratch (colour-split)
-  double* J = nullptr;         // [7][b][b][n]
+  double* J = nullptr;         // [7][b][b] planes of n cells, tiled
   double* props = nullptr;     // per-cell phase/mobility state for the flux kernel
   double* vin = nullptr;       // [b][n] input permutation scratch
   double* vin2 = nullptr;      // [b][n]
@@ -240,15 +263,15 @@ struct cpr_ctx {
   cpr_options_t opt;
   int setup_done = 0;
   double* w = nullptr;         // [b][n]   quasi-IMPES weights
-  double* R0 = nullptr;        // [7][b][n] row 0 of the decoupled blocks
+  double* R0 = nullptr;        // [7][b] planes, tiled: row 0 of the decoupled blocks
   double* Wabf = nullptr;      // [b][b][n] ABF decoupling D_i^-1
-  double* Jt = nullptr;        // [7][b][b][n] ABF decoupled blocks (rows >= 1; row 0 in R0)
+  double* Jt = nullptr;        // [7][b][b] planes, tiled: ABF decoupled blocks (rows >= 1; row 0 in R0)
   double* Rt = nullptr;        // [b][n] decoupled residual (ABF / FPF)
   float* Rtf = nullptr;
   double* Z1 = nullptr;        // [b][n] first ILU stage of CPR-FPF
   float* Z1f = nullptr;
-  double* Dinv = nullptr;      // [b][b][n] inverted ILU diagonals
-  float* Jf = nullptr;         // FP32 copy of the decoupled blocks [7][b][b][n]
+  double* Dinv = nullptr;      // [b][b] planes, tiled: inverted ILU diagonals
+  float* Jf = nullptr;         // FP32 copy of the decoupled blocks, [7][b][b] planes, tiled
   float* Dinvf = nullptr;
   std::vector<MGLevel> levels;
   double* cinv = nullptr;      // dense inverse of the coarsest level (column major)
@@ -325,6 +348,9 @@ inline long vec_len(const cpr_ctx* c) { return (long)c->b * c->lay.n + c->nrate;
 // layout.hip
 void launch_nat_to_cs(const Lay& L, int planes, const double* src, double* dst, hipStream_t s);
 void launch_cs_to_nat(const Lay& L, int planes, const double* src, double* dst, hipStream_t s);
+// The same permutations between natural-order planes and a tiled block array.
+void launch_nat_to_tiled(const Lay& L, int planes, const double* src, double* dst, hipStream_t s);
+void launch_tiled_to_nat(const Lay& L, int planes, const double* src, double* dst, hipStream_t s);
 
 // assemble.hip
 void launch_transmissibility(const Lay& L, const cpr_grid_t& g, const double* perm_nat,

@@ -99,7 +99,7 @@ __global__ void qimpes_kernel(int n, const double* __restrict__ J, double* __res
   const size_t N = n;
   double D[B][B], y[B], wv[B];
   for (int r = 0; r < B; ++r)
-    for (int c = 0; c < B; ++c) D[r][c] = J[((size_t)r * B + c) * N + t];
+    for (int c = 0; c < B; ++c) D[r][c] = J[tix(7 * B * B, r * B + c, t)];
   bool ok = solve_transposed_e0<B>(D, y);
   double y0 = y[0];
   if (ok && fabs(y0) > TINY && isfinite(y0)) {
@@ -113,8 +113,8 @@ __global__ void qimpes_kernel(int n, const double* __restrict__ J, double* __res
   for (int d = 0; d < 7; ++d) {
     for (int c = 0; c < B; ++c) {
       double s = 0.0;
-      for (int r = 0; r < B; ++r) s += wv[r] * J[((size_t)(d * B + r) * B + c) * N + t];
-      R0[((size_t)d * B + c) * N + t] = s;
+      for (int r = 0; r < B; ++r) s += wv[r] * J[tix(7 * B * B, (d * B + r) * B + c, t)];
+      R0[tix(7 * B, d * B + c, t)] = s;
       if (c == 0) Ap[(size_t)d * N + t] = s;
     }
   }
@@ -133,23 +133,23 @@ __global__ void abf_kernel(int n, const double* __restrict__ J, double* __restri
   const size_t N = n;
   double D[B][B], inv[B][B];
   for (int r = 0; r < B; ++r)
-    for (int c = 0; c < B; ++c) D[r][c] = J[((size_t)r * B + c) * N + t];
+    for (int c = 0; c < B; ++c) D[r][c] = J[tix(7 * B * B, r * B + c, t)];
   if (!small_inverse<B>(D, inv)) atomicExch(flag, 1);
   for (int r = 0; r < B; ++r)
     for (int c = 0; c < B; ++c) W[((size_t)r * B + c) * N + t] = inv[r][c];
   for (int d = 0; d < 7; ++d) {
     double a[B][B];
     for (int r = 0; r < B; ++r)
-      for (int c = 0; c < B; ++c) a[r][c] = J[((size_t)(d * B + r) * B + c) * N + t];
+      for (int c = 0; c < B; ++c) a[r][c] = J[tix(7 * B * B, (d * B + r) * B + c, t)];
     for (int r = 0; r < B; ++r)
       for (int c = 0; c < B; ++c) {
         double s = 0.0;
         for (int m = 0; m < B; ++m) s += inv[r][m] * a[m][c];
         if (r == 0) {
-          R0[((size_t)d * B + c) * N + t] = s;
+          R0[tix(7 * B, d * B + c, t)] = s;
           if (c == 0) Ap[(size_t)d * N + t] = s;
         } else {
-          Jt[((size_t)(d * B + r) * B + c) * N + t] = s;
+          Jt[tix(7 * B * B, (d * B + r) * B + c, t)] = s;
         }
       }
   }
@@ -460,7 +460,7 @@ __global__ void gj_extract_kernel(int nc, const double* __restrict__ M, double* 
 template <int B>
 __device__ inline double at_blk(const double* __restrict__ J, const double* __restrict__ R0, size_t N,
                                 int d, int r, int c, int t) {
-  return r == 0 ? R0[((size_t)d * B + c) * N + t] : J[((size_t)(d * B + r) * B + c) * N + t];
+  return r == 0 ? R0[tix(7 * B, d * B + c, t)] : J[tix(7 * B * B, (d * B + r) * B + c, t)];
 }
 
 template <int B>
@@ -484,7 +484,7 @@ __global__ void ilu_kernel(Lay L, int colour, const double* __restrict__ J, cons
       for (int r = 0; r < B; ++r)
         for (int c = 0; c < B; ++c) {
           Aik[r][c] = at_blk<B>(J, R0, N, d, r, c, t);
-          Dk[r][c] = Dinv[((size_t)r * B + c) * N + nb];
+          Dk[r][c] = Dinv[tix(B * B, r * B + c, nb)];
           Aki[r][c] = at_blk<B>(J, R0, N, od, r, c, nb);
         }
       for (int r = 0; r < B; ++r)
@@ -504,7 +504,7 @@ __global__ void ilu_kernel(Lay L, int colour, const double* __restrict__ J, cons
   double inv[B][B];
   if (!small_inverse<B>(D, inv)) atomicExch(flag, 1);
   for (int r = 0; r < B; ++r)
-    for (int c = 0; c < B; ++c) Dinv[((size_t)r * B + c) * N + t] = inv[r][c];
+    for (int c = 0; c < B; ++c) Dinv[tix(B * B, r * B + c, t)] = inv[r][c];
 }
 
 __global__ void zero_int_kernel(int* p, int n) {

@@ -1,10 +1,13 @@
 // Block 7-point sparse matrix-vector product y = A x (or y = rhs - A x).
 //
 // One thread per cell, colour-split order.  The 7 b x b blocks of a block
-// row sit in 7*b*b planes, so consecutive threads read consecutive doubles
-// of every plane; the neighbours' x values come from the other colour's
-// half at a fixed offset (+-y, +-z) or at m / m +- 1 (+-x).  HBM traffic per
-// cell: 7 b^2 matrix values + b values of x + b of y (+ b of rhs).
+// row sit in 7*b*b planes stored in 64-cell tiles, so a wave reads its
+// cells' whole matrix rows as one contiguous block of 7*b*b runs of 64
+// doubles; the neighbours' x values come from the other colour's half at a
+// fixed offset (+-y, +-z) or at m / m +- 1 (+-x), and the XCD-aware
+// workgroup order keeps the rows of x that neighbouring workgroups share in
+// one L2.  HBM traffic per cell: 7 b^2 matrix values + b values of x + b of
+// y (+ b of rhs).
 #include "internal.h"
 
 namespace {
@@ -23,7 +26,7 @@ __global__ __launch_bounds__(256) void spmv_kernel(Lay L, const double* __restri
                                                    const double* __restrict__ x,
                                                    double* __restrict__ y,
                                                    const double* __restrict__ rhs) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (t >= L.n) return;
   const size_t n = L.n;
   CsCell cc = cs_decode(L, t);
@@ -43,7 +46,7 @@ __global__ __launch_bounds__(256) void spmv_kernel(Lay L, const double* __restri
 #pragma unroll
     for (int r = 0; r < B; ++r)
 #pragma unroll
-      for (int c = 0; c < B; ++c) a[d][r][c] = __builtin_nontemporal_load(A + ((size_t)(d * B + r) * B + c) * n + t);
+      for (int c = 0; c < B; ++c) a[d][r][c] = __builtin_nontemporal_load(A + tix(7 * B * B, (d * B + r) * B + c, t));
   double acc[B];
 #pragma unroll
   for (int r = 0; r < B; ++r) acc[r] = 0.0;
@@ -85,7 +88,7 @@ __device__ inline void spmv_cell(const Lay& L, int t, const double* __restrict__
 #pragma unroll
     for (int r = 0; r < B; ++r)
 #pragma unroll
-      for (int c = 0; c < B; ++c) a[d][r][c] = __builtin_nontemporal_load(A + ((size_t)(d * B + r) * B + c) * n + t);
+      for (int c = 0; c < B; ++c) a[d][r][c] = __builtin_nontemporal_load(A + tix(7 * B * B, (d * B + r) * B + c, t));
 #pragma unroll
   for (int d = 0; d < 7; ++d) {
     double xv[B];
@@ -107,7 +110,7 @@ template <int B>
 __global__ __launch_bounds__(64) void spmv_small_kernel(Lay L, const double* __restrict__ A,
                                                         const double* __restrict__ x, double* __restrict__ y,
                                                         const double* __restrict__ rhs) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (t < L.n) spmv_cell<B>(L, t, A, x, y, rhs);
 }
 

@@ -80,7 +80,8 @@ enum { CPR_COMPOSE_PF = 0, CPR_COMPOSE_FPF = 1 };
 
 /* Structured Cartesian grid: cell sizes in metres, depth of the top face in
  * metres (depth positive downward).  nx must be even: the library stores
- * every per-cell array split by red-black colour along x. */
+ * every per-cell array split by red-black colour along x (coarse multigrid
+ * levels may have any shape). */
 typedef struct {
   int nx, ny, nz;
   double dx, dy, dz;
@@ -217,12 +218,14 @@ int assemble_jacobian(cpr_ctx_t* ctx, const double* x_old, const double* x, doub
 int cpr_import_jacobian(cpr_ctx_t* ctx, const double* blocks);
 int cpr_export_jacobian(cpr_ctx_t* ctx, double* blocks);
 
-/* Build the CPR preconditioner for the current Jacobian: the decoupling
- * (quasi-IMPES weights and decoupled rows, or the ABF inverses D_i^-1 and
- * the blocks D_i^-1 A_ij), the pressure multigrid hierarchy on
- * A_p = (A~)_pp (2x2x2 aggregation, Galerkin coarse operators, dense
- * inverse of the coarsest level) and the red-black block ILU(0) diagonals
- * of A~.  Synchronises the stream (to report singular blocks).  Returns
+/* Build the CPR preconditioner for the current Jacobian (Sec. 2.5: the
+ * two-stage CPR family; the pressure block A_pp and the full system of the
+ * block structure of eq. (16)): the decoupling (quasi-IMPES weights and
+ * decoupled rows, or the ABF inverses D_i^-1 and the blocks D_i^-1 A_ij),
+ * the pressure multigrid hierarchy on A_p = (A~)_pp (2x2x2 aggregation,
+ * Galerkin coarse operators, dense inverse of the coarsest level; a level
+ * above the coarsest with odd nx is stored with a ghost column) and the
+ * red-black block ILU(0) diagonals of A~.  Synchronises the stream (to report singular blocks).  Returns
  * CPR_ESINGULAR if a diagonal block or the coarsest operator cannot be
  * inverted, CPR_EINVAL for an unknown decoupling or composition. */
 int cpr_setup(cpr_ctx_t* ctx, const cpr_options_t* o);

@@ -11,8 +11,10 @@ r' = r~_p - A_p dp_mg, and the network input for it.  The
 target is the exact remaining correction A_p^-1 r', obtained with the same
 library by solving the pressure system to 1e-10 (A_p embedded as the
 pressure block of a two-unknown system whose second unknown is decoupled
-by an identity block), divided by the feature scale s so that
-dp_nn = s N(input) is the correction the network must produce.
+by an identity block), divided by the feature scale s.  The network learns
+only the direction of that correction: the loss is 1 - cos^2(N(input), t),
+and inside the solver the step length comes from the residual-minimising
+alpha = <A_p d, r'> / |A_p d|^2 for d = N(input), judged against plain CPR.
 """
 import argparse
 import json

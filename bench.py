@@ -87,11 +87,12 @@ def network_timing(nx, ny, nz, reps=20):
             "frac_of_bf16_peak": tflops / BF16_PEAK_TFLOPS, "grid": [nx, ny, nz], "batch": 1}
 
 
-def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision, levels=None):
+def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision, levels=None, orth="dcgs2"):
     """Bytes the launches of one kernel class in one Newton step must move at
     minimum (every array element touched once per launch, FP64), and the
     number of those launches.  iterations_per_cycle: Arnoldi steps of each
-    restart cycle; levels: cell counts of the multigrid levels."""
+    restart cycle; levels: cell counts of the multigrid levels; orth: the
+    FGMRES orthogonalisation (delayed CGS2 or CGS2)."""
     s = 8
     its = sum(iterations_per_cycle)
     if kclass == "spmv":
@@ -103,11 +104,17 @@ def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision, levels=None
         tot, launches = 0, 0
         for k in iterations_per_cycle:
             for j in range(k):
-                nv = j + 1
-                # dots: V (nv) + w; update+dots: V + w read + w write;
-                # update+norm: V + w read + w write
-                tot += ((nv + 1) + (nv + 2) + (nv + 2)) * b * n * s
-                launches += 3
+                if orth == "cgs2":
+                    # nv = j + 1 vectors; dots: V + w; update+dots: V + w read
+                    # + w write; update+norm: V + w read + w write
+                    nv = j + 1
+                    tot += ((nv + 1) + (nv + 2) + (nv + 2)) * b * n * s
+                    launches += 3
+                else:
+                    # delayed CGS2, j final vectors before uh: dots read V,
+                    # uh, w; update reads V, uh, w and writes v_j and u
+                    tot += ((j + 2) + (j + 4)) * b * n * s
+                    launches += 2
         return tot, launches
     if kclass == "smooth":
         # red-black Gauss-Seidel half-sweeps on the levels smoothed by
@@ -393,7 +400,8 @@ def main():
             forms.append(("fp64+learned", dict(precision="fp64", learned=1)))
         tuned = dict(mg_pre=2, mg_post=2, mg_alpha=1.25)
         forms += [("fp64 V(2,2) alpha 1.25", dict(precision="fp64", **tuned)),
-                  ("mixed V(2,2) alpha 1.25", dict(precision="mixed", **tuned))]
+                  ("mixed V(2,2) alpha 1.25", dict(precision="mixed", **tuned)),
+                  ("fp64 CGS2", dict(precision="fp64", orth="cgs2"))]
         for name, kw in forms:
             sp, _, vsts, dxv, _ = run.timed(cprmi.default_options(**kw), vs, 1)
             variants[name] = {"s_per_step": sp, "krylov_iterations": vsts[-1]["iterations"],

@@ -78,6 +78,16 @@ enum { CPR_PREC_FP64 = 0, CPR_PREC_MIXED = 1 };
 enum { CPR_DECOUPLE_QIMPES = 0, CPR_DECOUPLE_ABF = 1 };
 enum { CPR_COMPOSE_PF = 0, CPR_COMPOSE_FPF = 1 };
 
+/* Orthogonalisation of the FGMRES basis (the eq. (13) solve; not specified
+ * by the paper, whose examples use BiCGSTAB):
+ *   CPR_ORTH_DCGS2  classical Gram-Schmidt twice with the second pass of
+ *                   each vector delayed into the next Arnoldi step, so the
+ *                   basis is read twice per step instead of three times
+ *                   (the same basis in exact arithmetic; restart <= 32,
+ *                   longer restarts use CGS2);
+ *   CPR_ORTH_CGS2   both passes in the step. */
+enum { CPR_ORTH_DCGS2 = 0, CPR_ORTH_CGS2 = 1 };
+
 /* Structured Cartesian grid: cell sizes in metres, depth of the top face in
  * metres (depth positive downward).  nx must be even: the library stores
  * every per-cell array split by red-black colour along x (coarse multigrid
@@ -150,6 +160,7 @@ typedef struct {
                           started from, the remaining cycles apply the FP64
                           preconditioner (default 0.5: less than halved;
                           1.0: not decreased; <= 0: never)                 */
+  int orth;            /* CPR_ORTH_DCGS2 (default) or CPR_ORTH_CGS2        */
 } cpr_options_t;
 
 typedef struct {

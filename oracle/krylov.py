@@ -25,6 +25,28 @@ Algorithm (one restart cycle, x0 = 0 on entry):
     iterations remain.
 The iteration count is the number of Arnoldi matvecs (true-residual
 products are not counted).
+
+Orthogonalisation "dcgs2" (the default) computes the same basis with the
+second Gram-Schmidt pass of each vector delayed to the next step
+(delayed classical Gram-Schmidt twice, as in Swirydowicz, Langou,
+Ananthan, Yang and Thomas, "Low synchronization Gram-Schmidt and GMRES
+algorithms", 2020), so that each step projects the new vector and
+reorthogonalises the previous one from the same two sets of inner products.
+With u_j = the once-projected vector of step j-1, nu_j = ||u_j|| and
+uh_j = u_j / nu_j (what the preconditioner receives at step j):
+    w = A M^-1 uh_j
+    a = V_{j-1}^T uh_j, c = V_{j-1}^T w, d = uh_j^T w, e = uh_j^T uh_j
+    beta_j = sqrt(e - |a|^2),  v_j = (uh_j - V_{j-1} a) / beta_j
+    column j-1 of H: += nu_j a (rows < j), row j = nu_j beta_j
+    column j of H:   c (rows < j), g_j = (d - a.c) / beta_j (row j),
+                     nu_{j+1} = ||w - V_{j-1} c - g_j v_j|| (row j+1)
+Step 0 has no previous vector: v_0 = r / beta, g_0 = v_0^T w.  In exact
+arithmetic a = 0 and e = 1, so every quantity equals its CGS2 value; the
+Givens rotations are recomputed from H after each step (its previous column
+changes), and the last column keeps its once-projected values.  A
+vanishing beta_j (uh_j in the span of the basis) ends the cycle before step
+j, like a happy breakdown.  "cgs2" keeps both passes in the step; restarts
+longer than 32 use it as well.
 """
 import numpy as np
 import scipy.linalg
@@ -36,12 +58,107 @@ def _dot(a, b):
     return float(np.dot(a.ravel(), b.ravel()))
 
 
+def _givens_qr(H, beta, k):
+    """Givens QR of the (k+1) x k Hessenberg block: returns (R, g) with
+    g = Q^T beta e_0 (g[k] is the least-squares residual)."""
+    R = H[:k + 1, :k].copy()
+    g = np.zeros(k + 1)
+    g[0] = beta
+    for i in range(k):
+        den = np.hypot(R[i, i], R[i + 1, i])
+        if den == 0.0:
+            c, s = 1.0, 0.0
+        else:
+            c, s = R[i, i] / den, R[i + 1, i] / den
+        ri, ri1 = R[i, i:].copy(), R[i + 1, i:].copy()
+        R[i, i:] = c * ri + s * ri1
+        R[i + 1, i:] = -s * ri + c * ri1
+        g[i + 1] = -s * g[i]
+        g[i] = c * g[i]
+    return R, g
+
+
+def dcgs2_step(V, uh, w):
+    """One step of delayed CGS2 against the orthonormal vectors V (j >= 1 of
+    them): reorthogonalise uh and project w with the same inner products.
+    Returns (v, a, beta, c, g, u): v = (uh - V a) / beta the new basis
+    vector, a = V^T uh, beta = sqrt(uh.uh - |a|^2), c = V^T w,
+    g = v^T w = (uh.w - a.c) / beta, u = w - V c - g v; or None when beta
+    vanishes (uh in the span of V)."""
+    j = len(V)
+    a = np.array([_dot(V[i], uh) for i in range(j)])
+    c = np.array([_dot(V[i], w) for i in range(j)])
+    d = _dot(uh, w)
+    e = _dot(uh, uh)
+    b2 = e - float(np.dot(a, a))
+    if not b2 > 0.0:
+        return None
+    bj = np.sqrt(b2)
+    v = uh.copy()
+    for i in range(j):
+        v = v - a[i] * V[i]
+    v = v / bj
+    g = (d - float(np.dot(a, c))) / bj
+    u = w.copy()
+    for i in range(j):
+        u = u - c[i] * V[i]
+    u = u - g * v
+    return v, a, bj, c, g, u
+
+
+def _fgmres_cycle_dcgs2(apply_A, apply_M, r, beta, bnorm, m, rtol, max_iter, its, st, record):
+    """One restart cycle with delayed reorthogonalisation (module docstring).
+    Returns (Z, y, its, est)."""
+    V = [r / beta]
+    Z = []
+    H = np.zeros((m + 1, m))
+    uh, nu = None, None
+    k, g = 0, np.array([beta])
+    for j in range(m):
+        q = V[0] if j == 0 else uh
+        z = apply_M(q)
+        if record is not None:
+            record(its, q, z)
+        w = apply_A(z)
+        if j == 0:
+            c = np.zeros(0)
+            gj = _dot(V[0], w)
+            u = w - gj * V[0]
+        else:
+            out = dcgs2_step(V, uh, w)
+            if out is None:
+                break                      # uh_j in the span of the basis: stop before step j
+            v, a, bj, c, gj, u = out
+            V.append(v)
+            H[:j, j - 1] += nu * a
+            H[j, j - 1] = nu * bj
+        Z.append(z)
+        its += 1
+        nu = np.sqrt(_dot(u, u))
+        H[:j, j] = c
+        H[j, j] = gj
+        H[j + 1, j] = nu
+        k = j + 1
+        R, g = _givens_qr(H, beta, k)
+        st["history"].append(abs(g[k]) / bnorm)
+        az = np.sqrt(np.sum(H[:j + 2, j] ** 2))
+        if abs(g[k]) <= rtol * bnorm or nu <= BREAKDOWN * az or its >= max_iter:
+            break
+        uh = u / nu
+    R, g = _givens_qr(H, beta, k)
+    y = scipy.linalg.solve_triangular(R[:k, :k], g[:k], lower=False)
+    return Z, y, its, abs(g[k])
+
+
 def fgmres(apply_A, apply_M, b, restart=30, rtol=1e-6, max_iter=300, x0=None,
-           record=None):
+           record=None, orth="dcgs2"):
     """Returns (x, stats).  stats: iterations, cycles, converged, est_rel,
     true_rel, history (estimated relative residual after each iteration).
     `record`, if given, is called with (j, v_j, z_j) for every preconditioner
-    application (used to harvest pressure-stage inputs)."""
+    application (used to harvest pressure-stage inputs).  orth: "dcgs2"
+    (default) or "cgs2"."""
+    if orth not in ("dcgs2", "cgs2"):
+        raise ValueError(orth)
     x = np.zeros_like(b) if x0 is None else x0.copy()
     bnorm = np.sqrt(_dot(b, b))
     st = {"iterations": 0, "cycles": 0, "converged": False, "est_rel": 0.0,
@@ -61,6 +178,15 @@ def fgmres(apply_A, apply_M, b, restart=30, rtol=1e-6, max_iter=300, x0=None,
         if its >= max_iter:
             break
         m = restart
+        if orth == "dcgs2" and m <= 32:
+            Z, y, its, est = _fgmres_cycle_dcgs2(apply_A, apply_M, r, beta, bnorm, m, rtol, max_iter,
+                                                 its, st, record)
+            for i in range(len(y)):
+                x = x + y[i] * Z[i]
+            st["cycles"] += 1
+            st["est_rel"] = est / bnorm
+            r = b - apply_A(x)
+            continue
         V = [r / beta]
         Z = []
         H = np.zeros((m + 1, m))

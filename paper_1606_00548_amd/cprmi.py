@@ -23,6 +23,7 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENONFINI
 PREC = {"fp64": 0, "mixed": 1}
 DECOUPLING = {"qimpes": 0, "abf": 1}
 COMPOSITION = {"two-stage": 0, "fpf": 1}
+ORTH = {"dcgs2": 0, "cgs2": 1}
 
 
 class Grid(ctypes.Structure):
@@ -52,7 +53,7 @@ class Options(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double), ("mg_coarsest", ctypes.c_int),
                 ("mg_alpha", ctypes.c_double), ("decoupling", ctypes.c_int), ("composition", ctypes.c_int),
                 ("x0", ctypes.c_int), ("mg_pre", ctypes.c_int), ("mg_post", ctypes.c_int),
-                ("stall_ratio", ctypes.c_double)]
+                ("stall_ratio", ctypes.c_double), ("orth", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -337,6 +338,8 @@ def default_options(**kw):
             v = DECOUPLING[v]
         if k == "composition" and isinstance(v, str):
             v = COMPOSITION[v]
+        if k == "orth" and isinstance(v, str):
+            v = ORTH[v]
         setattr(o, k, v)
     return o
 

@@ -147,10 +147,10 @@ int create_impl(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, 
   ctx->nblk = div_up((long)b * n, 1024);
   if (ctx->nblk > 1024) ctx->nblk = 1024;
   ALLOC(ctx->part, 66 * (size_t)ctx->nblk);
-  ALLOC(ctx->hdev, 512);
+  ALLOC(ctx->hdev, 1024);
 #undef ALLOC
   {
-    hipError_t e = hipHostMalloc((void**)&ctx->hhost, 512 * sizeof(double), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void**)&ctx->hhost, 1024 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) return set_hip_err(ctx, e, "hipHostMalloc");
     CPR_TRY(hipHostGetDevicePointer((void**)&ctx->hhost_dev, ctx->hhost, 0));
   }
@@ -309,6 +309,8 @@ int setup_with_options(cpr_ctx* ctx, const cpr_options_t& opt) {
     return set_err(ctx, CPR_EINVAL, "unknown decoupling");
   if (opt.composition != CPR_COMPOSE_PF && opt.composition != CPR_COMPOSE_FPF)
     return set_err(ctx, CPR_EINVAL, "unknown composition");
+  if (opt.orth != CPR_ORTH_DCGS2 && opt.orth != CPR_ORTH_CGS2)
+    return set_err(ctx, CPR_EINVAL, "unknown orthogonalisation");
   if (opt.learned && !ctx->nn) return set_err(ctx, CPR_EINVAL, "no pressure-correction network attached");
   ctx->opt = opt;
   ctx->setup_done = 0;
@@ -353,6 +355,7 @@ void cpr_default_options(cpr_options_t* o) {
   o->x0 = 0;
   o->mg_pre = 1;
   o->mg_post = 1;
+  o->orth = CPR_ORTH_DCGS2;
 }
 
 int cpr_create(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, const double* poro,

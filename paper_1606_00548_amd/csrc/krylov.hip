@@ -10,12 +10,24 @@
 // it to pinned host memory, and one stream synchronisation per iteration is
 // the only one in the loop.
 //
-// Per Arnoldi step j (nv = j+1 basis vectors):
+// Per Arnoldi step j, CGS2 (options.orth = CPR_ORTH_CGS2; nv = j+1):
 //   z_j = M^-1 v_j ; w = A z_j            -> written into V[j+1]
 //   h  = V^T w  (partials, reduce)
 //   w -= V h, h' = V^T w (fused: each block updates its slice, then dots it)
 //   w -= V h', ||w||^2 (fused)
 //   h_{j+1,j} = ||w||; v_{j+1} = w / h_{j+1,j}
+// Delayed CGS2 (the default): the second pass of each vector is done in the
+// next step, from the same inner products as that step's projection, so V
+// is read twice per step instead of three times.  Slot j holds uh_j, the
+// once-projected vector of step j-1 scaled to unit norm (the
+// preconditioner's first kernel scales it), w lands in slot j+1:
+//   dots:   a = V_j^T uh_j, c = V_j^T w, d = uh_j . w, e = uh_j . uh_j
+//   coef:   beta = sqrt(e - |a|^2), g = (d - a.c) / beta (one block)
+//   update: v_j = (uh_j - V_j a) / beta over slot j; u = w - V_j c - g v_j
+//           over slot j+1, with ||u||^2
+// (V_j: the j final vectors before slot j).  The host adds nu_j a to column
+// j-1 of the Hessenberg matrix, sets its entry (j, j-1) to nu_j beta,
+// writes column j (c, g, nu_{j+1} = ||u||) and recomputes the Givens QR.
 #include <cmath>
 #include <vector>
 
@@ -184,6 +196,144 @@ __global__ __launch_bounds__(KB) void orth_fused_kernel(long len, int nv, const 
     for (int q = 0; q < KB / 64; ++q) s += sh[threadIdx.x * (KB / 64) + q];
     int row = mode == 0 ? threadIdx.x : nv;
     part[(size_t)row * nblk + blockIdx.x] = s;
+  }
+}
+
+// Delayed CGS2, dot pass of step j (j <= NV final vectors before slot j):
+// part rows 0..j-1 = V_k . uh, rows j..2j-1 = V_k . w, row 2j = uh . w,
+// row 2j+1 = uh . uh, each the sum over this block's slice.
+template <int NV>
+__global__ __launch_bounds__(KB) void dcgs_dots_kernel(long len, int j, const double* __restrict__ V, size_t stride,
+                                                       const double* __restrict__ uh, const double* __restrict__ w,
+                                                       double* __restrict__ part, int nblk) {
+  __shared__ double sh[(2 * NV + 2) * (KB / 64)];
+  long per = (len + nblk - 1) / nblk;
+  long beg = (long)blockIdx.x * per;
+  long end = beg + per < len ? beg + per : len;
+  double aa[NV], cc[NV], dd = 0.0, ee = 0.0;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) aa[k] = cc[k] = 0.0;
+  for (long e = beg + threadIdx.x; e < end; e += KB) {
+    // every basis load issued before the arithmetic (vectors past j read as 0)
+    double vv[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) vv[k] = k < j ? ldnt(V + k * stride + e) : 0.0;
+    const double u = uh[e], x = w[e];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      aa[k] += vv[k] * u;
+      cc[k] += vv[k] * x;
+    }
+    dd += u * x;
+    ee += u * u;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int rows = 2 * j + 2;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < j) {
+      double v = wave_sum(aa[k]);
+      if (lane == 0) sh[k * (KB / 64) + wid] = v;
+      v = wave_sum(cc[k]);
+      if (lane == 0) sh[(j + k) * (KB / 64) + wid] = v;
+    }
+  }
+  {
+    double v = wave_sum(dd);
+    if (lane == 0) sh[(2 * j) * (KB / 64) + wid] = v;
+    v = wave_sum(ee);
+    if (lane == 0) sh[(2 * j + 1) * (KB / 64) + wid] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < rows) {
+    double t = 0.0;
+    for (int q = 0; q < KB / 64; ++q) t += sh[threadIdx.x * (KB / 64) + q];
+    part[(size_t)threadIdx.x * nblk + blockIdx.x] = t;
+  }
+}
+
+// Offsets of the delayed CGS2 scalars: in the device scratch hdev (dots,
+// update coefficients, ||u||^2) and in each of the two pinned host slots.
+enum { D_DOTS = 384, D_COEF = 512, D_NRM = 640, D_HOST = 512, D_SLOT = 256 };
+enum { C_A = 0, C_C = 32, C_INVB = 64, C_G = 65 };                       // in D_COEF
+enum { S_A = 0, S_C = 32, S_BETA = 64, S_G = 65, S_NRM = 66, S_FLAG = 67 };   // in a host slot
+
+// The scalars of step j from its reduced dots (one thread, fixed order):
+// beta = sqrt(e - |a|^2) (1 at step 0, which has no vector to
+// reorthogonalise) and g = (d - a.c) / beta; flag = 1 when beta^2 <= 0.
+__global__ void dcgs_coef_kernel(int j, const double* __restrict__ dots, double* __restrict__ coef,
+                                 double* __restrict__ host) {
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    coef[C_A + i] = dots[i];
+    coef[C_C + i] = dots[j + i];
+    host[S_A + i] = dots[i];
+    host[S_C + i] = dots[j + i];
+  }
+  if (threadIdx.x != 0) return;
+  double aa = 0.0, ac = 0.0;
+  for (int i = 0; i < j; ++i) {
+    aa += dots[i] * dots[i];
+    ac += dots[i] * dots[j + i];
+  }
+  const double d = dots[2 * j], e = dots[2 * j + 1];
+  const double b2 = j == 0 ? 1.0 : e - aa;
+  const bool bad = !(b2 > 0.0);
+  const double beta = bad ? 0.0 : sqrt(b2);
+  const double g = j == 0 ? d : (bad ? 0.0 : (d - ac) / beta);
+  coef[C_INVB] = bad ? 0.0 : 1.0 / beta;
+  coef[C_G] = g;
+  host[S_BETA] = beta;
+  host[S_G] = g;
+  host[S_FLAG] = bad ? 1.0 : 0.0;
+}
+
+// Delayed CGS2, update pass of step j: v_j = (uh - V a) / beta over uh,
+// u = w - V c - g v_j over w, and part row 0 = this slice of ||u||^2.
+template <int NV>
+__global__ __launch_bounds__(KB) void dcgs_update_kernel(long len, int j, const double* __restrict__ V, size_t stride,
+                                                         double* __restrict__ uh, double* __restrict__ w,
+                                                         const double* __restrict__ coef, double* __restrict__ part,
+                                                         int nblk) {
+  __shared__ double cs[2 * NV + 2];
+  __shared__ double sh[KB / 64];
+  for (int i = threadIdx.x; i < NV; i += KB) {
+    cs[i] = i < j ? coef[C_A + i] : 0.0;
+    cs[NV + i] = i < j ? coef[C_C + i] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    cs[2 * NV] = coef[C_INVB];
+    cs[2 * NV + 1] = coef[C_G];
+  }
+  __syncthreads();
+  const double invb = cs[2 * NV], g = cs[2 * NV + 1];
+  long per = (len + nblk - 1) / nblk;
+  long beg = (long)blockIdx.x * per;
+  long end = beg + per < len ? beg + per : len;
+  double acc = 0.0;
+  for (long e = beg + threadIdx.x; e < end; e += KB) {
+    double vv[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) vv[k] = k < j ? ldnt(V + k * stride + e) : 0.0;
+    double va = uh[e], wa = w[e];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      va -= cs[k] * vv[k];
+      wa -= cs[NV + k] * vv[k];
+    }
+    va *= invb;
+    wa -= g * va;
+    uh[e] = va;
+    w[e] = wa;
+    acc += wa * wa;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double v = wave_sum(acc);
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < KB / 64; ++q) t += sh[q];
+    part[blockIdx.x] = t;
   }
 }
 
@@ -404,6 +554,140 @@ int reduce_dot(cpr_ctx* ctx, const double* a, const double* b, long len, double*
   return CPR_OK;
 }
 
+namespace {
+
+void dcgs_dots(cpr_ctx* ctx, long len, int j, const double* uh, const double* w) {
+  hipStream_t s = ctx->stream;
+  const int nblk = ctx->nblk;
+  const size_t stride = (size_t)len;
+  prof_begin(ctx, CPR_KCLASS_ORTH);
+  if (j <= 8)
+    dcgs_dots_kernel<8><<<nblk, KB, 0, s>>>(len, j, ctx->V, stride, uh, w, ctx->part, nblk);
+  else if (j <= 16)
+    dcgs_dots_kernel<16><<<nblk, KB, 0, s>>>(len, j, ctx->V, stride, uh, w, ctx->part, nblk);
+  else
+    dcgs_dots_kernel<32><<<nblk, KB, 0, s>>>(len, j, ctx->V, stride, uh, w, ctx->part, nblk);
+  prof_end(ctx, CPR_KCLASS_ORTH);
+}
+
+void dcgs_update(cpr_ctx* ctx, long len, int j, double* uh, double* w, const double* coef) {
+  hipStream_t s = ctx->stream;
+  const int nblk = ctx->nblk;
+  const size_t stride = (size_t)len;
+  prof_begin(ctx, CPR_KCLASS_ORTH);
+  if (j <= 8)
+    dcgs_update_kernel<8><<<nblk, KB, 0, s>>>(len, j, ctx->V, stride, uh, w, coef, ctx->part, nblk);
+  else if (j <= 16)
+    dcgs_update_kernel<16><<<nblk, KB, 0, s>>>(len, j, ctx->V, stride, uh, w, coef, ctx->part, nblk);
+  else
+    dcgs_update_kernel<32><<<nblk, KB, 0, s>>>(len, j, ctx->V, stride, uh, w, coef, ctx->part, nblk);
+  prof_end(ctx, CPR_KCLASS_ORTH);
+}
+
+// Givens QR of the (k+1) x k Hessenberg block Hh (row stride m) into R (the
+// same layout, upper triangle) and g = Q^T beta e_0.
+void givens_qr(const std::vector<double>& Hh, int m, int k, double beta, std::vector<double>& R,
+               std::vector<double>& g) {
+  std::fill(R.begin(), R.end(), 0.0);
+  for (int i = 0; i <= k; ++i)
+    for (int c = 0; c < k; ++c) R[(size_t)i * m + c] = Hh[(size_t)i * m + c];
+  std::fill(g.begin(), g.end(), 0.0);
+  g[0] = beta;
+  for (int i = 0; i < k; ++i) {
+    const double a = R[(size_t)i * m + i], b = R[(size_t)(i + 1) * m + i];
+    const double den = std::hypot(a, b);
+    double c = 1.0, sn = 0.0;
+    if (den != 0.0) { c = a / den; sn = b / den; }
+    for (int col = i; col < k; ++col) {
+      const double ri = R[(size_t)i * m + col], ri1 = R[(size_t)(i + 1) * m + col];
+      R[(size_t)i * m + col] = c * ri + sn * ri1;
+      R[(size_t)(i + 1) * m + col] = -sn * ri + c * ri1;
+    }
+    g[i + 1] = -sn * g[i];
+    g[i] = c * g[i];
+  }
+}
+
+}  // namespace
+
+// One restart cycle of FGMRES with delayed CGS2 (slot 0 of V holds r / beta
+// on entry).  On return R (row stride m) holds the triangular factor of the
+// cycle's k x k least-squares problem and g its right-hand side, both from
+// the corrected Hessenberg matrix; its counts the Arnoldi steps.
+int dcgs2_cycle(cpr_ctx* ctx, double beta, double bnorm, int& its, int& k, std::vector<double>& R,
+                std::vector<double>& g) {
+  hipStream_t s = ctx->stream;
+  const long len = vec_len(ctx);
+  const size_t stride = (size_t)len;
+  const int m = ctx->opt.restart;
+  const double rtol = ctx->opt.rtol;
+  const int max_iter = ctx->opt.max_iter;
+  const int nblk = ctx->nblk;
+  double* hd = ctx->hdev;
+  std::vector<double> Hh((size_t)(m + 1) * m, 0.0);
+  auto launch_step = [&](int j) -> int {
+    double* uj = ctx->V + (size_t)j * stride;
+    double* zj = ctx->Z + (size_t)j * stride;
+    double* w = ctx->V + (size_t)(j + 1) * stride;
+    double* slot = ctx->hhost_dev + D_HOST + (j & 1) * D_SLOT;
+    // slot j becomes uh_j = u_j / nu_j inside the preconditioner's first kernel
+    precond_apply(ctx, uj, uj, j == 0 ? nullptr : hd + D_NRM, zj);
+    prof_begin(ctx, CPR_KCLASS_SPMV);
+    system_spmv(ctx, zj, w, nullptr);
+    prof_end(ctx, CPR_KCLASS_SPMV);
+    dcgs_dots(ctx, len, j, uj, w);
+    reduce_kernel<<<2 * j + 2, KB, 0, s>>>(ctx->part, nblk, hd + D_DOTS, nullptr);
+    dcgs_coef_kernel<<<1, 64, 0, s>>>(j, hd + D_DOTS, hd + D_COEF, slot);
+    dcgs_update(ctx, len, j, uj, w, hd + D_COEF);
+    reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, hd + D_NRM, nullptr, slot + S_NRM);
+    CPR_TRY(hipGetLastError());
+    CPR_TRY(hipEventRecord(ctx->ev_iter[j & 1], s));
+    return CPR_OK;
+  };
+  double nu_prev = 0.0, est = beta;
+  int launched = -1, rc;
+  k = 0;
+  for (int j = 0; j < m; ++j) {
+    if (launched < j) {
+      if ((rc = launch_step(j)) != CPR_OK) return rc;
+      launched = j;
+    }
+    // run step j + 1 on the device while the host waits for step j (as in
+    // the CGS2 path: only while the residual is far above the tolerance)
+    if (j + 1 < m && its + 1 < max_iter && est > SPECULATE * rtol * bnorm) {
+      if ((rc = launch_step(j + 1)) != CPR_OK) return rc;
+      launched = j + 1;
+    }
+    CPR_TRY(hipEventSynchronize(ctx->ev_iter[j & 1]));
+    const double* sl = ctx->hhost + D_HOST + (j & 1) * D_SLOT;
+    if (j > 0 && sl[S_FLAG] != 0.0) break;     // uh_j in the span of the basis: stop before step j
+    its += 1;
+    if (j > 0) {
+      for (int i = 0; i < j; ++i) Hh[(size_t)i * m + j - 1] += nu_prev * sl[S_A + i];
+      Hh[(size_t)j * m + j - 1] = nu_prev * sl[S_BETA];
+    }
+    for (int i = 0; i < j; ++i) Hh[(size_t)i * m + j] = sl[S_C + i];
+    Hh[(size_t)j * m + j] = sl[S_G];
+    const double nu = std::sqrt(sl[S_NRM]);
+    Hh[(size_t)(j + 1) * m + j] = nu;
+    k = j + 1;
+    double az = 0.0;
+    for (int i = 0; i <= j + 1; ++i) az += Hh[(size_t)i * m + j] * Hh[(size_t)i * m + j];
+    az = std::sqrt(az);
+    if (!std::isfinite(az)) return set_err(ctx, CPR_ENONFINITE, "non-finite Hessenberg column");
+    givens_qr(Hh, m, k, beta, R, g);
+    est = std::fabs(g[k]);
+    if (est <= rtol * bnorm || nu <= BREAKDOWN * az || its >= max_iter) break;
+    nu_prev = nu;
+  }
+  if (launched >= k) {
+    // a step ran ahead but the cycle ended: undo its learned-stage count
+    if (ctx->opt.learned) learned_discard_last(ctx);
+  }
+  givens_qr(Hh, m, k, beta, R, g);
+  return CPR_OK;
+}
+
 // ctx->rs holds the right-hand side, ctx->xs receives the solution
 // (colour-split); with options.x0 it also holds the initial guess.
 // Mirrors the oracle's FGMRES step for step.
@@ -417,6 +701,9 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
   const int max_iter = ctx->opt.max_iter;
   const int nblk = ctx->nblk;
   const int eb = div_up(len, 256);
+  // delayed CGS2 keeps up to 32 vectors' coefficients in registers; longer
+  // restarts use CGS2 (as the oracle does)
+  const bool dcgs = ctx->opt.orth == CPR_ORTH_DCGS2 && m <= 32;
   double* x = ctx->xs;
   double* r = ctx->tmp;
   cpr_stats_t S = {};
@@ -484,85 +771,92 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int k = 0;
-    bool breakdown_stop = false;
-    // Arnoldi step j on the device; its Hessenberg column lands in host slot
-    // j % 2 and event ev_iter[j % 2] marks its completion.
-    auto launch_step = [&](int j) -> int {
-      double* vj = ctx->V + (size_t)j * stride;
-      double* zj = ctx->Z + (size_t)j * stride;
-      double* w = ctx->V + (size_t)(j + 1) * stride;
-      const int nv = j + 1;
-      double* slot = ctx->hhost_dev + (j & 1) * 128;
-      // v_j = w_j / h_{j,j-1} is formed inside the preconditioner's first kernel
-      precond_apply(ctx, vj, vj, j == 0 ? nullptr : hd + 128, zj);
-      prof_begin(ctx, CPR_KCLASS_SPMV);
-      system_spmv(ctx, zj, w, nullptr);
-      prof_end(ctx, CPR_KCLASS_SPMV);
-      // CGS pass 1: h1 = V^T w
-      orth_pass(ctx, len, nv, w, nullptr, 0);
-      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd, nullptr);
-      // w -= V h1 ; h2 = V^T w
-      orth_pass(ctx, len, nv, w, hd, 0);
-      // h = h1 + h2 (device and host) and h2 alone
-      reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd, slot, hd + 192);
-      // w -= V h2 ; ||w||^2
-      orth_pass(ctx, len, nv, w, hd + 192, 1);
-      reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr, slot + 64);
-      CPR_TRY(hipGetLastError());
-      CPR_TRY(hipEventRecord(ctx->ev_iter[j & 1], s));
-      return CPR_OK;
-    };
-    int launched = -1;
-    for (int j = 0; j < m; ++j) {
-      if (launched < j) {
-        if ((rc = launch_step(j)) != CPR_OK) return rc;
-        launched = j;
-      }
-      its += 1;
-      // While the host waits for step j, the device may already run step
-      // j + 1: it needs nothing from the host.  Done only while the residual
-      // estimate is far above the tolerance, so that a step launched but not
-      // needed (the cycle ends at j) is rare; its results are then ignored.
-      if (j + 1 < m && its < max_iter && std::fabs(g[j]) > SPECULATE * rtol * bnorm) {
-        if ((rc = launch_step(j + 1)) != CPR_OK) return rc;
-        launched = j + 1;
-      }
-      CPR_TRY(hipEventSynchronize(ctx->ev_iter[j & 1]));
-      const double* slot = ctx->hhost + (j & 1) * 128;
-      const int nv = j + 1;
-      double hn = std::sqrt(slot[64]);
-      for (int i = 0; i <= m; ++i) col[i] = 0.0;
-      for (int i = 0; i < nv; ++i) col[i] = slot[i];
-      col[j + 1] = hn;
-      double az = 0.0;
-      for (int i = 0; i <= j + 1; ++i) az += col[i] * col[i];
-      az = std::sqrt(az);
-      if (!std::isfinite(az)) {
+    if (dcgs) {
+      if ((rc = dcgs2_cycle(ctx, beta, bnorm, its, k, H, g)) != CPR_OK) {
         if (st) *st = S;
-        return set_err(ctx, CPR_ENONFINITE, "non-finite Hessenberg column");
+        return rc;
       }
-      for (int i = 0; i < j; ++i) {
-        double t = cs[i] * col[i] + sn[i] * col[i + 1];
-        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-        col[i] = t;
+    } else {
+      bool breakdown_stop = false;
+      // Arnoldi step j on the device; its Hessenberg column lands in host slot
+      // j % 2 and event ev_iter[j % 2] marks its completion.
+      auto launch_step = [&](int j) -> int {
+        double* vj = ctx->V + (size_t)j * stride;
+        double* zj = ctx->Z + (size_t)j * stride;
+        double* w = ctx->V + (size_t)(j + 1) * stride;
+        const int nv = j + 1;
+        double* slot = ctx->hhost_dev + (j & 1) * 128;
+        // v_j = w_j / h_{j,j-1} is formed inside the preconditioner's first kernel
+        precond_apply(ctx, vj, vj, j == 0 ? nullptr : hd + 128, zj);
+        prof_begin(ctx, CPR_KCLASS_SPMV);
+        system_spmv(ctx, zj, w, nullptr);
+        prof_end(ctx, CPR_KCLASS_SPMV);
+        // CGS pass 1: h1 = V^T w
+        orth_pass(ctx, len, nv, w, nullptr, 0);
+        reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd, nullptr);
+        // w -= V h1 ; h2 = V^T w
+        orth_pass(ctx, len, nv, w, hd, 0);
+        // h = h1 + h2 (device and host) and h2 alone
+        reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd, slot, hd + 192);
+        // w -= V h2 ; ||w||^2
+        orth_pass(ctx, len, nv, w, hd + 192, 1);
+        reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr, slot + 64);
+        CPR_TRY(hipGetLastError());
+        CPR_TRY(hipEventRecord(ctx->ev_iter[j & 1], s));
+        return CPR_OK;
+      };
+      int launched = -1;
+      for (int j = 0; j < m; ++j) {
+        if (launched < j) {
+          if ((rc = launch_step(j)) != CPR_OK) return rc;
+          launched = j;
+        }
+        its += 1;
+        // While the host waits for step j, the device may already run step
+        // j + 1: it needs nothing from the host.  Done only while the residual
+        // estimate is far above the tolerance, so that a step launched but not
+        // needed (the cycle ends at j) is rare; its results are then ignored.
+        if (j + 1 < m && its < max_iter && std::fabs(g[j]) > SPECULATE * rtol * bnorm) {
+          if ((rc = launch_step(j + 1)) != CPR_OK) return rc;
+          launched = j + 1;
+        }
+        CPR_TRY(hipEventSynchronize(ctx->ev_iter[j & 1]));
+        const double* slot = ctx->hhost + (j & 1) * 128;
+        const int nv = j + 1;
+        double hn = std::sqrt(slot[64]);
+        for (int i = 0; i <= m; ++i) col[i] = 0.0;
+        for (int i = 0; i < nv; ++i) col[i] = slot[i];
+        col[j + 1] = hn;
+        double az = 0.0;
+        for (int i = 0; i <= j + 1; ++i) az += col[i] * col[i];
+        az = std::sqrt(az);
+        if (!std::isfinite(az)) {
+          if (st) *st = S;
+          return set_err(ctx, CPR_ENONFINITE, "non-finite Hessenberg column");
+        }
+        for (int i = 0; i < j; ++i) {
+          double t = cs[i] * col[i] + sn[i] * col[i + 1];
+          col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+          col[i] = t;
+        }
+        double den = std::hypot(col[j], col[j + 1]);
+        if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
+        else { cs[j] = col[j] / den; sn[j] = col[j + 1] / den; }
+        col[j] = den;
+        col[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        for (int i = 0; i <= m; ++i) H[(size_t)i * m + j] = col[i];
+        k = j + 1;
+        if (std::fabs(g[j + 1]) <= rtol * bnorm || its >= max_iter) break;
+        if (hn <= BREAKDOWN * az) { breakdown_stop = true; break; }
       }
-      double den = std::hypot(col[j], col[j + 1]);
-      if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
-      else { cs[j] = col[j] / den; sn[j] = col[j + 1] / den; }
-      col[j] = den;
-      col[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      for (int i = 0; i <= m; ++i) H[(size_t)i * m + j] = col[i];
-      k = j + 1;
-      if (std::fabs(g[j + 1]) <= rtol * bnorm || its >= max_iter) break;
-      if (hn <= BREAKDOWN * az) { breakdown_stop = true; break; }
+      if (launched >= k) {
+        // a step ran ahead but the cycle ended: undo its learned-stage count
+        if (ctx->opt.learned) learned_discard_last(ctx);
+      }
+      (void)breakdown_stop;
     }
-    if (launched >= k) {
-      // a step ran ahead but the cycle ended: undo its learned-stage count
-      if (ctx->opt.learned) learned_discard_last(ctx);
-    }
-    (void)breakdown_stop;
     // back substitution H[:k,:k] y = g[:k]
     for (int i = k - 1; i >= 0; --i) {
       double t = g[i];

@@ -20,11 +20,20 @@ def test_spmv_bytes_are_552_per_cell_plus_rhs_once_per_cycle():
 
 
 def test_orth_bytes_count_each_basis_vector_once_per_pass():
-    # step j of a cycle: three passes over nv = j + 1 vectors plus w
-    tot, launches = bench.algorithmic_bytes("orth", 3, N, [2], "fp64")
+    # CGS2, step j of a cycle: three passes over nv = j + 1 vectors plus w
+    tot, launches = bench.algorithmic_bytes("orth", 3, N, [2], "fp64", orth="cgs2")
     per = 3 * 8 * N
     assert launches == 6
     assert tot == ((1 + 1) + (1 + 2) + (1 + 2)) * per + ((2 + 1) + (2 + 2) + (2 + 2)) * per
+    # delayed CGS2, step j: dots over j vectors + uh + w, update over j
+    # vectors + uh + w read and v_j, u written
+    tot, launches = bench.algorithmic_bytes("orth", 3, N, [2], "fp64")
+    assert launches == 4
+    assert tot == ((0 + 2) + (0 + 4)) * per + ((1 + 2) + (1 + 4)) * per
+    # two passes instead of three: a third fewer bytes over a 30-step cycle
+    c2, _ = bench.algorithmic_bytes("orth", 3, N, [30], "fp64", orth="cgs2")
+    d2, _ = bench.algorithmic_bytes("orth", 3, N, [30], "fp64")
+    assert 0.6 < d2 / c2 < 0.7
 
 
 def test_smoother_counts_only_the_multi_block_levels():

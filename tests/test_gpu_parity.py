@@ -332,3 +332,26 @@ def test_fgmres_from_an_initial_guess_matches_oracle():
     z, st0 = s.solve(s.vector(), dx=_gpu(x0))
     assert st0["iterations"] == 0 and float(z.abs().max()) == 0.0
     s.close()
+
+
+@pytest.mark.parametrize("orth", ["cgs2", "dcgs2"])
+def test_fgmres_orthogonalisation_options_match_oracle(orth):
+    # both orthogonalisations against the oracle's, a full solve and a fixed
+    # path across a restart (k = 45 with restart 30)
+    case = CASES["bo-chan-48x24x8"]()
+    x = synth.random_state_perturbation(case, 17)
+    J, b = _oracle_system(case, x)
+    pc = cpr.cpr_setup(J)
+    A = lambda v: cpr.block_spmv(J, v)
+    M = lambda v: cpr.cpr_apply(pc, v)
+    s = _solver(case)
+    s.import_jacobian(J)
+    for kw in (dict(), dict(rtol=0.0, max_iter=45)):
+        s.setup(orth=orth, **kw)
+        dx, st = s.solve(_gpu(b))
+        xo, so = krylov.fgmres(A, M, b, orth=orth, **kw)
+        d = np.linalg.norm(_np(dx) - xo) / np.linalg.norm(xo)
+        print(f"[gpu-parity] {orth} {kw}: {st['iterations']} iterations (oracle {so['iterations']}), rel. diff {d:.1e}")
+        assert st["iterations"] == so["iterations"]
+        assert d <= 1e-8
+    s.close()

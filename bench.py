@@ -397,6 +397,7 @@ def main():
         if os.path.exists(wfile) and b == 3:
             solver.attach_network(np.load(wfile))
             forms.append(("mixed+learned", dict(precision="mixed", learned=1)))
+            forms.append(("mixed+learned fine level", dict(precision="mixed", learned=1, nn_level=0)))
             forms.append(("fp64+learned", dict(precision="fp64", learned=1)))
         tuned = dict(mg_pre=2, mg_post=2, mg_alpha=1.25)
         forms += [("fp64 V(2,2) alpha 1.25", dict(precision="fp64", **tuned)),
@@ -408,6 +409,8 @@ def main():
                               "true_rel": vsts[-1]["true_rel"], "speedup_vs_fp64": sec / sp,
                               "rel_diff_vs_fp64": _rel(dxv, dx64), "nn_accepted": vsts[-1]["nn_accepted"],
                               "fp64_fallback_after_cycle": vsts[-1].get("fp64_fallback", 0)}
+            if kw.get("learned"):
+                variants[name]["nn_level"] = solver.nn_level()
         solver.attach_network(None)
 
     phases, _ = run.phases(fp64)

@@ -88,6 +88,13 @@ enum { CPR_COMPOSE_PF = 0, CPR_COMPOSE_FPF = 1 };
  *   CPR_ORTH_CGS2   both passes in the step. */
 enum { CPR_ORTH_DCGS2 = 0, CPR_ORTH_CGS2 = 1 };
 
+/* options.nn_level: cpr_setup chooses the multigrid level of the learned
+ * stage -- the coarsest level of at least 2^19 cells that it can run on, the
+ * fine level when none qualifies.  The options stored in the context then
+ * hold the resolved level, which cpr_pressure_stage and cpr_nn_features use
+ * as well. */
+enum { CPR_NN_LEVEL_AUTO = -1 };
+
 /* Structured Cartesian grid: cell sizes in metres, depth of the top face in
  * metres (depth positive downward).  nx must be even: the library stores
  * every per-cell array split by red-black colour along x (coarse multigrid
@@ -155,12 +162,19 @@ typedef struct {
                           (0, default: from zero; BiCGSTAB always from zero) */
   int mg_pre, mg_post; /* red-black Gauss-Seidel sweeps before / after the
                           coarse correction, 1..8 (1, 1: V(1,1))            */
-  double stall_ratio;  /* MIXED, FGMRES: when a restart cycle ends with the
-                          true residual above stall_ratio times the one it
-                          started from, the remaining cycles apply the FP64
-                          preconditioner (default 0.5: less than halved;
-                          1.0: not decreased; <= 0: never)                 */
+  double stall_ratio;  /* MIXED or learned, FGMRES: when a restart cycle ends
+                          with the true residual above stall_ratio times the
+                          one it started from, the remaining cycles apply
+                          plain FP64 CPR (FP64 preconditioner, no learned
+                          stage; default 0.5: less than halved; 1.0: not
+                          decreased; <= 0: never)                          */
   int orth;            /* CPR_ORTH_DCGS2 (default) or CPR_ORTH_CGS2        */
+  int nn_level;        /* learned stage (learned = 1) on multigrid level:
+                          0: the fine pressure residual after the cycle;
+                          l >= 1: inside the cycle on level l, after its
+                          post-smoothing (cpr_nn_attach);
+                          CPR_NN_LEVEL_AUTO (default): chosen by cpr_setup,
+                          level 0 below about 4.2 M cells                 */
 } cpr_options_t;
 
 typedef struct {
@@ -173,9 +187,8 @@ typedef struct {
   double bnorm;        /* ||b||_2                                            */
   double est_rel;      /* GMRES estimate of ||b - A dx|| / ||b|| at the end  */
   double true_rel;     /* recomputed ||b - A dx|| / ||b||                    */
-  int fp64_fallback;   /* MIXED: restart cycles run with the FP32
-                          preconditioner before the FP64 one took over
-                          (0: it never did)                                 */
+  int fp64_fallback;   /* MIXED or learned: restart cycles run before plain
+                          FP64 CPR took over (0: it never did)              */
 } cpr_stats_t;
 
 typedef struct cpr_ctx cpr_ctx_t;
@@ -381,6 +394,9 @@ long long cpr_spmv_noalloc_max_unknowns(void);
  * the inverted ILU diagonals D'^-1 as [b][b][n]. */
 int cpr_export_qimpes(cpr_ctx_t* ctx, double* w);
 int cpr_mg_level_shape(const cpr_ctx_t* ctx, int level, int* nx, int* ny, int* nz);
+/* The multigrid level of the learned stage under the options of the last
+ * cpr_setup (CPR_NN_LEVEL_AUTO resolved); CPR_EINVAL before any setup. */
+int cpr_nn_level(const cpr_ctx_t* ctx, int* level);
 int cpr_export_mg_level(cpr_ctx_t* ctx, int level, double* a7);
 int cpr_export_ilu(cpr_ctx_t* ctx, double* dinv);
 
@@ -472,21 +488,32 @@ int cpr_nn_make_target(const double* e, long long n, double scale, float* t, voi
  * for a direction d = N(features), takes the residual-minimising step
  * dp_nn = alpha d, alpha = <A_p d, r'> / |A_p d|^2, and keeps dp_mg + dp_nn
  * only when ||r' - A_p dp_nn||_2 < ||r'||_2; otherwise the plain CPR result
- * stands.
- * The grid must have dimensions divisible by 8. */
+ * stands.  The grid must have dimensions divisible by 8.
+ * With options.nn_level = l >= 1 the same judged step acts inside the
+ * multigrid cycle on level l after its post-smoothing: r' = r_l - A_l x_l,
+ * the features are the means of ln k_x and ln lambda_t over each coarse
+ * cell's 2^l x 2^l x 2^l block of fine cells and D = diag A_l, and an
+ * accepted correction is added to x_l before the finer levels'
+ * post-smoothing.  Level l must then have dimensions divisible by 8, be
+ * exactly 2^-l times the grid along each axis, and lie above the levels the
+ * cycle handles in one workgroup (cpr_setup returns CPR_EINVAL otherwise). */
 int cpr_nn_attach(cpr_ctx_t* ctx, const float* theta);
 
 /* The pressure stage on one vector, for building training data (device,
  * natural order): r~_p = w^T v; dp_mg = V-cycle(r~_p); rprime = r~_p -
  * A_p dp_mg ([n] each; dp_mg may be NULL).  After cpr_setup with
- * quasi-IMPES decoupling (CPR_EINVAL otherwise). */
+ * quasi-IMPES decoupling (CPR_EINVAL otherwise).  With options.nn_level =
+ * l >= 1: rprime = r_l - A_l x_l, the residual the cycle leaves on level l
+ * after its post-smoothing, and dp_mg = x_l, both [n_l] in the natural
+ * order of level l. */
 int cpr_pressure_stage(cpr_ctx_t* ctx, const double* v, double* rprime, double* dp_mg);
 
 /* Network input for a pressure residual rprime (device [n]): feat device
  * [n][3] natural order; *scale (host) receives rms(D^-1 rprime), the factor
  * that converts network output to a pressure correction.  After cpr_setup
  * of an assembled Jacobian (the mobility channel comes from the state of
- * the last assembly). */
+ * the last assembly).  With options.nn_level = l >= 1, rprime and feat
+ * belong to level l ([n_l] and [n_l][3]). */
 int cpr_nn_features(cpr_ctx_t* ctx, const double* rprime, float* feat, double* scale);
 
 /* Basis vector v_j (device [b][n], natural order) of the last FGMRES

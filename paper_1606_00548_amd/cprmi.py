@@ -53,7 +53,7 @@ class Options(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double), ("mg_coarsest", ctypes.c_int),
                 ("mg_alpha", ctypes.c_double), ("decoupling", ctypes.c_int), ("composition", ctypes.c_int),
                 ("x0", ctypes.c_int), ("mg_pre", ctypes.c_int), ("mg_post", ctypes.c_int),
-                ("stall_ratio", ctypes.c_double), ("orth", ctypes.c_int)]
+                ("stall_ratio", ctypes.c_double), ("orth", ctypes.c_int), ("nn_level", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -143,7 +143,7 @@ def write_jsonl(path, stats):
 EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error", "cpr_block_size",
            "cpr_num_cells", "assemble_jacobian", "cpr_import_jacobian", "cpr_export_jacobian",
            "cpr_setup", "cpr_gmres_solve", "cpr_newton_update", "cpr_spmv", "cpr_precond_apply",
-           "cpr_export_qimpes", "cpr_mg_level_shape", "cpr_export_mg_level", "cpr_export_ilu",
+           "cpr_export_qimpes", "cpr_mg_level_shape", "cpr_nn_level", "cpr_export_mg_level", "cpr_export_ilu",
            "cpr_profile_kernel", "cpr_profile_read", "cpr_nn_num_params", "cpr_nn_create",
            "cpr_nn_destroy", "cpr_nn_last_error", "cpr_nn_set_params", "cpr_nn_get_params",
            "cpr_nn_forward", "cpr_nn_backward", "cpr_nn_train_step", "cpr_nn_attach",
@@ -195,6 +195,7 @@ def load():
     lib.cpr_mg_level_shape.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.cpr_export_mg_level.argtypes = [P, ctypes.c_int, P]
+    lib.cpr_nn_level.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
     lib.cpr_export_ilu.argtypes = [P, P]
     lib.cpr_profile_kernel.argtypes = [P, ctypes.c_int]
     lib.cpr_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
@@ -564,6 +565,12 @@ class Solver:
             return None
         return (nz.value, ny.value, nx.value)
 
+    def nn_level(self):
+        """Multigrid level of the learned stage under the last setup's options."""
+        lv = ctypes.c_int()
+        self._check(self.lib.cpr_nn_level(self.ctx, ctypes.byref(lv)))
+        return lv.value
+
     def export_mg_level(self, level):
         shape = self.mg_level_shape(level)
         a = torch.empty((7,) + shape, dtype=torch.float64, device="cuda")
@@ -589,16 +596,26 @@ class Solver:
         th = np.ascontiguousarray(theta, dtype=np.float32)
         self._check(self.lib.cpr_nn_attach(self.ctx, th.ctypes.data_as(ctypes.c_void_p)))
 
-    def pressure_stage(self, v):
-        """(r', dp_mg) of the pressure stage applied to v [b, nz, ny, nx]."""
-        rp = torch.empty(self.shape, dtype=torch.float64, device="cuda")
-        dp = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+    def pressure_stage(self, v, level=None):
+        """(r', dp_mg) of the pressure stage applied to v [b, nz, ny, nx]; on
+        the multigrid level of the learned stage under the last setup's
+        options (nn_level(); `level`, if given, must equal it): the residual
+        the cycle leaves there and that level's correction, in its natural
+        order."""
+        lv = self.nn_level()
+        if level is not None and level != lv:
+            raise ValueError(f"level {level} is not the learned stage's level {lv}")
+        level = lv
+        shape = self.shape if level == 0 else self.mg_level_shape(level)
+        rp = torch.empty(shape, dtype=torch.float64, device="cuda")
+        dp = torch.empty(shape, dtype=torch.float64, device="cuda")
         self._check(self.lib.cpr_pressure_stage(self.ctx, _ptr(v), _ptr(rp), _ptr(dp)))
         return rp, dp
 
     def features(self, rprime):
-        """Network input [nz, ny, nx, 3] for a pressure residual, and its scale."""
-        f = torch.empty(self.shape + (3,), dtype=torch.float32, device="cuda")
+        """Network input [nz, ny, nx, 3] for a pressure residual (on the
+        level options.nn_level of the last setup), and its scale."""
+        f = torch.empty(tuple(rprime.shape) + (3,), dtype=torch.float32, device="cuda")
         sc = ctypes.c_double()
         self._check(self.lib.cpr_nn_features(self.ctx, _ptr(rprime), _fptr(f), ctypes.byref(sc)))
         return f, sc.value

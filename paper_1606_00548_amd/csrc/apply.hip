@@ -699,12 +699,10 @@ __global__ __launch_bounds__(256) void fpf_resid_kernel(Lay L, const T* __restri
     prof_end(ctx, cls);    \
   } while (0)
 
-template <typename T>
-void vcycle(cpr_ctx* ctx) {
-  hipStream_t s = ctx->stream;
+// First level handled by the single-workgroup kernel (nl: none).
+int fused_level(const cpr_ctx* ctx) {
   const int nl = (int)ctx->levels.size();
   const int nc = ctx->levels.back().lay.n;
-  // first level handled by the single-workgroup kernel
   int fuse = nl;
   if (nc <= DENSE_FUSED_MAX && nl <= MAXLV) {
     fuse = nl - 1;
@@ -712,6 +710,15 @@ void vcycle(cpr_ctx* ctx) {
       if (ctx->levels[l].lay.n <= FUSE_MAX) { fuse = l; break; }
     if (nl == 1) fuse = 0;
   }
+  return fuse;
+}
+
+template <typename T>
+void vcycle(cpr_ctx* ctx) {
+  hipStream_t s = ctx->stream;
+  const int nl = (int)ctx->levels.size();
+  const int nc = ctx->levels.back().lay.n;
+  const int fuse = fused_level(ctx);
   const T alpha = (T)ctx->opt.mg_alpha;
   const int down = fuse < nl ? fuse : nl - 1;   // levels smoothed by multi-block kernels
   for (int l = 0; l < down; ++l) {
@@ -764,6 +771,9 @@ void vcycle(cpr_ctx* ctx) {
                                                                        Pre<T>::x(L), Pre<T>::res(L))));
       TIMED(CPR_KCLASS_SMOOTH, (red_kernel<T><<<nh, SB, 0, s>>>(L.lay, Pre<T>::A(L), Pre<T>::r(L), Pre<T>::x(L))));
     }
+    // the learned correction on this level, before the finer levels'
+    // post-smoothing (cpr_setup checked that it is a multi-block level)
+    if (learned_on(ctx) && ctx->opt.nn_level == l && l > 0) learned_stage_at(ctx, l);
   }
 }
 
@@ -806,7 +816,7 @@ void apply_variant(cpr_ctx* ctx, const double* vin, double* v, const double* nrm
     TIMED(CPR_KCLASS_ILU, (fpf_resid_kernel<B, T><<<nh, SB, 0, s>>>(L, J, R0, Z1, Rt, rp)));
   }
   vcycle<T>(ctx);
-  if (ctx->opt.learned) learned_stage(ctx);
+  if (learned_on(ctx) && ctx->opt.nn_level == 0) learned_stage(ctx);
   stage2<B, T, T>(ctx, Rt, FPF ? Z1 : nullptr, z);
 }
 
@@ -823,7 +833,7 @@ void apply_impl(cpr_ctx* ctx, const double* vin, double* v, const double* nrm2, 
   decouple_red_kernel<B, T><<<div_up(L.n, SB), SB, 0, s>>>(L.n, L.nh, ctx->w, vin, v, nrm2, Pre<T>::A(L0),
                                                             Pre<T>::r(L0), Pre<T>::x(L0));
   vcycle<T>(ctx);
-  if (ctx->opt.learned) learned_stage(ctx);
+  if (learned_on(ctx) && ctx->opt.nn_level == 0) learned_stage(ctx);
   // rows >= 1 of the quasi-IMPES decoupled residual are those of v
   stage2<B, T, double>(ctx, v, nullptr, z);
 }
@@ -852,6 +862,8 @@ __global__ void to_float_kernel(size_t n, const double* __restrict__ a, float* _
 
 }  // namespace
 
+int vcycle_fused_level(const cpr_ctx* ctx) { return fused_level(ctx); }
+
 void launch_mixed_copies(cpr_ctx* ctx) {
   hipStream_t s = ctx->stream;
   int n = ctx->lay.n;
@@ -868,8 +880,15 @@ void launch_mixed_copies(cpr_ctx* ctx) {
   }
 }
 
-// Pressure stage alone (FP64): r~_p = w^T v into level 0's r, dp_mg into its x.
+// Pressure stage alone (FP64, the plain cycle even when a learned stage is
+// set up): r~_p = w^T v into level 0's r, dp_mg into its x.
 void precond_pressure_stage(cpr_ctx* ctx, const double* v) {
+  struct PlainCycle {
+    cpr_ctx* c;
+    int learned;
+    ~PlainCycle() { c->opt.learned = learned; }
+  } plain{ctx, ctx->opt.learned};
+  ctx->opt.learned = 0;
   const Lay& L = ctx->lay;
   MGLevel& L0 = ctx->levels[0];
   if (ctx->b == 1)

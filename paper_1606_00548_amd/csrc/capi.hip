@@ -45,7 +45,7 @@ void free_all(cpr_ctx* ctx) {
                   ctx->Y, ctx->rp, ctx->xs, ctx->rs, ctx->tmp, ctx->vf, ctx->zf, ctx->Yf, ctx->rpf,
                   ctx->part, ctx->hdev, ctx->lnk, ctx->rprime, ctx->qbuf, ctx->feat, ctx->nnscal,
                   ctx->nncount, ctx->Wabf, ctx->Jt, ctx->Rt, ctx->Rtf, ctx->Z1, ctx->Z1f, ctx->rwells_d,
-                  ctx->bord, ctx->pq, ctx->bord_d};
+                  ctx->bord, ctx->pq, ctx->bord_d, ctx->lnk_l, ctx->lt_l};
   for (void* b : bufs) dev_free(ctx->mem, b);
   if (ctx->hhost) (void)hipHostFree(ctx->hhost);
   ctx->hhost = nullptr;
@@ -57,6 +57,8 @@ void free_all(cpr_ctx* ctx) {
   ctx->aux = nullptr;
   if (ctx->nn) cpr_nn_destroy(ctx->nn);
   ctx->nn = nullptr;
+  if (ctx->nn_lv) cpr_nn_destroy(ctx->nn_lv);
+  ctx->nn_lv = nullptr;
   ctx->ev.clear();
 }
 
@@ -288,6 +290,24 @@ int ensure_mixed(cpr_ctx* ctx) {
   return CPR_OK;
 }
 
+// The level the learned stage acts on with nn_level = CPR_NN_LEVEL_AUTO:
+// the coarsest level of at least 2^19 cells that it can run on (dimensions
+// divisible by 8, exactly 2^-l of the grid, colour-split, above the
+// single-workgroup levels); the fine level when no coarser one qualifies.
+int auto_nn_level(const cpr_ctx* ctx) {
+  const Lay& F = ctx->lay;
+  const int fuse = vcycle_fused_level(ctx);
+  int best = 0;
+  for (int l = 1; l < (int)ctx->levels.size() && l < fuse; ++l) {
+    const Lay& L = ctx->levels[l].lay;
+    if ((long)L.n < (1L << 19)) break;
+    if (L.cs && L.nxr == L.nx && L.nx % 8 == 0 && L.ny % 8 == 0 && L.nz % 8 == 0 && F.nx == L.nx << l &&
+        F.ny == L.ny << l && F.nz == L.nz << l)
+      best = l;
+  }
+  return best;
+}
+
 }  // namespace
 
 int ensure_krylov_capacity(cpr_ctx* ctx, int m) { return ensure_krylov(ctx, m); }
@@ -311,6 +331,7 @@ int setup_with_options(cpr_ctx* ctx, const cpr_options_t& opt) {
     return set_err(ctx, CPR_EINVAL, "unknown composition");
   if (opt.orth != CPR_ORTH_DCGS2 && opt.orth != CPR_ORTH_CGS2)
     return set_err(ctx, CPR_EINVAL, "unknown orthogonalisation");
+  if (opt.nn_level < CPR_NN_LEVEL_AUTO) return set_err(ctx, CPR_EINVAL, "nn_level must be >= -1");
   if (opt.learned && !ctx->nn) return set_err(ctx, CPR_EINVAL, "no pressure-correction network attached");
   ctx->opt = opt;
   ctx->setup_done = 0;
@@ -319,6 +340,7 @@ int setup_with_options(cpr_ctx* ctx, const cpr_options_t& opt) {
   if (opt.precision == CPR_PREC_MIXED && (rc = ensure_mixed(ctx)) != CPR_OK) return rc;
   if ((rc = ensure_variants(ctx, opt)) != CPR_OK) return rc;
   if ((rc = setup_cpr(ctx)) != CPR_OK) return rc;
+  if (ctx->opt.nn_level == CPR_NN_LEVEL_AUTO) ctx->opt.nn_level = auto_nn_level(ctx);
   if (opt.learned) {
     if ((rc = learned_setup(ctx, true)) != CPR_OK) {
       ctx->setup_done = 0;
@@ -356,6 +378,7 @@ void cpr_default_options(cpr_options_t* o) {
   o->mg_pre = 1;
   o->mg_post = 1;
   o->orth = CPR_ORTH_DCGS2;
+  o->nn_level = CPR_NN_LEVEL_AUTO;
 }
 
 int cpr_create(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, const double* poro,
@@ -589,6 +612,9 @@ int cpr_nn_attach(cpr_ctx_t* ctx, const float* theta) {
   if (!theta) {
     if (ctx->nn) cpr_nn_destroy(ctx->nn);
     ctx->nn = nullptr;
+    if (ctx->nn_lv) cpr_nn_destroy(ctx->nn_lv);
+    ctx->nn_lv = nullptr;
+    ctx->theta.clear();
     if (ctx->opt.learned) ctx->setup_done = 0;
     return CPR_OK;
   }
@@ -607,6 +633,9 @@ int cpr_nn_attach(cpr_ctx_t* ctx, const float* theta) {
   }
   int rc = cpr_nn_set_params(ctx->nn, theta);
   if (rc != CPR_OK) return set_err(ctx, rc, cpr_nn_last_error(ctx->nn));
+  ctx->theta.assign(theta, theta + cpr_nn_num_params());
+  if (ctx->nn_lv && (rc = cpr_nn_set_params(ctx->nn_lv, theta)) != CPR_OK)
+    return set_err(ctx, rc, cpr_nn_last_error(ctx->nn_lv));
   return CPR_OK;
   GUARD_END
 }
@@ -618,11 +647,16 @@ int cpr_pressure_stage(cpr_ctx_t* ctx, const double* v, double* rprime, double* 
   if (ctx->opt.decoupling != CPR_DECOUPLE_QIMPES)
     return set_err(ctx, CPR_EINVAL, "the pressure stage export needs quasi-IMPES decoupling");
   hipStream_t s = ctx->stream;
+  const int lv = ctx->opt.nn_level;
+  if (lv >= (int)ctx->levels.size()) return set_err(ctx, CPR_EINVAL, "nn_level beyond the hierarchy");
+  const Lay& L = ctx->levels[lv].lay;
+  if (lv > 0 && (!L.cs || L.nxr != L.nx))
+    return set_err(ctx, CPR_EINVAL, "nn_level: the level must be stored colour-split without a ghost column");
   launch_nat_to_cs(ctx->lay, ctx->b, v, ctx->vin, s);
   precond_pressure_stage(ctx, ctx->vin);
   learned_rprime(ctx);
-  launch_cs_to_nat(ctx->lay, 1, ctx->rprime, rprime, s);
-  if (dp_mg) launch_cs_to_nat(ctx->lay, 1, ctx->levels[0].x, dp_mg, s);
+  launch_cs_to_nat(L, 1, ctx->rprime, rprime, s);
+  if (dp_mg) launch_cs_to_nat(L, 1, ctx->levels[lv].x, dp_mg, s);
   return launch_check(ctx, "cpr_pressure_stage");
 }
 
@@ -634,9 +668,10 @@ int cpr_nn_features(cpr_ctx_t* ctx, const double* rprime, float* feat, double* s
   int rc = learned_setup(ctx, false);
   if (rc != CPR_OK) return rc;
   hipStream_t s = ctx->stream;
-  launch_nat_to_cs(ctx->lay, 1, rprime, ctx->rprime, s);
+  const Lay& L = ctx->levels[ctx->opt.nn_level].lay;
+  launch_nat_to_cs(L, 1, rprime, ctx->rprime, s);
   learned_features_from_rprime(ctx);
-  CPR_TRY(hipMemcpyAsync(feat, ctx->feat, 3 * (size_t)ctx->lay.n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  CPR_TRY(hipMemcpyAsync(feat, ctx->feat, 3 * (size_t)L.n * sizeof(float), hipMemcpyDeviceToDevice, s));
   double sc[8];
   CPR_TRY(hipMemcpyAsync(sc, ctx->nnscal, sizeof(sc), hipMemcpyDeviceToHost, s));
   CPR_TRY(hipStreamSynchronize(s));
@@ -690,6 +725,12 @@ int cpr_mg_level_shape(const cpr_ctx_t* ctx, int level, int* nx, int* ny, int* n
   if (!ctx || level < 0 || level >= (int)ctx->levels.size() || !nx || !ny || !nz) return CPR_EINVAL;
   const Lay& L = ctx->levels[level].lay;
   *nx = L.nxr; *ny = L.ny; *nz = L.nz;
+  return CPR_OK;
+}
+
+int cpr_nn_level(const cpr_ctx_t* ctx, int* level) {
+  if (!ctx || !level || !ctx->setup_done) return CPR_EINVAL;
+  *level = ctx->opt.nn_level;
   return CPR_OK;
 }
 

@@ -228,8 +228,8 @@ struct cpr_ctx {
   hipStream_t aux = nullptr;
   hipEvent_t ev_q = nullptr, ev_rap = nullptr, ev_gj = nullptr;
   hipEvent_t ev_iter[2] = {nullptr, nullptr};   // completion of Arnoldi steps (even, odd)
-  // set by FGMRES when a mixed-precision restart cycle stalls: the rest of
-  // that solve applies the FP64 preconditioner
+  // set by FGMRES when a restart cycle with the FP32 preconditioner or the
+  // learned stage stalls: the rest of that solve applies plain FP64 CPR
   bool fp64_now = false;
   cpr_grid_t grid;
   FluidDev fl;
@@ -309,6 +309,13 @@ struct cpr_ctx {
   double* nnscal = nullptr;    // device scalars: feature statistics, norms
   int* nncount = nullptr;      // [2] accepted / rejected corrections
   int assembled = 0;           // a Jacobian was assembled (mobility plane valid)
+  // learned stage on a coarse multigrid level (options.nn_level >= 1)
+  std::vector<float> theta;    // the attached parameters (host copy)
+  struct cpr_nn* nn_lv = nullptr;  // network on that level's grid
+  int nn_lv_dims[3] = {0, 0, 0};
+  double* lnk_l = nullptr;     // [n_l] mean ln kx over each coarse cell's fine block (level layout)
+  double* lt_l = nullptr;      // [n_l] exp(mean ln lambda_t) over the same block
+  size_t lvl_cap = 0;          // cells allocated in lnk_l / lt_l
 
   int prof_class = -1;
   std::vector<hipEvent_t> ev;  // start/stop pairs
@@ -387,6 +394,11 @@ void precond_pressure_stage(cpr_ctx* ctx, const double* v);
 // learned.hip
 int learned_setup(cpr_ctx* ctx, bool need_nn);
 int learned_stage(cpr_ctx* ctx);
+// The learned stage inside the V-cycle on multigrid level `level` (>= 1).
+int learned_stage_at(cpr_ctx* ctx, int level);
+// First multigrid level that the V-cycle smooths inside its single-workgroup
+// kernel (levels.size() when there is none).
+int vcycle_fused_level(const cpr_ctx* ctx);
 void learned_discard_last(cpr_ctx* ctx);
 void learned_rprime(cpr_ctx* ctx);
 void learned_features_from_rprime(cpr_ctx* ctx);
@@ -403,6 +415,9 @@ int time_step(cpr_ctx* ctx, const double* xold_cs, double* x_cs, double dt_days,
 // krylov.hip
 // The preconditioner runs in FP32: MIXED precision and no FP64 fallback.
 inline bool precond_fp32(const cpr_ctx* c) { return c->opt.precision == CPR_PREC_MIXED && !c->fp64_now; }
+// The learned stage runs: requested, and no stalled cycle has handed the
+// solve to plain FP64 CPR.
+inline bool learned_on(const cpr_ctx* c) { return c->opt.learned && !c->fp64_now; }
 
 int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st);
 int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st);

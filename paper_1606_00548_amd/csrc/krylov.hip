@@ -682,7 +682,7 @@ int dcgs2_cycle(cpr_ctx* ctx, double beta, double bnorm, int& its, int& k, std::
   }
   if (launched >= k) {
     // a step ran ahead but the cycle ended: undo its learned-stage count
-    if (ctx->opt.learned) learned_discard_last(ctx);
+    if (learned_on(ctx)) learned_discard_last(ctx);
   }
   givens_qr(Hh, m, k, beta, R, g);
   return CPR_OK;
@@ -755,13 +755,14 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     }
     if (beta <= rtol * bnorm) { result = CPR_OK; break; }
     if (its >= max_iter) break;
-    // mixed precision: a restart cycle that left the true residual above
-    // stall_ratio times the one it started from (by default: less than
-    // halved, where a healthy cycle gains one to two orders) hands the
-    // remaining cycles to the FP64 preconditioner (FGMRES is flexible, so
-    // the change of preconditioner between cycles needs nothing else)
-    if (S.cycles > 0 && ctx->opt.precision == CPR_PREC_MIXED && !ctx->fp64_now && ctx->opt.stall_ratio > 0 &&
-        beta > ctx->opt.stall_ratio * beta_start) {
+    // mixed precision or the learned stage: a restart cycle that left the
+    // true residual above stall_ratio times the one it started from (by
+    // default: less than halved, where a healthy cycle gains one to two
+    // orders) hands the remaining cycles to plain FP64 CPR (FGMRES is
+    // flexible, so the change of preconditioner between cycles needs nothing
+    // else)
+    if (S.cycles > 0 && (ctx->opt.precision == CPR_PREC_MIXED || ctx->opt.learned) && !ctx->fp64_now &&
+        ctx->opt.stall_ratio > 0 && beta > ctx->opt.stall_ratio * beta_start) {
       ctx->fp64_now = true;
       S.fp64_fallback = S.cycles;
     }
@@ -853,7 +854,7 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
       }
       if (launched >= k) {
         // a step ran ahead but the cycle ended: undo its learned-stage count
-        if (ctx->opt.learned) learned_discard_last(ctx);
+        if (learned_on(ctx)) learned_discard_last(ctx);
       }
       (void)breakdown_stop;
     }

@@ -23,6 +23,13 @@
 // 1/s, which the first convolution applies as it loads the input), the
 // network, A_p d with its sums read from the network output in natural
 // order, alpha and the decision, and the correction.
+//
+// With options.nn_level = l >= 1 the same kernels run inside the multigrid
+// cycle on level l (called after that level's post-smoothing): r' =
+// r_l - A_l x_l, D = diag A_l, and the state features are the means of
+// ln k_x and ln lambda_t over each coarse cell's 2^l x 2^l x 2^l block of
+// fine cells, formed at setup; a second network object on that level's
+// grid holds the same parameters.
 #include <cmath>
 
 #include "internal.h"
@@ -238,6 +245,29 @@ __global__ void discard_kernel(const double* __restrict__ scal, int* __restrict_
   if (threadIdx.x == 0) count[scal[S_ACC] > 0.0 ? 0 : 1] -= 1;
 }
 
+// State fields of multigrid level C (grid = fine grid / f per axis): the
+// mean of the fine ln kx over each coarse cell's f^3 block, and
+// exp(mean ln lambda_t) so that the feature kernels' log gives the mean.
+__global__ void level_fields_kernel(Lay F, Lay C, int f, const double* __restrict__ lnk,
+                                    const double* __restrict__ lt, double* __restrict__ lnk_l,
+                                    double* __restrict__ lt_l) {
+  int tc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tc >= C.n) return;
+  int ci, cj, ck;
+  lay_coords(C, tc, ci, cj, ck);
+  double a = 0.0, b = 0.0;
+  for (int dz = 0; dz < f; ++dz)
+    for (int dy = 0; dy < f; ++dy)
+      for (int dx = 0; dx < f; ++dx) {
+        const int t = lay_index(F, ci * f + dx, cj * f + dy, ck * f + dz);
+        a += lnk[t];
+        b += log(lt[t]);
+      }
+  const double inv = 1.0 / ((double)f * f * f);
+  lnk_l[tc] = a * inv;
+  lt_l[tc] = exp(b * inv);
+}
+
 __global__ void lnk_kernel(Lay L, const double* __restrict__ perm, double* __restrict__ lnk) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= L.n) return;
@@ -251,54 +281,111 @@ void launch_lnk(const Lay& L, const double* perm_nat, double* lnk, hipStream_t s
   lnk_kernel<<<div_up(L.n, 256), 256, 0, s>>>(L, perm_nat, lnk);
 }
 
-// Feature statistics of the current state (after assembly), at setup.
+
+// Feature statistics of the current state (after assembly), at setup, on
+// the level the learned stage acts on (options.nn_level).
 int learned_setup(cpr_ctx* ctx, bool need_nn) {
   if (need_nn && !ctx->nn) return set_err(ctx, CPR_EINVAL, "options.learned set but no network attached");
   if (!ctx->assembled) return set_err(ctx, CPR_EINVAL, "the learned stage needs an assembled state");
   const double* lt = ctx->props + (size_t)props_lt_plane(ctx->fl.model) * ctx->lay.n;
-  stats_partial_kernel<<<ctx->nblk, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->lnk, lt, ctx->part, ctx->nblk);
-  stats_final_kernel<<<1, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->part, ctx->nblk, ctx->nnscal);
-  state_features_kernel<<<div_up(ctx->lay.n, LB), LB, 0, ctx->stream>>>(ctx->lay, ctx->lnk, lt, ctx->nnscal,
-                                                                       ctx->feat);
+  const int lv = ctx->opt.nn_level;
+  if (lv == 0) {
+    stats_partial_kernel<<<ctx->nblk, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->lnk, lt, ctx->part, ctx->nblk);
+    stats_final_kernel<<<1, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->part, ctx->nblk, ctx->nnscal);
+    state_features_kernel<<<div_up(ctx->lay.n, LB), LB, 0, ctx->stream>>>(ctx->lay, ctx->lnk, lt, ctx->nnscal,
+                                                                         ctx->feat);
+    return launch_check(ctx, "learned_setup");
+  }
+  if (lv >= (int)ctx->levels.size() || lv >= vcycle_fused_level(ctx))
+    return set_err(ctx, CPR_EINVAL, "nn_level must name a multigrid level above those of the single-workgroup cycle");
+  const Lay& L = ctx->levels[lv].lay;
+  const Lay& F = ctx->lay;
+  if (!L.cs || L.nxr != L.nx || L.nx % 8 || L.ny % 8 || L.nz % 8 || F.nx != L.nx << lv || F.ny != L.ny << lv ||
+      F.nz != L.nz << lv)
+    return set_err(ctx, CPR_EINVAL, "nn_level: the level needs dimensions divisible by 8 and exactly 2^-l of the grid");
+  if (need_nn) {
+    if (ctx->theta.empty()) return set_err(ctx, CPR_EINVAL, "options.learned set but no network attached");
+    if (!ctx->nn_lv || ctx->nn_lv_dims[0] != L.nx || ctx->nn_lv_dims[1] != L.ny || ctx->nn_lv_dims[2] != L.nz) {
+      if (ctx->nn_lv) cpr_nn_destroy(ctx->nn_lv);
+      ctx->nn_lv = nullptr;
+      cpr_nn_t* nn = nullptr;
+      int rc = cpr_nn_create(L.nx, L.ny, L.nz, 1, ctx->stream, &nn);
+      if (rc != CPR_OK) {
+        std::string m = nn ? cpr_nn_last_error(nn) : "network creation failed";
+        if (nn) cpr_nn_destroy(nn);
+        return set_err(ctx, rc, m);
+      }
+      ctx->nn_lv = nn;
+      ctx->nn_lv_dims[0] = L.nx; ctx->nn_lv_dims[1] = L.ny; ctx->nn_lv_dims[2] = L.nz;
+      rc = cpr_nn_set_params(nn, ctx->theta.data());
+      if (rc != CPR_OK) return set_err(ctx, rc, cpr_nn_last_error(nn));
+    }
+  }
+  if (ctx->lvl_cap < (size_t)L.n) {
+    dev_free(ctx->mem, ctx->lnk_l);
+    dev_free(ctx->mem, ctx->lt_l);
+    ctx->lnk_l = ctx->lt_l = nullptr;
+    ctx->lvl_cap = 0;
+    CPR_TRY(dev_malloc(ctx->mem, (void**)&ctx->lnk_l, (size_t)L.n * sizeof(double)));
+    CPR_TRY(dev_malloc(ctx->mem, (void**)&ctx->lt_l, (size_t)L.n * sizeof(double)));
+    ctx->lvl_cap = L.n;
+  }
+  level_fields_kernel<<<div_up(L.n, LB), LB, 0, ctx->stream>>>(F, L, 1 << lv, ctx->lnk, lt, ctx->lnk_l, ctx->lt_l);
+  stats_partial_kernel<<<ctx->nblk, LB, 0, ctx->stream>>>(L.n, ctx->lnk_l, ctx->lt_l, ctx->part, ctx->nblk);
+  stats_final_kernel<<<1, LB, 0, ctx->stream>>>(L.n, ctx->part, ctx->nblk, ctx->nnscal);
+  state_features_kernel<<<div_up(L.n, LB), LB, 0, ctx->stream>>>(L, ctx->lnk_l, ctx->lt_l, ctx->nnscal, ctx->feat);
   return launch_check(ctx, "learned_setup");
 }
 
-// Blocks of the per-application stage kernels: one cell per thread where
-// the partial-sum buffer (66 nblk values, two per block here) allows.
-static int stage_blocks(const cpr_ctx* ctx) {
-  const long nb = div_up((long)ctx->lay.n, LB), cap = 32L * ctx->nblk;
+// Blocks of the per-application stage kernels on n cells: one cell per
+// thread where the partial-sum buffer (66 nblk values, two per block here)
+// allows.
+static int stage_blocks(const cpr_ctx* ctx, int n) {
+  const long nb = div_up((long)n, LB), cap = 32L * ctx->nblk;
   return (int)(nb < cap ? nb : cap);
 }
 
-// r' and its norms for rp, dp of the fine level (T = preconditioner type);
-// with rp == nullptr, ctx->rprime already holds r'.
-template <typename T>
-static void rprime_launch(cpr_ctx* ctx, const T* rp, const T* dp, float* feat = nullptr) {
-  const MGLevel& L0 = ctx->levels[0];
-  const int nb = stage_blocks(ctx);
-  rprime_kernel<T><<<nb, LB, 0, ctx->stream>>>(ctx->lay, L0.A, rp, dp, ctx->rprime, ctx->part, nb, feat);
-  rprime_final_kernel<<<1, LB, 0, ctx->stream>>>(ctx->lay.n, ctx->part, nb, ctx->nnscal);
+// The level the learned stage acts on: its layout, operator and state fields.
+struct StageLevel {
+  Lay L;
+  const double* A;
+  const double* lnk;
+  const double* lt;
+};
+
+static StageLevel stage_level(const cpr_ctx* ctx) {
+  const int lv = ctx->opt.nn_level;
+  if (lv == 0)
+    return {ctx->lay, ctx->levels[0].A, ctx->lnk, ctx->props + (size_t)props_lt_plane(ctx->fl.model) * ctx->lay.n};
+  return {ctx->levels[lv].lay, ctx->levels[lv].A, ctx->lnk_l, ctx->lt_l};
 }
 
-static void features_launch(cpr_ctx* ctx) {
-  const double* lt = ctx->props + (size_t)props_lt_plane(ctx->fl.model) * ctx->lay.n;
-  features_kernel<<<div_up(ctx->lay.n, LB), LB, 0, ctx->stream>>>(ctx->lay, ctx->lnk, lt, ctx->levels[0].A,
-                                                                  ctx->rprime, ctx->nnscal, ctx->feat);
+// r' and its norms for rp, dp of the stage's level (T = preconditioner
+// type); with rp == nullptr, ctx->rprime already holds r'.
+template <typename T>
+static void rprime_launch(cpr_ctx* ctx, const StageLevel& S, const T* rp, const T* dp, float* feat = nullptr) {
+  const int nb = stage_blocks(ctx, S.L.n);
+  rprime_kernel<T><<<nb, LB, 0, ctx->stream>>>(S.L, S.A, rp, dp, ctx->rprime, ctx->part, nb, feat);
+  rprime_final_kernel<<<1, LB, 0, ctx->stream>>>(S.L.n, ctx->part, nb, ctx->nnscal);
 }
 
-// The learned stage on the fine level's (rp, dp) of one CPR application.
+static void features_launch(cpr_ctx* ctx, const StageLevel& S) {
+  features_kernel<<<div_up(S.L.n, LB), LB, 0, ctx->stream>>>(S.L, S.lnk, S.lt, S.A, ctx->rprime, ctx->nnscal,
+                                                             ctx->feat);
+}
+
+// The learned stage on (rp, dp) of the stage's level in one CPR application.
 template <typename T>
-static int learned_stage_t(cpr_ctx* ctx, const T* rp, T* dp) {
+static int learned_stage_t(cpr_ctx* ctx, const StageLevel& S, cpr_nn* net, const T* rp, T* dp) {
   hipStream_t s = ctx->stream;
-  const Lay& L = ctx->lay;
-  rprime_launch<T>(ctx, rp, dp, ctx->feat);
-  int rc = nn_infer(ctx->nn, ctx->feat, nullptr, ctx->nnscal + S_INV);
+  rprime_launch<T>(ctx, S, rp, dp, ctx->feat);
+  int rc = nn_infer(net, ctx->feat, nullptr, ctx->nnscal + S_INV);
   if (rc) return set_err(ctx, rc, "network inference failed");
-  const float* y = nn_output(ctx->nn);
-  const int nb = stage_blocks(ctx);
-  apply_dir_kernel<<<nb, LB, 0, s>>>(L, ctx->levels[0].A, ctx->rprime, y, ctx->qbuf, ctx->part, nb);
+  const float* y = nn_output(net);
+  const int nb = stage_blocks(ctx, S.L.n);
+  apply_dir_kernel<<<nb, LB, 0, s>>>(S.L, S.A, ctx->rprime, y, ctx->qbuf, ctx->part, nb);
   alpha_kernel<<<1, LB, 0, s>>>(ctx->part, nb, ctx->nnscal, ctx->nncount);
-  correct_kernel<T><<<div_up(L.n, LB), LB, 0, s>>>(L, ctx->nnscal, y, dp);
+  correct_kernel<T><<<div_up(S.L.n, LB), LB, 0, s>>>(S.L, ctx->nnscal, y, dp);
   return CPR_OK;
 }
 
@@ -308,18 +395,27 @@ void learned_discard_last(cpr_ctx* ctx) {
 
 int learned_stage(cpr_ctx* ctx) {
   MGLevel& L0 = ctx->levels[0];
-  if (precond_fp32(ctx)) return learned_stage_t<float>(ctx, L0.rf, L0.xf);
-  return learned_stage_t<double>(ctx, L0.r, L0.x);
+  const StageLevel S = stage_level(ctx);
+  if (precond_fp32(ctx)) return learned_stage_t<float>(ctx, S, ctx->nn, L0.rf, L0.xf);
+  return learned_stage_t<double>(ctx, S, ctx->nn, L0.r, L0.x);
 }
 
-// r' for the fine level after a pressure stage (FP64 path).
+int learned_stage_at(cpr_ctx* ctx, int level) {
+  MGLevel& M = ctx->levels[level];
+  const StageLevel S = stage_level(ctx);
+  if (precond_fp32(ctx)) return learned_stage_t<float>(ctx, S, ctx->nn_lv, M.rf, M.xf);
+  return learned_stage_t<double>(ctx, S, ctx->nn_lv, M.r, M.x);
+}
+
+// r' on the stage's level after a plain pressure stage (FP64 path).
 void learned_rprime(cpr_ctx* ctx) {
-  MGLevel& L0 = ctx->levels[0];
-  rprime_launch<double>(ctx, L0.r, L0.x);
+  MGLevel& M = ctx->levels[ctx->opt.nn_level];
+  rprime_launch<double>(ctx, stage_level(ctx), M.r, M.x);
 }
 
 // Features for a residual already stored in ctx->rprime.
 void learned_features_from_rprime(cpr_ctx* ctx) {
-  rprime_launch<double>(ctx, nullptr, nullptr);
-  features_launch(ctx);
+  const StageLevel S = stage_level(ctx);
+  rprime_launch<double>(ctx, S, nullptr, nullptr);
+  features_launch(ctx, S);
 }

@@ -358,3 +358,73 @@ def test_train_step_gradient_and_adam_match_oracle():
     assert np.all(np.abs(th2 - th2_ref) <= tol), np.abs(th2 - th2_ref).max()
     net.close()
     net2.close()
+
+
+def _level_case():
+    # 64 x 64 x 16: level 1 (32 x 32 x 8, 8,192 cells) is smoothed by
+    # multi-block kernels, the levels from 16 x 16 x 4 down run in one
+    # workgroup
+    return synth.oil_water_lognormal(64, 64, 16, seed=73)
+
+
+def test_level_pressure_stage_and_features_match_oracle():
+    from paper_1606_00548_amd import cprmi
+    case = _level_case()
+    s = cprmi.Solver.from_case(case)
+    s.assemble(torch.as_tensor(case["x_old"]).cuda(), torch.as_tensor(case["x"]).cuda(), case["dt"])
+    s.setup(nn_level=1)
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                          case["x_old"], case["x"], case["dt"])
+    pc = cpr.cpr_setup(J)
+    b = -R
+    v = b / np.linalg.norm(b)
+    rp_g, _ = s.pressure_stage(torch.as_tensor(v).cuda().contiguous(), level=1)
+    rp_o = learned.level_residual(pc, v, 1)
+    d = np.linalg.norm(rp_g.cpu().numpy() - rp_o) / np.linalg.norm(rp_o)
+    print(f"[learned-level] level-1 residual rel. diff {d:.1e}")
+    assert rp_g.shape == rp_o.shape and d <= 1e-9
+    f_g, sc_g = s.features(torch.as_tensor(rp_o).cuda().contiguous())
+    lam = learned.total_mobility(case["fluid"], case["poro"], case["x"])
+    lnk, lnl = learned.level_fields(case["perm"], lam, 1)
+    f_o, sc_o = learned.level_features(lnk, lnl, pc["mg"]["levels"][1], rp_o)
+    assert abs(sc_g - sc_o) <= 1e-12 * sc_o
+    assert np.allclose(f_g.cpu().numpy(), f_o, rtol=1e-5, atol=1e-5)
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_level_learned_cpr_apply_matches_oracle(precision):
+    # the learned correction inside the cycle on level 1 against the oracle,
+    # with the tolerances of the fine-level stage: only the network's
+    # correction carries the BF16 tolerance
+    from paper_1606_00548_amd import cprmi
+    case = _level_case()
+    theta = _theta(9)
+    s = cprmi.Solver.from_case(case)
+    s.assemble(torch.as_tensor(case["x_old"]).cuda(), torch.as_tensor(case["x"]).cuda(), case["dt"])
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                          case["x_old"], case["x"], case["dt"])
+    pc = cpr.cpr_setup(J)
+    b = -R
+    v = b / np.linalg.norm(b)
+    lam = learned.total_mobility(case["fluid"], case["poro"], case["x"])
+    z_o, acc = learned.learned_cpr_apply(pc, v, theta, case["perm"], lam, level=1)
+    z_p = cpr.cpr_apply(pc, v)
+    s.attach_network(theta.astype(np.float32))
+    s.setup(learned=1, nn_level=1, precision=precision)
+    z_g = s.precond(torch.as_tensor(v).cuda().contiguous()).cpu().numpy()
+    corr = np.linalg.norm(z_o - z_p)
+    err = np.linalg.norm(z_g - z_o)
+    base = 1e-9 if precision == "fp64" else 1e-5
+    print(f"[learned-level] {precision} apply: accepted {acc}, |correction| {corr:.3e}, |gpu - oracle| {err:.3e}")
+    assert acc and corr > 1e-4 * np.linalg.norm(z_p)
+    assert err <= 3e-2 * corr + base * np.linalg.norm(z_o)
+    # a network that outputs zero is rejected: plain CPR remains
+    s.attach_network(np.zeros(nn.num_params(), np.float32))
+    s.setup(learned=1, nn_level=1, precision=precision)
+    z0 = s.precond(torch.as_tensor(v).cuda().contiguous()).cpu().numpy()
+    assert np.linalg.norm(z0 - z_p) <= base * np.linalg.norm(z_p)
+    # a level inside the single-workgroup cycle is refused
+    with pytest.raises(cprmi.CPRError):
+        s.setup(learned=1, nn_level=2)
+    s.close()

@@ -189,12 +189,33 @@ typedef struct {
   double true_rel;     /* recomputed ||b - A dx|| / ||b||                    */
   int fp64_fallback;   /* MIXED or learned: restart cycles run before plain
                           FP64 CPR took over (0: it never did)              */
+  /* Phase times in milliseconds of device time (stream time between HIP
+   * events), filled while cpr_set_timing is on, else 0.                     */
+  double ms_assemble;  /* the last assemble_jacobian before this solve      */
+  double ms_setup;     /* the last cpr_setup before this solve              */
+  double ms_solve;     /* this solve, from the first kernel to the last     */
+  double ms_precond;   /* its preconditioner applications                   */
+  double ms_spmv;      /* its block SpMVs (Krylov steps, true residuals)    */
+  double ms_orth;      /* FGMRES: orthogonalisation passes and their
+                          reductions; BiCGSTAB: inner products and vector
+                          updates                                            */
 } cpr_stats_t;
 
 typedef struct cpr_ctx cpr_ctx_t;
 
 /* Fill *o with the defaults listed above. */
 void cpr_default_options(cpr_options_t* o);
+
+/* Phase timers (measurement, not part of the method).  on = 1: HIP events
+ * on the context's stream bracket assemble_jacobian, cpr_setup, the solves
+ * and, inside a solve, every preconditioner application, SpMV and
+ * orthogonalisation step; a solve's cpr_stats_t then carries the times.
+ * The inner events are read back where the solver already waits for the
+ * device, so timing adds no synchronisation, only the event records.  on =
+ * 0 (default) records nothing.  Independently of this switch, every entry
+ * point of the library opens a roctx range named after it (visible to
+ * rocprofv3 --marker-trace).  CPR_EINVAL for a null context. */
+int cpr_set_timing(cpr_ctx_t* ctx, int on);
 
 /* Device memory: by default the library allocates with hipMalloc and frees
  * with hipFree.  cpr_set_allocator installs a caller's allocator instead

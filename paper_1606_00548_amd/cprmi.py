@@ -61,7 +61,9 @@ class Stats(ctypes.Structure):
                 ("mg_levels", ctypes.c_int), ("qimpes_fallback", ctypes.c_int),
                 ("nn_accepted", ctypes.c_int), ("nn_rejected", ctypes.c_int),
                 ("bnorm", ctypes.c_double), ("est_rel", ctypes.c_double),
-                ("true_rel", ctypes.c_double), ("fp64_fallback", ctypes.c_int)]
+                ("true_rel", ctypes.c_double), ("fp64_fallback", ctypes.c_int),
+                ("ms_assemble", ctypes.c_double), ("ms_setup", ctypes.c_double), ("ms_solve", ctypes.c_double),
+                ("ms_precond", ctypes.c_double), ("ms_spmv", ctypes.c_double), ("ms_orth", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -144,7 +146,7 @@ EXPORTS = ["cpr_default_options", "cpr_create", "cpr_destroy", "cpr_last_error",
            "cpr_num_cells", "assemble_jacobian", "cpr_import_jacobian", "cpr_export_jacobian",
            "cpr_setup", "cpr_gmres_solve", "cpr_newton_update", "cpr_spmv", "cpr_precond_apply",
            "cpr_export_qimpes", "cpr_mg_level_shape", "cpr_nn_level", "cpr_export_mg_level", "cpr_export_ilu",
-           "cpr_profile_kernel", "cpr_profile_read", "cpr_nn_num_params", "cpr_nn_create",
+           "cpr_profile_kernel", "cpr_profile_read", "cpr_set_timing", "cpr_nn_num_params", "cpr_nn_create",
            "cpr_nn_destroy", "cpr_nn_last_error", "cpr_nn_set_params", "cpr_nn_get_params",
            "cpr_nn_forward", "cpr_nn_backward", "cpr_nn_train_step", "cpr_nn_attach",
            "cpr_pressure_stage", "cpr_nn_features", "cpr_export_krylov", "cpr_nn_eval_loss",
@@ -198,6 +200,7 @@ def load():
     lib.cpr_nn_level.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
     lib.cpr_export_ilu.argtypes = [P, P]
     lib.cpr_profile_kernel.argtypes = [P, ctypes.c_int]
+    lib.cpr_set_timing.argtypes = [P, ctypes.c_int]
     lib.cpr_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
     lib.cpr_nn_num_params.restype = ctypes.c_longlong
     lib.cpr_nn_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.POINTER(P)]
@@ -581,6 +584,11 @@ class Solver:
         """Sample every launch of one kernel class with HIP events (None: off)."""
         k = -1 if kclass is None else KCLASS[kclass]
         self._check(self.lib.cpr_profile_kernel(self.ctx, k))
+
+    def set_timing(self, on=True):
+        """Phase timers: solves then report ms_assemble, ms_setup, ms_solve,
+        ms_precond, ms_spmv and ms_orth in their stats."""
+        self._check(self.lib.cpr_set_timing(self.ctx, 1 if on else 0))
 
     def profile_read(self):
         """(launches, total milliseconds) sampled since the last read; syncs."""

@@ -50,6 +50,7 @@ void free_all(cpr_ctx* ctx) {
   if (ctx->hhost) (void)hipHostFree(ctx->hhost);
   ctx->hhost = nullptr;
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  phase_timing_release(ctx);
   for (hipEvent_t e : {ctx->ev_q, ctx->ev_rap, ctx->ev_gj, ctx->ev_iter[0], ctx->ev_iter[1]})
     if (e) (void)hipEventDestroy(e);
   ctx->ev_q = ctx->ev_rap = ctx->ev_gj = ctx->ev_iter[0] = ctx->ev_iter[1] = nullptr;
@@ -423,10 +424,13 @@ int assemble_jacobian(cpr_ctx_t* ctx, const double* x_old, const double* x, doub
   GUARD_BEGIN
   if (!x_old || !x || !rhs_out) return set_err(ctx, CPR_EINVAL, "null argument");
   if (!(dt_days > 0) || !std::isfinite(dt_days)) return set_err(ctx, CPR_EINVAL, "dt must be > 0");
+  TraceRange tr("assemble_jacobian");
+  ph_outer_begin(ctx, PH_ASSEMBLE);
   CPR_TRY(vec_nat_to_cs(ctx, x_old, ctx->vin2));
   CPR_TRY(vec_nat_to_cs(ctx, x, ctx->vin));
   launch_assemble(ctx, ctx->vin2, ctx->vin, dt_days, ctx->vout);
   CPR_TRY(vec_cs_to_nat(ctx, ctx->vout, rhs_out));
+  ph_outer_end(ctx, PH_ASSEMBLE);
   ctx->assembled = 1;
   ctx->setup_done = 0;
   return launch_check(ctx, "assemble_jacobian");
@@ -453,7 +457,11 @@ int cpr_setup(cpr_ctx_t* ctx, const cpr_options_t* o) {
   GUARD_BEGIN
   cpr_options_t opt;
   if (o) opt = *o; else cpr_default_options(&opt);
-  return setup_with_options(ctx, opt);
+  TraceRange tr("cpr_setup");
+  ph_outer_begin(ctx, PH_SETUP);
+  int rc = setup_with_options(ctx, opt);
+  ph_outer_end(ctx, PH_SETUP);
+  return rc;
   GUARD_END
 }
 
@@ -462,6 +470,7 @@ int cpr_gmres_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_t* 
   GUARD_BEGIN
   if (!rhs || !dx) return set_err(ctx, CPR_EINVAL, "null argument");
   if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
+  TraceRange tr("cpr_gmres_solve");
   hipStream_t s = ctx->stream;
   CPR_TRY(vec_nat_to_cs(ctx, rhs, ctx->rs));
   if (ctx->opt.x0) CPR_TRY(vec_nat_to_cs(ctx, dx, ctx->xs));
@@ -514,6 +523,7 @@ int cpr_time_step(cpr_ctx_t* ctx, const double* x_old, double* x, double dt_days
   if (!(no.newton_tol > 0) || !(no.theta_min > 0) || !(no.theta_max >= no.theta_min) || !(no.theta0 > 0) ||
       !std::isfinite(no.theta_max) || !std::isfinite(no.gamma) || !std::isfinite(no.beta))
     return set_err(ctx, CPR_EINVAL, "bad Newton tolerances");
+  TraceRange tr("cpr_time_step");
   CPR_TRY(vec_nat_to_cs(ctx, x_old, ctx->vin2));
   int rc = time_step(ctx, ctx->vin2, ctx->vin, dt_days, lo, no, st);
   if (rc < 0) return rc;
@@ -534,6 +544,7 @@ int cpr_simulate(cpr_ctx_t* ctx, const double* x0, double* x, double t_end_days,
     return set_err(ctx, CPR_EINVAL, "bad time-stepping parameters");
   cpr_options_t lo;
   if (lin) lo = *lin; else cpr_default_options(&lo);
+  TraceRange tr("cpr_simulate");
   cpr_newton_options_t no;
   if (nopt) no = *nopt; else cpr_default_newton_options(&no);
   hipStream_t s = ctx->stream;
@@ -587,6 +598,7 @@ int cpr_bicgstab_solve(cpr_ctx_t* ctx, const double* rhs, double* dx, cpr_stats_
   if (!ctx->setup_done) return set_err(ctx, CPR_EINVAL, "cpr_setup has not been called for this Jacobian");
   int rc;
   if ((rc = ensure_krylov(ctx, ctx->opt.restart > 8 ? ctx->opt.restart : 8)) != CPR_OK) return rc;
+  TraceRange tr("cpr_bicgstab_solve");
   hipStream_t s = ctx->stream;
   CPR_TRY(vec_nat_to_cs(ctx, rhs, ctx->rs));
   if (ctx->opt.learned) CPR_TRY(hipMemsetAsync(ctx->nncount, 0, 2 * sizeof(int), s));
@@ -748,6 +760,13 @@ int cpr_export_ilu(cpr_ctx_t* ctx, double* dinv) {
   if (!dinv || !ctx->setup_done) return set_err(ctx, CPR_EINVAL, "null argument or no setup");
   launch_tiled_to_nat(ctx->lay, ctx->b * ctx->b, ctx->Dinv, dinv, ctx->stream);
   return launch_check(ctx, "cpr_export_ilu");
+}
+
+int cpr_set_timing(cpr_ctx_t* ctx, int on) {
+  if (check_ctx(ctx)) return CPR_EINVAL;
+  GUARD_BEGIN
+  return phase_timing_enable(ctx, on != 0);
+  GUARD_END
 }
 
 int cpr_profile_kernel(cpr_ctx_t* ctx, int kclass) {

@@ -219,6 +219,23 @@ struct MGLevel {
   float* resf = nullptr;
 };
 
+// Phase timers (timing.hip): one event pair per outer phase and a ring of
+// pairs for the inner phases of a solve (which do not nest), harvested in
+// order wherever the host already waits for the device.
+enum { PH_ASSEMBLE = 0, PH_SETUP = 1, PH_SOLVE = 2, PH_OUTER = 3 };
+enum { PH_PRECOND = 0, PH_SPMV = 1, PH_ORTH = 2, PH_INNER = 3 };
+struct PhaseTimer {
+  bool on = false;
+  hipEvent_t outer[PH_OUTER][2] = {};
+  bool outer_pending[PH_OUTER] = {};
+  double outer_ms[PH_OUTER] = {};
+  std::vector<hipEvent_t> ring;   // 2 * RING events
+  std::vector<int> kind;          // RING phase ids
+  int head = 0, count = 0;        // oldest recorded pair, pairs outstanding
+  bool open = false;              // an inner pair has begun and not ended
+  double inner_ms[PH_INNER] = {};
+};
+
 struct cpr_ctx {
   std::string err;
   DevAlloc mem;                // device allocator taken at creation
@@ -320,6 +337,8 @@ struct cpr_ctx {
   int prof_class = -1;
   std::vector<hipEvent_t> ev;  // start/stop pairs
   int ev_used = 0;
+
+  PhaseTimer pt;
 };
 
 // Bracket one launch of kernel class `k` with HIP events when it is sampled.
@@ -333,6 +352,33 @@ inline void prof_end(cpr_ctx* ctx, int k) {
     ctx->ev_used += 1;
   }
 }
+
+// Phase timers and roctx ranges (timing.hip).
+int phase_timing_enable(cpr_ctx* ctx, bool on);
+void phase_timing_release(cpr_ctx* ctx);
+void ph_outer_begin(cpr_ctx* ctx, int k);
+void ph_outer_end(cpr_ctx* ctx, int k);
+bool ph_begin(cpr_ctx* ctx, int k);
+void ph_end(cpr_ctx* ctx);
+void ph_harvest(cpr_ctx* ctx, bool wait);
+void ph_solve_start(cpr_ctx* ctx);
+void ph_fill_stats(cpr_ctx* ctx, cpr_stats_t* st);
+void trace_push(const char* name);
+void trace_pop();
+// A roctx range over one scope.
+struct TraceRange {
+  explicit TraceRange(const char* name) { trace_push(name); }
+  ~TraceRange() { trace_pop(); }
+};
+// One inner phase over one scope.
+struct PhaseScope {
+  cpr_ctx* c;
+  bool opened;
+  PhaseScope(cpr_ctx* ctx, int k) : c(ctx), opened(ph_begin(ctx, k)) {}
+  ~PhaseScope() {
+    if (opened) ph_end(c);
+  }
+};
 
 // ---------------------------------------------------------------- helpers
 #define CPR_TRY(expr)                                                         \

@@ -631,15 +631,24 @@ int dcgs2_cycle(cpr_ctx* ctx, double beta, double bnorm, int& its, int& k, std::
     double* w = ctx->V + (size_t)(j + 1) * stride;
     double* slot = ctx->hhost_dev + D_HOST + (j & 1) * D_SLOT;
     // slot j becomes uh_j = u_j / nu_j inside the preconditioner's first kernel
-    precond_apply(ctx, uj, uj, j == 0 ? nullptr : hd + D_NRM, zj);
-    prof_begin(ctx, CPR_KCLASS_SPMV);
-    system_spmv(ctx, zj, w, nullptr);
-    prof_end(ctx, CPR_KCLASS_SPMV);
-    dcgs_dots(ctx, len, j, uj, w);
-    reduce_kernel<<<2 * j + 2, KB, 0, s>>>(ctx->part, nblk, hd + D_DOTS, nullptr);
-    dcgs_coef_kernel<<<1, 64, 0, s>>>(j, hd + D_DOTS, hd + D_COEF, slot);
-    dcgs_update(ctx, len, j, uj, w, hd + D_COEF);
-    reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, hd + D_NRM, nullptr, slot + S_NRM);
+    {
+      PhaseScope ps(ctx, PH_PRECOND);
+      precond_apply(ctx, uj, uj, j == 0 ? nullptr : hd + D_NRM, zj);
+    }
+    {
+      PhaseScope ps(ctx, PH_SPMV);
+      prof_begin(ctx, CPR_KCLASS_SPMV);
+      system_spmv(ctx, zj, w, nullptr);
+      prof_end(ctx, CPR_KCLASS_SPMV);
+    }
+    {
+      PhaseScope ps(ctx, PH_ORTH);
+      dcgs_dots(ctx, len, j, uj, w);
+      reduce_kernel<<<2 * j + 2, KB, 0, s>>>(ctx->part, nblk, hd + D_DOTS, nullptr);
+      dcgs_coef_kernel<<<1, 64, 0, s>>>(j, hd + D_DOTS, hd + D_COEF, slot);
+      dcgs_update(ctx, len, j, uj, w, hd + D_COEF);
+      reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, hd + D_NRM, nullptr, slot + S_NRM);
+    }
     CPR_TRY(hipGetLastError());
     CPR_TRY(hipEventRecord(ctx->ev_iter[j & 1], s));
     return CPR_OK;
@@ -659,6 +668,7 @@ int dcgs2_cycle(cpr_ctx* ctx, double beta, double bnorm, int& its, int& k, std::
       launched = j + 1;
     }
     CPR_TRY(hipEventSynchronize(ctx->ev_iter[j & 1]));
+    ph_harvest(ctx, false);
     const double* sl = ctx->hhost + D_HOST + (j & 1) * D_SLOT;
     if (j > 0 && sl[S_FLAG] != 0.0) break;     // uh_j in the span of the basis: stop before step j
     its += 1;
@@ -715,6 +725,7 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     ~FallbackReset() { c->fp64_now = false; }
   } fallback_reset{ctx};
   ctx->fp64_now = false;
+  ph_solve_start(ctx);
 
   const bool from_x0 = ctx->opt.x0 != 0;
   if (!from_x0) zero_kernel<<<eb, 256, 0, s>>>(len, x);
@@ -730,10 +741,12 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
   if (bnorm == 0.0) {
     if (from_x0) zero_kernel<<<eb, 256, 0, s>>>(len, x);
     S.converged = 1;
+    ph_fill_stats(ctx, &S);
     if (st) *st = S;
     return CPR_OK;
   }
   if (from_x0) {
+    PhaseScope ps(ctx, PH_SPMV);
     system_spmv(ctx, x, r, ctx->rs);      // r = b - A x0
   } else {
     CPR_TRY(hipMemcpyAsync(r, ctx->rs, len * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -788,20 +801,29 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
         const int nv = j + 1;
         double* slot = ctx->hhost_dev + (j & 1) * 128;
         // v_j = w_j / h_{j,j-1} is formed inside the preconditioner's first kernel
-        precond_apply(ctx, vj, vj, j == 0 ? nullptr : hd + 128, zj);
-        prof_begin(ctx, CPR_KCLASS_SPMV);
-        system_spmv(ctx, zj, w, nullptr);
-        prof_end(ctx, CPR_KCLASS_SPMV);
-        // CGS pass 1: h1 = V^T w
-        orth_pass(ctx, len, nv, w, nullptr, 0);
-        reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd, nullptr);
-        // w -= V h1 ; h2 = V^T w
-        orth_pass(ctx, len, nv, w, hd, 0);
-        // h = h1 + h2 (device and host) and h2 alone
-        reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd, slot, hd + 192);
-        // w -= V h2 ; ||w||^2
-        orth_pass(ctx, len, nv, w, hd + 192, 1);
-        reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr, slot + 64);
+        {
+          PhaseScope ps(ctx, PH_PRECOND);
+          precond_apply(ctx, vj, vj, j == 0 ? nullptr : hd + 128, zj);
+        }
+        {
+          PhaseScope ps(ctx, PH_SPMV);
+          prof_begin(ctx, CPR_KCLASS_SPMV);
+          system_spmv(ctx, zj, w, nullptr);
+          prof_end(ctx, CPR_KCLASS_SPMV);
+        }
+        {
+          PhaseScope ps(ctx, PH_ORTH);
+          // CGS pass 1: h1 = V^T w
+          orth_pass(ctx, len, nv, w, nullptr, 0);
+          reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd, nullptr);
+          // w -= V h1 ; h2 = V^T w
+          orth_pass(ctx, len, nv, w, hd, 0);
+          // h = h1 + h2 (device and host) and h2 alone
+          reduce_kernel<<<nv, KB, 0, s>>>(ctx->part, nblk, hd + 64, hd, slot, hd + 192);
+          // w -= V h2 ; ||w||^2
+          orth_pass(ctx, len, nv, w, hd + 192, 1);
+          reduce_kernel<<<1, KB, 0, s>>>(ctx->part + (size_t)nv * nblk, nblk, hd + 128, nullptr, slot + 64);
+        }
         CPR_TRY(hipGetLastError());
         CPR_TRY(hipEventRecord(ctx->ev_iter[j & 1], s));
         return CPR_OK;
@@ -822,6 +844,7 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
           launched = j + 1;
         }
         CPR_TRY(hipEventSynchronize(ctx->ev_iter[j & 1]));
+        ph_harvest(ctx, false);
         const double* slot = ctx->hhost + (j & 1) * 128;
         const int nv = j + 1;
         double hn = std::sqrt(slot[64]);
@@ -869,12 +892,14 @@ int fgmres_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     maxpy_kernel<<<eb, 256, 0, s>>>(len, k, ctx->Z, stride, hd + 256, x);
     S.cycles += 1;
     S.est_rel = std::fabs(g[k]) / bnorm;
+    PhaseScope ps(ctx, PH_SPMV);
     prof_begin(ctx, CPR_KCLASS_SPMV);
     system_spmv(ctx, x, r, ctx->rs);
     prof_end(ctx, CPR_KCLASS_SPMV);
   }
   S.iterations = its;
   S.converged = result == CPR_OK;
+  ph_fill_stats(ctx, &S);
   if (st) *st = S;
   return result;
 }
@@ -901,6 +926,7 @@ int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st) {
   cpr_stats_t S = {};
   S.mg_levels = (int)ctx->levels.size();
   S.qimpes_fallback = ctx->qimpes_bad;
+  ph_solve_start(ctx);
 
   zero_kernel<<<eb, 256, 0, s>>>(len, x);
   double bb;
@@ -914,6 +940,7 @@ int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st) {
   }
   if (bnorm == 0.0) {
     S.converged = 1;
+    ph_fill_stats(ctx, &S);
     if (st) *st = S;
     return CPR_OK;
   }
@@ -935,24 +962,46 @@ int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st) {
     while (its < max_iter) {
       const double rho = hh[1];
       if (!(rho != 0.0) || !std::isfinite(rho)) { stop = true; break; }
-      bicg_p_kernel<<<eb, 256, 0, s>>>(len, sc, r, v, p);
-      precond_apply(ctx, p, p, nullptr, ph);
-      prof_begin(ctx, CPR_KCLASS_SPMV);
-      system_spmv(ctx, ph, v, nullptr);
-      prof_end(ctx, CPR_KCLASS_SPMV);
-      dot2_kernel<<<nblk, KB, 0, s>>>(len, rh, v, nullptr, nullptr, ctx->part, nblk);
-      bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 1, 0, sc, host);
-      bicg_s_kernel<<<eb, 256, 0, s>>>(len, sc, r, v, sv);
-      precond_apply(ctx, sv, sv, nullptr, sh);
-      prof_begin(ctx, CPR_KCLASS_SPMV);
-      system_spmv(ctx, sh, t, nullptr);
-      prof_end(ctx, CPR_KCLASS_SPMV);
-      dot2_kernel<<<nblk, KB, 0, s>>>(len, t, sv, t, t, ctx->part, nblk);
-      bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 2, 1, sc, host);
-      bicg_xr_kernel<<<nblk, KB, 0, s>>>(len, sc, ph, sh, sv, t, x, r, rh, ctx->part, nblk);
-      bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 2, 2, sc, host);
+      {
+        PhaseScope ps(ctx, PH_ORTH);
+        bicg_p_kernel<<<eb, 256, 0, s>>>(len, sc, r, v, p);
+      }
+      {
+        PhaseScope ps(ctx, PH_PRECOND);
+        precond_apply(ctx, p, p, nullptr, ph);
+      }
+      {
+        PhaseScope ps(ctx, PH_SPMV);
+        prof_begin(ctx, CPR_KCLASS_SPMV);
+        system_spmv(ctx, ph, v, nullptr);
+        prof_end(ctx, CPR_KCLASS_SPMV);
+      }
+      {
+        PhaseScope ps(ctx, PH_ORTH);
+        dot2_kernel<<<nblk, KB, 0, s>>>(len, rh, v, nullptr, nullptr, ctx->part, nblk);
+        bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 1, 0, sc, host);
+        bicg_s_kernel<<<eb, 256, 0, s>>>(len, sc, r, v, sv);
+      }
+      {
+        PhaseScope ps(ctx, PH_PRECOND);
+        precond_apply(ctx, sv, sv, nullptr, sh);
+      }
+      {
+        PhaseScope ps(ctx, PH_SPMV);
+        prof_begin(ctx, CPR_KCLASS_SPMV);
+        system_spmv(ctx, sh, t, nullptr);
+        prof_end(ctx, CPR_KCLASS_SPMV);
+      }
+      {
+        PhaseScope ps(ctx, PH_ORTH);
+        dot2_kernel<<<nblk, KB, 0, s>>>(len, t, sv, t, t, ctx->part, nblk);
+        bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 2, 1, sc, host);
+        bicg_xr_kernel<<<nblk, KB, 0, s>>>(len, sc, ph, sh, sv, t, x, r, rh, ctx->part, nblk);
+        bicg_reduce_kernel<<<1, KB, 0, s>>>(ctx->part, nblk, 2, 2, sc, host);
+      }
       CPR_TRY(hipGetLastError());
       CPR_TRY(hipStreamSynchronize(s));
+      ph_harvest(ctx, false);
       if (hh[3] != 0.0) { stop = true; break; }       // <rh, v> vanished: x unchanged
       its += 1;
       const double rr = hh[0];
@@ -966,9 +1015,12 @@ int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st) {
       if (hh[2] == 0.0) { stop = true; break; }       // omega vanished
     }
     // true residual r = b - A x
-    prof_begin(ctx, CPR_KCLASS_SPMV);
-    system_spmv(ctx, x, r, ctx->rs);
-    prof_end(ctx, CPR_KCLASS_SPMV);
+    {
+      PhaseScope ps(ctx, PH_SPMV);
+      prof_begin(ctx, CPR_KCLASS_SPMV);
+      system_spmv(ctx, x, r, ctx->rs);
+      prof_end(ctx, CPR_KCLASS_SPMV);
+    }
     double rr;
     rc = reduce_dot(ctx, r, r, len, &rr);
     if (rc) return rc;
@@ -983,6 +1035,7 @@ int bicgstab_solve(cpr_ctx* ctx, cpr_stats_t* st) {
   }
   S.iterations = its;
   S.converged = result == CPR_OK;
+  ph_fill_stats(ctx, &S);
   if (st) *st = S;
   return result;
 }

@@ -332,6 +332,54 @@ def _rel(a, b):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
+def newton_iterations_mixed_vs_fp64(s, case, iters=10, dt0=0.01, newton_tol=1e-3):
+    """The first `iters` Newton iterations of the workload's time stepping
+    (Algorithm 1 with every system solved to 1e-6; steps from dt0 days,
+    doubling after each converged step, as the simulation's) along two
+    paths, plain FP64 CPR and the FP32 preconditioner.  Both paths take the
+    same step lengths and, within a step, as many iterations as the FP64
+    path needs to reach ||F(x_l)|| < newton_tol ||F(x_0)||.  Per iteration:
+    the nonlinear residual of each path, the FGMRES iterations, the relative
+    difference of the mixed correction from the FP64 one on the same
+    (FP64-path) state, and the relative difference of the two paths' states
+    after the update."""
+    import torch
+    from paper_1606_00548_amd import cprmi
+    o64 = cprmi.default_options(precision="fp64")
+    om = cprmi.default_options(precision="mixed")
+    old64 = torch.as_tensor(case["x_old"]).cuda()
+    oldm = old64.clone()
+    x64, xm = old64.clone(), oldm.clone()
+    rows = []
+    dt, step, f0 = dt0, 1, None
+    while len(rows) < iters:
+        rhs = s.assemble(old64, x64, dt)
+        f64 = float(torch.linalg.vector_norm(rhs))
+        f0 = f64 if f0 is None else f0
+        if f64 < newton_tol * f0:
+            # the step converged: both paths start the next one from it
+            old64, oldm = x64.clone(), xm.clone()
+            dt, step, f0 = min(2 * dt, case["dt"]), step + 1, None
+            continue
+        s.setup(o64)
+        dx64, st64 = s.solve(rhs)
+        s.setup(om)
+        dxs, sts = s.solve(rhs)
+        same = _rel(dxs, dx64)
+        rhm = s.assemble(oldm, xm, dt)
+        s.setup(om)
+        dxm, stm = s.solve(rhm)
+        s.newton_update(x64, dx64)
+        s.newton_update(xm, dxm)
+        torch.cuda.synchronize()
+        rows.append({"iteration": len(rows) + 1, "time_step": step, "dt_days": dt, "residual_fp64": f64,
+                     "residual_mixed": float(torch.linalg.vector_norm(rhm)),
+                     "fgmres_fp64": st64["iterations"], "fgmres_mixed": stm["iterations"],
+                     "dx_rel_diff_same_state": same, "state_rel_diff_after": _rel(xm, x64),
+                     "true_rel_fp64": st64["true_rel"], "true_rel_mixed": stm["true_rel"]})
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,6 +451,8 @@ def main():
         forms += [("fp64 V(2,2) alpha 1.25", dict(precision="fp64", **tuned)),
                   ("mixed V(2,2) alpha 1.25", dict(precision="mixed", **tuned)),
                   ("fp64 CGS2", dict(precision="fp64", orth="cgs2"))]
+        if os.path.exists(wfile) and b == 3:
+            forms.append(("mixed+learned V(2,2) alpha 1.25", dict(precision="mixed", learned=1, **tuned)))
         for name, kw in forms:
             sp, _, vsts, dxv, _ = run.timed(cprmi.default_options(**kw), vs, 1)
             variants[name] = {"s_per_step": sp, "krylov_iterations": vsts[-1]["iterations"],
@@ -557,6 +607,11 @@ def other_configs(steps=2):
                 res[f"simulation {prec}"] = {"s": t2 - t1, "steps": sst["steps"], "cuts": sst["cuts"],
                                              "total_newton": sst["total_newton"], "total_linear": sst["total_linear"],
                                              "completed": bool(sst["completed"])}
+        if name.startswith("black-oil channelised"):
+            try:
+                res["newton_iterations_mixed_vs_fp64"] = newton_iterations_mixed_vs_fp64(s, case)
+            except cprmi.CPRError as e:
+                res["newton_iterations_mixed_vs_fp64"] = {"error": str(e)}
         s.attach_network(None)
         run = None
         s.close()

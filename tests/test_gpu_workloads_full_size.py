@@ -218,3 +218,26 @@ def test_lattice_512x512x128_mixed_learned_vs_fp64():
         res["mixed+learned"][0]["iterations"]
     s.attach_network(None)
     s.close()
+
+
+def test_channelised_256x256x64_newton_iterations_mixed_error_per_iteration():
+    # the first ten Newton iterations of the channelised system's time
+    # stepping (from 0.01 day, doubling) along the FP64 and the mixed path:
+    # every system reaches 1e-6, the mixed correction stays within 1e-4 of
+    # the FP64 one on the same state, and the two paths' states agree to
+    # 1e-4 after every update
+    import bench
+    from paper_1606_00548_amd import cprmi
+    print("[full-size] black oil channelised 256x256x64, first 10 Newton iterations, mixed vs FP64", flush=True)
+    case = synth.black_oil_channelised()
+    s = cprmi.Solver.from_case(case)
+    rows = bench.newton_iterations_mixed_vs_fp64(s, case, 10)
+    assert len(rows) == 10
+    for r in rows:
+        print(f"[full-size]   step {r['time_step']} (dt {r['dt_days']:g} d), it {r['iteration']}: |F| fp64 {r['residual_fp64']:.3e} "
+              f"mixed {r['residual_mixed']:.3e}; FGMRES {r['fgmres_fp64']}/{r['fgmres_mixed']}; "
+              f"dx diff {r['dx_rel_diff_same_state']:.2e}; state diff {r['state_rel_diff_after']:.2e}", flush=True)
+        assert r["true_rel_fp64"] <= 1e-6 and r["true_rel_mixed"] <= 1e-6
+        assert r["dx_rel_diff_same_state"] <= 1e-4
+        assert r["state_rel_diff_after"] <= 1e-4
+    s.close()

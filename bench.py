@@ -3,7 +3,10 @@
 
 One step = assemble the Jacobian and right-hand side, set up the CPR
 preconditioner, solve with FGMRES(30) to a relative residual of 1e-6, and
-update the state (Algorithm 1, one iteration).  The default workload is the
+update the state (Algorithm 1, one iteration).  Every form on the line uses
+the same CPR: quasi-IMPES decoupling, an aggregation multigrid V(2,2) cycle
+with its coarse correction scaled by 1.25 for the pressure, red-black block
+ILU(0); the library's default V(1,1) cycle is reported beside it.  The default workload is the
 largest single-GPU one: saturated black oil on a 512 x 512 x 128 grid
 (33.5 M cells, 3x3 blocks, a 17 GB FP64 Jacobian), lognormal permeability
 with sigma 1.5 correlated over (4, 4, 1) cells, kz = 0.1 kx, 25 BHP wells on
@@ -36,6 +39,11 @@ BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak of the device
 # (input, output) channels and grid level (0 = full, l = 1/2^l per axis) of
 # the seven 3x3x3 convolutions of the pressure network
 NET_CONVS = [(3, 16, 0), (16, 32, 1), (32, 64, 2), (64, 64, 3), (64, 64, 2), (64, 32, 1), (32, 16, 0)]
+
+# multigrid cycle of every form on the headline line: two red-black
+# Gauss-Seidel sweeps before and after the coarse correction, which is scaled
+# by 1.25 (the library default is V(1,1) with alpha 1; both are reported)
+CYCLE = dict(mg_pre=2, mg_post=2, mg_alpha=1.25)
 
 # workload name -> (synth generator, default shape)
 WORKLOADS = {
@@ -87,12 +95,13 @@ def network_timing(nx, ny, nz, reps=20):
             "frac_of_bf16_peak": tflops / BF16_PEAK_TFLOPS, "grid": [nx, ny, nz], "batch": 1}
 
 
-def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision, levels=None, orth="dcgs2"):
+def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision, levels=None, orth="dcgs2", pre=1, post=1):
     """Bytes the launches of one kernel class in one Newton step must move at
     minimum (every array element touched once per launch, FP64), and the
     number of those launches.  iterations_per_cycle: Arnoldi steps of each
     restart cycle; levels: cell counts of the multigrid levels; orth: the
-    FGMRES orthogonalisation (delayed CGS2 or CGS2)."""
+    FGMRES orthogonalisation (delayed CGS2 or CGS2); pre / post: sweeps of
+    the V(pre, post) cycle."""
     s = 8
     its = sum(iterations_per_cycle)
     if kclass == "spmv":
@@ -121,14 +130,16 @@ def algorithmic_bytes(kclass, b, n, iterations_per_cycle, precision, levels=None
         # multi-block kernels (those above the first level of <= 4096 cells):
         # black pre-sweep 11 values per black cell (7 stencil, r, x, res, red x),
         # black post-sweep 10 + coarse correction n/8, red sweep 10 (the
-        # zero-guess red sweeps ride with the decoupling on the fine level and
-        # with the restriction on the others)
+        # zero-guess red sweep of the first pre-sweep rides with the
+        # decoupling on the fine level and with the restriction on the
+        # others); each further pre-sweep is red + black pre, each further
+        # post-sweep black pre + red
         down = next((l for l, nl in enumerate(levels) if nl <= 4096), len(levels) - 1)
         per, launches = 0, 0
         for l in range(down):
             nl = levels[l]
-            per += (44 + 41 + 40) * nl
-            launches += 3
+            per += (44 + 41 + 40 + (pre - 1 + post - 1) * (40 + 44)) * nl
+            launches += 3 + 2 * (pre - 1 + post - 1)
         return its * per, its * launches
     if kclass == "ilu":
         # stage-2 residual and red-black block ILU(0) sweeps, per cell of a
@@ -169,9 +180,10 @@ def _oracle_window(args):
         R, J = model.assemble(sub["grid"], sub["fluid"], sub["perm"], sub["poro"], sub["wells"],
                               sub["x_old"], sub["x"], sub["dt"])
         t1 = time.perf_counter()
-        pc = cpr.cpr_setup(J)
+        pc = cpr.cpr_setup(J, pre=CYCLE["mg_pre"], post=CYCLE["mg_post"])
         t2 = time.perf_counter()
-        dx, st = krylov.fgmres(lambda v: cpr.block_spmv(J, v), lambda v: cpr.cpr_apply(pc, v), -R)
+        dx, st = krylov.fgmres(lambda v: cpr.block_spmv(J, v),
+                               lambda v: cpr.cpr_apply(pc, v, alpha=CYCLE["mg_alpha"]), -R)
         t3 = time.perf_counter()
         newton.newton_update(sub["x"], dx, float(sub["fluid"]["pvt"][0][0]) if sub["fluid"]["model"] == 3 else None)
         t4 = time.perf_counter()
@@ -228,7 +240,8 @@ def cpu_baseline_value(sample, n, gpu_iterations, class_bytes):
         "value": value, "unit": "s/Newton step", "cores": sample["processes"], "kind": "oracle",
         "sample": (f"{sample['processes']} window(s) of {'x'.join(map(str, sample['window']))} cells of the "
                    f"same workload{' (the whole grid)' if sample['whole_grid'] else ', centred on wells'}, one full "
-                   "Newton step each (assemble, CPR setup, FGMRES(30) to 1e-6, update) in a single-threaded "
+                   "Newton step each (assemble, CPR setup, FGMRES(30) with the V(2,2), alpha 1.25 cycle to "
+                   "1e-6, update) in a single-threaded "
                    "numpy process per window, all running at once; value = measured per-cell assembly/setup/"
                    f"update time x {n} cells + measured per-cell-per-iteration FGMRES time x {n} cells x "
                    f"{gpu_iterations} iterations (the whole system's FP64 count)"),
@@ -285,20 +298,24 @@ class Stepper:
         return (t1 - t0) / steps, [b - a for a, b in zip(marks[:-1], marks[1:])], sts, dx, prof
 
     def phases(self, o):
+        """Device time of each phase of one Newton step from the library's
+        phase timers (HIP events on its stream), milliseconds."""
         torch = self.torch
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        self.s.set_timing(True)
         self.x.copy_(self.x0)
-        ev[0].record()
         rhs = self.s.assemble(self.x_old, self.x, self.case["dt"])
-        ev[1].record()
         self.s.setup(o)
-        ev[2].record()
         dx, st = self.s.solve(rhs)
-        ev[3].record()
-        self.s.newton_update(self.x, dx)
-        ev[4].record()
         torch.cuda.synchronize()
-        return {k: ev[i].elapsed_time(ev[i + 1]) for i, k in enumerate(["assemble", "setup", "solve", "update"])}, st
+        t0 = time.perf_counter()
+        self.s.newton_update(self.x, dx)
+        torch.cuda.synchronize()
+        upd = (time.perf_counter() - t0) * 1e3
+        self.s.set_timing(False)
+        out = {"assemble": st["ms_assemble"], "setup": st["ms_setup"], "solve": st["ms_solve"],
+               "update (host-timed)": upd, "solve: preconditioner": st["ms_precond"], "solve: spmv": st["ms_spmv"],
+               "solve: orthogonalisation": st["ms_orth"]}
+        return out, st
 
 
 def measured_bandwidth():
@@ -428,7 +445,7 @@ def main():
     if args.kernel_only:
         print(json.dumps(kernel_only(run, args.kernel_only, n, b)))
         return
-    fp64 = cprmi.default_options(precision="fp64")
+    fp64 = cprmi.default_options(precision="fp64", **CYCLE)
 
     # headline: plain FP64 CPR, no per-launch events inside the timed steps
     sec, host_times, sts, dx64, _ = run.timed(fp64, args.steps, args.warmup)
@@ -441,18 +458,18 @@ def main():
     wfile = train.weights_path("black-oil")
     if not args.no_variants:
         vs = min(args.variant_steps, args.steps)
-        forms = [("mixed", dict(precision="mixed"))]
-        if os.path.exists(wfile) and b == 3:
+        learned = os.path.exists(wfile) and b == 3
+        forms = [("mixed", dict(precision="mixed", **CYCLE))]
+        if learned:
             solver.attach_network(np.load(wfile))
-            forms.append(("mixed+learned", dict(precision="mixed", learned=1)))
-            forms.append(("mixed+learned fine level", dict(precision="mixed", learned=1, nn_level=0)))
-            forms.append(("fp64+learned", dict(precision="fp64", learned=1)))
-        tuned = dict(mg_pre=2, mg_post=2, mg_alpha=1.25)
-        forms += [("fp64 V(2,2) alpha 1.25", dict(precision="fp64", **tuned)),
-                  ("mixed V(2,2) alpha 1.25", dict(precision="mixed", **tuned)),
-                  ("fp64 CGS2", dict(precision="fp64", orth="cgs2"))]
-        if os.path.exists(wfile) and b == 3:
-            forms.append(("mixed+learned V(2,2) alpha 1.25", dict(precision="mixed", learned=1, **tuned)))
+            forms.append(("mixed+learned", dict(precision="mixed", learned=1, **CYCLE)))
+            forms.append(("mixed+learned fine level", dict(precision="mixed", learned=1, nn_level=0, **CYCLE)))
+            forms.append(("fp64+learned", dict(precision="fp64", learned=1, **CYCLE)))
+        forms += [("fp64 CGS2", dict(precision="fp64", orth="cgs2", **CYCLE)),
+                  ("fp64 V(1,1) alpha 1", dict(precision="fp64")),
+                  ("mixed V(1,1) alpha 1", dict(precision="mixed"))]
+        if learned:
+            forms.append(("mixed+learned V(1,1) alpha 1", dict(precision="mixed", learned=1)))
         for name, kw in forms:
             sp, _, vsts, dxv, _ = run.timed(cprmi.default_options(**kw), vs, 1)
             variants[name] = {"s_per_step": sp, "krylov_iterations": vsts[-1]["iterations"],
@@ -474,7 +491,7 @@ def main():
     classes = {}
     for cls in ("spmv", "orth", "smooth", "ilu"):
         _, _, _, _, (nl, ms) = run.timed(fp64, ks, 0, kclass=cls)
-        ab, al = algorithmic_bytes(cls, b, n, per_cycle, "fp64", levels)
+        ab, al = algorithmic_bytes(cls, b, n, per_cycle, "fp64", levels, pre=CYCLE["mg_pre"], post=CYCLE["mg_post"])
         gbs = ab * ks / (ms * 1e-3) / 1e9 if ms > 0 else None
         classes[cls] = {"launches_per_step": nl / ks, "expected_launches_per_step": al,
                         "ms_per_step": ms / ks, "avg_launch_us": 1e3 * ms / max(nl, 1),
@@ -518,8 +535,9 @@ def main():
         "config": {"workload": f"{case['name']} ({n} cells, {b}x{b} blocks), one Newton step, FGMRES(30) to 1e-6, "
                                "plain FP64 CPR",
                    "cells": n, "block": b, "precision": "fp64", "restart": 30, "rtol": 1e-6, "dt_days": case["dt"],
-                   "preconditioner": "quasi-IMPES CPR, P-then-F, multigrid V(1,1), alpha 1, coarsest <= 512 "
-                                     "cells, red-black block ILU(0)"},
+                   "preconditioner": "quasi-IMPES CPR, P-then-F, aggregation multigrid V(2,2) with red-black "
+                                     "Gauss-Seidel, coarse correction scaled by 1.25, coarsest <= 512 cells, "
+                                     "red-black block ILU(0)"},
         "median_ms_per_step": 1e3 * float(np.median(host_times)),
         "fgmres_iterations": st["iterations"], "restart_cycles": st["cycles"], "true_rel": st["true_rel"],
         "phases_ms": phases, "solve_class_bytes_GBps": solve_gbps, "roofline": roofline,

@@ -44,6 +44,16 @@ def test_smoother_counts_only_the_multi_block_levels():
     assert tot == 15 * (44 + 41 + 40) * (N + N // 8 + N // 64)
 
 
+def test_smoother_counts_the_extra_sweeps_of_a_longer_cycle():
+    # V(2,2): one more red + black-pre pair before and one more black-pre +
+    # red pair after the coarse correction on every multi-block level
+    levels = [N, N // 8, N // 64, N // 512, 128]
+    t1, l1 = bench.algorithmic_bytes("smooth", 3, N, [15], "fp64", levels=levels)
+    t2, l2 = bench.algorithmic_bytes("smooth", 3, N, [15], "fp64", levels=levels, pre=2, post=2)
+    assert l2 == 15 * 3 * 7 and l2 - l1 == 15 * 3 * 4
+    assert t2 - t1 == 15 * 2 * (40 + 44) * (N + N // 8 + N // 64)
+
+
 def test_ilu_bytes_match_the_colour_sweep_formulas():
     tot, launches = bench.algorithmic_bytes("ilu", 3, N, [15], "fp64")
     b, nh = 3, N // 2

@@ -459,9 +459,9 @@ def main():
     if not args.no_variants:
         vs = min(args.variant_steps, args.steps)
         learned = os.path.exists(wfile) and b == 3
+        auto_level = solver.nn_level()      # the learned stage's level chosen by the last setup
         forms = [("mixed", dict(precision="mixed", **CYCLE))]
         if learned:
-            solver.attach_network(np.load(wfile))
             forms.append(("mixed+learned", dict(precision="mixed", learned=1, **CYCLE)))
             forms.append(("mixed+learned fine level", dict(precision="mixed", learned=1, nn_level=0, **CYCLE)))
             forms.append(("fp64+learned", dict(precision="fp64", learned=1, **CYCLE)))
@@ -471,6 +471,11 @@ def main():
         if learned:
             forms.append(("mixed+learned V(1,1) alpha 1", dict(precision="mixed", learned=1)))
         for name, kw in forms:
+            net_file = None
+            if kw.get("learned"):
+                # the network trained for the level the stage acts on, if shipped
+                net_file = train.weights_for_level("black-oil", kw.get("nn_level", auto_level))
+                solver.attach_network(np.load(net_file))
             sp, _, vsts, dxv, _ = run.timed(cprmi.default_options(**kw), vs, 1)
             variants[name] = {"s_per_step": sp, "krylov_iterations": vsts[-1]["iterations"],
                               "true_rel": vsts[-1]["true_rel"], "speedup_vs_fp64": sec / sp,
@@ -478,6 +483,7 @@ def main():
                               "fp64_fallback_after_cycle": vsts[-1].get("fp64_fallback", 0)}
             if kw.get("learned"):
                 variants[name]["nn_level"] = solver.nn_level()
+                variants[name]["network"] = os.path.basename(net_file)
         solver.attach_network(None)
 
     phases, _ = run.phases(fp64)
@@ -572,17 +578,17 @@ def _kernel_sha(kclass):
 
 
 def other_configs(steps=2):
-    """The other workloads, each timed per Newton step from the same state:
-    the layered 128x128x32 black oil (FP64, mixed, mixed + learned, and the
-    tuned V(2,2), alpha 1.25 cycle; plus one whole backward-Euler day by
-    time stepping), the oil-water 32x32x8 system (latency regime) and the
-    first system of the channelised 256x256x64 black-oil 10-day step."""
+    """The other workloads, each timed per Newton step from the same state
+    with the same cycle as the headline (and the library's default V(1,1)
+    beside it): the layered 128x128x32 black oil (FP64, mixed, mixed +
+    learned; plus one whole backward-Euler day by time stepping), the
+    oil-water 32x32x8 system (latency regime) and the first system of the
+    channelised 256x256x64 black-oil 10-day step."""
     import numpy as np
     import torch
     from paper_1606_00548_amd import cprmi, synth, train
     out = {}
     wfile = train.weights_path("black-oil")
-    tuned = dict(mg_pre=2, mg_post=2, mg_alpha=1.25)
     for name, make, learned in (
             ("black-oil layered 128x128x32", lambda: synth.black_oil_layered(), True),
             ("oil-water 32x32x8", lambda: synth.oil_water_lognormal(), False),
@@ -592,12 +598,12 @@ def other_configs(steps=2):
         s = cprmi.Solver.from_case(case)
         run = Stepper(s, case)
         res = {"cells": int(np.prod(case["x"].shape[1:])), "block": int(case["x"].shape[0])}
-        forms = [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed")),
-                 ("fp64 V(2,2) alpha 1.25", dict(precision="fp64", **tuned)),
-                 ("mixed V(2,2) alpha 1.25", dict(precision="mixed", **tuned))]
+        forms = [("fp64", dict(precision="fp64", **CYCLE)), ("mixed", dict(precision="mixed", **CYCLE)),
+                 ("fp64 V(1,1) alpha 1", dict(precision="fp64")),
+                 ("mixed V(1,1) alpha 1", dict(precision="mixed"))]
         if learned and os.path.exists(wfile):
             s.attach_network(np.load(wfile))
-            forms.insert(2, ("mixed+learned", dict(precision="mixed", learned=1)))
+            forms.insert(2, ("mixed+learned", dict(precision="mixed", learned=1, **CYCLE)))
         dx64 = None
         for prec, kw in forms:
             sp, _, sts, dx, _ = run.timed(cprmi.default_options(**kw), steps, 1)
@@ -608,7 +614,8 @@ def other_configs(steps=2):
         if learned and os.path.exists(wfile):
             # one backward-Euler day: a single 1-day step (with its cuts) and
             # the same day by time stepping from 0.01 day with growth
-            for prec, kw in (("fp64", dict(precision="fp64")), ("mixed+learned", dict(precision="mixed", learned=1))):
+            for prec, kw in (("fp64", dict(precision="fp64", **CYCLE)),
+                             ("mixed+learned", dict(precision="mixed", learned=1, **CYCLE))):
                 lo = cprmi.default_options(**kw)
                 xts = torch.empty_like(run.x0)
                 s.time_step(run.x_old, case["dt"], options=lo, x=xts)

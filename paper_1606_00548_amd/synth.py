@@ -252,6 +252,23 @@ def black_oil_training(nx=64, ny=64, nz=32, seed=7000):
                  f"black-oil training {nx}x{ny}x{nz}")
 
 
+def black_oil_lattice_training(nx=256, ny=256, nz=64, seed=5100):
+    """Training systems for a learned stage on a coarse multigrid level:
+    lognormal fields around the lattice workload's (sigma ~ U(1, 2),
+    horizontal correlation U{2..8} cells, vertical 1), kz/kx =
+    10^U(-1.5, -0.5), a 3x3 to 5x5 lattice of wells, porosity U(0.1, 0.3),
+    dt 1 day."""
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    sigma, lh = rng.uniform(1.0, 2.0), float(rng.integers(2, 9))
+    kx = np.exp(np.log(100.0) + sigma * gaussian_field(rng, shape, (1.0, lh, lh)))
+    perm = np.stack([kx, kx, 10.0 ** rng.uniform(-1.5, -0.5) * kx])
+    poro = rng.uniform(0.1, 0.3, shape)
+    wells = lattice_wells(nx, ny, nz, per_side=int(rng.integers(3, 6)))
+    return _case(grid_of(nx, ny, nz), BLACK_OIL, perm, poro, wells, 1.0,
+                 f"black-oil lattice training {nx}x{ny}x{nz}")
+
+
 def oil_water_eval(nx=128, ny=128, nz=64, seed=6000):
     """Evaluation systems for the learned stage: sigma 1.0, correlation
     (4, 4, 1), five-spot, S_w field as in training."""

@@ -15,6 +15,11 @@ by an identity block), divided by the feature scale s.  The network learns
 only the direction of that correction: the loss is 1 - cos^2(N(input), t),
 and inside the solver the step length comes from the residual-minimising
 alpha = <A_p d, r'> / |A_p d|^2 for d = N(input), judged against plain CPR.
+
+With --level l the same is done for the learned stage inside the cycle on
+multigrid level l: r' is the residual the cycle leaves on that level after
+its post-smoothing, the features are those of the level (block means of
+ln k and ln lambda_t), and the target solves with the level's operator.
 """
 import argparse
 import json
@@ -36,11 +41,27 @@ FAMILIES = {
     "black-oil": {"train": synth.black_oil_training, "shape": (64, 64, 32),
                   "eval": synth.black_oil_layered, "eval_shape": (128, 128, 32), "seed0": 7000, "eval_seed0": 2000},
 }
+# A network for a coarse multigrid level: trained on level-l residuals of
+# larger systems (level 2 of 256 x 256 x 64 is 64 x 64 x 16) with fields
+# around the lattice workload's, evaluated where that level is the automatic
+# choice (level 2 of the 512 x 512 x 128 lattice, a seed outside training).
+LEVEL_TRAINING = {"black-oil": {"train": synth.black_oil_lattice_training, "shape": (256, 256, 64), "seed0": 5100,
+                                "eval": synth.black_oil_lattice, "eval_shape": (512, 512, 128), "eval_seed0": 5000}}
 
 
-def weights_path(family):
-    """Shipped parameters of the network trained for a family."""
-    return os.path.join(WEIGHT_DIR, f"pressure_unet_{family.replace('-', '_')}.npy")
+def weights_path(family, level=0):
+    """Shipped parameters of the network trained for a family, on the fine
+    pressure residual (level 0) or on the residual the multigrid cycle
+    leaves on level `level` (see harvest)."""
+    tag = "" if level == 0 else f"_level{level}"
+    return os.path.join(WEIGHT_DIR, f"pressure_unet_{family.replace('-', '_')}{tag}.npy")
+
+
+def weights_for_level(family, level):
+    """The parameters to attach for a learned stage on `level`: the network
+    trained for that level if one is shipped, else the fine-level one."""
+    p = weights_path(family, level)
+    return p if os.path.exists(p) else weights_path(family)
 
 
 def _dev(a):
@@ -48,11 +69,14 @@ def _dev(a):
 
 
 class PressureTarget:
-    """Solves A_p e = r' for the exact remaining pressure correction."""
+    """Solves A e = r' for the exact remaining pressure correction, A a
+    scalar 7-point operator on an nx x ny x nz grid (the fine pressure matrix
+    or a multigrid level's operator)."""
 
-    def __init__(self, case):
-        self.case = case
-        self.s = cprmi.Solver(case["grid"], synth.OIL_WATER, case["perm"], case["poro"], [])
+    def __init__(self, nx, ny, nz):
+        shape = (nz, ny, nx)
+        perm = np.ones((3,) + shape)
+        self.s = cprmi.Solver(synth.grid_of(nx, ny, nz), synth.OIL_WATER, perm, np.full(shape, 0.2), [])
         self.shape = self.s.shape
 
     def load(self, Ap):
@@ -69,18 +93,22 @@ class PressureTarget:
         return dx[0].clone(), st
 
 
-def harvest(case, per_system, cycle=None):
+def harvest(case, per_system, cycle=None, level=0):
     """(features [k, nz, ny, nx, 3] float32, targets [k, nz, ny, nx] float32)
     for the first k = per_system (<= 30) Krylov vectors of the system.
     cycle: multigrid options (mg_pre, mg_post, mg_alpha) of the pressure
-    stage whose residuals are harvested (default V(1,1), alpha 1)."""
+    stage whose residuals are harvested (default V(1,1), alpha 1).  level:
+    0 for the fine residual after the cycle, l >= 1 for the residual the
+    cycle leaves on multigrid level l after its post-smoothing (features and
+    targets then live on that level's grid)."""
     s = cprmi.Solver.from_case(case)
     rhs = s.assemble(_dev(case["x_old"]), _dev(case["x"]), case["dt"])
-    s.setup(rtol=0.0, max_iter=min(per_system, 30), **(cycle or {}))
+    s.setup(rtol=0.0, max_iter=min(per_system, 30), nn_level=level, **(cycle or {}))
     _, st = s.solve(rhs)
     k = min(per_system, st["iterations"], 30)
-    tgt = PressureTarget(case)
-    tgt.load(s.export_mg_level(0))
+    nz, ny, nx = s.mg_level_shape(level)
+    tgt = PressureTarget(nx, ny, nz)
+    tgt.load(s.export_mg_level(level))
     feats, targets = [], []
     for j in range(k):
         v = s.export_krylov(j)
@@ -97,14 +125,14 @@ def harvest(case, per_system, cycle=None):
 
 
 def make_dataset(n_systems, per_system, shape=(64, 64, 32), seed0=5000, log=print, family="oil-water",
-                 cycle=None):
+                 cycle=None, level=0, gen=None):
     nx, ny, nz = shape
-    gen = FAMILIES[family]["train"]
+    gen = gen or FAMILIES[family]["train"]
     X, T = [], []
     t0 = time.time()
     for i in range(n_systems):
         case = gen(nx, ny, nz, seed=seed0 + i)
-        f, t = harvest(case, per_system, cycle)
+        f, t = harvest(case, per_system, cycle, level)
         X.append(f)
         T.append(t)
         if log and (i + 1) % max(1, n_systems // 10) == 0:
@@ -211,12 +239,12 @@ def validation_loss(net, X, T, idx, batch):
 
 
 def evaluate(theta, seeds, shape=(128, 128, 64), control_seed=99, log=print, family="oil-water",
-             precision="fp64", cycle=None):
+             precision="fp64", cycle=None, level=0, gen=None):
     """FGMRES iterations and solve time to 1e-6 on evaluation systems: plain
     CPR, CPR with the trained network, CPR with a random-init network (all
-    with the multigrid options `cycle`)."""
+    with the multigrid options `cycle`, the learned stage on `level`)."""
     nx, ny, nz = shape
-    gen = FAMILIES[family]["eval"]
+    gen = gen or FAMILIES[family]["eval"]
     rows = []
     for sd in seeds:
         case = gen(nx, ny, nz, seed=sd)
@@ -227,7 +255,7 @@ def evaluate(theta, seeds, shape=(128, 128, 64), control_seed=99, log=print, fam
                          ("random", synth.nn_initial_weights(control_seed))):
             if th is not None:
                 s.attach_network(th)
-            s.setup(learned=0 if th is None else 1, precision=precision, **(cycle or {}))
+            s.setup(learned=0 if th is None else 1, precision=precision, nn_level=level, **(cycle or {}))
             s.solve(rhs)                       # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -262,10 +290,16 @@ def main():
     ap.add_argument("--mg-alpha", type=float, default=1.0, help="coarse-correction scaling of that cycle")
     ap.add_argument("--eval-only", action="store_true",
                     help="evaluate the parameters in --out (default: the shipped file) without training")
+    ap.add_argument("--level", type=int, default=0,
+                    help="multigrid level whose residuals the network is trained on (0: the fine residual)")
     args = ap.parse_args()
-    fam = FAMILIES[args.family]
-    out = args.out or weights_path(args.family)
+    fam = dict(FAMILIES[args.family])
+    if args.level > 0:
+        fam.update(LEVEL_TRAINING[args.family])
+    out = args.out or weights_path(args.family, args.level)
     cycle = {"mg_pre": args.mg_pre, "mg_post": args.mg_post, "mg_alpha": args.mg_alpha}
+    eval_kw = dict(family=args.family, cycle=cycle, level=args.level, gen=fam["eval"],
+                   log=lambda m: print(m, flush=True))
     if args.eval_only:
         theta = np.load(out)
         ex, ey, ez = fam["eval_shape"]
@@ -273,14 +307,14 @@ def main():
         for prec in ("fp64", "mixed"):
             rows += [dict(r, precision=prec) for r in evaluate(
                 theta, [fam["eval_seed0"] + i for i in range(args.eval_seeds)], shape=(ex, ey, ez),
-                family=args.family, precision=prec, cycle=cycle, log=lambda m: print(m, flush=True))]
+                precision=prec, **eval_kw)]
         if args.report:
             with open(args.report, "w") as f:
-                json.dump({"family": args.family, "weights": os.path.basename(out), "cycle": cycle, "eval": rows},
-                          f, indent=1)
+                json.dump({"family": args.family, "weights": os.path.basename(out), "cycle": cycle,
+                           "level": args.level, "eval": rows}, f, indent=1)
         return
     X, T = make_dataset(args.systems, args.per_system, fam["shape"], fam["seed0"], family=args.family,
-                        log=lambda m: print(m, flush=True), cycle=cycle)
+                        log=lambda m: print(m, flush=True), cycle=cycle, level=args.level, gen=fam["train"])
     pairs = int(X.shape[0])
     print(f"[data] {pairs} pairs", flush=True)
     theta, hist = train(X, T, args.epochs, lr=args.lr, log=lambda m: print(m, flush=True),
@@ -290,6 +324,8 @@ def main():
     os.makedirs(os.path.dirname(out), exist_ok=True)
     np.save(out, theta)
     nx, ny, nz = fam["shape"]
+    where = ("the pressure residuals after the multigrid cycle" if args.level == 0 else
+             f"the residuals the multigrid cycle leaves on level {args.level} after its post-smoothing")
     meta = {
         "family": args.family,
         "network": "3-D U-Net, channels (16, 32, 64, 64), one 3x3x3 convolution per level and path, ReLU, "
@@ -298,8 +334,9 @@ def main():
         "dtype": "float32 master (BF16 in the convolutions)",
         "data": f"{args.systems} {args.family} systems {nx}x{ny}x{nz} ({fam['train'].__module__}."
                 f"{fam['train'].__name__} seeds {fam['seed0']}-{fam['seed0'] + args.systems - 1}), "
-                f"the pressure residuals after the multigrid cycle for the first {args.per_system} Krylov "
-                f"vectors of each; targets A_p^-1 r' / rms(D^-1 r') from a 1e-10 pressure solve",
+                f"{where} for the first {args.per_system} Krylov vectors of each; targets A^-1 r' / "
+                f"rms(D^-1 r') from a 1e-10 solve with that level's operator A",
+        "level": args.level,
         "pairs": pairs, "epochs": args.epochs, "batch": 4,
         "optimizer": f"Adam lr {args.lr:g} (0.9, 0.999, 1e-8)", "init_seed": 1, "shuffle_seed": 0,
         "loss": "direction loss 1 - cos^2(N(x), t)", "cycle": cycle, "history": hist,
@@ -311,10 +348,11 @@ def main():
     for prec in ("fp64", "mixed"):
         rows += [dict(r, precision=prec) for r in evaluate(
             theta, [fam["eval_seed0"] + i for i in range(args.eval_seeds)], shape=(ex, ey, ez),
-            family=args.family, precision=prec, cycle=cycle, log=lambda m: print(m, flush=True))]
+            precision=prec, **eval_kw)]
     if args.report:
         with open(args.report, "w") as f:
-            json.dump({"family": args.family, "cycle": cycle, "history": hist, "eval": rows}, f, indent=1)
+            json.dump({"family": args.family, "cycle": cycle, "level": args.level, "history": hist, "eval": rows},
+                      f, indent=1)
 
 
 if __name__ == "__main__":

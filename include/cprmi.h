@@ -89,10 +89,10 @@ enum { CPR_COMPOSE_PF = 0, CPR_COMPOSE_FPF = 1 };
 enum { CPR_ORTH_DCGS2 = 0, CPR_ORTH_CGS2 = 1 };
 
 /* options.nn_level: cpr_setup chooses the multigrid level of the learned
- * stage -- the coarsest level of at least 2^19 cells that it can run on, the
- * fine level when none qualifies.  The options stored in the context then
- * hold the resolved level, which cpr_pressure_stage and cpr_nn_features use
- * as well. */
+ * stage among the coarse levels it can run on -- the coarsest of at least
+ * 2^19 cells, else the coarsest of at least 2^16 cells, else the fine level.
+ * The options stored in the context then hold the resolved level, which
+ * cpr_pressure_stage and cpr_nn_features use as well. */
 enum { CPR_NN_LEVEL_AUTO = -1 };
 
 /* Structured Cartesian grid: cell sizes in metres, depth of the top face in
@@ -173,8 +173,7 @@ typedef struct {
                           0: the fine pressure residual after the cycle;
                           l >= 1: inside the cycle on level l, after its
                           post-smoothing (cpr_nn_attach);
-                          CPR_NN_LEVEL_AUTO (default): chosen by cpr_setup,
-                          level 0 below about 4.2 M cells                 */
+                          CPR_NN_LEVEL_AUTO (default): chosen by cpr_setup */
 } cpr_options_t;
 
 typedef struct {

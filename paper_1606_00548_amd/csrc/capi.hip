@@ -291,22 +291,25 @@ int ensure_mixed(cpr_ctx* ctx) {
   return CPR_OK;
 }
 
-// The level the learned stage acts on with nn_level = CPR_NN_LEVEL_AUTO:
-// the coarsest level of at least 2^19 cells that it can run on (dimensions
-// divisible by 8, exactly 2^-l of the grid, colour-split, above the
-// single-workgroup levels); the fine level when no coarser one qualifies.
+// The level the learned stage acts on with nn_level = CPR_NN_LEVEL_AUTO,
+// among the coarse levels it can run on (dimensions divisible by 8, exactly
+// 2^-l of the grid, colour-split, above the single-workgroup levels): the
+// coarsest one of at least 2^19 cells, else the coarsest one of at least
+// 2^16 cells, else the fine level.
 int auto_nn_level(const cpr_ctx* ctx) {
   const Lay& F = ctx->lay;
   const int fuse = vcycle_fused_level(ctx);
-  int best = 0;
+  int big = 0, mid = 0;
   for (int l = 1; l < (int)ctx->levels.size() && l < fuse; ++l) {
     const Lay& L = ctx->levels[l].lay;
-    if ((long)L.n < (1L << 19)) break;
+    if ((long)L.n < (1L << 16)) break;
     if (L.cs && L.nxr == L.nx && L.nx % 8 == 0 && L.ny % 8 == 0 && L.nz % 8 == 0 && F.nx == L.nx << l &&
-        F.ny == L.ny << l && F.nz == L.nz << l)
-      best = l;
+        F.ny == L.ny << l && F.nz == L.nz << l) {
+      if ((long)L.n >= (1L << 19)) big = l;
+      mid = l;
+    }
   }
-  return best;
+  return big ? big : mid;
 }
 
 }  // namespace

@@ -428,3 +428,24 @@ def test_level_learned_cpr_apply_matches_oracle(precision):
     with pytest.raises(cprmi.CPRError):
         s.setup(learned=1, nn_level=2)
     s.close()
+
+
+@pytest.mark.parametrize("make,expected", [
+    (lambda: synth.oil_water_lognormal(64, 64, 16, seed=73), 0),      # level 1: 8,192 cells
+    (lambda: synth.black_oil_layered(128, 128, 32, seed=2000), 1),    # level 1: 65,536 cells
+    (lambda: synth.oil_water_lognormal(48, 40, 16, seed=74), 0),      # level 1: 24 x 20 x 8, too small
+    (lambda: synth.black_oil_lattice(256, 256, 64, seed=5000), 1),    # level 1: 2^19 cells
+])
+def test_automatic_level_choice(make, expected):
+    # nn_level = CPR_NN_LEVEL_AUTO (the default) resolves at setup to the
+    # coarsest level of at least 2^19 cells, else of at least 2^16 cells
+    # (among the levels the stage can run on), else the fine level
+    from paper_1606_00548_amd import cprmi
+    case = make()
+    s = cprmi.Solver.from_case(case)
+    s.assemble(torch.as_tensor(case["x_old"]).cuda(), torch.as_tensor(case["x"]).cuda(), case["dt"])
+    s.setup()
+    assert s.nn_level() == expected
+    s.setup(nn_level=0)
+    assert s.nn_level() == 0
+    s.close()

@@ -214,6 +214,8 @@ def test_lattice_512x512x128_mixed_learned_vs_fp64():
         print(f"[full-size]   {name}: {st['iterations']} iterations, {e0.elapsed_time(e1):.1f} ms solve, "
               f"true rel. {rel:.2e}, network accepted {st['nn_accepted']}", flush=True)
         assert st["status"] == 0 and st["true_rel"] <= 1e-6 and rel <= 1e-6
+    # the automatic level of the learned stage: level 2 (128 x 128 x 32)
+    assert s.nn_level() == 2
     assert res["mixed+learned"][0]["nn_accepted"] + res["mixed+learned"][0]["nn_rejected"] == \
         res["mixed+learned"][0]["iterations"]
     s.attach_network(None)

@@ -227,24 +227,30 @@ def cpu_baseline_sample(case, procs):
 
 
 def cpu_baseline_value(sample, n, gpu_iterations, class_bytes):
-    """Scale the sampled oracle rates to one Newton step of the whole grid:
-    per-cell assembly, setup and update times, and the per-cell time of one
-    FGMRES iteration times the iterations the full system takes (the GPU's
-    FP64 count; the oracle follows the same path)."""
+    """Scale the sampled oracle rates to one Newton step of the whole grid
+    on the cores the sample ran on: per-cell assembly, setup and update
+    times, and the per-cell time of one FGMRES iteration times the
+    iterations the full system takes (the GPU's FP64 count; the oracle
+    follows the same path), per core as measured with all windows running at
+    once, divided by the number of those cores (the windows are independent,
+    so p cores take the cells of p windows in the time one core takes one)."""
     ws = sample["windows"]
     cells = sum(w["cells"] for w in ws)
     fixed = sum(w["assemble_s"] + w["setup_s"] + w["update_s"] for w in ws) / cells
     per_it = sum(w["solve_s"] for w in ws) / sum(w["cells"] * w["iterations"] for w in ws)
-    value = fixed * n + per_it * n * gpu_iterations
+    single = fixed * n + per_it * n * gpu_iterations
+    value = single / sample["processes"]
     return {
         "value": value, "unit": "s/Newton step", "cores": sample["processes"], "kind": "oracle",
         "sample": (f"{sample['processes']} window(s) of {'x'.join(map(str, sample['window']))} cells of the "
                    f"same workload{' (the whole grid)' if sample['whole_grid'] else ', centred on wells'}, one full "
                    "Newton step each (assemble, CPR setup, FGMRES(30) with the V(2,2), alpha 1.25 cycle to "
                    "1e-6, update) in a single-threaded "
-                   "numpy process per window, all running at once; value = measured per-cell assembly/setup/"
+                   "numpy process per window, all running at once; value = (measured per-cell assembly/setup/"
                    f"update time x {n} cells + measured per-cell-per-iteration FGMRES time x {n} cells x "
-                   f"{gpu_iterations} iterations (the whole system's FP64 count)"),
+                   f"{gpu_iterations} iterations (the whole system's FP64 count)) / {sample['processes']} "
+                   "processes (per-core times measured with all of them running)"),
+        "single_core_value": single,
         "sample_wall_s": sample["wall_s"], "window_iterations": [w["iterations"] for w in ws],
         "windows_converged": all(w["converged"] for w in ws),
         "host": {"nproc": os.cpu_count(), "cpu_model": _cpu_model()},
@@ -434,7 +440,7 @@ def main():
     # the CPU sample runs first, before this process initialises the GPU
     sample = None
     if not args.no_cpu_baseline and not args.kernel_only:
-        sample = cpu_baseline_sample(case, procs=min(4, os.cpu_count() or 1))
+        sample = cpu_baseline_sample(case, procs=min(16, os.cpu_count() or 1))
 
     import numpy as np
     import torch

@@ -288,9 +288,17 @@ __global__ __launch_bounds__(256) void black_pre_kernel(Lay L, const T* __restri
   if (q < L.nh) black_pre_cell(L, A, r, x, res, q);
 }
 
-// Restriction with four threads per coarse cell: thread (tc, q, s) sums the
-// two fine cells (2ci, 2ci+1) of fine row (2cj+q, 2ck+s); the four partials
-// of a coarse cell sit in adjacent lanes and are combined in a fixed order.
+// Restriction with four threads per coarse cell: thread (cell, q, s) sums
+// the two fine cells (2ci, 2ci+1) of fine row (2cj+q, 2ck+s); the four
+// partials of a coarse cell sit in adjacent lanes and are combined in a
+// fixed order.  Coarse cells are taken in natural order (ci fastest), so
+// the lanes reading one fine row read consecutive cells of each colour half
+// (in colour-split order consecutive coarse cells are two apart in x, and
+// the fine reads would use every other value of each line).  Every lane
+// takes its row's red cell (residual r - A x formed here) and its black
+// cell (residual recorded by the black sweep) in the same order, so the
+// lanes do not diverge on the colour; the two terms are added as a sum of
+// two, whose value does not depend on their order.
 // If xc is given, the coarse level's zero-guess red sweep is done here too:
 // a red coarse cell stores x = r / a_0 as soon as its r is known.
 template <typename T>
@@ -299,27 +307,30 @@ __global__ __launch_bounds__(256) void restrict4_kernel(Lay F, Lay C, const T* _
                                                         const T* __restrict__ res, T* __restrict__ rc,
                                                         const T* __restrict__ Ac, T* __restrict__ xc) {
   int g = blockIdx.x * blockDim.x + threadIdx.x;
-  int tc = g >> 2, sub = g & 3;
+  int cn = g >> 2, sub = g & 3;
   T acc = 0;
-  if (tc < C.n) {
-    int ci, cj, ck;
-    lay_coords(C, tc, ci, cj, ck);
+  int tc = -1;
+  if (cn < C.n) {
+    const int ci = cn % C.nx, cjk = cn / C.nx;
+    const int cj = cjk % C.ny, ck = cjk / C.ny;
+    tc = lay_index(C, ci, cj, ck);
     int fj = 2 * cj + (sub & 1), fk = 2 * ck + (sub >> 1);
     if (fj < F.ny && fk < F.nz) {
-      for (int fi = 2 * ci; fi <= 2 * ci + 1 && fi < F.nx; ++fi) {
-        int f = lay_index(F, fi, fj, fk);
-        if (f < F.nh) {
-          T y = A[f] * x[f] + offdiag_sum(F, A, x, f);
-          acc += r[f] - y;
-        } else {
-          acc += res[f - F.nh];
-        }
+      const int odd = (fj + fk) & 1;
+      const int fr = 2 * ci + odd, fb = 2 * ci + 1 - odd;   // red and black cell of the pair
+      T vr = 0, vb = 0;
+      if (fr < F.nx) {
+        const int f = lay_index(F, fr, fj, fk);
+        T y = A[f] * x[f] + offdiag_sum(F, A, x, f);
+        vr = r[f] - y;
       }
+      if (fb < F.nx) vb = res[lay_index(F, fb, fj, fk) - F.nh];
+      acc = vr + vb;
     }
   }
   acc += __shfl_down(acc, 2, 4);
   acc += __shfl_down(acc, 1, 4);
-  if (tc < C.n && sub == 0) {
+  if (tc >= 0 && sub == 0) {
     rc[tc] = acc;
     if (xc && tc < C.nh) red_zero_cell(Ac, rc, xc, tc);
   }

@@ -115,3 +115,26 @@ def test_spe10_shaped_newton_step_runs_from_assembly():
           f"{st['mg_levels']} levels")
     assert st["status"] == 0 and st["true_rel"] <= 1e-6 and st["mg_levels"] == 5
     s.close()
+
+
+def test_benchmark_cycle_on_odd_levels_matches_oracle(system):
+    # V(2,2) with the coarse correction scaled by 1.25 (the benchmark's
+    # cycle) through the padded levels: one application at 1e-9 and a fixed
+    # FGMRES path of five iterations at 1e-8
+    name, case, J, b, _, coarsest, _ = system
+    s = _solver(case, J, mg_coarsest=coarsest, mg_pre=2, mg_post=2, mg_alpha=1.25, rtol=0.0, max_iter=5)
+    pc = cpr.cpr_setup(J, coarsest, pre=2, post=2)
+    v = b / np.linalg.norm(b)
+    z = s.precond(_gpu(v)).cpu().numpy()
+    ref = cpr.cpr_apply(pc, v, alpha=1.25)
+    d_apply = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    dx, st = s.solve(_gpu(b))
+    xo, so = krylov.fgmres(lambda u: cpr.block_spmv(J, u), lambda u: cpr.cpr_apply(pc, u, alpha=1.25), b,
+                           rtol=0.0, max_iter=5)
+    d = np.linalg.norm(dx.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"[odd-levels] {name} V(2,2) alpha 1.25: apply rel. diff {d_apply:.1e}; 5 FGMRES iterations "
+          f"rel. diff {d:.1e}")
+    assert d_apply <= 1e-9
+    assert st["iterations"] == so["iterations"] == 5
+    assert d <= 1e-8
+    s.close()

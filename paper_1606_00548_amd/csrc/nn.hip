@@ -37,11 +37,16 @@ constexpr int COUT[NCONV] = {16, 32, 64, 64, 64, 32, 16};
 constexpr int CIN_PAD[NCONV] = {16, 16, 32, 64, 64, 64, 32};
 constexpr int WG_CHUNK = 2048;   // voxels per weight-gradient block
 
+// FP32 -> BF16, round to nearest even (one value; the staging of the
+// convolutions converts pairs with pack_bf16x2)
 __device__ inline short f2bf(float f) {
   unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+  u += 0x7FFFu + ((u >> 16) & 1u);
   return (short)(u >> 16);
 }
+
+typedef __bf16 bf16x2_v __attribute__((ext_vector_type(2)));
+typedef float f32x2_v __attribute__((ext_vector_type(2)));
 
 struct Geo {
   int nx, ny, nz, V;   // grid of the tensor being produced
@@ -79,8 +84,10 @@ constexpr int TX = 16, TY = 4;
 
 __host__ __device__ constexpr int ksteps(int ci) { return ci >= 32 ? 27 * (ci / 32) : (ci == 16 ? 14 : 4); }
 
+// a in the low half, b in the high half, both rounded to nearest even by
+// one v_cvt_pk_bf16_f32
 __device__ inline unsigned pack_bf16x2(float a, float b) {
-  return (unsigned)(unsigned short)f2bf(a) | ((unsigned)(unsigned short)f2bf(b) << 16);
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2_v{a, b}, bf16x2_v));
 }
 
 struct ConvArgs {

@@ -32,6 +32,8 @@ namespace {
 
 constexpr int FUSE_MAX = 4096;   // cells of the first level handled by the fused kernel
 constexpr int DENSE_FUSED_MAX = 1024;
+constexpr int DENSE_PF = 16;
+constexpr int STAGE_UNROLL = 8;  // loads per thread in flight while the fused kernel stages its levels     // coarsest-inverse entries per thread loaded at the fused kernel's start
 constexpr int MAXLV = 16;
 // Threads per workgroup of the per-cell kernels (sweeps, restriction,
 // decoupling): one wave per workgroup streams their planes faster than four.
@@ -373,64 +375,175 @@ struct CoarseArgs {
   T* x[MAXLV];
   T* r[MAXLV];
   T* res[MAXLV];
+  // element offsets of each level's arrays in the LDS copy (staged form)
+  int sA[MAXLV], sx[MAXLV], sr[MAXLV], sres[MAXLV];
   const double* inv;
   T alpha;
   int pre, post;             // Gauss-Seidel sweeps before / after the coarse correction
 };
 
-template <typename T>
+// Bytes of LDS the staged form may take for its copy of the levels (the
+// kernel adds 8 KB of its own): on gfx950 a workgroup may use up to 160 KB.
+constexpr int COARSE_LDS_MAX = 96 * 1024;
+
+// Staged form (LDS = true): the levels' stencils and the first level's
+// right-hand side are copied into LDS once, every sweep, restriction and
+// prolongation then reads and writes LDS, and the levels' x (and the
+// restricted r) are copied back at the end; the coarsest inverse is read
+// from global memory.  Every sweep depends on the one before, so with the
+// arrays in global memory each costs an L2 round trip.  The arithmetic and
+// its order are the same in both forms.
+template <typename T, bool LDS>
 __global__ __launch_bounds__(1024) void coarse_cycle_kernel(CoarseArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char stage_raw[];
   __shared__ double part[1024];
+  T* sb = reinterpret_cast<T*>(stage_raw);
   const int tid = threadIdx.x, nt = blockDim.x;
+  auto Ap = [&](int l) -> const T* { return LDS ? sb + a.sA[l] : a.A[l]; };
+  auto xp = [&](int l) -> T* { return LDS ? sb + a.sx[l] : a.x[l]; };
+  auto rp = [&](int l) -> T* { return LDS ? sb + a.sr[l] : a.r[l]; };
+  auto resp = [&](int l) -> T* { return LDS ? sb + a.sres[l] : a.res[l]; };
+  // The dense coarsest solve x = A^-1 r: thread (row, p) sums columns p,
+  // p + parts, ... of its row.  When every thread has at most DENSE_PF of
+  // them, they are loaded here, so that the loads overlap the sweeps of the
+  // finer levels instead of forming a chain of dependent loads at the end.
+  const int nc = a.lay[a.count - 1].n;
+  const int parts = nt / nc;            // nc <= DENSE_FUSED_MAX <= nt
+  const int drow = tid % nc, dp = tid / nc;
+  const bool dactive = tid < nc * parts;
+  const bool prefetch = nc * nc <= nt * DENSE_PF;
+  double pre[DENSE_PF];
+#pragma unroll
+  for (int u = 0; u < DENSE_PF; ++u) {
+    const int c = dp + u * parts;
+    pre[u] = prefetch && dactive && c < nc ? a.inv[(size_t)c * nc + drow] : 0.0;
+  }
+  if constexpr (LDS) {
+    // STAGE_UNROLL independent loads per thread in flight at a time
+    auto stage = [&](const T* g, T* d, int len) {
+      for (int base = 0; base < len; base += STAGE_UNROLL * nt) {
+        T v[STAGE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < STAGE_UNROLL; ++u) {
+          const int i = base + u * nt + tid;
+          v[u] = i < len ? g[i] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < STAGE_UNROLL; ++u) {
+          const int i = base + u * nt + tid;
+          if (i < len) d[i] = v[u];
+        }
+      }
+    };
+    for (int l = 0; l + 1 < a.count; ++l) stage(a.A[l], sb + a.sA[l], 7 * a.lay[l].n);
+    stage(a.r[0], sb + a.sr[0], a.lay[0].n);
+    __syncthreads();
+  }
   for (int l = 0; l + 1 < a.count; ++l) {
     const Lay F = a.lay[l], C = a.lay[l + 1];
-    for (int q = tid; q < F.nh; q += nt) red_zero_cell(a.A[l], a.r[l], a.x[l], q);
+    const T* A = Ap(l);
+    T *x = xp(l), *r = rp(l), *res = resp(l);
+    for (int q = tid; q < F.nh; q += nt) red_zero_cell(A, r, x, q);
     __syncthreads();
-    for (int q = tid; q < F.nh; q += nt) black_pre_cell<T, false>(F, a.A[l], a.r[l], a.x[l], a.res[l], q);
+    for (int q = tid; q < F.nh; q += nt) black_pre_cell<T, false>(F, A, r, x, res, q);
     __syncthreads();
     for (int k = 1; k < a.pre; ++k) {
-      for (int q = tid; q < F.nh; q += nt) red_cell<T, false>(F, a.A[l], a.r[l], a.x[l], q);
+      for (int q = tid; q < F.nh; q += nt) red_cell<T, false>(F, A, r, x, q);
       __syncthreads();
-      for (int q = tid; q < F.nh; q += nt) black_pre_cell<T, false>(F, a.A[l], a.r[l], a.x[l], a.res[l], q);
+      for (int q = tid; q < F.nh; q += nt) black_pre_cell<T, false>(F, A, r, x, res, q);
       __syncthreads();
     }
-    for (int tc = tid; tc < C.n; tc += nt)
-      restrict_cell<T, false>(F, C, a.A[l], a.r[l], a.x[l], a.res[l], a.r[l + 1], tc);
+    T* rc = rp(l + 1);
+    for (int tc = tid; tc < C.n; tc += nt) restrict_cell<T, false>(F, C, A, r, x, res, rc, tc);
     __syncthreads();
   }
   {
     const int L = a.count - 1;
-    const int nc = a.lay[L].n;
-    const int parts = nt / nc;            // nc <= DENSE_FUSED_MAX <= nt
-    const T* rr = a.r[L];
-    if (tid < nc * parts) {
-      int row = tid % nc, p = tid / nc;
+    const T* rr = rp(L);
+    if (dactive) {
       double s = 0.0;
-      for (int c = p; c < nc; c += parts) s += a.inv[(size_t)c * nc + row] * (double)rr[c];
+      if (prefetch) {
+#pragma unroll
+        for (int u = 0; u < DENSE_PF; ++u) {
+          const int c = dp + u * parts;
+          if (c < nc) s += pre[u] * (double)rr[c];
+        }
+      } else {
+        for (int c = dp; c < nc; c += parts) s += a.inv[(size_t)c * nc + drow] * (double)rr[c];
+      }
       part[tid] = s;
     }
     __syncthreads();
+    T* xc = xp(L);
     for (int row = tid; row < nc; row += nt) {
       double s = 0.0;
       for (int p = 0; p < parts; ++p) s += part[p * nc + row];
-      a.x[L][row] = (T)s;
+      xc[row] = (T)s;
     }
     __syncthreads();
   }
   for (int l = a.count - 2; l >= 0; --l) {
     const Lay F = a.lay[l], C = a.lay[l + 1];
-    for (int q = tid; q < F.nh; q += nt)
-      black_post_cell<T, false>(F, C, a.alpha, a.A[l], a.r[l], a.x[l + 1], a.x[l], q);
+    const T* A = Ap(l);
+    T *x = xp(l), *r = rp(l), *res = resp(l);
+    const T* ec = xp(l + 1);
+    for (int q = tid; q < F.nh; q += nt) black_post_cell<T, false>(F, C, a.alpha, A, r, ec, x, q);
     __syncthreads();
-    for (int q = tid; q < F.nh; q += nt) red_cell<T, false>(F, a.A[l], a.r[l], a.x[l], q);
+    for (int q = tid; q < F.nh; q += nt) red_cell<T, false>(F, A, r, x, q);
     __syncthreads();
     for (int k = 1; k < a.post; ++k) {
-      for (int q = tid; q < F.nh; q += nt) black_pre_cell<T, false>(F, a.A[l], a.r[l], a.x[l], a.res[l], q);
+      for (int q = tid; q < F.nh; q += nt) black_pre_cell<T, false>(F, A, r, x, res, q);
       __syncthreads();
-      for (int q = tid; q < F.nh; q += nt) red_cell<T, false>(F, a.A[l], a.r[l], a.x[l], q);
+      for (int q = tid; q < F.nh; q += nt) red_cell<T, false>(F, A, r, x, q);
       __syncthreads();
     }
   }
+  if constexpr (LDS) {
+    for (int l = 0; l < a.count; ++l) {
+      const int n = a.lay[l].n;
+      for (int i = tid; i < n; i += nt) a.x[l][i] = sb[a.sx[l] + i];
+      if (l > 0)
+        for (int i = tid; i < n; i += nt) a.r[l][i] = sb[a.sr[l] + i];
+    }
+  }
+}
+
+// Lays out the levels' arrays in the LDS copy; returns its size in bytes.
+template <typename T>
+size_t coarse_stage_layout(CoarseArgs<T>& a) {
+  size_t off = 0;
+  for (int q = 0; q < a.count; ++q) {
+    const size_t n = (size_t)a.lay[q].n;
+    a.sA[q] = a.sres[q] = 0;
+    if (q + 1 < a.count) {
+      a.sA[q] = (int)off;
+      off += 7 * n;
+      a.sres[q] = (int)off;
+      off += n / 2 + 1;
+    }
+    a.sr[q] = (int)off;
+    off += n;
+    a.sx[q] = (int)off;
+    off += n;
+    off = (off + 1) & ~(size_t)1;   // 16-byte aligned arrays
+  }
+  return off * sizeof(T);
+}
+
+template <typename T>
+void launch_coarse_cycle(CoarseArgs<T>& a, hipStream_t s) {
+  // the staged form needs more than the default 64 KB of dynamic LDS
+  static const bool big_lds = [] {
+    const bool ok = hipFuncSetAttribute((const void*)coarse_cycle_kernel<T, true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, COARSE_LDS_MAX) == hipSuccess;
+    if (!ok) (void)hipGetLastError();   // leave no error for the launch checks
+    return ok;
+  }();
+  const size_t bytes = coarse_stage_layout(a);
+  if (big_lds && bytes <= (size_t)COARSE_LDS_MAX)
+    coarse_cycle_kernel<T, true><<<1, 1024, bytes, s>>>(a);
+  else
+    coarse_cycle_kernel<T, false><<<1, 1024, 0, s>>>(a);
 }
 
 // ------------------------------------------------------------ stage 2 + block ILU(0)
@@ -765,7 +878,7 @@ void vcycle(cpr_ctx* ctx) {
     a.alpha = alpha;
     a.pre = ctx->opt.mg_pre;
     a.post = ctx->opt.mg_post;
-    coarse_cycle_kernel<T><<<1, 1024, 0, s>>>(a);
+    launch_coarse_cycle<T>(a, s);
   } else {
     MGLevel& L = ctx->levels.back();
     coarse_gemv_kernel<T><<<div_up(nc, 128), 128, 0, s>>>(nc, ctx->cinv, Pre<T>::r(L), Pre<T>::x(L));

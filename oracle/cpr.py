@@ -306,65 +306,111 @@ def ilu_apply(At, Dinv, r):
 
 # ------------------------------------------- block ILU(0) in a general order
 
-def ordered_ilu_setup(At, rank):
-    """Block ILU(0) of A~ with the cells eliminated in the order of `rank`
-    (grid-shaped, distinct integers, lower first): the paper's potential
-    reordering (Sec. 4, Example 2) orders the unknowns by potential so that
-    the factorisation follows the flow.  On the 7-point graph (no
-    triangles) ILU(0) in any order keeps the off-diagonal blocks and only
-    changes the diagonal: D'_i = A~_ii - sum over neighbours k ranked before
-    i of A~_ik D'_k^-1 A~_ki.  The cells are taken one by one in rank order.
-    Returns the factor for ordered_ilu_apply."""
-    b = At.shape[1]
-    shape = At.shape[3:]
-    n = int(np.prod(shape))
+def _neighbours(shape):
+    """nbr[d, cell] = natural index of neighbour d of each cell, -1 outside."""
     nz, ny, nx = shape
-    Ab = np.moveaxis(At.reshape(7, b, b, n), 3, 1)           # [7][n][b][b]
+    n = nx * ny * nz
     cells = np.arange(n)
     i, j, k = cells % nx, (cells // nx) % ny, cells // (nx * ny)
     nbr = np.full((7, n), -1)
+    nbr[0] = cells
     for d in range(1, 7):
         di, dj, dk = DIRS[d]
         ok = (i + di >= 0) & (i + di < nx) & (j + dj >= 0) & (j + dj < ny) & (k + dk >= 0) & (k + dk < nz)
         nbr[d, ok] = (cells + di + nx * dj + nx * ny * dk)[ok]
+    return nbr
+
+
+def _wavefronts(nbr, r, earlier):
+    """Wavefront number of every cell: 0 without a neighbour that comes
+    before it (earlier=True: lower rank; False: higher rank), else one more
+    than the latest such neighbour's.  Cells of one wavefront do not depend
+    on each other, so taking them together gives the sequential result."""
+    n = r.size
+    dep = [(nbr[d] >= 0) & ((r[np.maximum(nbr[d], 0)] < r) if earlier else (r[np.maximum(nbr[d], 0)] > r))
+           for d in range(1, 7)]
+    lev = np.zeros(n, dtype=np.int64)
+    while True:
+        new = np.zeros(n, dtype=np.int64)
+        for d in range(1, 7):
+            m = dep[d - 1]
+            new[m] = np.maximum(new[m], lev[nbr[d + 0][m]] + 1)
+        if np.array_equal(new, lev):
+            return lev, dep
+        lev = new
+
+
+def ordered_ilu_setup(At, rank):
+    """Block ILU(0) of A~ with the cells eliminated in the order of `rank`
+    (grid-shaped, distinct integers, lower first).  The paper's potential
+    reordering (Sec. 4, Example 2) is one such order; the tiled red-black
+    order of tile_rank is another.  On the 7-point graph (no triangles)
+    ILU(0) in any order keeps the off-diagonal blocks and only changes the
+    diagonal: D'_i = A~_ii - sum over neighbours k ranked before i, in
+    direction order, of A~_ik D'_k^-1 A~_ki.  Cells are taken wavefront by
+    wavefront (see _wavefronts), which is the sequential order's result.
+    Returns the factor for ordered_ilu_apply."""
+    b = At.shape[1]
+    shape = At.shape[3:]
+    n = int(np.prod(shape))
+    Ab = np.moveaxis(At.reshape(7, b, b, n), 3, 1)           # [7][n][b][b]
+    nbr = _neighbours(shape)
     r = np.asarray(rank).ravel()
-    order = np.argsort(r, kind="stable")
-    Dinv = np.empty((n, b, b))
-    for c in order:
+    lev, low = _wavefronts(nbr, r, True)
+    ulev, up = _wavefronts(nbr, r, False)
+    Dinv = np.zeros((n, b, b))
+    for L in range(lev.max() + 1):
+        c = np.where(lev == L)[0]
         D = Ab[0, c].copy()
         for d in range(1, 7):
-            q = nbr[d, c]
-            if q >= 0 and r[q] < r[c]:
-                D -= Ab[d, c] @ Dinv[q] @ Ab[OPP[d], q]
-        Dinv[c] = _inv_blocks(D[:, :, None])[:, :, 0]
-    return {"Ab": Ab, "nbr": nbr, "rank": r, "order": order, "Dinv": Dinv, "shape": (b,) + tuple(shape)}
+            m = low[d - 1][c]
+            cc, q = c[m], nbr[d, c[m]]
+            D[m] -= Ab[d, cc] @ Dinv[q] @ Ab[OPP[d], q]
+        Dinv[c] = np.moveaxis(_inv_blocks(np.moveaxis(D, 0, -1)), -1, 0)
+    return {"Ab": Ab, "nbr": nbr, "lev": lev, "low": low, "ulev": ulev, "up": up, "Dinv": Dinv,
+            "shape": (b,) + tuple(shape)}
 
 
 def ordered_ilu_apply(fac, rhs):
     """Solve (D'+L) D'^-1 (D'+U) z = r for the factor of ordered_ilu_setup:
-    forward y_i = D'_i^-1 (r_i - sum over earlier neighbours A~_ik y_k) in
-    rank order, backward z_i = y_i - D'_i^-1 sum over later neighbours
-    A~_ik z_k in reverse rank order."""
-    Ab, nbr, r, order, Dinv = fac["Ab"], fac["nbr"], fac["rank"], fac["order"], fac["Dinv"]
+    forward y_i = D'_i^-1 (r_i - sum over earlier neighbours A~_ik y_k),
+    backward z_i = y_i - D'_i^-1 sum over later neighbours A~_ik z_k, each
+    wavefront by wavefront (forward in rank order, backward in reverse)."""
+    Ab, nbr, Dinv = fac["Ab"], fac["nbr"], fac["Dinv"]
     b = Ab.shape[2]
     rv = rhs.reshape(b, -1).T                                # [n][b]
     y = np.zeros_like(rv)
-    for c in order:
+    for L in range(fac["lev"].max() + 1):
+        c = np.where(fac["lev"] == L)[0]
         t = rv[c].copy()
         for d in range(1, 7):
-            q = nbr[d, c]
-            if q >= 0 and r[q] < r[c]:
-                t -= Ab[d, c] @ y[q]
-        y[c] = Dinv[c] @ t
+            m = fac["low"][d - 1][c]
+            t[m] -= np.einsum("nrc,nc->nr", Ab[d, c[m]], y[nbr[d, c[m]]])
+        y[c] = np.einsum("nrc,nc->nr", Dinv[c], t)
     z = y.copy()
-    for c in order[::-1]:
-        u = np.zeros(b)
+    for L in range(fac["ulev"].max() + 1):
+        c = np.where(fac["ulev"] == L)[0]
+        u = np.zeros((c.size, b))
         for d in range(1, 7):
-            q = nbr[d, c]
-            if q >= 0 and r[q] > r[c]:
-                u += Ab[d, c] @ z[q]
-        z[c] = y[c] - Dinv[c] @ u
+            m = fac["up"][d - 1][c]
+            u[m] += np.einsum("nrc,nc->nr", Ab[d, c[m]], z[nbr[d, c[m]]])
+        z[c] = y[c] - np.einsum("nrc,nc->nr", Dinv[c], u)
     return z.T.reshape(fac["shape"])
+
+
+def tile_rank(shape):
+    """The tiled red-black order: tiles of 1 x 2 x 2 cells (one cell in x,
+    two in y and z), coloured red or black by the parity of (i + j // 2 +
+    k // 2) so that face-neighbouring tiles differ; every red tile comes
+    before every black tile, and inside a tile the cells follow the natural
+    order (y before z).  Red-black is the case of one-cell tiles."""
+    nz, ny, nx = shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    tj, tk = j // 2, k // 2
+    colour = (i + tj + tk) & 1
+    tile = i + nx * (tj + ((ny + 1) // 2) * tk)
+    ntiles = nx * ((ny + 1) // 2) * ((nz + 1) // 2)
+    return (colour * ntiles + tile) * 4 + (j % 2) + 2 * (k % 2)
 
 
 def potential_rank(p, depth, rho, g=9.80665):
@@ -388,20 +434,43 @@ def abf(J):
     return W, At
 
 
-def cpr_setup(J, coarsest=512, decoupling="qimpes", pre=1, post=1):
+def _ilu(pc, ilu_order):
+    """Adds the block ILU(0) of pc["At"] in the given order: "red-black"
+    (ilu_setup) or "tiles" (tile_rank through ordered_ilu_setup; its D'^-1
+    is also stored as pc["Dinv"] in the [b][b][grid] layout)."""
+    At = pc["At"]
+    if ilu_order == "red-black":
+        pc["Dinv"] = ilu_setup(At)
+    elif ilu_order == "tiles":
+        fac = ordered_ilu_setup(At, tile_rank(At.shape[3:]))
+        pc["ilu_fac"] = fac
+        pc["Dinv"] = np.moveaxis(fac["Dinv"], 0, -1).reshape(At.shape[1:3] + At.shape[3:])
+    else:
+        raise ValueError(ilu_order)
+    pc["ilu_order"] = ilu_order
+    return pc
+
+
+def ilu_solve(pc, r):
+    """The second stage's ILU(0) solve in the order chosen at setup."""
+    if pc.get("ilu_order", "red-black") == "tiles":
+        return ordered_ilu_apply(pc["ilu_fac"], r)
+    return ilu_apply(pc["At"], pc["Dinv"], r)
+
+
+def cpr_setup(J, coarsest=512, decoupling="qimpes", pre=1, post=1, ilu_order="red-black"):
     """CPR preconditioner data: decoupling (quasi-IMPES weights w and rows R0,
     or ABF blocks W), the decoupled blocks A~, the pressure multigrid on
-    A_p = A~[:, 0, 0] and the red-black block ILU(0) of A~."""
+    A_p = A~[:, 0, 0] and the block ILU(0) of A~ (red-black order, or the
+    tiled red-black order of tile_rank)."""
     if decoupling == "abf":
         W, At = abf(J)
         mg = mg_setup(At[:, 0, 0].copy(), coarsest, pre, post)
-        Dinv = ilu_setup(At)
-        return {"decoupling": "abf", "W": W, "At": At, "mg": mg, "Dinv": Dinv, "nbad": 0}
+        return _ilu({"decoupling": "abf", "W": W, "At": At, "mg": mg, "nbad": 0}, ilu_order)
     w, R0, nbad = quasi_impes(J)
     At = decoupled_blocks(J, R0)
     mg = mg_setup(R0[:, 0].copy(), coarsest, pre, post)
-    Dinv = ilu_setup(At)
-    return {"decoupling": "qimpes", "w": w, "R0": R0, "At": At, "mg": mg, "Dinv": Dinv, "nbad": nbad}
+    return _ilu({"decoupling": "qimpes", "w": w, "R0": R0, "At": At, "mg": mg, "nbad": nbad}, ilu_order)
 
 
 def decouple(pc, v):
@@ -424,7 +493,7 @@ def _two_stage(pc, rt, alpha):
         sdp = shift(dp, d)
         for r in range(rt.shape[0]):
             r2[r] -= At[d, r, 0] * sdp
-    y = ilu_apply(At, pc["Dinv"], r2)
+    y = ilu_solve(pc, r2)
     y[0] += dp
     return y
 
@@ -439,7 +508,7 @@ def cpr_apply(pc, v, alpha=1.0, composition="two-stage"):
     rt = decouple(pc, v)
     if composition == "fpf":
         At = pc["At"]
-        z1 = ilu_apply(At, pc["Dinv"], rt)
+        z1 = ilu_solve(pc, rt)
         r1 = rt - block_spmv(At, z1)
         return z1 + _two_stage(pc, r1, alpha)
     return _two_stage(pc, rt, alpha)

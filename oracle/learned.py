@@ -145,7 +145,7 @@ def learned_cpr_apply(pc, v, theta, perm_md, lam_t, composition="two-stage", lev
     rt = cpr.decouple(pc, v)
     z1 = None
     if composition == "fpf":
-        z1 = cpr.ilu_apply(At, pc["Dinv"], rt)
+        z1 = cpr.ilu_solve(pc, rt)
         rt = rt - cpr.block_spmv(At, z1)
     rt0 = rt[0]
     if level == 0:
@@ -170,7 +170,7 @@ def learned_cpr_apply(pc, v, theta, perm_md, lam_t, composition="two-stage", lev
         sdp = cpr.shift(dp, d)
         for r in range(v.shape[0]):
             r2[r] -= At[d, r, 0] * sdp
-    z = cpr.ilu_apply(At, pc["Dinv"], r2)
+    z = cpr.ilu_solve(pc, r2)
     z[0] += dp
     if z1 is not None:
         z = z1 + z

@@ -538,7 +538,7 @@ def test_cpr_variants_solve_tiny_systems(maker, decoupling, composition):
 
 @pytest.mark.parametrize("maker", [lambda: synth.oil_water_lognormal(4, 4, 2, seed=46),
                                    lambda: synth.black_oil_layered(4, 3, 2, seed=47)])
-@pytest.mark.parametrize("ordering", ["natural", "random", "potential"])
+@pytest.mark.parametrize("ordering", ["natural", "random", "potential", "tiles"])
 def test_ordered_ilu0_matches_textbook(maker, ordering):
     # the block ILU(0) in a general elimination order (the paper's potential
     # reordering) against the dense textbook factorisation in that order
@@ -551,6 +551,8 @@ def test_ordered_ilu0_matches_textbook(maker, ordering):
         rank = np.arange(n).reshape(shape)
     elif ordering == "random":
         rank = np.random.default_rng(5).permutation(n).reshape(shape)
+    elif ordering == "tiles":
+        rank = cpr.tile_rank(shape)
     else:
         depth = case["grid"]["top"] + case["grid"]["dz"] * (np.arange(shape[0])[:, None, None] + 0.5)
         rank = cpr.potential_rank(case["x"][0], np.broadcast_to(depth, shape), 800.0)
@@ -588,3 +590,30 @@ def test_potential_rank_puts_high_potential_first():
     assert rank.ravel().tolist() == [4, 0, 2, 5, 1, 3]
     rank_flat = cpr.potential_rank(p, np.zeros_like(depth), 1000.0)
     assert rank_flat.ravel().tolist() == [5, 1, 3, 4, 0, 2]
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 5), (3, 5, 2), (1, 1, 4), (5, 1, 3)])
+def test_tile_rank_structure(shape):
+    # 1 x 2 x 2 tiles: a tile's cells are consecutive in the order, every red
+    # tile precedes every black one, and face neighbours in different tiles
+    # have tiles of different colours (so tiles of one colour are independent)
+    nz, ny, nx = shape
+    rank = cpr.tile_rank(shape)
+    assert sorted(rank.ravel().tolist()) == sorted(set(rank.ravel().tolist()))
+    tile = lambda i, j, k: (i, j // 2, k // 2)
+    colour = lambda i, j, k: (i + j // 2 + k // 2) & 1
+    cells = [(i, j, k) for k in range(nz) for j in range(ny) for i in range(nx)]
+    for a in cells:
+        for b in cells:
+            if tile(*a) == tile(*b):
+                assert abs(int(rank[a[2], a[1], a[0]]) // 4 - int(rank[b[2], b[1], b[0]]) // 4) == 0
+            elif colour(*a) < colour(*b):
+                assert rank[a[2], a[1], a[0]] < rank[b[2], b[1], b[0]]
+            if sum(abs(x - y) for x, y in zip(a, b)) == 1 and tile(*a) != tile(*b):
+                assert colour(*a) != colour(*b)
+    # inside a tile: natural order, y before z
+    assert rank[0, 0, 0] % 4 == 0
+    if ny > 1:
+        assert rank[0, 1, 0] % 4 == 1
+    if nz > 1:
+        assert rank[1, 0, 0] % 4 == 2

@@ -472,7 +472,11 @@ def main():
             forms.append(("mixed+learned fine level", dict(precision="mixed", learned=1, nn_level=0, **CYCLE)))
             forms.append(("fp64+learned", dict(precision="fp64", learned=1, **CYCLE)))
         forms += [("fp64 CGS2", dict(precision="fp64", orth="cgs2", **CYCLE)),
-                  ("fp64 V(1,1) alpha 1", dict(precision="fp64")),
+                  ("fp64 tiled ILU", dict(precision="fp64", ilu_order="tiles", **CYCLE)),
+                  ("mixed tiled ILU", dict(precision="mixed", ilu_order="tiles", **CYCLE))]
+        if learned:
+            forms.append(("mixed+learned tiled ILU", dict(precision="mixed", learned=1, ilu_order="tiles", **CYCLE)))
+        forms += [("fp64 V(1,1) alpha 1", dict(precision="fp64")),
                   ("mixed V(1,1) alpha 1", dict(precision="mixed"))]
         if learned:
             forms.append(("mixed+learned V(1,1) alpha 1", dict(precision="mixed", learned=1)))
@@ -605,6 +609,8 @@ def other_configs(steps=2):
         run = Stepper(s, case)
         res = {"cells": int(np.prod(case["x"].shape[1:])), "block": int(case["x"].shape[0])}
         forms = [("fp64", dict(precision="fp64", **CYCLE)), ("mixed", dict(precision="mixed", **CYCLE)),
+                 ("fp64 tiled ILU", dict(precision="fp64", ilu_order="tiles", **CYCLE)),
+                 ("mixed tiled ILU", dict(precision="mixed", ilu_order="tiles", **CYCLE)),
                  ("fp64 V(1,1) alpha 1", dict(precision="fp64")),
                  ("mixed V(1,1) alpha 1", dict(precision="mixed"))]
         if learned and os.path.exists(wfile):
@@ -621,6 +627,7 @@ def other_configs(steps=2):
             # one backward-Euler day: a single 1-day step (with its cuts) and
             # the same day by time stepping from 0.01 day with growth
             for prec, kw in (("fp64", dict(precision="fp64", **CYCLE)),
+                             ("fp64 tiled ILU", dict(precision="fp64", ilu_order="tiles", **CYCLE)),
                              ("mixed+learned", dict(precision="mixed", learned=1, **CYCLE))):
                 lo = cprmi.default_options(**kw)
                 xts = torch.empty_like(run.x0)

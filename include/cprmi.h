@@ -88,6 +88,19 @@ enum { CPR_COMPOSE_PF = 0, CPR_COMPOSE_FPF = 1 };
  *   CPR_ORTH_CGS2   both passes in the step. */
 enum { CPR_ORTH_DCGS2 = 0, CPR_ORTH_CGS2 = 1 };
 
+/* Elimination order of the block ILU(0) of the full-system stage (the paper
+ * leaves it open apart from its potential reordering, Sec. 4 Example 2):
+ *   CPR_ILU_RED_BLACK  red cells ((i+j+k) even) before black ones;
+ *   CPR_ILU_TILES      tiles of 1 x 2 x 2 cells (i; j, j+1; k, k+1 for even
+ *                      j, k) coloured red or black by the parity of
+ *                      (i + j/2 + k/2), red tiles before black ones, and the
+ *                      cells of a tile in natural order (y before z).  Cells
+ *                      of one tile couple inside the factorisation, which
+ *                      brings ILU(0) closer to the sequential natural order
+ *                      while tiles of one colour stay independent.  P-then-F
+ *                      composition only. */
+enum { CPR_ILU_RED_BLACK = 0, CPR_ILU_TILES = 1 };
+
 /* options.nn_level: cpr_setup chooses the multigrid level of the learned
  * stage among the coarse levels it can run on -- the coarsest of at least
  * 2^19 cells, else the coarsest of at least 2^16 cells, else the fine level.
@@ -174,6 +187,7 @@ typedef struct {
                           l >= 1: inside the cycle on level l, after its
                           post-smoothing (cpr_nn_attach);
                           CPR_NN_LEVEL_AUTO (default): chosen by cpr_setup */
+  int ilu_order;       /* CPR_ILU_RED_BLACK (default) or CPR_ILU_TILES      */
 } cpr_options_t;
 
 typedef struct {

@@ -24,6 +24,7 @@ PREC = {"fp64": 0, "mixed": 1}
 DECOUPLING = {"qimpes": 0, "abf": 1}
 COMPOSITION = {"two-stage": 0, "fpf": 1}
 ORTH = {"dcgs2": 0, "cgs2": 1}
+ILU_ORDER = {"red-black": 0, "tiles": 1}
 
 
 class Grid(ctypes.Structure):
@@ -53,7 +54,8 @@ class Options(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double), ("mg_coarsest", ctypes.c_int),
                 ("mg_alpha", ctypes.c_double), ("decoupling", ctypes.c_int), ("composition", ctypes.c_int),
                 ("x0", ctypes.c_int), ("mg_pre", ctypes.c_int), ("mg_post", ctypes.c_int),
-                ("stall_ratio", ctypes.c_double), ("orth", ctypes.c_int), ("nn_level", ctypes.c_int)]
+                ("stall_ratio", ctypes.c_double), ("orth", ctypes.c_int), ("nn_level", ctypes.c_int),
+                ("ilu_order", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -344,6 +346,8 @@ def default_options(**kw):
             v = COMPOSITION[v]
         if k == "orth" and isinstance(v, str):
             v = ORTH[v]
+        if k == "ilu_order" and isinstance(v, str):
+            v = ILU_ORDER[v]
         setattr(o, k, v)
     return o
 

@@ -740,6 +740,221 @@ __global__ __launch_bounds__(256) void stage2_red_bwd_kernel(Lay L, const T* __r
   }
 }
 
+// ------------------------------------------------------------ stage 2, tiled ILU order
+// The same stage with the block ILU(0) in the tiled red-black order (one
+// thread per tile of 1 x 2 x 2 cells, see tile_of_thread): forward over the
+// red tiles, forward and backward over the black tiles (whose neighbours in
+// other tiles are all red, so their backward step only involves
+// tile-mates), backward over the red tiles.  Inside a thread the tile's
+// cells are taken in order q = 0..3 forward and 3..0 backward, and each
+// sum over neighbours runs in direction order.
+
+template <int B, typename T>
+__device__ inline void blk_add(const T* J, const T* R0, size_t N, int d, int t, const T (&v)[B], T (&acc)[B]) {
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    T a = 0;
+#pragma unroll
+    for (int c = 0; c < B; ++c) a += at_blk<B, T>(J, R0, N, d, r, c, t) * v[c];
+    acc[r] += a;
+  }
+}
+
+// Forward step's right-hand side of cell t: the stage-2 residual r2 = r~ -
+// A~(:, p) dp minus the sum over the earlier neighbours (early[d]) of
+// A~_tk y_k (yn[d]), each block read once: the full block where the
+// neighbour is earlier, its pressure column otherwise.  The residual terms
+// run in direction order, and the neighbour sum is subtracted at the end.
+template <int B, typename T, typename VT>
+__device__ inline void stage2_fwd_rhs(const Lay& L, int t, const T* J, const T* R0, const VT* __restrict__ v,
+                                      const T* __restrict__ rp, const T* __restrict__ dp, const bool (&early)[7],
+                                      const T (&yn)[7][B], T (&out)[B]) {
+  const size_t N = L.n;
+  CsCell cc = cs_decode(L, t);
+  int nbr[7];
+  bool ok[7];
+  cs_nbrs(L, t, cc, nbr, ok);
+  T r2[B], s[B];
+  r2[0] = rp[t];
+#pragma unroll
+  for (int r = 1; r < B; ++r) r2[r] = (T)v[r * N + t];
+  {
+    const T p0 = dp[t];
+#pragma unroll
+    for (int r = 0; r < B; ++r) r2[r] -= at_blk<B, T>(J, R0, N, 0, r, 0, t) * p0;
+  }
+#pragma unroll
+  for (int r = 0; r < B; ++r) s[r] = 0;
+#pragma unroll
+  for (int d = 1; d < 7; ++d) {
+    T p = dp[nbr[d]];
+    p = ok[d] ? p : (T)0;
+    if (early[d]) {
+      T a[B][B];
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c) a[r][c] = at_blk<B, T>(J, R0, N, d, r, c, t);
+#pragma unroll
+      for (int r = 0; r < B; ++r) {
+        r2[r] -= a[r][0] * p;
+        T acc = a[r][0] * yn[d][0];
+#pragma unroll
+        for (int c = 1; c < B; ++c) acc += a[r][c] * yn[d][c];
+        s[r] += acc;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < B; ++r) r2[r] -= at_blk<B, T>(J, R0, N, d, r, 0, t) * p;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < B; ++r) out[r] = r2[r] - s[r];
+}
+
+template <int B, typename T, typename VT>
+__global__ __launch_bounds__(256) void stage2_tiles_red_fwd_kernel(Lay L, const T* __restrict__ J,
+                                                                   const T* __restrict__ R0,
+                                                                   const T* __restrict__ Dinv,
+                                                                   const VT* __restrict__ v,
+                                                                   const T* __restrict__ rp,
+                                                                   const T* __restrict__ dp, T* __restrict__ Y) {
+  int i, tj, tk;
+  if (!tile_of_thread(L, 0, (long)blockIdx.x * blockDim.x + threadIdx.x, i, tj, tk)) return;
+  const size_t N = L.n;
+  T y[4][B];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = 2 * tj + (q & 1), k = 2 * tk + (q >> 1);
+    if (j >= L.ny || k >= L.nz) continue;
+    const int t = lay_index(L, i, j, k);
+    // earlier neighbours of a red tile's cell: its tile-mates below q (-y, -z)
+    bool early[7] = {false, false, false, (q & 1) != 0, false, (q & 2) != 0, false};
+    T yn[7][B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      yn[3][c] = (q & 1) ? y[(q & 1) ? q - 1 : 0][c] : (T)0;
+      yn[5][c] = (q & 2) ? y[(q & 2) ? q - 2 : 0][c] : (T)0;
+    }
+    T r2[B];
+    stage2_fwd_rhs<B, T, VT>(L, t, J, R0, v, rp, dp, early, yn, r2);
+    dinv_apply<B, T>(Dinv, N, t, r2, y[q]);
+#pragma unroll
+    for (int r = 0; r < B; ++r) Y[(size_t)r * N + t] = y[q][r];
+  }
+}
+
+template <int B, typename T, typename VT>
+__global__ __launch_bounds__(256) void stage2_tiles_black_kernel(Lay L, const T* __restrict__ J,
+                                                                 const T* __restrict__ R0,
+                                                                 const T* __restrict__ Dinv,
+                                                                 const VT* __restrict__ v,
+                                                                 const T* __restrict__ rp,
+                                                                 const T* __restrict__ dp, T* __restrict__ Y,
+                                                                 double* __restrict__ z) {
+  int i, tj, tk;
+  if (!tile_of_thread(L, 1, (long)blockIdx.x * blockDim.x + threadIdx.x, i, tj, tk)) return;
+  const size_t N = L.n;
+  T y[4][B];
+  int tq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = 2 * tj + (q & 1), k = 2 * tk + (q >> 1);
+    tq[q] = (j < L.ny && k < L.nz) ? lay_index(L, i, j, k) : -1;
+    if (tq[q] < 0) continue;
+    const int t = tq[q];
+    CsCell cc = cs_decode(L, t);
+    int nbr[7];
+    bool ok[7];
+    cs_nbrs(L, t, cc, nbr, ok);
+    // earlier neighbours: tile-mates below q, and every neighbour in another
+    // tile (red); the latter's y come from the red forward kernel
+    bool early[7];
+    T yn[7][B];
+    early[0] = false;
+#pragma unroll
+    for (int d = 1; d < 7; ++d) {
+      const int mate = tile_mate(q, d);
+      early[d] = ok[d] && mate < q;
+#pragma unroll
+      for (int c = 0; c < B; ++c)
+        yn[d][c] = !early[d] ? (T)0 : mate >= 0 ? y[mate < 0 ? 0 : mate][c] : Y[(size_t)c * N + nbr[d]];
+    }
+    T r2[B];
+    stage2_fwd_rhs<B, T, VT>(L, t, J, R0, v, rp, dp, early, yn, r2);
+    dinv_apply<B, T>(Dinv, N, t, r2, y[q]);
+  }
+  // backward: only tile-mates above q are later
+  T zt[4][B];
+#pragma unroll
+  for (int q = 3; q >= 0; --q) {
+    if (tq[q] < 0) continue;
+    const int t = tq[q];
+    T u[B], w[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) u[r] = 0;
+    if (!(q & 1) && tq[q + 1 > 3 ? 3 : q + 1] >= 0) blk_add<B, T>(J, R0, N, 4, t, zt[q + 1 > 3 ? 3 : q + 1], u);
+    if (!(q & 2) && tq[q + 2 > 3 ? 3 : q + 2] >= 0) blk_add<B, T>(J, R0, N, 6, t, zt[q + 2 > 3 ? 3 : q + 2], u);
+    dinv_apply<B, T>(Dinv, N, t, u, w);
+#pragma unroll
+    for (int r = 0; r < B; ++r) zt[q][r] = y[q][r] - w[r];
+#pragma unroll
+    for (int r = 0; r < B; ++r) Y[(size_t)r * N + t] = zt[q][r];
+    z[t] = (double)zt[q][0] + (double)dp[t];
+#pragma unroll
+    for (int r = 1; r < B; ++r) z[(size_t)r * N + t] = (double)zt[q][r];
+  }
+}
+
+template <int B, typename T>
+__global__ __launch_bounds__(256) void stage2_tiles_red_bwd_kernel(Lay L, const T* __restrict__ J,
+                                                                   const T* __restrict__ R0,
+                                                                   const T* __restrict__ Dinv,
+                                                                   const T* __restrict__ dp,
+                                                                   const T* __restrict__ Y,
+                                                                   double* __restrict__ z) {
+  int i, tj, tk;
+  if (!tile_of_thread(L, 0, (long)blockIdx.x * blockDim.x + threadIdx.x, i, tj, tk)) return;
+  const size_t N = L.n;
+  int tq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = 2 * tj + (q & 1), k = 2 * tk + (q >> 1);
+    tq[q] = (j < L.ny && k < L.nz) ? lay_index(L, i, j, k) : -1;
+  }
+  // later neighbours of a red tile's cell: tile-mates above q, and every
+  // neighbour in another tile (black, whose z the black kernel left in Y)
+  T zt[4][B];
+#pragma unroll
+  for (int q = 3; q >= 0; --q) {
+    if (tq[q] < 0) continue;
+    const int t = tq[q];
+    CsCell cc = cs_decode(L, t);
+    int nbr[7];
+    bool ok[7];
+    cs_nbrs(L, t, cc, nbr, ok);
+    T u[B], w[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) u[r] = 0;
+#pragma unroll
+    for (int d = 1; d < 7; ++d) {
+      if (!ok[d]) continue;
+      const int mate = tile_mate(q, d);
+      if (mate >= 0 && mate < q) continue;
+      T zk[B];
+#pragma unroll
+      for (int c = 0; c < B; ++c) zk[c] = mate >= 0 ? zt[mate < 0 ? 0 : mate][c] : Y[(size_t)c * N + nbr[d]];
+      blk_add<B, T>(J, R0, N, d, t, zk, u);
+    }
+    dinv_apply<B, T>(Dinv, N, t, u, w);
+#pragma unroll
+    for (int r = 0; r < B; ++r) zt[q][r] = Y[(size_t)r * N + t] - w[r];
+    z[t] = (double)zt[q][0] + (double)dp[t];
+#pragma unroll
+    for (int r = 1; r < B; ++r) z[(size_t)r * N + t] = (double)zt[q][r];
+  }
+}
+
 // ------------------------------------------------------------ F-P-F first stage
 // z1 = ILU(0)^-1 r~ and the residual r1 = r~ - A~ z1 that the P-then-F
 // stages then see.  ILU(0) on the 7-point graph differs from A~ only between
@@ -912,6 +1127,15 @@ void stage2(cpr_ctx* ctx, const VT* vr, const T* z1, double* z) {
   const T* R0 = Pre<T>::R0(ctx);
   const T* Dinv = Pre<T>::Dinv(ctx);
   T* Y = Pre<T>::Y(ctx);
+  if (ctx->opt.ilu_order == CPR_ILU_TILES) {   // P-then-F only: z1 is null
+    const int nt = div_up(tile_threads(L), SB);
+    TIMED(CPR_KCLASS_ILU,
+          (stage2_tiles_red_fwd_kernel<B, T, VT><<<nt, SB, 0, s>>>(L, J, R0, Dinv, vr, rp, dp, Y)));
+    TIMED(CPR_KCLASS_ILU,
+          (stage2_tiles_black_kernel<B, T, VT><<<nt, SB, 0, s>>>(L, J, R0, Dinv, vr, rp, dp, Y, z)));
+    TIMED(CPR_KCLASS_ILU, (stage2_tiles_red_bwd_kernel<B, T><<<nt, SB, 0, s>>>(L, J, R0, Dinv, dp, Y, z)));
+    return;
+  }
   int nh = div_up(L.nh, SB);
   TIMED(CPR_KCLASS_ILU, (stage2_red_fwd_kernel<B, T, VT><<<nh, SB, 0, s>>>(L, J, R0, Dinv, vr, rp, dp, Y)));
   TIMED(CPR_KCLASS_ILU, (stage2_black_kernel<B, T, VT><<<nh, SB, 0, s>>>(L, J, R0, Dinv, vr, rp, dp, Y, z1, z)));

@@ -336,6 +336,10 @@ int setup_with_options(cpr_ctx* ctx, const cpr_options_t& opt) {
   if (opt.orth != CPR_ORTH_DCGS2 && opt.orth != CPR_ORTH_CGS2)
     return set_err(ctx, CPR_EINVAL, "unknown orthogonalisation");
   if (opt.nn_level < CPR_NN_LEVEL_AUTO) return set_err(ctx, CPR_EINVAL, "nn_level must be >= -1");
+  if (opt.ilu_order != CPR_ILU_RED_BLACK && opt.ilu_order != CPR_ILU_TILES)
+    return set_err(ctx, CPR_EINVAL, "unknown ILU order");
+  if (opt.ilu_order == CPR_ILU_TILES && opt.composition != CPR_COMPOSE_PF)
+    return set_err(ctx, CPR_EINVAL, "the tiled ILU order supports the P-then-F composition only");
   if (opt.learned && !ctx->nn) return set_err(ctx, CPR_EINVAL, "no pressure-correction network attached");
   ctx->opt = opt;
   ctx->setup_done = 0;
@@ -383,6 +387,7 @@ void cpr_default_options(cpr_options_t* o) {
   o->mg_post = 1;
   o->orth = CPR_ORTH_DCGS2;
   o->nn_level = CPR_NN_LEVEL_AUTO;
+  o->ilu_order = CPR_ILU_RED_BLACK;
 }
 
 int cpr_create(const cpr_grid_t* g, const cpr_fluid_t* f, const double* perm3, const double* poro,

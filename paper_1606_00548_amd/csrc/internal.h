@@ -82,6 +82,35 @@ __host__ __device__ inline int lay_nbr(const Lay& L, int i, int j, int k, int d)
   return lay_index(L, a, b, c);
 }
 
+// Tiled red-black order of the block ILU(0) (CPR_ILU_TILES): tile (i, tj,
+// tk) holds the cells (i, 2tj + b, 2tk + c), b, c in {0, 1}, as q = b + 2c
+// (natural order inside, y before z); its colour is (i + tj + tk) & 1.  A
+// launch over the tiles of one colour takes thread t to u = t % (nx/2)
+// fastest, i = 2u + parity, so consecutive threads read consecutive cells
+// of each colour-split row.
+__host__ __device__ inline long tile_threads(const Lay& L) {
+  return (long)(L.nx >> 1) * ((L.ny + 1) >> 1) * ((L.nz + 1) >> 1);
+}
+__device__ inline bool tile_of_thread(const Lay& L, int colour, long t, int& i, int& tj, int& tk) {
+  const int nu = L.nx >> 1, nty = (L.ny + 1) >> 1;
+  if (t >= tile_threads(L)) return false;
+  const int u = (int)(t % nu);
+  const long tjk = t / nu;
+  tj = (int)(tjk % nty);
+  tk = (int)(tjk / nty);
+  i = 2 * u + ((colour + tj + tk) & 1);
+  return true;
+}
+// The tile-mate of cell q in direction d (-y, +y, -z, +z), or -1 when the
+// neighbour in that direction lies in another tile.
+__host__ __device__ inline int tile_mate(int q, int d) {
+  if (d == 3) return (q & 1) ? q - 1 : -1;
+  if (d == 4) return (q & 1) ? -1 : q + 1;
+  if (d == 5) return (q & 2) ? q - 2 : -1;
+  if (d == 6) return (q & 2) ? -1 : q + 2;
+  return -1;
+}
+
 // A colour-split cell decoded once; its neighbours are then a few adds away.
 // All neighbours of a cell of colour c live in colour 1-c: +-y / +-z at a
 // fixed offset from `base` (same m), -x / +x at m or m -+ 1 by the parity

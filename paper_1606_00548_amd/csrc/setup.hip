@@ -507,6 +507,57 @@ __global__ void ilu_kernel(Lay L, int colour, const double* __restrict__ J, cons
     for (int c = 0; c < B; ++c) Dinv[tix(B * B, r * B + c, t)] = inv[r][c];
 }
 
+// Block ILU(0) diagonals in the tiled red-black order, one thread per tile
+// of one colour (red tiles first): the tile's cells in order q = 0..3, each
+// D'_q = A~_qq - sum over earlier neighbours k, in direction order, of
+// A~_qk D'_k^-1 A~_kq.  Earlier: the tile-mates before q, and for a black
+// tile every neighbour in another tile (all of them red).
+template <int B>
+__global__ void ilu_tiles_kernel(Lay L, int colour, const double* __restrict__ J, const double* __restrict__ R0,
+                                 double* Dinv, int* __restrict__ flag) {
+  int i, tj, tk;
+  if (!tile_of_thread(L, colour, (long)blockIdx.x * blockDim.x + threadIdx.x, i, tj, tk)) return;
+  const size_t N = L.n;
+  for (int q = 0; q < 4; ++q) {
+    const int j = 2 * tj + (q & 1), k = 2 * tk + (q >> 1);
+    if (j >= L.ny || k >= L.nz) continue;
+    const int t = lay_index(L, i, j, k);
+    double D[B][B];
+    for (int r = 0; r < B; ++r)
+      for (int c = 0; c < B; ++c) D[r][c] = at_blk<B>(J, R0, N, 0, r, c, t);
+    for (int d = 1; d < 7; ++d) {
+      const int nb = lay_nbr(L, i, j, k, d);
+      if (nb < 0) continue;
+      const int mate = tile_mate(q, d);
+      if (mate >= 0 ? mate > q : colour == 0) continue;   // a later neighbour
+      const int od = (d & 1) ? d + 1 : d - 1;   // direction from the neighbour back to t
+      double Aik[B][B], Dk[B][B], Aki[B][B], T1[B][B];
+      for (int r = 0; r < B; ++r)
+        for (int c = 0; c < B; ++c) {
+          Aik[r][c] = at_blk<B>(J, R0, N, d, r, c, t);
+          Dk[r][c] = Dinv[tix(B * B, r * B + c, nb)];
+          Aki[r][c] = at_blk<B>(J, R0, N, od, r, c, nb);
+        }
+      for (int r = 0; r < B; ++r)
+        for (int c = 0; c < B; ++c) {
+          double s = 0.0;
+          for (int m = 0; m < B; ++m) s += Aik[r][m] * Dk[m][c];
+          T1[r][c] = s;
+        }
+      for (int r = 0; r < B; ++r)
+        for (int c = 0; c < B; ++c) {
+          double s = 0.0;
+          for (int m = 0; m < B; ++m) s += T1[r][m] * Aki[m][c];
+          D[r][c] -= s;
+        }
+    }
+    double inv[B][B];
+    if (!small_inverse<B>(D, inv)) atomicExch(flag, 1);
+    for (int r = 0; r < B; ++r)
+      for (int c = 0; c < B; ++c) Dinv[tix(B * B, r * B + c, t)] = inv[r][c];
+  }
+}
+
 __global__ void zero_int_kernel(int* p, int n) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) p[t] = 0;
@@ -640,15 +691,24 @@ int setup_cpr(cpr_ctx* ctx) {
     gj_extract_kernel<<<div_up((long)nc * nc, 256), 256, 0, a>>>(nc, bufA, ctx->cinv, ctx->cinvf);
   }
   CPR_TRY(hipEventRecord(ctx->ev_gj, a));
-  // red-black block ILU(0): red diagonals first, black ones use them
-  int nh = div_up(L.nh, 64);
+  // block ILU(0): red diagonals (cells or tiles) first, black ones use them
+  const bool tiles = ctx->opt.ilu_order == CPR_ILU_TILES;
+  const int nh = tiles ? (int)div_up(tile_threads(L), 64) : div_up(L.nh, 64);
   for (int colour = 0; colour < 2; ++colour) {
-    if (ctx->b == 1)
+    if (tiles) {
+      if (ctx->b == 1)
+        ilu_tiles_kernel<1><<<nh, 64, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
+      else if (ctx->b == 2)
+        ilu_tiles_kernel<2><<<nh, 64, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
+      else
+        ilu_tiles_kernel<3><<<nh, 64, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
+    } else if (ctx->b == 1) {
       ilu_kernel<1><<<nh, 64, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
-    else if (ctx->b == 2)
+    } else if (ctx->b == 2) {
       ilu_kernel<2><<<nh, 64, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
-    else
+    } else {
       ilu_kernel<3><<<nh, 64, 0, s>>>(L, colour, Jdec, ctx->R0, ctx->Dinv, ctx->flag);
+    }
   }
   if (ctx->opt.precision == CPR_PREC_MIXED) {
     CPR_TRY(hipStreamWaitEvent(s, ctx->ev_rap, 0));   // FP32 copies of the levels

@@ -153,16 +153,26 @@ int run_model(int model, int nx, int ny, int nz, bool rate_well) {
   wrong.learned = 1;
   CHECK(cpr_setup(ctx, &wrong) == CPR_EINVAL, "learned without a network");
   CHECK(std::strlen(cpr_last_error(ctx)) > 0, "error text");
+  wrong = o;
+  wrong.ilu_order = 5;
+  CHECK(cpr_setup(ctx, &wrong) == CPR_EINVAL, "unknown ILU order");
+  wrong.ilu_order = CPR_ILU_TILES;
+  wrong.composition = CPR_COMPOSE_FPF;
+  CHECK(cpr_setup(ctx, &wrong) == CPR_EINVAL, "tiled ILU with F-P-F");
 
   struct Form {
     int precision, decoupling, composition, orth, pre, post;
     double alpha;
-  } forms[] = {{CPR_PREC_FP64, CPR_DECOUPLE_QIMPES, CPR_COMPOSE_PF, CPR_ORTH_DCGS2, 1, 1, 1.0},
-               {CPR_PREC_MIXED, CPR_DECOUPLE_QIMPES, CPR_COMPOSE_PF, CPR_ORTH_DCGS2, 2, 2, 1.25},
-               {CPR_PREC_FP64, CPR_DECOUPLE_ABF, CPR_COMPOSE_FPF, CPR_ORTH_CGS2, 1, 2, 1.0},
-               {CPR_PREC_MIXED, CPR_DECOUPLE_QIMPES, CPR_COMPOSE_FPF, CPR_ORTH_DCGS2, 2, 1, 1.5}};
+    int ilu_order;
+  } forms[] = {{CPR_PREC_FP64, CPR_DECOUPLE_QIMPES, CPR_COMPOSE_PF, CPR_ORTH_DCGS2, 1, 1, 1.0, CPR_ILU_RED_BLACK},
+               {CPR_PREC_MIXED, CPR_DECOUPLE_QIMPES, CPR_COMPOSE_PF, CPR_ORTH_DCGS2, 2, 2, 1.25, CPR_ILU_RED_BLACK},
+               {CPR_PREC_FP64, CPR_DECOUPLE_ABF, CPR_COMPOSE_FPF, CPR_ORTH_CGS2, 1, 2, 1.0, CPR_ILU_RED_BLACK},
+               {CPR_PREC_MIXED, CPR_DECOUPLE_QIMPES, CPR_COMPOSE_FPF, CPR_ORTH_DCGS2, 2, 1, 1.5, CPR_ILU_RED_BLACK},
+               {CPR_PREC_FP64, CPR_DECOUPLE_QIMPES, CPR_COMPOSE_PF, CPR_ORTH_DCGS2, 2, 2, 1.25, CPR_ILU_TILES},
+               {CPR_PREC_MIXED, CPR_DECOUPLE_ABF, CPR_COMPOSE_PF, CPR_ORTH_DCGS2, 1, 1, 1.0, CPR_ILU_TILES}};
   for (const Form& fm : forms) {
     cpr_options_t q = o;
+    q.ilu_order = fm.ilu_order;
     q.precision = fm.precision;
     q.decoupling = fm.decoupling;
     q.composition = fm.composition;

@@ -111,3 +111,27 @@ def test_tiled_order_options_are_checked():
     assert e.value.code == -1
     s.setup(ilu_order="tiles")     # and a valid setup afterwards
     s.close()
+
+
+def test_undersaturated_black_oil_matches_oracle():
+    # cells whose third unknown is the bubble-point pressure (variable
+    # switching) change the blocks' meaning, not the ILU's structure
+    from paper_1606_00548_amd import cprmi
+    case = synth.black_oil_layered(24, 22, 6, seed=135)
+    x = synth.undersaturated_cells(case, synth.random_state_perturbation(case, 21), 22)
+    x_old = synth.undersaturated_cells(case, case["x_old"], 23, frac=0.2)
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                          x_old, x, case["dt"])
+    b = -R
+    s = cprmi.Solver.from_case(case)
+    s.import_jacobian(J)
+    s.setup(ilu_order="tiles", mg_pre=2, mg_post=2, mg_alpha=1.25)
+    pc = cpr.cpr_setup(J, pre=2, post=2, ilu_order="tiles")
+    M = lambda u: cpr.cpr_apply(pc, u, alpha=1.25)
+    v = b / np.linalg.norm(b)
+    assert np.linalg.norm(_np(s.precond(_gpu(v))) - M(v)) <= 1e-9 * np.linalg.norm(M(v))
+    xo, so = krylov.fgmres(lambda u: cpr.block_spmv(J, u), M, b)
+    dx, st = s.solve(_gpu(b))
+    assert st["iterations"] == so["iterations"]
+    assert np.linalg.norm(_np(dx) - xo) <= 1e-8 * np.linalg.norm(xo)
+    s.close()

@@ -97,3 +97,39 @@ def test_default_stall_check_keeps_fp32_on_a_converging_solve():
         s.setup(precision="mixed", stall_ratio=float("nan"))
     assert e.value.code == -1
     s.close()
+
+
+@pytest.mark.parametrize("orth", ["dcgs2", "cgs2"])
+def test_early_stall_ends_the_cycle_after_ten_steps(orth):
+    # restart 30 and a forced stall: the first cycle ends after ten steps
+    # (FGMRES's estimate is above the bound), the check after the cycle
+    # hands the rest to plain FP64 CPR; the run equals ten steps of the
+    # mixed form followed by a plain FP64 solve from that iterate
+    from paper_1606_00548_amd import cprmi
+    case = synth.black_oil_channelised(32, 24, 8, seed=103)
+    x = synth.random_state_perturbation(case, 17)
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                          case["x_old"], x, case["dt"])
+    b = -R
+    s = cprmi.Solver.from_case(case)
+    s.import_jacobian(J)
+    bg = _gpu(b)
+    s.setup(precision="mixed", restart=30, stall_ratio=1e-300, orth=orth)
+    dxf, stf = s.solve(bg)
+    s.setup(precision="mixed", restart=30, max_iter=10, orth=orth)
+    x1, st1 = s.solve(bg)
+    assert st1["status"] == 1 and st1["iterations"] == 10
+    s.setup(precision="fp64", restart=30, x0=1, orth=orth)
+    dx2, st2 = s.solve(bg, dx=x1.clone())
+    print(f"[early-stall] {orth}: {stf['iterations']} iterations, FP64 after cycle {stf['fp64_fallback']}; "
+          f"reference 10 + {st2['iterations']}", flush=True)
+    assert stf["status"] == 0 and stf["fp64_fallback"] == 1
+    assert stf["iterations"] == 10 + st2["iterations"]
+    xf, x2 = _np(dxf), _np(dx2)
+    assert np.linalg.norm(xf - x2) <= 1e-12 * np.linalg.norm(x2)
+    assert np.linalg.norm(b - cpr.block_spmv(J, xf)) <= 1e-6 * np.linalg.norm(b)
+    # an unforced solve of the same system never stops early
+    s.setup(precision="mixed", restart=30, orth=orth)
+    _, st3 = s.solve(bg)
+    assert st3["fp64_fallback"] == 0
+    s.close()

@@ -180,10 +180,11 @@ typedef struct {
                           one it started from, the remaining cycles apply
                           plain FP64 CPR (FP64 preconditioner, no learned
                           stage; default 0.5: less than halved; 1.0: not
-                          decreased; <= 0: never).  With restart > 10 the
-                          first cycle ends after 10 steps if its residual
-                          estimate is still above that bound (and the check
-                          above follows).                                  */
+                          decreased; <= 0: never).  With restart m > 10
+                          the first cycle ends after 10 steps if its residual
+                          estimate is still above stall_ratio^(10/m) times
+                          the initial residual (and the check above
+                          follows).                                        */
   int orth;            /* CPR_ORTH_DCGS2 (default) or CPR_ORTH_CGS2        */
   int nn_level;        /* learned stage (learned = 1) on multigrid level:
                           0: the fine pressure residual after the cycle;

@@ -614,20 +614,22 @@ void givens_qr(const std::vector<double>& Hh, int m, int k, double beta, std::ve
 // on entry).  On return R (row stride m) holds the triangular factor of the
 // cycle's k x k least-squares problem and g its right-hand side, both from
 // the corrected Hessenberg matrix; its counts the Arnoldi steps.
-// Early stall check: ten steps into the first restart cycle (of more than
-// ten), with the FP32 preconditioner or the learned stage in use, FGMRES's
-// own residual estimate above stall_ratio times the initial residual ends
-// the cycle there; the check after the cycle then hands the rest of the
-// solve to plain FP64 CPR without spending the rest of the cycle.  (Measured
-// after ten first-cycle steps: 0.90-0.96 where the FP32 preconditioner
-// stalls, at most 0.04 on the healthy forms of the bench's workloads; later
-// cycles, which start from a restarted basis, are left to the check after
-// the cycle.)
+// Early stall check: ten steps into the first restart cycle (of m > ten),
+// with the FP32 preconditioner or the learned stage in use, FGMRES's own
+// residual estimate above stall_ratio^(10/m) times the initial residual
+// (the cycle's bound shared out over its steps at a constant rate: 0.79 for
+// the defaults) ends the cycle there, and the check after the cycle then
+// hands the rest of the solve to plain FP64 CPR.  (Measured after ten
+// first-cycle steps: 0.90-0.96 where the FP32 preconditioner stalls, at
+// most 0.04 on the healthy forms of the bench's workloads; later cycles,
+// which start from a restarted basis, are left to the check after the
+// cycle.)
 constexpr int STALL_EARLY = 10;
 static bool early_stall(const cpr_ctx* ctx, int steps, int its, double est, double beta) {
-  return steps == STALL_EARLY && its == steps && ctx->opt.restart > STALL_EARLY &&
+  const int m = ctx->opt.restart;
+  return steps == STALL_EARLY && its == steps && m > STALL_EARLY &&
          (ctx->opt.precision == CPR_PREC_MIXED || ctx->opt.learned) && !ctx->fp64_now &&
-         ctx->opt.stall_ratio > 0 && est > ctx->opt.stall_ratio * beta;
+         ctx->opt.stall_ratio > 0 && est > std::pow(ctx->opt.stall_ratio, (double)STALL_EARLY / m) * beta;
 }
 
 int dcgs2_cycle(cpr_ctx* ctx, double beta, double bnorm, int& its, int& k, std::vector<double>& R,

@@ -418,9 +418,11 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed / mixed+learned / tuned-cycle comparison runs")
     ap.add_argument("--no-other-configs", action="store_true")
-    ap.add_argument("--kernel-only", choices=["spmv"],
-                    help="for counter runs: assemble once, then launch only this kernel 20 times and copy "
-                         "the state vector once (calibration), printing one JSON line")
+    ap.add_argument("--kernel-only", choices=["spmv", "ilu"],
+                    help="for counter runs, printing one JSON line: 'spmv' assembles once, then launches only "
+                         "the SpMV 20 times and copies the state vector once (calibration); 'ilu' sets up the "
+                         "V(2,2) cycle with each ILU order in FP64 and FP32, applies each form 10 times and "
+                         "copies the state vector once")
     ap.add_argument("--network-only", action="store_true",
                     help="time only the pressure network's inference on the workload grid")
     args = ap.parse_args()
@@ -565,10 +567,27 @@ def main():
 
 def kernel_only(run, kclass, n, b):
     """Assemble once, then 20 SpMV launches and one copy of the state
-    vector (the calibration transfer for the memory counters)."""
+    vector (the calibration transfer for the memory counters); or, for
+    'ilu', ten CPR applications of each of the four forms (red-black and
+    tiled ILU order, FP64 and FP32) with the benchmark's cycle, then the
+    same calibration copy."""
     import torch
     s = run.s
     rhs = s.assemble(run.x_old, run.x, run.case["dt"])
+    if kclass == "ilu":
+        v = rhs / torch.linalg.vector_norm(rhs)
+        z = torch.empty_like(v)
+        forms = [(p, o) for p in ("fp64", "mixed") for o in ("red-black", "tiles")]
+        for prec, order in forms:
+            s.setup(precision=prec, ilu_order=order, **CYCLE)
+            for _ in range(10):
+                s.precond(v, z)
+            torch.cuda.synchronize()
+        cp = torch.empty_like(rhs)
+        cp.copy_(rhs)
+        torch.cuda.synchronize()
+        return {"kernel": kclass, "forms": [f"{p} {o}" for p, o in forms], "applications": 10, "cells": n,
+                "copy_bytes": rhs.numel() * 8, "source_sha": _kernel_sha(kclass)}
     xin = torch.randn_like(rhs)
     y = torch.empty_like(rhs)
     for _ in range(20):
@@ -582,7 +601,7 @@ def kernel_only(run, kclass, n, b):
 
 def _kernel_sha(kclass):
     import hashlib
-    f = {"spmv": "spmv.hip", "orth": "krylov.hip"}[kclass]
+    f = {"spmv": "spmv.hip", "orth": "krylov.hip", "ilu": "apply.hip"}[kclass]
     p = os.path.join(ROOT, "paper_1606_00548_amd", "csrc", f)
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 

@@ -418,11 +418,12 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed / mixed+learned / tuned-cycle comparison runs")
     ap.add_argument("--no-other-configs", action="store_true")
-    ap.add_argument("--kernel-only", choices=["spmv", "ilu"],
+    ap.add_argument("--kernel-only", choices=["spmv", "ilu", "orth"],
                     help="for counter runs, printing one JSON line: 'spmv' assembles once, then launches only "
                          "the SpMV 20 times and copies the state vector once (calibration); 'ilu' sets up the "
                          "V(2,2) cycle with each ILU order in FP64 and FP32, applies each form 10 times and "
-                         "copies the state vector once")
+                         "copies the state vector once; 'orth' runs one FGMRES(30) cycle of 30 steps (FP64, rtol 0) "
+                         "and the same copy")
     ap.add_argument("--network-only", action="store_true",
                     help="time only the pressure network's inference on the workload grid")
     args = ap.parse_args()
@@ -570,10 +571,20 @@ def kernel_only(run, kclass, n, b):
     vector (the calibration transfer for the memory counters); or, for
     'ilu', ten CPR applications of each of the four forms (red-black and
     tiled ILU order, FP64 and FP32) with the benchmark's cycle, then the
-    same calibration copy."""
+    same calibration copy; for 'orth', one full FGMRES(30) cycle in FP64
+    (rtol 0) and the copy."""
     import torch
     s = run.s
     rhs = s.assemble(run.x_old, run.x, run.case["dt"])
+    if kclass == "orth":
+        s.setup(precision="fp64", rtol=0.0, max_iter=30, **CYCLE)
+        _, st = s.solve(rhs)
+        torch.cuda.synchronize()
+        cp = torch.empty_like(rhs)
+        cp.copy_(rhs)
+        torch.cuda.synchronize()
+        return {"kernel": kclass, "arnoldi_steps": st["iterations"], "cells": n, "copy_bytes": rhs.numel() * 8,
+                "source_sha": _kernel_sha(kclass)}
     if kclass == "ilu":
         v = rhs / torch.linalg.vector_norm(rhs)
         z = torch.empty_like(v)

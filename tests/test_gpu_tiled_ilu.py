@@ -5,7 +5,8 @@ FGMRES with the same iteration count and 1e-8 (V(1,1) and V(2,2) with
 alpha = 1.25, quasi-IMPES and ABF), the FP32 preconditioner within 1e-5 of
 the FP64 oracle per application and to 1e-6 in FP64 residual, on grids
 whose ny or nz is odd (tiles cut by the boundary).  Tolerances as in the
-other parity tests."""
+other parity tests; BiCGSTAB over the tiled V(2,2) preconditioner on
+fixed 1- and 3-iteration paths to 1e-10 and 1e-7 and to a true residual of 1e-6."""
 import numpy as np
 import pytest
 
@@ -134,4 +135,35 @@ def test_undersaturated_black_oil_matches_oracle():
     dx, st = s.solve(_gpu(b))
     assert st["iterations"] == so["iterations"]
     assert np.linalg.norm(_np(dx) - xo) <= 1e-8 * np.linalg.norm(xo)
+    s.close()
+
+
+@pytest.mark.parametrize("k,tol", [(1, 1e-10), (3, 1e-7)])
+def test_bicgstab_with_tiled_order_matches_oracle(system, k, tol):
+    # The paper's Krylov method over the same preconditioner (V(2,2),
+    # alpha = 1.25, tiled ILU order): a fixed k-iteration path (rtol = 0)
+    # against the oracle's, with the bars of the red-black BiCGSTAB tests;
+    # then full solves, FP64 and mixed, held to the true residual.
+    name, case, J, b = system
+    s = _solver(case)
+    s.import_jacobian(J)
+    pc = cpr.cpr_setup(J, pre=2, post=2, ilu_order="tiles")
+    M = lambda u: cpr.cpr_apply(pc, u, alpha=1.25)
+    A = lambda u: cpr.block_spmv(J, u)
+    s.setup(ilu_order="tiles", mg_pre=2, mg_post=2, mg_alpha=1.25, rtol=0.0, max_iter=k)
+    dx, st = s.bicgstab(_gpu(b))
+    xo, so = krylov.bicgstab(A, M, b, rtol=0.0, max_iter=k)
+    d = np.linalg.norm(_np(dx) - xo) / np.linalg.norm(xo)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        s.setup(precision=prec, ilu_order="tiles", mg_pre=2, mg_post=2, mg_alpha=1.25)
+        dxf, stf = s.bicgstab(_gpu(b))
+        res[prec] = (stf["status"], stf["iterations"], np.linalg.norm(b - A(_np(dxf))) / np.linalg.norm(b))
+    print(f"[tiled-ilu] {name} BiCGSTAB {k} iterations: rel. diff {d:.1e}; full solves "
+          f"FP64 {res['fp64'][1]} iterations, true rel. {res['fp64'][2]:.1e}, "
+          f"mixed {res['mixed'][1]}, {res['mixed'][2]:.1e}", flush=True)
+    assert st["status"] == 1 and st["iterations"] == so["iterations"] == k
+    assert d <= tol
+    for prec in ("fp64", "mixed"):
+        assert res[prec][0] == 0 and res[prec][2] <= 1e-6
     s.close()

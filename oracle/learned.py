@@ -24,16 +24,17 @@ import scipy.linalg
 from . import cpr, model, nn
 
 
-def _pressure_stage_rt(pc, rt0):
-    dp = cpr.vcycle(pc["mg"], rt0)
+def _pressure_stage_rt(pc, rt0, alpha=1.0):
+    dp = cpr.vcycle(pc["mg"], rt0, 0, alpha)
     Ap = pc["mg"]["levels"][0]
     return rt0 - cpr.scalar_spmv(Ap, dp), dp
 
 
-def pressure_stage(pc, v):
-    """(r', dp_mg, r~_p) for one vector v[b, grid]."""
+def pressure_stage(pc, v, alpha=1.0):
+    """(r', dp_mg, r~_p) for one vector v[b, grid]; alpha scales the
+    cycle's coarse corrections as in cpr.vcycle."""
     rt0 = cpr.decouple(pc, v)[0]
-    rp, dp = _pressure_stage_rt(pc, rt0)
+    rp, dp = _pressure_stage_rt(pc, rt0, alpha)
     return rp, dp, rt0
 
 
@@ -133,13 +134,15 @@ def level_residual(pc, v, level, alpha=1.0):
     return out["rp"]
 
 
-def learned_cpr_apply(pc, v, theta, perm_md, lam_t, composition="two-stage", level=0):
+def learned_cpr_apply(pc, v, theta, perm_md, lam_t, composition="two-stage", level=0, alpha=1.0):
     """CPR application with the judged network correction in the pressure
     stage; returns (z, accepted).  level 0: on the fine pressure residual
     after the multigrid cycle; level l >= 1: inside the cycle on multigrid
     level l, after its post-smoothing (features from level_fields).  With
     composition "fpf" the pressure stage sees the residual left by the first
-    block ILU(0) stage, as in cpr.cpr_apply."""
+    block ILU(0) stage, as in cpr.cpr_apply.  alpha scales the cycle's
+    coarse corrections as in cpr.cpr_apply (on level l >= 1 the finer
+    levels scale the corrected level's result as well)."""
     At = pc["At"]
     Ap = pc["mg"]["levels"][0]
     rt = cpr.decouple(pc, v)
@@ -149,7 +152,7 @@ def learned_cpr_apply(pc, v, theta, perm_md, lam_t, composition="two-stage", lev
         rt = rt - cpr.block_spmv(At, z1)
     rt0 = rt[0]
     if level == 0:
-        rp, dp = _pressure_stage_rt(pc, rt0)
+        rp, dp = _pressure_stage_rt(pc, rt0, alpha)
         lnk, lnl = level_fields(perm_md, lam_t, 0)
         dpnn, accepted = judged_step(Ap, theta, lnk, lnl, rp)
         dp = dp + dpnn
@@ -163,7 +166,7 @@ def learned_cpr_apply(pc, v, theta, perm_md, lam_t, composition="two-stage", lev
             d, a = judged_step(A_l, theta, lnk, lnl, r - cpr.scalar_spmv(A_l, x))
             acc.append(a)
             return d
-        dp = vcycle_with_hook(mg, rt0, level, hook)
+        dp = vcycle_with_hook(mg, rt0, level, hook, 0, alpha)
         accepted = acc[0]
     r2 = rt.copy()
     for d in range(7):

@@ -110,3 +110,26 @@ def test_accepted_level_correction_reduces_the_level_residual():
         assert np.linalg.norm(rl - cpr.scalar_spmv(A_l, d)) < np.linalg.norm(rl)
     else:
         assert not np.any(d)
+
+
+def test_scaled_cycle_threads_alpha_through_the_learned_stage():
+    # with the coarse corrections scaled (V(2,2), alpha = 1.25): a hook that
+    # adds nothing gives cpr.vcycle with that alpha bit for bit, and a
+    # rejected network leaves cpr.cpr_apply with that alpha bit for bit, on
+    # the fine level and inside the cycle; alpha = 1 there differs
+    case, J, b, _ = _system()
+    pc = cpr.cpr_setup(J, pre=2, post=2)
+    v = b / np.linalg.norm(b)
+    r = cpr.decouple(pc, v)[0]
+    for level in (1, 2):
+        x = learned.vcycle_with_hook(pc["mg"], r, level, lambda rr, xx: np.zeros_like(xx), 0, 1.25)
+        assert np.array_equal(x, cpr.vcycle(pc["mg"], r, 0, 1.25))
+    lam = learned.total_mobility(case["fluid"], case["poro"], case["x"])
+    ref = cpr.cpr_apply(pc, v, alpha=1.25)
+    for level in (0, 1):
+        z, acc = learned.learned_cpr_apply(pc, v, np.zeros(nn.num_params()), case["perm"], lam, level=level,
+                                           alpha=1.25)
+        assert not acc and np.array_equal(z, ref)
+    rp, dp, _ = learned.pressure_stage(pc, v, alpha=1.25)
+    assert np.array_equal(dp, cpr.vcycle(pc["mg"], r, 0, 1.25))
+    assert not np.allclose(ref, cpr.cpr_apply(pc, v), rtol=1e-6, atol=0)

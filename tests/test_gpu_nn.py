@@ -449,3 +449,40 @@ def test_automatic_level_choice(make, expected):
     s.setup(nn_level=0)
     assert s.nn_level() == 0
     s.close()
+
+
+@pytest.mark.parametrize("order", ["red-black", "tiles"])
+@pytest.mark.parametrize("level", [0, 1])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_learned_apply_with_the_tuned_cycle_matches_oracle(precision, level, order):
+    # the learned correction with the V(2,2) cycle whose coarse corrections
+    # are scaled by 1.25, on the fine level and inside the cycle on level 1,
+    # in both ILU orders, against the oracle; tolerances of the V(1,1) tests
+    from paper_1606_00548_amd import cprmi
+    case = _level_case()
+    theta = _theta(9)
+    s = cprmi.Solver.from_case(case)
+    s.assemble(torch.as_tensor(case["x_old"]).cuda(), torch.as_tensor(case["x"]).cuda(), case["dt"])
+    R, J = model.assemble(case["grid"], case["fluid"], case["perm"], case["poro"], case["wells"],
+                          case["x_old"], case["x"], case["dt"])
+    pc = cpr.cpr_setup(J, pre=2, post=2, ilu_order=order)
+    b = -R
+    v = b / np.linalg.norm(b)
+    lam = learned.total_mobility(case["fluid"], case["poro"], case["x"])
+    z_o, acc = learned.learned_cpr_apply(pc, v, theta, case["perm"], lam, level=level, alpha=1.25)
+    z_p = cpr.cpr_apply(pc, v, alpha=1.25)
+    s.attach_network(theta.astype(np.float32))
+    s.setup(learned=1, nn_level=level, precision=precision, ilu_order=order, mg_pre=2, mg_post=2, mg_alpha=1.25)
+    z_g = s.precond(torch.as_tensor(v).cuda().contiguous()).cpu().numpy()
+    corr = np.linalg.norm(z_o - z_p)
+    err = np.linalg.norm(z_g - z_o)
+    base = 1e-9 if precision == "fp64" else 1e-5
+    print(f"[learned-tuned] {precision} level {level} {order}: accepted {acc}, |correction| {corr:.3e}, "
+          f"|gpu - oracle| {err:.3e} ({err / np.linalg.norm(z_o):.1e} relative)", flush=True)
+    if acc:
+        assert corr > 1e-4 * np.linalg.norm(z_p)
+        assert err <= 3e-2 * corr + base * np.linalg.norm(z_o)
+    else:
+        assert err <= base * np.linalg.norm(z_o)
+    s.attach_network(None)
+    s.close()
